@@ -1,0 +1,232 @@
+"""Plain CPU reference (oracle) of the geometric multigrid V-cycle.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+CPU-baseline leg of ``bench.py``.  The product package never imports it.
+
+The arithmetic lives in ``oracle.cpp`` (plain loops, FP64 / FP32, no
+floating-point contraction, optional OpenMP over the outermost loop).  This
+module only builds/loads that library and marshals numpy arrays into it.
+Every array is a C-ordered numpy array of shape (n, n) or (n, n, n), x fastest,
+boundary included.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+# A test may point the loader at a deliberately mutated build of oracle.cpp.
+_LIB_OVERRIDE = os.environ.get("MG_ORACLE_LIB")
+
+CXXFLAGS = ["-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+SMOOTH_RBGS = 0
+SMOOTH_JACOBI = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with g++ (no FMA contraction, no fast-math)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    subprocess.run(["g++", *CXXFLAGS, _SRC, "-o", tmp], check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+_d = C.c_double
+_i = C.c_int
+_p = C.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if _LIB_OVERRIDE:
+        lib = C.CDLL(_LIB_OVERRIDE)
+    else:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = C.CDLL(_LIB)
+    sig = {
+        "orc_num_threads": (_i, []),
+        "orc_residual_f64": (None, [_i, _i, _p, _p, _p, _p]),
+        "orc_residual_f32": (None, [_i, _i, _p, _p, _p, _p]),
+        "orc_smooth_f64": (None, [_i, _i, _p, _i, _d, _p, _p]),
+        "orc_smooth_f32": (None, [_i, _i, _p, _i, _d, _p, _p]),
+        "orc_rbgs_colour_f64": (None, [_i, _i, _p, _d, _i, _i, _p, _p]),
+        "orc_restrict_f64": (None, [_i, _i, _p, _p]),
+        "orc_restrict_f32": (None, [_i, _i, _p, _p]),
+        "orc_prolong_correct_f64": (None, [_i, _i, _p, _p]),
+        "orc_prolong_correct_f32": (None, [_i, _i, _p, _p]),
+        "orc_coarsest_f64": (None, [_i, _p, _p, _p]),
+        "orc_residual_norm_f64": (_d, [_i, _i, _p, _p, _p]),
+        "orc_vcycle_f64": (_i, [_i, _i, _p, _i, _d, _i, _i, _p, _p]),
+        "orc_vcycle_f32": (_i, [_i, _i, _p, _i, _d, _i, _i, _p, _p]),
+        "orc_solve_f64": (_i, [_i, _i, _p, _i, _d, _i, _i, _p, _p, _d, _i, _p, _p]),
+        "orc_ir_update_f32": (_d, [_i, _i, _p, _p, _p, _p, _p]),
+        "orc_solve_ir_f32": (_i, [_i, _i, _p, _i, _d, _i, _i, _p, _p, _d, _i, _p, _p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _chk(a, dtype, name):
+    if a is None:
+        return None
+    if not isinstance(a, np.ndarray) or a.dtype != dtype or not a.flags.c_contiguous:
+        raise TypeError(f"{name} must be a C-contiguous {np.dtype(dtype).name} numpy array")
+    return a
+
+
+def _dims(a):
+    dim = a.ndim
+    n = a.shape[0]
+    if dim not in (2, 3) or any(s != n for s in a.shape):
+        raise ValueError(f"expected a square/cubic node array, got shape {a.shape}")
+    return dim, n
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+def residual(u, f, k=None):
+    """r = f - A u on inner nodes, 0 on the boundary (FP64 or FP32 by dtype)."""
+    dt = u.dtype
+    _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, dt, "k")
+    dim, n = _dims(u)
+    r = np.zeros_like(u)
+    fn = _load().orc_residual_f64 if dt == np.float64 else _load().orc_residual_f32
+    fn(dim, n, _ptr(k), _ptr(u), _ptr(f), _ptr(r))
+    return r
+
+
+def smooth(u, f, smoother=SMOOTH_RBGS, omega=1.0, k=None):
+    """One smoothing sweep; returns a new array."""
+    dt = u.dtype
+    _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, dt, "k")
+    dim, n = _dims(u)
+    out = u.copy()
+    fn = _load().orc_smooth_f64 if dt == np.float64 else _load().orc_smooth_f32
+    fn(dim, n, _ptr(k), smoother, omega, _ptr(out), _ptr(f))
+    return out
+
+
+def rbgs_colour(u, f, colour, omega=1.0, reverse=False, k=None):
+    """Red (0) or black (1) half-sweep with serial loops, optionally reversed."""
+    _chk(u, np.float64, "u"), _chk(f, np.float64, "f"), _chk(k, np.float64, "k")
+    dim, n = _dims(u)
+    out = u.copy()
+    _load().orc_rbgs_colour_f64(dim, n, _ptr(k), omega, colour, int(reverse), _ptr(out), _ptr(f))
+    return out
+
+
+def restrict(r):
+    """Full-weighting restriction of a fine residual to the next coarser grid."""
+    dt = r.dtype
+    _chk(r, dt, "r")
+    dim, nf = _dims(r)
+    nc = (nf - 1) // 2 + 1
+    fc = np.zeros((nc,) * dim, dtype=dt)
+    fn = _load().orc_restrict_f64 if dt == np.float64 else _load().orc_restrict_f32
+    fn(dim, nf, _ptr(r), _ptr(fc))
+    return fc
+
+
+def prolong_correct(u, ec):
+    """u + P ec on inner fine nodes (bi-/trilinear interpolation); returns a new array."""
+    dt = u.dtype
+    _chk(u, dt, "u"), _chk(ec, dt, "ec")
+    dim, nf = _dims(u)
+    if ec.shape != ((nf - 1) // 2 + 1,) * dim:
+        raise ValueError("coarse array has the wrong shape")
+    out = u.copy()
+    fn = _load().orc_prolong_correct_f64 if dt == np.float64 else _load().orc_prolong_correct_f32
+    fn(dim, nf, _ptr(out), _ptr(ec))
+    return out
+
+
+def coarsest(u, f, k=None):
+    """Exact solve on the n = 3 grid; returns a new array."""
+    _chk(u, np.float64, "u"), _chk(f, np.float64, "f"), _chk(k, np.float64, "k")
+    dim, n = _dims(u)
+    if n != 3:
+        raise ValueError("coarsest solve needs n = 3")
+    out = u.copy()
+    _load().orc_coarsest_f64(dim, _ptr(k), _ptr(out), _ptr(f))
+    return out
+
+
+def residual_norm(u, f, k=None) -> float:
+    _chk(u, np.float64, "u"), _chk(f, np.float64, "f"), _chk(k, np.float64, "k")
+    dim, n = _dims(u)
+    return float(_load().orc_residual_norm_f64(dim, n, _ptr(k), _ptr(u), _ptr(f)))
+
+
+def vcycle(u, f, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None):
+    """One V(nu1, nu2) cycle; FP64 or FP32 by dtype; returns a new array."""
+    dt = u.dtype
+    _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, dt, "k")
+    dim, n = _dims(u)
+    out = u.copy()
+    fn = _load().orc_vcycle_f64 if dt == np.float64 else _load().orc_vcycle_f32
+    rc = fn(dim, n, _ptr(k), smoother, omega, nu1, nu2, _ptr(out), _ptr(f))
+    if rc != 0:
+        raise ValueError(f"oracle vcycle rejected its arguments (rc={rc})")
+    return out
+
+
+def solve(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None):
+    """FP64 V-cycle solve.  Returns (u, history of ||f - A u||_2, status)."""
+    _chk(u0, np.float64, "u0"), _chk(f, np.float64, "f"), _chk(k, np.float64, "k")
+    dim, n = _dims(u0)
+    u = u0.copy()
+    hist = np.zeros(max_cycles + 1)
+    cyc = C.c_int(0)
+    rc = _load().orc_solve_f64(dim, n, _ptr(k), smoother, omega, nu1, nu2, _ptr(u), _ptr(f), tol,
+                               max_cycles, _ptr(hist), C.addressof(cyc))
+    if rc < 0:
+        raise ValueError(f"oracle solve rejected its arguments (rc={rc})")
+    return u, hist[: cyc.value + 1].copy(), rc
+
+
+def ir_update(u, e, f, k=None):
+    """One FP64 refinement pass: returns (u + e, float32 residual, ||r||)."""
+    _chk(u, np.float64, "u"), _chk(e, np.float32, "e"), _chk(f, np.float64, "f"), _chk(k, np.float64, "k")
+    dim, n = _dims(u)
+    out = u.copy()
+    r32 = np.zeros(u.shape, dtype=np.float32)
+    rho = _load().orc_ir_update_f32(dim, n, _ptr(k), _ptr(out), _ptr(e), _ptr(f), _ptr(r32))
+    return out, r32, float(rho)
+
+
+def solve_ir_f32(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None):
+    """FP32 V-cycles inside FP64 iterative refinement.  Returns (u, history, status)."""
+    _chk(u0, np.float64, "u0"), _chk(f, np.float64, "f"), _chk(k, np.float64, "k")
+    dim, n = _dims(u0)
+    u = u0.copy()
+    hist = np.zeros(max_cycles + 1)
+    cyc = C.c_int(0)
+    rc = _load().orc_solve_ir_f32(dim, n, _ptr(k), smoother, omega, nu1, nu2, _ptr(u), _ptr(f), tol,
+                                  max_cycles, _ptr(hist), C.addressof(cyc))
+    if rc < 0:
+        raise ValueError(f"oracle solve rejected its arguments (rc={rc})")
+    return u, hist[: cyc.value + 1].copy(), rc

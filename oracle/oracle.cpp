@@ -1,0 +1,615 @@
+/*
+ * oracle.cpp -- plain CPU reference of the geometric multigrid V-cycle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  The product library shares
+ * no source with it and never calls it.
+ *
+ * What it computes (Koestler et al., arXiv:1406.5369):
+ *   - Section 2.1, Eq. (1): Poisson's equation with homogeneous Dirichlet
+ *     boundary on the unit square / cube, solved here in the form -Lap u = f
+ *     (the symmetric positive definite sign; the smoother formula of
+ *     Section 2.4 is sign-agnostic because it divides by the diagonal of the
+ *     same operator).
+ *   - Section 2.2: node-based grids, second-order finite differences, a
+ *     constant 5-point (2D) / 7-point (3D) stencil, coarsening by 2 per axis.
+ *     A grid has n = 2^L + 1 nodes per axis including the boundary and
+ *     spacing h = 1/(n-1); levels are coarsened down to n = 3 (one unknown
+ *     per axis), as in the caption of Table 2.
+ *   - Section 2.3, Algorithm 1: the recursive V-cycle (correction scheme):
+ *     presmooth, residual, restriction, recursion from a zero guess,
+ *     prolongation and correction, postsmooth; exact solve on the coarsest
+ *     grid (one unknown: u = f / diag).
+ *   - Section 2.3 component list and Table 1: omega-Jacobi and red-black
+ *     Gauss-Seidel smoothers, "direct" coarse operators (the stencil is
+ *     re-discretised with the coarse spacing), full-weighting restriction
+ *     and bi-/trilinear interpolation.
+ *   - Section 2.4 (Layer-4 functions GaussSeidel, Restrict, interpolatecorr,
+ *     VCycle, Application): the update u + omega * diag^-1 (f - A u) on inner
+ *     points, red points first, the solve loop that prints the L2 residual
+ *     after every cycle.
+ *   - Section 4 / Table 2 caption: omega = 0.8 for Jacobi, 1.0 for RBGS.
+ *   - Table 1 "single/double accuracy": the same algorithm instantiated in
+ *     float (used as the inner solver of FP64 iterative refinement).
+ *
+ * Readings taken where the paper is silent (each also fixed on the HIP side):
+ *   - colour of node (i,j[,k]) is (i+j[+k]) mod 2; red = 0 is updated first
+ *     in every sweep, pre- and post-smoothing alike;
+ *   - full weighting is the tensor product of (1/4, 1/2, 1/4) per axis, and
+ *     the interpolation is bilinear / trilinear (weights 1, 1/2, 1/4, 1/8),
+ *     i.e. P = 2^d R^T;
+ *   - every operation touches inner nodes only; boundary nodes stay 0;
+ *   - the residual norm is the unscaled Euclidean norm over inner nodes;
+ *   - per-point expressions are written in one fixed evaluation order (below)
+ *     and compiled without floating-point contraction, so that any other
+ *     implementation writing the same expressions rounds identically.
+ *
+ * Variable coefficients (-div(k grad u) = f, 7-/5-point flux form): the face
+ * coefficient between nodes p and q is the harmonic mean 2 k_p k_q/(k_p+k_q);
+ * coarse k is taken by injection k_{l+1}(I) = k_l(2I) and the operator is
+ * re-discretised on every level (Table 1, "direct (re-discretization)").
+ *
+ * Layout: x fastest, idx = (k*n + j)*n + i (3D) or j*n + i (2D).
+ */
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+typedef std::ptrdiff_t idx_t;
+
+/* ------------------------------------------------------------------ */
+/* Per-point operator: (A u)_p for inner node p.                        */
+/* ------------------------------------------------------------------ */
+
+template <typename T>
+struct Grid {
+    int dim;      /* 2 or 3 */
+    int n;        /* nodes per axis, boundary included */
+    T c;          /* 1/h^2 in working precision */
+    T wd;         /* omega*h^2/(2d): inverse diagonal times omega (Poisson) */
+    T omega;      /* smoother weight */
+    const T* k;   /* nodal coefficient (variable coefficients) or nullptr */
+};
+
+/* harmonic-mean face coefficient between nodes with values a and b */
+template <typename T>
+inline T kface(T a, T b) {
+    return ((T(2) * a) * b) / (a + b);
+}
+
+/* Poisson: (A u)_p = c * (2d u_p - sum of neighbours), fixed summation order */
+template <typename T>
+inline T apply_poisson(const Grid<T>& g, const T* u, idx_t p) {
+    const idx_t sx = 1, sy = g.n, sz = (idx_t)g.n * g.n;
+    const T uC = u[p];
+    if (g.dim == 2) {
+        const T s = (u[p - sx] + u[p + sx]) + (u[p - sy] + u[p + sy]);
+        return g.c * (T(4) * uC - s);
+    }
+    const T s = ((u[p - sx] + u[p + sx]) + (u[p - sy] + u[p + sy])) + (u[p - sz] + u[p + sz]);
+    return g.c * (T(6) * uC - s);
+}
+
+/* Variable coefficients: (A u)_p = c * (dsum u_p - t); also returns dsum */
+template <typename T>
+inline T apply_varcoef(const Grid<T>& g, const T* u, idx_t p, T* dsum_out) {
+    const idx_t sx = 1, sy = g.n, sz = (idx_t)g.n * g.n;
+    const T* k = g.k;
+    const T kp = k[p];
+    const T kxW = kface(k[p - sx], kp), kxC = kface(kp, k[p + sx]);
+    const T kyS = kface(k[p - sy], kp), kyC = kface(kp, k[p + sy]);
+    T dsum, t;
+    if (g.dim == 2) {
+        dsum = (kxW + kxC) + (kyS + kyC);
+        t = (kxW * u[p - sx] + kxC * u[p + sx]) + (kyS * u[p - sy] + kyC * u[p + sy]);
+    } else {
+        const T kzB = kface(k[p - sz], kp), kzC = kface(kp, k[p + sz]);
+        dsum = ((kxW + kxC) + (kyS + kyC)) + (kzB + kzC);
+        t = ((kxW * u[p - sx] + kxC * u[p + sx]) + (kyS * u[p - sy] + kyC * u[p + sy])) +
+            (kzB * u[p - sz] + kzC * u[p + sz]);
+    }
+    *dsum_out = dsum;
+    return g.c * (dsum * u[p] - t);
+}
+
+/* residual r_p = f_p - (A u)_p */
+template <typename T>
+inline T residual_at(const Grid<T>& g, const T* u, const T* f, idx_t p) {
+    if (g.k) {
+        T dsum;
+        const T Au = apply_varcoef(g, u, p, &dsum);
+        return f[p] - Au;
+    }
+    return f[p] - apply_poisson(g, u, p);
+}
+
+/* smoother update of Section 2.4: u + omega * diag^-1 * (f - A u) */
+template <typename T>
+inline T smooth_at(const Grid<T>& g, const T* u, const T* f, idx_t p) {
+    if (g.k) {
+        T dsum;
+        const T Au = apply_varcoef(g, u, p, &dsum);
+        const T r = f[p] - Au;
+        return u[p] + (g.omega * r) / (g.c * dsum);
+    }
+    const T r = f[p] - apply_poisson(g, u, p);
+    return u[p] + g.wd * r;
+}
+
+/* loops over inner nodes: (outer index, inner linear index) */
+inline idx_t at(int dim, int n, int i, int j, int k) {
+    return dim == 2 ? (idx_t)j * n + i : ((idx_t)k * n + j) * n + i;
+}
+
+/* ------------------------------------------------------------------ */
+/* Smoothers (Section 2.3 component list; Section 2.4 GaussSeidel)      */
+/* ------------------------------------------------------------------ */
+
+/* One red-black Gauss-Seidel sweep in place: all red nodes, then all black. */
+template <typename T>
+void rbgs_sweep(const Grid<T>& g, T* u, const T* f) {
+    const int n = g.n;
+    const int k0 = g.dim == 3 ? 1 : 0, k1 = g.dim == 3 ? n - 1 : 1; /* one pass of k in 2D */
+    for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(static)
+        for (int k = k0; k < k1; ++k)
+            for (int j = 1; j < n - 1; ++j)
+                for (int i = 1; i < n - 1; ++i) {
+                    if (((i + j + k) & 1) != colour) continue; /* k = 0 in 2D */
+                    const idx_t p = at(g.dim, n, i, j, k);
+                    u[p] = smooth_at(g, u, f, p);
+                }
+    }
+}
+
+/* One omega-Jacobi sweep: every new value from old values only. */
+template <typename T>
+void jacobi_sweep(const Grid<T>& g, T* u, const T* f, std::vector<T>& tmp) {
+    const int n = g.n;
+    const size_t total = g.dim == 3 ? (size_t)n * n * n : (size_t)n * n;
+    tmp.assign(u, u + total);
+    const int k0 = g.dim == 3 ? 1 : 0, k1 = g.dim == 3 ? n - 1 : 1;
+#pragma omp parallel for schedule(static)
+    for (int k = k0; k < k1; ++k)
+        for (int j = 1; j < n - 1; ++j)
+            for (int i = 1; i < n - 1; ++i) {
+                const idx_t p = at(g.dim, n, i, j, k);
+                tmp[p] = smooth_at(g, u, f, p);
+            }
+    std::memcpy(u, tmp.data(), total * sizeof(T));
+}
+
+/* r = f - A u on inner nodes, 0 on the boundary (Algorithm 1, residual) */
+template <typename T>
+void residual(const Grid<T>& g, const T* u, const T* f, T* r) {
+    const int n = g.n;
+    const size_t total = g.dim == 3 ? (size_t)n * n * n : (size_t)n * n;
+    std::memset(r, 0, total * sizeof(T));
+    const int k0 = g.dim == 3 ? 1 : 0, k1 = g.dim == 3 ? n - 1 : 1;
+#pragma omp parallel for schedule(static)
+    for (int k = k0; k < k1; ++k)
+        for (int j = 1; j < n - 1; ++j)
+            for (int i = 1; i < n - 1; ++i) {
+                const idx_t p = at(g.dim, n, i, j, k);
+                r[p] = residual_at(g, u, f, p);
+            }
+}
+
+/* Unscaled Euclidean norm of f - A u over inner nodes, summed in FP64.
+ * Partial sums per outer index, then added in index order (deterministic
+ * whatever the thread count). */
+template <typename T>
+double residual_norm(const Grid<T>& g, const T* u, const T* f) {
+    const int n = g.n;
+    const int k0 = g.dim == 3 ? 1 : 0, k1 = g.dim == 3 ? n - 1 : 1;
+    std::vector<double> part((size_t)n, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int k = k0; k < k1; ++k) {
+        double s = 0.0;
+        for (int j = 1; j < n - 1; ++j)
+            for (int i = 1; i < n - 1; ++i) {
+                const double r = (double)residual_at(g, u, f, at(g.dim, n, i, j, k));
+                s += r * r;
+            }
+        part[(size_t)k] = s;
+    }
+    double s = 0.0;
+    for (int k = k0; k < k1; ++k) s += part[(size_t)k];
+    return std::sqrt(s);
+}
+
+/* ------------------------------------------------------------------ */
+/* Inter-grid transfers (Section 2.3: full weighting and its partner    */
+/* bilinear/trilinear interpolation; Section 2.4 Restrict, interpolatecorr) */
+/* ------------------------------------------------------------------ */
+
+/* fc(I) = sum over the 3^d fine neighbours of 2I of w(delta) r(2I+delta),
+ * w = prod_a 2^-|delta_a| / 2^d; coarse boundary set to 0. */
+template <typename T>
+void restrict_fw(int dim, int nf, const T* r, T* fc) {
+    const int nc = (nf - 1) / 2 + 1;
+    const size_t total = dim == 3 ? (size_t)nc * nc * nc : (size_t)nc * nc;
+    std::memset(fc, 0, total * sizeof(T));
+    const idx_t sx = 1, sy = nf, sz = (idx_t)nf * nf;
+    const int K0 = dim == 3 ? 1 : 0, K1 = dim == 3 ? nc - 1 : 1;
+#pragma omp parallel for schedule(static)
+    for (int K = K0; K < K1; ++K)
+        for (int J = 1; J < nc - 1; ++J)
+            for (int I = 1; I < nc - 1; ++I) {
+                const idx_t q = at(dim, nc, I, J, K);
+                if (dim == 2) {
+                    const idx_t p = at(2, nf, 2 * I, 2 * J, 0);
+                    const T edges = (r[p - sx] + r[p + sx]) + (r[p - sy] + r[p + sy]);
+                    const T corners = (r[p - sx - sy] + r[p + sx - sy]) + (r[p - sx + sy] + r[p + sx + sy]);
+                    fc[q] = (T(0.25) * r[p] + T(0.125) * edges) + T(0.0625) * corners;
+                } else {
+                    const idx_t p = at(3, nf, 2 * I, 2 * J, 2 * K);
+                    const T faces = ((r[p - sx] + r[p + sx]) + (r[p - sy] + r[p + sy])) + (r[p - sz] + r[p + sz]);
+                    const T exy = (r[p - sx - sy] + r[p + sx - sy]) + (r[p - sx + sy] + r[p + sx + sy]);
+                    const T exz = (r[p - sx - sz] + r[p + sx - sz]) + (r[p - sx + sz] + r[p + sx + sz]);
+                    const T eyz = (r[p - sy - sz] + r[p + sy - sz]) + (r[p - sy + sz] + r[p + sy + sz]);
+                    const T edges = (exy + exz) + eyz;
+                    const T cz0 = (r[p - sx - sy - sz] + r[p + sx - sy - sz]) + (r[p - sx + sy - sz] + r[p + sx + sy - sz]);
+                    const T cz1 = (r[p - sx - sy + sz] + r[p + sx - sy + sz]) + (r[p - sx + sy + sz] + r[p + sx + sy + sz]);
+                    const T corners = cz0 + cz1;
+                    fc[q] = ((T(0.125) * r[p] + T(0.0625) * faces) + T(0.03125) * edges) + T(0.015625) * corners;
+                }
+            }
+}
+
+/* Interpolated coarse value at fine node (i,j,k): bilinear / trilinear.
+ * Along an odd axis the node lies midway between coarse nodes I and I+1. */
+template <typename T>
+T interp_at(int dim, int nc, const T* e, int i, int j, int k) {
+    const int I = i / 2, J = j / 2, K = k / 2;
+    const int oi = i & 1, oj = j & 1, ok = dim == 3 ? (k & 1) : 0;
+    const idx_t sx = 1, sy = nc, sz = (idx_t)nc * nc;
+    const idx_t q = at(dim, nc, I, J, K);
+    /* collect the strides of the odd axes in x, y, z order */
+    idx_t s[3];
+    int m = 0;
+    if (oi) s[m++] = sx;
+    if (oj) s[m++] = sy;
+    if (ok) s[m++] = sz;
+    if (m == 0) return e[q];
+    if (m == 1) return T(0.5) * (e[q] + e[q + s[0]]);
+    if (m == 2) return T(0.25) * ((e[q] + e[q + s[0]]) + (e[q + s[1]] + e[q + s[0] + s[1]]));
+    return T(0.125) * (((e[q] + e[q + s[0]]) + (e[q + s[1]] + e[q + s[0] + s[1]])) +
+                       ((e[q + s[2]] + e[q + s[0] + s[2]]) + (e[q + s[1] + s[2]] + e[q + s[0] + s[1] + s[2]])));
+}
+
+/* u_fine += P e_coarse on inner fine nodes */
+template <typename T>
+void prolong_correct(int dim, int nf, T* u, const T* ec) {
+    const int nc = (nf - 1) / 2 + 1;
+    const int k0 = dim == 3 ? 1 : 0, k1 = dim == 3 ? nf - 1 : 1;
+#pragma omp parallel for schedule(static)
+    for (int k = k0; k < k1; ++k)
+        for (int j = 1; j < nf - 1; ++j)
+            for (int i = 1; i < nf - 1; ++i) {
+                const idx_t p = at(dim, nf, i, j, k);
+                u[p] = u[p] + interp_at(dim, nc, ec, i, j, k);
+            }
+}
+
+/* Coarsest grid n = 3: a single unknown, solved exactly: u = f / diag. */
+template <typename T>
+void coarsest_solve(const Grid<T>& g, T* u, const T* f) {
+    const idx_t p = at(g.dim, 3, 1, 1, 1);
+    T diag;
+    if (g.k) {
+        T dsum;
+        (void)apply_varcoef(g, u, p, &dsum);
+        diag = g.c * dsum;
+    } else {
+        diag = g.c * (g.dim == 2 ? T(4) : T(6));
+    }
+    u[p] = f[p] / diag;
+}
+
+/* ------------------------------------------------------------------ */
+/* Level hierarchy and the recursive V-cycle (Algorithm 1)              */
+/* ------------------------------------------------------------------ */
+
+enum { SMOOTH_RBGS = 0, SMOOTH_JACOBI = 1 };
+
+inline size_t npts(int dim, int n) { return dim == 3 ? (size_t)n * n * n : (size_t)n * n; }
+
+/* constants of level with n nodes per axis, computed in double then rounded */
+inline double level_c(int n) {
+    const double h = 1.0 / (double)(n - 1);
+    return 1.0 / (h * h);
+}
+inline double level_wd(int dim, int n, double omega) {
+    const double h = 1.0 / (double)(n - 1);
+    return (omega * (h * h)) / (2.0 * (double)dim);
+}
+
+template <typename T>
+struct Hierarchy {
+    int dim, nlev, smoother, nu1, nu2;
+    double omega;
+    std::vector<int> n;               /* n[0] finest */
+    std::vector<std::vector<T>> u, f, r, k;
+    std::vector<T> tmp;
+
+    Grid<T> grid(int l) const {
+        Grid<T> g;
+        g.dim = dim;
+        g.n = n[(size_t)l];
+        g.c = (T)level_c(g.n);
+        g.wd = (T)level_wd(dim, g.n, omega);
+        g.omega = (T)omega;
+        g.k = k.empty() ? nullptr : k[(size_t)l].data();
+        return g;
+    }
+};
+
+/* Build levels n, (n-1)/2+1, ..., 3.  Level 0 arrays u[0], f[0] are left
+ * empty: the caller's arrays are used there.  k (if given) is converted to T
+ * and injected to coarse levels. */
+template <typename T>
+void build(Hierarchy<T>& H, int dim, int n, const double* k64, int smoother, double omega, int nu1, int nu2) {
+    H.dim = dim;
+    H.smoother = smoother;
+    H.omega = omega;
+    H.nu1 = nu1;
+    H.nu2 = nu2;
+    H.n.clear();
+    for (int m = n; m >= 3; m = (m - 1) / 2 + 1) {
+        H.n.push_back(m);
+        if (m == 3) break;
+    }
+    H.nlev = (int)H.n.size();
+    H.u.assign((size_t)H.nlev, {});
+    H.f.assign((size_t)H.nlev, {});
+    H.r.assign((size_t)H.nlev, {});
+    for (int l = 0; l < H.nlev; ++l) {
+        const size_t sz = npts(dim, H.n[(size_t)l]);
+        if (l > 0) {
+            H.u[(size_t)l].assign(sz, T(0));
+            H.f[(size_t)l].assign(sz, T(0));
+        }
+        H.r[(size_t)l].assign(sz, T(0));
+    }
+    H.k.clear();
+    if (k64) {
+        H.k.assign((size_t)H.nlev, {});
+        H.k[0].resize(npts(dim, n));
+        for (size_t p = 0; p < H.k[0].size(); ++p) H.k[0][p] = (T)k64[p];
+        for (int l = 1; l < H.nlev; ++l) {
+            const int nf = H.n[(size_t)l - 1], nc = H.n[(size_t)l];
+            H.k[(size_t)l].resize(npts(dim, nc));
+            const int K1 = dim == 3 ? nc : 1;
+            for (int K = 0; K < K1; ++K)
+                for (int J = 0; J < nc; ++J)
+                    for (int I = 0; I < nc; ++I)
+                        H.k[(size_t)l][(size_t)at(dim, nc, I, J, K)] =
+                            H.k[(size_t)l - 1][(size_t)at(dim, nf, 2 * I, 2 * J, 2 * K)];
+        }
+    }
+}
+
+template <typename T>
+void smooth(Hierarchy<T>& H, int l, T* u, const T* f) {
+    const Grid<T> g = H.grid(l);
+    if (H.smoother == SMOOTH_RBGS)
+        rbgs_sweep(g, u, f);
+    else
+        jacobi_sweep(g, u, f, H.tmp);
+}
+
+/* Algorithm 1 on level l with solution u and right-hand side f */
+template <typename T>
+void vcycle(Hierarchy<T>& H, int l, T* u, const T* f) {
+    const Grid<T> g = H.grid(l);
+    if (l == H.nlev - 1) {
+        coarsest_solve(g, u, f);
+        return;
+    }
+    for (int s = 0; s < H.nu1; ++s) smooth(H, l, u, f);          /* presmoothing */
+    T* r = H.r[(size_t)l].data();
+    residual(g, u, f, r);                                         /* residual */
+    T* fc = H.f[(size_t)l + 1].data();
+    restrict_fw(H.dim, g.n, r, fc);                               /* restriction */
+    T* uc = H.u[(size_t)l + 1].data();
+    std::fill(H.u[(size_t)l + 1].begin(), H.u[(size_t)l + 1].end(), T(0)); /* zero guess */
+    vcycle(H, l + 1, uc, fc);                                     /* recursion */
+    prolong_correct(H.dim, g.n, u, uc);                           /* coarse-grid correction */
+    for (int s = 0; s < H.nu2; ++s) smooth(H, l, u, f);        /* postsmoothing */
+}
+
+template <typename T>
+Grid<T> make_grid(int dim, int n, const T* kf, double omega) {
+    Grid<T> g;
+    g.dim = dim;
+    g.n = n;
+    g.c = (T)level_c(n);
+    g.wd = (T)level_wd(dim, n, omega);
+    g.omega = (T)omega;
+    g.k = kf;
+    return g;
+}
+
+bool valid_edge(int n) { return n >= 3 && ((n - 1) & (n - 2)) == 0; }
+
+} /* namespace */
+
+/* ==================================================================== */
+/* C interface (called through ctypes by the tests).                      */
+/* Every array is dense, x fastest, n nodes per axis, boundary included. */
+/* Return codes: 0 ok, 1 not converged within max_cycles, -1 bad args.    */
+/* ==================================================================== */
+
+extern "C" {
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+
+
+/* r = f - A u (inner), 0 on boundary */
+void orc_residual_f64(int dim, int n, const double* k, const double* u, const double* f, double* r) {
+    const Grid<double> g = make_grid<double>(dim, n, k, 1.0);
+    residual(g, u, f, r);
+}
+void orc_residual_f32(int dim, int n, const float* k, const float* u, const float* f, float* r) {
+    const Grid<float> g = make_grid<float>(dim, n, k, 1.0);
+    residual(g, u, f, r);
+}
+
+/* one smoothing sweep in place (smoother 0 = RBGS, 1 = Jacobi) */
+void orc_smooth_f64(int dim, int n, const double* k, int smoother, double omega, double* u, const double* f) {
+    const Grid<double> g = make_grid<double>(dim, n, k, omega);
+    std::vector<double> tmp;
+    if (smoother == SMOOTH_RBGS) rbgs_sweep(g, u, f);
+    else jacobi_sweep(g, u, f, tmp);
+}
+void orc_smooth_f32(int dim, int n, const float* k, int smoother, double omega, float* u, const float* f) {
+    const Grid<float> g = make_grid<float>(dim, n, k, omega);
+    std::vector<float> tmp;
+    if (smoother == SMOOTH_RBGS) rbgs_sweep(g, u, f);
+    else jacobi_sweep(g, u, f, tmp);
+}
+
+/* only the red (colour 0) or black (colour 1) half of an RBGS sweep */
+void orc_rbgs_colour_f64(int dim, int n, const double* k, double omega, int colour, int reverse, double* u,
+                         const double* f) {
+    const Grid<double> g = make_grid<double>(dim, n, k, omega);
+    const int k0 = dim == 3 ? 1 : 0, k1 = dim == 3 ? n - 1 : 1;
+    /* serial loops, optionally in reversed lexicographic order */
+    for (int kk = 0; kk < k1 - k0; ++kk)
+        for (int jj = 1; jj < n - 1; ++jj)
+            for (int ii = 1; ii < n - 1; ++ii) {
+                const int k = reverse ? k1 - 1 - kk : k0 + kk;
+                const int j = reverse ? n - 1 - jj : jj;
+                const int i = reverse ? n - 1 - ii : ii;
+                const int kc = dim == 3 ? k : 0;
+                if (((i + j + kc) & 1) != colour) continue;
+                const idx_t p = at(dim, n, i, j, k);
+                u[p] = smooth_at(g, u, f, p);
+            }
+}
+
+void orc_restrict_f64(int dim, int nf, const double* r, double* fc) { restrict_fw(dim, nf, r, fc); }
+void orc_restrict_f32(int dim, int nf, const float* r, float* fc) { restrict_fw(dim, nf, r, fc); }
+
+void orc_prolong_correct_f64(int dim, int nf, double* u, const double* ec) { prolong_correct(dim, nf, u, ec); }
+void orc_prolong_correct_f32(int dim, int nf, float* u, const float* ec) { prolong_correct(dim, nf, u, ec); }
+
+void orc_coarsest_f64(int dim, const double* k, double* u, const double* f) {
+    const Grid<double> g = make_grid<double>(dim, 3, k, 1.0);
+    coarsest_solve(g, u, f);
+}
+
+double orc_residual_norm_f64(int dim, int n, const double* k, const double* u, const double* f) {
+    const Grid<double> g = make_grid<double>(dim, n, k, 1.0);
+    return residual_norm(g, u, f);
+}
+
+/* One V(nu1,nu2) cycle on the finest grid, u updated in place. */
+int orc_vcycle_f64(int dim, int n, const double* k, int smoother, double omega, int nu1, int nu2, double* u,
+                   const double* f) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n)) return -1;
+    Hierarchy<double> H;
+    build(H, dim, n, k, smoother, omega, nu1, nu2);
+    vcycle(H, 0, u, f);
+    return 0;
+}
+
+/* Same cycle in single precision (u, f, k in float). */
+int orc_vcycle_f32(int dim, int n, const float* k32, int smoother, double omega, int nu1, int nu2, float* u,
+                   const float* f) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n)) return -1;
+    Hierarchy<float> H;
+    std::vector<double> k64;
+    if (k32) k64.assign(k32, k32 + npts(dim, n));
+    build(H, dim, n, k32 ? k64.data() : nullptr, smoother, omega, nu1, nu2);
+    vcycle(H, 0, u, f);
+    return 0;
+}
+
+/* Solve loop of the Layer-4 Application function: rho_0 = ||f - A u||, then
+ * V-cycles until rho_k <= tol * rho_0 or max_cycles.  hist (len max_cycles+1,
+ * may be NULL) receives rho_0..rho_k; *cycles the number of cycles done. */
+int orc_solve_f64(int dim, int n, const double* k, int smoother, double omega, int nu1, int nu2, double* u,
+                  const double* f, double tol, int max_cycles, double* hist, int* cycles) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || max_cycles < 0) return -1;
+    Hierarchy<double> H;
+    build(H, dim, n, k, smoother, omega, nu1, nu2);
+    const Grid<double> g0 = H.grid(0);
+    const double rho0 = residual_norm(g0, u, f);
+    if (hist) hist[0] = rho0;
+    int it = 0;
+    int status = 1;
+    if (rho0 == 0.0) status = 0;
+    while (status == 1 && it < max_cycles) {
+        vcycle(H, 0, u, f);
+        ++it;
+        const double rho = residual_norm(g0, u, f);
+        if (hist) hist[it] = rho;
+        if (rho <= tol * rho0) status = 0;
+    }
+    if (cycles) *cycles = it;
+    return status;
+}
+
+/* One FP64 refinement pass: u += e (inner nodes), r = f - A u in FP64,
+ * r32 = (float) r, returns ||r||_2.  k64 may be NULL. */
+double orc_ir_update_f32(int dim, int n, const double* k64, double* u, const float* e, const double* f, float* r32) {
+    const Grid<double> g = make_grid<double>(dim, n, k64, 1.0);
+    const size_t total = npts(dim, n);
+    const int k0 = dim == 3 ? 1 : 0, k1 = dim == 3 ? n - 1 : 1;
+    for (int k = k0; k < k1; ++k)
+        for (int j = 1; j < n - 1; ++j)
+            for (int i = 1; i < n - 1; ++i) {
+                const idx_t p = at(dim, n, i, j, k);
+                u[p] = u[p] + (double)e[p];
+            }
+    std::vector<double> r(total);
+    residual(g, u, f, r.data());
+    for (size_t p = 0; p < total; ++p) r32[p] = (float)r[p];
+    return residual_norm(g, u, f);
+}
+
+/* Mixed precision: single-precision V-cycles on the correction equation
+ * A e = r inside FP64 iterative refinement.  Each outer step: u += e, r = f -
+ * A u and ||r|| in FP64, r rounded to float, then one float V-cycle from
+ * e = 0.  hist[0..] holds the FP64 residual norms; stop as in orc_solve_f64. */
+int orc_solve_ir_f32(int dim, int n, const double* k64, int smoother, double omega, int nu1, int nu2, double* u,
+                     const double* f, double tol, int max_cycles, double* hist, int* cycles) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || max_cycles < 0) return -1;
+    Hierarchy<float> H;
+    build(H, dim, n, k64, smoother, omega, nu1, nu2);
+    const size_t total = npts(dim, n);
+    std::vector<float> e(total, 0.0f), r32(total, 0.0f);
+    double rho0 = orc_ir_update_f32(dim, n, k64, u, e.data(), f, r32.data());
+    if (hist) hist[0] = rho0;
+    int it = 0;
+    int status = rho0 == 0.0 ? 0 : 1;
+    while (status == 1 && it < max_cycles) {
+        std::fill(e.begin(), e.end(), 0.0f);
+        vcycle(H, 0, e.data(), r32.data());
+        ++it;
+        const double rho = orc_ir_update_f32(dim, n, k64, u, e.data(), f, r32.data());
+        if (hist) hist[it] = rho;
+        if (rho <= tol * rho0) status = 0;
+    }
+    if (cycles) *cycles = it;
+    return status;
+}
+
+} /* extern "C" */

@@ -1,0 +1,55 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of oracle.cpp (a dropped or repeated
+term, a wrong sign, weight, index or colouring), builds it on the CPU and runs
+the pin suite against it in a subprocess: the suite must fail.
+"""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
+
+MUTANTS = {
+    "dropped_neighbour_2d": ("const T s = (u[p - sx] + u[p + sx]) + (u[p - sy] + u[p + sy]);",
+                             "const T s = (u[p - sx] + u[p + sx]) + (u[p - sy] + u[p - sy]);"),
+    "stencil_sign_3d": ("return g.c * (T(6) * uC - s);", "return g.c * (T(6) * uC + s);"),
+    "diag_2d": ("return g.c * (T(4) * uC - s);", "return g.c * (T(5) * uC - s);"),
+    "smoother_sign": ("return u[p] + g.wd * r;", "return u[p] - g.wd * r;"),
+    "colouring_3d": ("if (((i + j + k) & 1) != colour) continue; /* k = 0 in 2D */",
+                     "if (((i + j) & 1) != colour) continue;"),
+    "fw_edge_weight_2d": ("fc[q] = (T(0.25) * r[p] + T(0.125) * edges) + T(0.0625) * corners;",
+                          "fc[q] = (T(0.25) * r[p] + T(0.25) * edges) + T(0.0625) * corners;"),
+    "fw_index_3d": ("const T exz = (r[p - sx - sz] + r[p + sx - sz]) + (r[p - sx + sz] + r[p + sx + sz]);",
+                    "const T exz = (r[p - sx - sy] + r[p + sx - sz]) + (r[p - sx + sz] + r[p + sx + sz]);"),
+    "interp_edge": ("if (m == 1) return T(0.5) * (e[q] + e[q + s[0]]);", "if (m == 1) return T(0.5) * (e[q] + e[q]);"),
+    "interp_cell_3d": ("((e[q + s[2]] + e[q + s[0] + s[2]]) + (e[q + s[1] + s[2]] + e[q + s[0] + s[1] + s[2]])));",
+                       "((e[q + s[2]] + e[q + s[0] + s[2]]) + (e[q + s[1] + s[2]] + e[q + s[0] + s[1]])));"),
+    "no_correction": ("u[p] = u[p] + interp_at(dim, nc, ec, i, j, k);", "u[p] = u[p];"),
+    "kface_arith_mean": ("return ((T(2) * a) * b) / (a + b);", "return (a + b) / T(2);"),
+    "varcoef_face_index": ("const T kyS = kface(k[p - sy], kp), kyC = kface(kp, k[p + sy]);",
+                           "const T kyS = kface(k[p - sx], kp), kyC = kface(kp, k[p + sy]);"),
+    "coarsest_diag": ("diag = g.c * (g.dim == 2 ? T(4) : T(6));", "diag = g.c * (g.dim == 2 ? T(4) : T(4));"),
+    "jacobi_in_place": ("tmp[p] = smooth_at(g, u, f, p);", "u[p] = smooth_at(g, u, f, p); tmp[p] = u[p];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    mut = tmp_path / "oracle_mut.cpp"
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / "liboracle_mut.so"
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                    str(mut), "-o", str(lib)], check=True)
+    env = dict(os.environ, MG_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert res.returncode != 0, f"pins did not catch mutant {name}:\n{res.stdout[-2000:]}"
