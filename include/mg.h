@@ -1,0 +1,169 @@
+/*
+ * mg.h -- C ABI of the MI355X geometric multigrid library (libmg.so).
+ *
+ * The library solves the node-based finite-difference Poisson problem
+ * -Laplace(u) = f on the unit square / cube with zero Dirichlet boundary
+ * (Koestler et al., arXiv:1406.5369, Section 2.1 Eq. (1) and Section 2.2),
+ * and the variable-coefficient problem -div(k grad u) = f in flux form with
+ * harmonic-mean face coefficients, by the recursive multigrid V-cycle of
+ * Algorithm 1 (Section 2.3): omega-Jacobi or red-black Gauss-Seidel smoothing,
+ * full-weighting restriction, bi-/trilinear interpolation and correction, and
+ * an exact solve on the coarsest 3 x 3 (x 3) grid.  The solve loop follows the
+ * Layer-4 Application function (Section 2.4): L2 residual before and after
+ * every cycle.
+ *
+ * Conventions shared by every entry point:
+ *   - A grid has n = 2^L + 1 nodes per axis (L >= 1) including the boundary,
+ *     spacing h = 1/(n-1), and is stored as one dense array of n^dim values,
+ *     x fastest: idx = (k*n + j)*n + i (3D), j*n + i (2D).
+ *   - Array arguments are DEVICE pointers (HIP global memory) unless stated
+ *     otherwise; the caller owns them.  Boundary entries of u must be zero;
+ *     the library reads them as the Dirichlet value and never writes them.
+ *     Boundary entries of f are ignored.
+ *   - 'stream' is a hipStream_t passed as void*; all work is enqueued on it.
+ *     Entry points that return host scalars synchronise that stream.
+ *   - Return value: MG_OK (0) on success, > 0 for a non-fatal outcome
+ *     (MG_ENOTCONV: u is valid but the tolerance was not reached), < 0 for an
+ *     error.  On MG_EINVAL / MG_ENOTSUP nothing was enqueued and u is untouched.
+ *   - A context is not thread-safe and is bound to one device (the current
+ *     device at mg_setup) and one stream.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_ctx mg_ctx;
+
+enum mg_status {
+    MG_OK = 0,
+    MG_ENOTCONV = 1,     /* max_cycles reached before the tolerance; u valid */
+    MG_EINVAL = -1,      /* bad argument (size not 2^L+1, null pointer, ...) */
+    MG_ENOTSUP = -2,     /* valid but unsupported combination */
+    MG_ENOMEM = -3,      /* device allocation failed or budget exceeded */
+    MG_EDEVICE = -4,     /* a HIP runtime call failed */
+    MG_EDIVERGED = -5,   /* residual became NaN/Inf or grew by more than 1e6 */
+    MG_EBUSY = -6        /* server: no slot or budget left for this request now */
+};
+
+enum mg_operator {
+    MG_OP_LAPLACE = 0,       /* constant 5-point (2D) / 7-point (3D) stencil, Section 2.2 */
+    MG_OP_VARCOEF_NODAL = 2  /* -div(k grad u): nodal k, face k = 2 k_p k_q / (k_p + k_q) */
+};
+enum mg_bc { MG_BC_DIRICHLET_ZERO = 0 };
+enum mg_smoother {
+    MG_SMOOTH_RBGS = 0,    /* red-black Gauss-Seidel, red ((i+j[+k]) even) first, Section 2.4 */
+    MG_SMOOTH_WJACOBI = 1  /* weighted Jacobi, Section 2.3; omega 0.8 in Table 2 */
+};
+enum mg_precision {
+    MG_PREC_FP64 = 0,    /* every step in FP64 */
+    MG_PREC_FP32_IR = 1  /* FP32 V-cycles on the correction equation inside FP64 iterative refinement */
+};
+
+typedef struct mg_params {
+    int dim;         /* 2 or 3 (unit square / unit cube, Table 1) */
+    int n;           /* nodes per axis incl. boundary, 2^L + 1, L >= 1 */
+    int op;          /* enum mg_operator */
+    const double* k; /* MG_OP_VARCOEF_NODAL: device pointer to n^dim positive FP64 nodal
+                        coefficients, copied during mg_setup; otherwise ignored */
+    int bc;          /* enum mg_bc (only MG_BC_DIRICHLET_ZERO) */
+    int smoother;    /* enum mg_smoother */
+    double omega;    /* relaxation weight; <= 0 selects the paper's value (1.0 RBGS, 0.8 Jacobi) */
+    int nu1, nu2;    /* pre- and post-smoothing sweeps (paper: 2, 2); 0..16 */
+    int precision;   /* enum mg_precision */
+} mg_params;
+
+/* Build the level hierarchy n, (n-1)/2+1, ..., 3 (Section 2.2 coarsening by 2;
+ * Table 2 caption: down to fewer than three unknowns per direction) and
+ * allocate every coarse level and scratch buffer on the current device.
+ * 'stream' is the hipStream_t all later work of this context goes to.
+ * Errors: MG_EINVAL (null p/out, bad dim/n/nu/bc/op/smoother, var-coef without k),
+ * MG_ENOMEM, MG_EDEVICE.  On error *out is NULL. */
+int mg_setup(const mg_params* p, void* stream, mg_ctx** out);
+
+/* Release every device buffer of the context (after finishing its work). NULL is a no-op. */
+void mg_destroy(mg_ctx* ctx);
+
+/* One V(nu1, nu2) cycle of Algorithm 1 on u (in/out, device) for rhs f (device).
+ * With MG_PREC_FP32_IR it is one refinement step: r = f - A u (FP64), one FP32
+ * V-cycle on A e = r from e = 0, u += e (FP64).  Asynchronous on the stream. */
+int mg_vcycle(mg_ctx* ctx, double* u, const double* f);
+
+/* Solve loop of the Layer-4 Application function: rho_0 = ||f - A u||_2, then
+ * cycles (or refinement steps) until rho_k <= tol * rho_0 or max_cycles.
+ * u: device, in (initial guess) / out.  cycles_done, res_hist: HOST pointers,
+ * may be NULL; res_hist needs max_cycles + 1 doubles and receives rho_0..rho_k
+ * (FP64 Euclidean norms over inner nodes).  Synchronises the stream.
+ * Returns MG_OK, MG_ENOTCONV, MG_EDIVERGED (u then holds the last iterate). */
+int mg_solve(mg_ctx* ctx, double* u, const double* f, double tol, int max_cycles, int* cycles_done,
+             double* res_hist);
+
+/* FP64 residual norm sqrt(sum over inner nodes of (f - A u)^2) into *out (HOST).
+ * Synchronises the stream. */
+int mg_residual_norm(mg_ctx* ctx, const double* u, const double* f, double* out);
+
+/* Number of levels of the context's hierarchy (>= 1), or a negative status. */
+int mg_num_levels(const mg_ctx* ctx);
+
+/* Human-readable name of a status code. */
+const char* mg_strerror(int code);
+
+/* ---------------------------------------------------------------------------
+ * Single-level operations (one kernel each; the steps of Algorithm 1).  They
+ * run one grid level with no context: dim 2/3, n = 2^L+1 >= 5 (n >= 3 for the
+ * coarsest solve), dtype 0 = FP64 / 1 = FP32 for every array argument.
+ * 'k' is null (Laplacian) or the nodal coefficient of this level.  'by' and
+ * 'zchunk' pick the tile shape (0 = library default): by in {8, 16, 32},
+ * zchunk >= 1 (3D only).  Asynchronous on 'stream'.
+ * ------------------------------------------------------------------------- */
+
+/* One smoothing sweep (Section 2.4 GaussSeidel / Section 2.3 Jacobi) from u_in
+ * to u_out (out of place; u_out's boundary is not written).  zero_guess != 0
+ * treats u_in as identically zero (u_in may then be NULL).  ec, if not NULL,
+ * is the coarse-grid correction ((n-1)/2+1 nodes per axis) added by
+ * interpolation to u_in before the sweep (Algorithm 1: coarse-grid correction
+ * followed by post-smoothing). */
+int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const void* k, const void* u_in,
+                    const void* f, void* u_out, const void* ec, int zero_guess, int by, int zchunk, void* stream);
+
+/* fc = full weighting of r = f - A u (Algorithm 1: residual and restriction)
+ * on the inner nodes of the coarse grid ((n-1)/2+1 per axis); fc's boundary is not written. */
+int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const void* u, const void* f, void* fc,
+                               int by, int zchunk, void* stream);
+
+/* u += P ec on inner fine nodes (Section 2.4 interpolatecorr; bilinear / trilinear P). */
+int mg_level_prolong_correct(int dim, int n, int dtype, void* u, const void* ec, void* stream);
+
+/* Coarsest grid (n = 3): u = f / diag at the single inner node. */
+int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f, void* stream);
+
+/* FP64 refinement pass: u_out = u_in + e on inner nodes, r = (float)(f - A u_out)
+ * on inner nodes (FP64 operator, FP64 k or NULL), *norm_out (HOST) = ||f - A u_out||_2.
+ * e and r are FP32 arrays; u_out's and r's boundaries are not written.
+ * Synchronises the stream. */
+int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
+                       double* u_out, float* r, double* norm_out, int by, int zchunk, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Measurement hooks.
+ * ------------------------------------------------------------------------- */
+
+/* When on, every finest-level smoothing launch of the context is bracketed by
+ * HIP events recorded on the context's stream; mg_prof_read returns the
+ * number of such launches and their summed duration in ms (and resets). */
+int mg_prof_enable(mg_ctx* ctx, int on);
+int mg_prof_read(mg_ctx* ctx, int* launches, double* total_ms);
+
+/* Plain device-to-device copy kernel of 'bytes' bytes (multiple of 16):
+ * calibration of the HBM traffic counters against a known byte count. */
+int mg_copy_kernel(void* dst, const void* src, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H */

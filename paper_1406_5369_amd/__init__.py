@@ -1,0 +1,320 @@
+"""Python binding of libmg.so, the MI355X geometric multigrid library.
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  Functions carry the C names of ``include/mg.h``; arrays are torch
+tensors on the HIP device (their ``data_ptr()`` is passed), the stream is
+torch's current stream unless one is given.  Importing this package never
+touches a GPU; the first call that needs ``libmg.so`` loads it and raises if
+it has not been built (``python -m paper_1406_5369_amd.build``).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from dataclasses import dataclass
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mg.h")
+
+# status codes (enum mg_status)
+MG_OK, MG_ENOTCONV, MG_EINVAL, MG_ENOTSUP, MG_ENOMEM, MG_EDEVICE, MG_EDIVERGED, MG_EBUSY = 0, 1, -1, -2, -3, -4, -5, -6
+OP_LAPLACE, OP_VARCOEF_NODAL = 0, 2
+BC_DIRICHLET_ZERO = 0
+SMOOTH_RBGS, SMOOTH_JACOBI = 0, 1
+PREC_FP64, PREC_FP32_IR = 0, 1
+
+
+class MGError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int),
+        ("n", C.c_int),
+        ("op", C.c_int),
+        ("k", C.c_void_p),
+        ("bc", C.c_int),
+        ("smoother", C.c_int),
+        ("omega", C.c_double),
+        ("nu1", C.c_int),
+        ("nu2", C.c_int),
+        ("precision", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmg.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1406_5369_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        i, d, p, sz = C.c_int, C.c_double, C.c_void_p, C.c_size_t
+        sig = {
+            "mg_setup": (i, [C.POINTER(_Params), p, C.POINTER(p)]),
+            "mg_destroy": (None, [p]),
+            "mg_vcycle": (i, [p, p, p]),
+            "mg_solve": (i, [p, p, p, d, i, C.POINTER(i), p]),
+            "mg_residual_norm": (i, [p, p, p, C.POINTER(d)]),
+            "mg_num_levels": (i, [p]),
+            "mg_strerror": (C.c_char_p, [i]),
+            "mg_level_smooth": (i, [i, i, i, i, d, p, p, p, p, p, i, i, i, p]),
+            "mg_level_residual_restrict": (i, [i, i, i, p, p, p, p, i, i, p]),
+            "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
+            "mg_level_coarsest": (i, [i, i, p, p, p, p]),
+            "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, p]),
+            "mg_prof_enable": (i, [p, i]),
+            "mg_prof_read": (i, [p, C.POINTER(i), C.POINTER(d)]),
+            "mg_copy_kernel": (i, [p, p, sz, p]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of every function declared in include/mg.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z0-9_]+)\s*\(", text)))
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().mg_strerror(int(code)).decode()
+    except RuntimeError:
+        return f"status {code}"
+
+
+def _check(code: int, where: str, ok=(MG_OK,)) -> int:
+    if code not in ok:
+        raise MGError(code, where)
+    return code
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dptr(t, dtype=None, shape=None, name="array"):
+    """Device pointer of a contiguous torch tensor on the HIP device (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the HIP device")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+@dataclass
+class Params:
+    """Problem and solver parameters (struct mg_params).  Defaults are the paper's:
+    V(2,2) cycles (Section 4), RBGS with omega = 1.0 (Section 2.3 Layer-3
+    parameters) or Jacobi with omega = 0.8 (Table 2 caption)."""
+
+    dim: int
+    n: int
+    op: int = OP_LAPLACE
+    k: object = None  # torch float64 tensor of shape (n,)*dim for OP_VARCOEF_NODAL
+    bc: int = BC_DIRICHLET_ZERO
+    smoother: int = SMOOTH_RBGS
+    omega: float = 0.0
+    nu1: int = 2
+    nu2: int = 2
+    precision: int = PREC_FP64
+
+    def __post_init__(self):
+        if self.omega <= 0.0:
+            self.omega = 1.0 if self.smoother == SMOOTH_RBGS else 0.8
+
+    @property
+    def shape(self):
+        return (self.n,) * self.dim
+
+    def to_c(self) -> _Params:
+        import torch
+
+        kp = _dptr(self.k, torch.float64, self.shape, "k") if self.k is not None else None
+        return _Params(self.dim, self.n, self.op, kp, self.bc, self.smoother, self.omega, self.nu1, self.nu2,
+                       self.precision)
+
+
+def mg_setup(params: Params, stream=None) -> int:
+    """Create a context (returns the opaque handle as an int)."""
+    cp = params.to_c()
+    out = C.c_void_p()
+    _check(lib().mg_setup(C.byref(cp), _stream(stream), C.byref(out)), "mg_setup")
+    return out.value
+
+
+def mg_destroy(ctx: int) -> None:
+    lib().mg_destroy(ctx)
+
+
+def mg_num_levels(ctx: int) -> int:
+    return lib().mg_num_levels(ctx)
+
+
+def mg_vcycle(ctx: int, u, f) -> None:
+    import torch
+
+    _check(lib().mg_vcycle(ctx, _dptr(u, torch.float64, name="u"), _dptr(f, torch.float64, name="f")), "mg_vcycle")
+
+
+def mg_solve(ctx: int, u, f, tol: float = 1e-8, max_cycles: int = 50):
+    """Returns (status, cycles, residual history as a list)."""
+    import torch
+
+    hist = (C.c_double * (max_cycles + 1))()
+    cyc = C.c_int(0)
+    st = lib().mg_solve(ctx, _dptr(u, torch.float64, name="u"), _dptr(f, torch.float64, name="f"), float(tol),
+                        int(max_cycles), C.byref(cyc), hist)
+    _check(st, "mg_solve", ok=(MG_OK, MG_ENOTCONV, MG_EDIVERGED))
+    return st, cyc.value, list(hist[: cyc.value + 1])
+
+
+def mg_residual_norm(ctx: int, u, f) -> float:
+    import torch
+
+    out = C.c_double(0.0)
+    _check(lib().mg_residual_norm(ctx, _dptr(u, torch.float64, name="u"), _dptr(f, torch.float64, name="f"),
+                                  C.byref(out)), "mg_residual_norm")
+    return out.value
+
+
+def _dtype_code(t):
+    import torch
+
+    if t.dtype == torch.float64:
+        return 0
+    if t.dtype == torch.float32:
+        return 1
+    raise TypeError("arrays must be float64 or float32")
+
+
+def mg_level_smooth(u_in, f, u_out, smoother=SMOOTH_RBGS, omega=0.0, k=None, ec=None, zero_guess=False, by=0,
+                    zchunk=0, stream=None) -> None:
+    dim, n = f.dim(), f.shape[0]
+    if omega <= 0.0:
+        omega = 1.0 if smoother == SMOOTH_RBGS else 0.8
+    dt = f.dtype
+    _check(lib().mg_level_smooth(dim, n, _dtype_code(f), smoother, float(omega), _dptr(k, dt, f.shape, "k"),
+                                 _dptr(u_in, dt, f.shape, "u_in"), _dptr(f, dt, None, "f"),
+                                 _dptr(u_out, dt, f.shape, "u_out"), _dptr(ec, dt, None, "ec"), int(zero_guess),
+                                 by, zchunk, _stream(stream)), "mg_level_smooth")
+
+
+def mg_level_residual_restrict(u, f, fc, k=None, by=0, zchunk=0, stream=None) -> None:
+    dim, n = f.dim(), f.shape[0]
+    dt = f.dtype
+    nc = (n - 1) // 2 + 1
+    _check(lib().mg_level_residual_restrict(dim, n, _dtype_code(f), _dptr(k, dt, f.shape, "k"),
+                                            _dptr(u, dt, f.shape, "u"), _dptr(f, dt, None, "f"),
+                                            _dptr(fc, dt, (nc,) * dim, "fc"), by, zchunk, _stream(stream)),
+           "mg_level_residual_restrict")
+
+
+def mg_level_prolong_correct(u, ec, stream=None) -> None:
+    dim, n = u.dim(), u.shape[0]
+    dt = u.dtype
+    nc = (n - 1) // 2 + 1
+    _check(lib().mg_level_prolong_correct(dim, n, _dtype_code(u), _dptr(u, dt, None, "u"),
+                                          _dptr(ec, dt, (nc,) * dim, "ec"), _stream(stream)),
+           "mg_level_prolong_correct")
+
+
+def mg_level_coarsest(u, f, k=None, stream=None) -> None:
+    dim = f.dim()
+    dt = f.dtype
+    _check(lib().mg_level_coarsest(dim, _dtype_code(f), _dptr(k, dt, (3,) * dim, "k"), _dptr(u, dt, (3,) * dim, "u"),
+                                   _dptr(f, dt, (3,) * dim, "f"), _stream(stream)), "mg_level_coarsest")
+
+
+def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, stream=None) -> float:
+    import torch
+
+    dim, n = f.dim(), f.shape[0]
+    sh = f.shape
+    out = C.c_double(0.0)
+    _check(lib().mg_level_ir_update(dim, n, _dptr(k, torch.float64, sh, "k"), _dptr(u_in, torch.float64, sh, "u_in"),
+                                    _dptr(e, torch.float32, sh, "e"), _dptr(f, torch.float64, sh, "f"),
+                                    _dptr(u_out, torch.float64, sh, "u_out"), _dptr(r, torch.float32, sh, "r"),
+                                    C.byref(out), by, zchunk, _stream(stream)), "mg_level_ir_update")
+    return out.value
+
+
+def mg_prof_enable(ctx: int, on: bool = True) -> None:
+    _check(lib().mg_prof_enable(ctx, int(on)), "mg_prof_enable")
+
+
+def mg_prof_read(ctx: int):
+    """(launches, total ms) of the finest-level smoothing launches since enabling."""
+    n = C.c_int(0)
+    ms = C.c_double(0.0)
+    _check(lib().mg_prof_read(ctx, C.byref(n), C.byref(ms)), "mg_prof_read")
+    return n.value, ms.value
+
+
+def mg_copy_kernel(dst, src, stream=None) -> None:
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy: size mismatch")
+    _check(lib().mg_copy_kernel(_dptr(dst), _dptr(src), nbytes, _stream(stream)), "mg_copy_kernel")
+
+
+class Solver:
+    """Owns one context; convenience wrapper over the mg_* calls."""
+
+    def __init__(self, params: Params, stream=None):
+        self.params = params
+        self.ctx = mg_setup(params, stream)
+
+    def vcycle(self, u, f):
+        mg_vcycle(self.ctx, u, f)
+
+    def solve(self, u, f, tol=1e-8, max_cycles=50):
+        return mg_solve(self.ctx, u, f, tol, max_cycles)
+
+    def residual_norm(self, u, f):
+        return mg_residual_norm(self.ctx, u, f)
+
+    @property
+    def num_levels(self):
+        return mg_num_levels(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            mg_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,684 @@
+// C ABI of libmg.so (declared in include/mg.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "mg_solver.h"
+
+using namespace mg;
+
+namespace {
+
+bool valid_edge(int n) { return n >= 3 && ((n - 1) & (n - 2)) == 0; }
+
+int dev_status(hipError_t e) {
+    if (e == hipSuccess) return MG_OK;
+    if (e == hipErrorOutOfMemory) return MG_ENOMEM;
+    return MG_EDEVICE;
+}
+
+#define CK(x)                                 \
+    do {                                      \
+        hipError_t e_ = (x);                  \
+        if (e_ != hipSuccess) return dev_status(e_); \
+    } while (0)
+
+double level_c(int n) {
+    const double h = 1.0 / (double)(n - 1);
+    return 1.0 / (h * h);
+}
+double level_wd(int dim, int n, double omega) {
+    const double h = 1.0 / (double)(n - 1);
+    return (omega * (h * h)) / (2.0 * (double)dim);
+}
+
+hipError_t zalloc(void** p, size_t bytes, hipStream_t s) {
+    *p = nullptr;
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    return hipMemsetAsync(*p, 0, bytes, s);
+}
+
+void ffree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+// Build a hierarchy of 'elem'-byte values.  Level 0 u/f are left null when
+// caller-owned (own0 = false).  k0: device nodal coefficient of level 0 in the
+// same precision (or null).
+hipError_t build_levels(Levels& L, int dim, const std::vector<int>& n, int elem, bool own0, const void* k0,
+                        hipStream_t s) {
+    L.dim = dim;
+    L.nlev = (int)n.size();
+    L.elem = elem;
+    L.n = n;
+    L.u.assign(n.size(), nullptr);
+    L.t.assign(n.size(), nullptr);
+    L.f.assign(n.size(), nullptr);
+    L.k.assign(n.size(), nullptr);
+    L.own_u.assign(n.size(), 0);
+    L.own_f.assign(n.size(), 0);
+    for (size_t l = 0; l < n.size(); ++l) {
+        const size_t bytes = npts(dim, n[l]) * (size_t)elem;
+        if (l > 0 || own0) {
+            hipError_t e = zalloc(&L.u[l], bytes, s);
+            if (e != hipSuccess) return e;
+            e = zalloc(&L.f[l], bytes, s);
+            if (e != hipSuccess) return e;
+            L.own_u[l] = 1;
+            L.own_f[l] = 1;
+        }
+        if (n[l] > 3) {
+            hipError_t e = zalloc(&L.t[l], bytes, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    if (k0) {
+        L.k[0] = const_cast<void*>(k0);
+        for (size_t l = 1; l < n.size(); ++l) {
+            const size_t bytes = npts(dim, n[l]) * (size_t)elem;
+            hipError_t e = zalloc(&L.k[l], bytes, s);
+            if (e != hipSuccess) return e;
+            e = elem == 8 ? launch_inject<double, double>(dim, n[l - 1], (const double*)L.k[l - 1], n[l],
+                                                          (double*)L.k[l], s)
+                          : launch_inject<float, float>(dim, n[l - 1], (const float*)L.k[l - 1], n[l],
+                                                        (float*)L.k[l], s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+void free_levels(Levels& L) {
+    for (size_t l = 0; l < L.u.size(); ++l) {
+        if (L.own_u[l]) ffree(L.u[l]);
+        if (L.own_f[l]) ffree(L.f[l]);
+        ffree(L.t[l]);
+        if (l > 0 || L.own_k0) ffree(L.k[l]);
+    }
+    L.u.clear();
+    L.t.clear();
+    L.f.clear();
+    L.k.clear();
+}
+
+// One descriptor per level for a single-instance hierarchy.
+hipError_t build_groups(std::vector<Group>& G, const Levels& L, const Problem& P, const int* done, hipStream_t s) {
+    G.assign((size_t)L.nlev, Group{});
+    for (int l = 0; l < L.nlev; ++l) {
+        Group& g = G[(size_t)l];
+        g.n = L.n[(size_t)l];
+        g.ninst = 1;
+        GridDesc d{};
+        d.u = L.u[(size_t)l];
+        d.t = L.t[(size_t)l];
+        d.f = L.f[(size_t)l];
+        d.k = L.k[(size_t)l];
+        d.uc = l + 1 < L.nlev ? L.u[(size_t)l + 1] : nullptr;
+        d.fc = l + 1 < L.nlev ? L.f[(size_t)l + 1] : nullptr;
+        d.done = done;
+        d.n = g.n;
+        d.inst = 0;
+        d.c = level_c(g.n);
+        d.wd = level_wd(P.dim, g.n, P.omega);
+        d.omega = P.omega;
+        g.h.assign(1, d);
+        hipError_t e = hipMalloc((void**)&g.d, sizeof(GridDesc));
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(g.d, g.h.data(), sizeof(GridDesc), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(s);
+}
+
+void free_groups(std::vector<Group>& G) {
+    for (auto& g : G) ffree(g.d);
+    G.clear();
+}
+
+int validate(const mg_params* p) {
+    if (!p) return MG_EINVAL;
+    if (p->dim != 2 && p->dim != 3) return MG_EINVAL;
+    if (!valid_edge(p->n)) return MG_EINVAL;
+    if (p->bc != MG_BC_DIRICHLET_ZERO) return MG_ENOTSUP;
+    if (p->op != MG_OP_LAPLACE && p->op != MG_OP_VARCOEF_NODAL) return MG_ENOTSUP;
+    if (p->op == MG_OP_VARCOEF_NODAL && !p->k) return MG_EINVAL;
+    if (p->smoother != MG_SMOOTH_RBGS && p->smoother != MG_SMOOTH_WJACOBI) return MG_EINVAL;
+    if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 > 16 || p->nu2 > 16) return MG_EINVAL;
+    if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_FP32_IR) return MG_ENOTSUP;
+    if (!(p->omega == p->omega) || p->omega > 2.0) return MG_EINVAL;
+    if (p->dim == 3 && (size_t)p->n > 2049) return MG_EINVAL;
+    if ((size_t)p->n > 65537) return MG_EINVAL;
+    return MG_OK;
+}
+
+void destroy(mg_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    free_groups(c->G64);
+    free_groups(c->G32);
+    free_levels(c->L64);
+    free_levels(c->L32);
+    ffree(c->d_ir);
+    ffree(c->d_top);
+    ffree(c->u64_scratch);
+    ffree(c->k64);
+    ffree(c->d_partial);
+    ffree(c->d_norm);
+    ffree(c->d_norm0);
+    ffree(c->d_ctrl);
+    ffree(c->d_hist);
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
+    for (auto e : c->prof_ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+// Point the level-0 descriptors at the caller's u and f (only when they change).
+int bind(mg_ctx* c, const void* u, const void* f) {
+    if (!u || !f) return MG_EINVAL;
+    if (u == c->bound_u && f == c->bound_f) return MG_OK;
+    c->h_top.u = const_cast<void*>(u);
+    c->h_top.f = f;
+    CK(hipMemcpyAsync(c->d_top, &c->h_top, sizeof(GridDesc), hipMemcpyHostToDevice, c->stream));
+    if (c->p.precision == MG_PREC_FP64) {
+        GridDesc& d = c->G64[0].h[0];
+        d.u = const_cast<void*>(u);
+        d.f = f;
+        CK(hipMemcpyAsync(c->G64[0].d, &d, sizeof(GridDesc), hipMemcpyHostToDevice, c->stream));
+    } else {
+        c->h_ir.u[0] = (double*)const_cast<void*>(u);
+        c->h_ir.f = (const double*)f;
+        CK(hipMemcpyAsync(c->d_ir, &c->h_ir, sizeof(IRDesc), hipMemcpyHostToDevice, c->stream));
+    }
+    CK(hipStreamSynchronize(c->stream));  // the host descriptors may change again right away
+    c->bound_u = u;
+    c->bound_f = f;
+    return MG_OK;
+}
+
+int* ctl_done(mg_ctx* c) { return c->d_ctrl; }
+int* ctl_steps(mg_ctx* c) { return c->d_ctrl + 1; }
+int* ctl_status(mg_ctx* c) { return c->d_ctrl + 2; }
+
+// FP64 norm of the bound (u, f) into d_norm (partials + fixed-order finalize).
+hipError_t enqueue_norm(mg_ctx* c, hipStream_t s) {
+    const bool var = c->prob.var;
+    const int nparts = norm_tiles(c->p.dim, c->p.n, c->t64.norm);
+    hipError_t e = launch_norm(c->p.dim, var, c->d_top, 1, c->p.n, 0, c->d_partial, c->pstride, c->t64.norm, s);
+    if (e != hipSuccess) return e;
+    return launch_norm_finalize(c->d_partial, c->pstride, nparts, 0, 1, c->d_norm, s);
+}
+
+hipError_t enqueue_ir(mg_ctx* c, int sel, int flags, hipStream_t s) {
+    const int nparts = norm_tiles(c->p.dim, c->p.n, c->t64.norm);
+    hipError_t e = launch_ir_update(c->p.dim, c->prob.var, c->d_ir, 1, c->p.n, sel, flags, c->d_partial, c->pstride,
+                                    c->t64.norm, s);
+    if (e != hipSuccess) return e;
+    return launch_norm_finalize(c->d_partial, c->pstride, nparts, 0, 1, c->d_norm, s);
+}
+
+// K solve steps (cycle + residual norm + stop test), IR steps alternate the
+// FP64 ping-pong starting from sel 0 (K even keeps the parity per chunk).
+hipError_t enqueue_steps(mg_ctx* c, int K, double tol, int max_cycles, hipStream_t s, bool prof) {
+    hipEvent_t* pev = prof ? c->prof_ev.data() : nullptr;
+    int* pn = prof ? &c->prof_n : nullptr;
+    const int pcap = (int)c->prof_ev.size();
+    for (int i = 0; i < K; ++i) {
+        hipError_t e;
+        if (c->p.precision == MG_PREC_FP64) {
+            e = vcycle<double>(c->prob, c->G64, false, c->t64, s, pev, pn, pcap);
+            if (e != hipSuccess) return e;
+            e = enqueue_norm(c, s);
+        } else {
+            e = vcycle<float>(c->prob, c->G32, true, c->t32, s, pev, pn, pcap);
+            if (e != hipSuccess) return e;
+            e = enqueue_ir(c, i & 1, 0, s);
+        }
+        if (e != hipSuccess) return e;
+        e = launch_stop_test(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist,
+                             c->hist_cap, tol, max_cycles, 1, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int ensure_hist(mg_ctx* c, int cap) {
+    if (cap <= c->hist_cap) return MG_OK;
+    ffree(c->d_hist);
+    c->d_hist = nullptr;
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
+    c->h_pin = nullptr;
+    c->hist_cap = 0;
+    CK(hipMalloc((void**)&c->d_hist, sizeof(double) * (size_t)cap));
+    CK(hipHostMalloc((void**)&c->h_pin, sizeof(double) * (size_t)(cap + 8), hipHostMallocDefault));
+    c->hist_cap = cap;
+    // the hist pointer is baked into captured graphs
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    return MG_OK;
+}
+
+int run_chunk(mg_ctx* c, int K, double tol, int max_cycles) {
+    const bool use_graph = !c->prof_on && c->use_graphs;
+    if (!use_graph) {
+        CK(enqueue_steps(c, K, tol, max_cycles, c->stream, c->prof_on));
+        return MG_OK;
+    }
+    if (!c->graph || c->graph_steps != K || c->graph_tol != tol || c->graph_max != max_cycles) {
+        if (c->graph) {
+            (void)hipGraphExecDestroy(c->graph);
+            c->graph = nullptr;
+        }
+        if (!c->cap_stream) CK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        CK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_steps(c, K, tol, max_cycles, c->cap_stream, false);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return dev_status(e);
+        }
+        CK(e2);
+        hipError_t e3 = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        CK(e3);
+        c->graph_steps = K;
+        c->graph_tol = tol;
+        c->graph_max = max_cycles;
+    }
+    CK(hipGraphLaunch(c->graph, c->stream));
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mg_strerror(int code) {
+    switch (code) {
+        case MG_OK: return "ok";
+        case MG_ENOTCONV: return "not converged within max_cycles";
+        case MG_EINVAL: return "invalid argument";
+        case MG_ENOTSUP: return "unsupported combination";
+        case MG_ENOMEM: return "out of device memory or budget";
+        case MG_EDEVICE: return "HIP runtime error";
+        case MG_EDIVERGED: return "diverged (NaN/Inf or residual growth)";
+        case MG_EBUSY: return "no capacity for the request now";
+        default: return "unknown status";
+    }
+}
+
+int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
+    if (!out) return MG_EINVAL;
+    *out = nullptr;
+    int v = validate(p);
+    if (v != MG_OK) return v;
+    mg_ctx* c = new (std::nothrow) mg_ctx();
+    if (!c) return MG_ENOMEM;
+    c->p = *p;
+    if (c->p.omega <= 0.0) c->p.omega = p->smoother == MG_SMOOTH_RBGS ? 1.0 : 0.8;
+    c->stream = (hipStream_t)stream;
+    c->use_graphs = std::getenv("MG_NO_GRAPHS") == nullptr;
+    (void)hipGetDevice(&c->device);
+    const int dim = p->dim;
+    c->prob = Problem{dim, p->smoother, p->nu1, p->nu2, c->p.omega, p->op == MG_OP_VARCOEF_NODAL};
+    for (int m = p->n;; m = (m - 1) / 2 + 1) {
+        c->n.push_back(m);
+        if (m == 3) break;
+    }
+    c->nlev = (int)c->n.size();
+    c->t64 = default_tiles(dim, 8);
+    c->t32 = default_tiles(dim, 4);
+    hipStream_t s = c->stream;
+    const size_t N = npts(dim, p->n);
+    hipError_t e = hipSuccess;
+#define SETUP_CK(x)                \
+    do {                           \
+        e = (x);                   \
+        if (e != hipSuccess) {     \
+            destroy(c);            \
+            return dev_status(e);  \
+        }                          \
+    } while (0)
+    if (c->prob.var) {
+        SETUP_CK(hipMalloc((void**)&c->k64, N * sizeof(double)));
+        SETUP_CK(hipMemcpyAsync(c->k64, p->k, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    SETUP_CK(hipMalloc((void**)&c->d_ctrl, 3 * sizeof(int)));
+    SETUP_CK(launch_fill_int(c->d_ctrl, 0, 3, s));
+    if (p->precision == MG_PREC_FP64) {
+        SETUP_CK(build_levels(c->L64, dim, c->n, 8, false, c->k64, s));
+        SETUP_CK(build_groups(c->G64, c->L64, c->prob, ctl_done(c), s));
+    } else {
+        SETUP_CK(build_levels(c->L32, dim, c->n, 4, true, nullptr, s));
+        if (c->prob.var) {
+            void* k32 = nullptr;
+            SETUP_CK(zalloc(&k32, N * sizeof(float), s));
+            SETUP_CK((launch_convert<double, float>(N, c->k64, (float*)k32, s)));
+            c->L32.k[0] = k32;
+            for (int l = 1; l < c->nlev; ++l) {
+                SETUP_CK(zalloc(&c->L32.k[(size_t)l], npts(dim, c->n[(size_t)l]) * sizeof(float), s));
+                SETUP_CK((launch_inject<float, float>(dim, c->n[(size_t)l - 1],
+                                                      (const float*)c->L32.k[(size_t)l - 1], c->n[(size_t)l],
+                                                      (float*)c->L32.k[(size_t)l], s)));
+            }
+            c->L32.own_k0 = true;
+        }
+        SETUP_CK(build_groups(c->G32, c->L32, c->prob, ctl_done(c), s));
+        SETUP_CK(zalloc((void**)&c->u64_scratch, N * sizeof(double), s));
+        c->h_ir = IRDesc{};
+        c->h_ir.u[0] = nullptr;
+        c->h_ir.u[1] = c->u64_scratch;
+        c->h_ir.e = (const float*)c->L32.u[0];
+        c->h_ir.f = nullptr;
+        c->h_ir.k = c->k64;
+        c->h_ir.r = (float*)c->L32.f[0];
+        c->h_ir.done = ctl_done(c);
+        c->h_ir.n = p->n;
+        c->h_ir.inst = 0;
+        c->h_ir.c = level_c(p->n);
+        SETUP_CK(hipMalloc((void**)&c->d_ir, sizeof(IRDesc)));
+        SETUP_CK(hipMemcpyAsync(c->d_ir, &c->h_ir, sizeof(IRDesc), hipMemcpyHostToDevice, s));
+    }
+    // FP64 view of the finest level for residual norms
+    c->h_top = GridDesc{};
+    c->h_top.k = c->k64;
+    c->h_top.n = p->n;
+    c->h_top.inst = 0;
+    c->h_top.c = level_c(p->n);
+    c->h_top.wd = level_wd(dim, p->n, c->p.omega);
+    c->h_top.omega = c->p.omega;
+    SETUP_CK(hipMalloc((void**)&c->d_top, sizeof(GridDesc)));
+    SETUP_CK(hipMemcpyAsync(c->d_top, &c->h_top, sizeof(GridDesc), hipMemcpyHostToDevice, s));
+    c->pstride = std::max(1, norm_tiles(dim, p->n, c->t64.norm));
+    SETUP_CK(hipMalloc((void**)&c->d_partial, sizeof(double) * (size_t)c->pstride));
+    SETUP_CK(hipMalloc((void**)&c->d_norm, sizeof(double)));
+    SETUP_CK(hipMalloc((void**)&c->d_norm0, sizeof(double)));
+    c->prof_ev.resize(512);
+    for (auto& ev : c->prof_ev) SETUP_CK(hipEventCreate(&ev));
+    int r = ensure_hist(c, 64);
+    if (r != MG_OK) {
+        destroy(c);
+        return r;
+    }
+    SETUP_CK(hipStreamSynchronize(s));
+#undef SETUP_CK
+    *out = c;
+    return MG_OK;
+}
+
+void mg_destroy(mg_ctx* c) { destroy(c); }
+
+int mg_num_levels(const mg_ctx* c) { return c ? c->nlev : MG_EINVAL; }
+
+int mg_vcycle(mg_ctx* c, double* u, const double* f) {
+    if (!c) return MG_EINVAL;
+    int r = bind(c, u, f);
+    if (r != MG_OK) return r;
+    CK(launch_fill_int(ctl_done(c), 0, 1, c->stream));
+    if (c->p.precision == MG_PREC_FP64) {
+        CK(vcycle<double>(c->prob, c->G64, false, c->t64, c->stream, nullptr, nullptr, 0));
+    } else {
+        CK(enqueue_ir(c, 0, IR_NO_UPDATE, c->stream));
+        CK(vcycle<float>(c->prob, c->G32, true, c->t32, c->stream, nullptr, nullptr, 0));
+        CK(enqueue_ir(c, 0, 0, c->stream));
+        CK(hipMemcpyAsync(u, c->u64_scratch, npts(c->p.dim, c->p.n) * sizeof(double), hipMemcpyDeviceToDevice,
+                          c->stream));
+    }
+    return MG_OK;
+}
+
+int mg_residual_norm(mg_ctx* c, const double* u, const double* f, double* out) {
+    if (!c || !out) return MG_EINVAL;
+    int r = bind(c, u, f);
+    if (r != MG_OK) return r;
+    CK(enqueue_norm(c, c->stream));
+    CK(hipMemcpyAsync(c->h_pin, c->d_norm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CK(hipStreamSynchronize(c->stream));
+    *out = c->h_pin[0];
+    return MG_OK;
+}
+
+int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, int* cycles_done, double* res_hist) {
+    if (!c || max_cycles < 0 || !(tol >= 0.0)) return MG_EINVAL;
+    int r = bind(c, u, f);
+    if (r != MG_OK) return r;
+    r = ensure_hist(c, max_cycles + 1);
+    if (r != MG_OK) return r;
+    hipStream_t s = c->stream;
+    const bool ir = c->p.precision == MG_PREC_FP32_IR;
+    // rho_0
+    if (ir) CK(enqueue_ir(c, 0, IR_NO_UPDATE, s));
+    else CK(enqueue_norm(c, s));
+    CK(launch_solve_init(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist, c->hist_cap, 1,
+                         s));
+    // cycles in chunks of K; kernels of a finished solve exit at once
+    const size_t N = npts(c->p.dim, c->p.n);
+    int K = N > (size_t)(1 << 20) ? 4 : 10;
+    if (ir && (K & 1)) ++K;
+    int steps = 0, status = 1, done = 0;
+    CK(hipMemcpyAsync(c->h_pin, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    done = ((int*)c->h_pin)[0];
+    status = ((int*)c->h_pin)[2];
+    int enqueued = 0;
+    while (!done && enqueued < max_cycles) {
+        const int k = ir ? K : std::min(K, max_cycles - enqueued);
+        r = run_chunk(c, k, tol, max_cycles);
+        if (r != MG_OK) return r;
+        enqueued += k;
+        CK(hipMemcpyAsync(c->h_pin, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        done = ((int*)c->h_pin)[0];
+        steps = ((int*)c->h_pin)[1];
+        status = ((int*)c->h_pin)[2];
+    }
+    CK(hipMemcpyAsync(c->h_pin, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    steps = ((int*)c->h_pin)[1];
+    status = ((int*)c->h_pin)[2];
+    if (res_hist) {
+        CK(hipMemcpyAsync(c->h_pin, c->d_hist, sizeof(double) * (size_t)(steps + 1), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        std::memcpy(res_hist, c->h_pin, sizeof(double) * (size_t)(steps + 1));
+    }
+    if (ir && (steps & 1)) {  // the last refinement step wrote the scratch iterate
+        CK(hipMemcpyAsync(u, c->u64_scratch, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        CK(hipStreamSynchronize(s));
+    }
+    if (cycles_done) *cycles_done = steps;
+    if (status == 0) return MG_OK;
+    if (status == -5) return MG_EDIVERGED;
+    return MG_ENOTCONV;
+}
+
+int mg_prof_enable(mg_ctx* c, int on) {
+    if (!c) return MG_EINVAL;
+    c->prof_on = on != 0;
+    c->prof_n = 0;
+    c->prof_launches = 0;
+    c->prof_ms = 0.0;
+    return MG_OK;
+}
+
+int mg_prof_read(mg_ctx* c, int* launches, double* total_ms) {
+    if (!c) return MG_EINVAL;
+    CK(hipStreamSynchronize(c->stream));
+    double ms = 0.0;
+    for (int i = 0; i + 1 < c->prof_n; i += 2) {
+        float t = 0.f;
+        CK(hipEventElapsedTime(&t, c->prof_ev[(size_t)i], c->prof_ev[(size_t)i + 1]));
+        ms += (double)t;
+    }
+    c->prof_launches += c->prof_n / 2;
+    c->prof_ms += ms;
+    c->prof_n = 0;
+    if (launches) *launches = c->prof_launches;
+    if (total_ms) *total_ms = c->prof_ms;
+    c->prof_launches = 0;
+    c->prof_ms = 0.0;
+    return MG_OK;
+}
+
+int mg_copy_kernel(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || bytes % 16 != 0) return MG_EINVAL;
+    CK(launch_copy_bytes(dst, src, bytes, (hipStream_t)stream));
+    return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Single-level operations
+// ---------------------------------------------------------------------------
+
+static TileCfg pick_cfg(int dim, int elem, int by, int zchunk, int kind) {
+    Tiles t = default_tiles(dim, elem);
+    TileCfg c = kind == 0 ? t.smooth : (kind == 1 ? t.restr : t.norm);
+    if (by) c.by = by;
+    if (zchunk) c.zchunk = zchunk;
+    return c;
+}
+
+static bool valid_cfg(TileCfg c) { return (c.by == 8 || c.by == 16 || c.by == 32) && c.zchunk >= 1; }
+
+// Temporary device descriptor for a context-free call; the stream is synchronised before release.
+static int with_desc(const GridDesc& h, hipStream_t s, GridDesc** d) {
+    CK(hipMalloc((void**)d, sizeof(GridDesc)));
+    CK(hipMemcpyAsync(*d, &h, sizeof(GridDesc), hipMemcpyHostToDevice, s));
+    return MG_OK;
+}
+
+static int finish_desc(void* d, hipStream_t s, hipError_t launch) {
+    hipError_t e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (launch != hipSuccess) return dev_status(launch);
+    return dev_status(e);
+}
+
+int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const void* k, const void* u_in,
+                    const void* f, void* u_out, const void* ec, int zero_guess, int by, int zchunk, void* stream) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
+    if ((smoother != 0 && smoother != 1) || !f || !u_out || (!u_in && !zero_guess)) return MG_EINVAL;
+    if (ec && zero_guess) return MG_EINVAL;
+    if (ec && dim == 3) return MG_ENOTSUP;  // 3D sweeps take the correction from mg_level_prolong_correct
+    const TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, by, zchunk, 0);
+    if (!valid_cfg(cfg)) return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    GridDesc h{};
+    h.u = const_cast<void*>(u_in);
+    h.t = u_out;
+    h.f = f;
+    h.k = k;
+    h.uc = const_cast<void*>(ec);
+    h.n = n;
+    h.c = level_c(n);
+    h.wd = level_wd(dim, n, omega);
+    h.omega = omega;
+    GridDesc* d = nullptr;
+    int r = with_desc(h, s, &d);
+    if (r != MG_OK) return r;
+    const int flags = (zero_guess ? SWEEP_ZERO_GUESS : 0) | (ec ? SWEEP_PROLONG : 0);
+    hipError_t e = dtype == 0 ? launch_smooth<double>(dim, smoother, k != nullptr, d, 1, n, 0, flags, cfg, s)
+                              : launch_smooth<float>(dim, smoother, k != nullptr, d, 1, n, 0, flags, cfg, s);
+    return finish_desc(d, s, e);
+}
+
+int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const void* u, const void* f, void* fc,
+                               int by, int zchunk, void* stream) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
+    if (!u || !f || !fc) return MG_EINVAL;
+    const TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, by, zchunk, 1);
+    if (!valid_cfg(cfg)) return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    GridDesc h{};
+    h.u = const_cast<void*>(u);
+    h.f = f;
+    h.k = k;
+    h.fc = fc;
+    h.n = n;
+    h.c = level_c(n);
+    GridDesc* d = nullptr;
+    int r = with_desc(h, s, &d);
+    if (r != MG_OK) return r;
+    hipError_t e = dtype == 0 ? launch_restrict<double>(dim, k != nullptr, d, 1, n, 0, cfg, s)
+                              : launch_restrict<float>(dim, k != nullptr, d, 1, n, 0, cfg, s);
+    return finish_desc(d, s, e);
+}
+
+int mg_level_prolong_correct(int dim, int n, int dtype, void* u, const void* ec, void* stream) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
+    if (!u || !ec) return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    GridDesc h{};
+    h.u = u;
+    h.uc = const_cast<void*>(ec);
+    h.n = n;
+    GridDesc* d = nullptr;
+    int r = with_desc(h, s, &d);
+    if (r != MG_OK) return r;
+    hipError_t e = dtype == 0 ? launch_prolong<double>(dim, d, 1, n, 0, s) : launch_prolong<float>(dim, d, 1, n, 0, s);
+    return finish_desc(d, s, e);
+}
+
+int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f, void* stream) {
+    if ((dim != 2 && dim != 3) || (dtype != 0 && dtype != 1) || !u || !f) return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    GridDesc h{};
+    h.u = u;
+    h.f = f;
+    h.k = k;
+    h.n = 3;
+    h.c = level_c(3);
+    GridDesc* d = nullptr;
+    int r = with_desc(h, s, &d);
+    if (r != MG_OK) return r;
+    hipError_t e = dtype == 0 ? launch_coarsest<double>(dim, k != nullptr, d, 1, s)
+                              : launch_coarsest<float>(dim, k != nullptr, d, 1, s);
+    return finish_desc(d, s, e);
+}
+
+int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
+                       double* u_out, float* r, double* norm_out, int by, int zchunk, void* stream) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5) return MG_EINVAL;
+    if (!u_in || !e || !f || !u_out || !r || !norm_out || u_in == u_out) return MG_EINVAL;
+    const TileCfg cfg = pick_cfg(dim, 8, by, zchunk, 2);
+    if (!valid_cfg(cfg)) return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    IRDesc h{};
+    h.u[0] = const_cast<double*>(u_in);
+    h.u[1] = u_out;
+    h.e = e;
+    h.f = f;
+    h.k = k;
+    h.r = r;
+    h.n = n;
+    h.c = level_c(n);
+    const int nparts = norm_tiles(dim, n, cfg);
+    IRDesc* d = nullptr;
+    double* part = nullptr;
+    double* nrm = nullptr;
+    CK(hipMalloc((void**)&d, sizeof(IRDesc)));
+    hipError_t err = hipMalloc((void**)&part, sizeof(double) * (size_t)nparts);
+    if (err == hipSuccess) err = hipMalloc((void**)&nrm, sizeof(double));
+    if (err == hipSuccess) err = hipMemcpyAsync(d, &h, sizeof(IRDesc), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = launch_ir_update(dim, k != nullptr, d, 1, n, 0, 0, part, nparts, cfg, s);
+    if (err == hipSuccess) err = launch_norm_finalize(part, nparts, nparts, 0, 1, nrm, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(norm_out, nrm, sizeof(double), hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    ffree(d);
+    ffree(part);
+    ffree(nrm);
+    if (err != hipSuccess) return dev_status(err);
+    return dev_status(e2);
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Internal declarations shared by the HIP kernels and the solver core.
+// (Not part of the public C ABI; see include/mg.h for that.)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mg {
+
+enum Smoother { SM_RBGS = 0, SM_JACOBI = 1 };
+
+// Kernel flags for the smoothing sweep.
+enum SweepFlags {
+    SWEEP_ZERO_GUESS = 1,  // the incoming iterate is identically zero: read nothing
+    SWEEP_PROLONG = 2,     // incoming iterate is u + P uc (coarse-grid correction fused into the load)
+};
+
+// One grid at one level, as the kernels see it.  All pointers are device
+// pointers to dense node arrays (n^dim values, x fastest, boundary included).
+// Sweeps ping-pong between u and t; 'sel' kernel arguments name the input
+// buffer (0: u, 1: t).  The coarse iterate of a V-cycle always ends in u.
+struct GridDesc {
+    void* u;          // iterate
+    void* t;          // ping-pong partner of u (same shape)
+    const void* f;    // right-hand side
+    const void* k;    // nodal diffusion coefficient, or null for the Laplacian
+    void* uc;         // next coarser level's u (prolongation source), or null
+    void* fc;         // next coarser level's f (restriction target), or null
+    const int* done;  // per-instance stop flag (non-zero: skip), or null
+    int n;            // nodes per axis
+    int inst;         // instance number (index of this grid's norm partial row)
+    double c;         // 1/h^2
+    double wd;        // omega*h^2/(2d)
+    double omega;     // smoother weight
+};
+
+// FP64 refinement pass of one grid: u_out = u_in + e (inner nodes),
+// r = f - A u_out in FP64, r32 = (float) r, per-block partial sums of r^2.
+struct IRDesc {
+    double* u[2];     // ping-pong FP64 iterate; kernel argument 'sel' names the input
+    const float* e;   // single-precision correction (zero boundary)
+    const double* f;  // FP64 right-hand side
+    const double* k;  // FP64 nodal coefficient or null
+    float* r;         // single-precision residual out (boundary left untouched, zero)
+    const int* done;  // stop flag or null
+    int n;
+    int inst;
+    double c;
+};
+
+// Launch geometry of one kernel family (picked by the autotuner).
+struct TileCfg {
+    int by;      // LDS box rows (2D) / rows of the x-y box (3D): 8, 16, 32 or 64
+    int zchunk;  // 3D: output planes per workgroup (ignored in 2D)
+};
+
+// Number of workgroups in x for a level of n nodes per axis (one instance).
+int smooth_tiles(int dim, int sm, int n, TileCfg cfg);
+int restrict_tiles(int dim, int nf, TileCfg cfg);
+int norm_tiles(int dim, int n, TileCfg cfg);
+
+// Kernel launchers.  'ninst' grids with equal n are processed by one launch
+// (blockIdx.y selects the descriptor).  'T' is double or float.
+template <typename T>
+hipError_t launch_smooth(int dim, int sm, bool var, const GridDesc* d, int ninst, int n, int sel, int flags,
+                         TileCfg cfg, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(int dim, bool var, const GridDesc* d, int ninst, int nf, int sel, TileCfg cfg,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_prolong(int dim, const GridDesc* d, int ninst, int nf, int sel, hipStream_t s);
+template <typename T>
+hipError_t launch_coarsest(int dim, bool var, const GridDesc* d, int ninst, hipStream_t s);
+template <typename T>
+hipError_t launch_copy_t_to_u(int dim, const GridDesc* d, int ninst, int n, hipStream_t s);
+template <typename T>
+hipError_t launch_zero_u(int dim, const GridDesc* d, int ninst, int n, hipStream_t s);
+
+// FP64 residual norm partials: partial[inst * pstride + block] = sum r^2 over the block.
+hipError_t launch_norm(int dim, bool var, const GridDesc* d, int ninst, int n, int sel, double* partial,
+                       int pstride, TileCfg cfg, hipStream_t s);
+// FP64 refinement pass (see IRDesc); same partial layout as launch_norm.
+// flags & IR_NO_UPDATE: u is not changed (e not read, u_out not written).
+enum IRFlags { IR_NO_UPDATE = 1 };
+hipError_t launch_ir_update(int dim, bool var, const IRDesc* d, int ninst, int n, int sel, int flags,
+                            double* partial, int pstride, TileCfg cfg, hipStream_t s);
+// norm[inst] = sqrt(sum of partial[inst*pstride + 0 .. nparts-1]) in a fixed order; for
+// each of 'ninst' rows starting at row 'row0'.
+hipError_t launch_norm_finalize(const double* partial, int pstride, int nparts, int row0, int ninst,
+                                double* norm, hipStream_t s);
+
+// Device-side solve control, one entry per instance i in [0, ninst):
+//   solve_init: norm0[i] = norm[i], hist[i*hstride] = norm[i], steps[i] = 0,
+//               status[i] = 1 (running) / 0 (zero residual) / -5, done[i] set unless running.
+//   stop_test:  for running instances: steps[i]++, hist[i*hstride+steps] = norm[i],
+//               status 0 when norm <= tol*norm0, -5 on NaN/Inf/growth > 1e6,
+//               2 when steps reaches max_steps; done[i] = 1 once status != 1.
+hipError_t launch_solve_init(const double* norm, double* norm0, int* done, int* steps, int* status, double* hist,
+                             int hstride, int ninst, hipStream_t s);
+hipError_t launch_stop_test(const double* norm, const double* norm0, int* done, int* steps, int* status, double* hist,
+                            int hstride, double tol, int max_steps, int ninst, hipStream_t s);
+
+// Coarse coefficient by injection: dst(I) = (TD) src(2I) over every coarse node,
+// nf = 2*nc - 1 nodes per axis on the fine side.
+template <typename TS, typename TD>
+hipError_t launch_inject(int dim, int nf, const TS* src, int nc, TD* dst, hipStream_t s);
+// dst[q] = (TD) src[q] for q < total.
+template <typename TS, typename TD>
+hipError_t launch_convert(size_t total, const TS* src, TD* dst, hipStream_t s);
+hipError_t launch_fill_int(int* p, int v, int count, hipStream_t s);
+
+// Plain device copy of 'bytes' bytes (bandwidth calibration kernel).
+hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+}  // namespace mg

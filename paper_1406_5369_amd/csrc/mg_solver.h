@@ -1,0 +1,111 @@
+// Solver core: level hierarchies, the V-cycle driver (Algorithm 1), the
+// solve loop with device-side stop test, FP64 iterative refinement around
+// FP32 V-cycles, hipGraph capture and the tile autotuner.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/mg.h"
+#include "mg_internal.h"
+
+namespace mg {
+
+// Launch geometry of every kernel family of one hierarchy.
+struct Tiles {
+    TileCfg smooth{16, 128};
+    TileCfg restr{16, 64};
+    TileCfg norm{16, 128};
+};
+
+Tiles default_tiles(int dim, int elem_bytes);
+
+// Device buffers of one instance's hierarchy in working precision T
+// (sizeof(T) bytes per value).  Level 0 buffers may belong to the caller.
+struct Levels {
+    int dim = 0, nlev = 0, elem = 8;
+    std::vector<int> n;           // n[0] finest
+    std::vector<void*> u, t, f, k;  // per level; k empty when Laplacian
+    std::vector<char> own_u, own_f; // level owns u / f
+    bool own_k0 = false;            // level-0 coefficient allocated by the hierarchy
+};
+
+// A group of instances that share one level size: one launch processes all.
+struct Group {
+    int n = 0;
+    int ninst = 0;
+    GridDesc* d = nullptr;         // device descriptors [ninst]
+    std::vector<GridDesc> h;       // host mirror
+};
+
+struct Problem {
+    int dim, smoother, nu1, nu2;
+    double omega;
+    bool var;
+};
+
+// V-cycle over groups[0..L-1] (groups[l] holds every instance's level l);
+// zero_top: the iterate at level 0 is known to be zero.  Works in precision T.
+template <typename T>
+hipError_t vcycle(const Problem& P, const std::vector<Group>& groups, bool zero_top, const Tiles& tiles,
+                  hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap);
+
+size_t npts(int dim, int n);
+int count_levels(int n);
+
+}  // namespace mg
+
+// The opaque context of the C ABI.
+struct mg_ctx {
+    mg_params p;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    mg::Problem prob{};
+    int nlev = 0;
+    std::vector<int> n;
+    mg::Tiles t64, t32;
+
+    // FP64 hierarchy (precision FP64): level 0 u/f are the caller's.
+    mg::Levels L64;
+    std::vector<mg::Group> G64;
+    // FP32 hierarchy (precision FP32_IR): all levels owned; level-0 u = e, f = r32.
+    mg::Levels L32;
+    std::vector<mg::Group> G32;
+    // FP64 refinement state
+    mg::IRDesc* d_ir = nullptr;
+    mg::IRDesc h_ir{};
+    double* u64_scratch = nullptr;
+    double* k64 = nullptr;  // private copy of the FP64 nodal coefficient (var-coef)
+
+    // solve control (one instance)
+    double* d_partial = nullptr;
+    int pstride = 0;
+    double* d_norm = nullptr;   // [1]
+    double* d_norm0 = nullptr;  // [1]
+    double* d_hist = nullptr;
+    int hist_cap = 0;
+    double* h_pin = nullptr;  // pinned host staging
+
+    mg::GridDesc* d_top = nullptr;  // FP64 view of the finest level (residual norms)
+    mg::GridDesc h_top{};
+    int* d_ctrl = nullptr;            // done, steps, status
+
+    const void* bound_u = nullptr;
+    const void* bound_f = nullptr;
+
+    // graph cache for a chunk of cycles
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_steps = 0;
+    int graph_prec = -1;
+    double graph_tol = -1.0;
+    int graph_max = -1;
+
+    // measurement
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;
+    int prof_n = 0;
+    int prof_launches = 0;
+    double prof_ms = 0.0;
+};

@@ -14,10 +14,13 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def dev():
-    """The HIP device used by GPU tests; fails loudly when none is visible."""
+def dev_ok():
+    """GPU tests: a HIP device must be visible and libmg.so built."""
     import torch
 
     if not torch.cuda.is_available():
         pytest.fail("GPU test run without a visible HIP device")
-    return torch.device("cuda:0")
+    import paper_1406_5369_amd as mg
+
+    mg.lib()
+    return True

@@ -1,0 +1,266 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Per-point arithmetic is the same expression on both sides and neither side
+contracts to FMA, so every field the HIP kernels produce is compared bit for
+bit with the oracle's (torch.equal / numpy.array_equal).  Residual norms are
+sums in different orders and are compared to 1e-13 relative; solve histories
+to 1e-12 relative per cycle.  Sizes span several tiles with ragged last tiles
+(3D tiles are 60 x 12 nodes by default, 2D 60 x 28), and tile shapes are varied.
+"""
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+RB, JAC = 0, 1
+
+
+def mg():
+    import paper_1406_5369_amd as m
+
+    return m
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def same(a, b):
+    return a.shape == b.shape and np.array_equal(a, b)
+
+
+def case_arrays(dim, n, dt, varcoef, seed=0):
+    u = inputs.random_guess(dim, n, 100 + seed).astype(dt)
+    f = (inputs.uniform_rhs(dim, n, 200 + seed) * 50.0).astype(dt)
+    k = inputs.varcoef_k(n, 300 + seed, dim=dim).astype(dt) if varcoef else None
+    return u, f, k
+
+
+SMOOTH_CASES = [
+    # dim, n, by, zchunk
+    (2, 5, 0, 0), (2, 9, 8, 0), (2, 33, 16, 0), (2, 129, 0, 0), (2, 257, 32, 0), (2, 65, 8, 0),
+    (3, 5, 0, 0), (3, 9, 8, 1), (3, 17, 16, 3), (3, 33, 0, 0), (3, 65, 32, 7), (3, 65, 8, 64),
+]
+
+
+@pytest.mark.parametrize("dim,n,by,zc", SMOOTH_CASES)
+@pytest.mark.parametrize("smoother", [RB, JAC])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("varcoef", [False, True])
+def test_smooth_sweep_bitwise(dim, n, by, zc, smoother, dt, varcoef, dev_ok):
+    u, f, k = case_arrays(dim, n, dt, varcoef, seed=n)
+    omega = 1.0 if smoother == RB else 0.8
+    expect = oracle.smooth(u, f, smoother=smoother, omega=omega, k=k)
+    ud, fd = dev(u), dev(f)
+    out = dev(np.zeros_like(u))
+    mg().mg_level_smooth(ud, fd, out, smoother=smoother, omega=omega, k=dev(k) if k is not None else None,
+                         by=by, zchunk=zc)
+    assert same(host(out), expect)
+
+
+@pytest.mark.parametrize("dim,n,by,zc", [(2, 65, 16, 0), (3, 33, 16, 5), (3, 17, 8, 0)])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_smooth_zero_guess_bitwise(dim, n, by, zc, dt, dev_ok):
+    _, f, _ = case_arrays(dim, n, dt, False, seed=3)
+    expect = oracle.smooth(np.zeros_like(f), f)
+    out = dev(np.zeros_like(f))
+    mg().mg_level_smooth(None, dev(f), out, zero_guess=True, by=by, zchunk=zc)
+    assert same(host(out), expect)
+
+
+@pytest.mark.parametrize("n", [9, 65, 257])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("smoother", [RB, JAC])
+def test_smooth_with_fused_correction_2d_bitwise(n, dt, smoother, dev_ok):
+    u, f, _ = case_arrays(2, n, dt, False, seed=5)
+    nc = (n - 1) // 2 + 1
+    ec = inputs.random_guess(2, nc, 77).astype(dt)
+    omega = 1.0 if smoother == RB else 0.8
+    expect = oracle.smooth(oracle.prolong_correct(u, ec), f, smoother=smoother, omega=omega)
+    out = dev(np.zeros_like(u))
+    mg().mg_level_smooth(dev(u), dev(f), out, smoother=smoother, omega=omega, ec=dev(ec))
+    assert same(host(out), expect)
+
+
+@pytest.mark.parametrize("dim,n,by,zc", [(2, 5, 0, 0), (2, 65, 8, 0), (2, 129, 32, 0), (2, 257, 16, 0),
+                                         (3, 5, 0, 0), (3, 17, 8, 1), (3, 33, 16, 2), (3, 65, 0, 0),
+                                         (3, 129, 32, 9)])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("varcoef", [False, True])
+def test_residual_restrict_bitwise(dim, n, by, zc, dt, varcoef, dev_ok):
+    u, f, k = case_arrays(dim, n, dt, varcoef, seed=7)
+    expect = oracle.restrict(oracle.residual(u, f, k=k))
+    nc = (n - 1) // 2 + 1
+    fc = dev(np.zeros((nc,) * dim, dtype=dt))
+    mg().mg_level_residual_restrict(dev(u), dev(f), fc, k=dev(k) if k is not None else None, by=by, zchunk=zc)
+    assert same(host(fc), expect)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 5), (2, 129), (3, 5), (3, 33), (3, 65)])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_prolong_correct_bitwise(dim, n, dt, dev_ok):
+    u, _, _ = case_arrays(dim, n, dt, False, seed=9)
+    nc = (n - 1) // 2 + 1
+    ec = inputs.random_guess(dim, nc, 99).astype(dt)
+    expect = oracle.prolong_correct(u, ec)
+    ud = dev(u)
+    mg().mg_level_prolong_correct(ud, dev(ec))
+    assert same(host(ud), expect)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("varcoef", [False, True])
+def test_coarsest_bitwise(dim, varcoef, dev_ok):
+    f = np.zeros((3,) * dim)
+    f[(1,) * dim] = 0.37
+    k = inputs.varcoef_k(3, 4, dim=dim) if varcoef else None
+    expect = oracle.coarsest(np.zeros_like(f), f, k=k)
+    ud = dev(np.zeros_like(f))
+    mg().mg_level_coarsest(ud, dev(f), k=dev(k) if k is not None else None)
+    assert same(host(ud), expect)
+
+
+@pytest.mark.parametrize("dim,n,by,zc", [(2, 65, 0, 0), (2, 257, 8, 0), (3, 33, 0, 0), (3, 65, 16, 3)])
+@pytest.mark.parametrize("varcoef", [False, True])
+def test_refinement_pass(dim, n, by, zc, varcoef, dev_ok):
+    import torch
+
+    u, f, k = case_arrays(dim, n, np.float64, varcoef, seed=11)
+    e = (inputs.random_guess(dim, n, 12) * 1e-3).astype(np.float32)
+    u_exp, r_exp, rho_exp = oracle.ir_update(u, e, f, k=k)
+    uo = dev(np.zeros_like(u))
+    r = torch.zeros(u.shape, dtype=torch.float32, device="cuda")
+    rho = mg().mg_level_ir_update(dev(u), dev(e), dev(f), uo, r, k=dev(k) if k is not None else None, by=by,
+                                  zchunk=zc)
+    assert same(host(uo), u_exp)
+    assert same(host(r), r_exp)
+    assert rho == pytest.approx(rho_exp, rel=1e-13)
+
+
+# ---------------------------------------------------------------- full solves
+def run_solve(dim, n, f, k=None, smoother=RB, precision=0, tol=0.0, max_cycles=10, u0=None):
+    m = mg()
+    p = m.Params(dim=dim, n=n, smoother=smoother, precision=precision,
+                 op=m.OP_VARCOEF_NODAL if k is not None else m.OP_LAPLACE,
+                 k=dev(k) if k is not None else None)
+    s = m.Solver(p)
+    u = dev(np.zeros_like(f) if u0 is None else u0)
+    st, cyc, hist = s.solve(u, dev(f), tol=tol, max_cycles=max_cycles)
+    out = host(u)
+    s.close()
+    return st, cyc, np.array(hist), out
+
+
+@pytest.mark.parametrize("smoother", [RB, JAC])
+def test_poisson2d_129_sine_history_and_field(smoother, dev_ok):
+    """The 129 x 129 workload: ten V(2,2) cycles, FP64."""
+    f = inputs.sine_rhs(2, 129)
+    omega = 1.0 if smoother == RB else 0.8
+    u_exp, h_exp, _ = oracle.solve(np.zeros_like(f), f, tol=0.0, max_cycles=10, smoother=smoother, omega=omega)
+    st, cyc, h, u = run_solve(2, 129, f, smoother=smoother)
+    assert cyc == 10
+    np.testing.assert_allclose(h, h_exp, rtol=1e-12, atol=0)
+    assert same(u, u_exp)
+
+
+@pytest.mark.parametrize("dim,n,varcoef,smoother", [(3, 65, False, RB), (3, 33, True, RB), (3, 33, False, JAC),
+                                                    (2, 257, True, RB), (2, 1025, False, RB), (3, 129, False, RB)])
+def test_fp64_solve_matches_oracle(dim, n, varcoef, smoother, dev_ok):
+    f = inputs.uniform_rhs(dim, n, 5)
+    k = inputs.varcoef_k(n, 6, dim=dim) if varcoef else None
+    omega = 1.0 if smoother == RB else 0.8
+    u_exp, h_exp, rc = oracle.solve(np.zeros_like(f), f, tol=1e-10, max_cycles=30, smoother=smoother, omega=omega,
+                                    k=k)
+    st, cyc, h, u = run_solve(dim, n, f, k=k, smoother=smoother, tol=1e-10, max_cycles=30)
+    assert cyc == len(h_exp) - 1
+    np.testing.assert_allclose(h, h_exp, rtol=1e-12, atol=0)
+    assert same(u, u_exp)
+    assert st == 0
+
+
+@pytest.mark.parametrize("dim,n,varcoef", [(2, 129, False), (3, 65, False), (3, 33, True), (2, 513, False)])
+def test_fp32_refinement_solve_matches_oracle(dim, n, varcoef, dev_ok):
+    f = inputs.uniform_rhs(dim, n, 15)
+    k = inputs.varcoef_k(n, 16, dim=dim) if varcoef else None
+    u_exp, h_exp, rc = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-8, max_cycles=30, k=k)
+    st, cyc, h, u = run_solve(dim, n, f, k=k, precision=1, tol=1e-8, max_cycles=30)
+    assert st == 0 and cyc == len(h_exp) - 1
+    np.testing.assert_allclose(h, h_exp, rtol=1e-12, atol=0)
+    assert same(u, u_exp)
+
+
+def test_fp32_refinement_reaches_fp64_solution(dev_ok):
+    """Mixed precision driven to 1e-12: the answer agrees with the FP64 oracle to 1e-10."""
+    dim, n = 3, 65
+    f = inputs.uniform_rhs(dim, n, 21)
+    u64, h64, _ = oracle.solve(np.zeros_like(f), f, tol=1e-12, max_cycles=40)
+    st, cyc, h, u = run_solve(dim, n, f, precision=1, tol=1e-12, max_cycles=40)
+    assert h[-1] <= 1e-12 * h[0]
+    assert np.linalg.norm(u - u64) <= 1e-10 * np.linalg.norm(u64)
+
+
+def test_vcycle_entry_and_residual_norm(dev_ok):
+    m = mg()
+    dim, n = 3, 33
+    f = inputs.uniform_rhs(dim, n, 31)
+    u0 = inputs.random_guess(dim, n, 32)
+    expect = oracle.vcycle(u0, f)
+    s = m.Solver(m.Params(dim=dim, n=n))
+    ud, fd = dev(u0), dev(f)
+    s.vcycle(ud, fd)
+    assert same(host(ud), expect)
+    assert s.residual_norm(ud, fd) == pytest.approx(oracle.residual_norm(expect, f), rel=1e-13)
+    s.close()
+
+
+def test_fp32_vcycle_entry_is_one_refinement_step(dev_ok):
+    m = mg()
+    dim, n = 2, 129
+    f = inputs.uniform_rhs(dim, n, 41)
+    u0 = inputs.random_guess(dim, n, 42)
+    _, r32, _ = oracle.ir_update(u0, np.zeros(f.shape, np.float32), f)
+    e = oracle.vcycle(np.zeros(f.shape, np.float32), r32)
+    expect, _, _ = oracle.ir_update(u0, e, f)
+    s = m.Solver(m.Params(dim=dim, n=n, precision=m.PREC_FP32_IR))
+    ud = dev(u0)
+    s.vcycle(ud, dev(f))
+    assert same(host(ud), expect)
+    s.close()
+
+
+def test_setup_rejects_bad_arguments(dev_ok):
+    m = mg()
+    for kw in [dict(dim=2, n=128), dict(dim=4, n=9), dict(dim=2, n=9, nu1=-1), dict(dim=3, n=9, smoother=5),
+               dict(dim=2, n=9, op=m.OP_VARCOEF_NODAL)]:
+        with pytest.raises(m.MGError) as ei:
+            m.mg_setup(m.Params(**kw))
+        assert ei.value.code == m.MG_EINVAL
+    with pytest.raises(m.MGError) as ei:
+        m.mg_setup(m.Params(dim=2, n=9, bc=1))
+    assert ei.value.code == m.MG_ENOTSUP
+
+
+def test_nan_rhs_reports_divergence(dev_ok):
+    f = inputs.uniform_rhs(2, 65, 1)
+    f[10, 10] = np.nan
+    st, cyc, h, u = run_solve(2, 65, f, tol=1e-8, max_cycles=10)
+    assert st == mg().MG_EDIVERGED
+
+
+def test_max_cycles_exhaustion_reports_not_converged(dev_ok):
+    f = inputs.uniform_rhs(3, 33, 2)
+    st, cyc, h, u = run_solve(3, 33, f, tol=1e-30, max_cycles=3)
+    assert st == mg().MG_ENOTCONV and cyc == 3 and len(h) == 4
