@@ -1,0 +1,310 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X multigrid solver.
+
+One step = one complete solve, from u = 0 to a relative residual of 1e-8, of
+the 3D Poisson problem -Laplace(u) = f on 513^3 nodes (h = 1/512, zero
+Dirichlet boundary, f i.i.d. U[-1, 1] from numpy default_rng(0) with a zeroed
+boundary), by FP32 V(2,2) red-black Gauss-Seidel cycles inside FP64 iterative
+refinement.  Inputs are resident in HBM before the timed region.
+
+Printed: one JSON line with fine-grid DoF/s (value), the plain FP64 solve of
+the same problem for context, the roofline of the dominant kernel (finest-level
+FP32 smoothing sweep, timed with HIP events on the solver's stream over the
+timed region) and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, datasheet
+
+WORKLOADS = {
+    # name: dim, n, precision, rhs, tol
+    "poisson3d_513_fp32ir": dict(dim=3, n=513, precision=1, rhs=("uniform", 0), tol=1e-8),
+    "poisson3d_513_fp64": dict(dim=3, n=513, precision=0, rhs=("uniform", 0), tol=1e-8),
+    "poisson2d_129_sine_fp64": dict(dim=2, n=129, precision=0, rhs=("sine",), tol=0.0, cycles=10),
+    "poisson3d_257_fp32ir": dict(dim=3, n=257, precision=1, rhs=("uniform", 0), tol=1e-8),
+    "poisson2d_4097_fp32ir": dict(dim=2, n=4097, precision=1, rhs=("uniform", 0), tol=1e-8),
+}
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    """Hash of the device-code sources (kernels and their shared headers)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1406_5369_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.startswith(("mg_smooth", "mg_resid", "mg_transfer", "mg_kern", "mg_internal")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_rhs(w):
+    import inputs
+
+    if w["rhs"][0] == "sine":
+        return inputs.sine_rhs(w["dim"], w["n"])
+    return inputs.uniform_rhs(w["dim"], w["n"], w["rhs"][1])
+
+
+def traffic_record(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(w, gpu_steps: int, budget_s: float):
+    """Time the oracle (as it stands) on one refinement step / one V-cycle of
+    the same workload on this host; scale to the solve's step count."""
+    import ctypes as C
+
+    import numpy as np
+
+    import oracle
+
+    lib = oracle._load()
+    dim, n = w["dim"], w["n"]
+    f = make_rhs(w)
+    u = np.zeros_like(f)
+    threads = oracle.num_threads()
+    t_steps = []
+    t0 = time.perf_counter()
+    if w["precision"] == 1:
+        e = np.zeros(f.shape, np.float32)
+        r32 = np.zeros(f.shape, np.float32)
+        while True:
+            ts = time.perf_counter()
+            lib.orc_ir_update_f32(dim, n, None, u.ctypes.data, e.ctypes.data, f.ctypes.data, r32.ctypes.data)
+            e[...] = 0.0
+            lib.orc_vcycle_f32(dim, n, None, 0, 1.0, 2, 2, e.ctypes.data, r32.ctypes.data)
+            t_steps.append(time.perf_counter() - ts)
+            if time.perf_counter() - t0 > budget_s or len(t_steps) >= 3:
+                break
+        sample = "FP64 refinement pass + FP32 V(2,2) cycle"
+    else:
+        while True:
+            ts = time.perf_counter()
+            lib.orc_vcycle_f64(dim, n, None, 0, 1.0, 2, 2, u.ctypes.data, f.ctypes.data)
+            lib.orc_residual_norm_f64(dim, n, None, u.ctypes.data, f.ctypes.data)
+            t_steps.append(time.perf_counter() - ts)
+            if time.perf_counter() - t0 > budget_s or len(t_steps) >= 3:
+                break
+        sample = "FP64 V(2,2) cycle + residual norm"
+    t_step = float(np.median(t_steps))
+    dof = (n - 2) ** dim
+    t_solve = t_step * gpu_steps
+    return {
+        "value": dof / t_solve,
+        "unit": "DoF/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{len(t_steps)} x ({sample}) on the {n}^{dim} workload, median {t_step:.3f} s per step, "
+                  f"scaled by the {gpu_steps} steps of the solve",
+    }
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="poisson3d_513_fp32ir", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 context solve")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run the plain copy kernel over 1 GiB three times (counter calibration)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1406_5369_amd as mg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 2
+    w = WORKLOADS[args.workload]
+    dim, n = w["dim"], w["n"]
+    dof = (n - 2) ** dim
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"[bench] workload {args.workload}: dim={dim} n={n} dof={dof}")
+    f = torch.from_numpy(make_rhs(w)).to(dev)
+    max_cycles = w.get("cycles", 50)
+    tol = w["tol"]
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            mg.mg_copy_kernel(dst, src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] copy kernel: 3 x 1 GiB")
+
+    # measured HBM copy ceiling of this device: library copy kernel over 1 GiB (read + write)
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        mg.mg_copy_kernel(dst, src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = 1e30
+    for _ in range(10):
+        ev0.record()
+        mg.mg_copy_kernel(dst, src)
+        ev1.record()
+        ev1.synchronize()
+        best = min(best, ev0.elapsed_time(ev1))
+    copy_gbps = 2.0 * (1 << 30) / (best * 1e-3) / 1e9
+    del src, dst
+    log(f"[bench] copy kernel ceiling: {copy_gbps:.0f} GB/s")
+
+    # solution buffers, zeroed before the timed region (u0 = 0 for every step)
+    nbuf = args.steps + args.warmup
+    us = [torch.zeros_like(f) for _ in range(min(nbuf, 4))]
+    params = mg.Params(dim=dim, n=n, precision=w["precision"])
+    solver = mg.Solver(params)
+    stream = torch.cuda.current_stream()
+
+    def one(i):
+        u = us[i % len(us)]
+        u.zero_()
+        return solver.solve(u, f, tol=tol, max_cycles=max_cycles)
+
+    for i in range(args.warmup):
+        st, cyc, hist = one(i)
+        log(f"[bench] warmup {i}: status={st} cycles={cyc} reduction={hist[-1] / hist[0]:.3e}")
+    # timed region: K complete solves; the zeroing of u is part of each solve's setup
+    mg.mg_prof_enable(solver.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles = []
+    for i in range(args.steps):
+        st, cyc, hist = one(i)
+        cycles.append(cyc)
+        if st != mg.MG_OK:
+            log(f"[bench] step {i}: status {st}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, sweep_ms = mg.mg_prof_read(solver.ctx)
+    mg.mg_prof_enable(solver.ctx, False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = dof * args.steps / (t1 - t0)
+    log(f"[bench] {args.steps} solves: {ms_per_step:.3f} ms/solve, cycles {cycles}, {value / 1e9:.3f} GDoF/s")
+
+    # dominant kernel: finest-level smoothing sweep (reads u and f, writes u: 3 words per inner node);
+    # the zero-guess first sweep of each cycle is excluded from the event brackets.
+    word = 4 if w["precision"] == 1 else 8
+    bytes_per_launch = 3 * word * dof
+    avg_ms = sweep_ms / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    kname = f"k_smooth3d<{'float' if word == 4 else 'double'},RBGS>" if dim == 3 else \
+        f"k_smooth2d<{'float' if word == 4 else 'double'},RBGS>"
+    roofline = {
+        "bound": "hbm",
+        "kernel": kname + " (finest level, non-zero-guess sweeps)",
+        "launches": launches,
+        "avg_launch_ms": avg_ms,
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBPS,
+        "copy_ceiling": copy_gbps,
+        "frac_of_copy_ceiling": achieved / copy_gbps,
+        "traffic": traffic_record(kname, args.workload),
+    }
+
+    extra = {"solves_per_s": args.steps / (t1 - t0), "cycles_per_solve": cycles[-1],
+             "kernel_source_hash": kernel_source_hash(),
+             "fine_tiles": {fam: mg.mg_tile_config(solver.ctx, 0, i) for i, fam in
+                            enumerate(["smooth", "restrict", "norm_or_refinement"])}}
+    if not args.no_fp64 and w["precision"] == 1:
+        s64 = mg.Solver(mg.Params(dim=dim, n=n, precision=mg.PREC_FP64))
+        u = us[0]
+        u.zero_()
+        s64.solve(u, f, tol=tol, max_cycles=max_cycles)  # warm
+        reps = 3
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(reps):
+            u.zero_()
+            st64, cyc64, h64 = s64.solve(u, f, tol=tol, max_cycles=max_cycles)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        s64.close()
+        extra["fp64_solve"] = {"dof_per_s": dof * reps / (tb - ta), "ms_per_solve": (tb - ta) * 1e3 / reps,
+                               "cycles": cyc64, "status": st64}
+        extra["mixed_over_fp64_speedup"] = value / extra["fp64_solve"]["dof_per_s"]
+        log(f"[bench] FP64 solve: {(tb - ta) * 1e3 / reps:.3f} ms, {cyc64} cycles")
+    solver.close()
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline ...")
+        cpu = cpu_baseline(w, cycles[-1], args.cpu_budget)
+        log(f"[bench] CPU oracle: {cpu['value'] / 1e6:.3f} MDoF/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "fine-grid DoF/s + HBM GB/s %peak; solves/s & p99 latency at 1e-8 residual",
+        "value": value,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if w["precision"] == 1 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "dim": dim,
+            "n": n,
+            "dof": dof,
+            "tol": tol,
+            "solver": "V(2,2) RBGS, full weighting, linear interpolation, exact 3-point coarsest solve"
+                      + (", FP32 cycles in FP64 iterative refinement" if w["precision"] == 1 else ", FP64"),
+            "parallelism": "single GPU",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

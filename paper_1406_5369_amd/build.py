@@ -19,7 +19,16 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmg.so")
-SOURCES = ["mg_kernels.hip", "mg_solver.hip", "mg_capi.hip", "mg_batch.hip"]
+SOURCES = [
+    "mg_smooth3d_f64.hip",
+    "mg_smooth3d_f32.hip",
+    "mg_resid.hip",
+    "mg_transfer.hip",
+    "mg_smooth2d.hip",
+    "mg_solver.hip",
+    "mg_capi.hip",
+    "mg_batch.hip",
+]
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -52,7 +61,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+    with ThreadPoolExecutor(max_workers=min(int(os.environ.get("MAX_JOBS", "8")), len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

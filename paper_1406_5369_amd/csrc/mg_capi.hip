@@ -3,7 +3,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 
 #include "mg_solver.h"
 
@@ -211,16 +214,16 @@ int* ctl_status(mg_ctx* c) { return c->d_ctrl + 2; }
 // FP64 norm of the bound (u, f) into d_norm (partials + fixed-order finalize).
 hipError_t enqueue_norm(mg_ctx* c, hipStream_t s) {
     const bool var = c->prob.var;
-    const int nparts = norm_tiles(c->p.dim, c->p.n, c->t64.norm);
-    hipError_t e = launch_norm(c->p.dim, var, c->d_top, 1, c->p.n, 0, c->d_partial, c->pstride, c->t64.norm, s);
+    const int nparts = norm_tiles(c->p.dim, c->p.n, c->top.norm);
+    hipError_t e = launch_norm(c->p.dim, var, c->d_top, 1, c->p.n, 0, c->d_partial, c->pstride, c->top.norm, s);
     if (e != hipSuccess) return e;
     return launch_norm_finalize(c->d_partial, c->pstride, nparts, 0, 1, c->d_norm, s);
 }
 
 hipError_t enqueue_ir(mg_ctx* c, int sel, int flags, hipStream_t s) {
-    const int nparts = norm_tiles(c->p.dim, c->p.n, c->t64.norm);
+    const int nparts = norm_tiles(c->p.dim, c->p.n, c->top.norm);
     hipError_t e = launch_ir_update(c->p.dim, c->prob.var, c->d_ir, 1, c->p.n, sel, flags, c->d_partial, c->pstride,
-                                    c->t64.norm, s);
+                                    c->top.norm, s);
     if (e != hipSuccess) return e;
     return launch_norm_finalize(c->d_partial, c->pstride, nparts, 0, 1, c->d_norm, s);
 }
@@ -234,11 +237,11 @@ hipError_t enqueue_steps(mg_ctx* c, int K, double tol, int max_cycles, hipStream
     for (int i = 0; i < K; ++i) {
         hipError_t e;
         if (c->p.precision == MG_PREC_FP64) {
-            e = vcycle<double>(c->prob, c->G64, false, c->t64, s, pev, pn, pcap);
+            e = vcycle<double>(c->prob, c->G64, false, c->tl64, s, pev, pn, pcap);
             if (e != hipSuccess) return e;
             e = enqueue_norm(c, s);
         } else {
-            e = vcycle<float>(c->prob, c->G32, true, c->t32, s, pev, pn, pcap);
+            e = vcycle<float>(c->prob, c->G32, true, c->tl32, s, pev, pn, pcap);
             if (e != hipSuccess) return e;
             e = enqueue_ir(c, i & 1, 0, s);
         }
@@ -300,6 +303,225 @@ int run_chunk(mg_ctx* c, int K, double tol, int max_cycles) {
     return MG_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Autotuner: for every level large enough to matter, time each candidate
+// launch geometry (tile rows x z-chunk) of the smoothing, restriction and
+// finest-level norm / refinement kernels on the context's own buffers and
+// keep the fastest.  Results are bitwise independent of the geometry, so
+// tuning changes time only.  Choices are cached per process.
+// ---------------------------------------------------------------------------
+
+typedef std::tuple<int, int, int, int, int, int, int> TuneKey;  // dim, elem, n, family, smoother, var, mode
+std::mutex g_tune_mu;
+std::map<TuneKey, TileCfg> g_tune;
+
+constexpr size_t kTuneMinPoints = 1u << 16;
+
+std::vector<TileCfg> tune_candidates(int dim, int planes, bool with_pd) {
+    std::vector<TileCfg> v;
+    const int bys[3] = {8, 16, 32};
+    for (int by : bys) {
+        if (dim == 2) {
+            v.push_back({by, 1, 1});
+            continue;
+        }
+        for (int zc = 4; zc <= 256; zc *= 2) {
+            if (zc > std::max(4, planes)) break;
+            v.push_back({by, zc, 1});
+            if (with_pd) v.push_back({by, zc, 2});
+        }
+    }
+    return v;
+}
+
+// Time every candidate (after warming the GPU up to its working clocks) in three
+// interleaved rounds and keep the fastest by its best round.
+template <class Launch>
+TileCfg pick_fastest(const std::vector<TileCfg>& cands, TileCfg fallback, Launch&& launch, hipStream_t s) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (cands.empty() || hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fallback;
+    std::vector<float> best_ms(cands.size(), 1e30f);
+    std::vector<char> ok(cands.size(), 1);
+    // warm-up: about 60 ms of the first candidate (the GPU leaves its idle clocks)
+    {
+        (void)hipEventRecord(a, s);
+        (void)launch(cands[0]);
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        const int reps = std::min(600, std::max(2, (int)(60.0f / std::max(ms, 1e-3f))));
+        for (int r = 0; r < reps; ++r) (void)launch(cands[0]);
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
+    }
+    for (int round = 0; round < 3; ++round) {
+        for (size_t i = 0; i < cands.size(); ++i) {
+            if (!ok[i]) continue;
+            if (launch(cands[i]) != hipSuccess) {
+                (void)hipGetLastError();
+                ok[i] = 0;
+                continue;
+            }
+            (void)hipEventRecord(a, s);
+            for (int r = 0; r < 3; ++r) (void)launch(cands[i]);
+            (void)hipEventRecord(b, s);
+            if (hipEventSynchronize(b) != hipSuccess) {
+                ok[i] = 0;
+                continue;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            best_ms[i] = std::min(best_ms[i], ms);
+        }
+    }
+    TileCfg best = fallback;
+    float bt = 1e30f;
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (ok[i] && best_ms[i] < bt) {
+            bt = best_ms[i];
+            best = cands[i];
+        }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return best;
+}
+
+bool tune_lookup(const TuneKey& k, TileCfg* out) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(k);
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_store(const TuneKey& k, TileCfg v) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[k] = v;
+}
+
+// Tune one hierarchy (levels of 'elem' bytes).  scratch_u / scratch_f stand in
+// for caller-owned level-0 arrays.
+hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void* scratch_u, void* scratch_f) {
+    const int dim = c->p.dim;
+    hipStream_t s = c->stream;
+    GridDesc* d = nullptr;
+    hipError_t e = hipMalloc((void**)&d, sizeof(GridDesc));
+    if (e != hipSuccess) return e;
+    for (int l = 0; l + 1 < L.nlev; ++l) {
+        const int n = L.n[(size_t)l];
+        if (npts(dim, n) < kTuneMinPoints) continue;
+        GridDesc h{};
+        h.u = L.u[(size_t)l] ? L.u[(size_t)l] : scratch_u;
+        h.t = L.t[(size_t)l];
+        h.f = L.f[(size_t)l] ? L.f[(size_t)l] : scratch_f;
+        h.k = L.k[(size_t)l];
+        h.fc = L.f[(size_t)l + 1];
+        h.n = n;
+        h.c = level_c(n);
+        h.wd = level_wd(dim, n, c->p.omega);
+        h.omega = c->p.omega;
+        e = hipMemcpyAsync(d, &h, sizeof(GridDesc), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) break;
+        const bool var = c->prob.var;
+        const int sm = c->p.smoother;
+        TuneKey ks{dim, L.elem, n, 0, sm, var ? 1 : 0, 0};
+        TileCfg cfg;
+        if (!tune_lookup(ks, &cfg)) {
+            cfg = pick_fastest(tune_candidates(dim, n - 2, true), tl[(size_t)l].smooth, [&](TileCfg t) {
+                return L.elem == 8 ? launch_smooth<double>(dim, sm, var, d, 1, n, 0, 0, t, s)
+                                   : launch_smooth<float>(dim, sm, var, d, 1, n, 0, 0, t, s);
+            }, s);
+            tune_store(ks, cfg);
+        }
+        tl[(size_t)l].smooth = cfg;
+        TuneKey kr{dim, L.elem, n, 1, 0, var ? 1 : 0, 0};
+        if (!tune_lookup(kr, &cfg)) {
+            std::vector<TileCfg> cands;
+            for (TileCfg t : tune_candidates(dim, (n - 1) / 2 - 1, false))
+                if (t.by >= 8) cands.push_back(t);
+            cfg = pick_fastest(cands, tl[(size_t)l].restr, [&](TileCfg t) {
+                return L.elem == 8 ? launch_restrict<double>(dim, var, d, 1, n, 0, t, s)
+                                   : launch_restrict<float>(dim, var, d, 1, n, 0, t, s);
+            }, s);
+            tune_store(kr, cfg);
+        }
+        tl[(size_t)l].restr = cfg;
+    }
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    return e != hipSuccess ? e : e2;
+}
+
+hipError_t autotune(mg_ctx* c) {
+    const int dim = c->p.dim, n = c->p.n;
+    const size_t N = npts(dim, n);
+    hipStream_t s = c->stream;
+    void* su = nullptr;
+    void* sf = nullptr;
+    hipError_t e = hipSuccess;
+    if (N >= kTuneMinPoints) {
+        e = zalloc(&su, N * sizeof(double), s);
+        if (e == hipSuccess) e = zalloc(&sf, N * sizeof(double), s);
+    }
+    if (e == hipSuccess) {
+        if (c->p.precision == MG_PREC_FP64) e = tune_levels(c, c->L64, c->tl64, su, sf);
+        else e = tune_levels(c, c->L32, c->tl32, nullptr, nullptr);
+    }
+    // finest-level FP64 norm (FP64 solves) or refinement pass (mixed precision)
+    if (e == hipSuccess && N >= kTuneMinPoints) {
+        const bool var = c->prob.var;
+        const int mode = c->p.precision == MG_PREC_FP64 ? 0 : 1;
+        TuneKey kn{dim, 8, n, 2, 0, var ? 1 : 0, mode};
+        TileCfg cfg;
+        if (!tune_lookup(kn, &cfg)) {
+            const std::vector<TileCfg> cands = tune_candidates(dim, n - 2, true);
+            int maxparts = 1;
+            for (TileCfg t : cands) maxparts = std::max(maxparts, norm_tiles(dim, n, t));
+            double* part = nullptr;
+            e = hipMalloc((void**)&part, sizeof(double) * (size_t)maxparts);
+            if (e == hipSuccess) {
+                if (mode == 0) {
+                    GridDesc h = c->h_top;
+                    h.u = su;
+                    h.f = sf;
+                    GridDesc* d = nullptr;
+                    e = hipMalloc((void**)&d, sizeof(GridDesc));
+                    if (e == hipSuccess) e = hipMemcpyAsync(d, &h, sizeof(GridDesc), hipMemcpyHostToDevice, s);
+                    if (e == hipSuccess)
+                        cfg = pick_fastest(cands, c->top.norm, [&](TileCfg t) {
+                            return launch_norm(dim, var, d, 1, n, 0, part, maxparts, t, s);
+                        }, s);
+                    (void)hipStreamSynchronize(s);
+                    ffree(d);
+                } else {
+                    IRDesc h = c->h_ir;
+                    h.u[0] = (double*)su;
+                    h.f = (const double*)sf;
+                    h.done = nullptr;
+                    IRDesc* d = nullptr;
+                    e = hipMalloc((void**)&d, sizeof(IRDesc));
+                    if (e == hipSuccess) e = hipMemcpyAsync(d, &h, sizeof(IRDesc), hipMemcpyHostToDevice, s);
+                    if (e == hipSuccess)
+                        cfg = pick_fastest(cands, c->top.norm, [&](TileCfg t) {
+                            return launch_ir_update(dim, var, d, 1, n, 0, 0, part, maxparts, t, s);
+                        }, s);
+                    (void)hipStreamSynchronize(s);
+                    ffree(d);
+                }
+                ffree(part);
+                if (e == hipSuccess) tune_store(kn, cfg);
+            }
+        }
+        if (e == hipSuccess) c->top.norm = cfg;
+    }
+    (void)hipStreamSynchronize(s);
+    ffree(su);
+    ffree(sf);
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -337,8 +559,13 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
         if (m == 3) break;
     }
     c->nlev = (int)c->n.size();
-    c->t64 = default_tiles(dim, 8);
-    c->t32 = default_tiles(dim, 4);
+    for (int l = 0; l < c->nlev; ++l) {
+        c->tl64.push_back(default_tiles(dim, 8, c->n[(size_t)l], p->smoother));
+        c->tl32.push_back(default_tiles(dim, 4, c->n[(size_t)l], p->smoother));
+    }
+    c->top = c->tl64[0];
+    const char* at = std::getenv("MG_AUTOTUNE");
+    c->autotune = !(at && at[0] == '0');
     hipStream_t s = c->stream;
     const size_t N = npts(dim, p->n);
     hipError_t e = hipSuccess;
@@ -400,7 +627,8 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
     c->h_top.omega = c->p.omega;
     SETUP_CK(hipMalloc((void**)&c->d_top, sizeof(GridDesc)));
     SETUP_CK(hipMemcpyAsync(c->d_top, &c->h_top, sizeof(GridDesc), hipMemcpyHostToDevice, s));
-    c->pstride = std::max(1, norm_tiles(dim, p->n, c->t64.norm));
+    if (c->autotune) SETUP_CK(autotune(c));
+    c->pstride = std::max(1, norm_tiles(dim, p->n, c->top.norm));
     SETUP_CK(hipMalloc((void**)&c->d_partial, sizeof(double) * (size_t)c->pstride));
     SETUP_CK(hipMalloc((void**)&c->d_norm, sizeof(double)));
     SETUP_CK(hipMalloc((void**)&c->d_norm0, sizeof(double)));
@@ -421,16 +649,27 @@ void mg_destroy(mg_ctx* c) { destroy(c); }
 
 int mg_num_levels(const mg_ctx* c) { return c ? c->nlev : MG_EINVAL; }
 
+int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch) {
+    if (!c || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 2) return MG_EINVAL;
+    const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
+    TileCfg t = family == 0 ? tl[(size_t)level].smooth : (family == 1 ? tl[(size_t)level].restr : c->top.norm);
+    if (family == 2 && level != 0) return MG_EINVAL;
+    *by = t.by;
+    *zchunk = t.zchunk;
+    if (prefetch) *prefetch = t.pd;
+    return MG_OK;
+}
+
 int mg_vcycle(mg_ctx* c, double* u, const double* f) {
     if (!c) return MG_EINVAL;
     int r = bind(c, u, f);
     if (r != MG_OK) return r;
     CK(launch_fill_int(ctl_done(c), 0, 1, c->stream));
     if (c->p.precision == MG_PREC_FP64) {
-        CK(vcycle<double>(c->prob, c->G64, false, c->t64, c->stream, nullptr, nullptr, 0));
+        CK(vcycle<double>(c->prob, c->G64, false, c->tl64, c->stream, nullptr, nullptr, 0));
     } else {
         CK(enqueue_ir(c, 0, IR_NO_UPDATE, c->stream));
-        CK(vcycle<float>(c->prob, c->G32, true, c->t32, c->stream, nullptr, nullptr, 0));
+        CK(vcycle<float>(c->prob, c->G32, true, c->tl32, c->stream, nullptr, nullptr, 0));
         CK(enqueue_ir(c, 0, 0, c->stream));
         CK(hipMemcpyAsync(u, c->u64_scratch, npts(c->p.dim, c->p.n) * sizeof(double), hipMemcpyDeviceToDevice,
                           c->stream));
@@ -457,7 +696,8 @@ int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
     if (r != MG_OK) return r;
     hipStream_t s = c->stream;
     const bool ir = c->p.precision == MG_PREC_FP32_IR;
-    // rho_0
+    // rho_0 (clear the stop flag a previous solve left set first: every kernel honours it)
+    CK(launch_fill_int(ctl_done(c), 0, 1, s));
     if (ir) CK(enqueue_ir(c, 0, IR_NO_UPDATE, s));
     else CK(enqueue_norm(c, s));
     CK(launch_solve_init(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist, c->hist_cap, 1,
@@ -540,15 +780,17 @@ int mg_copy_kernel(void* dst, const void* src, size_t bytes, void* stream) {
 // Single-level operations
 // ---------------------------------------------------------------------------
 
-static TileCfg pick_cfg(int dim, int elem, int by, int zchunk, int kind) {
-    Tiles t = default_tiles(dim, elem);
+static TileCfg pick_cfg(int dim, int elem, int n, int smoother, int by, int zchunk, int kind) {
+    Tiles t = default_tiles(dim, elem, n, smoother);
     TileCfg c = kind == 0 ? t.smooth : (kind == 1 ? t.restr : t.norm);
     if (by) c.by = by;
     if (zchunk) c.zchunk = zchunk;
     return c;
 }
 
-static bool valid_cfg(TileCfg c) { return (c.by == 8 || c.by == 16 || c.by == 32) && c.zchunk >= 1; }
+static bool valid_cfg(TileCfg c) {
+    return (c.by == 8 || c.by == 16 || c.by == 32) && c.zchunk >= 1 && (c.pd == 1 || c.pd == 2);
+}
 
 // Temporary device descriptor for a context-free call; the stream is synchronised before release.
 static int with_desc(const GridDesc& h, hipStream_t s, GridDesc** d) {
@@ -565,13 +807,15 @@ static int finish_desc(void* d, hipStream_t s, hipError_t launch) {
 }
 
 int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const void* k, const void* u_in,
-                    const void* f, void* u_out, const void* ec, int zero_guess, int by, int zchunk, void* stream) {
+                    const void* f, void* u_out, const void* ec, int zero_guess, int by, int zchunk, int prefetch,
+                    void* stream) {
     if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
     if ((smoother != 0 && smoother != 1) || !f || !u_out || (!u_in && !zero_guess)) return MG_EINVAL;
     if (ec && zero_guess) return MG_EINVAL;
     if (ec && dim == 3) return MG_ENOTSUP;  // 3D sweeps take the correction from mg_level_prolong_correct
-    const TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, by, zchunk, 0);
-    if (!valid_cfg(cfg)) return MG_EINVAL;
+    TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, n, smoother, by, zchunk, 0);
+    if (prefetch) cfg.pd = prefetch;
+    if (!valid_cfg(cfg) || (cfg.pd != 1 && cfg.pd != 2)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
     h.u = const_cast<void*>(u_in);
@@ -596,7 +840,7 @@ int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const v
                                int by, int zchunk, void* stream) {
     if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
     if (!u || !f || !fc) return MG_EINVAL;
-    const TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, by, zchunk, 1);
+    const TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, n, 0, by, zchunk, 1);
     if (!valid_cfg(cfg)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
@@ -650,7 +894,7 @@ int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, cons
                        double* u_out, float* r, double* norm_out, int by, int zchunk, void* stream) {
     if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5) return MG_EINVAL;
     if (!u_in || !e || !f || !u_out || !r || !norm_out || u_in == u_out) return MG_EINVAL;
-    const TileCfg cfg = pick_cfg(dim, 8, by, zchunk, 2);
+    const TileCfg cfg = pick_cfg(dim, 8, n, 0, by, zchunk, 2);
     if (!valid_cfg(cfg)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     IRDesc h{};

@@ -52,8 +52,9 @@ struct IRDesc {
 
 // Launch geometry of one kernel family (picked by the autotuner).
 struct TileCfg {
-    int by;      // LDS box rows (2D) / rows of the x-y box (3D): 8, 16, 32 or 64
+    int by;      // LDS box rows (2D) / rows of the x-y box (3D): 8, 16 or 32
     int zchunk;  // 3D: output planes per workgroup (ignored in 2D)
+    int pd = 1;  // 3D smoothing: planes of old u prefetched ahead (1 or 2)
 };
 
 // Number of workgroups in x for a level of n nodes per axis (one instance).
@@ -66,6 +67,13 @@ int norm_tiles(int dim, int n, TileCfg cfg);
 template <typename T>
 hipError_t launch_smooth(int dim, int sm, bool var, const GridDesc* d, int ninst, int n, int sel, int flags,
                          TileCfg cfg, hipStream_t s);
+// Per-dimension sweep launchers behind launch_smooth (grid already sized).
+template <typename T>
+hipError_t launch_smooth2d(int sm, bool var, const GridDesc* d, int sel, int flags, TileCfg cfg, dim3 grid,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_smooth3d(int sm, bool var, const GridDesc* d, int sel, int flags, TileCfg cfg, dim3 grid,
+                           hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(int dim, bool var, const GridDesc* d, int ninst, int nf, int sel, TileCfg cfg,
                            hipStream_t s);

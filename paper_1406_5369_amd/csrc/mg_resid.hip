@@ -1,0 +1,507 @@
+// FP64 residual norms, the FP64 refinement pass, device-side solve control and setup kernels.
+#include "mg_kern.h"
+
+namespace mg {
+namespace {
+
+// ---------------------------------------------------------------------------
+// FP64 residual norm partials (solve loop of the Layer-4 Application function)
+// ---------------------------------------------------------------------------
+
+template <bool VAR, int BY>
+__global__ __launch_bounds__(NT) void k_norm2d(const GridDesc* __restrict__ descs, int sel, double* __restrict__ part,
+                                               int pstride) {
+    const GridDesc d = descs[blockIdx.y];
+    __shared__ double red4[4];
+    if (d.done && *gp(d.done)) return;
+    constexpr int TX = BX - 2, TY = BY - 2, RPT = BY / 4;
+    const int n = d.n;
+    const int ntx = (n - 2 + TX - 1) / TX;
+    const int tile = blockIdx.x;
+    const int x0 = 1 + (tile % ntx) * TX, y0 = 1 + (tile / ntx) * TY;
+    const MG_GLOBAL double* __restrict__ u = gp((const double*)(sel ? d.t : d.u));
+    const MG_GLOBAL double* __restrict__ f = gp((const double*)d.f);
+    const MG_GLOBAL double* __restrict__ kf = gp((const double*)d.k);
+    const double c = d.c;
+    __shared__ double U[BY][BX];
+    __shared__ double K[VAR ? BY : 1][BX];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gx = x0 - 1 + lane;
+    double fr[RPT];
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w + 4 * m, gy = y0 - 1 + ly;
+        const bool ing = gx < n && gy < n;
+        const size_t p = (size_t)gy * n + gx;
+        U[ly][lane] = ing ? u[p] : 0.0;
+        if constexpr (VAR) K[ly][lane] = ing ? kf[p] : 1.0;
+        fr[m] = ing ? f[p] : 0.0;
+    }
+    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w + 4 * m, gy = y0 - 1 + ly;
+        if (lane >= 1 && lane <= BX - 2 && ly >= 1 && ly <= BY - 2 && gx <= n - 2 && gy <= n - 2) {
+            double ds;
+            const double r = lds_res2<double, VAR>(U, K, ly, lane, fr[m], c, ds);
+            acc += r * r;
+        }
+    }
+    const double s = block_sum(acc, red4);
+    if (threadIdx.x == 0) part[(size_t)d.inst * pstride + blockIdx.x] = s;
+}
+
+// 3D residual of the FP64 finest level, marching along z.  IR selects the
+// refinement variant: the plane entering the ring is u_in + e (inner nodes),
+// its owned part is written to u_out, and r is stored in FP32.
+template <bool VAR, int BY, int PD, bool IR>
+struct Resid3D {
+    static constexpr int TX = BX - 2, TY = BY - 2, RPT = BY / 4;
+    double (*U)[BY][BX];
+    double (*K)[BY][BX];
+    const MG_GLOBAL double* __restrict__ uin;
+    MG_GLOBAL double* __restrict__ uout;
+    const MG_GLOBAL float* __restrict__ e;
+    const MG_GLOBAL double* __restrict__ f;
+    const MG_GLOBAL double* __restrict__ kf;
+    MG_GLOBAL float* __restrict__ r32;
+    int n, x0, y0, z0, z1, kstart, kend, flags;
+    double c;
+    int lane, w, gx;
+    bool coli, lane1;
+    double un[3][RPT], kn[3][RPT], fr[3][RPT];
+    double uo[3][RPT], ko[3][RPT];  // plane values (u + e) and k at own positions, planes kk, kk-1, kk-2
+    float en[3][RPT];
+    double acc = 0.0;
+
+    __device__ __forceinline__ size_t at(int x, int y, int z) const { return ((size_t)z * n + y) * n + x; }
+    __device__ __forceinline__ int gy(int m) const { return y0 - 1 + w + 4 * m; }
+
+    // unconditional loads from clamped addresses, values selected afterwards
+    __device__ __forceinline__ void issue(int z, double (&du)[RPT], float (&de)[RPT], double (&dk)[RPT]) {
+        const bool zok = z < n && z <= kend;
+        const bool zin = z >= 1 && z <= n - 2;
+        const int zc = min(max(z, 0), n - 1), xc = min(max(gx, 0), n - 1);
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int y = gy(m);
+            const bool ing = zok && gx < n && y < n;
+            const size_t p = at(xc, min(max(y, 0), n - 1), zc);
+            const double v = uin[p];
+            du[m] = ing ? v : 0.0;
+            if constexpr (IR) {
+                if (!(flags & IR_NO_UPDATE)) {
+                    const float ev = e[p];
+                    de[m] = (zin && coli && y >= 1 && y <= n - 2) ? ev : 0.0f;
+                } else {
+                    de[m] = 0.0f;
+                }
+            }
+            if constexpr (VAR) {
+                const double kv = kf[p];
+                dk[m] = ing ? kv : 1.0;
+            }
+        }
+    }
+    __device__ __forceinline__ void issue_f(int z, double (&dst)[RPT]) {
+        const bool zin = z >= 1 && z <= n - 2;
+        const int zc = min(max(z, 0), n - 1), xc = min(max(gx, 0), n - 1);
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int y = gy(m), ly = w + 4 * m;
+            const double v = f[at(xc, min(max(y, 0), n - 1), zc)];
+            dst[m] = (zin && coli && y >= 1 && y <= n - 2 && lane1 && ly >= 1 && ly <= BY - 2) ? v : 0.0;
+        }
+    }
+
+    template <int P>
+    __device__ __forceinline__ void step(int kk) {
+        constexpr int S0 = P, S1 = (P + 2) % 3, S2 = (P + 1) % 3, SN = (P + PD) % 3;
+        const bool zin = kk >= 1 && kk <= n - 2;
+        const bool own = kk >= z0 && kk < z1;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + 4 * m, y = gy(m);
+            double v = un[S0][m];
+            if constexpr (IR) {
+                const bool inn = zin && coli && y >= 1 && y <= n - 2;
+                if (inn && !(flags & IR_NO_UPDATE)) {
+                    v = v + (double)en[S0][m];
+                    if (own && lane1 && ly >= 1 && ly <= BY - 2) uout[at(gx, y, kk)] = v;
+                }
+            }
+            uo[S0][m] = v;
+            U[S0][ly][lane] = v;
+            if constexpr (VAR) {
+                ko[S0][m] = kn[S0][m];
+                K[S0][ly][lane] = kn[S0][m];
+            }
+        }
+        issue_f(kk, fr[S0]);
+        issue(kk + PD, un[SN], en[SN], kn[SN]);
+        __syncthreads();
+        // residual of plane kk-1: z-neighbours from registers, x from the
+        // adjacent lanes, y from LDS (slot S1 is rewritten two steps later,
+        // after the next barrier)
+        const int zz = kk - 1;
+        if (zz >= z0) {
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) {
+                const int ly = w + 4 * m, y = gy(m);
+                const double uc = uo[S1][m];
+                const double uw = lane_prev(uc), ue = lane_next(uc);
+                double kc = 1.0, kw = 1.0, ke = 1.0, kb = 1.0, ka = 1.0, kS = 1.0, kN = 1.0;
+                if constexpr (VAR) {
+                    kc = ko[S1][m];
+                    kw = lane_prev(kc);
+                    ke = lane_next(kc);
+                    kb = ko[S2][m];
+                    ka = ko[S0][m];
+                }
+                if (lane1 && ly >= 1 && ly <= BY - 2 && gx <= n - 2 && y <= n - 2) {
+                    if constexpr (VAR) {
+                        kS = K[S1][ly - 1][lane];
+                        kN = K[S1][ly + 1][lane];
+                    }
+                    double ds;
+                    const double r = res3<double, VAR>(uc, uw, ue, U[S1][ly - 1][lane], U[S1][ly + 1][lane],
+                                                       uo[S2][m], uo[S0][m], kc, kw, ke, kS, kN, kb, ka, fr[S1][m],
+                                                       c, ds);
+                    if constexpr (IR) r32[at(gx, y, zz)] = (float)r;
+                    acc += r * r;
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ void run() {
+        int kk = kstart;
+        issue(kk, un[0], en[0], kn[0]);
+        if constexpr (PD == 2) issue(kk + 1, un[1], en[1], kn[1]);
+        for (; kk + 2 <= kend; kk += 3) {
+            step<0>(kk);
+            step<1>(kk + 1);
+            step<2>(kk + 2);
+        }
+        if (kk <= kend) step<0>(kk);
+        if (kk + 1 <= kend) step<1>(kk + 1);
+    }
+};
+
+template <bool VAR, int BY, int PD, bool IR>
+__device__ __forceinline__ void resid3d_body(const GridDesc* gd, const IRDesc* ird, int sel, int flags,
+                                             double* __restrict__ part, int pstride, int zchunk) {
+    using S = Resid3D<VAR, BY, PD, IR>;
+    __shared__ double red4[4];
+    __shared__ double U[3][BY][BX];
+    __shared__ double K[VAR ? 3 : 1][BY][BX];
+    S s;
+    int n, inst;
+    if constexpr (IR) {
+        const IRDesc d = *ird;
+        n = d.n;
+        inst = d.inst;
+        s.uin = gp((const double*)(sel ? d.u[1] : d.u[0]));  // a select: indexing the copy would spill it
+        s.uout = gp(sel ? d.u[0] : d.u[1]);
+        s.e = gp(d.e);
+        s.f = gp(d.f);
+        s.kf = gp(d.k);
+        s.r32 = gp(d.r);
+        s.c = d.c;
+    } else {
+        const GridDesc d = *gd;
+        n = d.n;
+        inst = d.inst;
+        s.uin = gp((const double*)(sel ? d.t : d.u));
+        s.uout = nullptr;
+        s.e = nullptr;
+        s.f = gp((const double*)d.f);
+        s.kf = gp((const double*)d.k);
+        s.r32 = nullptr;
+        s.c = d.c;
+    }
+    s.U = U;
+    s.K = K;
+    const int ntx = (n - 2 + S::TX - 1) / S::TX, nty = (n - 2 + S::TY - 1) / S::TY;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
+    s.n = n;
+    s.x0 = 1 + tx * S::TX;
+    s.y0 = 1 + ty * S::TY;
+    s.z0 = 1 + tz * zchunk;
+    s.z1 = min(s.z0 + zchunk, n - 1);
+    s.kstart = s.z0 - 1;
+    s.kend = s.z1;
+    s.flags = flags;
+    s.lane = threadIdx.x & 63;
+    s.w = threadIdx.x >> 6;
+    s.gx = s.x0 - 1 + s.lane;
+    s.coli = s.gx >= 1 && s.gx <= n - 2;
+    s.lane1 = s.lane >= 1 && s.lane <= BX - 2;
+    s.run();
+    const double t = block_sum(s.acc, red4);
+    if (threadIdx.x == 0) part[(size_t)inst * pstride + blockIdx.x] = t;
+}
+
+template <bool VAR, int BY, int PD>
+__global__ __launch_bounds__(NT) void k_norm3d(const GridDesc* __restrict__ descs, int sel, double* __restrict__ part,
+                                               int pstride, int zchunk) {
+    const GridDesc* d = descs + blockIdx.y;
+    if (d->done && *gp(d->done)) return;
+    resid3d_body<VAR, BY, PD, false>(d, nullptr, sel, 0, part, pstride, zchunk);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 refinement pass: u_out = u_in + e (inner), r = f - A u_out (FP64),
+// r32 = (float) r on inner nodes, partial sums of r^2.
+// ---------------------------------------------------------------------------
+
+template <bool VAR, int BY, int FL>
+__global__ __launch_bounds__(NT) void k_ir2d(const IRDesc* __restrict__ descs, int sel, double* __restrict__ part,
+                                             int pstride) {
+    constexpr int flags = FL;
+    const IRDesc d = descs[blockIdx.y];
+    __shared__ double red4[4];
+    if (d.done && *gp(d.done)) return;
+    constexpr int TX = BX - 2, TY = BY - 2, RPT = BY / 4;
+    const int n = d.n;
+    const int ntx = (n - 2 + TX - 1) / TX;
+    const int tile = blockIdx.x;
+    const int x0 = 1 + (tile % ntx) * TX, y0 = 1 + (tile / ntx) * TY;
+    const MG_GLOBAL double* __restrict__ uin = gp((const double*)(sel ? d.u[1] : d.u[0]));
+    MG_GLOBAL double* __restrict__ uout = gp(sel ? d.u[0] : d.u[1]);
+    const MG_GLOBAL float* __restrict__ e = gp(d.e);
+    const MG_GLOBAL double* __restrict__ f = gp(d.f);
+    const MG_GLOBAL double* __restrict__ kf = gp(d.k);
+    MG_GLOBAL float* __restrict__ r32 = gp(d.r);
+    const double c = d.c;
+    __shared__ double U[BY][BX];
+    __shared__ double K[VAR ? BY : 1][BX];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gx = x0 - 1 + lane;
+    double fr[RPT];
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w + 4 * m, gy = y0 - 1 + ly;
+        const bool ing = gx < n && gy < n;
+        const bool inn = gx >= 1 && gx <= n - 2 && gy >= 1 && gy <= n - 2;
+        const size_t p = (size_t)gy * n + gx;
+        double v = ing ? uin[p] : 0.0;
+        if (inn && !(flags & IR_NO_UPDATE)) v = v + (double)e[p];
+        U[ly][lane] = v;
+        if constexpr (VAR) K[ly][lane] = ing ? kf[p] : 1.0;
+        fr[m] = ing ? f[p] : 0.0;
+    }
+    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w + 4 * m, gy = y0 - 1 + ly;
+        if (lane >= 1 && lane <= BX - 2 && ly >= 1 && ly <= BY - 2 && gx <= n - 2 && gy <= n - 2) {
+            const size_t p = (size_t)gy * n + gx;
+            double ds;
+            const double r = lds_res2<double, VAR>(U, K, ly, lane, fr[m], c, ds);
+            if (!(flags & IR_NO_UPDATE)) uout[p] = U[ly][lane];
+            r32[p] = (float)r;
+            acc += r * r;
+        }
+    }
+    const double s = block_sum(acc, red4);
+    if (threadIdx.x == 0) part[(size_t)d.inst * pstride + blockIdx.x] = s;
+}
+
+template <bool VAR, int BY, int PD, int FL>
+__global__ __launch_bounds__(NT) void k_ir3d(const IRDesc* __restrict__ descs, int sel, double* __restrict__ part,
+                                             int pstride, int zchunk) {
+    const IRDesc* d = descs + blockIdx.y;
+    if (d->done && *gp(d->done)) return;
+    resid3d_body<VAR, BY, PD, true>(nullptr, d, sel, FL, part, pstride, zchunk);
+}
+
+__global__ __launch_bounds__(NT) void k_norm_finalize(const double* __restrict__ part, int pstride, int nparts,
+                                                      int row0, double* __restrict__ norm) {
+    __shared__ double red4[4];
+    const int row = row0 + blockIdx.x;
+    const double* p = part + (size_t)row * pstride;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += NT) s += p[i];
+    const double t = block_sum(s, red4);
+    if (threadIdx.x == 0) norm[row] = sqrt(t);
+}
+
+// Start of a solve: norm0 = norm, hist[0] = norm, steps = 0, and a zero
+// initial residual is already converged.
+__global__ void k_solve_init(const double* __restrict__ norm, double* __restrict__ norm0, int* __restrict__ done,
+                             int* __restrict__ steps, int* __restrict__ status, double* __restrict__ hist,
+                             int hstride, int ninst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    const double r = norm[i];
+    norm0[i] = r;
+    steps[i] = 0;
+    if (hist) hist[(size_t)i * hstride] = r;
+    const bool zero = r == 0.0;
+    const bool bad = !(r == r) || r > 1e300;
+    status[i] = bad ? -5 : (zero ? 0 : 1);
+    done[i] = (zero || bad) ? 1 : 0;
+}
+
+// After each cycle: count it, record the residual, and stop the instance
+// when converged (rho <= tol rho0), diverged (NaN/Inf or growth > 1e6) or
+// out of cycles.  status: 1 running, 0 converged, 2 not converged, -5 diverged.
+__global__ void k_stop_test(const double* __restrict__ norm, const double* __restrict__ norm0, int* __restrict__ done,
+                            int* __restrict__ steps, int* __restrict__ status, double* __restrict__ hist, int hstride,
+                            double tol, int max_steps, int ninst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || done[i]) return;
+    const double r = norm[i], r0 = norm0[i];
+    const int s = steps[i] + 1;
+    steps[i] = s;
+    if (hist && s < hstride) hist[(size_t)i * hstride + s] = r;
+    int st = 1;
+    if (!(r == r) || r > 1e300) st = -5;
+    else if (r > 1e6 * r0) st = -5;
+    else if (r <= tol * r0) st = 0;
+    else if (s >= max_steps) st = 2;
+    if (st != 1) {
+        status[i] = st;
+        done[i] = 1;
+    }
+}
+
+// Setup helpers: coarse coefficient by injection, precision conversion, fills.
+template <typename TS, typename TD>
+__global__ __launch_bounds__(NT) void k_inject(const TS* __restrict__ src, int nf, TD* __restrict__ dst, int nc,
+                                               int dim) {
+    const size_t total = dim == 2 ? (size_t)nc * nc : (size_t)nc * nc * nc;
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        const int I = (int)(q % nc);
+        const size_t r = q / nc;
+        const int J = (int)(r % nc);
+        const int K = dim == 2 ? 0 : (int)(r / nc);
+        dst[q] = (TD)src[((size_t)(2 * K) * nf + 2 * J) * nf + 2 * I];
+    }
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(NT) void k_convert(const TS* __restrict__ src, TD* __restrict__ dst, size_t total) {
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) dst[q] = (TD)src[q];
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int v, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_norm(int dim, bool var, const GridDesc* d, int ninst, int n, int sel, double* partial, int pstride,
+                       TileCfg cfg, hipStream_t s) {
+    const dim3 grid(norm_tiles(dim, n, cfg), ninst);
+    if ((int)grid.x > pstride) return hipErrorInvalidValue;
+    if (dim == 2) {
+        if (var) {
+            MG_BY_SWITCH(cfg.by, (k_norm2d<true, BY><<<grid, NT, 0, s>>>(d, sel, partial, pstride)))
+        } else {
+            MG_BY_SWITCH(cfg.by, (k_norm2d<false, BY><<<grid, NT, 0, s>>>(d, sel, partial, pstride)))
+        }
+    } else {
+        if (var) {
+            if (cfg.pd == 2) {
+                MG_BY_SWITCH(cfg.by, (k_norm3d<true, BY, 2><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+            } else {
+                MG_BY_SWITCH(cfg.by, (k_norm3d<true, BY, 1><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+            }
+        } else {
+            if (cfg.pd == 2) {
+                MG_BY_SWITCH(cfg.by, (k_norm3d<false, BY, 2><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+            } else {
+                MG_BY_SWITCH(cfg.by, (k_norm3d<false, BY, 1><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+            }
+        }
+    }
+    return hipGetLastError();
+}
+
+template <bool VARV, int FL>
+hipError_t launch_ir_fl(int dim, const IRDesc* d, int sel, double* partial, int pstride, TileCfg cfg, dim3 grid,
+                        hipStream_t s) {
+    if (dim == 2) {
+        MG_BY_SWITCH(cfg.by, (k_ir2d<VARV, BY, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride)))
+    } else if (cfg.pd == 2) {
+        MG_BY_SWITCH(cfg.by, (k_ir3d<VARV, BY, 2, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+    } else {
+        MG_BY_SWITCH(cfg.by, (k_ir3d<VARV, BY, 1, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_ir_update(int dim, bool var, const IRDesc* d, int ninst, int n, int sel, int flags,
+                            double* partial, int pstride, TileCfg cfg, hipStream_t s) {
+    const dim3 grid(norm_tiles(dim, n, cfg), ninst);
+    if ((int)grid.x > pstride) return hipErrorInvalidValue;
+    hipError_t e;
+    if (flags == IR_NO_UPDATE) {
+        e = var ? launch_ir_fl<true, IR_NO_UPDATE>(dim, d, sel, partial, pstride, cfg, grid, s)
+                : launch_ir_fl<false, IR_NO_UPDATE>(dim, d, sel, partial, pstride, cfg, grid, s);
+    } else if (flags == 0) {
+        e = var ? launch_ir_fl<true, 0>(dim, d, sel, partial, pstride, cfg, grid, s)
+                : launch_ir_fl<false, 0>(dim, d, sel, partial, pstride, cfg, grid, s);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_finalize(const double* partial, int pstride, int nparts, int row0, int ninst, double* norm,
+                                hipStream_t s) {
+    k_norm_finalize<<<ninst, NT, 0, s>>>(partial, pstride, nparts, row0, norm);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_init(const double* norm, double* norm0, int* done, int* steps, int* status, double* hist,
+                             int hstride, int ninst, hipStream_t s) {
+    k_solve_init<<<cdiv(ninst, 256), 256, 0, s>>>(norm, norm0, done, steps, status, hist, hstride, ninst);
+    return hipGetLastError();
+}
+
+hipError_t launch_stop_test(const double* norm, const double* norm0, int* done, int* steps, int* status, double* hist,
+                            int hstride, double tol, int max_steps, int ninst, hipStream_t s) {
+    k_stop_test<<<cdiv(ninst, 256), 256, 0, s>>>(norm, norm0, done, steps, status, hist, hstride, tol, max_steps,
+                                                  ninst);
+    return hipGetLastError();
+}
+
+template <typename TS, typename TD>
+hipError_t launch_inject(int dim, int nf, const TS* src, int nc, TD* dst, hipStream_t s) {
+    const size_t total = dim == 2 ? (size_t)nc * nc : (size_t)nc * nc * nc;
+    const int blocks = (int)std::min<size_t>((total + NT - 1) / NT, 8192);
+    k_inject<TS, TD><<<blocks, NT, 0, s>>>(src, nf, dst, nc, dim);
+    return hipGetLastError();
+}
+template hipError_t launch_inject<double, double>(int, int, const double*, int, double*, hipStream_t);
+template hipError_t launch_inject<double, float>(int, int, const double*, int, float*, hipStream_t);
+template hipError_t launch_inject<float, float>(int, int, const float*, int, float*, hipStream_t);
+
+template <typename TS, typename TD>
+hipError_t launch_convert(size_t total, const TS* src, TD* dst, hipStream_t s) {
+    const int blocks = (int)std::min<size_t>((total + NT - 1) / NT, 8192);
+    k_convert<TS, TD><<<blocks, NT, 0, s>>>(src, dst, total);
+    return hipGetLastError();
+}
+template hipError_t launch_convert<double, float>(size_t, const double*, float*, hipStream_t);
+template hipError_t launch_convert<double, double>(size_t, const double*, double*, hipStream_t);
+template hipError_t launch_convert<float, float>(size_t, const float*, float*, hipStream_t);
+
+hipError_t launch_fill_int(int* p, int v, int count, hipStream_t s) {
+    k_fill_int<<<cdiv(count, 256), 256, 0, s>>>(p, v, count);
+    return hipGetLastError();
+}
+
+
+
+
+
+}  // namespace mg

@@ -1,0 +1,126 @@
+// 2D smoothing sweeps (omega-Jacobi, fused red-black Gauss-Seidel); one LDS tile per workgroup.
+#include "mg_kern.h"
+
+namespace mg {
+namespace {
+
+// ---------------------------------------------------------------------------
+// 2D smoothing sweep (one LDS tile per workgroup, no marching)
+// ---------------------------------------------------------------------------
+
+template <typename T, int SM, bool VAR, int BY, int FL>
+__global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ descs, int sel) {
+    constexpr int flags = FL;
+    const GridDesc d = descs[blockIdx.y];
+    if (d.done && *gp(d.done)) return;
+    constexpr int H = SM == SM_RBGS ? 2 : 1;
+    constexpr int TX = BX - 2 * H, TY = BY - 2 * H, RPT = BY / 4;
+    const int n = d.n;
+    const int ntx = (n - 2 + TX - 1) / TX;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = 1 + (tile % ntx) * TX, y0 = 1 + (tile / ntx) * TY;
+    const MG_GLOBAL T* __restrict__ uin = gp((const T*)(sel ? d.t : d.u));
+    MG_GLOBAL T* __restrict__ uout = gp((T*)(sel ? d.u : d.t));
+    const MG_GLOBAL T* __restrict__ f = gp((const T*)d.f);
+    const MG_GLOBAL T* __restrict__ kf = gp((const T*)d.k);
+    const MG_GLOBAL T* __restrict__ ec = gp((const T*)d.uc);
+    const int nc = (n - 1) / 2 + 1;
+    const T c = (T)d.c, wd = (T)d.wd, om = (T)d.omega;
+
+    __shared__ T U[BY][BX];
+    __shared__ T R[SM == SM_RBGS ? BY : 1][BX];
+    __shared__ T K[VAR ? BY : 1][BX];
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gx = x0 - H + lane;
+    const bool colg = gx >= 0 && gx < n, coli = gx >= 1 && gx <= n - 2;
+    const bool lane1 = lane >= 1 && lane <= BX - 2;  // tile + 1 ring (RBGS) / tile (Jacobi)
+    T fr[RPT];
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w + 4 * m, gy = y0 - H + ly;
+        const bool ing = colg && gy >= 0 && gy < n;
+        const bool inn = coli && gy >= 1 && gy <= n - 2;
+        const size_t p = (size_t)gy * n + gx;
+        T v = T(0);
+        if (ing && !(flags & SWEEP_ZERO_GUESS)) v = uin[p];
+        if (inn && (flags & SWEEP_PROLONG)) v = v + interp2<T>(ec, nc, gx, gy);
+        U[ly][lane] = v;
+        if constexpr (VAR) K[ly][lane] = ing ? kf[p] : T(1);
+        fr[m] = (inn && lane1 && ly >= 1 && ly <= BY - 2) ? f[p] : T(0);
+    }
+    __syncthreads();
+    if constexpr (SM == SM_RBGS) {
+        // red half-sweep on the tile plus a one-node ring
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + 4 * m, gy = y0 - H + ly;
+            if (lane1 && ly >= 1 && ly <= BY - 2) {
+                const bool inn = coli && gy >= 1 && gy <= n - 2;
+                T v = U[ly][lane];
+                if (inn && ((gx + gy) & 1) == 0) {
+                    T ds;
+                    const T r = lds_res2<T, VAR>(U, K, ly, lane, fr[m], c, ds);
+                    v = relax<T, VAR>(v, r, ds, c, wd, om);
+                }
+                R[ly][lane] = v;
+            }
+        }
+        __syncthreads();
+        // black half-sweep on the tile, written out of place
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + 4 * m, gy = y0 - H + ly;
+            if (lane >= 2 && lane <= BX - 3 && ly >= 2 && ly <= BY - 3 && gx <= n - 2 && gy <= n - 2) {
+                T v = R[ly][lane];
+                if (((gx + gy) & 1) == 1) {
+                    T ds;
+                    const T r = lds_res2<T, VAR>(R, K, ly, lane, fr[m], c, ds);
+                    v = relax<T, VAR>(v, r, ds, c, wd, om);
+                }
+                uout[(size_t)gy * n + gx] = v;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + 4 * m, gy = y0 - H + ly;
+            if (lane1 && ly >= 1 && ly <= BY - 2 && gx <= n - 2 && gy <= n - 2) {
+                T ds;
+                const T r = lds_res2<T, VAR>(U, K, ly, lane, fr[m], c, ds);
+                uout[(size_t)gy * n + gx] = relax<T, VAR>(U[ly][lane], r, ds, c, wd, om);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+template <typename T, int SMV, bool VARV, int FL>
+hipError_t launch_smooth2d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
+    MG_BY_SWITCH(cfg.by, (k_smooth2d<T, SMV, VARV, BY, FL><<<grid, NT, 0, s>>>(d, sel)))
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_smooth2d(int sm, bool var, const GridDesc* d, int sel, int flags, TileCfg cfg, dim3 grid,
+                           hipStream_t s) {
+#define MG_FL(SMV, VARV)                                                                                   \
+    switch (flags) {                                                                                       \
+        case 0: return launch_smooth2d_fl<T, SMV, VARV, 0>(d, sel, cfg, grid, s);                           \
+        case SWEEP_ZERO_GUESS: return launch_smooth2d_fl<T, SMV, VARV, SWEEP_ZERO_GUESS>(d, sel, cfg, grid, s); \
+        case SWEEP_PROLONG: return launch_smooth2d_fl<T, SMV, VARV, SWEEP_PROLONG>(d, sel, cfg, grid, s);   \
+        default: return hipErrorInvalidValue;                                                              \
+    }
+    if (sm == SM_RBGS) {
+        if (var) MG_FL(SM_RBGS, true) else MG_FL(SM_RBGS, false)
+    } else {
+        if (var) MG_FL(SM_JACOBI, true) else MG_FL(SM_JACOBI, false)
+    }
+#undef MG_FL
+}
+
+template hipError_t launch_smooth2d<double>(int, bool, const GridDesc*, int, int, TileCfg, dim3, hipStream_t);
+template hipError_t launch_smooth2d<float>(int, bool, const GridDesc*, int, int, TileCfg, dim3, hipStream_t);
+
+}  // namespace mg

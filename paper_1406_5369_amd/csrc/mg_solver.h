@@ -18,7 +18,11 @@ struct Tiles {
     TileCfg norm{16, 128};
 };
 
-Tiles default_tiles(int dim, int elem_bytes);
+// Heuristic launch geometry for one level (used when autotuning is off and
+// for levels too small to be worth timing): enough workgroups to cover the
+// chip (z-chunks in 3D) and the smallest tile height on small grids.
+Tiles default_tiles(int dim, int elem_bytes, int n, int smoother);
+int heuristic_zchunk(int dim, int n, int by, int halo, int target_blocks);
 
 // Device buffers of one instance's hierarchy in working precision T
 // (sizeof(T) bytes per value).  Level 0 buffers may belong to the caller.
@@ -47,7 +51,7 @@ struct Problem {
 // V-cycle over groups[0..L-1] (groups[l] holds every instance's level l);
 // zero_top: the iterate at level 0 is known to be zero.  Works in precision T.
 template <typename T>
-hipError_t vcycle(const Problem& P, const std::vector<Group>& groups, bool zero_top, const Tiles& tiles,
+hipError_t vcycle(const Problem& P, const std::vector<Group>& groups, bool zero_top, const std::vector<Tiles>& tiles,
                   hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap);
 
 size_t npts(int dim, int n);
@@ -63,7 +67,9 @@ struct mg_ctx {
     mg::Problem prob{};
     int nlev = 0;
     std::vector<int> n;
-    mg::Tiles t64, t32;
+    std::vector<mg::Tiles> tl64, tl32;  // per level launch geometry of each hierarchy
+    mg::Tiles top;                      // finest-level FP64 norm / refinement kernels
+    bool autotune = true;
 
     // FP64 hierarchy (precision FP64): level 0 u/f are the caller's.
     mg::Levels L64;

@@ -18,23 +18,54 @@ int count_levels(int n) {
     return L;
 }
 
-Tiles default_tiles(int dim, int elem_bytes) {
+int heuristic_zchunk(int dim, int n, int by, int halo, int target_blocks) {
+    if (dim == 2) return 1;
+    const int m = n - 2;
+    const int TX = 64 - 2 * halo, TY = by - 2 * halo;
+    const int cols = ((m + TX - 1) / TX) * ((m + TY - 1) / TY);
+    const int chunks = std::max(1, (target_blocks + cols - 1) / cols);
+    return std::max(2, (m + chunks - 1) / chunks);
+}
+
+Tiles default_tiles(int dim, int elem_bytes, int n, int smoother) {
     Tiles t;
+    const int H = smoother == SM_RBGS ? 2 : 1;
+    const int target = 2048;
     if (dim == 2) {
-        t.smooth = {32, 1};
-        t.restr = {32, 1};
-        t.norm = {32, 1};
-    } else if (elem_bytes == 8) {
-        t.smooth = {16, 128};
-        t.restr = {16, 64};
-        t.norm = {16, 128};
-    } else {
-        t.smooth = {16, 128};
-        t.restr = {16, 64};
-        t.norm = {16, 128};
+        const int by = n >= 257 ? 32 : (n >= 65 ? 16 : 8);
+        t.smooth = {by, 1};
+        t.restr = {by < 16 ? 16 : by, 1};
+        t.norm = {by, 1};
+        return t;
     }
+    const int by = n >= 129 ? 16 : 8;
+    t.smooth = {by, heuristic_zchunk(3, n, by, H, target)};
+    const int nc = (n - 1) / 2 + 1;
+    const int rb = 16;
+    // restriction tiles: 30 x ((rb-3)/2) coarse nodes per z-chunk of coarse planes
+    {
+        const int mc = nc - 2;
+        const int cols = ((mc + 29) / 30) * ((mc + (rb - 3) / 2 - 1) / ((rb - 3) / 2));
+        const int chunks = std::max(1, (target + cols - 1) / std::max(cols, 1));
+        t.restr = {rb, std::max(1, (mc + chunks - 1) / chunks)};
+    }
+    t.norm = {by, heuristic_zchunk(3, n, by, 1, target)};
+    (void)elem_bytes;
     return t;
 }
+
+template <typename T>
+hipError_t launch_smooth(int dim, int sm, bool var, const GridDesc* d, int ninst, int n, int sel, int flags,
+                         TileCfg cfg, hipStream_t s) {
+    if (n < 5 || ninst <= 0) return hipErrorInvalidValue;
+    const dim3 grid(smooth_tiles(dim, sm, n, cfg), ninst);
+    const hipError_t e = dim == 2 ? launch_smooth2d<T>(sm, var, d, sel, flags, cfg, grid, s)
+                                  : launch_smooth3d<T>(sm, var, d, sel, flags, cfg, grid, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+template hipError_t launch_smooth<double>(int, int, bool, const GridDesc*, int, int, int, int, TileCfg, hipStream_t);
+template hipError_t launch_smooth<float>(int, int, bool, const GridDesc*, int, int, int, int, TileCfg, hipStream_t);
 
 namespace {
 
@@ -65,8 +96,8 @@ struct Prof {
     } while (0)
 
 template <typename T>
-hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, const Tiles& tiles, hipStream_t s,
-                  hipEvent_t* prof_ev, int* prof_n, int prof_cap) {
+hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, const std::vector<Tiles>& tiles,
+                  hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap) {
     const int L = (int)G.size();
     const int dim = P.dim;
     Prof prof{prof_ev, prof_n, prof_cap, s};
@@ -79,13 +110,15 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
         int cur = 0;
         for (int i = 0; i < P.nu1; ++i) {
             const int flags = (i == 0 && zero) ? SWEEP_ZERO_GUESS : 0;
-            if (l == 0) prof.begin();
-            MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags, tiles.smooth, s));
-            if (l == 0) prof.end();
+            const bool timed = l == 0 && flags == 0;  // plain finest-level sweeps only
+            if (timed) prof.begin();
+            MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags, tiles[(size_t)l].smooth,
+                                    s));
+            if (timed) prof.end();
             cur ^= 1;
         }
         if (P.nu1 == 0 && zero) MG_TRY(launch_zero_u<T>(dim, g.d, g.ninst, g.n, s));
-        MG_TRY(launch_restrict<T>(dim, P.var, g.d, g.ninst, g.n, cur, tiles.restr, s));
+        MG_TRY(launch_restrict<T>(dim, P.var, g.d, g.ninst, g.n, cur, tiles[(size_t)l].restr, s));
         sel[(size_t)l] = cur;
     }
     // coarsest grid: exact solve from the zero guess
@@ -98,9 +131,11 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
         if (!fuse) MG_TRY(launch_prolong<T>(dim, g.d, g.ninst, g.n, cur, s));
         for (int i = 0; i < P.nu2; ++i) {
             const int flags = (i == 0 && fuse) ? SWEEP_PROLONG : 0;
-            if (l == 0) prof.begin();
-            MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags, tiles.smooth, s));
-            if (l == 0) prof.end();
+            const bool timed = l == 0 && flags == 0;
+            if (timed) prof.begin();
+            MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags, tiles[(size_t)l].smooth,
+                                    s));
+            if (timed) prof.end();
             cur ^= 1;
         }
         if (cur == 1) MG_TRY(launch_copy_t_to_u<T>(dim, g.d, g.ninst, g.n, s));
@@ -108,9 +143,9 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
     return hipSuccess;
 }
 
-template hipError_t vcycle<double>(const Problem&, const std::vector<Group>&, bool, const Tiles&, hipStream_t,
-                                   hipEvent_t*, int*, int);
-template hipError_t vcycle<float>(const Problem&, const std::vector<Group>&, bool, const Tiles&, hipStream_t,
-                                  hipEvent_t*, int*, int);
+template hipError_t vcycle<double>(const Problem&, const std::vector<Group>&, bool, const std::vector<Tiles>&,
+                                   hipStream_t, hipEvent_t*, int*, int);
+template hipError_t vcycle<float>(const Problem&, const std::vector<Group>&, bool, const std::vector<Tiles>&,
+                                  hipStream_t, hipEvent_t*, int*, int);
 
 }  // namespace mg

@@ -1,0 +1,368 @@
+// Residual + full-weighting restriction, interpolation + correction, coarsest solve, copies.
+#include "mg_kern.h"
+
+namespace mg {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Residual + full-weighting restriction (Algorithm 1, residual and restrict)
+//   fc(I) = sum_delta prod_a 2^-|delta_a| / 2^d * r(2I + delta), r = f - A u
+// 2D: (0.25 rC + 0.125 ((rW+rE)+(rS+rN))) + 0.0625 ((rSW+rSE)+(rNW+rNE))
+// 3D: ((0.125 rC + 0.0625 faces) + 0.03125 edges) + 0.015625 corners with
+//   faces = ((rW+rE)+(rS+rN))+(rB+rT), edges = (exy+exz)+eyz, each e a sum of
+//   the four edge midpoints of one coordinate plane in (-,-),(+,-),(-,+),(+,+)
+//   order paired as (a+b)+(c+d), corners = (z- face quad) + (z+ face quad).
+// A workgroup owns CX x CY coarse nodes: fine box of (2CX+3) x (2CY+3).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T fw2(const T (*Rr)[BX], int ly, int lx) {
+    const T edges = (Rr[ly][lx - 1] + Rr[ly][lx + 1]) + (Rr[ly - 1][lx] + Rr[ly + 1][lx]);
+    const T corners = (Rr[ly - 1][lx - 1] + Rr[ly - 1][lx + 1]) + (Rr[ly + 1][lx - 1] + Rr[ly + 1][lx + 1]);
+    return (T(0.25) * Rr[ly][lx] + T(0.125) * edges) + T(0.0625) * corners;
+}
+
+template <typename T>
+__device__ __forceinline__ T fw3(const T (*Rb)[BX], const T (*Rc)[BX], const T (*Ra)[BX], int ly, int lx) {
+    const T faces = ((Rc[ly][lx - 1] + Rc[ly][lx + 1]) + (Rc[ly - 1][lx] + Rc[ly + 1][lx])) + (Rb[ly][lx] + Ra[ly][lx]);
+    const T exy = (Rc[ly - 1][lx - 1] + Rc[ly - 1][lx + 1]) + (Rc[ly + 1][lx - 1] + Rc[ly + 1][lx + 1]);
+    const T exz = (Rb[ly][lx - 1] + Rb[ly][lx + 1]) + (Ra[ly][lx - 1] + Ra[ly][lx + 1]);
+    const T eyz = (Rb[ly - 1][lx] + Rb[ly + 1][lx]) + (Ra[ly - 1][lx] + Ra[ly + 1][lx]);
+    const T edges = (exy + exz) + eyz;
+    const T cz0 = (Rb[ly - 1][lx - 1] + Rb[ly - 1][lx + 1]) + (Rb[ly + 1][lx - 1] + Rb[ly + 1][lx + 1]);
+    const T cz1 = (Ra[ly - 1][lx - 1] + Ra[ly - 1][lx + 1]) + (Ra[ly + 1][lx - 1] + Ra[ly + 1][lx + 1]);
+    const T corners = cz0 + cz1;
+    return ((T(0.125) * Rc[ly][lx] + T(0.0625) * faces) + T(0.03125) * edges) + T(0.015625) * corners;
+}
+
+template <typename T, bool VAR, int BY>
+__global__ __launch_bounds__(NT) void k_restrict2d(const GridDesc* __restrict__ descs, int sel) {
+    const GridDesc d = descs[blockIdx.y];
+    if (d.done && *gp(d.done)) return;
+    constexpr int CX = (BX - 3) / 2, CY = (BY - 3) / 2, RPT = BY / 4;
+    const int nf = d.n, nc = (nf - 1) / 2 + 1;
+    const int ncx = (nc - 2 + CX - 1) / CX;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int X0 = 1 + (tile % ncx) * CX, Y0 = 1 + (tile / ncx) * CY;
+    const int fx0 = 2 * X0 - 2, fy0 = 2 * Y0 - 2;
+    const MG_GLOBAL T* __restrict__ u = gp((const T*)(sel ? d.t : d.u));
+    const MG_GLOBAL T* __restrict__ f = gp((const T*)d.f);
+    const MG_GLOBAL T* __restrict__ kf = gp((const T*)d.k);
+    MG_GLOBAL T* __restrict__ fc = gp((T*)d.fc);
+    const T c = (T)d.c;
+    __shared__ T U[BY][BX];
+    __shared__ T Rr[BY][BX];
+    __shared__ T K[VAR ? BY : 1][BX];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gx = fx0 + lane;
+    const bool lres = lane >= 1 && lane <= 2 * CX + 1;
+    T fr[RPT];
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w + 4 * m, gy = fy0 + ly;
+        const bool ing = gx < nf && gy < nf && ly <= 2 * CY + 2 && lane <= 2 * CX + 2;
+        const bool inn = gx >= 1 && gx <= nf - 2 && gy >= 1 && gy <= nf - 2;
+        const size_t p = (size_t)gy * nf + gx;
+        U[ly][lane] = ing ? u[p] : T(0);
+        if constexpr (VAR) K[ly][lane] = ing ? kf[p] : T(1);
+        fr[m] = (inn && lres && ly >= 1 && ly <= 2 * CY + 1) ? f[p] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w + 4 * m, gy = fy0 + ly;
+        if (lres && ly >= 1 && ly <= 2 * CY + 1) {
+            const bool inn = gx >= 1 && gx <= nf - 2 && gy >= 1 && gy <= nf - 2;
+            T ds;
+            Rr[ly][lane] = inn ? lds_res2<T, VAR>(U, K, ly, lane, fr[m], c, ds) : T(0);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < CX * CY; t += NT) {
+        const int X = X0 + t % CX, Y = Y0 + t / CX;
+        if (X <= nc - 2 && Y <= nc - 2) fc[(size_t)Y * nc + X] = fw2<T>(Rr, 2 * (Y - Y0) + 2, 2 * (X - X0) + 2);
+    }
+}
+
+// 3D: marching over fine planes; step m publishes u plane m, computes the
+// residual of plane m-1 and, once planes 2K-1..2K+1 are in the residual ring,
+// the coarse plane K.
+template <typename T, bool VAR, int BY>
+__global__ __launch_bounds__(NT) void k_restrict3d(const GridDesc* __restrict__ descs, int sel, int zchunk) {
+    const GridDesc d = descs[blockIdx.y];
+    if (d.done && *gp(d.done)) return;
+    constexpr int CX = (BX - 3) / 2, CY = (BY - 3) / 2, RPT = BY / 4;
+    const int nf = d.n, nc = (nf - 1) / 2 + 1;
+    const int ncx = (nc - 2 + CX - 1) / CX, ncy = (nc - 2 + CY - 1) / CY;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % ncx, t2 = tile / ncx, ty = t2 % ncy, tz = t2 / ncy;
+    const int X0 = 1 + tx * CX, Y0 = 1 + ty * CY, Z0 = 1 + tz * zchunk, Z1 = min(Z0 + zchunk, nc - 1);
+    const int fx0 = 2 * X0 - 2, fy0 = 2 * Y0 - 2;
+    const MG_GLOBAL T* __restrict__ u = gp((const T*)(sel ? d.t : d.u));
+    const MG_GLOBAL T* __restrict__ f = gp((const T*)d.f);
+    const MG_GLOBAL T* __restrict__ kf = gp((const T*)d.k);
+    MG_GLOBAL T* __restrict__ fc = gp((T*)d.fc);
+    const T c = (T)d.c;
+    __shared__ T U[3][BY][BX];
+    __shared__ T Rr[3][BY][BX];
+    __shared__ T K[VAR ? 3 : 1][BY][BX];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gx = fx0 + lane;
+    const bool lres = lane >= 1 && lane <= 2 * CX + 1;
+    const bool colg = gx < nf && lane <= 2 * CX + 2, coli = gx >= 1 && gx <= nf - 2;
+    const size_t pl = (size_t)nf * nf;
+    const int mstart = 2 * Z0 - 2, mend = 2 * Z1;
+    T un[RPT], kn[RPT];
+    T fr[2][RPT];
+    // unconditional loads from clamped addresses, values selected afterwards
+    auto issue_u = [&](int z) {
+        const int zc = min(z, nf - 1), xc = min(gx, nf - 1);
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + 4 * m, gy = fy0 + ly;
+            const bool ing = colg && gy < nf && ly <= 2 * CY + 2 && z < nf;
+            const size_t p = (size_t)zc * pl + (size_t)min(gy, nf - 1) * nf + xc;
+            const T v = u[p];
+            un[m] = ing ? v : T(0);
+            if constexpr (VAR) {
+                const T kv = kf[p];
+                kn[m] = ing ? kv : T(1);
+            }
+        }
+    };
+    auto issue_f = [&](int z, T (&dst)[RPT]) {
+        const bool zin = z >= 1 && z <= nf - 2;
+        const int zc = min(z, nf - 1), xc = min(gx, nf - 1);
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + 4 * m, gy = fy0 + ly;
+            const bool inn = zin && coli && gy >= 1 && gy <= nf - 2 && lres && ly >= 1 && ly <= 2 * CY + 1;
+            const T v = f[(size_t)zc * pl + (size_t)min(gy, nf - 1) * nf + xc];
+            dst[m] = inn ? v : T(0);
+        }
+    };
+    auto step = [&](int mm, T (&fcur)[RPT], T (&fprev)[RPT]) {
+        const int s0 = (mm - mstart) % 3, s1 = (mm - 1 - mstart + 3) % 3, s2 = (mm - 2 - mstart + 6) % 3;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            U[s0][w + 4 * m][lane] = un[m];
+            if constexpr (VAR) K[s0][w + 4 * m][lane] = kn[m];
+        }
+        issue_f(mm, fcur);
+        if (mm + 1 <= mend) issue_u(mm + 1);
+        __syncthreads();
+        const int rp = mm - 1;  // residual plane
+        if (rp >= mstart + 1) {
+            const bool zin = rp >= 1 && rp <= nf - 2;
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) {
+                const int ly = w + 4 * m, gy = fy0 + ly;
+                if (lres && ly >= 1 && ly <= 2 * CY + 1) {
+                    const bool inn = zin && coli && gy >= 1 && gy <= nf - 2;
+                    T ds;
+                    Rr[s1][ly][lane] =
+                        inn ? lds_res3<T, VAR>(U[s2], U[s1], U[s0], K[s2], K[s1], K[s0], ly, lane, fprev[m], c, ds)
+                            : T(0);
+                }
+            }
+        }
+        __syncthreads();
+        if (((rp & 1) == 1) && rp >= 2 * Z0 + 1) {  // rp = 2K+1: planes 2K-1..2K+1 ready
+            const int Kz = (rp - 1) / 2;
+            const int sb = (rp - 2 - mstart + 6) % 3, sc = (rp - 1 - mstart + 3) % 3;  // planes 2K-1, 2K
+            for (int t = threadIdx.x; t < CX * CY; t += NT) {
+                const int X = X0 + t % CX, Y = Y0 + t / CX;
+                if (X <= nc - 2 && Y <= nc - 2)
+                    fc[((size_t)Kz * nc + Y) * nc + X] = fw3<T>(Rr[sb], Rr[sc], Rr[s1], 2 * (Y - Y0) + 2,
+                                                               2 * (X - X0) + 2);
+            }
+        }
+    };
+    int mm = mstart;
+    issue_u(mm);
+    for (; mm + 1 <= mend; mm += 2) {
+        step(mm, fr[0], fr[1]);
+        step(mm + 1, fr[1], fr[0]);
+    }
+    if (mm <= mend) step(mm, fr[0], fr[1]);
+}
+
+// ---------------------------------------------------------------------------
+// Prolongation + correction u += P uc on inner fine nodes (used when no
+// post-smoothing sweep can absorb it), coarsest solve, copies.
+// ---------------------------------------------------------------------------
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_prolong(const GridDesc* __restrict__ descs, int sel) {
+    const GridDesc d = descs[blockIdx.y];
+    if (d.done && *gp(d.done)) return;
+    const int n = d.n, nc = (n - 1) / 2 + 1, m = n - 2;
+    const size_t total = DIM == 2 ? (size_t)m * m : (size_t)m * m * m;
+    MG_GLOBAL T* __restrict__ u = gp((T*)(sel ? d.t : d.u));
+    const MG_GLOBAL T* __restrict__ ec = gp((const T*)d.uc);
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        const int i = 1 + (int)(q % m);
+        const size_t r = q / m;
+        const int j = 1 + (int)(r % m);
+        const int k = DIM == 2 ? 0 : 1 + (int)(r / m);
+        const size_t p = ((size_t)k * n + j) * n + i;
+        u[p] = u[p] + (DIM == 2 ? interp2<T>(ec, nc, i, j) : interp3<T>(ec, nc, i, j, k));
+    }
+}
+
+// n = 3: one unknown, u = f / diag (diag = c*2d, or c*dsum).
+template <typename T, int DIM, bool VAR>
+__global__ void k_coarsest(const GridDesc* __restrict__ descs) {
+    const GridDesc d = descs[blockIdx.x];
+    if (threadIdx.x != 0 || (d.done && *gp(d.done))) return;
+    const int p = DIM == 2 ? 4 : 13;
+    MG_GLOBAL T* u = gp((T*)d.u);
+    const MG_GLOBAL T* f = gp((const T*)d.f);
+    const T c = (T)d.c;
+    T diag;
+    if constexpr (VAR) {
+        const MG_GLOBAL T* k = gp((const T*)d.k);
+        const T kC = k[p];
+        const int sy = 3, sz = 9;
+        const T kxW = kface(k[p - 1], kC), kxC = kface(kC, k[p + 1]);
+        const T kyS = kface(k[p - sy], kC), kyC = kface(kC, k[p + sy]);
+        T dsum;
+        if (DIM == 2) {
+            dsum = (kxW + kxC) + (kyS + kyC);
+        } else {
+            const T kzB = kface(k[p - sz], kC), kzC = kface(kC, k[p + sz]);
+            dsum = ((kxW + kxC) + (kyS + kyC)) + (kzB + kzC);
+        }
+        diag = c * dsum;
+    } else {
+        diag = c * (DIM == 2 ? T(4) : T(6));
+    }
+    u[p] = f[p] / diag;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_copy_t_to_u(const GridDesc* __restrict__ descs, size_t total) {
+    const GridDesc d = descs[blockIdx.y];
+    if (d.done && *gp(d.done)) return;
+    MG_GLOBAL T* __restrict__ u = gp((T*)d.u);
+    const MG_GLOBAL T* __restrict__ t = gp((const T*)d.t);
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) u[q] = t[q];
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_zero_u(const GridDesc* __restrict__ descs, size_t total) {
+    const GridDesc d = descs[blockIdx.y];
+    if (d.done && *gp(d.done)) return;
+    MG_GLOBAL T* __restrict__ u = gp((T*)d.u);
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) u[q] = T(0);
+}
+
+__global__ __launch_bounds__(NT) void k_copy_bytes(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                   size_t n16) {
+    const size_t q = (size_t)blockIdx.x * NT + threadIdx.x;  // one 16-byte element per thread
+    if (q < n16) dst[q] = src[q];
+}
+
+}  // namespace
+
+int smooth_tiles(int dim, int sm, int n, TileCfg cfg) {
+    const int H = sm == SM_RBGS ? 2 : 1;
+    const int TX = BX - 2 * H, TY = cfg.by - 2 * H;
+    const int m = n - 2;
+    if (dim == 2) return cdiv(m, TX) * cdiv(m, TY);
+    return cdiv(m, TX) * cdiv(m, TY) * nzchunks(m, cfg.zchunk);
+}
+
+int restrict_tiles(int dim, int nf, TileCfg cfg) {
+    const int CX = (BX - 3) / 2, CY = (cfg.by - 3) / 2;
+    const int mc = (nf - 1) / 2 + 1 - 2;
+    if (dim == 2) return cdiv(mc, CX) * cdiv(mc, CY);
+    return cdiv(mc, CX) * cdiv(mc, CY) * nzchunks(mc, cfg.zchunk);
+}
+
+int norm_tiles(int dim, int n, TileCfg cfg) {
+    const int TX = BX - 2, TY = cfg.by - 2, m = n - 2;
+    if (dim == 2) return cdiv(m, TX) * cdiv(m, TY);
+    return cdiv(m, TX) * cdiv(m, TY) * nzchunks(m, cfg.zchunk);
+}
+
+template <typename T>
+hipError_t launch_restrict(int dim, bool var, const GridDesc* d, int ninst, int nf, int sel, TileCfg cfg,
+                           hipStream_t s) {
+    if (nf < 5 || ninst <= 0) return hipErrorInvalidValue;
+    const dim3 grid(restrict_tiles(dim, nf, cfg), ninst);
+    if (dim == 2) {
+        if (var) {
+            MG_BY_SWITCH(cfg.by, (k_restrict2d<T, true, BY><<<grid, NT, 0, s>>>(d, sel)))
+        } else {
+            MG_BY_SWITCH(cfg.by, (k_restrict2d<T, false, BY><<<grid, NT, 0, s>>>(d, sel)))
+        }
+    } else {
+        if (var) {
+            MG_BY_SWITCH(cfg.by, (k_restrict3d<T, true, BY><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
+        } else {
+            MG_BY_SWITCH(cfg.by, (k_restrict3d<T, false, BY><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
+        }
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(int dim, const GridDesc* d, int ninst, int nf, int sel, hipStream_t s) {
+    const size_t m = (size_t)(nf - 2);
+    const size_t total = dim == 2 ? m * m : m * m * m;
+    const int blocks = (int)std::min<size_t>((total + NT - 1) / NT, 4096);
+    const dim3 grid(blocks, ninst);
+    if (dim == 2) k_prolong<T, 2><<<grid, NT, 0, s>>>(d, sel);
+    else k_prolong<T, 3><<<grid, NT, 0, s>>>(d, sel);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarsest(int dim, bool var, const GridDesc* d, int ninst, hipStream_t s) {
+    if (dim == 2) {
+        if (var) k_coarsest<T, 2, true><<<ninst, 64, 0, s>>>(d);
+        else k_coarsest<T, 2, false><<<ninst, 64, 0, s>>>(d);
+    } else {
+        if (var) k_coarsest<T, 3, true><<<ninst, 64, 0, s>>>(d);
+        else k_coarsest<T, 3, false><<<ninst, 64, 0, s>>>(d);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy_t_to_u(int dim, const GridDesc* d, int ninst, int n, hipStream_t s) {
+    const size_t total = dim == 2 ? (size_t)n * n : (size_t)n * n * n;
+    const int blocks = (int)std::min<size_t>((total + NT - 1) / NT, 4096);
+    k_copy_t_to_u<T><<<dim3(blocks, ninst), NT, 0, s>>>(d, total);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zero_u(int dim, const GridDesc* d, int ninst, int n, hipStream_t s) {
+    const size_t total = dim == 2 ? (size_t)n * n : (size_t)n * n * n;
+    const int blocks = (int)std::min<size_t>((total + NT - 1) / NT, 4096);
+    k_zero_u<T><<<dim3(blocks, ninst), NT, 0, s>>>(d, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes % 16 != 0) return hipErrorInvalidValue;
+    const size_t n16 = bytes / 16;
+    const size_t blocks = (n16 + NT - 1) / NT;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (blocks) k_copy_bytes<<<(unsigned)blocks, NT, 0, s>>>((uint4*)dst, (const uint4*)src, n16);
+    return hipGetLastError();
+}
+
+#define MG_INST(T)                                                                                              \
+    template hipError_t launch_restrict<T>(int, bool, const GridDesc*, int, int, int, TileCfg, hipStream_t);    \
+    template hipError_t launch_prolong<T>(int, const GridDesc*, int, int, int, hipStream_t);                    \
+    template hipError_t launch_coarsest<T>(int, bool, const GridDesc*, int, hipStream_t);                       \
+    template hipError_t launch_copy_t_to_u<T>(int, const GridDesc*, int, int, hipStream_t);                     \
+    template hipError_t launch_zero_u<T>(int, const GridDesc*, int, int, hipStream_t);
+MG_INST(double)
+MG_INST(float)
+#undef MG_INST
+
+}  // namespace mg

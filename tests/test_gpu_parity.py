@@ -50,34 +50,35 @@ def case_arrays(dim, n, dt, varcoef, seed=0):
 
 
 SMOOTH_CASES = [
-    # dim, n, by, zchunk
-    (2, 5, 0, 0), (2, 9, 8, 0), (2, 33, 16, 0), (2, 129, 0, 0), (2, 257, 32, 0), (2, 65, 8, 0),
-    (3, 5, 0, 0), (3, 9, 8, 1), (3, 17, 16, 3), (3, 33, 0, 0), (3, 65, 32, 7), (3, 65, 8, 64),
+    # dim, n, by, zchunk, prefetch
+    (2, 5, 0, 0, 0), (2, 9, 8, 0, 0), (2, 33, 16, 0, 0), (2, 129, 0, 0, 0), (2, 257, 32, 0, 0), (2, 65, 8, 0, 0),
+    (3, 5, 0, 0, 1), (3, 9, 8, 1, 2), (3, 17, 16, 3, 1), (3, 33, 0, 0, 2), (3, 65, 32, 7, 2), (3, 65, 8, 64, 1),
+    (3, 129, 16, 128, 2), (3, 33, 32, 2, 1),
 ]
 
 
-@pytest.mark.parametrize("dim,n,by,zc", SMOOTH_CASES)
+@pytest.mark.parametrize("dim,n,by,zc,pd", SMOOTH_CASES)
 @pytest.mark.parametrize("smoother", [RB, JAC])
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 @pytest.mark.parametrize("varcoef", [False, True])
-def test_smooth_sweep_bitwise(dim, n, by, zc, smoother, dt, varcoef, dev_ok):
+def test_smooth_sweep_bitwise(dim, n, by, zc, pd, smoother, dt, varcoef, dev_ok):
     u, f, k = case_arrays(dim, n, dt, varcoef, seed=n)
     omega = 1.0 if smoother == RB else 0.8
     expect = oracle.smooth(u, f, smoother=smoother, omega=omega, k=k)
     ud, fd = dev(u), dev(f)
     out = dev(np.zeros_like(u))
     mg().mg_level_smooth(ud, fd, out, smoother=smoother, omega=omega, k=dev(k) if k is not None else None,
-                         by=by, zchunk=zc)
+                         by=by, zchunk=zc, prefetch=pd)
     assert same(host(out), expect)
 
 
-@pytest.mark.parametrize("dim,n,by,zc", [(2, 65, 16, 0), (3, 33, 16, 5), (3, 17, 8, 0)])
+@pytest.mark.parametrize("dim,n,by,zc,pd", [(2, 65, 16, 0, 0), (3, 33, 16, 5, 1), (3, 17, 8, 0, 2)])
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
-def test_smooth_zero_guess_bitwise(dim, n, by, zc, dt, dev_ok):
+def test_smooth_zero_guess_bitwise(dim, n, by, zc, pd, dt, dev_ok):
     _, f, _ = case_arrays(dim, n, dt, False, seed=3)
     expect = oracle.smooth(np.zeros_like(f), f)
     out = dev(np.zeros_like(f))
-    mg().mg_level_smooth(None, dev(f), out, zero_guess=True, by=by, zchunk=zc)
+    mg().mg_level_smooth(None, dev(f), out, zero_guess=True, by=by, zchunk=zc, prefetch=pd)
     assert same(host(out), expect)
 
 
@@ -264,3 +265,38 @@ def test_max_cycles_exhaustion_reports_not_converged(dev_ok):
     f = inputs.uniform_rhs(3, 33, 2)
     st, cyc, h, u = run_solve(3, 33, f, tol=1e-30, max_cycles=3)
     assert st == mg().MG_ENOTCONV and cyc == 3 and len(h) == 4
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_repeated_solves_on_one_context_are_identical(precision, dev_ok):
+    """A context is reusable: back-to-back solves (same or new buffers) give the oracle's answer each time."""
+    import torch
+
+    m = mg()
+    dim, n = 3, 33
+    f = inputs.uniform_rhs(dim, n, 51)
+    solve = oracle.solve if precision == 0 else oracle.solve_ir_f32
+    u_exp, h_exp, _ = solve(np.zeros_like(f), f, tol=1e-8, max_cycles=30)
+    s = m.Solver(m.Params(dim=dim, n=n, precision=precision))
+    fd = dev(f)
+    bufs = [torch.zeros(f.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    for u in [bufs[0], bufs[1], bufs[1], bufs[2], bufs[0]]:
+        u.zero_()
+        st, cyc, hist = s.solve(u, fd, tol=1e-8, max_cycles=30)
+        assert st == 0 and cyc == len(h_exp) - 1
+        np.testing.assert_allclose(hist, h_exp, rtol=1e-12, atol=0)
+        assert same(host(u), u_exp)
+    s.close()
+
+
+@pytest.mark.parametrize("dim,n,precision", [(3, 129, 1), (3, 65, 0), (2, 1025, 1)])
+def test_solve_independent_of_launch_geometry(dim, n, precision, dev_ok, monkeypatch):
+    """Autotuned tile shapes and the built-in heuristic give bit-identical solves."""
+    f = inputs.uniform_rhs(dim, n, 61)
+    monkeypatch.setenv("MG_AUTOTUNE", "0")
+    st0, c0, h0, u0 = run_solve(dim, n, f, precision=precision, tol=1e-8, max_cycles=30)
+    monkeypatch.setenv("MG_AUTOTUNE", "1")
+    st1, c1, h1, u1 = run_solve(dim, n, f, precision=precision, tol=1e-8, max_cycles=30)
+    assert st0 == st1 == 0 and c0 == c1
+    assert same(u0, u1)
+    np.testing.assert_allclose(h0, h1, rtol=1e-13, atol=0)
