@@ -129,15 +129,173 @@ def cpu_baseline(w, gpu_steps: int, budget_s: float):
     }
 
 
+def bench_batched(args, mg, torch):
+    """512 independent 2D Poisson grids, edges drawn from {65, ..., 1025}, each
+    solved to 1e-8 by FP32 V-cycles in FP64 refinement in one batched context;
+    compared with solving the same grids one after another in FP64."""
+    import numpy as np
+
+    import inputs
+
+    count = args.batch_count
+    edges, rhs = inputs.batch_problem(count=count, seed=3)
+    dof = sum((n - 2) ** 2 for n in edges)
+    dev = torch.device("cuda:0")
+    fs = [torch.from_numpy(f).to(dev) for f in rhs]
+    us = [torch.zeros_like(f) for f in fs]
+    del rhs
+    log(f"[bench] batched: {count} grids, {dof} DoF, edges {sorted(set(edges))}")
+    ctx = mg.mg_batch_setup([mg.Params(dim=2, n=n, precision=mg.PREC_FP32_IR) for n in edges])
+    for _ in range(args.warmup):
+        for u in us:
+            u.zero_()
+        mg.mg_batch_solve(ctx, us, fs, tol=1e-8, max_cycles=50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for u in us:
+            u.zero_()
+        st, cyc, stt = mg.mg_batch_solve(ctx, us, fs, tol=1e-8, max_cycles=50)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mg.mg_destroy(ctx)
+    t_batch = (t1 - t0) / args.steps
+    log(f"[bench] batched FP32-IR: {t_batch * 1e3:.2f} ms per batch, status {st}, cycles {min(cyc)}..{max(cyc)}")
+    # the same grids one at a time, plain FP64 (one context per size)
+    ctxs = {n: mg.Solver(mg.Params(dim=2, n=n, precision=mg.PREC_FP64)) for n in set(edges)}
+    for u in us:
+        u.zero_()
+    for i, n in enumerate(edges[:8]):
+        ctxs[n].solve(us[i], fs[i], tol=1e-8, max_cycles=50)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for i, n in enumerate(edges):
+        us[i].zero_()
+        ctxs[n].solve(us[i], fs[i], tol=1e-8, max_cycles=50)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for c in ctxs.values():
+        c.close()
+    t64 = tb - ta
+    log(f"[bench] sequential FP64: {t64 * 1e3:.2f} ms for {count} solves")
+    return {
+        "metric": "fine-grid DoF/s + HBM GB/s %peak; solves/s & p99 latency at 1e-8 residual",
+        "value": dof / t_batch,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched_2d_{count}", "grids": count, "dof": dof,
+                   "edges": "uniform from {65,129,257,513,1025}, seed 3", "tol": 1e-8,
+                   "solver": "batched FP32 V(2,2) RBGS in FP64 refinement, one launch per grid level"},
+        "extra": {"solves_per_s": count / t_batch, "fp64_sequential_solves_per_s": count / t64,
+                  "batched_over_fp64_sequential": t64 / t_batch,
+                  "cycles_min_max": [min(cyc), max(cyc)]},
+    }
+
+
+def bench_serving(args, mg, torch):
+    """Poisson arrival stream of mixed 2D/3D requests against the serving loop."""
+    import numpy as np
+
+    import inputs
+
+    sp = mg.ServerParams(hbm_budget_bytes=args.serve_budget_gib << 30, max_slots=args.serve_slots,
+                         max_n2d=2049, max_n3d=257, tol=1e-8, max_cycles=50)
+    ctx = mg.mg_server_create(sp)
+    # a pool of right-hand sides per size (requests of one size share a few seeds)
+    pool = {}
+
+    def rhs_for(req):
+        key = (req.dim, req.n, req.seed % 3)
+        if key not in pool:
+            pool[key] = inputs.uniform_rhs(req.dim, req.n, 5000 + req.seed % 3)
+        return pool[key]
+
+    def run(reqs, closed_loop=False):
+        lat, t_first, t_last = [], None, None
+        i = 0
+        start = time.perf_counter()
+        arrival_of = {}
+        while i < len(reqs) or arrival_of:
+            now = time.perf_counter() - start
+            while i < len(reqs) and (closed_loop or reqs[i].t_arrival <= now):
+                rid = mg.mg_server_submit(ctx, rhs_for(reqs[i]))
+                arrival_of[rid] = start + (0.0 if closed_loop else reqs[i].t_arrival)
+                i += 1
+            used, active, queued = mg.mg_server_info(ctx)
+            if active == 0 and queued == 0 and i < len(reqs):
+                time.sleep(max(0.0, reqs[i].t_arrival - (time.perf_counter() - start)))
+                continue
+            mg.mg_server_step(ctx)
+            for rid in mg.mg_server_poll(ctx):
+                st, _, cyc, rr, _ = mg.mg_server_fetch(ctx, rid)
+                tdone = time.perf_counter()
+                lat.append(tdone - arrival_of.pop(rid))
+                t_first = t_first or tdone
+                t_last = tdone
+        span = time.perf_counter() - start
+        return np.array(lat), span
+
+    # saturated throughput: everything submitted at once
+    sat_reqs = inputs.serving_requests(args.serve_requests, rate=1.0, seed=4)
+    _ = run(sat_reqs[: max(8, args.serve_requests // 8)], closed_loop=True)  # warm pools and tuner
+    lat, span = run(sat_reqs, closed_loop=True)
+    mu_sat = len(sat_reqs) / span
+    log(f"[bench] serving: saturated {mu_sat:.1f} solves/s ({len(sat_reqs)} requests in {span:.2f} s)")
+    sweep = []
+    for frac in (0.2, 0.4, 0.6, 0.8, 0.95):
+        reqs = inputs.serving_requests(args.serve_requests, rate=frac * mu_sat, seed=4)
+        lat, span = run(reqs)
+        rec = {"lambda_frac": frac, "lambda": frac * mu_sat, "solves_per_s": len(reqs) / span,
+               "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+        sweep.append(rec)
+        log(f"[bench] serving lambda={rec['lambda']:.1f}/s: {rec['solves_per_s']:.1f} solves/s, "
+            f"p50 {rec['p50_ms']:.2f} ms, p99 {rec['p99_ms']:.2f} ms")
+    mg.mg_destroy(ctx)
+    mean_dof = float(np.mean([(r.n - 2) ** r.dim for r in sat_reqs]))
+    return {
+        "metric": "fine-grid DoF/s + HBM GB/s %peak; solves/s & p99 latency at 1e-8 residual",
+        "value": mu_sat,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(sat_reqs),
+        "warmup": 1,
+        "ms_per_step": 1e3 / mu_sat,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "serving_mix", "requests_per_lambda": args.serve_requests,
+                   "mix": "60% 2D edges {257,513,1025,2049}, 40% 3D edges {33,65,129,257}",
+                   "arrivals": "exponential inter-arrival, seed 4", "tol": 1e-8,
+                   "budget_gib": args.serve_budget_gib, "slots_per_dim": args.serve_slots},
+        "extra": {"saturated_solves_per_s": mu_sat, "mean_dof_per_request": mean_dof,
+                  "saturated_dof_per_s": mu_sat * mean_dof, "lambda_sweep": sweep},
+    }
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="poisson3d_513_fp32ir", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="poisson3d_513_fp32ir",
+                    choices=sorted(WORKLOADS) + ["batched_2d", "serving_mix"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 context solve")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the baseline")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=int, default=48)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run the plain copy kernel over 1 GiB three times (counter calibration)")
     args = ap.parse_args(argv)
@@ -154,6 +312,12 @@ def main(argv=None) -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         return 2
+    if args.workload == "batched_2d":
+        print(json.dumps(bench_batched(args, mg, torch)), flush=True)
+        return 0
+    if args.workload == "serving_mix":
+        print(json.dumps(bench_serving(args, mg, torch)), flush=True)
+        return 0
     w = WORKLOADS[args.workload]
     dim, n = w["dim"], w["n"]
     dof = (n - 2) ** dim

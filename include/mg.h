@@ -159,6 +159,64 @@ int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, cons
                        double* u_out, float* r, double* norm_out, int by, int zchunk, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched solves: many independent grids (sizes may differ) in one context.
+ * Every instance is solved with FP32 V-cycles inside FP64 refinement; each V-cycle
+ * step is one launch per grid level shared by every instance that has that level,
+ * so instances of different sizes join the descending leg at their own finest
+ * level.  Each instance stops on its own residual test (a device-side flag);
+ * its result is bitwise identical to solving it alone with mg_solve.
+ * ------------------------------------------------------------------------- */
+
+/* count instances, each[i] their parameters: same dim, smoother, omega, nu1, nu2 for
+ * all; precision MG_PREC_FP32_IR; op MG_OP_LAPLACE (MG_ENOTSUP otherwise); n may differ.
+ * Allocates every instance's hierarchy.  Destroy with mg_destroy. */
+int mg_batch_setup(int count, const mg_params* each, void* stream, mg_ctx** out);
+
+/* u[i], f[i]: DEVICE pointers (host array of count pointers) of instance i, as in
+ * mg_solve.  cycles_done[i] / status[i] (HOST, may be NULL) receive each instance's
+ * refinement steps and status (MG_OK, MG_ENOTCONV, MG_EDIVERGED).  Returns the worst
+ * status.  Synchronises the stream. */
+int mg_batch_solve(mg_ctx* ctx, double* const* u, const double* const* f, double tol, int max_cycles,
+                   int* cycles_done, int* status);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.  Requests (2D or 3D grids
+ * of any accepted size) are queued; each mg_server_step admits queued requests
+ * in arrival order while a slot and the HBM budget allow (hierarchies are kept
+ * resident and reused from a per-size pool), then runs one refinement step
+ * (FP32 V-cycle + FP64 pass) of every admitted request in shared per-level
+ * launches, and completes the requests whose residual test passed.
+ * ------------------------------------------------------------------------- */
+
+typedef struct mg_server_params {
+    size_t hbm_budget_bytes; /* device bytes request hierarchies may hold (pool included) */
+    int max_slots;           /* concurrent requests per dimension */
+    int max_n2d, max_n3d;    /* largest accepted edges (2^L+1; 3D at most 1025) */
+    int smoother;            /* enum mg_smoother */
+    double omega;            /* <= 0: paper's value */
+    int nu1, nu2;            /* 0, 0 selects V(2,2) */
+    double tol;              /* relative residual reduction of every request */
+    int max_cycles;          /* refinement steps before a request completes unconverged */
+} mg_server_params;
+
+int mg_server_create(const mg_server_params* sp, void* stream, mg_ctx** out);
+/* Queue a request: dim 2/3, n = 2^L+1 (5 <= n <= max edge), f_host: HOST array of n^dim
+ * doubles (copied).  MG_ENOMEM if the request alone exceeds the budget. */
+int mg_server_submit(mg_ctx* ctx, int dim, int n, const double* f_host, long long* req_id);
+/* Admit, one refinement step of every active request, complete finished ones.
+ * Synchronises the stream.  n_active / n_queued (HOST, may be NULL) after the step. */
+int mg_server_step(mg_ctx* ctx, int* n_active, int* n_queued);
+/* Ids of requests completed since the last poll (up to cap) into done_ids (HOST). */
+int mg_server_poll(mg_ctx* ctx, long long* done_ids, int cap, int* ndone);
+/* Result of a completed request: u_host (n^dim doubles, may be NULL), refinement steps,
+ * final ||r||/||r0|| and seconds from submit to completion.  The request is released.
+ * Returns its status, or MG_EBUSY if it has not completed. */
+int mg_server_fetch(mg_ctx* ctx, long long req_id, double* u_host, int* cycles, double* final_rel_res,
+                    double* latency_s);
+/* Device bytes held (active + pooled hierarchies), active and queued requests. */
+int mg_server_info(mg_ctx* ctx, size_t* used_bytes, int* active, int* queued);
+
+/* ---------------------------------------------------------------------------
  * Measurement hooks.
  * ------------------------------------------------------------------------- */
 

@@ -49,6 +49,21 @@ class _Params(C.Structure):
     ]
 
 
+class _ServerParams(C.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", C.c_size_t),
+        ("max_slots", C.c_int),
+        ("max_n2d", C.c_int),
+        ("max_n3d", C.c_int),
+        ("smoother", C.c_int),
+        ("omega", C.c_double),
+        ("nu1", C.c_int),
+        ("nu2", C.c_int),
+        ("tol", C.c_double),
+        ("max_cycles", C.c_int),
+    ]
+
+
 _lib = None
 
 
@@ -77,6 +92,14 @@ def lib():
             "mg_prof_enable": (i, [p, i]),
             "mg_prof_read": (i, [p, C.POINTER(i), C.POINTER(d)]),
             "mg_copy_kernel": (i, [p, p, sz, p]),
+            "mg_batch_setup": (i, [i, p, p, C.POINTER(p)]),
+            "mg_batch_solve": (i, [p, p, p, d, i, p, p]),
+            "mg_server_create": (i, [C.POINTER(_ServerParams), p, C.POINTER(p)]),
+            "mg_server_submit": (i, [p, i, i, p, C.POINTER(C.c_longlong)]),
+            "mg_server_step": (i, [p, C.POINTER(i), C.POINTER(i)]),
+            "mg_server_poll": (i, [p, p, i, C.POINTER(i)]),
+            "mg_server_fetch": (i, [p, C.c_longlong, p, C.POINTER(i), C.POINTER(d), C.POINTER(d)]),
+            "mg_server_info": (i, [p, C.POINTER(sz), C.POINTER(i), C.POINTER(i)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -326,3 +349,94 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------- batches
+def mg_batch_setup(params_list, stream=None) -> int:
+    """One context for many instances (list of Params; FP32_IR, Laplacian)."""
+    arr = (_Params * len(params_list))(*[p.to_c() for p in params_list])
+    out = C.c_void_p()
+    _check(lib().mg_batch_setup(len(params_list), arr, _stream(stream), C.byref(out)), "mg_batch_setup")
+    return out.value
+
+
+def mg_batch_solve(ctx: int, us, fs, tol: float = 1e-8, max_cycles: int = 50):
+    """Solve every instance; returns (worst status, [cycles], [status])."""
+    import torch
+
+    n = len(us)
+    up = (C.c_void_p * n)(*[_dptr(u, torch.float64, name="u") for u in us])
+    fp = (C.c_void_p * n)(*[_dptr(f, torch.float64, name="f") for f in fs])
+    cyc = (C.c_int * n)()
+    stt = (C.c_int * n)()
+    st = lib().mg_batch_solve(ctx, up, fp, float(tol), int(max_cycles), cyc, stt)
+    _check(st, "mg_batch_solve", ok=(MG_OK, MG_ENOTCONV, MG_EDIVERGED))
+    return st, list(cyc), list(stt)
+
+
+# ----------------------------------------------------------------- serving
+@dataclass
+class ServerParams:
+    hbm_budget_bytes: int = 64 << 30
+    max_slots: int = 64
+    max_n2d: int = 2049
+    max_n3d: int = 257
+    smoother: int = SMOOTH_RBGS
+    omega: float = 0.0
+    nu1: int = 2
+    nu2: int = 2
+    tol: float = 1e-8
+    max_cycles: int = 50
+
+    def to_c(self):
+        return _ServerParams(self.hbm_budget_bytes, self.max_slots, self.max_n2d, self.max_n3d, self.smoother,
+                             self.omega, self.nu1, self.nu2, self.tol, self.max_cycles)
+
+
+def mg_server_create(sp: ServerParams, stream=None) -> int:
+    cp = sp.to_c()
+    out = C.c_void_p()
+    _check(lib().mg_server_create(C.byref(cp), _stream(stream), C.byref(out)), "mg_server_create")
+    return out.value
+
+
+def mg_server_submit(ctx: int, f_host) -> int:
+    """Queue a request; f_host is a C-contiguous float64 numpy array of shape (n,)*dim."""
+    import numpy as np
+
+    f = np.ascontiguousarray(f_host, dtype=np.float64)
+    rid = C.c_longlong(0)
+    _check(lib().mg_server_submit(ctx, f.ndim, f.shape[0], f.ctypes.data, C.byref(rid)), "mg_server_submit")
+    return rid.value
+
+
+def mg_server_step(ctx: int):
+    """Admit + one refinement step of every active request; returns (active, queued)."""
+    a, q = C.c_int(0), C.c_int(0)
+    _check(lib().mg_server_step(ctx, C.byref(a), C.byref(q)), "mg_server_step")
+    return a.value, q.value
+
+
+def mg_server_poll(ctx: int, cap: int = 4096):
+    ids = (C.c_longlong * cap)()
+    nd = C.c_int(0)
+    _check(lib().mg_server_poll(ctx, ids, cap, C.byref(nd)), "mg_server_poll")
+    return list(ids[: nd.value])
+
+
+def mg_server_fetch(ctx: int, req_id: int, shape=None):
+    """(status, u or None, cycles, final relative residual, latency seconds)."""
+    import numpy as np
+
+    u = np.empty(shape, dtype=np.float64) if shape is not None else None
+    cyc, rr, lat = C.c_int(0), C.c_double(0.0), C.c_double(0.0)
+    st = lib().mg_server_fetch(ctx, req_id, u.ctypes.data if u is not None else None, C.byref(cyc), C.byref(rr),
+                               C.byref(lat))
+    _check(st, "mg_server_fetch", ok=(MG_OK, MG_ENOTCONV, MG_EDIVERGED))
+    return st, u, cyc.value, rr.value, lat.value
+
+
+def mg_server_info(ctx: int):
+    used, a, q = C.c_size_t(0), C.c_int(0), C.c_int(0)
+    _check(lib().mg_server_info(ctx, C.byref(used), C.byref(a), C.byref(q)), "mg_server_info")
+    return used.value, a.value, q.value

@@ -1,0 +1,955 @@
+// Batched and served solves: many independent grids (of uneven sizes) share
+// every kernel launch.
+//
+// Each instance keeps a resident hierarchy: FP32 levels n = 2^a+1, ..., 3 for
+// the V-cycle on the correction equation, plus the FP64 partner array of the
+// refinement ping-pong.  Grids of different sizes meet on common absolute
+// levels (every grid with 2^a+1 >= n_level has a level of exactly that size),
+// so one launch per V-cycle step and absolute level covers every active
+// instance (blockIdx.y selects the instance), and the descending leg picks up
+// an instance at its own finest level.  The FP64 refinement pass runs once per
+// distinct finest size.  Each instance has its own device stop flag, step
+// counter and ping-pong parity: a converged instance's work is skipped inside
+// the kernels while the others continue, and per-instance arithmetic is
+// exactly that of a solve of the instance alone.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "mg_solver.h"
+
+namespace mg {
+namespace {
+
+double lvl_c(int n) {
+    const double h = 1.0 / (double)(n - 1);
+    return 1.0 / (h * h);
+}
+double lvl_wd(int dim, int n, double omega) {
+    const double h = 1.0 / (double)(n - 1);
+    return (omega * (h * h)) / (2.0 * (double)dim);
+}
+int log2edge(int n) {
+    int a = 0;
+    while ((1 << a) + 1 < n) ++a;
+    return a;
+}
+bool valid_edge(int n) { return n >= 3 && ((n - 1) & (n - 2)) == 0; }
+
+int st(hipError_t e) {
+    if (e == hipSuccess) return MG_OK;
+    return e == hipErrorOutOfMemory ? MG_ENOMEM : MG_EDEVICE;
+}
+#define BCK(x)                              \
+    do {                                    \
+        hipError_t e_ = (x);                \
+        if (e_ != hipSuccess) return st(e_); \
+    } while (0)
+
+// One resident hierarchy.
+struct Inst {
+    int dim = 0, n = 0, a = 0;  // finest edge n = 2^a + 1
+    int slot = -1;
+    std::vector<void*> e, t, r;  // FP32 levels, 0 = finest
+    double* u2 = nullptr;        // FP64 ping-pong partner of u
+    double* u64 = nullptr;       // owned FP64 iterate (served requests)
+    double* f64 = nullptr;       // owned FP64 rhs (served requests)
+    size_t bytes = 0;
+    double* u = nullptr;        // bound FP64 iterate
+    const double* f = nullptr;  // bound FP64 rhs
+};
+
+size_t inst_bytes(int dim, int n, bool own_io) {
+    size_t b = 0;
+    for (int m = n;; m = (m - 1) / 2 + 1) {
+        b += npts(dim, m) * 4 * (m > 3 ? 3 : 2);
+        if (m == 3) break;
+    }
+    b += npts(dim, n) * 8 * (own_io ? 3 : 1);
+    return b;
+}
+
+void free_inst(Inst& I) {
+    for (void* p : I.e) (void)hipFree(p);
+    for (void* p : I.t) (void)hipFree(p);
+    for (void* p : I.r) (void)hipFree(p);
+    if (I.u2) (void)hipFree(I.u2);
+    if (I.u64) (void)hipFree(I.u64);
+    if (I.f64) (void)hipFree(I.f64);
+    I.e.clear();
+    I.t.clear();
+    I.r.clear();
+    I.u2 = I.u64 = I.f64 = nullptr;
+}
+
+hipError_t zmalloc(void** p, size_t bytes, hipStream_t s) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    return hipMemsetAsync(*p, 0, bytes, s);
+}
+
+hipError_t alloc_inst(Inst& I, int dim, int n, bool own_io, hipStream_t s) {
+    I.dim = dim;
+    I.n = n;
+    I.a = log2edge(n);
+    I.bytes = inst_bytes(dim, n, own_io);
+    hipError_t e = hipSuccess;
+    for (int m = n;; m = (m - 1) / 2 + 1) {
+        const size_t b = npts(dim, m) * 4;
+        void *pe = nullptr, *pt = nullptr, *pr = nullptr;
+        e = zmalloc(&pe, b, s);
+        I.e.push_back(pe);
+        if (e != hipSuccess) break;
+        if (m > 3) {
+            e = zmalloc(&pt, b, s);
+            I.t.push_back(pt);
+            if (e != hipSuccess) break;
+        } else {
+            I.t.push_back(nullptr);
+        }
+        e = zmalloc(&pr, b, s);
+        I.r.push_back(pr);
+        if (e != hipSuccess) break;
+        if (m == 3) break;
+    }
+    const size_t N = npts(dim, n) * 8;
+    if (e == hipSuccess) e = zmalloc((void**)&I.u2, N, s);
+    if (e == hipSuccess && own_io) e = zmalloc((void**)&I.u64, N, s);
+    if (e == hipSuccess && own_io) e = zmalloc((void**)&I.f64, N, s);
+    if (e != hipSuccess) free_inst(I);
+    return e;
+}
+
+struct IRGroup {
+    int a, n, cnt;
+    IRDesc* d;
+};
+
+// Shared launch machinery for a set of instances of one dimension.
+struct Engine {
+    int dim = 2;
+    Problem prob{};
+    hipStream_t s = nullptr;
+    int cap = 0;        // instance slots
+    int max_a = 1;      // largest finest level accepted
+    std::vector<Tiles> tiles;  // by absolute level a (index a)
+    int pstride = 1;
+    int *d_done = nullptr, *d_steps = nullptr, *d_status = nullptr, *d_par = nullptr, *d_nparts = nullptr;
+    int* d_rows = nullptr;
+    int* d_newrows = nullptr;
+    double *d_norm = nullptr, *d_norm0 = nullptr, *d_partial = nullptr;
+    int* h_ctrl = nullptr;  // pinned: done, steps, status (3 * cap)
+    double* h_nrm = nullptr;  // pinned: norm, norm0 (2 * cap)
+    GridDesc* d_gd = nullptr;
+    size_t gd_cap = 0;
+    IRDesc* d_ir = nullptr;
+    size_t ir_cap = 0;
+    std::vector<GridDesc> h_gd;
+    std::vector<IRDesc> h_ir;
+    std::vector<Group> groups;  // finest-first over absolute levels
+    std::vector<Tiles> gtiles;  // tiles in group order
+    std::vector<IRGroup> irg;   // all members, by finest size
+    std::vector<IRGroup> irg_new;
+    std::vector<int> h_rows, h_newrows;
+    std::vector<Inst*> members;
+    std::vector<Inst*> fresh;  // members that still need their initial residual
+    hipGraphExec_t graph = nullptr;
+    int graph_k = 0;
+    double graph_tol = -1;
+    int graph_max = -1;
+    hipStream_t cap_stream = nullptr;
+
+    ~Engine() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (void* p : {(void*)d_done, (void*)d_steps, (void*)d_status, (void*)d_par, (void*)d_nparts,
+                        (void*)d_rows, (void*)d_newrows, (void*)d_norm, (void*)d_norm0, (void*)d_partial,
+                        (void*)d_gd, (void*)d_ir})
+            if (p) (void)hipFree(p);
+        if (h_ctrl) (void)hipHostFree(h_ctrl);
+        if (h_nrm) (void)hipHostFree(h_nrm);
+    }
+
+    int init(int dim_, const Problem& P, hipStream_t s_, int cap_, int max_n) {
+        dim = dim_;
+        prob = P;
+        s = s_;
+        cap = cap_;
+        max_a = log2edge(max_n);
+        tiles.resize((size_t)max_a + 1);
+        for (int a = 1; a <= max_a; ++a) tiles[(size_t)a] = default_tiles(dim, 4, (1 << a) + 1, P.smoother);
+        for (int a = 2; a <= max_a; ++a)
+            pstride = std::max(pstride, norm_tiles(dim, (1 << a) + 1, tiles[(size_t)a].norm));
+        const size_t ci = sizeof(int) * (size_t)cap;
+        BCK(hipMalloc((void**)&d_done, ci));
+        BCK(hipMalloc((void**)&d_steps, ci));
+        BCK(hipMalloc((void**)&d_status, ci));
+        BCK(hipMalloc((void**)&d_par, ci));
+        BCK(hipMalloc((void**)&d_nparts, ci));
+        BCK(hipMalloc((void**)&d_rows, ci));
+        BCK(hipMalloc((void**)&d_newrows, ci));
+        BCK(hipMalloc((void**)&d_norm, sizeof(double) * (size_t)cap));
+        BCK(hipMalloc((void**)&d_norm0, sizeof(double) * (size_t)cap));
+        BCK(hipMalloc((void**)&d_partial, sizeof(double) * (size_t)cap * (size_t)pstride));
+        BCK(hipHostMalloc((void**)&h_ctrl, 3 * ci, hipHostMallocDefault));
+        BCK(hipHostMalloc((void**)&h_nrm, 2 * sizeof(double) * (size_t)cap, hipHostMallocDefault));
+        BCK(launch_fill_int(d_done, 1, cap, s));  // empty slots are "done"
+        BCK(launch_fill_int(d_steps, 0, cap, s));
+        BCK(launch_fill_int(d_status, 0, cap, s));
+        BCK(launch_fill_int(d_par, 0, cap, s));
+        BCK(launch_fill_int(d_nparts, 0, cap, s));
+        return MG_OK;
+    }
+
+    GridDesc level_desc(const Inst& I, int a) const {
+        const int l = I.a - a;  // level index inside the instance
+        GridDesc d{};
+        const int n = (1 << a) + 1;
+        d.u = I.e[(size_t)l];
+        d.t = I.t[(size_t)l];
+        d.f = I.r[(size_t)l];
+        d.k = nullptr;
+        d.uc = a > 1 ? I.e[(size_t)l + 1] : nullptr;
+        d.fc = a > 1 ? I.r[(size_t)l + 1] : nullptr;
+        d.done = d_done + I.slot;
+        d.n = n;
+        d.inst = I.slot;
+        d.c = lvl_c(n);
+        d.wd = lvl_wd(dim, n, prob.omega);
+        d.omega = prob.omega;
+        return d;
+    }
+
+    IRDesc ir_desc(const Inst& I) const {
+        IRDesc d{};
+        d.u[0] = I.u;
+        d.u[1] = I.u2;
+        d.e = (const float*)I.e[0];
+        d.f = I.f;
+        d.k = nullptr;
+        d.r = (float*)I.r[0];
+        d.done = d_done + I.slot;
+        d.par = d_par + I.slot;
+        d.n = I.n;
+        d.inst = I.slot;
+        d.c = lvl_c(I.n);
+        return d;
+    }
+
+    // Rebuild every descriptor for the current members and upload them.
+    int rebuild() {
+        if (graph) {
+            (void)hipGraphExecDestroy(graph);
+            graph = nullptr;
+        }
+        std::sort(members.begin(), members.end(), [](const Inst* x, const Inst* y) { return x->slot < y->slot; });
+        groups.clear();
+        gtiles.clear();
+        irg.clear();
+        irg_new.clear();
+        h_gd.clear();
+        h_ir.clear();
+        if (members.empty()) return MG_OK;
+        int amax = 1;
+        for (const Inst* I : members) amax = std::max(amax, I->a);
+        std::vector<std::pair<size_t, size_t>> goff;  // (offset, count) into h_gd per absolute level
+        for (int a = amax; a >= 1; --a) {
+            const size_t off = h_gd.size();
+            for (const Inst* I : members)
+                if (I->a >= a) h_gd.push_back(level_desc(*I, a));
+            goff.push_back({off, h_gd.size() - off});
+        }
+        std::vector<std::pair<int, std::pair<size_t, size_t>>> ioff, inew;
+        for (int pass = 0; pass < 2; ++pass) {
+            const std::vector<Inst*>& list = pass == 0 ? members : fresh;
+            for (int a = amax; a >= 1; --a) {
+                const size_t off = h_ir.size();
+                for (const Inst* I : list)
+                    if (I->a == a) h_ir.push_back(ir_desc(*I));
+                if (h_ir.size() > off) (pass == 0 ? ioff : inew).push_back({a, {off, h_ir.size() - off}});
+            }
+        }
+        if (h_gd.size() > gd_cap || h_ir.size() > ir_cap) BCK(hipStreamSynchronize(s));  // old arrays may be in use
+        if (h_gd.size() > gd_cap) {
+            if (d_gd) (void)hipFree(d_gd);
+            gd_cap = std::max(h_gd.size(), 2 * gd_cap);
+            BCK(hipMalloc((void**)&d_gd, sizeof(GridDesc) * gd_cap));
+        }
+        if (h_ir.size() > ir_cap) {
+            if (d_ir) (void)hipFree(d_ir);
+            ir_cap = std::max(h_ir.size(), 2 * ir_cap);
+            BCK(hipMalloc((void**)&d_ir, sizeof(IRDesc) * ir_cap));
+        }
+        BCK(hipMemcpyAsync(d_gd, h_gd.data(), sizeof(GridDesc) * h_gd.size(), hipMemcpyHostToDevice, s));
+        BCK(hipMemcpyAsync(d_ir, h_ir.data(), sizeof(IRDesc) * h_ir.size(), hipMemcpyHostToDevice, s));
+        for (size_t g = 0; g < goff.size(); ++g) {
+            Group G;
+            G.n = (1 << (amax - (int)g)) + 1;
+            G.ninst = (int)goff[g].second;
+            G.d = d_gd + goff[g].first;
+            groups.push_back(G);
+            gtiles.push_back(tiles[(size_t)(amax - (int)g)]);
+        }
+        for (auto& x : ioff) irg.push_back({x.first, (1 << x.first) + 1, (int)x.second.second, d_ir + x.second.first});
+        for (auto& x : inew)
+            irg_new.push_back({x.first, (1 << x.first) + 1, (int)x.second.second, d_ir + x.second.first});
+        h_rows.clear();
+        for (const Inst* I : members) h_rows.push_back(I->slot);
+        h_newrows.clear();
+        for (const Inst* I : fresh) h_newrows.push_back(I->slot);
+        std::vector<int> np((size_t)cap, 0);
+        for (const Inst* I : members) np[(size_t)I->slot] = norm_tiles(dim, I->n, tiles[(size_t)I->a].norm);
+        BCK(hipMemcpyAsync(d_rows, h_rows.data(), sizeof(int) * h_rows.size(), hipMemcpyHostToDevice, s));
+        if (!h_newrows.empty())
+            BCK(hipMemcpyAsync(d_newrows, h_newrows.data(), sizeof(int) * h_newrows.size(), hipMemcpyHostToDevice,
+                               s));
+        BCK(hipMemcpyAsync(d_nparts, np.data(), sizeof(int) * np.size(), hipMemcpyHostToDevice, s));
+        BCK(hipStreamSynchronize(s));  // host vectors are reused by the next rebuild
+        return MG_OK;
+    }
+
+    // Initial residual (rho_0) of the fresh members; their stop flags open.
+    hipError_t start_fresh() {
+        if (fresh.empty()) return hipSuccess;
+        // open the stop flags of the fresh rows (every kernel honours them)
+        hipError_t e0 = launch_set_rows(d_done, 0, d_newrows, (int)h_newrows.size(), s);
+        if (e0 != hipSuccess) return e0;
+        // the iterate starts in u (parity 0), whatever a previous solve in this slot left
+        e0 = launch_set_rows(d_par, 0, d_newrows, (int)h_newrows.size(), s);
+        if (e0 != hipSuccess) return e0;
+        for (const IRGroup& g : irg_new) {
+            hipError_t e = launch_ir_update(dim, false, g.d, g.cnt, g.n, 0, IR_NO_UPDATE, d_partial, pstride,
+                                            tiles[(size_t)g.a].norm, s);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = launch_norm_finalize_rows(d_partial, pstride, d_nparts, d_newrows, (int)h_newrows.size(),
+                                                 d_norm, s);
+        if (e != hipSuccess) return e;
+        return launch_solve_init_rows(d_norm, d_norm0, d_done, d_steps, d_status, d_par, d_newrows,
+                                      (int)h_newrows.size(), s);
+    }
+
+    // One refinement step of every member: FP32 V-cycle from e = 0, FP64 pass, stop test.
+    hipError_t enqueue_step(double tol, int max_steps, hipStream_t q) {
+        if (members.empty()) return hipSuccess;
+        hipError_t e = vcycle<float>(prob, groups, true, gtiles, q, nullptr, nullptr, 0);
+        if (e != hipSuccess) return e;
+        for (const IRGroup& g : irg) {
+            e = launch_ir_update(dim, false, g.d, g.cnt, g.n, 0, 0, d_partial, pstride, tiles[(size_t)g.a].norm, q);
+            if (e != hipSuccess) return e;
+        }
+        e = launch_norm_finalize_rows(d_partial, pstride, d_nparts, d_rows, (int)h_rows.size(), d_norm, q);
+        if (e != hipSuccess) return e;
+        return launch_stop_test(d_norm, d_norm0, d_done, d_steps, d_status, nullptr, 0, tol, max_steps, cap, q,
+                                d_par);
+    }
+
+    int run_chunk(int K, double tol, int max_steps, bool use_graph) {
+        if (!use_graph) {
+            for (int i = 0; i < K; ++i) BCK(enqueue_step(tol, max_steps, s));
+            return MG_OK;
+        }
+        if (!graph || graph_k != K || graph_tol != tol || graph_max != max_steps) {
+            if (graph) {
+                (void)hipGraphExecDestroy(graph);
+                graph = nullptr;
+            }
+            if (!cap_stream) BCK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+            BCK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int i = 0; i < K && e == hipSuccess; ++i) e = enqueue_step(tol, max_steps, cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cap_stream, &g);
+            if (e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return st(e);
+            }
+            BCK(e2);
+            hipError_t e3 = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            BCK(e3);
+            graph_k = K;
+            graph_tol = tol;
+            graph_max = max_steps;
+        }
+        BCK(hipGraphLaunch(graph, s));
+        return MG_OK;
+    }
+
+    int read_ctrl(bool norms = false) {
+        BCK(hipMemcpyAsync(h_ctrl, d_done, sizeof(int) * (size_t)cap, hipMemcpyDeviceToHost, s));
+        BCK(hipMemcpyAsync(h_ctrl + cap, d_steps, sizeof(int) * (size_t)cap, hipMemcpyDeviceToHost, s));
+        BCK(hipMemcpyAsync(h_ctrl + 2 * cap, d_status, sizeof(int) * (size_t)cap, hipMemcpyDeviceToHost, s));
+        if (norms) {
+            BCK(hipMemcpyAsync(h_nrm, d_norm, sizeof(double) * (size_t)cap, hipMemcpyDeviceToHost, s));
+            BCK(hipMemcpyAsync(h_nrm + cap, d_norm0, sizeof(double) * (size_t)cap, hipMemcpyDeviceToHost, s));
+        }
+        BCK(hipStreamSynchronize(s));
+        return MG_OK;
+    }
+    int done(int slot) const { return h_ctrl[slot]; }
+    int steps(int slot) const { return h_ctrl[cap + slot]; }
+    int status(int slot) const { return h_ctrl[2 * cap + slot]; }
+
+    // After a finished solve: the iterate is in u2 when an odd number of update passes ran.
+    hipError_t copy_back(const Inst& I) {
+        if (steps(I.slot) & 1) return hipMemcpyAsync(I.u, I.u2, npts(dim, I.n) * 8, hipMemcpyDeviceToDevice, s);
+        return hipSuccess;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Static batch (mg_batch_*)
+// ---------------------------------------------------------------------------
+
+struct Batch {
+    int count = 0;
+    int dim = 2;
+    std::vector<Inst> inst;  // in caller order
+    std::unique_ptr<Engine> eng;
+    bool use_graphs = true;
+    ~Batch() {
+        if (eng && eng->s) (void)hipStreamSynchronize(eng->s);
+        eng.reset();
+        for (Inst& I : inst) free_inst(I);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Server (mg_server_*)
+// ---------------------------------------------------------------------------
+
+struct Request {
+    long long id = 0;
+    int dim = 2, n = 0;
+    double* f_pin = nullptr;   // pinned copy of the rhs (until uploaded)
+    std::vector<double> f_pageable;  // used instead when too many payloads are queued
+    double* u_pin = nullptr;   // pinned result (filled by an asynchronous copy)
+    hipEvent_t ev = nullptr;   // completes when u_pin holds the result
+    Inst* inst = nullptr;
+    int cycles = 0, status = 1;
+    double rel_res = 0.0;
+    bool complete = false;
+    std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
+};
+
+// Pinned host buffers by size (request payloads and results).
+struct PinnedPool {
+    std::map<size_t, std::vector<void*>> free;
+    void* get(size_t bytes) {
+        auto& v = free[bytes];
+        if (!v.empty()) {
+            void* p = v.back();
+            v.pop_back();
+            return p;
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        return p;
+    }
+    void put(void* p, size_t bytes) {
+        if (p) free[bytes].push_back(p);
+    }
+    ~PinnedPool() {
+        for (auto& kv : free)
+            for (void* p : kv.second) (void)hipHostFree(p);
+    }
+};
+
+struct Server {
+    mg_server_params sp{};
+    PinnedPool pinned;
+    size_t queued_pinned = 0;  // bytes of queued payloads held in pinned memory
+    static constexpr size_t kMaxQueuedPinned = size_t(4) << 30;
+    std::vector<Request*> copying;          // results on their way to the host
+    std::vector<std::pair<void*, size_t>> release_after_sync;  // uploaded payloads
+    hipStream_t s = nullptr;
+    std::unique_ptr<Engine> eng[2];  // 2D, 3D
+    std::deque<long long> queue;     // admission order
+    std::map<long long, std::unique_ptr<Request>> reqs;
+    std::map<std::pair<int, int>, std::vector<Inst*>> pool;  // (dim, n) -> free hierarchies
+    std::vector<char> slot_used[2];
+    std::vector<long long> completed;  // not yet returned by poll
+    size_t used_bytes = 0;             // held by active hierarchies and the pool
+    long long next_id = 1;
+    int active = 0;
+    double* h_norm = nullptr;
+
+    ~Server() {
+        if (s) (void)hipStreamSynchronize(s);
+        for (auto& kv : reqs) {
+            if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
+            if (kv.second->f_pin) pinned.put(kv.second->f_pin, npts(kv.second->dim, kv.second->n) * 8);
+            if (kv.second->u_pin) pinned.put(kv.second->u_pin, npts(kv.second->dim, kv.second->n) * 8);
+        }
+        for (auto& pr : release_after_sync) pinned.put(pr.first, pr.second);
+        for (int d = 0; d < 2; ++d) eng[d].reset();
+        for (auto& kv : pool)
+            for (Inst* I : kv.second) {
+                free_inst(*I);
+                delete I;
+            }
+        for (auto& kv : reqs)
+            if (kv.second->inst) {
+                free_inst(*kv.second->inst);
+                delete kv.second->inst;
+            }
+        if (h_norm) (void)hipHostFree(h_norm);
+    }
+};
+
+}  // namespace
+}  // namespace mg
+
+using namespace mg;
+
+// Batched / served contexts live behind the same opaque handle type.
+struct mg_batch_handle {
+    int kind;  // 1 batch, 2 server
+    mg::Batch* batch = nullptr;
+    mg::Server* server = nullptr;
+};
+
+namespace {
+
+mg_batch_handle* as_handle(mg_ctx* c) { return reinterpret_cast<mg_batch_handle*>(c); }
+
+// Handles of batches and servers are told apart from solver contexts by a registry.
+std::mutex g_reg_mu;
+std::vector<mg_batch_handle*> g_reg;
+
+bool registered(mg_ctx* c) {
+    std::lock_guard<std::mutex> g(g_reg_mu);
+    return std::find(g_reg.begin(), g_reg.end(), as_handle(c)) != g_reg.end();
+}
+
+void reg_add(mg_batch_handle* h) {
+    std::lock_guard<std::mutex> g(g_reg_mu);
+    g_reg.push_back(h);
+}
+
+void reg_remove(mg_batch_handle* h) {
+    std::lock_guard<std::mutex> g(g_reg_mu);
+    g_reg.erase(std::remove(g_reg.begin(), g_reg.end(), h), g_reg.end());
+}
+
+bool same_solver(const mg_params& a, const mg_params& b) {
+    return a.dim == b.dim && a.smoother == b.smoother && a.nu1 == b.nu1 && a.nu2 == b.nu2 && a.omega == b.omega &&
+           a.precision == b.precision && a.op == b.op && a.bc == b.bc;
+}
+
+int server_admit(Server& S);
+int server_retire(Server& S, int d);
+void server_collect(Server& S);
+
+}  // namespace
+
+namespace mg {
+bool is_batch_handle(const mg_ctx* c) { return registered(const_cast<mg_ctx*>(c)); }
+void destroy_batch_handle(mg_ctx* c) {
+    mg_batch_handle* h = as_handle(c);
+    reg_remove(h);
+    delete h->batch;
+    delete h->server;
+    delete h;
+}
+}  // namespace mg
+
+extern "C" {
+
+int mg_batch_setup(int count, const mg_params* each, void* stream, mg_ctx** out) {
+    if (!out) return MG_EINVAL;
+    *out = nullptr;
+    if (count <= 0 || !each) return MG_EINVAL;
+    const mg_params& p0 = each[0];
+    if (p0.dim != 2 && p0.dim != 3) return MG_EINVAL;
+    if (p0.precision != MG_PREC_FP32_IR || p0.op != MG_OP_LAPLACE || p0.bc != MG_BC_DIRICHLET_ZERO) return MG_ENOTSUP;
+    if (p0.smoother != MG_SMOOTH_RBGS && p0.smoother != MG_SMOOTH_WJACOBI) return MG_EINVAL;
+    if (p0.nu1 < 0 || p0.nu2 < 0 || p0.nu1 > 16 || p0.nu2 > 16) return MG_EINVAL;
+    int max_n = 3;
+    for (int i = 0; i < count; ++i) {
+        mg_params q = each[i];
+        if (q.omega <= 0.0) q.omega = p0.omega;
+        mg_params q0 = p0;
+        if (q0.omega <= 0.0) q0.omega = q.omega;
+        if (!same_solver(q, q0) || !valid_edge(q.n) || q.n < 5) return MG_EINVAL;
+        if (q.dim == 3 && q.n > 1025) return MG_EINVAL;
+        max_n = std::max(max_n, q.n);
+    }
+    double omega = p0.omega > 0.0 ? p0.omega : (p0.smoother == MG_SMOOTH_RBGS ? 1.0 : 0.8);
+    hipStream_t s = (hipStream_t)stream;
+    auto* B = new (std::nothrow) Batch();
+    if (!B) return MG_ENOMEM;
+    B->count = count;
+    B->dim = p0.dim;
+    B->use_graphs = std::getenv("MG_NO_GRAPHS") == nullptr;
+    B->inst.resize((size_t)count);
+    B->eng.reset(new Engine());
+    Problem P{p0.dim, p0.smoother, p0.nu1, p0.nu2, omega, false};
+    int r = B->eng->init(p0.dim, P, s, count, max_n);
+    for (int i = 0; r == MG_OK && i < count; ++i) {
+        r = st(alloc_inst(B->inst[(size_t)i], p0.dim, each[i].n, false, s));
+        B->inst[(size_t)i].slot = i;
+    }
+    if (r != MG_OK) {
+        delete B;
+        return r;
+    }
+    for (Inst& I : B->inst) B->eng->members.push_back(&I);
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        delete B;
+        return MG_EDEVICE;
+    }
+    auto* h = new mg_batch_handle{1, B, nullptr};
+    reg_add(h);
+    *out = reinterpret_cast<mg_ctx*>(h);
+    return MG_OK;
+}
+
+int mg_batch_solve(mg_ctx* ctx, double* const* u, const double* const* f, double tol, int max_cycles,
+                   int* cycles_done, int* status) {
+    if (!ctx || !registered(ctx) || !u || !f || max_cycles < 0 || !(tol >= 0.0)) return MG_EINVAL;
+    mg_batch_handle* h = as_handle(ctx);
+    if (h->kind != 1) return MG_EINVAL;
+    Batch& B = *h->batch;
+    Engine& E = *B.eng;
+    for (int i = 0; i < B.count; ++i)
+        if (!u[i] || !f[i]) return MG_EINVAL;
+    bool changed = false;
+    for (int i = 0; i < B.count; ++i) {
+        Inst& I = B.inst[(size_t)i];
+        if (I.u != u[i] || I.f != f[i]) changed = true;
+        I.u = u[i];
+        I.f = f[i];
+    }
+    E.fresh = E.members;
+    if (changed || E.groups.empty() || E.h_newrows.size() != E.fresh.size()) {
+        int r = E.rebuild();
+        if (r != MG_OK) return r;
+    }
+    BCK(E.start_fresh());
+    int enq = 0;
+    const int K = 4;
+    int r = E.read_ctrl();
+    if (r != MG_OK) return r;
+    auto all_done = [&]() {
+        for (int i = 0; i < B.count; ++i)
+            if (!E.done(B.inst[(size_t)i].slot)) return false;
+        return true;
+    };
+    while (!all_done() && enq < max_cycles) {
+        r = E.run_chunk(K, tol, max_cycles, B.use_graphs);
+        if (r != MG_OK) return r;
+        enq += K;
+        r = E.read_ctrl();
+        if (r != MG_OK) return r;
+    }
+    int worst = MG_OK;
+    for (int i = 0; i < B.count; ++i) {
+        Inst& I = B.inst[(size_t)i];
+        BCK(E.copy_back(I));
+        const int stt = E.status(I.slot);
+        if (cycles_done) cycles_done[i] = E.steps(I.slot);
+        int code = stt == 0 ? MG_OK : (stt == -5 ? MG_EDIVERGED : MG_ENOTCONV);
+        if (status) status[i] = code;
+        if (code == MG_EDIVERGED) worst = MG_EDIVERGED;
+        else if (code == MG_ENOTCONV && worst == MG_OK) worst = MG_ENOTCONV;
+    }
+    BCK(hipStreamSynchronize(E.s));
+    return worst;
+}
+
+int mg_server_create(const mg_server_params* sp, void* stream, mg_ctx** out) {
+    if (!out) return MG_EINVAL;
+    *out = nullptr;
+    if (!sp || sp->max_slots <= 0 || sp->hbm_budget_bytes == 0 || !(sp->tol >= 0.0) || sp->max_cycles <= 0)
+        return MG_EINVAL;
+    if (sp->smoother != MG_SMOOTH_RBGS && sp->smoother != MG_SMOOTH_WJACOBI) return MG_EINVAL;
+    if (!valid_edge(sp->max_n2d) || !valid_edge(sp->max_n3d) || sp->max_n3d > 1025) return MG_EINVAL;
+    auto* S = new (std::nothrow) Server();
+    if (!S) return MG_ENOMEM;
+    S->sp = *sp;
+    if (S->sp.omega <= 0.0) S->sp.omega = sp->smoother == MG_SMOOTH_RBGS ? 1.0 : 0.8;
+    if (S->sp.nu1 == 0 && S->sp.nu2 == 0) S->sp.nu1 = S->sp.nu2 = 2;
+    S->s = (hipStream_t)stream;
+    int r = MG_OK;
+    for (int d = 0; d < 2 && r == MG_OK; ++d) {
+        S->eng[d].reset(new Engine());
+        Problem P{2 + d, S->sp.smoother, S->sp.nu1, S->sp.nu2, S->sp.omega, false};
+        r = S->eng[d]->init(2 + d, P, S->s, sp->max_slots, d == 0 ? sp->max_n2d : sp->max_n3d);
+        S->slot_used[d].assign((size_t)sp->max_slots, 0);
+    }
+    if (r == MG_OK && hipStreamSynchronize(S->s) != hipSuccess) r = MG_EDEVICE;
+    if (r != MG_OK) {
+        delete S;
+        return r;
+    }
+    auto* h = new mg_batch_handle{2, nullptr, S};
+    reg_add(h);
+    *out = reinterpret_cast<mg_ctx*>(h);
+    return MG_OK;
+}
+
+int mg_server_submit(mg_ctx* ctx, int dim, int n, const double* f_host, long long* req_id) {
+    if (!ctx || !registered(ctx) || !f_host || !req_id) return MG_EINVAL;
+    mg_batch_handle* h = as_handle(ctx);
+    if (h->kind != 2) return MG_EINVAL;
+    Server& S = *h->server;
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5) return MG_EINVAL;
+    if (n > (dim == 2 ? S.sp.max_n2d : S.sp.max_n3d)) return MG_EINVAL;
+    if (inst_bytes(dim, n, true) > S.sp.hbm_budget_bytes) return MG_ENOMEM;
+    auto R = std::make_unique<Request>();
+    R->id = S.next_id++;
+    R->dim = dim;
+    R->n = n;
+    const size_t bytes = npts(dim, n) * sizeof(double);
+    if (S.queued_pinned + bytes <= Server::kMaxQueuedPinned) R->f_pin = (double*)S.pinned.get(bytes);
+    if (R->f_pin) {
+        std::memcpy(R->f_pin, f_host, bytes);
+        S.queued_pinned += bytes;
+    } else {
+        R->f_pageable.assign(f_host, f_host + npts(dim, n));
+    }
+    R->t_submit = std::chrono::steady_clock::now();
+    *req_id = R->id;
+    S.queue.push_back(R->id);
+    S.reqs[R->id] = std::move(R);
+    return MG_OK;
+}
+
+int mg_server_step(mg_ctx* ctx, int* n_active, int* n_queued) {
+    if (!ctx || !registered(ctx)) return MG_EINVAL;
+    mg_batch_handle* h = as_handle(ctx);
+    if (h->kind != 2) return MG_EINVAL;
+    Server& S = *h->server;
+    int r = server_admit(S);
+    if (r != MG_OK) return r;
+    for (int d = 0; d < 2; ++d) {
+        Engine& E = *S.eng[d];
+        if (E.members.empty()) continue;
+        BCK(E.start_fresh());
+        E.fresh.clear();
+        BCK(E.enqueue_step(S.sp.tol, S.sp.max_cycles, S.s));
+    }
+    for (int d = 0; d < 2; ++d) {
+        r = server_retire(S, d);
+        if (r != MG_OK) return r;
+    }
+    server_collect(S);
+    if (n_active) *n_active = S.active;
+    if (n_queued) *n_queued = (int)S.queue.size();
+    return MG_OK;
+}
+
+int mg_server_poll(mg_ctx* ctx, long long* done_ids, int cap, int* ndone) {
+    if (!ctx || !registered(ctx) || !ndone || (cap > 0 && !done_ids)) return MG_EINVAL;
+    mg_batch_handle* h = as_handle(ctx);
+    if (h->kind != 2) return MG_EINVAL;
+    Server& S = *h->server;
+    server_collect(S);
+    const int k = std::min<int>(cap, (int)S.completed.size());
+    for (int i = 0; i < k; ++i) done_ids[i] = S.completed[(size_t)i];
+    S.completed.erase(S.completed.begin(), S.completed.begin() + k);
+    *ndone = k;
+    return MG_OK;
+}
+
+int mg_server_fetch(mg_ctx* ctx, long long req_id, double* u_host, int* cycles, double* final_rel_res,
+                    double* latency_s) {
+    if (!ctx || !registered(ctx)) return MG_EINVAL;
+    mg_batch_handle* h = as_handle(ctx);
+    if (h->kind != 2) return MG_EINVAL;
+    Server& S = *h->server;
+    auto it = S.reqs.find(req_id);
+    if (it == S.reqs.end()) return MG_EINVAL;
+    Request& R = *it->second;
+    if (!R.complete) return MG_EBUSY;
+    const size_t bytes = npts(R.dim, R.n) * sizeof(double);
+    if (u_host) std::memcpy(u_host, R.u_pin, bytes);
+    S.pinned.put(R.u_pin, bytes);
+    R.u_pin = nullptr;
+    if (R.ev) (void)hipEventDestroy(R.ev);
+    R.ev = nullptr;
+    if (cycles) *cycles = R.cycles;
+    if (final_rel_res) *final_rel_res = R.rel_res;
+    if (latency_s) *latency_s = std::chrono::duration<double>(R.t_done - R.t_submit).count();
+    const int stt = R.status;
+    S.reqs.erase(it);
+    return stt == 0 ? MG_OK : (stt == -5 ? MG_EDIVERGED : MG_ENOTCONV);
+}
+
+int mg_server_info(mg_ctx* ctx, size_t* used_bytes, int* active, int* queued) {
+    if (!ctx || !registered(ctx)) return MG_EINVAL;
+    mg_batch_handle* h = as_handle(ctx);
+    if (h->kind != 2) return MG_EINVAL;
+    Server& S = *h->server;
+    if (used_bytes) *used_bytes = S.used_bytes;
+    if (active) *active = S.active;
+    if (queued) *queued = (int)S.queue.size();
+    return MG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Admit queued requests in arrival order while a slot and the HBM budget
+// allow: take a hierarchy of the right size from the pool (or allocate one,
+// first releasing pooled hierarchies of other sizes if the budget requires),
+// upload f and point the request at it.  A request that does not fit now
+// stays first in the queue (no overtaking, so no starvation).
+int server_admit(Server& S) {
+    bool any[2] = {false, false};
+    while (!S.queue.empty()) {
+        Request& R = *S.reqs[S.queue.front()];
+        const int d = R.dim - 2;
+        Engine& E = *S.eng[d];
+        int slot = -1;
+        for (int i = 0; i < E.cap; ++i)
+            if (!S.slot_used[d][(size_t)i]) {
+                slot = i;
+                break;
+            }
+        if (slot < 0) break;
+        Inst* I = nullptr;
+        auto& freel = S.pool[{R.dim, R.n}];
+        if (!freel.empty()) {
+            I = freel.back();
+            freel.pop_back();
+        } else {
+            const size_t need = inst_bytes(R.dim, R.n, true);
+            // make room by releasing pooled hierarchies of other sizes
+            for (auto it = S.pool.begin(); S.used_bytes + need > S.sp.hbm_budget_bytes && it != S.pool.end(); ++it)
+                while (!it->second.empty() && S.used_bytes + need > S.sp.hbm_budget_bytes) {
+                    Inst* v = it->second.back();
+                    it->second.pop_back();
+                    S.used_bytes -= v->bytes;
+                    free_inst(*v);
+                    delete v;
+                }
+            if (S.used_bytes + need > S.sp.hbm_budget_bytes) break;  // wait for running requests to finish
+            I = new (std::nothrow) Inst();
+            if (!I) return MG_ENOMEM;
+            hipError_t e = alloc_inst(*I, R.dim, R.n, true, S.s);
+            if (e != hipSuccess) {
+                delete I;
+                if (e == hipErrorOutOfMemory) break;
+                return st(e);
+            }
+            S.used_bytes += I->bytes;
+        }
+        I->slot = slot;
+        I->u = I->u64;
+        I->f = I->f64;
+        const size_t N = npts(R.dim, R.n);
+        BCK(hipMemsetAsync(I->u64, 0, N * sizeof(double), S.s));
+        if (R.f_pin) {
+            BCK(hipMemcpyAsync(I->f64, R.f_pin, N * sizeof(double), hipMemcpyHostToDevice, S.s));
+            S.release_after_sync.push_back({R.f_pin, N * sizeof(double)});  // the copy is in flight
+            S.queued_pinned -= N * sizeof(double);
+            R.f_pin = nullptr;
+        } else {
+            BCK(hipMemcpy(I->f64, R.f_pageable.data(), N * sizeof(double), hipMemcpyHostToDevice));
+            std::vector<double>().swap(R.f_pageable);
+        }
+        S.slot_used[d][(size_t)slot] = 1;
+        R.inst = I;
+        R.t_admit = std::chrono::steady_clock::now();
+        E.members.push_back(I);
+        E.fresh.push_back(I);
+        any[d] = true;
+        ++S.active;
+        S.queue.pop_front();
+    }
+    for (int d = 0; d < 2; ++d)
+        if (any[d]) {
+            int r = S.eng[d]->rebuild();  // synchronises the stream: uploads are done
+            if (r != MG_OK) return r;
+        }
+    if (any[0] || any[1]) {
+        for (auto& pr : S.release_after_sync) S.pinned.put(pr.first, pr.second);
+        S.release_after_sync.clear();
+    }
+    return MG_OK;
+}
+
+// Complete the requests whose stop flag is set: copy u to the host, return
+// the hierarchy to the pool and free the slot.
+int server_retire(Server& S, int d) {
+    Engine& E = *S.eng[d];
+    if (E.members.empty()) return MG_OK;
+    int r = E.read_ctrl(true);
+    if (r != MG_OK) return r;
+    for (auto& pr : S.release_after_sync) S.pinned.put(pr.first, pr.second);  // stream is idle here
+    S.release_after_sync.clear();
+    std::vector<Inst*> keep;
+    std::vector<Request*> out;
+    for (Inst* I : E.members) {
+        if (!E.done(I->slot)) {
+            keep.push_back(I);
+            continue;
+        }
+        Request* R = nullptr;
+        for (auto& kv : S.reqs)
+            if (kv.second->inst == I) R = kv.second.get();
+        if (!R) return MG_EDEVICE;
+        const size_t bytes = npts(I->dim, I->n) * sizeof(double);
+        const double* src = (E.steps(I->slot) & 1) ? I->u2 : I->u64;
+        R->u_pin = (double*)S.pinned.get(bytes);
+        if (!R->u_pin) return MG_ENOMEM;
+        BCK(hipMemcpyAsync(R->u_pin, src, bytes, hipMemcpyDeviceToHost, S.s));
+        const double n0 = E.h_nrm[E.cap + I->slot];
+        R->rel_res = n0 > 0.0 ? E.h_nrm[I->slot] / n0 : 0.0;
+        R->cycles = E.steps(I->slot);
+        R->status = E.status(I->slot);
+        R->inst = nullptr;
+        S.slot_used[(size_t)d][(size_t)I->slot] = 0;
+        // the hierarchy may be reused at once: later work on it is ordered after the copy
+        S.pool[{I->dim, I->n}].push_back(I);
+        --S.active;
+        out.push_back(R);
+    }
+    if (!out.empty()) {
+        hipEvent_t ev = nullptr;
+        BCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        BCK(hipEventRecord(ev, S.s));
+        for (size_t i = 0; i < out.size(); ++i) {
+            if (i == 0) {
+                out[i]->ev = ev;
+            } else {
+                BCK(hipEventCreateWithFlags(&out[i]->ev, hipEventDisableTiming));
+                BCK(hipEventRecord(out[i]->ev, S.s));
+            }
+            S.copying.push_back(out[i]);
+        }
+        E.members = keep;
+        return E.rebuild();
+    }
+    return MG_OK;
+}
+
+// Requests whose result copy has landed become complete.
+void server_collect(Server& S) {
+    std::vector<Request*> still;
+    for (Request* R : S.copying) {
+        if (hipEventQuery(R->ev) == hipSuccess) {
+            R->complete = true;
+            R->t_done = std::chrono::steady_clock::now();
+            S.completed.push_back(R->id);
+        } else {
+            still.push_back(R);
+        }
+    }
+    S.copying.swap(still);
+}
+
+}  // namespace

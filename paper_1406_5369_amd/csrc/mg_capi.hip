@@ -645,12 +645,16 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
     return MG_OK;
 }
 
-void mg_destroy(mg_ctx* c) { destroy(c); }
+void mg_destroy(mg_ctx* c) {
+    if (c && is_batch_handle(c)) destroy_batch_handle(c);
+    else destroy(c);
+}
 
-int mg_num_levels(const mg_ctx* c) { return c ? c->nlev : MG_EINVAL; }
+int mg_num_levels(const mg_ctx* c) { return c && !is_batch_handle(c) ? c->nlev : MG_EINVAL; }
 
 int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch) {
-    if (!c || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 2) return MG_EINVAL;
+    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 2)
+        return MG_EINVAL;
     const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
     TileCfg t = family == 0 ? tl[(size_t)level].smooth : (family == 1 ? tl[(size_t)level].restr : c->top.norm);
     if (family == 2 && level != 0) return MG_EINVAL;
@@ -662,6 +666,7 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
 
 int mg_vcycle(mg_ctx* c, double* u, const double* f) {
     if (!c) return MG_EINVAL;
+    if (is_batch_handle(c)) return MG_EINVAL;
     int r = bind(c, u, f);
     if (r != MG_OK) return r;
     CK(launch_fill_int(ctl_done(c), 0, 1, c->stream));
@@ -679,6 +684,7 @@ int mg_vcycle(mg_ctx* c, double* u, const double* f) {
 
 int mg_residual_norm(mg_ctx* c, const double* u, const double* f, double* out) {
     if (!c || !out) return MG_EINVAL;
+    if (is_batch_handle(c)) return MG_EINVAL;
     int r = bind(c, u, f);
     if (r != MG_OK) return r;
     CK(enqueue_norm(c, c->stream));
@@ -690,6 +696,7 @@ int mg_residual_norm(mg_ctx* c, const double* u, const double* f, double* out) {
 
 int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, int* cycles_done, double* res_hist) {
     if (!c || max_cycles < 0 || !(tol >= 0.0)) return MG_EINVAL;
+    if (is_batch_handle(c)) return MG_EINVAL;
     int r = bind(c, u, f);
     if (r != MG_OK) return r;
     r = ensure_hist(c, max_cycles + 1);
@@ -744,6 +751,7 @@ int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
 
 int mg_prof_enable(mg_ctx* c, int on) {
     if (!c) return MG_EINVAL;
+    if (is_batch_handle(c)) return MG_EINVAL;
     c->prof_on = on != 0;
     c->prof_n = 0;
     c->prof_launches = 0;
@@ -753,6 +761,7 @@ int mg_prof_enable(mg_ctx* c, int on) {
 
 int mg_prof_read(mg_ctx* c, int* launches, double* total_ms) {
     if (!c) return MG_EINVAL;
+    if (is_batch_handle(c)) return MG_EINVAL;
     CK(hipStreamSynchronize(c->stream));
     double ms = 0.0;
     for (int i = 0; i + 1 < c->prof_n; i += 2) {

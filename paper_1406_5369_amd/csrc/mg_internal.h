@@ -45,6 +45,7 @@ struct IRDesc {
     const double* k;  // FP64 nodal coefficient or null
     float* r;         // single-precision residual out (boundary left untouched, zero)
     const int* done;  // stop flag or null
+    const int* par;   // per-instance ping-pong parity (overrides 'sel') or null
     int n;
     int inst;
     double c;
@@ -108,7 +109,16 @@ hipError_t launch_norm_finalize(const double* partial, int pstride, int nparts, 
 hipError_t launch_solve_init(const double* norm, double* norm0, int* done, int* steps, int* status, double* hist,
                              int hstride, int ninst, hipStream_t s);
 hipError_t launch_stop_test(const double* norm, const double* norm0, int* done, int* steps, int* status, double* hist,
-                            int hstride, double tol, int max_steps, int ninst, hipStream_t s);
+                            int hstride, double tol, int max_steps, int ninst, hipStream_t s, int* par = nullptr);
+// Batched variants over an explicit list of instance rows.
+//   finalize_rows: norm[r] = sqrt(sum of partial[r*pstride + 0 .. nparts[r]-1]) for r in rows
+//   solve_init_rows: as launch_solve_init for the listed rows (par[r] = 0 when par is given)
+hipError_t launch_norm_finalize_rows(const double* partial, int pstride, const int* nparts, const int* rows, int nrows,
+                                     double* norm, hipStream_t s);
+// arr[rows[j]] = v for j < nrows.
+hipError_t launch_set_rows(int* arr, int v, const int* rows, int nrows, hipStream_t s);
+hipError_t launch_solve_init_rows(const double* norm, double* norm0, int* done, int* steps, int* status, int* par,
+                                  const int* rows, int nrows, hipStream_t s);
 
 // Coarse coefficient by injection: dst(I) = (TD) src(2I) over every coarse node,
 // nf = 2*nc - 1 nodes per axis on the fine side.

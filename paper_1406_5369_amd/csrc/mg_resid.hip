@@ -200,6 +200,7 @@ __device__ __forceinline__ void resid3d_body(const GridDesc* gd, const IRDesc* i
     int n, inst;
     if constexpr (IR) {
         const IRDesc d = *ird;
+        if (d.par) sel = *gp(d.par);
         n = d.n;
         inst = d.inst;
         s.uin = gp((const double*)(sel ? d.u[1] : d.u[0]));  // a select: indexing the copy would spill it
@@ -264,6 +265,7 @@ __global__ __launch_bounds__(NT) void k_ir2d(const IRDesc* __restrict__ descs, i
     const IRDesc d = descs[blockIdx.y];
     __shared__ double red4[4];
     if (d.done && *gp(d.done)) return;
+    if (d.par) sel = *gp(d.par);
     constexpr int TX = BX - 2, TY = BY - 2, RPT = BY / 4;
     const int n = d.n;
     const int ntx = (n - 2 + TX - 1) / TX;
@@ -330,6 +332,40 @@ __global__ __launch_bounds__(NT) void k_norm_finalize(const double* __restrict__
     if (threadIdx.x == 0) norm[row] = sqrt(t);
 }
 
+__global__ __launch_bounds__(NT) void k_norm_finalize_rows(const double* __restrict__ part, int pstride,
+                                                           const int* __restrict__ nparts,
+                                                           const int* __restrict__ rows, double* __restrict__ norm) {
+    __shared__ double red4[4];
+    const int row = rows[blockIdx.x];
+    const double* p = part + (size_t)row * pstride;
+    const int np = nparts[row];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += NT) s += p[i];
+    const double t = block_sum(s, red4);
+    if (threadIdx.x == 0) norm[row] = sqrt(t);
+}
+
+__global__ void k_set_rows(int* __restrict__ arr, int v, const int* __restrict__ rows, int nrows) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nrows) arr[rows[j]] = v;
+}
+
+__global__ void k_solve_init_rows(const double* __restrict__ norm, double* __restrict__ norm0, int* __restrict__ done,
+                                  int* __restrict__ steps, int* __restrict__ status, int* __restrict__ par,
+                                  const int* __restrict__ rows, int nrows) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nrows) return;
+    const int i = rows[j];
+    const double r = norm[i];
+    norm0[i] = r;
+    steps[i] = 0;
+    if (par) par[i] = 0;
+    const bool zero = r == 0.0;
+    const bool bad = !(r == r) || r > 1e300;
+    status[i] = bad ? -5 : (zero ? 0 : 1);
+    done[i] = (zero || bad) ? 1 : 0;
+}
+
 // Start of a solve: norm0 = norm, hist[0] = norm, steps = 0, and a zero
 // initial residual is already converged.
 __global__ void k_solve_init(const double* __restrict__ norm, double* __restrict__ norm0, int* __restrict__ done,
@@ -352,12 +388,13 @@ __global__ void k_solve_init(const double* __restrict__ norm, double* __restrict
 // out of cycles.  status: 1 running, 0 converged, 2 not converged, -5 diverged.
 __global__ void k_stop_test(const double* __restrict__ norm, const double* __restrict__ norm0, int* __restrict__ done,
                             int* __restrict__ steps, int* __restrict__ status, double* __restrict__ hist, int hstride,
-                            double tol, int max_steps, int ninst) {
+                            double tol, int max_steps, int ninst, int* __restrict__ par) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ninst || done[i]) return;
     const double r = norm[i], r0 = norm0[i];
     const int s = steps[i] + 1;
     steps[i] = s;
+    if (par) par[i] ^= 1;  // the refinement pass of this step wrote the other buffer
     if (hist && s < hstride) hist[(size_t)i * hstride + s] = r;
     int st = 1;
     if (!(r == r) || r > 1e300) st = -5;
@@ -461,6 +498,26 @@ hipError_t launch_norm_finalize(const double* partial, int pstride, int nparts, 
     return hipGetLastError();
 }
 
+hipError_t launch_norm_finalize_rows(const double* partial, int pstride, const int* nparts, const int* rows, int nrows,
+                                     double* norm, hipStream_t s) {
+    if (nrows <= 0) return hipSuccess;
+    k_norm_finalize_rows<<<nrows, NT, 0, s>>>(partial, pstride, nparts, rows, norm);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_rows(int* arr, int v, const int* rows, int nrows, hipStream_t s) {
+    if (nrows <= 0) return hipSuccess;
+    k_set_rows<<<cdiv(nrows, 256), 256, 0, s>>>(arr, v, rows, nrows);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_init_rows(const double* norm, double* norm0, int* done, int* steps, int* status, int* par,
+                                  const int* rows, int nrows, hipStream_t s) {
+    if (nrows <= 0) return hipSuccess;
+    k_solve_init_rows<<<cdiv(nrows, 256), 256, 0, s>>>(norm, norm0, done, steps, status, par, rows, nrows);
+    return hipGetLastError();
+}
+
 hipError_t launch_solve_init(const double* norm, double* norm0, int* done, int* steps, int* status, double* hist,
                              int hstride, int ninst, hipStream_t s) {
     k_solve_init<<<cdiv(ninst, 256), 256, 0, s>>>(norm, norm0, done, steps, status, hist, hstride, ninst);
@@ -468,9 +525,9 @@ hipError_t launch_solve_init(const double* norm, double* norm0, int* done, int* 
 }
 
 hipError_t launch_stop_test(const double* norm, const double* norm0, int* done, int* steps, int* status, double* hist,
-                            int hstride, double tol, int max_steps, int ninst, hipStream_t s) {
+                            int hstride, double tol, int max_steps, int ninst, hipStream_t s, int* par) {
     k_stop_test<<<cdiv(ninst, 256), 256, 0, s>>>(norm, norm0, done, steps, status, hist, hstride, tol, max_steps,
-                                                  ninst);
+                                                  ninst, par);
     return hipGetLastError();
 }
 

@@ -9,6 +9,8 @@
 #include "../../include/mg.h"
 #include "mg_internal.h"
 
+struct mg_ctx;
+
 namespace mg {
 
 // Launch geometry of every kernel family of one hierarchy.
@@ -56,6 +58,10 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& groups, bool zero_
 
 size_t npts(int dim, int n);
 int count_levels(int n);
+
+// Batched / served contexts share the opaque mg_ctx handle type.
+bool is_batch_handle(const mg_ctx* c);
+void destroy_batch_handle(mg_ctx* c);
 
 }  // namespace mg
 

@@ -1,0 +1,131 @@
+"""Batched and served solves: every instance's answer is bit-identical to
+solving it alone (mg_solve, and the CPU oracle's FP32-in-FP64 refinement)."""
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def mg():
+    import paper_1406_5369_amd as m
+
+    return m
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def alone(dim, n, f):
+    m = mg()
+    s = m.Solver(m.Params(dim=dim, n=n, precision=m.PREC_FP32_IR))
+    u = dev(np.zeros_like(f))
+    st, cyc, hist = s.solve(u, dev(f), tol=1e-8, max_cycles=40)
+    import torch
+
+    torch.cuda.synchronize()
+    out = u.cpu().numpy()
+    s.close()
+    return st, cyc, out
+
+
+@pytest.mark.parametrize("dim,edges", [(2, [65, 129, 33, 257, 65, 9, 129, 513]), (3, [17, 33, 9, 65, 33])])
+def test_batch_matches_alone_and_oracle(dim, edges, dev_ok):
+    import torch
+
+    m = mg()
+    fs = [inputs.uniform_rhs(dim, n, 700 + i) for i, n in enumerate(edges)]
+    ctx = m.mg_batch_setup([m.Params(dim=dim, n=n, precision=m.PREC_FP32_IR) for n in edges])
+    us = [dev(np.zeros_like(f)) for f in fs]
+    st, cyc, stt = m.mg_batch_solve(ctx, us, [dev(f) for f in fs], tol=1e-8, max_cycles=40)
+    assert st == 0 and all(x == 0 for x in stt)
+    torch.cuda.synchronize()
+    for i, (n, f) in enumerate(zip(edges, fs)):
+        got = us[i].cpu().numpy()
+        u_ref, h_ref, _ = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-8, max_cycles=40)
+        assert cyc[i] == len(h_ref) - 1
+        assert np.array_equal(got, u_ref)
+        st1, c1, u1 = alone(dim, n, f)
+        assert c1 == cyc[i] and np.array_equal(u1, got)
+    # a second solve on the same context (same buffers, reset) repeats the answer
+    for u in us:
+        u.zero_()
+    st2, cyc2, _ = m.mg_batch_solve(ctx, us, [dev(f) for f in fs], tol=1e-8, max_cycles=40)
+    assert cyc2 == cyc
+    m.mg_destroy(ctx)
+
+
+def test_batch_rejects_mixed_solver_settings(dev_ok):
+    m = mg()
+    with pytest.raises(m.MGError):
+        m.mg_batch_setup([m.Params(dim=2, n=65, precision=1), m.Params(dim=2, n=65, precision=1, nu1=1)])
+    with pytest.raises(m.MGError) as ei:
+        m.mg_batch_setup([m.Params(dim=2, n=65, precision=0)])
+    assert ei.value.code == m.MG_ENOTSUP
+
+
+def test_server_results_equal_alone_in_the_mix(dev_ok):
+    """Requests that arrive while others run are admitted as slots and budget free up;
+    each result equals the solve of that request alone."""
+    m = mg()
+    sp = m.ServerParams(hbm_budget_bytes=256 << 20, max_slots=3, max_n2d=257, max_n3d=33, tol=1e-8, max_cycles=40)
+    ctx = m.mg_server_create(sp)
+    reqs = [(2, 129, 1), (3, 33, 2), (2, 257, 3), (2, 65, 4), (3, 17, 5), (2, 129, 6), (2, 33, 7), (3, 33, 8),
+            (2, 257, 9), (2, 65, 10)]
+    f_of = {}
+    pending = list(reqs)
+    done = {}
+    steps = 0
+    # submit two at a time between steps: arrivals overlap running requests
+    while pending or len(done) < len(reqs):
+        for _ in range(2):
+            if pending:
+                dim, n, seed = pending.pop(0)
+                f = inputs.uniform_rhs(dim, n, 900 + seed)
+                rid = m.mg_server_submit(ctx, f)
+                f_of[rid] = (dim, n, f)
+        active, queued = m.mg_server_step(ctx)
+        assert active <= 2 * sp.max_slots
+        used, _, _ = m.mg_server_info(ctx)
+        assert used <= sp.hbm_budget_bytes
+        for rid in m.mg_server_poll(ctx):
+            dim, n, f = f_of[rid]
+            st, u, cyc, rr, lat = m.mg_server_fetch(ctx, rid, shape=f.shape)
+            done[rid] = (st, u, cyc, rr)
+        steps += 1
+        assert steps < 500
+    for rid, (st, u, cyc, rr) in done.items():
+        dim, n, f = f_of[rid]
+        assert st == 0 and rr <= 1e-8
+        u_ref, h_ref, _ = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-8, max_cycles=40)
+        assert cyc == len(h_ref) - 1
+        assert np.array_equal(u, u_ref)
+    m.mg_destroy(ctx)
+
+
+def test_server_budget_blocks_then_admits(dev_ok):
+    """A budget that fits one large request at a time serialises them without starving any."""
+    m = mg()
+    f = inputs.uniform_rhs(2, 513, 1)
+    need = 513 * 513 * (24 + 4 * 3 * 4 // 3) + (1 << 20)
+    sp = m.ServerParams(hbm_budget_bytes=need, max_slots=8, max_n2d=513, max_n3d=17, tol=1e-8, max_cycles=40)
+    ctx = m.mg_server_create(sp)
+    ids = [m.mg_server_submit(ctx, f) for _ in range(3)]
+    finished = []
+    for _ in range(200):
+        active, queued = m.mg_server_step(ctx)
+        assert active <= 1
+        finished += m.mg_server_poll(ctx)
+        if len(finished) == 3:
+            break
+    assert finished == ids  # arrival order, none overtaken
+    for rid in ids:
+        st, u, cyc, rr, lat = m.mg_server_fetch(ctx, rid)
+        assert st == 0
+    m.mg_destroy(ctx)
