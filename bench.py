@@ -18,7 +18,6 @@ timed region) and the CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -26,6 +25,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+from paper_1406_5369_amd.profsum import kernel_source_hash, sweep_blocks, sweep_kernel  # noqa: E402
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, datasheet
 
@@ -36,6 +37,8 @@ WORKLOADS = {
     "poisson2d_129_sine_fp64": dict(dim=2, n=129, precision=0, rhs=("sine",), tol=0.0, cycles=10),
     "poisson3d_257_fp32ir": dict(dim=3, n=257, precision=1, rhs=("uniform", 0), tol=1e-8),
     "poisson2d_4097_fp32ir": dict(dim=2, n=4097, precision=1, rhs=("uniform", 0), tol=1e-8),
+    # smooth log-normal coefficient in [1, 100] (seed 1), f ~ U[-1, 1] (seed 2)
+    "varcoef3d_257_fp32ir": dict(dim=3, n=257, precision=1, rhs=("uniform", 2), k=1, tol=1e-8),
 }
 
 
@@ -43,16 +46,10 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    """Hash of the device-code sources (kernels and their shared headers)."""
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1406_5369_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.startswith(("mg_smooth", "mg_resid", "mg_transfer", "mg_kern", "mg_internal")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode())
-                h.update(fh.read())
-    return h.hexdigest()[:16]
+def make_k(w):
+    import inputs
+
+    return inputs.varcoef_k(w["n"], w["k"], dim=w["dim"]) if "k" in w else None
 
 
 def make_rhs(w):
@@ -63,57 +60,56 @@ def make_rhs(w):
     return inputs.uniform_rhs(w["dim"], w["n"], w["rhs"][1])
 
 
-def traffic_record(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+def traffic_record(workload: str, tiles) -> dict | None:
+    """HBM bytes per launch of the dominant kernel (finest-level sweep with the
+    given tile geometry) from the committed rocprofv3 counter runs (FETCH_SIZE
+    and WRITE_SIZE, each calibrated on a 1 GiB copy), if they were taken on the
+    current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path))
+        with open(path) as fh:
+            rec = json.load(fh).get(workload)
     except (OSError, ValueError):
         return None
-    ent = rec.get(workload, {}).get(kernel)
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
-    return ent.get("bytes_per_launch")
+    return rec.get("configs", {}).get(",".join(str(int(t)) for t in tiles))
 
 
 def cpu_baseline(w, gpu_steps: int, budget_s: float):
     """Time the oracle (as it stands) on one refinement step / one V-cycle of
     the same workload on this host; scale to the solve's step count."""
-    import ctypes as C
-
     import numpy as np
 
     import oracle
 
-    lib = oracle._load()
     dim, n = w["dim"], w["n"]
     f = make_rhs(w)
+    k = make_k(w)
+    k32 = k.astype(np.float32) if k is not None else None
     u = np.zeros_like(f)
     threads = oracle.num_threads()
     t_steps = []
     t0 = time.perf_counter()
     if w["precision"] == 1:
         e = np.zeros(f.shape, np.float32)
-        r32 = np.zeros(f.shape, np.float32)
         while True:
             ts = time.perf_counter()
-            lib.orc_ir_update_f32(dim, n, None, u.ctypes.data, e.ctypes.data, f.ctypes.data, r32.ctypes.data)
-            e[...] = 0.0
-            lib.orc_vcycle_f32(dim, n, None, 0, 1.0, 2, 2, e.ctypes.data, r32.ctypes.data)
+            u, r32, _ = oracle.ir_update(u, e, f, k=k)
+            e = oracle.vcycle(np.zeros(f.shape, np.float32), r32, k=k32)
             t_steps.append(time.perf_counter() - ts)
-            if time.perf_counter() - t0 > budget_s or len(t_steps) >= 3:
+            if time.perf_counter() - t0 > budget_s or (len(t_steps) >= 3 and time.perf_counter() - t0 > 1.0):
                 break
         sample = "FP64 refinement pass + FP32 V(2,2) cycle"
     else:
         while True:
             ts = time.perf_counter()
-            lib.orc_vcycle_f64(dim, n, None, 0, 1.0, 2, 2, u.ctypes.data, f.ctypes.data)
-            lib.orc_residual_norm_f64(dim, n, None, u.ctypes.data, f.ctypes.data)
+            u = oracle.vcycle(u, f, k=k)
+            oracle.residual_norm(u, f, k=k)
             t_steps.append(time.perf_counter() - ts)
-            if time.perf_counter() - t0 > budget_s or len(t_steps) >= 3:
+            if time.perf_counter() - t0 > budget_s or (len(t_steps) >= 3 and time.perf_counter() - t0 > 1.0):
                 break
         sample = "FP64 V(2,2) cycle + residual norm"
     t_step = float(np.median(t_steps))
@@ -357,7 +353,10 @@ def main(argv=None) -> int:
     # solution buffers, zeroed before the timed region (u0 = 0 for every step)
     nbuf = args.steps + args.warmup
     us = [torch.zeros_like(f) for _ in range(min(nbuf, 4))]
-    params = mg.Params(dim=dim, n=n, precision=w["precision"])
+    k_host = make_k(w)
+    kd = torch.from_numpy(k_host).to(dev) if k_host is not None else None
+    op = mg.OP_VARCOEF_NODAL if kd is not None else mg.OP_LAPLACE
+    params = mg.Params(dim=dim, n=n, precision=w["precision"], op=op, k=kd)
     solver = mg.Solver(params)
     stream = torch.cuda.current_stream()
 
@@ -390,14 +389,18 @@ def main(argv=None) -> int:
     # dominant kernel: finest-level smoothing sweep (reads u and f, writes u: 3 words per inner node);
     # the zero-guess first sweep of each cycle is excluded from the event brackets.
     word = 4 if w["precision"] == 1 else 8
-    bytes_per_launch = 3 * word * dof
+    var = kd is not None
+    bytes_per_launch = (4 if var else 3) * word * dof  # u, f (and k) read, u written
     avg_ms = sweep_ms / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    kname = f"k_smooth3d<{'float' if word == 4 else 'double'},RBGS>" if dim == 3 else \
-        f"k_smooth2d<{'float' if word == 4 else 'double'},RBGS>"
+    by, zchunk, pd = mg.mg_tile_config(solver.ctx, 0, 0)
+    kname = sweep_kernel(dim, word, by, pd, var)
+    kblocks = sweep_blocks(dim, n, by, zchunk)
     roofline = {
         "bound": "hbm",
-        "kernel": kname + " (finest level, non-zero-guess sweeps)",
+        "kernel": kname,
+        "blocks": kblocks,
+        "note": "finest-level RBGS sweeps that read the previous iterate (the zero-guess first sweep excluded)",
         "launches": launches,
         "avg_launch_ms": avg_ms,
         "achieved": achieved,
@@ -406,15 +409,20 @@ def main(argv=None) -> int:
         "frac": achieved / HBM_PEAK_GBPS,
         "copy_ceiling": copy_gbps,
         "frac_of_copy_ceiling": achieved / copy_gbps,
-        "traffic": traffic_record(kname, args.workload),
+        "traffic": None,
     }
+
+    tr = traffic_record(args.workload, (by, zchunk, pd))
+    if tr and tr.get("kernel") == kname and tr.get("blocks") == kblocks:
+        roofline["traffic"] = tr["bytes_per_launch"]
+        roofline["traffic_ratio_to_algorithmic"] = tr["ratio_to_algorithmic"]
 
     extra = {"solves_per_s": args.steps / (t1 - t0), "cycles_per_solve": cycles[-1],
              "kernel_source_hash": kernel_source_hash(),
              "fine_tiles": {fam: mg.mg_tile_config(solver.ctx, 0, i) for i, fam in
                             enumerate(["smooth", "restrict", "norm_or_refinement"])}}
     if not args.no_fp64 and w["precision"] == 1:
-        s64 = mg.Solver(mg.Params(dim=dim, n=n, precision=mg.PREC_FP64))
+        s64 = mg.Solver(mg.Params(dim=dim, n=n, precision=mg.PREC_FP64, op=op, k=kd))
         u = us[0]
         u.zero_()
         s64.solve(u, f, tol=tol, max_cycles=max_cycles)  # warm

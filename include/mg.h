@@ -66,7 +66,8 @@ enum mg_precision {
 
 typedef struct mg_params {
     int dim;         /* 2 or 3 (unit square / unit cube, Table 1) */
-    int n;           /* nodes per axis incl. boundary, 2^L + 1, L >= 1 */
+    int n;           /* nodes per axis incl. boundary, 2^L + 1, L >= 1; at most 32769 in 2D
+                        and 1025 in 3D, so every node index fits in 32 bits */
     int op;          /* enum mg_operator */
     const double* k; /* MG_OP_VARCOEF_NODAL: device pointer to n^dim positive FP64 nodal
                         coefficients, copied during mg_setup; otherwise ignored */
@@ -191,7 +192,7 @@ int mg_batch_solve(mg_ctx* ctx, double* const* u, const double* const* f, double
 typedef struct mg_server_params {
     size_t hbm_budget_bytes; /* device bytes request hierarchies may hold (pool included) */
     int max_slots;           /* concurrent requests per dimension */
-    int max_n2d, max_n3d;    /* largest accepted edges (2^L+1; 3D at most 1025) */
+    int max_n2d, max_n3d;    /* largest accepted edges (2^L+1; at most 32769 / 1025) */
     int smoother;            /* enum mg_smoother */
     double omega;            /* <= 0: paper's value */
     int nu1, nu2;            /* 0, 0 selects V(2,2) */

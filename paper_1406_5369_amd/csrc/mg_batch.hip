@@ -22,6 +22,7 @@
 #include <new>
 #include <vector>
 
+#include "mg_sched.h"
 #include "mg_solver.h"
 
 namespace mg {
@@ -40,7 +41,6 @@ int log2edge(int n) {
     while ((1 << a) + 1 < n) ++a;
     return a;
 }
-bool valid_edge(int n) { return n >= 3 && ((n - 1) & (n - 2)) == 0; }
 
 int st(hipError_t e) {
     if (e == hipSuccess) return MG_OK;
@@ -465,6 +465,29 @@ struct PinnedPool {
     }
 };
 
+// Device side of the serving policy: request hierarchies (FP32 levels plus
+// owned FP64 u, f and the refinement partner).
+struct InstBackend {
+    hipStream_t s = nullptr;
+    size_t bytes(int dim, int n) const { return inst_bytes(dim, n, true); }
+    size_t bytes_of(const Inst* I) const { return I->bytes; }
+    int alloc(int dim, int n, Inst** out) {
+        Inst* I = new (std::nothrow) Inst();
+        if (!I) return MG_ENOMEM;
+        hipError_t e = alloc_inst(*I, dim, n, true, s);
+        if (e != hipSuccess) {
+            delete I;
+            return e == hipErrorOutOfMemory ? 1 : st(e);
+        }
+        *out = I;
+        return 0;
+    }
+    void release(Inst* I) {
+        free_inst(*I);
+        delete I;
+    }
+};
+
 struct Server {
     mg_server_params sp{};
     PinnedPool pinned;
@@ -474,14 +497,11 @@ struct Server {
     std::vector<std::pair<void*, size_t>> release_after_sync;  // uploaded payloads
     hipStream_t s = nullptr;
     std::unique_ptr<Engine> eng[2];  // 2D, 3D
-    std::deque<long long> queue;     // admission order
     std::map<long long, std::unique_ptr<Request>> reqs;
-    std::map<std::pair<int, int>, std::vector<Inst*>> pool;  // (dim, n) -> free hierarchies
-    std::vector<char> slot_used[2];
+    Sched<Inst*> sch;                  // queue, slots, pool and budget
+    InstBackend backend;
     std::vector<long long> completed;  // not yet returned by poll
-    size_t used_bytes = 0;             // held by active hierarchies and the pool
     long long next_id = 1;
-    int active = 0;
     double* h_norm = nullptr;
 
     ~Server() {
@@ -493,16 +513,9 @@ struct Server {
         }
         for (auto& pr : release_after_sync) pinned.put(pr.first, pr.second);
         for (int d = 0; d < 2; ++d) eng[d].reset();
-        for (auto& kv : pool)
-            for (Inst* I : kv.second) {
-                free_inst(*I);
-                delete I;
-            }
+        sch.drain_pool(backend);
         for (auto& kv : reqs)
-            if (kv.second->inst) {
-                free_inst(*kv.second->inst);
-                delete kv.second->inst;
-            }
+            if (kv.second->inst) backend.release(kv.second->inst);
         if (h_norm) (void)hipHostFree(h_norm);
     }
 };
@@ -581,8 +594,7 @@ int mg_batch_setup(int count, const mg_params* each, void* stream, mg_ctx** out)
         if (q.omega <= 0.0) q.omega = p0.omega;
         mg_params q0 = p0;
         if (q0.omega <= 0.0) q0.omega = q.omega;
-        if (!same_solver(q, q0) || !valid_edge(q.n) || q.n < 5) return MG_EINVAL;
-        if (q.dim == 3 && q.n > 1025) return MG_EINVAL;
+        if (!same_solver(q, q0) || !valid_edge(q.dim, q.n) || q.n < 5) return MG_EINVAL;
         max_n = std::max(max_n, q.n);
     }
     double omega = p0.omega > 0.0 ? p0.omega : (p0.smoother == MG_SMOOTH_RBGS ? 1.0 : 0.8);
@@ -674,19 +686,20 @@ int mg_server_create(const mg_server_params* sp, void* stream, mg_ctx** out) {
     if (!sp || sp->max_slots <= 0 || sp->hbm_budget_bytes == 0 || !(sp->tol >= 0.0) || sp->max_cycles <= 0)
         return MG_EINVAL;
     if (sp->smoother != MG_SMOOTH_RBGS && sp->smoother != MG_SMOOTH_WJACOBI) return MG_EINVAL;
-    if (!valid_edge(sp->max_n2d) || !valid_edge(sp->max_n3d) || sp->max_n3d > 1025) return MG_EINVAL;
+    if (!valid_edge(2, sp->max_n2d) || !valid_edge(3, sp->max_n3d)) return MG_EINVAL;
     auto* S = new (std::nothrow) Server();
     if (!S) return MG_ENOMEM;
     S->sp = *sp;
     if (S->sp.omega <= 0.0) S->sp.omega = sp->smoother == MG_SMOOTH_RBGS ? 1.0 : 0.8;
     if (S->sp.nu1 == 0 && S->sp.nu2 == 0) S->sp.nu1 = S->sp.nu2 = 2;
     S->s = (hipStream_t)stream;
+    S->backend.s = S->s;
+    S->sch.init(sp->hbm_budget_bytes, sp->max_slots);
     int r = MG_OK;
     for (int d = 0; d < 2 && r == MG_OK; ++d) {
         S->eng[d].reset(new Engine());
         Problem P{2 + d, S->sp.smoother, S->sp.nu1, S->sp.nu2, S->sp.omega, false};
         r = S->eng[d]->init(2 + d, P, S->s, sp->max_slots, d == 0 ? sp->max_n2d : sp->max_n3d);
-        S->slot_used[d].assign((size_t)sp->max_slots, 0);
     }
     if (r == MG_OK && hipStreamSynchronize(S->s) != hipSuccess) r = MG_EDEVICE;
     if (r != MG_OK) {
@@ -704,7 +717,7 @@ int mg_server_submit(mg_ctx* ctx, int dim, int n, const double* f_host, long lon
     mg_batch_handle* h = as_handle(ctx);
     if (h->kind != 2) return MG_EINVAL;
     Server& S = *h->server;
-    if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5) return MG_EINVAL;
+    if (!valid_edge(dim, n) || n < 5) return MG_EINVAL;
     if (n > (dim == 2 ? S.sp.max_n2d : S.sp.max_n3d)) return MG_EINVAL;
     if (inst_bytes(dim, n, true) > S.sp.hbm_budget_bytes) return MG_ENOMEM;
     auto R = std::make_unique<Request>();
@@ -721,7 +734,7 @@ int mg_server_submit(mg_ctx* ctx, int dim, int n, const double* f_host, long lon
     }
     R->t_submit = std::chrono::steady_clock::now();
     *req_id = R->id;
-    S.queue.push_back(R->id);
+    S.sch.submit(R->id);
     S.reqs[R->id] = std::move(R);
     return MG_OK;
 }
@@ -745,8 +758,8 @@ int mg_server_step(mg_ctx* ctx, int* n_active, int* n_queued) {
         if (r != MG_OK) return r;
     }
     server_collect(S);
-    if (n_active) *n_active = S.active;
-    if (n_queued) *n_queued = (int)S.queue.size();
+    if (n_active) *n_active = S.sch.active;
+    if (n_queued) *n_queued = (int)S.sch.queue.size();
     return MG_OK;
 }
 
@@ -792,9 +805,9 @@ int mg_server_info(mg_ctx* ctx, size_t* used_bytes, int* active, int* queued) {
     mg_batch_handle* h = as_handle(ctx);
     if (h->kind != 2) return MG_EINVAL;
     Server& S = *h->server;
-    if (used_bytes) *used_bytes = S.used_bytes;
-    if (active) *active = S.active;
-    if (queued) *queued = (int)S.queue.size();
+    if (used_bytes) *used_bytes = S.sch.used;
+    if (active) *active = S.sch.active;
+    if (queued) *queued = (int)S.sch.queue.size();
     return MG_OK;
 }
 
@@ -809,44 +822,15 @@ namespace {
 // stays first in the queue (no overtaking, so no starvation).
 int server_admit(Server& S) {
     bool any[2] = {false, false};
-    while (!S.queue.empty()) {
-        Request& R = *S.reqs[S.queue.front()];
+    while (!S.sch.queue.empty()) {
+        Request& R = *S.reqs[S.sch.queue.front()];
         const int d = R.dim - 2;
         Engine& E = *S.eng[d];
         int slot = -1;
-        for (int i = 0; i < E.cap; ++i)
-            if (!S.slot_used[d][(size_t)i]) {
-                slot = i;
-                break;
-            }
-        if (slot < 0) break;
         Inst* I = nullptr;
-        auto& freel = S.pool[{R.dim, R.n}];
-        if (!freel.empty()) {
-            I = freel.back();
-            freel.pop_back();
-        } else {
-            const size_t need = inst_bytes(R.dim, R.n, true);
-            // make room by releasing pooled hierarchies of other sizes
-            for (auto it = S.pool.begin(); S.used_bytes + need > S.sp.hbm_budget_bytes && it != S.pool.end(); ++it)
-                while (!it->second.empty() && S.used_bytes + need > S.sp.hbm_budget_bytes) {
-                    Inst* v = it->second.back();
-                    it->second.pop_back();
-                    S.used_bytes -= v->bytes;
-                    free_inst(*v);
-                    delete v;
-                }
-            if (S.used_bytes + need > S.sp.hbm_budget_bytes) break;  // wait for running requests to finish
-            I = new (std::nothrow) Inst();
-            if (!I) return MG_ENOMEM;
-            hipError_t e = alloc_inst(*I, R.dim, R.n, true, S.s);
-            if (e != hipSuccess) {
-                delete I;
-                if (e == hipErrorOutOfMemory) break;
-                return st(e);
-            }
-            S.used_bytes += I->bytes;
-        }
+        const int a = S.sch.admit_head(S.backend, R.dim, R.n, &slot, &I);
+        if (a < 0) return a;
+        if (a == 0) break;  // the head waits for a slot or for memory
         I->slot = slot;
         I->u = I->u64;
         I->f = I->f64;
@@ -861,14 +845,11 @@ int server_admit(Server& S) {
             BCK(hipMemcpy(I->f64, R.f_pageable.data(), N * sizeof(double), hipMemcpyHostToDevice));
             std::vector<double>().swap(R.f_pageable);
         }
-        S.slot_used[d][(size_t)slot] = 1;
         R.inst = I;
         R.t_admit = std::chrono::steady_clock::now();
         E.members.push_back(I);
         E.fresh.push_back(I);
         any[d] = true;
-        ++S.active;
-        S.queue.pop_front();
     }
     for (int d = 0; d < 2; ++d)
         if (any[d]) {
@@ -912,10 +893,8 @@ int server_retire(Server& S, int d) {
         R->cycles = E.steps(I->slot);
         R->status = E.status(I->slot);
         R->inst = nullptr;
-        S.slot_used[(size_t)d][(size_t)I->slot] = 0;
         // the hierarchy may be reused at once: later work on it is ordered after the copy
-        S.pool[{I->dim, I->n}].push_back(I);
-        --S.active;
+        S.sch.retire(I->dim, I->slot, I->n, I);
         out.push_back(R);
     }
     if (!out.empty()) {

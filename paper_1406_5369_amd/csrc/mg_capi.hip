@@ -14,8 +14,6 @@ using namespace mg;
 
 namespace {
 
-bool valid_edge(int n) { return n >= 3 && ((n - 1) & (n - 2)) == 0; }
-
 int dev_status(hipError_t e) {
     if (e == hipSuccess) return MG_OK;
     if (e == hipErrorOutOfMemory) return MG_ENOMEM;
@@ -148,7 +146,7 @@ void free_groups(std::vector<Group>& G) {
 int validate(const mg_params* p) {
     if (!p) return MG_EINVAL;
     if (p->dim != 2 && p->dim != 3) return MG_EINVAL;
-    if (!valid_edge(p->n)) return MG_EINVAL;
+    if (!valid_edge(p->dim, p->n)) return MG_EINVAL;
     if (p->bc != MG_BC_DIRICHLET_ZERO) return MG_ENOTSUP;
     if (p->op != MG_OP_LAPLACE && p->op != MG_OP_VARCOEF_NODAL) return MG_ENOTSUP;
     if (p->op == MG_OP_VARCOEF_NODAL && !p->k) return MG_EINVAL;
@@ -156,8 +154,6 @@ int validate(const mg_params* p) {
     if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 > 16 || p->nu2 > 16) return MG_EINVAL;
     if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_FP32_IR) return MG_ENOTSUP;
     if (!(p->omega == p->omega) || p->omega > 2.0) return MG_EINVAL;
-    if (p->dim == 3 && (size_t)p->n > 2049) return MG_EINVAL;
-    if ((size_t)p->n > 65537) return MG_EINVAL;
     return MG_OK;
 }
 
@@ -818,7 +814,7 @@ static int finish_desc(void* d, hipStream_t s, hipError_t launch) {
 int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const void* k, const void* u_in,
                     const void* f, void* u_out, const void* ec, int zero_guess, int by, int zchunk, int prefetch,
                     void* stream) {
-    if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
+    if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
     if ((smoother != 0 && smoother != 1) || !f || !u_out || (!u_in && !zero_guess)) return MG_EINVAL;
     if (ec && zero_guess) return MG_EINVAL;
     if (ec && dim == 3) return MG_ENOTSUP;  // 3D sweeps take the correction from mg_level_prolong_correct
@@ -847,7 +843,7 @@ int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const
 
 int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const void* u, const void* f, void* fc,
                                int by, int zchunk, void* stream) {
-    if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
+    if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
     if (!u || !f || !fc) return MG_EINVAL;
     const TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, n, 0, by, zchunk, 1);
     if (!valid_cfg(cfg)) return MG_EINVAL;
@@ -868,7 +864,7 @@ int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const v
 }
 
 int mg_level_prolong_correct(int dim, int n, int dtype, void* u, const void* ec, void* stream) {
-    if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
+    if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
     if (!u || !ec) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
@@ -901,7 +897,7 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
 
 int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
                        double* u_out, float* r, double* norm_out, int by, int zchunk, void* stream) {
-    if ((dim != 2 && dim != 3) || !valid_edge(n) || n < 5) return MG_EINVAL;
+    if (!valid_edge(dim, n) || n < 5) return MG_EINVAL;
     if (!u_in || !e || !f || !u_out || !r || !norm_out || u_in == u_out) return MG_EINVAL;
     const TileCfg cfg = pick_cfg(dim, 8, n, 0, by, zchunk, 2);
     if (!valid_cfg(cfg)) return MG_EINVAL;

@@ -9,6 +9,15 @@
 
 namespace mg {
 
+// Largest accepted grid edges: every node index of a grid (and of each level)
+// then fits in 32 bits (32769^2 and 1025^3 are both below 2^31).
+constexpr int kMaxEdge2D = 32769, kMaxEdge3D = 1025;
+
+// n = 2^L + 1 nodes per axis, L >= 1, within the size limit of its dimension.
+inline bool valid_edge(int dim, int n) {
+    return (dim == 2 || dim == 3) && n >= 3 && ((n - 1) & (n - 2)) == 0 && n <= (dim == 2 ? kMaxEdge2D : kMaxEdge3D);
+}
+
 enum Smoother { SM_RBGS = 0, SM_JACOBI = 1 };
 
 // Kernel flags for the smoothing sweep.

@@ -75,43 +75,59 @@ struct Resid3D {
     float en[3][RPT];
     double acc = 0.0;
 
-    __device__ __forceinline__ size_t at(int x, int y, int z) const { return ((size_t)z * n + y) * n + x; }
     __device__ __forceinline__ int gy(int m) const { return y0 - 1 + w + 4 * m; }
+
+    // per-thread clamped row offsets and row masks, computed once; planes are
+    // addressed through wave-uniform base pointers
+    unsigned roff[RPT];
+    unsigned mgrid, minner, mring;
+    size_t pl;
+
+    __device__ __forceinline__ void init_rows() {
+        pl = (size_t)n * n;
+        const int xc = min(max(gx, 0), n - 1);
+        mgrid = minner = mring = 0;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int y = gy(m), ly = w + 4 * m;
+            roff[m] = (unsigned)(min(max(y, 0), n - 1) * n + xc);
+            if (gx < n && y < n) mgrid |= 1u << m;
+            if (coli && y >= 1 && y <= n - 2) minner |= 1u << m;
+            if (lane1 && ly >= 1 && ly <= BY - 2) mring |= 1u << m;
+        }
+    }
 
     // unconditional loads from clamped addresses, values selected afterwards
     __device__ __forceinline__ void issue(int z, double (&du)[RPT], float (&de)[RPT], double (&dk)[RPT]) {
         const bool zok = z < n && z <= kend;
         const bool zin = z >= 1 && z <= n - 2;
-        const int zc = min(max(z, 0), n - 1), xc = min(max(gx, 0), n - 1);
+        const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
+        const MG_GLOBAL double* __restrict__ up = uin + zoff;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const int y = gy(m);
-            const bool ing = zok && gx < n && y < n;
-            const size_t p = at(xc, min(max(y, 0), n - 1), zc);
-            const double v = uin[p];
-            du[m] = ing ? v : 0.0;
+            const double v = up[roff[m]];
+            du[m] = (zok && ((mgrid >> m) & 1u)) ? v : 0.0;
             if constexpr (IR) {
                 if (!(flags & IR_NO_UPDATE)) {
-                    const float ev = e[p];
-                    de[m] = (zin && coli && y >= 1 && y <= n - 2) ? ev : 0.0f;
+                    const float ev = e[zoff + roff[m]];
+                    de[m] = (zin && ((minner >> m) & 1u)) ? ev : 0.0f;
                 } else {
                     de[m] = 0.0f;
                 }
             }
             if constexpr (VAR) {
-                const double kv = kf[p];
-                dk[m] = ing ? kv : 1.0;
+                const double kv = kf[zoff + roff[m]];
+                dk[m] = (zok && ((mgrid >> m) & 1u)) ? kv : 1.0;
             }
         }
     }
     __device__ __forceinline__ void issue_f(int z, double (&dst)[RPT]) {
         const bool zin = z >= 1 && z <= n - 2;
-        const int zc = min(max(z, 0), n - 1), xc = min(max(gx, 0), n - 1);
+        const MG_GLOBAL double* __restrict__ fp = f + (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const int y = gy(m), ly = w + 4 * m;
-            const double v = f[at(xc, min(max(y, 0), n - 1), zc)];
-            dst[m] = (zin && coli && y >= 1 && y <= n - 2 && lane1 && ly >= 1 && ly <= BY - 2) ? v : 0.0;
+            const double v = fp[roff[m]];
+            dst[m] = (zin && ((minner >> m) & (mring >> m) & 1u)) ? v : 0.0;
         }
     }
 
@@ -128,7 +144,7 @@ struct Resid3D {
                 const bool inn = zin && coli && y >= 1 && y <= n - 2;
                 if (inn && !(flags & IR_NO_UPDATE)) {
                     v = v + (double)en[S0][m];
-                    if (own && lane1 && ly >= 1 && ly <= BY - 2) uout[at(gx, y, kk)] = v;
+                    if (own && ((mring >> m) & 1u)) uout[(size_t)kk * pl + roff[m]] = v;
                 }
             }
             uo[S0][m] = v;
@@ -159,7 +175,7 @@ struct Resid3D {
                     kb = ko[S2][m];
                     ka = ko[S0][m];
                 }
-                if (lane1 && ly >= 1 && ly <= BY - 2 && gx <= n - 2 && y <= n - 2) {
+                if ((mring >> m) & (minner >> m) & 1u) {
                     if constexpr (VAR) {
                         kS = K[S1][ly - 1][lane];
                         kN = K[S1][ly + 1][lane];
@@ -168,7 +184,7 @@ struct Resid3D {
                     const double r = res3<double, VAR>(uc, uw, ue, U[S1][ly - 1][lane], U[S1][ly + 1][lane],
                                                        uo[S2][m], uo[S0][m], kc, kw, ke, kS, kN, kb, ka, fr[S1][m],
                                                        c, ds);
-                    if constexpr (IR) r32[at(gx, y, zz)] = (float)r;
+                    if constexpr (IR) r32[(size_t)zz * pl + roff[m]] = (float)r;
                     acc += r * r;
                 }
             }
@@ -176,6 +192,7 @@ struct Resid3D {
     }
 
     __device__ __forceinline__ void run() {
+        init_rows();
         int kk = kstart;
         issue(kk, un[0], en[0], kn[0]);
         if constexpr (PD == 2) issue(kk + 1, un[1], en[1], kn[1]);

@@ -45,42 +45,65 @@ struct Smooth3D {
     T ro[3][RPT];              // red-updated u of planes kk-1, kk-2, kk-3
     T fr[3][RPT];              // f of planes kk, kk-1, kk-2
 
-    __device__ __forceinline__ size_t at(int x, int y, int z) const {
-        return ((size_t)z * n + y) * n + x;
-    }
     __device__ __forceinline__ int gy(int m) const { return y0 - H + w + 4 * m; }
+
+    // Per-thread addressing, computed once: the clamped (always in-bounds)
+    // offset of each of the thread's rows inside a plane, and row masks.
+    // A plane is addressed by a wave-uniform base pointer, so every load and
+    // store is a scalar base plus a 32-bit per-lane offset.
+    unsigned roff[RPT];  // clamp(y)*n + clamp(x)
+    unsigned mgrid;      // bit m: row m inside the grid (x and y)
+    unsigned minner;     // bit m: row m an inner node (x and y)
+    unsigned mring;      // bit m: row m in the relaxed region of the first half-sweep
+    unsigned mtile;      // bit m: row m in the output tile (second half-sweep)
+    size_t pl;           // n*n
+
+    __device__ __forceinline__ void init_rows() {
+        pl = (size_t)n * n;
+        const int xc = min(max(gx, 0), n - 1);
+        mgrid = minner = mring = mtile = 0;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int y = gy(m), ly = w + 4 * m;
+            roff[m] = (unsigned)(min(max(y, 0), n - 1) * n + xc);
+            if (colg && y >= 0 && y < n) mgrid |= 1u << m;
+            if (coli && y >= 1 && y <= n - 2) minner |= 1u << m;
+            if (lane1 && ly >= 1 && ly <= BY - 2) mring |= 1u << m;
+            if (lane >= 2 && lane <= BX - 3 && ly >= 2 && ly <= BY - 3 && gx <= n - 2 && y <= n - 2)
+                mtile |= 1u << m;
+        }
+    }
 
     // Loads are unconditional from clamped (always in-bounds) addresses and
     // the value is selected afterwards: no branches around loads, so the
     // compiler can keep the prefetches in flight across steps.
     __device__ __forceinline__ void issue_u(int z, T (&du)[RPT], T (&dk)[RPT]) {
         const bool zok = z >= 0 && z < n && z <= kend;
-        const int zc = min(max(z, 0), n - 1), xc = min(max(gx, 0), n - 1);
+        const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
+        const MG_GLOBAL T* __restrict__ up = uin + zoff;
+        const MG_GLOBAL T* __restrict__ kp = kf + zoff;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const int y = gy(m);
-            const bool ing = zok && colg && y >= 0 && y < n;
-            const size_t p = at(xc, min(max(y, 0), n - 1), zc);
+            const bool ing = zok && ((mgrid >> m) & 1u);
             if constexpr (!(flags & SWEEP_ZERO_GUESS)) {
-                const T v = uin[p];
+                const T v = up[roff[m]];
                 du[m] = ing ? v : T(0);
             } else {
                 du[m] = T(0);
             }
             if constexpr (VAR) {
-                const T kv = kf[p];
+                const T kv = kp[roff[m]];
                 dk[m] = ing ? kv : T(1);
             }
         }
     }
     __device__ __forceinline__ void issue_f(int z, T (&dst)[RPT]) {
         const bool zin = z >= 1 && z <= n - 2;
-        const int zc = min(max(z, 0), n - 1), xc = min(max(gx, 0), n - 1);
+        const MG_GLOBAL T* __restrict__ fp = f + (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const int y = gy(m), ly = w + 4 * m;
-            const bool inn = zin && coli && y >= 1 && y <= n - 2 && lane1 && ly >= 1 && ly <= BY - 2;
-            const T v = f[at(xc, min(max(y, 0), n - 1), zc)];
+            const bool inn = zin && ((minner >> m) & 1u) && ((mring >> m) & 1u);
+            const T v = fp[roff[m]];
             dst[m] = inn ? v : T(0);
         }
     }
@@ -134,8 +157,7 @@ struct Smooth3D {
                         ka = ko[S0][m];
                     }
                     T v = uc;
-                    if (lane1 && ly >= 1 && ly <= BY - 2 && zin && coli && y >= 1 && y <= n - 2 &&
-                        ((gx + y + m1) & 1) == 0)
+                    if (zin && ((mring >> m) & (minner >> m) & 1u) && ((gx + y + m1) & 1) == 0)
                         v = relax_at(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, kc, kb, ka, kw, ke, S1,
                                          fr[S1][m]);
                     ro[S1][m] = v;
@@ -159,12 +181,12 @@ struct Smooth3D {
                         kb = kbelow[m];
                         ka = ko[S1][m];
                     }
-                    if (lane >= 2 && lane <= BX - 3 && ly >= 2 && ly <= BY - 3 && gx <= n - 2 && y <= n - 2) {
+                    if ((mtile >> m) & 1u) {
                         T v = rc;
                         if (((gx + y + m2) & 1) == 1)
                             v = relax_at(R[S2], rc, ro[P][m], ro[S1][m], rw, re, ly, kc, kb, ka, kw, ke, S2,
                                              fr[S2][m]);
-                        uout[at(gx, y, m2)] = v;
+                        uout[(size_t)m2 * pl + roff[m]] = v;
                     }
                 }
             }
@@ -188,9 +210,9 @@ struct Smooth3D {
                         kb = ko[S2][m];
                         ka = ko[S0][m];
                     }
-                    if (lane1 && ly >= 1 && ly <= BY - 2 && gx <= n - 2 && y <= n - 2)
-                        uout[at(gx, y, m1)] = relax_at(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, kc, kb, ka,
-                                                       kw, ke, S1, fr[S1][m]);
+                    if (((mring >> m) & (minner >> m) & 1u))
+                        uout[(size_t)m1 * pl + roff[m]] = relax_at(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, kc,
+                                                                   kb, ka, kw, ke, S1, fr[S1][m]);
                 }
             }
         }
@@ -202,6 +224,7 @@ struct Smooth3D {
     T kbelow[VAR ? RPT : 1];  // k of plane kk-3 for the black relaxation
 
     __device__ __forceinline__ void run() {
+        init_rows();
         int kk = kstart;
         issue_u(kk, un[0], kn[0]);
         if constexpr (PD == 2) issue_u(kk + 1, un[1], kn[1]);

@@ -192,21 +192,48 @@ __global__ __launch_bounds__(NT) void k_restrict3d(const GridDesc* __restrict__ 
 // post-smoothing sweep can absorb it), coarsest solve, copies.
 // ---------------------------------------------------------------------------
 
+// One wavefront per fine row (j, k); the parities of j and k are uniform per
+// wave, so only the x parity varies across lanes.  The sum is formed along x,
+// then y, then z, and scaled by 1/2 per odd axis, which is the order of the
+// bilinear / trilinear formulas (odd axes taken in x, y, z order).
 template <typename T, int DIM>
 __global__ __launch_bounds__(NT) void k_prolong(const GridDesc* __restrict__ descs, int sel) {
     const GridDesc d = descs[blockIdx.y];
     if (d.done && *gp(d.done)) return;
     const int n = d.n, nc = (n - 1) / 2 + 1, m = n - 2;
-    const size_t total = DIM == 2 ? (size_t)m * m : (size_t)m * m * m;
-    MG_GLOBAL T* __restrict__ u = gp((T*)(sel ? d.t : d.u));
+    const int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    const int nrows = DIM == 2 ? m : m * m;
+    if (row >= nrows) return;
+    const int j = 1 + row % m, k = DIM == 2 ? 0 : 1 + row / m;
+    const int oj = j & 1, ok = k & 1;
+    MG_GLOBAL T* __restrict__ u = gp((T*)(sel ? d.t : d.u)) + ((size_t)k * n + j) * n;
     const MG_GLOBAL T* __restrict__ ec = gp((const T*)d.uc);
-    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
-        const int i = 1 + (int)(q % m);
-        const size_t r = q / m;
-        const int j = 1 + (int)(r % m);
-        const int k = DIM == 2 ? 0 : 1 + (int)(r / m);
-        const size_t p = ((size_t)k * n + j) * n + i;
-        u[p] = u[p] + (DIM == 2 ? interp2<T>(ec, nc, i, j) : interp3<T>(ec, nc, i, j, k));
+    const MG_GLOBAL T* __restrict__ q00 = ec + ((size_t)(k >> 1) * nc + (j >> 1)) * nc;  // rows (J0, K0)
+    const MG_GLOBAL T* __restrict__ q10 = q00 + (size_t)oj * nc;                      // (J1, K0)
+    const MG_GLOBAL T* __restrict__ q01 = q00 + (size_t)ok * nc * nc;                 // (J0, K1)
+    const MG_GLOBAL T* __restrict__ q11 = q01 + (size_t)oj * nc;                      // (J1, K1)
+    const int lane = threadIdx.x & 63;
+    for (int i = 1 + lane; i <= m; i += 64) {
+        const int oi = i & 1, i0 = i >> 1, i1 = i0 + oi;
+        const T a0 = q00[i0], a1 = q00[i1];
+        T sy0 = oi ? a0 + a1 : a0;
+        if (oj) {
+            const T b0 = q10[i0], b1 = q10[i1];
+            sy0 = sy0 + (oi ? b0 + b1 : b0);
+        }
+        T s = sy0;
+        if (DIM == 3 && ok) {
+            const T c0 = q01[i0], c1 = q01[i1];
+            T sy1 = oi ? c0 + c1 : c0;
+            if (oj) {
+                const T d0 = q11[i0], d1 = q11[i1];
+                sy1 = sy1 + (oi ? d0 + d1 : d0);
+            }
+            s = s + sy1;
+        }
+        const int nodd = oi + oj + ok;
+        const T corr = nodd == 0 ? s : (nodd == 1 ? T(0.5) * s : (nodd == 2 ? T(0.25) * s : T(0.125) * s));
+        u[i] = u[i] + corr;
     }
 }
 
@@ -309,10 +336,9 @@ hipError_t launch_restrict(int dim, bool var, const GridDesc* d, int ninst, int 
 
 template <typename T>
 hipError_t launch_prolong(int dim, const GridDesc* d, int ninst, int nf, int sel, hipStream_t s) {
-    const size_t m = (size_t)(nf - 2);
-    const size_t total = dim == 2 ? m * m : m * m * m;
-    const int blocks = (int)std::min<size_t>((total + NT - 1) / NT, 4096);
-    const dim3 grid(blocks, ninst);
+    const int m = nf - 2;
+    const int rows = dim == 2 ? m : m * m;
+    const dim3 grid(cdiv(rows, NT / 64), ninst);
     if (dim == 2) k_prolong<T, 2><<<grid, NT, 0, s>>>(d, sel);
     else k_prolong<T, 3><<<grid, NT, 0, s>>>(d, sel);
     return hipGetLastError();

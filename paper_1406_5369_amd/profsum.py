@@ -2,22 +2,68 @@
 
     python -m paper_1406_5369_amd.profsum RESULTS.db [--top N] [--match SUBSTR]
     python -m paper_1406_5369_amd.profsum kernel_trace.csv
+    python -m paper_1406_5369_amd.profsum --counters PMC_RESULTS.db
+    python -m paper_1406_5369_amd.profsum --traffic FETCH.db WRITE.db --bench BENCH.json --out traffic.json
 
 Reads a rocprofv3 ``--kernel-trace`` result (the SQLite ``*_results.db`` that
 rocprofv3 writes by default, or a ``kernel_trace.csv``) and prints, for each
 (kernel, grid) pair, the number of dispatches and their total / average
 duration, so that launches of one kernel on different grid levels are told
-apart.  It reads only rocprofv3's output files.
+apart.  ``--counters`` prints per-dispatch averages of the counters of a
+``--pmc`` run.  ``--traffic`` turns one ``FETCH_SIZE`` run and one
+``WRITE_SIZE`` run of the benchmark (started with ``--calibrate-copy``, so
+that each run also holds three 1 GiB device copies) into HBM bytes per launch
+of the benchmark's dominant kernel: each counter is scaled by the factor that
+makes it read 1 GiB for the copy kernel, and the record is tagged with the
+hash of the device sources it was measured on.  It reads only rocprofv3's
+output files and the benchmark's JSON line.
 """
 
 from __future__ import annotations
 
 import argparse
 import csv
+import hashlib
+import json
+import os
 import re
 import sqlite3
 import sys
 from collections import defaultdict
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+COPY_BYTES = 1 << 30  # size of each calibration copy (bench.py --calibrate-copy)
+BX = 64               # tile width of the sweep kernels
+
+
+def kernel_source_hash() -> str:
+    """Hash of the device-code sources (kernels and their shared headers)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.startswith(("mg_smooth", "mg_resid", "mg_transfer", "mg_kern", "mg_internal")):
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def sweep_kernel(dim: int, word: int, by: int, pd: int, var: bool = False) -> str:
+    """Demangled name of a plain (not zero-guess, no fused correction) RBGS
+    sweep with the given tile height and prefetch depth."""
+    t = "float" if word == 4 else "double"
+    v = "true" if var else "false"
+    if dim == 2:
+        return f"mg::k_smooth2d<{t}, 0, {v}, {by}, 0>"
+    return f"mg::k_smooth3d<{t}, 0, {v}, {by}, {pd}, 0>"
+
+
+def sweep_blocks(dim: int, n: int, by: int, zchunk: int) -> int:
+    """Workgroups of one RBGS sweep over an n^dim node grid: tiles of
+    (BX - 4) x (by - 4) inner points (a two-point halo), times z-chunks in 3D."""
+    m = n - 2
+    cd = lambda a, b: -(-a // b)  # noqa: E731
+    b = cd(m, BX - 4) * cd(m, by - 4)
+    return b if dim == 2 else b * cd(m, zchunk)
 
 
 def short_name(name: str) -> str:
@@ -79,13 +125,102 @@ def counters(path: str, match: str | None = None):
     return out
 
 
+def _counter_rows(path: str, cname: str):
+    con = sqlite3.connect(path)
+    q = ("select kernel_name, grid_size_x, workgroup_size_x, value from counters_collection "
+         "where counter_name = ?")
+    per = defaultdict(list)
+    for name, gx, wx, val in con.execute(q, (cname,)):
+        per[(short_name(name), int(gx) // max(int(wx), 1))].append(float(val))
+    return per
+
+
+def _bench_line(path: str) -> dict:
+    with open(path) as fh:
+        lines = [ln for ln in fh if ln.lstrip().startswith("{")]
+    if not lines:
+        raise SystemExit(f"{path}: no JSON line")
+    return json.loads(lines[-1])
+
+
+def traffic(fetch_db: str, write_db: str, bench_json: str) -> dict:
+    """HBM bytes per launch of the benchmark's finest-level sweep, from one
+    FETCH_SIZE and one WRITE_SIZE run (KiB per dispatch), each calibrated on the
+    1 GiB copies of the same run.  The tile autotuner launches every candidate
+    geometry on the finest level during setup, so the record holds one entry per
+    geometry present in both runs, keyed "by,zchunk,prefetch"."""
+    b = _bench_line(bench_json)
+    cfg = b["config"]
+    dim, n = cfg["dim"], cfg["n"]
+    word = 4 if "f32" in b["dtype"] else 8
+    var = "varcoef" in cfg["workload"]
+    algo = (4 if var else 3) * word * (n - 2) ** dim
+    runs = {}
+    for db, cname in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
+        per = _counter_rows(db, cname)
+        copies = [v for (k, _), vals in per.items() if k == "mg::k_copy_bytes" for v in vals]
+        if not copies:
+            raise SystemExit(f"{db}: no k_copy_bytes dispatches (run the benchmark with --calibrate-copy)")
+        calib_kib = max(copies)
+        runs[cname] = (per, calib_kib, COPY_BYTES / (calib_kib * 1024.0))
+    configs = {}
+    for by in (8, 16, 32):
+        for pd in ((1, 2) if dim == 3 else (1,)):
+            for zc in ((4, 8, 16, 32, 64, 128, 256) if dim == 3 else (1,)):
+                kname = sweep_kernel(dim, word, by, pd, var)
+                blocks = sweep_blocks(dim, n, by, zc)
+                ent = {"kernel": kname, "blocks": blocks}
+                total = 0.0
+                for cname, (per, calib_kib, factor) in runs.items():
+                    vals = per.get((kname, blocks))
+                    if not vals:
+                        break
+                    avg = sum(vals) / len(vals)
+                    ent[cname] = {"kib_per_dispatch": avg, "dispatches": len(vals), "factor": factor}
+                    total += avg * 1024.0 * factor
+                else:
+                    ent["bytes_per_launch"] = total
+                    ent["ratio_to_algorithmic"] = total / algo
+                    configs[f"{by},{zc},{pd}"] = ent
+    if not configs:
+        raise SystemExit("no finest-level sweep dispatches found in both runs")
+    by, zc, pd = b["extra"]["fine_tiles"]["smooth"]
+    return {
+        "workload": cfg["workload"],
+        "source_hash": kernel_source_hash(),
+        "algorithmic_bytes": algo,
+        "calibration": {c: {"copy_kib_per_GiB": v[1], "factor": v[2]} for c, v in runs.items()},
+        "bench_tiles": f"{by},{zc},{pd}",
+        "configs": configs,
+    }
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("trace")
+    ap.add_argument("trace", nargs="+")
     ap.add_argument("--top", type=int, default=40)
     ap.add_argument("--match", default=None)
     ap.add_argument("--counters", action="store_true", help="per-dispatch counter averages (--pmc runs)")
+    ap.add_argument("--traffic", action="store_true", help="FETCH.db WRITE.db -> bytes per launch")
+    ap.add_argument("--bench", help="benchmark output (JSON line) of the counter runs")
+    ap.add_argument("--out", help="traffic JSON to update (one record per workload)")
     a = ap.parse_args(argv)
+    if a.traffic:
+        if len(a.trace) != 2 or not a.bench:
+            ap.error("--traffic needs FETCH.db WRITE.db and --bench")
+        rec = traffic(a.trace[0], a.trace[1], a.bench)
+        print(json.dumps(rec, indent=1))
+        if a.out:
+            allrec = {}
+            if os.path.exists(a.out):
+                with open(a.out) as fh:
+                    allrec = json.load(fh)
+            allrec[rec["workload"]] = rec
+            with open(a.out, "w") as fh:
+                json.dump(allrec, fh, indent=1, sort_keys=True)
+                fh.write("\n")
+        return 0
+    a.trace = a.trace[0]
     if a.counters:
         print(f"{'counter':>12} {'avg/dispatch':>16} {'n':>5} {'blocks':>7}  kernel")
         for d in counters(a.trace, a.match):
