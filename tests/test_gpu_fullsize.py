@@ -4,7 +4,7 @@ the degenerate and the largest accepted grids.
 
 * 513^3 Poisson, FP32 V(2,2) cycles in FP64 refinement to 1e-8: the whole
   solve is compared with the oracle's (history to 1e-12 per step, field bit for
-  bit).  The oracle needs about half a minute of host time for it.
+  bit).
 * 257^3 variable-coefficient problem (k in [1, 100]), same solver: same bar.
 * 512 batched 2D grids with edges 65..1025: a sample of instances (always
   including the largest ones) is compared with the oracle bit for bit; every
@@ -154,6 +154,10 @@ def test_largest_grids_converge(dim, n, dev_ok):
     print(f"[fullsize] largest grid: {cyc} steps; oracle residual", flush=True)
     r0 = oracle.residual_norm(np.zeros_like(f), f)
     r = oracle.residual_norm(uh, f)
-    assert r0 == pytest.approx(hist[0], rel=1e-12)
+    # The two sides sum ~1e9 squares in different orders: the oracle row by row
+    # (or plane by plane) then over rows, the GPU per tile then over tiles.  With
+    # at most ~6.6e4 sequential additions on either side the relative difference
+    # of the sums is bounded by ~6.6e4 * 2^-53 = 7e-12, halved by the square root.
+    assert r0 == pytest.approx(hist[0], rel=1e-10)
     assert r == pytest.approx(hist[-1], rel=1e-9)
     assert r <= 1e-8 * r0
