@@ -257,7 +257,7 @@ def mg_level_smooth(u_in, f, u_out, smoother=SMOOTH_RBGS, omega=0.0, k=None, ec=
     dt = f.dtype
     _check(lib().mg_level_smooth(dim, n, _dtype_code(f), smoother, float(omega), _dptr(k, dt, f.shape, "k"),
                                  _dptr(u_in, dt, f.shape, "u_in"), _dptr(f, dt, None, "f"),
-                                 _dptr(u_out, dt, f.shape, "u_out"), _dptr(ec, dt, None, "ec"), int(zero_guess),
+                                 _dptr(u_out, dt, f.shape, "u_out"), _dptr(ec, dt, ((n - 1) // 2 + 1,) * dim, "ec"), int(zero_guess),
                                  by, zchunk, prefetch, _stream(stream)), "mg_level_smooth")
 
 

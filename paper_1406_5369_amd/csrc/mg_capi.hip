@@ -314,10 +314,11 @@ std::map<TuneKey, TileCfg> g_tune;
 
 constexpr size_t kTuneMinPoints = 1u << 16;
 
-std::vector<TileCfg> tune_candidates(int dim, int planes, bool with_pd) {
+std::vector<TileCfg> tune_candidates(int dim, int planes, bool with_pd, int max_by) {
     std::vector<TileCfg> v;
     const int bys[3] = {8, 16, 32};
     for (int by : bys) {
+        if (by > max_by) continue;
         if (dim == 2) {
             v.push_back({by, 1, 1});
             continue;
@@ -425,7 +426,7 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
         TuneKey ks{dim, L.elem, n, 0, sm, var ? 1 : 0, 0};
         TileCfg cfg;
         if (!tune_lookup(ks, &cfg)) {
-            cfg = pick_fastest(tune_candidates(dim, n - 2, true), tl[(size_t)l].smooth, [&](TileCfg t) {
+            cfg = pick_fastest(tune_candidates(dim, n - 2, true, max_tile_rows(dim, L.elem, var, 0)), tl[(size_t)l].smooth, [&](TileCfg t) {
                 return L.elem == 8 ? launch_smooth<double>(dim, sm, var, d, 1, n, 0, 0, t, s)
                                    : launch_smooth<float>(dim, sm, var, d, 1, n, 0, 0, t, s);
             }, s);
@@ -435,7 +436,7 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
         TuneKey kr{dim, L.elem, n, 1, 0, var ? 1 : 0, 0};
         if (!tune_lookup(kr, &cfg)) {
             std::vector<TileCfg> cands;
-            for (TileCfg t : tune_candidates(dim, (n - 1) / 2 - 1, false))
+            for (TileCfg t : tune_candidates(dim, (n - 1) / 2 - 1, false, max_tile_rows(dim, L.elem, var, 1)))
                 if (t.by >= 8) cands.push_back(t);
             cfg = pick_fastest(cands, tl[(size_t)l].restr, [&](TileCfg t) {
                 return L.elem == 8 ? launch_restrict<double>(dim, var, d, 1, n, 0, t, s)
@@ -472,7 +473,7 @@ hipError_t autotune(mg_ctx* c) {
         TuneKey kn{dim, 8, n, 2, 0, var ? 1 : 0, mode};
         TileCfg cfg;
         if (!tune_lookup(kn, &cfg)) {
-            const std::vector<TileCfg> cands = tune_candidates(dim, n - 2, true);
+            const std::vector<TileCfg> cands = tune_candidates(dim, n - 2, true, max_tile_rows(dim, 8, var, 2));
             int maxparts = 1;
             for (TileCfg t : cands) maxparts = std::max(maxparts, norm_tiles(dim, n, t));
             double* part = nullptr;
@@ -793,8 +794,8 @@ static TileCfg pick_cfg(int dim, int elem, int n, int smoother, int by, int zchu
     return c;
 }
 
-static bool valid_cfg(TileCfg c) {
-    return (c.by == 8 || c.by == 16 || c.by == 32) && c.zchunk >= 1 && (c.pd == 1 || c.pd == 2);
+static bool valid_cfg(TileCfg c, int max_by) {
+    return (c.by == 8 || c.by == 16 || c.by == 32) && c.by <= max_by && c.zchunk >= 1 && (c.pd == 1 || c.pd == 2);
 }
 
 // Temporary device descriptor for a context-free call; the stream is synchronised before release.
@@ -817,10 +818,9 @@ int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const
     if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
     if ((smoother != 0 && smoother != 1) || !f || !u_out || (!u_in && !zero_guess)) return MG_EINVAL;
     if (ec && zero_guess) return MG_EINVAL;
-    if (ec && dim == 3) return MG_ENOTSUP;  // 3D sweeps take the correction from mg_level_prolong_correct
     TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, n, smoother, by, zchunk, 0);
     if (prefetch) cfg.pd = prefetch;
-    if (!valid_cfg(cfg) || (cfg.pd != 1 && cfg.pd != 2)) return MG_EINVAL;
+    if (!valid_cfg(cfg, max_tile_rows(dim, dtype == 0 ? 8 : 4, k != nullptr, 0))) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
     h.u = const_cast<void*>(u_in);
@@ -846,7 +846,7 @@ int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const v
     if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
     if (!u || !f || !fc) return MG_EINVAL;
     const TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, n, 0, by, zchunk, 1);
-    if (!valid_cfg(cfg)) return MG_EINVAL;
+    if (!valid_cfg(cfg, max_tile_rows(dim, dtype == 0 ? 8 : 4, k != nullptr, 1))) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
     h.u = const_cast<void*>(u);
@@ -900,7 +900,7 @@ int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, cons
     if (!valid_edge(dim, n) || n < 5) return MG_EINVAL;
     if (!u_in || !e || !f || !u_out || !r || !norm_out || u_in == u_out) return MG_EINVAL;
     const TileCfg cfg = pick_cfg(dim, 8, n, 0, by, zchunk, 2);
-    if (!valid_cfg(cfg)) return MG_EINVAL;
+    if (!valid_cfg(cfg, max_tile_rows(dim, 8, k != nullptr, 2))) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     IRDesc h{};
     h.u[0] = const_cast<double*>(u_in);

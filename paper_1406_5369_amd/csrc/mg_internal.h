@@ -18,6 +18,17 @@ inline bool valid_edge(int dim, int n) {
     return (dim == 2 || dim == 3) && n >= 3 && ((n - 1) & (n - 2)) == 0 && n <= (dim == 2 ? kMaxEdge2D : kMaxEdge3D);
 }
 
+// Largest tile height (rows of a 64-wide tile) of a kernel family: the 3D
+// marching kernels keep three planes of their rows in registers, and with
+// FP64 words or a coefficient field a 32-row tile would not fit the 256
+// architectural VGPRs.  family: 0 smoothing, 1 residual + restriction,
+// 2 FP64 norm / refinement pass.
+inline int max_tile_rows(int dim, int elem, bool var, int family) {
+    if (dim == 2 || family == 1) return 32;
+    if (family == 0) return (elem == 8 || var) ? 16 : 32;
+    return var ? 16 : 32;
+}
+
 enum Smoother { SM_RBGS = 0, SM_JACOBI = 1 };
 
 // Kernel flags for the smoothing sweep.

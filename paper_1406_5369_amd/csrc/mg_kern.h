@@ -49,6 +49,18 @@ __device__ __forceinline__ MG_GLOBAL T* gp(T* p) {
     return (MG_GLOBAL T*)p;
 }
 
+// Element at a 32-bit byte offset from a wave-uniform base: the base stays in
+// scalar registers and only the offset is per lane, so the access is a global
+// load / store with a scalar base address and no per-lane 64-bit address math.
+template <typename T>
+__device__ __forceinline__ T ld_off(const MG_GLOBAL T* base, unsigned boff) {
+    return *(const MG_GLOBAL T*)((const MG_GLOBAL char*)base + boff);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(MG_GLOBAL T* base, unsigned boff, T v) {
+    *(MG_GLOBAL T*)((MG_GLOBAL char*)base + boff) = v;
+}
+
 
 constexpr int BX = 64;   // LDS box width: one wavefront per row
 constexpr int NT = 256;  // threads per workgroup
@@ -234,6 +246,22 @@ inline int nzchunks(int m, int zchunk) { return cdiv(m, zchunk); }
         } break;               \
         case 32: {             \
             constexpr int BY = 32; \
+            CALL;              \
+        } break;               \
+        default:               \
+            return hipErrorInvalidValue; \
+    }
+
+// Tile heights 8 and 16 only (kernels whose 32-row variant would exceed the
+// architectural register file).
+#define MG_BY_SWITCH16(by, CALL) \
+    switch (by) {              \
+        case 8: {              \
+            constexpr int BY = 8; \
+            CALL;              \
+        } break;               \
+        case 16: {             \
+            constexpr int BY = 16; \
             CALL;              \
         } break;               \
         default:               \

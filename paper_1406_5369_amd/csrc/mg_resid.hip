@@ -463,9 +463,9 @@ hipError_t launch_norm(int dim, bool var, const GridDesc* d, int ninst, int n, i
     } else {
         if (var) {
             if (cfg.pd == 2) {
-                MG_BY_SWITCH(cfg.by, (k_norm3d<true, BY, 2><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+                MG_BY_SWITCH16(cfg.by, (k_norm3d<true, BY, 2><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
             } else {
-                MG_BY_SWITCH(cfg.by, (k_norm3d<true, BY, 1><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+                MG_BY_SWITCH16(cfg.by, (k_norm3d<true, BY, 1><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
             }
         } else {
             if (cfg.pd == 2) {
@@ -483,6 +483,12 @@ hipError_t launch_ir_fl(int dim, const IRDesc* d, int sel, double* partial, int 
                         hipStream_t s) {
     if (dim == 2) {
         MG_BY_SWITCH(cfg.by, (k_ir2d<VARV, BY, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride)))
+    } else if constexpr (VARV) {  // at most 16 rows (max_tile_rows)
+        if (cfg.pd == 2) {
+            MG_BY_SWITCH16(cfg.by, (k_ir3d<VARV, BY, 2, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+        } else {
+            MG_BY_SWITCH16(cfg.by, (k_ir3d<VARV, BY, 1, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+        }
     } else if (cfg.pd == 2) {
         MG_BY_SWITCH(cfg.by, (k_ir3d<VARV, BY, 2, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
     } else {

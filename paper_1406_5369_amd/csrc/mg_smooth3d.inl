@@ -20,6 +20,12 @@ namespace {
 // lanes (DPP), y-neighbours from LDS.  Register rings are indexed by
 // (plane - first plane) mod 3, resolved at compile time by unrolling three
 // steps; the coefficient ring for variable coefficients works the same way.
+//
+// With SWEEP_PROLONG the incoming iterate is u + P uc (trilinear correction
+// from the coarse grid, inner nodes only), formed as each plane enters.  A
+// coarse plane K serves fine planes 2K-1, 2K and 2K+1, so each coarse plane is
+// loaded once per march (issued one step ahead) and reduced per thread row to
+// its x-then-y partial sum; the odd-x partner value comes from the next lane.
 // ---------------------------------------------------------------------------
 
 template <typename T, int SM, bool VAR, int BY, int PD, int FL>
@@ -27,6 +33,8 @@ struct Smooth3D {
     static constexpr int flags = FL;
     static constexpr int H = SM == SM_RBGS ? 2 : 1;
     static constexpr int TX = BX - 2 * H, TY = BY - 2 * H, RPT = BY / 4;
+
+    static constexpr bool PRO = (FL & SWEEP_PROLONG) != 0;
 
     T (*U)[BY][BX];   // old u of recent planes (y-neighbour exchange)
     T (*R)[BY][BX];   // red-updated u of recent planes
@@ -47,31 +55,105 @@ struct Smooth3D {
 
     __device__ __forceinline__ int gy(int m) const { return y0 - H + w + 4 * m; }
 
-    // Per-thread addressing, computed once: the clamped (always in-bounds)
-    // offset of each of the thread's rows inside a plane, and row masks.
-    // A plane is addressed by a wave-uniform base pointer, so every load and
-    // store is a scalar base plus a 32-bit per-lane offset.
-    unsigned roff[RPT];  // clamp(y)*n + clamp(x)
+    // Addressing: a thread's rows are wave-uniform (the wave index is read
+    // into a scalar register), so each row of a plane has a scalar base
+    // address and the only per-lane part is the byte offset of the lane's
+    // (clamped, always in-bounds) x position.
+    unsigned xb;         // clamp(x) * sizeof(T)
     unsigned mgrid;      // bit m: row m inside the grid (x and y)
     unsigned minner;     // bit m: row m an inner node (x and y)
     unsigned mring;      // bit m: row m in the relaxed region of the first half-sweep
     unsigned mtile;      // bit m: row m in the output tile (second half-sweep)
     size_t pl;           // n*n
 
+    __device__ __forceinline__ int rowoff(int m) const { return min(max(gy(m), 0), n - 1) * n; }
+
+    // coarse-grid correction (SWEEP_PROLONG)
+    const MG_GLOBAL T* __restrict__ ec;  // coarse correction, edge nc
+    int nc;
+    unsigned codd;                       // bit m: row m has odd y
+    unsigned cxb;                        // byte offset of the lane's coarse column
+    T craw[PRO ? RPT : 1][2];            // coarse rows y/2 and y/2 + (y odd) of the pending coarse plane
+    T sylast[PRO ? RPT : 1];             // x-y partial sum of the latest completed coarse plane
+
+    __device__ __forceinline__ int crowoff(int m) const { return (min(max(gy(m), 0), n - 1) >> 1) * nc; }
+
     __device__ __forceinline__ void init_rows() {
         pl = (size_t)n * n;
         const int xc = min(max(gx, 0), n - 1);
+        xb = (unsigned)xc * (unsigned)sizeof(T);
         mgrid = minner = mring = mtile = 0;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const int y = gy(m), ly = w + 4 * m;
-            roff[m] = (unsigned)(min(max(y, 0), n - 1) * n + xc);
             if (colg && y >= 0 && y < n) mgrid |= 1u << m;
             if (coli && y >= 1 && y <= n - 2) minner |= 1u << m;
             if (lane1 && ly >= 1 && ly <= BY - 2) mring |= 1u << m;
             if (lane >= 2 && lane <= BX - 3 && ly >= 2 && ly <= BY - 3 && gx <= n - 2 && y <= n - 2)
                 mtile |= 1u << m;
         }
+        if constexpr (PRO) {
+            cxb = (unsigned)(H == 2 ? xc >> 1 : (xc + 1) >> 1) * (unsigned)sizeof(T);
+            codd = 0;
+#pragma unroll
+            for (int m = 0; m < RPT; ++m)
+                if (min(max(gy(m), 0), n - 1) & 1) codd |= 1u << m;
+        }
+    }
+
+    // Coarse plane K (clamped): for each row, the coarse row y/2 and, for odd
+    // y, the row above it (the same row again for even y).
+    __device__ __forceinline__ void issue_c(int K) {
+        const MG_GLOBAL T* __restrict__ cp = ec + (size_t)min(max(K, 0), nc - 1) * ((size_t)nc * nc);
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const MG_GLOBAL T* __restrict__ row = cp + crowoff(m);
+            craw[m][0] = ld_off(row, cxb);
+            craw[m][1] = ld_off(row + (((codd >> m) & 1u) ? nc : 0), cxb);
+        }
+    }
+    // x-then-y partial sum of the pending coarse plane at row m.  Each lane
+    // holds one coarse column; an odd-x lane takes its other column from a
+    // neighbouring lane.  With a two-node halo (RBGS) the first lane has odd x
+    // and the last even x, so lanes hold column x/2 and odd lanes pair with the
+    // next lane; with a one-node halo (Jacobi) it is the other way round, so
+    // lanes hold column (x+1)/2 and odd lanes pair with the previous lane.
+    __device__ __forceinline__ T coarse_sum(int m) const {
+        const T a = craw[m][0], b = craw[m][1];
+        const bool xo = (gx & 1) != 0;
+        T sa, sb;
+        if constexpr (H == 2) {
+            const T an = lane_next(a), bn = lane_next(b);
+            sa = xo ? a + an : a;
+            sb = xo ? b + bn : b;
+        } else {
+            const T ap = lane_prev(a), bp = lane_prev(b);
+            sa = xo ? ap + a : a;
+            sb = xo ? bp + b : b;
+        }
+        return ((codd >> m) & 1u) ? sa + sb : sa;
+    }
+    // Plane kk enters: add the interpolated correction on inner nodes, then
+    // issue the coarse plane the next (odd) fine plane needs.
+    template <int S0>
+    __device__ __forceinline__ void correct_entering(int kk) {
+        const bool zo = (kk & 1) != 0;
+        const bool zin = kk >= 1 && kk <= n - 2;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            T sum;
+            if (zo) {
+                const T sn = coarse_sum(m);
+                sum = sylast[m] + sn;
+                sylast[m] = sn;
+            } else {
+                sum = sylast[m];
+            }
+            const int nodd = (gx & 1) + (int)((codd >> m) & 1u) + (zo ? 1 : 0);
+            const T corr = nodd == 0 ? sum : (nodd == 1 ? T(0.5) * sum : (nodd == 2 ? T(0.25) * sum : T(0.125) * sum));
+            if (zin && ((minner >> m) & 1u)) un[S0][m] = un[S0][m] + corr;
+        }
+        if (!zo) issue_c((kk + 2) >> 1);
     }
 
     // Loads are unconditional from clamped (always in-bounds) addresses and
@@ -86,13 +168,13 @@ struct Smooth3D {
         for (int m = 0; m < RPT; ++m) {
             const bool ing = zok && ((mgrid >> m) & 1u);
             if constexpr (!(flags & SWEEP_ZERO_GUESS)) {
-                const T v = up[roff[m]];
+                const T v = ld_off(up + rowoff(m), xb);
                 du[m] = ing ? v : T(0);
             } else {
                 du[m] = T(0);
             }
             if constexpr (VAR) {
-                const T kv = kp[roff[m]];
+                const T kv = ld_off(kp + rowoff(m), xb);
                 dk[m] = ing ? kv : T(1);
             }
         }
@@ -103,7 +185,7 @@ struct Smooth3D {
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const bool inn = zin && ((minner >> m) & 1u) && ((mring >> m) & 1u);
-            const T v = fp[roff[m]];
+            const T v = ld_off(fp + rowoff(m), xb);
             dst[m] = inn ? v : T(0);
         }
     }
@@ -127,6 +209,7 @@ struct Smooth3D {
     __device__ __forceinline__ void step(int kk) {
         constexpr int S0 = P, S1 = (P + 2) % 3, S2 = (P + 1) % 3;  // slots of planes kk, kk-1, kk-2
         constexpr int SN = (P + PD) % 3;                           // slot of plane kk+PD
+        if constexpr (PRO) correct_entering<S0>(kk);
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             uo[S0][m] = un[S0][m];
@@ -186,7 +269,7 @@ struct Smooth3D {
                         if (((gx + y + m2) & 1) == 1)
                             v = relax_at(R[S2], rc, ro[P][m], ro[S1][m], rw, re, ly, kc, kb, ka, kw, ke, S2,
                                              fr[S2][m]);
-                        uout[(size_t)m2 * pl + roff[m]] = v;
+                        st_off(uout + (size_t)m2 * pl + rowoff(m), xb, v);
                     }
                 }
             }
@@ -211,8 +294,9 @@ struct Smooth3D {
                         ka = ko[S0][m];
                     }
                     if (((mring >> m) & (minner >> m) & 1u))
-                        uout[(size_t)m1 * pl + roff[m]] = relax_at(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, kc,
-                                                                   kb, ka, kw, ke, S1, fr[S1][m]);
+                        st_off(uout + (size_t)m1 * pl + rowoff(m), xb,
+                               relax_at(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, kc, kb, ka, kw, ke, S1,
+                                        fr[S1][m]));
                 }
             }
         }
@@ -226,6 +310,14 @@ struct Smooth3D {
     __device__ __forceinline__ void run() {
         init_rows();
         int kk = kstart;
+        if constexpr (PRO) {
+            // plane kstart needs the coarse plane kstart/2 (rounded down) completed,
+            // and for odd kstart the next coarse plane pending
+            issue_c((kk - (kk & 1)) >> 1);
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) sylast[m] = coarse_sum(m);
+            if (kk & 1) issue_c((kk + 1) >> 1);
+        }
         issue_u(kk, un[0], kn[0]);
         if constexpr (PD == 2) issue_u(kk + 1, un[1], kn[1]);
 #pragma unroll
@@ -272,11 +364,13 @@ __global__ __launch_bounds__(NT) void k_smooth3d(const GridDesc* __restrict__ de
     s.uout = gp((T*)(sel ? d.u : d.t));
     s.f = gp((const T*)d.f);
     s.kf = gp((const T*)d.k);
+    s.ec = gp((const T*)d.uc);
+    s.nc = (n - 1) / 2 + 1;
     s.c = (T)d.c;
     s.wd = (T)d.wd;
     s.om = (T)d.omega;
     s.lane = threadIdx.x & 63;
-    s.w = threadIdx.x >> 6;
+    s.w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     s.gx = s.x0 - S::H + s.lane;
     s.colg = s.gx >= 0 && s.gx < n;
     s.coli = s.gx >= 1 && s.gx <= n - 2;
@@ -288,10 +382,18 @@ __global__ __launch_bounds__(NT) void k_smooth3d(const GridDesc* __restrict__ de
 
 template <typename T, int SMV, bool VARV, int FL>
 hipError_t launch_smooth3d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
-    if (cfg.pd == 2) {
-        MG_BY_SWITCH(cfg.by, (k_smooth3d<T, SMV, VARV, BY, 2, FL><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
+    if constexpr (sizeof(T) == 8 || VARV) {  // at most 16 rows (max_tile_rows)
+        if (cfg.pd == 2) {
+            MG_BY_SWITCH16(cfg.by, (k_smooth3d<T, SMV, VARV, BY, 2, FL><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
+        } else {
+            MG_BY_SWITCH16(cfg.by, (k_smooth3d<T, SMV, VARV, BY, 1, FL><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
+        }
     } else {
-        MG_BY_SWITCH(cfg.by, (k_smooth3d<T, SMV, VARV, BY, 1, FL><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
+        if (cfg.pd == 2) {
+            MG_BY_SWITCH(cfg.by, (k_smooth3d<T, SMV, VARV, BY, 2, FL><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
+        } else {
+            MG_BY_SWITCH(cfg.by, (k_smooth3d<T, SMV, VARV, BY, 1, FL><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
+        }
     }
     return hipSuccess;
 }
@@ -303,6 +405,7 @@ hipError_t launch_smooth3d(int sm, bool var, const GridDesc* d, int sel, int fla
     switch (flags) {                                                                                       \
         case 0: return launch_smooth3d_fl<T, SMV, VARV, 0>(d, sel, cfg, grid, s);                           \
         case SWEEP_ZERO_GUESS: return launch_smooth3d_fl<T, SMV, VARV, SWEEP_ZERO_GUESS>(d, sel, cfg, grid, s); \
+        case SWEEP_PROLONG: return launch_smooth3d_fl<T, SMV, VARV, SWEEP_PROLONG>(d, sel, cfg, grid, s);       \
         default: return hipErrorInvalidValue;                                                              \
     }
     if (sm == SM_RBGS) {

@@ -127,7 +127,7 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
     for (int l = L - 2; l >= 0; --l) {
         const Group& g = G[(size_t)l];
         int cur = sel[(size_t)l];
-        const bool fuse = P.nu2 > 0 && dim == 2;  // 2D sweeps add P uc while loading
+        const bool fuse = P.nu2 > 0;  // the first post-sweep adds P uc while loading
         if (!fuse) MG_TRY(launch_prolong<T>(dim, g.d, g.ninst, g.n, cur, s));
         for (int i = 0; i < P.nu2; ++i) {
             const int flags = (i == 0 && fuse) ? SWEEP_PROLONG : 0;

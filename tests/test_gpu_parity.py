@@ -42,6 +42,13 @@ def same(a, b):
     return a.shape == b.shape and np.array_equal(a, b)
 
 
+def over_row_limit(dim, by, dt, varcoef):
+    """3D sweeps in FP64 or with a coefficient field take tiles of at most 16
+    rows (a 32-row tile would not fit the register file); the library rejects
+    larger ones."""
+    return dim == 3 and by == 32 and (dt == np.float64 or varcoef)
+
+
 def case_arrays(dim, n, dt, varcoef, seed=0):
     u = inputs.random_guess(dim, n, 100 + seed).astype(dt)
     f = (inputs.uniform_rhs(dim, n, 200 + seed) * 50.0).astype(dt)
@@ -67,8 +74,13 @@ def test_smooth_sweep_bitwise(dim, n, by, zc, pd, smoother, dt, varcoef, dev_ok)
     expect = oracle.smooth(u, f, smoother=smoother, omega=omega, k=k)
     ud, fd = dev(u), dev(f)
     out = dev(np.zeros_like(u))
-    mg().mg_level_smooth(ud, fd, out, smoother=smoother, omega=omega, k=dev(k) if k is not None else None,
-                         by=by, zchunk=zc, prefetch=pd)
+    kd = dev(k) if k is not None else None
+    if over_row_limit(dim, by, dt, varcoef):
+        with pytest.raises(mg().MGError) as ei:
+            mg().mg_level_smooth(ud, fd, out, smoother=smoother, omega=omega, k=kd, by=by, zchunk=zc, prefetch=pd)
+        assert ei.value.code == mg().MG_EINVAL
+        return
+    mg().mg_level_smooth(ud, fd, out, smoother=smoother, omega=omega, k=kd, by=by, zchunk=zc, prefetch=pd)
     assert same(host(out), expect)
 
 
@@ -82,17 +94,36 @@ def test_smooth_zero_guess_bitwise(dim, n, by, zc, pd, dt, dev_ok):
     assert same(host(out), expect)
 
 
-@pytest.mark.parametrize("n", [9, 65, 257])
+FUSED_CASES = [(2, 9, 0, 0, 0), (2, 65, 0, 0, 0), (2, 257, 0, 0, 0),
+               (3, 5, 0, 0, 0), (3, 9, 8, 1, 1), (3, 17, 16, 3, 2), (3, 33, 8, 5, 1), (3, 33, 32, 2, 2),
+               (3, 65, 32, 7, 2), (3, 65, 0, 0, 0), (3, 129, 16, 13, 1)]
+
+
+@pytest.mark.parametrize("dim,n,by,zc,pd", FUSED_CASES)
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 @pytest.mark.parametrize("smoother", [RB, JAC])
-def test_smooth_with_fused_correction_2d_bitwise(n, dt, smoother, dev_ok):
-    u, f, _ = case_arrays(2, n, dt, False, seed=5)
+@pytest.mark.parametrize("varcoef", [False, True])
+def test_smooth_with_fused_correction_bitwise(dim, n, by, zc, pd, dt, smoother, varcoef, dev_ok):
+    """First post-smoothing sweep with the coarse-grid correction added while
+    loading: equals interpolation + correction followed by the sweep.  Odd
+    z-chunks put the first plane of a chunk on both parities."""
+    if varcoef and n > 65:
+        pytest.skip("var-coef covered at the smaller sizes")
+    u, f, k = case_arrays(dim, n, dt, varcoef, seed=5)
     nc = (n - 1) // 2 + 1
-    ec = inputs.random_guess(2, nc, 77).astype(dt)
+    ec = inputs.random_guess(dim, nc, 77).astype(dt)
     omega = 1.0 if smoother == RB else 0.8
-    expect = oracle.smooth(oracle.prolong_correct(u, ec), f, smoother=smoother, omega=omega)
+    expect = oracle.smooth(oracle.prolong_correct(u, ec), f, smoother=smoother, omega=omega, k=k)
     out = dev(np.zeros_like(u))
-    mg().mg_level_smooth(dev(u), dev(f), out, smoother=smoother, omega=omega, ec=dev(ec))
+    kd = dev(k) if varcoef else None
+    if over_row_limit(dim, by, dt, varcoef):
+        with pytest.raises(mg().MGError) as ei:
+            mg().mg_level_smooth(dev(u), dev(f), out, smoother=smoother, omega=omega, k=kd, ec=dev(ec), by=by,
+                                 zchunk=zc, prefetch=pd)
+        assert ei.value.code == mg().MG_EINVAL
+        return
+    mg().mg_level_smooth(dev(u), dev(f), out, smoother=smoother, omega=omega, k=kd, ec=dev(ec), by=by, zchunk=zc,
+                         prefetch=pd)
     assert same(host(out), expect)
 
 
