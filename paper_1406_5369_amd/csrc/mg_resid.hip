@@ -77,58 +77,52 @@ struct Resid3D {
 
     __device__ __forceinline__ int gy(int m) const { return y0 - 1 + w + 4 * m; }
 
-    // per-thread clamped row offsets and row masks, computed once; planes are
-    // addressed through wave-uniform base pointers
-    unsigned roff[RPT];
-    unsigned mgrid, minner, mring;
+    // Rows are wave-uniform (the wave index is read into a scalar register):
+    // each row of a plane has a scalar base address and the per-lane part is
+    // the byte offset of the lane's clamped x position (xb for 8-byte words,
+    // xb4 for the FP32 correction and residual).
+    unsigned xb, xb4;
+    unsigned minner, mring;
     size_t pl;
+
+    __device__ __forceinline__ int rowoff(int m) const { return min(max(gy(m), 0), n - 1) * n; }
 
     __device__ __forceinline__ void init_rows() {
         pl = (size_t)n * n;
         const int xc = min(max(gx, 0), n - 1);
-        mgrid = minner = mring = 0;
+        xb = (unsigned)xc * 8u;
+        xb4 = (unsigned)xc * 4u;
+        minner = mring = 0;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const int y = gy(m), ly = w + 4 * m;
-            roff[m] = (unsigned)(min(max(y, 0), n - 1) * n + xc);
-            if (gx < n && y < n) mgrid |= 1u << m;
             if (coli && y >= 1 && y <= n - 2) minner |= 1u << m;
             if (lane1 && ly >= 1 && ly <= BY - 2) mring |= 1u << m;
         }
     }
 
-    // unconditional loads from clamped addresses, values selected afterwards
+    // Unconditional loads from clamped (always in-bounds) addresses, kept as
+    // loaded: a value at a position outside the grid or off the inner nodes is
+    // never used, since every residual and update is taken at an inner node,
+    // whose neighbours all lie in the grid.  No select on the loaded value, so
+    // no branch around the loads and no wait for them before they are used.
     __device__ __forceinline__ void issue(int z, double (&du)[RPT], float (&de)[RPT], double (&dk)[RPT]) {
-        const bool zok = z < n && z <= kend;
-        const bool zin = z >= 1 && z <= n - 2;
         const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
         const MG_GLOBAL double* __restrict__ up = uin + zoff;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const double v = up[roff[m]];
-            du[m] = (zok && ((mgrid >> m) & 1u)) ? v : 0.0;
+            du[m] = ld_off(up + rowoff(m), xb);
             if constexpr (IR) {
-                if (!(flags & IR_NO_UPDATE)) {
-                    const float ev = e[zoff + roff[m]];
-                    de[m] = (zin && ((minner >> m) & 1u)) ? ev : 0.0f;
-                } else {
-                    de[m] = 0.0f;
-                }
+                if (!(flags & IR_NO_UPDATE)) de[m] = ld_off(e + zoff + rowoff(m), xb4);
+                else de[m] = 0.0f;
             }
-            if constexpr (VAR) {
-                const double kv = kf[zoff + roff[m]];
-                dk[m] = (zok && ((mgrid >> m) & 1u)) ? kv : 1.0;
-            }
+            if constexpr (VAR) dk[m] = ld_off(kf + zoff + rowoff(m), xb);
         }
     }
     __device__ __forceinline__ void issue_f(int z, double (&dst)[RPT]) {
-        const bool zin = z >= 1 && z <= n - 2;
         const MG_GLOBAL double* __restrict__ fp = f + (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
-        for (int m = 0; m < RPT; ++m) {
-            const double v = fp[roff[m]];
-            dst[m] = (zin && ((minner >> m) & (mring >> m) & 1u)) ? v : 0.0;
-        }
+        for (int m = 0; m < RPT; ++m) dst[m] = ld_off(fp + rowoff(m), xb);
     }
 
     template <int P>
@@ -144,7 +138,7 @@ struct Resid3D {
                 const bool inn = zin && coli && y >= 1 && y <= n - 2;
                 if (inn && !(flags & IR_NO_UPDATE)) {
                     v = v + (double)en[S0][m];
-                    if (own && ((mring >> m) & 1u)) uout[(size_t)kk * pl + roff[m]] = v;
+                    if (own && ((mring >> m) & 1u)) st_off(uout + (size_t)kk * pl + rowoff(m), xb, v);
                 }
             }
             uo[S0][m] = v;
@@ -184,7 +178,7 @@ struct Resid3D {
                     const double r = res3<double, VAR>(uc, uw, ue, U[S1][ly - 1][lane], U[S1][ly + 1][lane],
                                                        uo[S2][m], uo[S0][m], kc, kw, ke, kS, kN, kb, ka, fr[S1][m],
                                                        c, ds);
-                    if constexpr (IR) r32[(size_t)zz * pl + roff[m]] = (float)r;
+                    if constexpr (IR) st_off(r32 + (size_t)zz * pl + rowoff(m), xb4, (float)r);
                     acc += r * r;
                 }
             }
@@ -253,7 +247,7 @@ __device__ __forceinline__ void resid3d_body(const GridDesc* gd, const IRDesc* i
     s.kend = s.z1;
     s.flags = flags;
     s.lane = threadIdx.x & 63;
-    s.w = threadIdx.x >> 6;
+    s.w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     s.gx = s.x0 - 1 + s.lane;
     s.coli = s.gx >= 1 && s.gx <= n - 2;
     s.lane1 = s.lane >= 1 && s.lane <= BX - 2;

@@ -60,7 +60,6 @@ struct Smooth3D {
     // address and the only per-lane part is the byte offset of the lane's
     // (clamped, always in-bounds) x position.
     unsigned xb;         // clamp(x) * sizeof(T)
-    unsigned mgrid;      // bit m: row m inside the grid (x and y)
     unsigned minner;     // bit m: row m an inner node (x and y)
     unsigned mring;      // bit m: row m in the relaxed region of the first half-sweep
     unsigned mtile;      // bit m: row m in the output tile (second half-sweep)
@@ -82,11 +81,10 @@ struct Smooth3D {
         pl = (size_t)n * n;
         const int xc = min(max(gx, 0), n - 1);
         xb = (unsigned)xc * (unsigned)sizeof(T);
-        mgrid = minner = mring = mtile = 0;
+        minner = mring = mtile = 0;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const int y = gy(m), ly = w + 4 * m;
-            if (colg && y >= 0 && y < n) mgrid |= 1u << m;
             if (coli && y >= 1 && y <= n - 2) minner |= 1u << m;
             if (lane1 && ly >= 1 && ly <= BY - 2) mring |= 1u << m;
             if (lane >= 2 && lane <= BX - 3 && ly >= 2 && ly <= BY - 3 && gx <= n - 2 && y <= n - 2)
@@ -157,37 +155,25 @@ struct Smooth3D {
     }
 
     // Loads are unconditional from clamped (always in-bounds) addresses and
-    // the value is selected afterwards: no branches around loads, so the
-    // compiler can keep the prefetches in flight across steps.
+    // the values are kept as loaded: a value at a position outside the grid is
+    // never used, because every relaxation is taken at an inner node, whose
+    // neighbours all lie in the grid.  With no select on loaded values there is
+    // no branch around the loads, so the prefetches stay in flight across steps.
     __device__ __forceinline__ void issue_u(int z, T (&du)[RPT], T (&dk)[RPT]) {
-        const bool zok = z >= 0 && z < n && z <= kend;
         const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
         const MG_GLOBAL T* __restrict__ up = uin + zoff;
         const MG_GLOBAL T* __restrict__ kp = kf + zoff;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const bool ing = zok && ((mgrid >> m) & 1u);
-            if constexpr (!(flags & SWEEP_ZERO_GUESS)) {
-                const T v = ld_off(up + rowoff(m), xb);
-                du[m] = ing ? v : T(0);
-            } else {
-                du[m] = T(0);
-            }
-            if constexpr (VAR) {
-                const T kv = ld_off(kp + rowoff(m), xb);
-                dk[m] = ing ? kv : T(1);
-            }
+            if constexpr (!(flags & SWEEP_ZERO_GUESS)) du[m] = ld_off(up + rowoff(m), xb);
+            else du[m] = T(0);
+            if constexpr (VAR) dk[m] = ld_off(kp + rowoff(m), xb);
         }
     }
     __device__ __forceinline__ void issue_f(int z, T (&dst)[RPT]) {
-        const bool zin = z >= 1 && z <= n - 2;
         const MG_GLOBAL T* __restrict__ fp = f + (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
-        for (int m = 0; m < RPT; ++m) {
-            const bool inn = zin && ((minner >> m) & 1u) && ((mring >> m) & 1u);
-            const T v = ld_off(fp + rowoff(m), xb);
-            dst[m] = inn ? v : T(0);
-        }
+        for (int m = 0; m < RPT; ++m) dst[m] = ld_off(fp + rowoff(m), xb);
     }
 
     // relaxation at row m of the thread, plane values: A (centre plane
