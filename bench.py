@@ -393,8 +393,8 @@ def main(argv=None) -> int:
     bytes_per_launch = (4 if var else 3) * word * dof  # u, f (and k) read, u written
     avg_ms = sweep_ms / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    by, zchunk, pd = mg.mg_tile_config(solver.ctx, 0, 0)
-    kname = sweep_kernel(dim, word, by, pd, var)
+    by, zchunk, pd, wv = mg.mg_tile_config(solver.ctx, 0, 0)
+    kname = sweep_kernel(dim, word, by, pd, var, wv)
     kblocks = sweep_blocks(dim, n, by, zchunk)
     roofline = {
         "bound": "hbm",
@@ -412,7 +412,7 @@ def main(argv=None) -> int:
         "traffic": None,
     }
 
-    tr = traffic_record(args.workload, (by, zchunk, pd))
+    tr = traffic_record(args.workload, (by, zchunk, pd, wv))
     if tr and tr.get("kernel") == kname and tr.get("blocks") == kblocks:
         roofline["traffic"] = tr["bytes_per_launch"]
         roofline["traffic_ratio_to_algorithmic"] = tr["ratio_to_algorithmic"]

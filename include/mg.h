@@ -112,11 +112,13 @@ int mg_num_levels(const mg_ctx* ctx);
 
 /* Launch geometry the context uses on 'level' (0 = finest) for kernel 'family'
  * (0 smoothing, 1 residual + restriction, 2 finest-level norm / refinement
- * pass): tile rows *by, z-chunk *zchunk (3D planes per workgroup) and, for 3D
- * smoothing, *prefetch = planes of u loaded ahead (1 or 2; may be NULL).  These are
- * the autotuner's choices (measured at mg_setup unless the environment sets
- * MG_AUTOTUNE=0) or the built-in heuristic.  Results never depend on them. */
-int mg_tile_config(const mg_ctx* ctx, int level, int family, int* by, int* zchunk, int* prefetch);
+ * pass): tile rows *by, z-chunk *zchunk (3D planes per workgroup), for 3D
+ * marching kernels *prefetch = planes of u loaded ahead (1 or 2), and *waves =
+ * wavefronts per workgroup (4, or 8 for 3D smoothing); prefetch and waves may
+ * be NULL.  These are the autotuner's choices (measured at mg_setup unless the
+ * environment sets MG_AUTOTUNE=0) or the built-in heuristic.  Results never
+ * depend on them. */
+int mg_tile_config(const mg_ctx* ctx, int level, int family, int* by, int* zchunk, int* prefetch, int* waves);
 
 /* Human-readable name of a status code. */
 const char* mg_strerror(int code);
@@ -128,7 +130,10 @@ const char* mg_strerror(int code);
  * 'k' is null (Laplacian) or the nodal coefficient of this level.  'by' and
  * 'zchunk' pick the tile shape (0 = library default): by in {8, 16, 32},
  * zchunk >= 1 (3D only); 'prefetch' (3D smoothing) is 1 or 2 planes of u
- * loaded ahead (0 = default).  Asynchronous on 'stream'.
+ * loaded ahead and 'waves' (3D smoothing) 4 or 8 wavefronts per workgroup
+ * (0 = default).  3D sweeps hold by/waves rows per thread: at most 4 in FP64
+ * or with a coefficient field, 8 otherwise (MG_EINVAL beyond).  Asynchronous
+ * on 'stream'.
  * ------------------------------------------------------------------------- */
 
 /* One smoothing sweep (Section 2.4 GaussSeidel / Section 2.3 Jacobi) from u_in
@@ -139,7 +144,7 @@ const char* mg_strerror(int code);
  * followed by post-smoothing). */
 int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const void* k, const void* u_in,
                     const void* f, void* u_out, const void* ec, int zero_guess, int by, int zchunk, int prefetch,
-                    void* stream);
+                    int waves, void* stream);
 
 /* fc = full weighting of r = f - A u (Algorithm 1: residual and restriction)
  * on the inner nodes of the coarse grid ((n-1)/2+1 per axis); fc's boundary is not written. */

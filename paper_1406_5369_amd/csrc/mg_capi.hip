@@ -314,19 +314,23 @@ std::map<TuneKey, TileCfg> g_tune;
 
 constexpr size_t kTuneMinPoints = 1u << 16;
 
-std::vector<TileCfg> tune_candidates(int dim, int planes, bool with_pd, int max_by) {
+// Candidate launch geometries.  family 0 (3D smoothing) also varies the
+// wavefronts per workgroup (8 wavefronts for 16- and 32-row tiles).
+std::vector<TileCfg> tune_candidates(int dim, int planes, bool with_pd, int family, int elem, bool var) {
     std::vector<TileCfg> v;
-    const int bys[3] = {8, 16, 32};
-    for (int by : bys) {
-        if (by > max_by) continue;
+    const int geo[5][2] = {{8, 4}, {16, 4}, {32, 4}, {16, 8}, {32, 8}};
+    for (const auto& g : geo) {
+        const int by = g[0], wv = g[1];
+        if (wv == 8 && (dim == 2 || family != 0)) continue;
+        if (by > max_tile_rows(dim, elem, var, family, wv)) continue;
         if (dim == 2) {
-            v.push_back({by, 1, 1});
+            v.push_back({by, 1, 1, 4});
             continue;
         }
         for (int zc = 4; zc <= 256; zc *= 2) {
             if (zc > std::max(4, planes)) break;
-            v.push_back({by, zc, 1});
-            if (with_pd) v.push_back({by, zc, 2});
+            v.push_back({by, zc, 1, wv});
+            if (with_pd) v.push_back({by, zc, 2, wv});
         }
     }
     return v;
@@ -426,7 +430,7 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
         TuneKey ks{dim, L.elem, n, 0, sm, var ? 1 : 0, 0};
         TileCfg cfg;
         if (!tune_lookup(ks, &cfg)) {
-            cfg = pick_fastest(tune_candidates(dim, n - 2, true, max_tile_rows(dim, L.elem, var, 0)), tl[(size_t)l].smooth, [&](TileCfg t) {
+            cfg = pick_fastest(tune_candidates(dim, n - 2, true, 0, L.elem, var), tl[(size_t)l].smooth, [&](TileCfg t) {
                 return L.elem == 8 ? launch_smooth<double>(dim, sm, var, d, 1, n, 0, 0, t, s)
                                    : launch_smooth<float>(dim, sm, var, d, 1, n, 0, 0, t, s);
             }, s);
@@ -436,7 +440,7 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
         TuneKey kr{dim, L.elem, n, 1, 0, var ? 1 : 0, 0};
         if (!tune_lookup(kr, &cfg)) {
             std::vector<TileCfg> cands;
-            for (TileCfg t : tune_candidates(dim, (n - 1) / 2 - 1, false, max_tile_rows(dim, L.elem, var, 1)))
+            for (TileCfg t : tune_candidates(dim, (n - 1) / 2 - 1, false, 1, L.elem, var))
                 if (t.by >= 8) cands.push_back(t);
             cfg = pick_fastest(cands, tl[(size_t)l].restr, [&](TileCfg t) {
                 return L.elem == 8 ? launch_restrict<double>(dim, var, d, 1, n, 0, t, s)
@@ -473,7 +477,7 @@ hipError_t autotune(mg_ctx* c) {
         TuneKey kn{dim, 8, n, 2, 0, var ? 1 : 0, mode};
         TileCfg cfg;
         if (!tune_lookup(kn, &cfg)) {
-            const std::vector<TileCfg> cands = tune_candidates(dim, n - 2, true, max_tile_rows(dim, 8, var, 2));
+            const std::vector<TileCfg> cands = tune_candidates(dim, n - 2, true, 2, 8, var);
             int maxparts = 1;
             for (TileCfg t : cands) maxparts = std::max(maxparts, norm_tiles(dim, n, t));
             double* part = nullptr;
@@ -649,7 +653,7 @@ void mg_destroy(mg_ctx* c) {
 
 int mg_num_levels(const mg_ctx* c) { return c && !is_batch_handle(c) ? c->nlev : MG_EINVAL; }
 
-int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch) {
+int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch, int* waves) {
     if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 2)
         return MG_EINVAL;
     const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
@@ -658,6 +662,7 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
     *by = t.by;
     *zchunk = t.zchunk;
     if (prefetch) *prefetch = t.pd;
+    if (waves) *waves = t.wv;
     return MG_OK;
 }
 
@@ -794,8 +799,10 @@ static TileCfg pick_cfg(int dim, int elem, int n, int smoother, int by, int zchu
     return c;
 }
 
-static bool valid_cfg(TileCfg c, int max_by) {
-    return (c.by == 8 || c.by == 16 || c.by == 32) && c.by <= max_by && c.zchunk >= 1 && (c.pd == 1 || c.pd == 2);
+static bool valid_cfg(TileCfg c, int dim, int elem, bool var, int family) {
+    if (c.by != 8 && c.by != 16 && c.by != 32) return false;
+    if (c.wv != 4 && !(c.wv == 8 && dim == 3 && family == 0 && c.by >= 16)) return false;
+    return c.by <= max_tile_rows(dim, elem, var, family, c.wv) && c.zchunk >= 1 && (c.pd == 1 || c.pd == 2);
 }
 
 // Temporary device descriptor for a context-free call; the stream is synchronised before release.
@@ -814,13 +821,14 @@ static int finish_desc(void* d, hipStream_t s, hipError_t launch) {
 
 int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const void* k, const void* u_in,
                     const void* f, void* u_out, const void* ec, int zero_guess, int by, int zchunk, int prefetch,
-                    void* stream) {
+                    int waves, void* stream) {
     if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
     if ((smoother != 0 && smoother != 1) || !f || !u_out || (!u_in && !zero_guess)) return MG_EINVAL;
     if (ec && zero_guess) return MG_EINVAL;
     TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, n, smoother, by, zchunk, 0);
     if (prefetch) cfg.pd = prefetch;
-    if (!valid_cfg(cfg, max_tile_rows(dim, dtype == 0 ? 8 : 4, k != nullptr, 0))) return MG_EINVAL;
+    if (waves) cfg.wv = waves;
+    if (!valid_cfg(cfg, dim, dtype == 0 ? 8 : 4, k != nullptr, 0)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
     h.u = const_cast<void*>(u_in);
@@ -846,7 +854,7 @@ int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const v
     if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
     if (!u || !f || !fc) return MG_EINVAL;
     const TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, n, 0, by, zchunk, 1);
-    if (!valid_cfg(cfg, max_tile_rows(dim, dtype == 0 ? 8 : 4, k != nullptr, 1))) return MG_EINVAL;
+    if (!valid_cfg(cfg, dim, dtype == 0 ? 8 : 4, k != nullptr, 1)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
     h.u = const_cast<void*>(u);
@@ -900,7 +908,7 @@ int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, cons
     if (!valid_edge(dim, n) || n < 5) return MG_EINVAL;
     if (!u_in || !e || !f || !u_out || !r || !norm_out || u_in == u_out) return MG_EINVAL;
     const TileCfg cfg = pick_cfg(dim, 8, n, 0, by, zchunk, 2);
-    if (!valid_cfg(cfg, max_tile_rows(dim, 8, k != nullptr, 2))) return MG_EINVAL;
+    if (!valid_cfg(cfg, dim, 8, k != nullptr, 2)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     IRDesc h{};
     h.u[0] = const_cast<double*>(u_in);

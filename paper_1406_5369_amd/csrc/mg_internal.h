@@ -20,13 +20,13 @@ inline bool valid_edge(int dim, int n) {
 
 // Largest tile height (rows of a 64-wide tile) of a kernel family: the 3D
 // marching kernels keep three planes of their rows in registers, and with
-// FP64 words or a coefficient field a 32-row tile would not fit the 256
-// architectural VGPRs.  family: 0 smoothing, 1 residual + restriction,
-// 2 FP64 norm / refinement pass.
-inline int max_tile_rows(int dim, int elem, bool var, int family) {
+// FP64 words or a coefficient field more than four rows per thread would not
+// fit the 256 architectural VGPRs.  family: 0 smoothing, 1 residual +
+// restriction, 2 FP64 norm / refinement pass; wv: wavefronts per workgroup.
+inline int max_tile_rows(int dim, int elem, bool var, int family, int wv = 4) {
     if (dim == 2 || family == 1) return 32;
-    if (family == 0) return (elem == 8 || var) ? 16 : 32;
-    return var ? 16 : 32;
+    const int rows_per_thread = (family == 0 ? (elem == 8 || var) : var) ? 4 : 8;
+    return rows_per_thread * wv < 32 ? rows_per_thread * wv : 32;
 }
 
 enum Smoother { SM_RBGS = 0, SM_JACOBI = 1 };
@@ -76,6 +76,7 @@ struct TileCfg {
     int by;      // LDS box rows (2D) / rows of the x-y box (3D): 8, 16 or 32
     int zchunk;  // 3D: output planes per workgroup (ignored in 2D)
     int pd = 1;  // 3D smoothing: planes of old u prefetched ahead (1 or 2)
+    int wv = 4;  // 3D smoothing: wavefronts per workgroup (4 or 8); a thread holds by/wv rows
 };
 
 // Number of workgroups in x for a level of n nodes per axis (one instance).

@@ -28,11 +28,12 @@ namespace {
 // its x-then-y partial sum; the odd-x partner value comes from the next lane.
 // ---------------------------------------------------------------------------
 
-template <typename T, int SM, bool VAR, int BY, int PD, int FL>
+template <typename T, int SM, bool VAR, int BY, int PD, int FL, int WV>
 struct Smooth3D {
     static constexpr int flags = FL;
     static constexpr int H = SM == SM_RBGS ? 2 : 1;
-    static constexpr int TX = BX - 2 * H, TY = BY - 2 * H, RPT = BY / 4;
+    static constexpr int TX = BX - 2 * H, TY = BY - 2 * H, RPT = BY / WV;  // WV wavefronts, RPT rows each
+    static_assert(RPT >= 1 && RPT * WV == BY, "tile rows must be a multiple of the wavefronts");
 
     static constexpr bool PRO = (FL & SWEEP_PROLONG) != 0;
 
@@ -53,7 +54,7 @@ struct Smooth3D {
     T ro[3][RPT];              // red-updated u of planes kk-1, kk-2, kk-3
     T fr[3][RPT];              // f of planes kk, kk-1, kk-2
 
-    __device__ __forceinline__ int gy(int m) const { return y0 - H + w + 4 * m; }
+    __device__ __forceinline__ int gy(int m) const { return y0 - H + w + WV * m; }
 
     // Addressing: a thread's rows are wave-uniform (the wave index is read
     // into a scalar register), so each row of a plane has a scalar base
@@ -84,7 +85,7 @@ struct Smooth3D {
         minner = mring = mtile = 0;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const int y = gy(m), ly = w + 4 * m;
+            const int y = gy(m), ly = w + WV * m;
             if (coli && y >= 1 && y <= n - 2) minner |= 1u << m;
             if (lane1 && ly >= 1 && ly <= BY - 2) mring |= 1u << m;
             if (lane >= 2 && lane <= BX - 3 && ly >= 2 && ly <= BY - 3 && gx <= n - 2 && y <= n - 2)
@@ -199,10 +200,10 @@ struct Smooth3D {
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             uo[S0][m] = un[S0][m];
-            U[S0][w + 4 * m][lane] = uo[S0][m];
+            U[S0][w + WV * m][lane] = uo[S0][m];
             if constexpr (VAR) {
                 ko[S0][m] = kn[S0][m];
-                K[S0][w + 4 * m][lane] = ko[S0][m];
+                K[S0][w + WV * m][lane] = ko[S0][m];
             }
         }
         issue_f(kk, fr[S0]);
@@ -214,7 +215,7 @@ struct Smooth3D {
                 const bool zin = m1 >= 1 && m1 <= n - 2;
 #pragma unroll
                 for (int m = 0; m < RPT; ++m) {
-                    const int ly = w + 4 * m, y = gy(m);
+                    const int ly = w + WV * m, y = gy(m);
                     const T uc = uo[S1][m];
                     const T uw = lane_prev(uc), ue = lane_next(uc);
                     T kc = T(1), kw = T(1), ke = T(1), kb = T(1), ka = T(1);
@@ -238,7 +239,7 @@ struct Smooth3D {
             if (m2 >= z0 && m2 < z1) {
 #pragma unroll
                 for (int m = 0; m < RPT; ++m) {
-                    const int ly = w + 4 * m, y = gy(m);
+                    const int ly = w + WV * m, y = gy(m);
                     const T rc = ro[S2][m];
                     const T rw = lane_prev(rc), re = lane_next(rc);
                     T kc = T(1), kw = T(1), ke = T(1), kb = T(1), ka = T(1);
@@ -268,7 +269,7 @@ struct Smooth3D {
             if (m1 >= z0 && m1 < z1) {
 #pragma unroll
                 for (int m = 0; m < RPT; ++m) {
-                    const int ly = w + 4 * m, y = gy(m);
+                    const int ly = w + WV * m, y = gy(m);
                     const T uc = uo[S1][m];
                     const T uw = lane_prev(uc), ue = lane_next(uc);
                     T kc = T(1), kw = T(1), ke = T(1), kb = T(1), ka = T(1);
@@ -323,11 +324,11 @@ struct Smooth3D {
     }
 };
 
-template <typename T, int SM, bool VAR, int BY, int PD, int FL>
-__global__ __launch_bounds__(NT) void k_smooth3d(const GridDesc* __restrict__ descs, int sel, int zchunk) {
+template <typename T, int SM, bool VAR, int BY, int PD, int FL, int WV>
+__global__ __launch_bounds__(64 * WV) void k_smooth3d(const GridDesc* __restrict__ descs, int sel, int zchunk) {
     const GridDesc d = descs[blockIdx.y];
     if (d.done && *gp(d.done)) return;
-    using S = Smooth3D<T, SM, VAR, BY, PD, FL>;
+    using S = Smooth3D<T, SM, VAR, BY, PD, FL, WV>;
     __shared__ T U[3][BY][BX];
     __shared__ T R[SM == SM_RBGS ? 3 : 1][BY][BX];
     __shared__ T K[VAR ? 3 : 1][BY][BX];
@@ -366,22 +367,36 @@ __global__ __launch_bounds__(NT) void k_smooth3d(const GridDesc* __restrict__ de
 
 }  // namespace
 
+template <typename T, int SMV, bool VARV, int FL, int BY, int WV>
+hipError_t launch_smooth3d_g(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
+    if (cfg.pd == 2) k_smooth3d<T, SMV, VARV, BY, 2, FL, WV><<<grid, 64 * WV, 0, s>>>(d, sel, cfg.zchunk);
+    else k_smooth3d<T, SMV, VARV, BY, 1, FL, WV><<<grid, 64 * WV, 0, s>>>(d, sel, cfg.zchunk);
+    return hipSuccess;
+}
+
+// Tile geometries (rows x wavefronts): 8x4, 16x4, 32x4 (FP32 Laplacian only:
+// eight rows per thread), 16x8 and 32x8.
 template <typename T, int SMV, bool VARV, int FL>
 hipError_t launch_smooth3d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
-    if constexpr (sizeof(T) == 8 || VARV) {  // at most 16 rows (max_tile_rows)
-        if (cfg.pd == 2) {
-            MG_BY_SWITCH16(cfg.by, (k_smooth3d<T, SMV, VARV, BY, 2, FL><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
-        } else {
-            MG_BY_SWITCH16(cfg.by, (k_smooth3d<T, SMV, VARV, BY, 1, FL><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
-        }
-    } else {
-        if (cfg.pd == 2) {
-            MG_BY_SWITCH(cfg.by, (k_smooth3d<T, SMV, VARV, BY, 2, FL><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
-        } else {
-            MG_BY_SWITCH(cfg.by, (k_smooth3d<T, SMV, VARV, BY, 1, FL><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
+    constexpr bool wide = sizeof(T) == 4 && !VARV;
+    if (cfg.wv == 4) {
+        switch (cfg.by) {
+            case 8: return launch_smooth3d_g<T, SMV, VARV, FL, 8, 4>(d, sel, cfg, grid, s);
+            case 16: return launch_smooth3d_g<T, SMV, VARV, FL, 16, 4>(d, sel, cfg, grid, s);
+            case 32:
+                if constexpr (wide) return launch_smooth3d_g<T, SMV, VARV, FL, 32, 4>(d, sel, cfg, grid, s);
+                return hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;
         }
     }
-    return hipSuccess;
+    if (cfg.wv == 8) {
+        switch (cfg.by) {
+            case 16: return launch_smooth3d_g<T, SMV, VARV, FL, 16, 8>(d, sel, cfg, grid, s);
+            case 32: return launch_smooth3d_g<T, SMV, VARV, FL, 32, 8>(d, sel, cfg, grid, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T>

@@ -47,14 +47,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def sweep_kernel(dim: int, word: int, by: int, pd: int, var: bool = False) -> str:
+def sweep_kernel(dim: int, word: int, by: int, pd: int, var: bool = False, wv: int = 4) -> str:
     """Demangled name of a plain (not zero-guess, no fused correction) RBGS
-    sweep with the given tile height and prefetch depth."""
+    sweep with the given tile height, prefetch depth and wavefronts."""
     t = "float" if word == 4 else "double"
     v = "true" if var else "false"
     if dim == 2:
         return f"mg::k_smooth2d<{t}, 0, {v}, {by}, 0>"
-    return f"mg::k_smooth3d<{t}, 0, {v}, {by}, {pd}, 0>"
+    return f"mg::k_smooth3d<{t}, 0, {v}, {by}, {pd}, 0, {wv}>"
 
 
 def sweep_blocks(dim: int, n: int, by: int, zchunk: int) -> int:
@@ -148,7 +148,7 @@ def traffic(fetch_db: str, write_db: str, bench_json: str) -> dict:
     FETCH_SIZE and one WRITE_SIZE run (KiB per dispatch), each calibrated on the
     1 GiB copies of the same run.  The tile autotuner launches every candidate
     geometry on the finest level during setup, so the record holds one entry per
-    geometry present in both runs, keyed "by,zchunk,prefetch"."""
+    geometry present in both runs, keyed "by,zchunk,prefetch,waves"."""
     b = _bench_line(bench_json)
     cfg = b["config"]
     dim, n = cfg["dim"], cfg["n"]
@@ -164,10 +164,12 @@ def traffic(fetch_db: str, write_db: str, bench_json: str) -> dict:
         calib_kib = max(copies)
         runs[cname] = (per, calib_kib, COPY_BYTES / (calib_kib * 1024.0))
     configs = {}
-    for by in (8, 16, 32):
+    for by, wv in ((8, 4), (16, 4), (32, 4), (16, 8), (32, 8)):
+        if dim == 2 and wv != 4:
+            continue
         for pd in ((1, 2) if dim == 3 else (1,)):
             for zc in ((4, 8, 16, 32, 64, 128, 256) if dim == 3 else (1,)):
-                kname = sweep_kernel(dim, word, by, pd, var)
+                kname = sweep_kernel(dim, word, by, pd, var, wv)
                 blocks = sweep_blocks(dim, n, by, zc)
                 ent = {"kernel": kname, "blocks": blocks}
                 total = 0.0
@@ -181,16 +183,16 @@ def traffic(fetch_db: str, write_db: str, bench_json: str) -> dict:
                 else:
                     ent["bytes_per_launch"] = total
                     ent["ratio_to_algorithmic"] = total / algo
-                    configs[f"{by},{zc},{pd}"] = ent
+                    configs[f"{by},{zc},{pd},{wv}"] = ent
     if not configs:
         raise SystemExit("no finest-level sweep dispatches found in both runs")
-    by, zc, pd = b["extra"]["fine_tiles"]["smooth"]
+    by, zc, pd, wv = b["extra"]["fine_tiles"]["smooth"]
     return {
         "workload": cfg["workload"],
         "source_hash": kernel_source_hash(),
         "algorithmic_bytes": algo,
         "calibration": {c: {"copy_kib_per_GiB": v[1], "factor": v[2]} for c, v in runs.items()},
-        "bench_tiles": f"{by},{zc},{pd}",
+        "bench_tiles": f"{by},{zc},{pd},{wv}",
         "configs": configs,
     }
 

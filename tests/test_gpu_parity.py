@@ -42,11 +42,12 @@ def same(a, b):
     return a.shape == b.shape and np.array_equal(a, b)
 
 
-def over_row_limit(dim, by, dt, varcoef):
-    """3D sweeps in FP64 or with a coefficient field take tiles of at most 16
-    rows (a 32-row tile would not fit the register file); the library rejects
-    larger ones."""
-    return dim == 3 and by == 32 and (dt == np.float64 or varcoef)
+def over_row_limit(dim, by, dt, varcoef, waves=0):
+    """3D sweeps hold by / waves rows per thread (4 wavefronts by default): at
+    most 4 in FP64 or with a coefficient field, 8 otherwise; the library
+    rejects more (they would not fit the register file)."""
+    rows = by // (waves or 4) if by else 0
+    return dim == 3 and rows > (4 if (dt == np.float64 or varcoef) else 8)
 
 
 def case_arrays(dim, n, dt, varcoef, seed=0):
@@ -57,30 +58,32 @@ def case_arrays(dim, n, dt, varcoef, seed=0):
 
 
 SMOOTH_CASES = [
-    # dim, n, by, zchunk, prefetch
-    (2, 5, 0, 0, 0), (2, 9, 8, 0, 0), (2, 33, 16, 0, 0), (2, 129, 0, 0, 0), (2, 257, 32, 0, 0), (2, 65, 8, 0, 0),
-    (3, 5, 0, 0, 1), (3, 9, 8, 1, 2), (3, 17, 16, 3, 1), (3, 33, 0, 0, 2), (3, 65, 32, 7, 2), (3, 65, 8, 64, 1),
-    (3, 129, 16, 128, 2), (3, 33, 32, 2, 1),
+    # dim, n, by, zchunk, prefetch, waves
+    (2, 5, 0, 0, 0, 0), (2, 9, 8, 0, 0, 0), (2, 33, 16, 0, 0, 0), (2, 129, 0, 0, 0, 0), (2, 257, 32, 0, 0, 0),
+    (2, 65, 8, 0, 0, 0), (3, 5, 0, 0, 1, 0), (3, 9, 8, 1, 2, 0), (3, 17, 16, 3, 1, 0), (3, 33, 0, 0, 2, 0),
+    (3, 65, 32, 7, 2, 0), (3, 65, 8, 64, 1, 0), (3, 129, 16, 128, 2, 0), (3, 33, 32, 2, 1, 0),
+    (3, 33, 16, 3, 1, 8), (3, 65, 32, 7, 2, 8), (3, 129, 32, 16, 1, 8),
 ]
 
 
-@pytest.mark.parametrize("dim,n,by,zc,pd", SMOOTH_CASES)
+@pytest.mark.parametrize("dim,n,by,zc,pd,wv", SMOOTH_CASES)
 @pytest.mark.parametrize("smoother", [RB, JAC])
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 @pytest.mark.parametrize("varcoef", [False, True])
-def test_smooth_sweep_bitwise(dim, n, by, zc, pd, smoother, dt, varcoef, dev_ok):
+def test_smooth_sweep_bitwise(dim, n, by, zc, pd, wv, smoother, dt, varcoef, dev_ok):
     u, f, k = case_arrays(dim, n, dt, varcoef, seed=n)
     omega = 1.0 if smoother == RB else 0.8
     expect = oracle.smooth(u, f, smoother=smoother, omega=omega, k=k)
     ud, fd = dev(u), dev(f)
     out = dev(np.zeros_like(u))
     kd = dev(k) if k is not None else None
-    if over_row_limit(dim, by, dt, varcoef):
+    if over_row_limit(dim, by, dt, varcoef, wv):
         with pytest.raises(mg().MGError) as ei:
-            mg().mg_level_smooth(ud, fd, out, smoother=smoother, omega=omega, k=kd, by=by, zchunk=zc, prefetch=pd)
+            mg().mg_level_smooth(ud, fd, out, smoother=smoother, omega=omega, k=kd, by=by, zchunk=zc, prefetch=pd,
+                                 waves=wv)
         assert ei.value.code == mg().MG_EINVAL
         return
-    mg().mg_level_smooth(ud, fd, out, smoother=smoother, omega=omega, k=kd, by=by, zchunk=zc, prefetch=pd)
+    mg().mg_level_smooth(ud, fd, out, smoother=smoother, omega=omega, k=kd, by=by, zchunk=zc, prefetch=pd, waves=wv)
     assert same(host(out), expect)
 
 
@@ -94,16 +97,17 @@ def test_smooth_zero_guess_bitwise(dim, n, by, zc, pd, dt, dev_ok):
     assert same(host(out), expect)
 
 
-FUSED_CASES = [(2, 9, 0, 0, 0), (2, 65, 0, 0, 0), (2, 257, 0, 0, 0),
-               (3, 5, 0, 0, 0), (3, 9, 8, 1, 1), (3, 17, 16, 3, 2), (3, 33, 8, 5, 1), (3, 33, 32, 2, 2),
-               (3, 65, 32, 7, 2), (3, 65, 0, 0, 0), (3, 129, 16, 13, 1)]
+FUSED_CASES = [(2, 9, 0, 0, 0, 0), (2, 65, 0, 0, 0, 0), (2, 257, 0, 0, 0, 0),
+               (3, 5, 0, 0, 0, 0), (3, 9, 8, 1, 1, 0), (3, 17, 16, 3, 2, 0), (3, 33, 8, 5, 1, 0),
+               (3, 33, 32, 2, 2, 0), (3, 65, 32, 7, 2, 0), (3, 65, 0, 0, 0, 0), (3, 129, 16, 13, 1, 0),
+               (3, 33, 16, 5, 2, 8), (3, 65, 32, 7, 1, 8)]
 
 
-@pytest.mark.parametrize("dim,n,by,zc,pd", FUSED_CASES)
+@pytest.mark.parametrize("dim,n,by,zc,pd,wv", FUSED_CASES)
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 @pytest.mark.parametrize("smoother", [RB, JAC])
 @pytest.mark.parametrize("varcoef", [False, True])
-def test_smooth_with_fused_correction_bitwise(dim, n, by, zc, pd, dt, smoother, varcoef, dev_ok):
+def test_smooth_with_fused_correction_bitwise(dim, n, by, zc, pd, wv, dt, smoother, varcoef, dev_ok):
     """First post-smoothing sweep with the coarse-grid correction added while
     loading: equals interpolation + correction followed by the sweep.  Odd
     z-chunks put the first plane of a chunk on both parities."""
@@ -116,14 +120,14 @@ def test_smooth_with_fused_correction_bitwise(dim, n, by, zc, pd, dt, smoother, 
     expect = oracle.smooth(oracle.prolong_correct(u, ec), f, smoother=smoother, omega=omega, k=k)
     out = dev(np.zeros_like(u))
     kd = dev(k) if varcoef else None
-    if over_row_limit(dim, by, dt, varcoef):
+    if over_row_limit(dim, by, dt, varcoef, wv):
         with pytest.raises(mg().MGError) as ei:
             mg().mg_level_smooth(dev(u), dev(f), out, smoother=smoother, omega=omega, k=kd, ec=dev(ec), by=by,
-                                 zchunk=zc, prefetch=pd)
+                                 zchunk=zc, prefetch=pd, waves=wv)
         assert ei.value.code == mg().MG_EINVAL
         return
     mg().mg_level_smooth(dev(u), dev(f), out, smoother=smoother, omega=omega, k=kd, ec=dev(ec), by=by, zchunk=zc,
-                         prefetch=pd)
+                         prefetch=pd, waves=wv)
     assert same(host(out), expect)
 
 
