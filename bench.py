@@ -420,7 +420,8 @@ def main(argv=None) -> int:
     extra = {"solves_per_s": args.steps / (t1 - t0), "cycles_per_solve": cycles[-1],
              "kernel_source_hash": kernel_source_hash(),
              "fine_tiles": {fam: mg.mg_tile_config(solver.ctx, 0, i) for i, fam in
-                            enumerate(["smooth", "restrict", "norm_or_refinement"])}}
+                            enumerate(["smooth", "restrict", "norm_or_refinement", "smooth_zero_guess",
+                                       "smooth_fused_correction"])}}
     if not args.no_fp64 and w["precision"] == 1:
         s64 = mg.Solver(mg.Params(dim=dim, n=n, precision=mg.PREC_FP64, op=op, k=kd))
         u = us[0]

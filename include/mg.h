@@ -112,7 +112,8 @@ int mg_num_levels(const mg_ctx* ctx);
 
 /* Launch geometry the context uses on 'level' (0 = finest) for kernel 'family'
  * (0 smoothing, 1 residual + restriction, 2 finest-level norm / refinement
- * pass): tile rows *by, z-chunk *zchunk (3D planes per workgroup), for 3D
+ * pass, 3 smoothing from a zero iterate, 4 smoothing with the coarse-grid
+ * correction fused in): tile rows *by, z-chunk *zchunk (3D planes per workgroup), for 3D
  * marching kernels *prefetch = planes of u loaded ahead (1 or 2), and *waves =
  * wavefronts per workgroup (4, or 8 for 3D smoothing); prefetch and waves may
  * be NULL.  These are the autotuner's choices (measured at mg_setup unless the

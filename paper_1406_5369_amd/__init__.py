@@ -206,7 +206,8 @@ def mg_num_levels(ctx: int) -> int:
 
 
 def mg_tile_config(ctx: int, level: int, family: int):
-    """(by, zchunk, prefetch, waves) used on a level by a kernel family (0 smooth, 1 restrict, 2 norm)."""
+    """(by, zchunk, prefetch, waves) used on a level by a kernel family (0 smooth, 1 restrict, 2 norm,
+    3 smooth from a zero iterate, 4 smooth with the fused coarse-grid correction)."""
     by, zc, pd, wv = C.c_int(0), C.c_int(0), C.c_int(0), C.c_int(0)
     _check(lib().mg_tile_config(ctx, level, family, C.byref(by), C.byref(zc), C.byref(pd), C.byref(wv)),
            "mg_tile_config")

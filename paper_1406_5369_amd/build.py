@@ -28,6 +28,7 @@ SOURCES = [
     "mg_solver.hip",
     "mg_capi.hip",
     "mg_batch.hip",
+    "mg_tail.hip",
 ]
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -13,6 +13,7 @@
 // the kernels while the others continue, and per-instance arithmetic is
 // exactly that of a solve of the instance alone.
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cstring>
 #include <deque>
@@ -153,6 +154,10 @@ struct Engine {
     size_t gd_cap = 0;
     IRDesc* d_ir = nullptr;
     size_t ir_cap = 0;
+    TailDesc* d_tail = nullptr;  // one per member: its levels at or below the tail edge
+    size_t tail_cap = 0;
+    std::vector<TailDesc> h_tail;
+    TailPlan tailplan;
     std::vector<GridDesc> h_gd;
     std::vector<IRDesc> h_ir;
     std::vector<Group> groups;  // finest-first over absolute levels
@@ -173,7 +178,7 @@ struct Engine {
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void* p : {(void*)d_done, (void*)d_steps, (void*)d_status, (void*)d_par, (void*)d_nparts,
                         (void*)d_rows, (void*)d_newrows, (void*)d_norm, (void*)d_norm0, (void*)d_partial,
-                        (void*)d_gd, (void*)d_ir})
+                        (void*)d_gd, (void*)d_ir, (void*)d_tail})
             if (p) (void)hipFree(p);
         if (h_ctrl) (void)hipHostFree(h_ctrl);
         if (h_nrm) (void)hipHostFree(h_nrm);
@@ -258,6 +263,8 @@ struct Engine {
         irg_new.clear();
         h_gd.clear();
         h_ir.clear();
+        h_tail.clear();
+        tailplan = TailPlan{};
         if (members.empty()) return MG_OK;
         int amax = 1;
         for (const Inst* I : members) amax = std::max(amax, I->a);
@@ -267,6 +274,20 @@ struct Engine {
             for (const Inst* I : members)
                 if (I->a >= a) h_gd.push_back(level_desc(*I, a));
             goff.push_back({off, h_gd.size() - off});
+        }
+        // coarse tail: every member's levels with edges up to the tail edge, in
+        // one workgroup per member (all batched iterates start at zero)
+        const int a_t = std::getenv("MG_NO_TAIL") ? 0 : log2edge(tail_max_edge(dim, 4));
+        if (a_t >= 1 && a_t <= kMaxTailLevels) {
+            for (const Inst* I : members) {
+                TailDesc t{};
+                const int top = std::min(I->a, a_t);
+                t.nlev = top;
+                for (int j = 0; j < top; ++j) t.lv[j] = level_desc(*I, top - j);
+                h_tail.push_back(t);
+            }
+            tailplan.first = amax - std::min(amax, a_t);
+            tailplan.ninst = (int)h_tail.size();
         }
         std::vector<std::pair<int, std::pair<size_t, size_t>>> ioff, inew;
         for (int pass = 0; pass < 2; ++pass) {
@@ -278,7 +299,17 @@ struct Engine {
                 if (h_ir.size() > off) (pass == 0 ? ioff : inew).push_back({a, {off, h_ir.size() - off}});
             }
         }
-        if (h_gd.size() > gd_cap || h_ir.size() > ir_cap) BCK(hipStreamSynchronize(s));  // old arrays may be in use
+        if (h_gd.size() > gd_cap || h_ir.size() > ir_cap || h_tail.size() > tail_cap)
+            BCK(hipStreamSynchronize(s));  // old arrays may be in use
+        if (h_tail.size() > tail_cap) {
+            if (d_tail) (void)hipFree(d_tail);
+            tail_cap = std::max(h_tail.size(), 2 * tail_cap);
+            BCK(hipMalloc((void**)&d_tail, sizeof(TailDesc) * tail_cap));
+        }
+        if (!h_tail.empty()) {
+            BCK(hipMemcpyAsync(d_tail, h_tail.data(), sizeof(TailDesc) * h_tail.size(), hipMemcpyHostToDevice, s));
+            tailplan.d = d_tail;
+        }
         if (h_gd.size() > gd_cap) {
             if (d_gd) (void)hipFree(d_gd);
             gd_cap = std::max(h_gd.size(), 2 * gd_cap);
@@ -341,7 +372,7 @@ struct Engine {
     // One refinement step of every member: FP32 V-cycle from e = 0, FP64 pass, stop test.
     hipError_t enqueue_step(double tol, int max_steps, hipStream_t q) {
         if (members.empty()) return hipSuccess;
-        hipError_t e = vcycle<float>(prob, groups, true, gtiles, q, nullptr, nullptr, 0);
+        hipError_t e = vcycle<float>(prob, groups, true, gtiles, q, nullptr, nullptr, 0, &tailplan);
         if (e != hipSuccess) return e;
         for (const IRGroup& g : irg) {
             e = launch_ir_update(dim, false, g.d, g.cnt, g.n, 0, 0, d_partial, pstride, tiles[(size_t)g.a].norm, q);

@@ -138,6 +138,22 @@ hipError_t build_groups(std::vector<Group>& G, const Levels& L, const Problem& P
     return hipStreamSynchronize(s);
 }
 
+// Tail descriptor of a single-instance hierarchy: its levels from 'first' on.
+hipError_t build_tail(TailPlan& T, const std::vector<Group>& G, int first, hipStream_t s) {
+    T = TailPlan{};
+    if (first < 0) return hipSuccess;
+    TailDesc h{};
+    h.nlev = (int)G.size() - first;
+    for (int j = 0; j < h.nlev; ++j) h.lv[j] = G[(size_t)(first + j)].h[0];
+    hipError_t e = hipMalloc((void**)&T.d, sizeof(TailDesc));
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(T.d, &h, sizeof(TailDesc), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    T.first = first;
+    T.ninst = 1;
+    return hipStreamSynchronize(s);
+}
+
 void free_groups(std::vector<Group>& G) {
     for (auto& g : G) ffree(g.d);
     G.clear();
@@ -164,6 +180,8 @@ void destroy(mg_ctx* c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     free_groups(c->G64);
     free_groups(c->G32);
+    ffree(c->tail64.d);
+    ffree(c->tail32.d);
     free_levels(c->L64);
     free_levels(c->L32);
     ffree(c->d_ir);
@@ -233,11 +251,11 @@ hipError_t enqueue_steps(mg_ctx* c, int K, double tol, int max_cycles, hipStream
     for (int i = 0; i < K; ++i) {
         hipError_t e;
         if (c->p.precision == MG_PREC_FP64) {
-            e = vcycle<double>(c->prob, c->G64, false, c->tl64, s, pev, pn, pcap);
+            e = vcycle<double>(c->prob, c->G64, false, c->tl64, s, pev, pn, pcap, &c->tail64);
             if (e != hipSuccess) return e;
             e = enqueue_norm(c, s);
         } else {
-            e = vcycle<float>(c->prob, c->G32, true, c->tl32, s, pev, pn, pcap);
+            e = vcycle<float>(c->prob, c->G32, true, c->tl32, s, pev, pn, pcap, &c->tail32);
             if (e != hipSuccess) return e;
             e = enqueue_ir(c, i & 1, 0, s);
         }
@@ -419,6 +437,7 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
         h.f = L.f[(size_t)l] ? L.f[(size_t)l] : scratch_f;
         h.k = L.k[(size_t)l];
         h.fc = L.f[(size_t)l + 1];
+        h.uc = L.u[(size_t)l + 1];
         h.n = n;
         h.c = level_c(n);
         h.wd = level_wd(dim, n, c->p.omega);
@@ -427,16 +446,23 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
         if (e != hipSuccess) break;
         const bool var = c->prob.var;
         const int sm = c->p.smoother;
-        TuneKey ks{dim, L.elem, n, 0, sm, var ? 1 : 0, 0};
         TileCfg cfg;
-        if (!tune_lookup(ks, &cfg)) {
-            cfg = pick_fastest(tune_candidates(dim, n - 2, true, 0, L.elem, var), tl[(size_t)l].smooth, [&](TileCfg t) {
-                return L.elem == 8 ? launch_smooth<double>(dim, sm, var, d, 1, n, 0, 0, t, s)
-                                   : launch_smooth<float>(dim, sm, var, d, 1, n, 0, 0, t, s);
-            }, s);
-            tune_store(ks, cfg);
+        // the three sweep variants (plain, from a zero iterate, with the fused
+        // coarse-grid correction) load different data and are tuned separately
+        const int vflags[3] = {0, SWEEP_ZERO_GUESS, SWEEP_PROLONG};
+        TileCfg* vcfg[3] = {&tl[(size_t)l].smooth, &tl[(size_t)l].smooth_zg, &tl[(size_t)l].smooth_pro};
+        for (int v = 0; v < 3; ++v) {
+            const int fl = vflags[v];
+            TuneKey ks{dim, L.elem, n, 0, sm, var ? 1 : 0, 10 + v};
+            if (!tune_lookup(ks, &cfg)) {
+                cfg = pick_fastest(tune_candidates(dim, n - 2, true, 0, L.elem, var), *vcfg[v], [&](TileCfg t) {
+                    return L.elem == 8 ? launch_smooth<double>(dim, sm, var, d, 1, n, 0, fl, t, s)
+                                       : launch_smooth<float>(dim, sm, var, d, 1, n, 0, fl, t, s);
+                }, s);
+                tune_store(ks, cfg);
+            }
+            *vcfg[v] = cfg;
         }
-        tl[(size_t)l].smooth = cfg;
         TuneKey kr{dim, L.elem, n, 1, 0, var ? 1 : 0, 0};
         if (!tune_lookup(kr, &cfg)) {
             std::vector<TileCfg> cands;
@@ -587,6 +613,7 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
     if (p->precision == MG_PREC_FP64) {
         SETUP_CK(build_levels(c->L64, dim, c->n, 8, false, c->k64, s));
         SETUP_CK(build_groups(c->G64, c->L64, c->prob, ctl_done(c), s));
+        SETUP_CK(build_tail(c->tail64, c->G64, tail_first_level(dim, 8, c->n, false), s));
     } else {
         SETUP_CK(build_levels(c->L32, dim, c->n, 4, true, nullptr, s));
         if (c->prob.var) {
@@ -603,6 +630,7 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
             c->L32.own_k0 = true;
         }
         SETUP_CK(build_groups(c->G32, c->L32, c->prob, ctl_done(c), s));
+        SETUP_CK(build_tail(c->tail32, c->G32, tail_first_level(dim, 4, c->n, true), s));
         SETUP_CK(zalloc((void**)&c->u64_scratch, N * sizeof(double), s));
         c->h_ir = IRDesc{};
         c->h_ir.u[0] = nullptr;
@@ -654,10 +682,15 @@ void mg_destroy(mg_ctx* c) {
 int mg_num_levels(const mg_ctx* c) { return c && !is_batch_handle(c) ? c->nlev : MG_EINVAL; }
 
 int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch, int* waves) {
-    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 2)
+    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 4)
         return MG_EINVAL;
     const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
-    TileCfg t = family == 0 ? tl[(size_t)level].smooth : (family == 1 ? tl[(size_t)level].restr : c->top.norm);
+    const Tiles& tv = tl[(size_t)level];
+    const TileCfg t = family == 0   ? tv.smooth
+                      : family == 1 ? tv.restr
+                      : family == 2 ? c->top.norm
+                      : family == 3 ? tv.smooth_zg
+                                    : tv.smooth_pro;
     if (family == 2 && level != 0) return MG_EINVAL;
     *by = t.by;
     *zchunk = t.zchunk;
@@ -673,10 +706,10 @@ int mg_vcycle(mg_ctx* c, double* u, const double* f) {
     if (r != MG_OK) return r;
     CK(launch_fill_int(ctl_done(c), 0, 1, c->stream));
     if (c->p.precision == MG_PREC_FP64) {
-        CK(vcycle<double>(c->prob, c->G64, false, c->tl64, c->stream, nullptr, nullptr, 0));
+        CK(vcycle<double>(c->prob, c->G64, false, c->tl64, c->stream, nullptr, nullptr, 0, &c->tail64));
     } else {
         CK(enqueue_ir(c, 0, IR_NO_UPDATE, c->stream));
-        CK(vcycle<float>(c->prob, c->G32, true, c->tl32, c->stream, nullptr, nullptr, 0));
+        CK(vcycle<float>(c->prob, c->G32, true, c->tl32, c->stream, nullptr, nullptr, 0, &c->tail32));
         CK(enqueue_ir(c, 0, 0, c->stream));
         CK(hipMemcpyAsync(u, c->u64_scratch, npts(c->p.dim, c->p.n) * sizeof(double), hipMemcpyDeviceToDevice,
                           c->stream));

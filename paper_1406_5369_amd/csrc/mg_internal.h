@@ -71,6 +71,14 @@ struct IRDesc {
     double c;
 };
 
+// Coarse tail of a V-cycle for one instance: its levels from the tail's finest
+// (lv[0], edge at most tail_max_edge) down to n = 3, run by one workgroup.
+constexpr int kMaxTailLevels = 6;
+struct TailDesc {
+    GridDesc lv[kMaxTailLevels];
+    int nlev;
+};
+
 // Launch geometry of one kernel family (picked by the autotuner).
 struct TileCfg {
     int by;      // LDS box rows (2D) / rows of the x-y box (3D): 8, 16 or 32
@@ -101,6 +109,11 @@ hipError_t launch_restrict(int dim, bool var, const GridDesc* d, int ninst, int 
                            hipStream_t s);
 template <typename T>
 hipError_t launch_prolong(int dim, const GridDesc* d, int ninst, int nf, int sel, hipStream_t s);
+// Largest tail edge for a dimension and word size (levels at or below it can
+// run in the single-workgroup tail kernel).
+int tail_max_edge(int dim, int elem);
+template <typename T>
+hipError_t launch_tail(int dim, int sm, bool var, const TailDesc* d, int ninst, int nu1, int nu2, hipStream_t s);
 template <typename T>
 hipError_t launch_coarsest(int dim, bool var, const GridDesc* d, int ninst, hipStream_t s);
 template <typename T>

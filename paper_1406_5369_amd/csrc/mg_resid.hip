@@ -332,14 +332,28 @@ __global__ __launch_bounds__(NT) void k_ir3d(const IRDesc* __restrict__ descs, i
     resid3d_body<VAR, BY, PD, true>(nullptr, d, sel, FL, part, pstride, zchunk);
 }
 
+// Sum of np partials by one workgroup in a fixed order: thread t takes
+// elements t, t + NT, t + 2 NT, ... into eight interleaved accumulators (eight
+// loads in flight per thread), combined pairwise, then the fixed-order
+// workgroup sum.  Result valid in thread 0.
+__device__ __forceinline__ double sum_parts(const double* __restrict__ p, int np, double* red4) {
+    const MG_GLOBAL double* __restrict__ q = gp(p);
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int i = threadIdx.x;
+    for (; i + 7 * NT < np; i += 8 * NT) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] += q[i + j * NT];
+    }
+    for (int j = 0; i < np; i += NT, ++j) a[j] += q[i];  // at most seven more
+    const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    return block_sum(s, red4);
+}
+
 __global__ __launch_bounds__(NT) void k_norm_finalize(const double* __restrict__ part, int pstride, int nparts,
                                                       int row0, double* __restrict__ norm) {
     __shared__ double red4[4];
     const int row = row0 + blockIdx.x;
-    const double* p = part + (size_t)row * pstride;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += NT) s += p[i];
-    const double t = block_sum(s, red4);
+    const double t = sum_parts(part + (size_t)row * pstride, nparts, red4);
     if (threadIdx.x == 0) norm[row] = sqrt(t);
 }
 
@@ -348,11 +362,7 @@ __global__ __launch_bounds__(NT) void k_norm_finalize_rows(const double* __restr
                                                            const int* __restrict__ rows, double* __restrict__ norm) {
     __shared__ double red4[4];
     const int row = rows[blockIdx.x];
-    const double* p = part + (size_t)row * pstride;
-    const int np = nparts[row];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += NT) s += p[i];
-    const double t = block_sum(s, red4);
+    const double t = sum_parts(part + (size_t)row * pstride, nparts[row], red4);
     if (threadIdx.x == 0) norm[row] = sqrt(t);
 }
 

@@ -15,9 +15,14 @@ namespace mg {
 
 // Launch geometry of every kernel family of one hierarchy.
 struct Tiles {
-    TileCfg smooth{16, 128};
+    TileCfg smooth{16, 128};      // plain sweep
+    TileCfg smooth_zg{16, 128};   // sweep from a zero iterate (first presmoothing sweep on coarse grids)
+    TileCfg smooth_pro{16, 128};  // sweep with the coarse-grid correction fused in (first postsmoothing sweep)
     TileCfg restr{16, 64};
     TileCfg norm{16, 128};
+    const TileCfg& sweep(int flags) const {
+        return (flags & SWEEP_ZERO_GUESS) ? smooth_zg : ((flags & SWEEP_PROLONG) ? smooth_pro : smooth);
+    }
 };
 
 // Heuristic launch geometry for one level (used when autotuning is off and
@@ -50,11 +55,24 @@ struct Problem {
     bool var;
 };
 
+// Coarse levels of a V-cycle run by the single-workgroup tail kernel:
+// groups[first..L-1], one TailDesc per instance (first = -1: no tail).
+struct TailPlan {
+    int first = -1;
+    int ninst = 0;
+    TailDesc* d = nullptr;  // device [ninst]
+};
+
+// First level of a hierarchy (edges n[0] > n[1] > ... > 3) that the tail kernel
+// takes, or -1: the largest level with an edge up to tail_max_edge, not the
+// top level unless its iterate starts at zero.  MG_NO_TAIL disables the tail.
+int tail_first_level(int dim, int elem, const std::vector<int>& n, bool zero_top);
+
 // V-cycle over groups[0..L-1] (groups[l] holds every instance's level l);
 // zero_top: the iterate at level 0 is known to be zero.  Works in precision T.
 template <typename T>
 hipError_t vcycle(const Problem& P, const std::vector<Group>& groups, bool zero_top, const std::vector<Tiles>& tiles,
-                  hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap);
+                  hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap, const TailPlan* tail = nullptr);
 
 size_t npts(int dim, int n);
 int count_levels(int n);
@@ -80,9 +98,11 @@ struct mg_ctx {
     // FP64 hierarchy (precision FP64): level 0 u/f are the caller's.
     mg::Levels L64;
     std::vector<mg::Group> G64;
+    mg::TailPlan tail64;
     // FP32 hierarchy (precision FP32_IR): all levels owned; level-0 u = e, f = r32.
     mg::Levels L32;
     std::vector<mg::Group> G32;
+    mg::TailPlan tail32;
     // FP64 refinement state
     mg::IRDesc* d_ir = nullptr;
     mg::IRDesc h_ir{};

@@ -1,6 +1,7 @@
 // Solver core: the V-cycle driver of Algorithm 1 over groups of equal-size
 // grids, default launch geometry, and helper kernels for hierarchy setup.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "mg_solver.h"
@@ -33,13 +34,13 @@ Tiles default_tiles(int dim, int elem_bytes, int n, int smoother) {
     const int target = 2048;
     if (dim == 2) {
         const int by = n >= 257 ? 32 : (n >= 65 ? 16 : 8);
-        t.smooth = {by, 1};
+        t.smooth = t.smooth_zg = t.smooth_pro = {by, 1};
         t.restr = {by < 16 ? 16 : by, 1};
         t.norm = {by, 1};
         return t;
     }
     const int by = n >= 129 ? 16 : 8;
-    t.smooth = {by, heuristic_zchunk(3, n, by, H, target)};
+    t.smooth = t.smooth_zg = t.smooth_pro = {by, heuristic_zchunk(3, n, by, H, target)};
     const int nc = (n - 1) / 2 + 1;
     const int rb = 16;
     // restriction tiles: 30 x ((rb-3)/2) coarse nodes per z-chunk of coarse planes
@@ -95,16 +96,27 @@ struct Prof {
         if (e_ != hipSuccess) return e_;   \
     } while (0)
 
+int tail_first_level(int dim, int elem, const std::vector<int>& n, bool zero_top) {
+    if (std::getenv("MG_NO_TAIL")) return -1;
+    const int tmax = tail_max_edge(dim, elem);
+    for (int l = zero_top ? 0 : 1; l < (int)n.size(); ++l)
+        if (n[(size_t)l] <= tmax && (int)n.size() - l <= kMaxTailLevels) return l;
+    return -1;
+}
+
 template <typename T>
 hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, const std::vector<Tiles>& tiles,
-                  hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap) {
+                  hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap, const TailPlan* tail) {
     const int L = (int)G.size();
     const int dim = P.dim;
     Prof prof{prof_ev, prof_n, prof_cap, s};
-    if (L == 1) return launch_coarsest<T>(dim, P.var, G[0].d, G[0].ninst, s);
+    const bool use_tail = tail && tail->first >= 0 && tail->first < L && tail->d;
+    // levels [0, stop) run level by level; the rest is the tail (or the coarsest solve)
+    const int stop = use_tail ? tail->first : L - 1;
+    if (stop == 0 && !use_tail) return launch_coarsest<T>(dim, P.var, G[0].d, G[0].ninst, s);
     std::vector<int> sel((size_t)L, 0);
     // descending leg: presmoothing, residual, restriction (Algorithm 1)
-    for (int l = 0; l + 1 < L; ++l) {
+    for (int l = 0; l < stop; ++l) {
         const Group& g = G[(size_t)l];
         const bool zero = l == 0 ? zero_top : true;
         int cur = 0;
@@ -112,8 +124,8 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
             const int flags = (i == 0 && zero) ? SWEEP_ZERO_GUESS : 0;
             const bool timed = l == 0 && flags == 0;  // plain finest-level sweeps only
             if (timed) prof.begin();
-            MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags, tiles[(size_t)l].smooth,
-                                    s));
+            MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags,
+                                    tiles[(size_t)l].sweep(flags), s));
             if (timed) prof.end();
             cur ^= 1;
         }
@@ -121,10 +133,15 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
         MG_TRY(launch_restrict<T>(dim, P.var, g.d, g.ninst, g.n, cur, tiles[(size_t)l].restr, s));
         sel[(size_t)l] = cur;
     }
-    // coarsest grid: exact solve from the zero guess
-    MG_TRY(launch_coarsest<T>(dim, P.var, G[(size_t)L - 1].d, G[(size_t)L - 1].ninst, s));
+    if (use_tail) {
+        // every level from 'stop' to the coarsest in one launch, from a zero guess
+        MG_TRY(launch_tail<T>(dim, P.smoother, P.var, tail->d, tail->ninst, P.nu1, P.nu2, s));
+    } else {
+        // coarsest grid: exact solve from the zero guess
+        MG_TRY(launch_coarsest<T>(dim, P.var, G[(size_t)L - 1].d, G[(size_t)L - 1].ninst, s));
+    }
     // ascending leg: interpolation + correction, postsmoothing
-    for (int l = L - 2; l >= 0; --l) {
+    for (int l = stop - 1; l >= 0; --l) {
         const Group& g = G[(size_t)l];
         int cur = sel[(size_t)l];
         const bool fuse = P.nu2 > 0;  // the first post-sweep adds P uc while loading
@@ -133,8 +150,8 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
             const int flags = (i == 0 && fuse) ? SWEEP_PROLONG : 0;
             const bool timed = l == 0 && flags == 0;
             if (timed) prof.begin();
-            MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags, tiles[(size_t)l].smooth,
-                                    s));
+            MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags,
+                                    tiles[(size_t)l].sweep(flags), s));
             if (timed) prof.end();
             cur ^= 1;
         }
@@ -144,8 +161,8 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
 }
 
 template hipError_t vcycle<double>(const Problem&, const std::vector<Group>&, bool, const std::vector<Tiles>&,
-                                   hipStream_t, hipEvent_t*, int*, int);
+                                   hipStream_t, hipEvent_t*, int*, int, const TailPlan*);
 template hipError_t vcycle<float>(const Problem&, const std::vector<Group>&, bool, const std::vector<Tiles>&,
-                                  hipStream_t, hipEvent_t*, int*, int);
+                                  hipStream_t, hipEvent_t*, int*, int, const TailPlan*);
 
 }  // namespace mg

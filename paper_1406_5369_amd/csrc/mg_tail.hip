@@ -1,0 +1,300 @@
+// Coarse tail of the V-cycle in one launch: every level from a small grid down
+// to the coarsest, one workgroup per instance, all fields in LDS.
+//
+// Below a few thousand nodes a level is far too small to fill the chip, and
+// the six launches a level costs per cycle (two pre-sweeps, residual and
+// restriction, correction, two post-sweeps) are pure launch latency.  Here the
+// whole descending and ascending leg of Algorithm 1 below the tail's finest
+// level runs inside one workgroup with barriers between the steps.  The per-
+// point arithmetic is the same as in the level kernels (same helpers, same
+// operation order), so results are bitwise those of the level-by-level path:
+//   * the coarse iterate starts at zero (Algorithm 1), then nu1 sweeps;
+//   * RBGS relaxes all red nodes, then all black nodes, in place (a colour's
+//     updates read only the other colour); Jacobi relaxes out of place;
+//   * r = f - A u on inner nodes, full weighting onto the coarse inner nodes;
+//   * the coarsest grid (n = 3) is solved exactly, u = f / diag;
+//   * u += P u_coarse on inner nodes, then nu2 sweeps;
+//   * the tail's finest iterate is written back to its level's u.
+#include "mg_kern.h"
+
+namespace mg {
+namespace {
+
+constexpr int TNT = 1024;  // threads per tail workgroup
+
+// Nodes of all levels from edge N down to 3.
+__host__ __device__ constexpr int tail_nodes(int dim, int N) {
+    int s = 0;
+    for (int m = N;; m = (m - 1) / 2 + 1) {
+        s += dim == 2 ? m * m : m * m * m;
+        if (m == 3) break;
+    }
+    return s;
+}
+
+// One level of the tail inside the workgroup's LDS arrays: its nodes start at
+// 'off' in each array (iterate U, right-hand side F, work W, coefficient K).
+template <typename T>
+struct Lvl {
+    int off, n;
+    T c, wd, om;
+};
+
+template <typename T, int DIM, bool VAR>
+__device__ __forceinline__ T tail_res(const T* u, const T* f, const T* k, int n, T c, int p, T& ds) {
+    const int sy = n, sz = n * n;
+    if constexpr (DIM == 2) {
+        if constexpr (VAR) {
+            return res_var2(u[p], u[p - 1], u[p + 1], u[p - sy], u[p + sy], k[p], k[p - 1], k[p + 1], k[p - sy],
+                            k[p + sy], f[p], c, ds);
+        } else {
+            ds = T(0);
+            return res_lap2(u[p], u[p - 1], u[p + 1], u[p - sy], u[p + sy], f[p], c);
+        }
+    } else {
+        if constexpr (VAR) {
+            return res_var3(u[p], u[p - 1], u[p + 1], u[p - sy], u[p + sy], u[p - sz], u[p + sz], k[p], k[p - 1],
+                            k[p + 1], k[p - sy], k[p + sy], k[p - sz], k[p + sz], f[p], c, ds);
+        } else {
+            ds = T(0);
+            return res_lap3(u[p], u[p - 1], u[p + 1], u[p - sy], u[p + sy], u[p - sz], u[p + sz], f[p], c);
+        }
+    }
+}
+
+// Inner node q (0-based over the (n-2)^dim inner nodes) -> node index and
+// colour (i + j [+ k]) mod 2.
+template <int DIM>
+__device__ __forceinline__ int tail_node(int q, int n, int& colour) {
+    const int m = n - 2;
+    const int i = 1 + q % m;
+    const int r = q / m;
+    const int j = 1 + (DIM == 2 ? r : r % m);
+    const int k = DIM == 2 ? 0 : 1 + r / m;
+    colour = (i + j + k) & 1;
+    return (k * n + j) * n + i;
+}
+
+template <int DIM>
+__device__ __forceinline__ int tail_inner(int n) {
+    return DIM == 2 ? (n - 2) * (n - 2) : (n - 2) * (n - 2) * (n - 2);
+}
+
+// One smoothing sweep of a level (arrays already offset to the level).
+template <typename T, int DIM, int SM, bool VAR>
+__device__ void tail_sweep(T* u, const T* f, T* w, const T* k, const Lvl<T>& L) {
+    const int cnt = tail_inner<DIM>(L.n);
+    if constexpr (SM == SM_RBGS) {
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int q = threadIdx.x; q < cnt; q += TNT) {
+                int cl;
+                const int p = tail_node<DIM>(q, L.n, cl);
+                if (cl != colour) continue;
+                T ds;
+                const T r = tail_res<T, DIM, VAR>(u, f, k, L.n, L.c, p, ds);
+                u[p] = relax<T, VAR>(u[p], r, ds, L.c, L.wd, L.om);
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int q = threadIdx.x; q < cnt; q += TNT) {
+            int cl;
+            const int p = tail_node<DIM>(q, L.n, cl);
+            T ds;
+            const T r = tail_res<T, DIM, VAR>(u, f, k, L.n, L.c, p, ds);
+            w[p] = relax<T, VAR>(u[p], r, ds, L.c, L.wd, L.om);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt; q += TNT) {
+            int cl;
+            const int p = tail_node<DIM>(q, L.n, cl);
+            u[p] = w[p];
+        }
+        __syncthreads();
+    }
+}
+
+// Full weighting of the residual array R (edge nf) around fine node fp; same
+// operation order as the restriction kernel.
+template <typename T, int DIM>
+__device__ __forceinline__ T tail_fw(const T* R, int nf, int fp) {
+    const int sy = nf, sz = nf * nf;
+    if constexpr (DIM == 2) {
+        const T edges = (R[fp - 1] + R[fp + 1]) + (R[fp - sy] + R[fp + sy]);
+        const T corners = (R[fp - sy - 1] + R[fp - sy + 1]) + (R[fp + sy - 1] + R[fp + sy + 1]);
+        return (T(0.25) * R[fp] + T(0.125) * edges) + T(0.0625) * corners;
+    } else {
+        const T* Rb = R - sz;
+        const T* Ra = R + sz;
+        const T faces = ((R[fp - 1] + R[fp + 1]) + (R[fp - sy] + R[fp + sy])) + (Rb[fp] + Ra[fp]);
+        const T exy = (R[fp - sy - 1] + R[fp - sy + 1]) + (R[fp + sy - 1] + R[fp + sy + 1]);
+        const T exz = (Rb[fp - 1] + Rb[fp + 1]) + (Ra[fp - 1] + Ra[fp + 1]);
+        const T eyz = (Rb[fp - sy] + Rb[fp + sy]) + (Ra[fp - sy] + Ra[fp + sy]);
+        const T edges = (exy + exz) + eyz;
+        const T cz0 = (Rb[fp - sy - 1] + Rb[fp - sy + 1]) + (Rb[fp + sy - 1] + Rb[fp + sy + 1]);
+        const T cz1 = (Ra[fp - sy - 1] + Ra[fp - sy + 1]) + (Ra[fp + sy - 1] + Ra[fp + sy + 1]);
+        const T corners = cz0 + cz1;
+        return ((T(0.125) * R[fp] + T(0.0625) * faces) + T(0.03125) * edges) + T(0.015625) * corners;
+    }
+}
+
+template <typename T, int DIM, int SM, bool VAR, int NMAX>
+__global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs, int nu1, int nu2) {
+    constexpr int TOT = tail_nodes(DIM, NMAX);
+    __shared__ T Us[TOT];
+    __shared__ T Fs[TOT];
+    __shared__ T Ws[TOT];
+    __shared__ T Ks[VAR ? TOT : 1];
+    __shared__ Lvl<T> L[kMaxTailLevels];
+    __shared__ int s_tot;
+    const TailDesc& td = descs[blockIdx.x];
+    const int nl = td.nlev;
+    const int* done = td.lv[0].done;
+    if (done && *gp(done)) return;
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int j = 0; j < nl; ++j) {
+            const GridDesc& g = td.lv[j];
+            L[j].off = off;
+            L[j].n = g.n;
+            L[j].c = (T)g.c;
+            L[j].wd = (T)g.wd;
+            L[j].om = (T)g.omega;
+            off += DIM == 2 ? g.n * g.n : g.n * g.n * g.n;
+        }
+        s_tot = off;
+    }
+    __syncthreads();
+    const int tot = s_tot;
+    // every iterate starts at zero; f of the tail's finest level and the
+    // coefficients of all levels come from device memory
+    const int n0 = td.lv[0].n;
+    const int np0 = DIM == 2 ? n0 * n0 : n0 * n0 * n0;
+    const MG_GLOBAL T* __restrict__ f0 = gp((const T*)td.lv[0].f);
+    for (int p = threadIdx.x; p < tot; p += TNT) {
+        Us[p] = T(0);
+        Ws[p] = T(0);
+        Fs[p] = p < np0 ? f0[p] : T(0);
+    }
+    if constexpr (VAR) {
+        for (int j = 0; j < nl; ++j) {
+            const MG_GLOBAL T* __restrict__ kg = gp((const T*)td.lv[j].k);
+            const int n = L[j].n, np = DIM == 2 ? n * n : n * n * n;
+            for (int p = threadIdx.x; p < np; p += TNT) Ks[L[j].off + p] = kg[p];
+        }
+    }
+    __syncthreads();
+
+    // descending leg
+    for (int j = 0; j + 1 < nl; ++j) {
+        const Lvl<T> lv = L[j];
+        T* u = Us + lv.off;
+        T* w = Ws + lv.off;
+        const T* f = Fs + lv.off;
+        const T* k = Ks + (VAR ? lv.off : 0);
+        for (int s = 0; s < nu1; ++s) tail_sweep<T, DIM, SM, VAR>(u, f, w, k, lv);
+        const int cnt = tail_inner<DIM>(lv.n);
+        for (int q = threadIdx.x; q < cnt; q += TNT) {
+            int cl;
+            const int p = tail_node<DIM>(q, lv.n, cl);
+            T ds;
+            w[p] = tail_res<T, DIM, VAR>(u, f, k, lv.n, lv.c, p, ds);
+        }
+        __syncthreads();
+        const int nf = lv.n, nc = L[j + 1].n;
+        T* fc = Fs + L[j + 1].off;
+        const int cc = tail_inner<DIM>(nc);
+        for (int q = threadIdx.x; q < cc; q += TNT) {
+            int cl;
+            const int P = tail_node<DIM>(q, nc, cl);
+            const int I = P % nc, J = (P / nc) % nc, K = DIM == 2 ? 0 : P / (nc * nc);
+            fc[P] = tail_fw<T, DIM>(w, nf, ((2 * K) * nf + 2 * J) * nf + 2 * I);
+        }
+        __syncthreads();
+    }
+    // coarsest grid: one unknown, u = f / diag
+    if (threadIdx.x == 0) {
+        const Lvl<T> lv = L[nl - 1];
+        const int p = DIM == 2 ? 4 : 13;
+        T diag;
+        if constexpr (VAR) {
+            const T* k = Ks + lv.off;
+            const T kC = k[p];
+            const T kxW = kface(k[p - 1], kC), kxC = kface(kC, k[p + 1]);
+            const T kyS = kface(k[p - 3], kC), kyC = kface(kC, k[p + 3]);
+            T dsum;
+            if constexpr (DIM == 2) {
+                dsum = (kxW + kxC) + (kyS + kyC);
+            } else {
+                const T kzB = kface(k[p - 9], kC), kzC = kface(kC, k[p + 9]);
+                dsum = ((kxW + kxC) + (kyS + kyC)) + (kzB + kzC);
+            }
+            diag = lv.c * dsum;
+        } else {
+            diag = lv.c * (DIM == 2 ? T(4) : T(6));
+        }
+        Us[lv.off + p] = Fs[lv.off + p] / diag;
+    }
+    __syncthreads();
+    // ascending leg
+    for (int j = nl - 2; j >= 0; --j) {
+        const Lvl<T> lv = L[j];
+        T* u = Us + lv.off;
+        T* w = Ws + lv.off;
+        const T* f = Fs + lv.off;
+        const T* k = Ks + (VAR ? lv.off : 0);
+        const T* uc = Us + L[j + 1].off;
+        const int nc = L[j + 1].n, n = lv.n;
+        const int cnt = tail_inner<DIM>(n);
+        for (int q = threadIdx.x; q < cnt; q += TNT) {
+            int cl;
+            const int p = tail_node<DIM>(q, n, cl);
+            const int i = p % n, jj = (p / n) % n, kk = DIM == 2 ? 0 : p / (n * n);
+            const T corr = DIM == 2 ? interp2<T>(uc, nc, i, jj) : interp3<T>(uc, nc, i, jj, kk);
+            u[p] = u[p] + corr;
+        }
+        __syncthreads();
+        for (int s = 0; s < nu2; ++s) tail_sweep<T, DIM, SM, VAR>(u, f, w, k, lv);
+    }
+    // the tail's finest iterate back to device memory (inner nodes; its
+    // boundary there is zero already)
+    MG_GLOBAL T* __restrict__ u0 = gp((T*)td.lv[0].u);
+    const int cnt = tail_inner<DIM>(n0);
+    for (int q = threadIdx.x; q < cnt; q += TNT) {
+        int cl;
+        const int p = tail_node<DIM>(q, n0, cl);
+        u0[p] = Us[p];
+    }
+}
+
+}  // namespace
+
+int tail_max_edge(int dim, int elem) {
+    if (dim == 2) return elem == 4 ? 65 : 33;
+    return elem == 4 ? 17 : 9;
+}
+
+template <typename T>
+hipError_t launch_tail(int dim, int sm, bool var, const TailDesc* d, int ninst, int nu1, int nu2, hipStream_t s) {
+    if (ninst <= 0) return hipSuccess;
+    constexpr bool F = sizeof(T) == 4;
+#define MG_TAIL(DIMV, NMAXV)                                                                                     \
+    do {                                                                                                      \
+        if (sm == SM_RBGS) {                                                                                  \
+            if (var) k_tail<T, DIMV, SM_RBGS, true, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2);               \
+            else k_tail<T, DIMV, SM_RBGS, false, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2);                  \
+        } else {                                                                                              \
+            if (var) k_tail<T, DIMV, SM_JACOBI, true, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2);             \
+            else k_tail<T, DIMV, SM_JACOBI, false, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2);                \
+        }                                                                                                     \
+    } while (0)
+    if (dim == 2) MG_TAIL(2, (F ? 65 : 33));
+    else MG_TAIL(3, (F ? 17 : 9));
+#undef MG_TAIL
+    return hipGetLastError();
+}
+
+template hipError_t launch_tail<double>(int, int, bool, const TailDesc*, int, int, int, hipStream_t);
+template hipError_t launch_tail<float>(int, int, bool, const TailDesc*, int, int, int, hipStream_t);
+
+}  // namespace mg

@@ -72,12 +72,14 @@ def short_name(name: str) -> str:
     return name.replace("void ", "")
 
 
-def load(path: str):
+def load(path: str, from_kernel: str | None = None):
+    """Dispatches in start order; with from_kernel, only those from the first
+    dispatch whose name contains it (e.g. the first solve after setup)."""
     rows = []
     if path.endswith(".db"):
         con = sqlite3.connect(path)
         cur = con.cursor()
-        q = "select name, duration, grid_x, grid_y, grid_z, workgroup_x from kernels"
+        q = "select name, duration, grid_x, grid_y, grid_z, workgroup_x from kernels order by start"
         for name, dur, gx, gy, gz, wx in cur.execute(q):
             rows.append((short_name(name), float(dur), int(gx), int(gy), int(gz), int(wx)))
     else:
@@ -86,6 +88,9 @@ def load(path: str):
                 dur = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
                 rows.append((short_name(r["Kernel_Name"]), dur, int(r["Grid_Size_X"]), int(r["Grid_Size_Y"]),
                              int(r["Grid_Size_Z"]), int(r["Workgroup_Size_X"])))
+    if from_kernel:
+        first = next((i for i, r in enumerate(rows) if from_kernel in r[0]), len(rows))
+        rows = rows[first:]
     return rows
 
 
@@ -202,6 +207,7 @@ def main(argv=None) -> int:
     ap.add_argument("trace", nargs="+")
     ap.add_argument("--top", type=int, default=40)
     ap.add_argument("--match", default=None)
+    ap.add_argument("--from-kernel", default=None, help="skip dispatches before the first one of this kernel")
     ap.add_argument("--counters", action="store_true", help="per-dispatch counter averages (--pmc runs)")
     ap.add_argument("--traffic", action="store_true", help="FETCH.db WRITE.db -> bytes per launch")
     ap.add_argument("--bench", help="benchmark output (JSON line) of the counter runs")
@@ -228,7 +234,7 @@ def main(argv=None) -> int:
         for d in counters(a.trace, a.match):
             print(f"{d['counter']:>12} {d['avg']:16.1f} {d['dispatches']:5d} {d['blocks_x']:7d}  {d['kernel']}")
         return 0
-    res = summarize(load(a.trace), a.match)
+    res = summarize(load(a.trace, a.from_kernel), a.match)
     print(f"{'pct':>6} {'total_ms':>10} {'calls':>6} {'avg_us':>10} {'blocks':>7} {'gy':>4}  kernel")
     for d in res[: a.top]:
         print(f"{d['pct']:6.2f} {d['total_ms']:10.3f} {d['calls']:6d} {d['avg_us']:10.2f} {d['blocks_x']:7d} "

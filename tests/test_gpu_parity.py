@@ -335,3 +335,28 @@ def test_solve_independent_of_launch_geometry(dim, n, precision, dev_ok, monkeyp
     assert st0 == st1 == 0 and c0 == c1
     assert same(u0, u1)
     np.testing.assert_allclose(h0, h1, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("dim,n,precision,varcoef,smoother", [(2, 129, 1, False, RB), (2, 65, 1, False, RB),
+                                                              (2, 257, 0, True, RB), (3, 65, 1, False, RB),
+                                                              (3, 33, 0, True, JAC), (3, 17, 1, False, JAC),
+                                                              (2, 33, 0, False, JAC), (3, 129, 0, False, RB)])
+def test_coarse_tail_kernel_equals_level_by_level(dim, n, precision, varcoef, smoother, dev_ok, monkeypatch):
+    """The coarse levels run by the single-workgroup tail kernel give the same
+    bits as running them level by level (and both equal the oracle)."""
+    f = inputs.uniform_rhs(dim, n, 63)
+    k = inputs.varcoef_k(n, 64, dim=dim) if varcoef else None
+    monkeypatch.setenv("MG_NO_TAIL", "1")
+    st0, c0, h0, u0 = run_solve(dim, n, f, k=k, smoother=smoother, precision=precision, tol=1e-9, max_cycles=30)
+    monkeypatch.delenv("MG_NO_TAIL")
+    st1, c1, h1, u1 = run_solve(dim, n, f, k=k, smoother=smoother, precision=precision, tol=1e-9, max_cycles=30)
+    assert st0 == st1 == 0 and c0 == c1
+    assert same(u0, u1)
+    np.testing.assert_allclose(h0, h1, rtol=1e-13, atol=0)
+    omega = 1.0 if smoother == RB else 0.8
+    if precision == 0:
+        u_exp, _, _ = oracle.solve(np.zeros_like(f), f, tol=1e-9, max_cycles=30, smoother=smoother, omega=omega, k=k)
+    else:
+        u_exp, _, _ = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-9, max_cycles=30, smoother=smoother,
+                                          omega=omega, k=k)
+    assert same(u1, u_exp)
