@@ -43,7 +43,7 @@ def same(a, b):
 
 
 def over_row_limit(dim, by, dt, varcoef, waves=0):
-    """3D sweeps hold by / waves rows per thread (4 wavefronts by default): at
+    """3D sweeps hold by / waves rows per thread (4 wavefronts unless given): at
     most 4 in FP64 or with a coefficient field, 8 otherwise; the library
     rejects more (they would not fit the register file)."""
     rows = by // (waves or 4) if by else 0
@@ -58,11 +58,11 @@ def case_arrays(dim, n, dt, varcoef, seed=0):
 
 
 SMOOTH_CASES = [
-    # dim, n, by, zchunk, prefetch, waves
+    # dim, n, by, zchunk, prefetch, waves (0: library default); 3D boxes are 128 nodes wide
     (2, 5, 0, 0, 0, 0), (2, 9, 8, 0, 0, 0), (2, 33, 16, 0, 0, 0), (2, 129, 0, 0, 0, 0), (2, 257, 32, 0, 0, 0),
-    (2, 65, 8, 0, 0, 0), (3, 5, 0, 0, 1, 0), (3, 9, 8, 1, 2, 0), (3, 17, 16, 3, 1, 0), (3, 33, 0, 0, 2, 0),
-    (3, 65, 32, 7, 2, 0), (3, 65, 8, 64, 1, 0), (3, 129, 16, 128, 2, 0), (3, 33, 32, 2, 1, 0),
-    (3, 33, 16, 3, 1, 8), (3, 65, 32, 7, 2, 8), (3, 129, 32, 16, 1, 8),
+    (2, 65, 8, 0, 0, 0), (3, 5, 0, 0, 1, 0), (3, 9, 8, 1, 2, 0), (3, 17, 16, 3, 1, 8), (3, 17, 16, 3, 1, 0),
+    (3, 33, 0, 0, 2, 0), (3, 65, 32, 7, 2, 8), (3, 65, 8, 64, 1, 0), (3, 129, 16, 128, 2, 8), (3, 33, 32, 2, 1, 0),
+    (3, 33, 16, 5, 2, 4), (3, 129, 32, 16, 1, 8), (3, 257, 16, 40, 1, 8),
 ]
 
 
@@ -87,20 +87,25 @@ def test_smooth_sweep_bitwise(dim, n, by, zc, pd, wv, smoother, dt, varcoef, dev
     assert same(host(out), expect)
 
 
-@pytest.mark.parametrize("dim,n,by,zc,pd", [(2, 65, 16, 0, 0), (3, 33, 16, 5, 1), (3, 17, 8, 0, 2)])
+@pytest.mark.parametrize("dim,n,by,zc,pd,wv", [(2, 65, 16, 0, 0, 0), (3, 33, 16, 5, 1, 8), (3, 17, 8, 0, 2, 0),
+                                              (3, 65, 32, 9, 2, 8), (3, 129, 16, 11, 1, 4)])
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
-def test_smooth_zero_guess_bitwise(dim, n, by, zc, pd, dt, dev_ok):
+def test_smooth_zero_guess_bitwise(dim, n, by, zc, pd, wv, dt, dev_ok):
     _, f, _ = case_arrays(dim, n, dt, False, seed=3)
     expect = oracle.smooth(np.zeros_like(f), f)
     out = dev(np.zeros_like(f))
-    mg().mg_level_smooth(None, dev(f), out, zero_guess=True, by=by, zchunk=zc, prefetch=pd)
+    if over_row_limit(dim, by, dt, False, wv):
+        with pytest.raises(mg().MGError):
+            mg().mg_level_smooth(None, dev(f), out, zero_guess=True, by=by, zchunk=zc, prefetch=pd, waves=wv)
+        return
+    mg().mg_level_smooth(None, dev(f), out, zero_guess=True, by=by, zchunk=zc, prefetch=pd, waves=wv)
     assert same(host(out), expect)
 
 
 FUSED_CASES = [(2, 9, 0, 0, 0, 0), (2, 65, 0, 0, 0, 0), (2, 257, 0, 0, 0, 0),
-               (3, 5, 0, 0, 0, 0), (3, 9, 8, 1, 1, 0), (3, 17, 16, 3, 2, 0), (3, 33, 8, 5, 1, 0),
-               (3, 33, 32, 2, 2, 0), (3, 65, 32, 7, 2, 0), (3, 65, 0, 0, 0, 0), (3, 129, 16, 13, 1, 0),
-               (3, 33, 16, 5, 2, 8), (3, 65, 32, 7, 1, 8)]
+               (3, 5, 0, 0, 0, 0), (3, 9, 8, 1, 1, 0), (3, 17, 16, 3, 2, 8), (3, 33, 8, 5, 1, 0),
+               (3, 33, 32, 2, 2, 8), (3, 65, 16, 7, 1, 8), (3, 65, 0, 0, 0, 0), (3, 129, 16, 13, 1, 8),
+               (3, 33, 16, 5, 2, 4), (3, 129, 32, 7, 1, 8)]
 
 
 @pytest.mark.parametrize("dim,n,by,zc,pd,wv", FUSED_CASES)
