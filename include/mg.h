@@ -115,7 +115,7 @@ int mg_num_levels(const mg_ctx* ctx);
  * pass, 3 smoothing from a zero iterate, 4 smoothing with the coarse-grid
  * correction fused in): tile rows *by, z-chunk *zchunk (3D planes per workgroup), for 3D
  * marching kernels *prefetch = planes of u loaded ahead (1 or 2), and *waves =
- * wavefronts per workgroup (4, or 8 for 3D smoothing); prefetch and waves may
+ * wavefronts per workgroup (4; 1 or 8 for 3D smoothing); prefetch and waves may
  * be NULL.  These are the autotuner's choices (measured at mg_setup unless the
  * environment sets MG_AUTOTUNE=0) or the built-in heuristic.  Results never
  * depend on them. */
@@ -131,10 +131,12 @@ const char* mg_strerror(int code);
  * 'k' is null (Laplacian) or the nodal coefficient of this level.  'by' and
  * 'zchunk' pick the tile shape (0 = library default): by in {8, 16, 32},
  * zchunk >= 1 (3D only); 'prefetch' (3D smoothing) is 1 or 2 planes of u
- * loaded ahead and 'waves' (3D smoothing) 4 or 8 wavefronts per workgroup
- * (0 = default).  3D sweeps hold by/waves rows per thread: at most 4 in FP64
- * or with a coefficient field, 8 otherwise (MG_EINVAL beyond).  Asynchronous
- * on 'stream'.
+ * loaded ahead and 'waves' (3D smoothing) 4 or 8 wavefronts per workgroup,
+ * or 1: one wavefront per tile holding all of its rows in registers (by 8 or
+ * 12) (0 = default).  3D sweeps hold by/waves rows per thread: at most 4 in
+ * FP64 or with a coefficient field, 8 otherwise; with one wavefront, 12 rows
+ * in FP32 without a coefficient field, 8 in FP32 with one or in FP64 without,
+ * not available in FP64 with one (MG_EINVAL beyond).  Asynchronous on 'stream'.
  * ------------------------------------------------------------------------- */
 
 /* One smoothing sweep (Section 2.4 GaussSeidel / Section 2.3 Jacobi) from u_in

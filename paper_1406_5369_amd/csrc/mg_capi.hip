@@ -336,10 +336,10 @@ constexpr size_t kTuneMinPoints = 1u << 16;
 // wavefronts per workgroup (8 wavefronts for 16- and 32-row tiles).
 std::vector<TileCfg> tune_candidates(int dim, int planes, bool with_pd, int family, int elem, bool var) {
     std::vector<TileCfg> v;
-    const int geo[5][2] = {{8, 4}, {16, 4}, {32, 4}, {16, 8}, {32, 8}};
+    const int geo[7][2] = {{8, 4}, {16, 4}, {32, 4}, {16, 8}, {32, 8}, {8, 1}, {12, 1}};
     for (const auto& g : geo) {
         const int by = g[0], wv = g[1];
-        if (wv == 8 && (dim == 2 || family != 0)) continue;
+        if (wv != 4 && (dim == 2 || family != 0)) continue;
         if (by > max_tile_rows(dim, elem, var, family, wv)) continue;
         if (dim == 2) {
             v.push_back({by, 1, 1, 4});
@@ -833,8 +833,12 @@ static TileCfg pick_cfg(int dim, int elem, int n, int smoother, int by, int zchu
 }
 
 static bool valid_cfg(TileCfg c, int dim, int elem, bool var, int family) {
-    if (c.by != 8 && c.by != 16 && c.by != 32) return false;
-    if (c.wv != 4 && !(c.wv == 8 && dim == 3 && family == 0 && c.by >= 16)) return false;
+    if (c.wv == 1) {  // 3D sweep, one wavefront per tile
+        if (dim != 3 || family != 0 || (c.by != 8 && c.by != 12)) return false;
+    } else {
+        if (c.by != 8 && c.by != 16 && c.by != 32) return false;
+        if (c.wv != 4 && !(c.wv == 8 && dim == 3 && family == 0 && c.by >= 16)) return false;
+    }
     return c.by <= max_tile_rows(dim, elem, var, family, c.wv) && c.zchunk >= 1 && (c.pd == 1 || c.pd == 2);
 }
 

@@ -25,6 +25,10 @@ inline bool valid_edge(int dim, int n) {
 // restriction, 2 FP64 norm / refinement pass; wv: wavefronts per workgroup.
 inline int max_tile_rows(int dim, int elem, bool var, int family, int wv = 4) {
     if (dim == 2 || family == 1) return 32;
+    if (wv == 1) {  // 3D sweep with one wavefront per tile: the thread holds every row
+        if (family != 0) return 0;
+        return elem == 4 && !var ? 12 : (elem == 8 && var ? 0 : 8);
+    }
     const int rows_per_thread = (family == 0 ? (elem == 8 || var) : var) ? 4 : 8;
     return rows_per_thread * wv < 32 ? rows_per_thread * wv : 32;
 }
@@ -84,7 +88,7 @@ struct TileCfg {
     int by;      // LDS box rows (2D) / rows of the x-y box (3D): 8, 16 or 32
     int zchunk;  // 3D: output planes per workgroup (ignored in 2D)
     int pd = 1;  // 3D smoothing: planes of old u prefetched ahead (1 or 2)
-    int wv = 4;  // 3D smoothing: wavefronts per workgroup (4 or 8); a thread holds by/wv rows
+    int wv = 4;  // 3D smoothing: wavefronts per workgroup (1, 4 or 8); a thread holds by/wv rows
 };
 
 // Number of workgroups in x for a level of n nodes per axis (one instance).

@@ -1,6 +1,7 @@
 // 3D smoothing sweeps, instantiated per precision by mg_smooth3d_f64.hip / mg_smooth3d_f32.hip.
 #pragma once
 #include "mg_kern.h"
+#include "mg_smooth3d_rc.inl"
 
 namespace mg {
 namespace {
@@ -374,11 +375,29 @@ hipError_t launch_smooth3d_g(const GridDesc* d, int sel, TileCfg cfg, dim3 grid,
     return hipSuccess;
 }
 
+template <typename T, int SMV, bool VARV, int FL, int BY>
+hipError_t launch_smooth3d_rc(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
+    if (cfg.pd == 2) k_smooth3d_rc<T, SMV, VARV, BY, 2, FL><<<grid, 64, 0, s>>>(d, sel, cfg.zchunk);
+    else k_smooth3d_rc<T, SMV, VARV, BY, 1, FL><<<grid, 64, 0, s>>>(d, sel, cfg.zchunk);
+    return hipSuccess;
+}
+
 // Tile geometries (rows x wavefronts): 8x4, 16x4, 32x4 (FP32 Laplacian only:
-// eight rows per thread), 16x8 and 32x8.
+// eight rows per thread), 16x8 and 32x8; 8x1 and 12x1 in registers.
+
 template <typename T, int SMV, bool VARV, int FL>
 hipError_t launch_smooth3d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
     constexpr bool wide = sizeof(T) == 4 && !VARV;
+    if (cfg.wv == 1) {  // one wavefront per tile, rows in registers: 8 rows, or 12 in FP32 without coefficients
+        if constexpr (sizeof(T) == 8 && VARV) return hipErrorInvalidValue;
+        switch (cfg.by) {
+            case 8: return launch_smooth3d_rc<T, SMV, VARV, FL, 8>(d, sel, cfg, grid, s);
+            case 12:
+                if constexpr (wide) return launch_smooth3d_rc<T, SMV, VARV, FL, 12>(d, sel, cfg, grid, s);
+                return hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (cfg.wv == 4) {
         switch (cfg.by) {
             case 8: return launch_smooth3d_g<T, SMV, VARV, FL, 8, 4>(d, sel, cfg, grid, s);

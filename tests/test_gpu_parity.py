@@ -44,10 +44,16 @@ def same(a, b):
 
 def over_row_limit(dim, by, dt, varcoef, waves=0):
     """3D sweeps hold by / waves rows per thread (4 wavefronts unless given): at
-    most 4 in FP64 or with a coefficient field, 8 otherwise; the library
-    rejects more (they would not fit the register file)."""
-    rows = by // (waves or 4) if by else 0
-    return dim == 3 and rows > (4 if (dt == np.float64 or varcoef) else 8)
+    most 4 in FP64 or with a coefficient field, 8 otherwise; with one wavefront
+    per tile (waves = 1) the tile has 12 rows at most in FP32 without
+    coefficients, 8 in FP32 with them or FP64 without, none in FP64 with them.
+    The library rejects more (they would not fit the register file)."""
+    if dim != 3 or not by:
+        return False
+    fp64 = dt == np.float64
+    if waves == 1:
+        return by > (0 if (fp64 and varcoef) else (8 if (fp64 or varcoef) else 12))
+    return by // (waves or 4) > (4 if (fp64 or varcoef) else 8)
 
 
 def case_arrays(dim, n, dt, varcoef, seed=0):
@@ -63,6 +69,7 @@ SMOOTH_CASES = [
     (2, 65, 8, 0, 0, 0), (3, 5, 0, 0, 1, 0), (3, 9, 8, 1, 2, 0), (3, 17, 16, 3, 1, 8), (3, 17, 16, 3, 1, 0),
     (3, 33, 0, 0, 2, 0), (3, 65, 32, 7, 2, 8), (3, 65, 8, 64, 1, 0), (3, 129, 16, 128, 2, 8), (3, 33, 32, 2, 1, 0),
     (3, 33, 16, 5, 2, 4), (3, 129, 32, 16, 1, 8), (3, 257, 16, 40, 1, 8),
+    (3, 65, 8, 7, 1, 1), (3, 129, 12, 16, 2, 1), (3, 33, 12, 5, 1, 1), (3, 17, 8, 0, 2, 1),
 ]
 
 
@@ -88,7 +95,8 @@ def test_smooth_sweep_bitwise(dim, n, by, zc, pd, wv, smoother, dt, varcoef, dev
 
 
 @pytest.mark.parametrize("dim,n,by,zc,pd,wv", [(2, 65, 16, 0, 0, 0), (3, 33, 16, 5, 1, 8), (3, 17, 8, 0, 2, 0),
-                                              (3, 65, 32, 9, 2, 8), (3, 129, 16, 11, 1, 4)])
+                                              (3, 65, 32, 9, 2, 8), (3, 129, 16, 11, 1, 4), (3, 65, 12, 9, 1, 1),
+                                              (3, 33, 8, 3, 2, 1)])
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 def test_smooth_zero_guess_bitwise(dim, n, by, zc, pd, wv, dt, dev_ok):
     _, f, _ = case_arrays(dim, n, dt, False, seed=3)
@@ -105,7 +113,8 @@ def test_smooth_zero_guess_bitwise(dim, n, by, zc, pd, wv, dt, dev_ok):
 FUSED_CASES = [(2, 9, 0, 0, 0, 0), (2, 65, 0, 0, 0, 0), (2, 257, 0, 0, 0, 0),
                (3, 5, 0, 0, 0, 0), (3, 9, 8, 1, 1, 0), (3, 17, 16, 3, 2, 8), (3, 33, 8, 5, 1, 0),
                (3, 33, 32, 2, 2, 8), (3, 65, 16, 7, 1, 8), (3, 65, 0, 0, 0, 0), (3, 129, 16, 13, 1, 8),
-               (3, 33, 16, 5, 2, 4), (3, 129, 32, 7, 1, 8)]
+               (3, 33, 16, 5, 2, 4), (3, 129, 32, 7, 1, 8), (3, 65, 8, 7, 2, 1), (3, 129, 12, 13, 1, 1),
+               (3, 33, 8, 5, 1, 1)]
 
 
 @pytest.mark.parametrize("dim,n,by,zc,pd,wv", FUSED_CASES)
