@@ -207,6 +207,12 @@ def bench_serving(args, mg, torch):
     ctx = mg.mg_server_create(sp)
     # a pool of right-hand sides per size (requests of one size share a few seeds)
     pool = {}
+    outs = {}  # one result buffer per size: every solution is copied back to the host
+
+    def out_for(dim, n):
+        if (dim, n) not in outs:
+            outs[(dim, n)] = np.empty((n,) * dim)
+        return outs[(dim, n)]
 
     def rhs_for(req):
         key = (req.dim, req.n, req.seed % 3)
@@ -214,37 +220,53 @@ def bench_serving(args, mg, torch):
             pool[key] = inputs.uniform_rhs(req.dim, req.n, 5000 + req.seed % 3)
         return pool[key]
 
-    def run(reqs, closed_loop=False):
-        lat, t_first, t_last = [], None, None
+    def run(reqs, closed_loop=False, host=None):
+        lat = []
         i = 0
         start = time.perf_counter()
         arrival_of = {}
+        shape_of = {}
+        clock = time.perf_counter
         while i < len(reqs) or arrival_of:
-            now = time.perf_counter() - start
+            now = clock() - start
             while i < len(reqs) and (closed_loop or reqs[i].t_arrival <= now):
+                t0 = clock()
                 rid = mg.mg_server_submit(ctx, rhs_for(reqs[i]))
+                if host is not None:
+                    host["submit"] += clock() - t0
                 arrival_of[rid] = start + (0.0 if closed_loop else reqs[i].t_arrival)
+                shape_of[rid] = (reqs[i].dim, reqs[i].n)
                 i += 1
             used, active, queued = mg.mg_server_info(ctx)
-            if active == 0 and queued == 0 and i < len(reqs):
-                time.sleep(max(0.0, reqs[i].t_arrival - (time.perf_counter() - start)))
+            if active == 0 and queued == 0 and not arrival_of and i < len(reqs):
+                # idle: nothing admitted, queued or on its way back to the host
+                time.sleep(max(0.0, reqs[i].t_arrival - (clock() - start)))
                 continue
+            t0 = clock()
             mg.mg_server_step(ctx)
+            t1 = clock()
             for rid in mg.mg_server_poll(ctx):
-                st, _, cyc, rr, _ = mg.mg_server_fetch(ctx, rid)
-                tdone = time.perf_counter()
+                st, _, cyc, rr, _ = mg.mg_server_fetch(ctx, rid, out=out_for(*shape_of.pop(rid)))
+                if st != 0:
+                    raise RuntimeError(f"serving request {rid} ended with status {st}")
+                tdone = clock()
                 lat.append(tdone - arrival_of.pop(rid))
-                t_first = t_first or tdone
-                t_last = tdone
-        span = time.perf_counter() - start
+            if host is not None:
+                host["step"] += t1 - t0
+                host["poll_fetch"] += clock() - t1
+                host["steps"] += 1
+        span = clock() - start
         return np.array(lat), span
 
     # saturated throughput: everything submitted at once
     sat_reqs = inputs.serving_requests(args.serve_requests, rate=1.0, seed=4)
     _ = run(sat_reqs[: max(8, args.serve_requests // 8)], closed_loop=True)  # warm pools and tuner
-    lat, span = run(sat_reqs, closed_loop=True)
+    host = {"submit": 0.0, "step": 0.0, "poll_fetch": 0.0, "steps": 0}
+    lat, span = run(sat_reqs, closed_loop=True, host=host)
     mu_sat = len(sat_reqs) / span
-    log(f"[bench] serving: saturated {mu_sat:.1f} solves/s ({len(sat_reqs)} requests in {span:.2f} s)")
+    log(f"[bench] serving: saturated {mu_sat:.1f} solves/s ({len(sat_reqs)} requests in {span:.2f} s); "
+        f"host time in submit {host['submit']:.2f} s, step {host['step']:.2f} s ({host['steps']} calls), "
+        f"poll+fetch {host['poll_fetch']:.2f} s")
     sweep = []
     for frac in (0.2, 0.4, 0.6, 0.8, 0.95):
         reqs = inputs.serving_requests(args.serve_requests, rate=frac * mu_sat, seed=4)
@@ -274,6 +296,7 @@ def bench_serving(args, mg, torch):
                    "arrivals": "exponential inter-arrival, seed 4", "tol": 1e-8,
                    "budget_gib": args.serve_budget_gib, "slots_per_dim": args.serve_slots},
         "extra": {"saturated_solves_per_s": mu_sat, "mean_dof_per_request": mean_dof,
+                  "saturated_host_seconds": host,
                   "saturated_dof_per_s": mu_sat * mean_dof, "lambda_sweep": sweep},
     }
 

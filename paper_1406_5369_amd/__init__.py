@@ -199,6 +199,8 @@ def mg_setup(params: Params, stream=None) -> int:
 
 def mg_destroy(ctx: int) -> None:
     lib().mg_destroy(ctx)
+    for key in [k for k in _server_shapes if k[0] == ctx]:
+        del _server_shapes[key]
 
 
 def mg_num_levels(ctx: int) -> int:
@@ -409,7 +411,11 @@ def mg_server_submit(ctx: int, f_host) -> int:
     f = np.ascontiguousarray(f_host, dtype=np.float64)
     rid = C.c_longlong(0)
     _check(lib().mg_server_submit(ctx, f.ndim, f.shape[0], f.ctypes.data, C.byref(rid)), "mg_server_submit")
+    _server_shapes[(ctx, rid.value)] = f.shape
     return rid.value
+
+
+_server_shapes = {}  # (server, request id) -> shape of the request's grid
 
 
 def mg_server_step(ctx: int):
@@ -426,15 +432,23 @@ def mg_server_poll(ctx: int, cap: int = 4096):
     return list(ids[: nd.value])
 
 
-def mg_server_fetch(ctx: int, req_id: int, shape=None):
-    """(status, u or None, cycles, final relative residual, latency seconds)."""
+def mg_server_fetch(ctx: int, req_id: int, shape=None, out=None):
+    """(status, u or None, cycles, final relative residual, latency seconds).
+
+    The solution is copied into `out` (a C-contiguous float64 array of the
+    request's shape) when given, else into a new array when `shape` is given."""
     import numpy as np
 
-    u = np.empty(shape, dtype=np.float64) if shape is not None else None
+    u = out if out is not None else (np.empty(shape, dtype=np.float64) if shape is not None else None)
+    if u is not None and (u.dtype != np.float64 or not u.flags.c_contiguous or not u.flags.writeable):
+        raise ValueError("out must be a writeable C-contiguous float64 array")
+    if u is not None and _server_shapes.get((ctx, req_id), u.shape) != u.shape:
+        raise ValueError(f"output shape {u.shape} != request shape {_server_shapes[(ctx, req_id)]}")
     cyc, rr, lat = C.c_int(0), C.c_double(0.0), C.c_double(0.0)
     st = lib().mg_server_fetch(ctx, req_id, u.ctypes.data if u is not None else None, C.byref(cyc), C.byref(rr),
                                C.byref(lat))
     _check(st, "mg_server_fetch", ok=(MG_OK, MG_ENOTCONV, MG_EDIVERGED))
+    _server_shapes.pop((ctx, req_id), None)
     return st, u, cyc.value, rr.value, lat.value
 
 

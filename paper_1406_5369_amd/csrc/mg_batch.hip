@@ -21,6 +21,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "mg_sched.h"
@@ -463,15 +464,46 @@ struct Request {
     long long id = 0;
     int dim = 2, n = 0;
     double* f_pin = nullptr;   // pinned copy of the rhs (until uploaded)
-    std::vector<double> f_pageable;  // used instead when too many payloads are queued
+    std::unique_ptr<double[]> f_heap;  // used instead when too many payloads are queued
     double* u_pin = nullptr;   // pinned result (filled by an asynchronous copy)
     hipEvent_t ev = nullptr;   // completes when u_pin holds the result
+    hipEvent_t up = nullptr;   // completes when the hierarchy holds u = 0 and f
     Inst* inst = nullptr;
     int cycles = 0, status = 1;
     double rel_res = 0.0;
     bool complete = false;
     std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
 };
+
+// Host copy of a request payload or result, split over a few threads for
+// large buffers (one thread reaches a fraction of the host's memory bandwidth
+// on a copy of tens of MB).  A thread that cannot be started copies nothing:
+// its part is copied by the caller.
+void host_copy(void* dst, const void* src, size_t bytes) {
+    constexpr size_t kPart = size_t(4) << 20;
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>(std::min<size_t>(8, hw), (bytes + kPart - 1) / kPart);
+    if (nt <= 1) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t part = (bytes / nt + 4095) & ~size_t(4095);
+    auto piece = [dst, src, bytes, part](size_t t) {
+        const size_t o = t * part;
+        if (o < bytes) std::memcpy((char*)dst + o, (const char*)src + o, std::min(part, bytes - o));
+    };
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (size_t t = 1; t < nt; ++t) {
+        try {
+            th.emplace_back(piece, t);
+        } catch (...) {
+            piece(t);
+        }
+    }
+    piece(0);
+    for (std::thread& x : th) x.join();
+}
 
 // Pinned host buffers by size (request payloads and results).
 struct PinnedPool {
@@ -499,7 +531,7 @@ struct PinnedPool {
 // Device side of the serving policy: request hierarchies (FP32 levels plus
 // owned FP64 u, f and the refinement partner).
 struct InstBackend {
-    hipStream_t s = nullptr;
+    hipStream_t s = nullptr;  // the copy stream: allocation clears and uploads are ordered on it
     size_t bytes(int dim, int n) const { return inst_bytes(dim, n, true); }
     size_t bytes_of(const Inst* I) const { return I->bytes; }
     int alloc(int dim, int n, Inst** out) {
@@ -514,6 +546,7 @@ struct InstBackend {
         return 0;
     }
     void release(Inst* I) {
+        (void)hipStreamSynchronize(s);  // a result copy out of the hierarchy may be in flight
         free_inst(*I);
         delete I;
     }
@@ -526,7 +559,10 @@ struct Server {
     static constexpr size_t kMaxQueuedPinned = size_t(4) << 30;
     std::vector<Request*> copying;          // results on their way to the host
     std::vector<std::pair<void*, size_t>> release_after_sync;  // uploaded payloads
-    hipStream_t s = nullptr;
+    std::vector<std::unique_ptr<double[]>> heap_after_sync;     // uploaded payloads (not pinned)
+    std::vector<Request*> staged;  // admitted, upload in flight, not yet in an engine
+    hipStream_t s = nullptr;   // compute stream (the caller's)
+    hipStream_t cs = nullptr;  // copy stream: uploads and result copies overlap compute
     std::unique_ptr<Engine> eng[2];  // 2D, 3D
     std::map<long long, std::unique_ptr<Request>> reqs;
     Sched<Inst*> sch;                  // queue, slots, pool and budget
@@ -537,8 +573,10 @@ struct Server {
 
     ~Server() {
         if (s) (void)hipStreamSynchronize(s);
+        if (cs) (void)hipStreamSynchronize(cs);
         for (auto& kv : reqs) {
             if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
+            if (kv.second->up) (void)hipEventDestroy(kv.second->up);
             if (kv.second->f_pin) pinned.put(kv.second->f_pin, npts(kv.second->dim, kv.second->n) * 8);
             if (kv.second->u_pin) pinned.put(kv.second->u_pin, npts(kv.second->dim, kv.second->n) * 8);
         }
@@ -548,6 +586,7 @@ struct Server {
         for (auto& kv : reqs)
             if (kv.second->inst) backend.release(kv.second->inst);
         if (h_norm) (void)hipHostFree(h_norm);
+        if (cs) (void)hipStreamDestroy(cs);
     }
 };
 
@@ -592,6 +631,7 @@ bool same_solver(const mg_params& a, const mg_params& b) {
 }
 
 int server_admit(Server& S);
+int server_join(Server& S);
 int server_retire(Server& S, int d);
 void server_collect(Server& S);
 
@@ -724,7 +764,12 @@ int mg_server_create(const mg_server_params* sp, void* stream, mg_ctx** out) {
     if (S->sp.omega <= 0.0) S->sp.omega = sp->smoother == MG_SMOOTH_RBGS ? 1.0 : 0.8;
     if (S->sp.nu1 == 0 && S->sp.nu2 == 0) S->sp.nu1 = S->sp.nu2 = 2;
     S->s = (hipStream_t)stream;
-    S->backend.s = S->s;
+    if (hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking) != hipSuccess) {
+        S->cs = nullptr;
+        delete S;
+        return MG_EDEVICE;
+    }
+    S->backend.s = S->cs;
     S->sch.init(sp->hbm_budget_bytes, sp->max_slots);
     int r = MG_OK;
     for (int d = 0; d < 2 && r == MG_OK; ++d) {
@@ -758,10 +803,12 @@ int mg_server_submit(mg_ctx* ctx, int dim, int n, const double* f_host, long lon
     const size_t bytes = npts(dim, n) * sizeof(double);
     if (S.queued_pinned + bytes <= Server::kMaxQueuedPinned) R->f_pin = (double*)S.pinned.get(bytes);
     if (R->f_pin) {
-        std::memcpy(R->f_pin, f_host, bytes);
+        host_copy(R->f_pin, f_host, bytes);
         S.queued_pinned += bytes;
     } else {
-        R->f_pageable.assign(f_host, f_host + npts(dim, n));
+        R->f_heap.reset(new (std::nothrow) double[npts(dim, n)]);
+        if (!R->f_heap) return MG_ENOMEM;
+        host_copy(R->f_heap.get(), f_host, bytes);
     }
     R->t_submit = std::chrono::steady_clock::now();
     *req_id = R->id;
@@ -776,6 +823,8 @@ int mg_server_step(mg_ctx* ctx, int* n_active, int* n_queued) {
     if (h->kind != 2) return MG_EINVAL;
     Server& S = *h->server;
     int r = server_admit(S);
+    if (r != MG_OK) return r;
+    r = server_join(S);
     if (r != MG_OK) return r;
     for (int d = 0; d < 2; ++d) {
         Engine& E = *S.eng[d];
@@ -818,7 +867,7 @@ int mg_server_fetch(mg_ctx* ctx, long long req_id, double* u_host, int* cycles, 
     Request& R = *it->second;
     if (!R.complete) return MG_EBUSY;
     const size_t bytes = npts(R.dim, R.n) * sizeof(double);
-    if (u_host) std::memcpy(u_host, R.u_pin, bytes);
+    if (u_host) host_copy(u_host, R.u_pin, bytes);
     S.pinned.put(R.u_pin, bytes);
     R.u_pin = nullptr;
     if (R.ev) (void)hipEventDestroy(R.ev);
@@ -849,14 +898,11 @@ namespace {
 // Admit queued requests in arrival order while a slot and the HBM budget
 // allow: take a hierarchy of the right size from the pool (or allocate one,
 // first releasing pooled hierarchies of other sizes if the budget requires),
-// upload f and point the request at it.  A request that does not fit now
-// stays first in the queue (no overtaking, so no starvation).
+// and start clearing u and uploading f on the copy stream.  A request that
+// does not fit now stays first in the queue (no overtaking, so no starvation).
 int server_admit(Server& S) {
-    bool any[2] = {false, false};
     while (!S.sch.queue.empty()) {
         Request& R = *S.reqs[S.sch.queue.front()];
-        const int d = R.dim - 2;
-        Engine& E = *S.eng[d];
         int slot = -1;
         Inst* I = nullptr;
         const int a = S.sch.admit_head(S.backend, R.dim, R.n, &slot, &I);
@@ -865,32 +911,59 @@ int server_admit(Server& S) {
         I->slot = slot;
         I->u = I->u64;
         I->f = I->f64;
-        const size_t N = npts(R.dim, R.n);
-        BCK(hipMemsetAsync(I->u64, 0, N * sizeof(double), S.s));
-        if (R.f_pin) {
-            BCK(hipMemcpyAsync(I->f64, R.f_pin, N * sizeof(double), hipMemcpyHostToDevice, S.s));
-            S.release_after_sync.push_back({R.f_pin, N * sizeof(double)});  // the copy is in flight
-            S.queued_pinned -= N * sizeof(double);
-            R.f_pin = nullptr;
-        } else {
-            BCK(hipMemcpy(I->f64, R.f_pageable.data(), N * sizeof(double), hipMemcpyHostToDevice));
-            std::vector<double>().swap(R.f_pageable);
-        }
         R.inst = I;
         R.t_admit = std::chrono::steady_clock::now();
-        E.members.push_back(I);
-        E.fresh.push_back(I);
+        S.staged.push_back(&R);
+        const size_t N = npts(R.dim, R.n);
+        // ordered after the result copy of the hierarchy's previous request (same stream)
+        BCK(hipMemsetAsync(I->u64, 0, N * sizeof(double), S.cs));
+        if (R.f_pin) {
+            BCK(hipMemcpyAsync(I->f64, R.f_pin, N * sizeof(double), hipMemcpyHostToDevice, S.cs));
+        } else {
+            BCK(hipMemcpyAsync(I->f64, R.f_heap.get(), N * sizeof(double), hipMemcpyHostToDevice, S.cs));
+        }
+        if (!R.up) BCK(hipEventCreateWithFlags(&R.up, hipEventDisableTiming));
+        BCK(hipEventRecord(R.up, S.cs));
+    }
+    return MG_OK;
+}
+
+// Admitted requests join their engine once their upload has landed, so the
+// upload overlaps the other requests' refinement steps.  An engine with no
+// other work takes the request at once and its stream waits for the upload
+// on the device.
+int server_join(Server& S) {
+    bool any[2] = {false, false};
+    std::vector<Request*> still;
+    for (Request* R : S.staged) {
+        const int d = R->dim - 2;
+        Engine& E = *S.eng[d];
+        const hipError_t q = hipEventQuery(R->up);
+        if (q != hipSuccess && q != hipErrorNotReady) return st(q);
+        const size_t bytes = npts(R->dim, R->n) * sizeof(double);
+        if (q == hipSuccess) {
+            if (R->f_pin) S.pinned.put(R->f_pin, bytes);
+            R->f_heap.reset();
+        } else if (E.members.empty() && !any[d]) {
+            BCK(hipStreamWaitEvent(S.s, R->up, 0));
+            if (R->f_pin) S.release_after_sync.push_back({R->f_pin, bytes});
+            if (R->f_heap) S.heap_after_sync.push_back(std::move(R->f_heap));
+        } else {
+            still.push_back(R);
+            continue;
+        }
+        if (R->f_pin) S.queued_pinned -= bytes;
+        R->f_pin = nullptr;
+        E.members.push_back(R->inst);
+        E.fresh.push_back(R->inst);
         any[d] = true;
     }
+    S.staged.swap(still);
     for (int d = 0; d < 2; ++d)
         if (any[d]) {
-            int r = S.eng[d]->rebuild();  // synchronises the stream: uploads are done
+            int r = S.eng[d]->rebuild();  // synchronises the compute stream
             if (r != MG_OK) return r;
         }
-    if (any[0] || any[1]) {
-        for (auto& pr : S.release_after_sync) S.pinned.put(pr.first, pr.second);
-        S.release_after_sync.clear();
-    }
     return MG_OK;
 }
 
@@ -901,8 +974,10 @@ int server_retire(Server& S, int d) {
     if (E.members.empty()) return MG_OK;
     int r = E.read_ctrl(true);
     if (r != MG_OK) return r;
-    for (auto& pr : S.release_after_sync) S.pinned.put(pr.first, pr.second);  // stream is idle here
+    // the compute stream is idle here: uploads it waited for have landed
+    for (auto& pr : S.release_after_sync) S.pinned.put(pr.first, pr.second);
     S.release_after_sync.clear();
+    S.heap_after_sync.clear();
     std::vector<Inst*> keep;
     std::vector<Request*> out;
     for (Inst* I : E.members) {
@@ -918,26 +993,27 @@ int server_retire(Server& S, int d) {
         const double* src = (E.steps(I->slot) & 1) ? I->u2 : I->u64;
         R->u_pin = (double*)S.pinned.get(bytes);
         if (!R->u_pin) return MG_ENOMEM;
-        BCK(hipMemcpyAsync(R->u_pin, src, bytes, hipMemcpyDeviceToHost, S.s));
+        BCK(hipMemcpyAsync(R->u_pin, src, bytes, hipMemcpyDeviceToHost, S.cs));
         const double n0 = E.h_nrm[E.cap + I->slot];
         R->rel_res = n0 > 0.0 ? E.h_nrm[I->slot] / n0 : 0.0;
         R->cycles = E.steps(I->slot);
         R->status = E.status(I->slot);
         R->inst = nullptr;
-        // the hierarchy may be reused at once: later work on it is ordered after the copy
+        // the hierarchy may be reused at once: its next clear and upload are
+        // ordered after the copy on the copy stream
         S.sch.retire(I->dim, I->slot, I->n, I);
         out.push_back(R);
     }
     if (!out.empty()) {
         hipEvent_t ev = nullptr;
         BCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        BCK(hipEventRecord(ev, S.s));
+        BCK(hipEventRecord(ev, S.cs));
         for (size_t i = 0; i < out.size(); ++i) {
             if (i == 0) {
                 out[i]->ev = ev;
             } else {
                 BCK(hipEventCreateWithFlags(&out[i]->ev, hipEventDisableTiming));
-                BCK(hipEventRecord(out[i]->ev, S.s));
+                BCK(hipEventRecord(out[i]->ev, S.cs));
             }
             S.copying.push_back(out[i]);
         }
