@@ -229,12 +229,13 @@ def bench_serving(args, mg, torch):
         clock = time.perf_counter
         while i < len(reqs) or arrival_of:
             now = clock() - start
-            while i < len(reqs) and (closed_loop or reqs[i].t_arrival <= now):
+            # closed loop: a fixed number of requests in flight, a new one per completion
+            while i < len(reqs) and (len(arrival_of) < inflight if closed_loop else reqs[i].t_arrival <= now):
                 t0 = clock()
                 rid = mg.mg_server_submit(ctx, rhs_for(reqs[i]))
                 if host is not None:
                     host["submit"] += clock() - t0
-                arrival_of[rid] = start + (0.0 if closed_loop else reqs[i].t_arrival)
+                arrival_of[rid] = clock() if closed_loop else start + reqs[i].t_arrival
                 shape_of[rid] = (reqs[i].dim, reqs[i].n)
                 i += 1
             used, active, queued = mg.mg_server_info(ctx)
@@ -258,13 +259,16 @@ def bench_serving(args, mg, torch):
         span = clock() - start
         return np.array(lat), span
 
-    # saturated throughput: everything submitted at once
+    # saturated throughput: closed loop with a fixed number of requests in flight
+    inflight = args.serve_inflight
     sat_reqs = inputs.serving_requests(args.serve_requests, rate=1.0, seed=4)
     _ = run(sat_reqs[: max(8, args.serve_requests // 8)], closed_loop=True)  # warm pools and tuner
     host = {"submit": 0.0, "step": 0.0, "poll_fetch": 0.0, "steps": 0}
     lat, span = run(sat_reqs, closed_loop=True, host=host)
     mu_sat = len(sat_reqs) / span
-    log(f"[bench] serving: saturated {mu_sat:.1f} solves/s ({len(sat_reqs)} requests in {span:.2f} s); "
+    sat_p = [float(np.percentile(lat, q) * 1e3) for q in (50, 99)]
+    log(f"[bench] serving: saturated {mu_sat:.1f} solves/s ({len(sat_reqs)} requests in {span:.2f} s, "
+        f"{inflight} in flight, p50/p99 {sat_p[0]:.2f}/{sat_p[1]:.2f} ms); "
         f"host time in submit {host['submit']:.2f} s, step {host['step']:.2f} s ({host['steps']} calls), "
         f"poll+fetch {host['poll_fetch']:.2f} s")
     sweep = []
@@ -292,11 +296,12 @@ def bench_serving(args, mg, torch):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "serving_mix", "requests_per_lambda": args.serve_requests,
+                   "saturated_inflight": args.serve_inflight,
                    "mix": "60% 2D edges {257,513,1025,2049}, 40% 3D edges {33,65,129,257}",
                    "arrivals": "exponential inter-arrival, seed 4", "tol": 1e-8,
                    "budget_gib": args.serve_budget_gib, "slots_per_dim": args.serve_slots},
         "extra": {"saturated_solves_per_s": mu_sat, "mean_dof_per_request": mean_dof,
-                  "saturated_host_seconds": host,
+                  "saturated_host_seconds": host, "saturated_p50_ms": sat_p[0], "saturated_p99_ms": sat_p[1],
                   "saturated_dof_per_s": mu_sat * mean_dof, "lambda_sweep": sweep},
     }
 
@@ -312,8 +317,9 @@ def main(argv=None) -> int:
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 context solve")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the baseline")
     ap.add_argument("--batch-count", type=int, default=512)
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-inflight", type=int, default=64, help="requests in flight in the saturated run")
     ap.add_argument("--serve-budget-gib", type=int, default=48)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run the plain copy kernel over 1 GiB three times (counter calibration)")

@@ -58,6 +58,7 @@ int st(hipError_t e) {
 struct Inst {
     int dim = 0, n = 0, a = 0;  // finest edge n = 2^a + 1
     int slot = -1;
+    long long join_step = 0;     // serving: the step whose launches first include it
     std::vector<void*> e, t, r;  // FP32 levels, 0 = finest
     double* u2 = nullptr;        // FP64 ping-pong partner of u
     double* u64 = nullptr;       // owned FP64 iterate (served requests)
@@ -136,6 +137,61 @@ struct IRGroup {
     IRDesc* d;
 };
 
+// Pinned host staging for descriptor uploads in a ring of generations: a
+// rebuild writes one generation while the copies of earlier ones may still be
+// queued behind running work, so a rebuild rarely waits for the device (only
+// when it comes back to a generation whose copies have not run yet).
+struct Staging {
+    static constexpr int G = 4;
+    char* buf[G] = {};
+    size_t cap[G] = {};
+    hipEvent_t ev[G] = {};
+    bool queued[G] = {};
+    int g = 0;
+    size_t off = 0;
+    static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+    hipError_t begin(size_t need) {
+        g = (g + 1) % G;
+        if (queued[g]) {
+            hipError_t e = hipEventSynchronize(ev[g]);
+            if (e != hipSuccess) return e;
+            queued[g] = false;
+        }
+        if (!ev[g]) {
+            hipError_t e = hipEventCreateWithFlags(&ev[g], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        if (need > cap[g]) {
+            if (buf[g]) (void)hipHostFree(buf[g]);
+            buf[g] = nullptr;
+            cap[g] = 0;
+            hipError_t e = hipHostMalloc((void**)&buf[g], need, hipHostMallocDefault);
+            if (e != hipSuccess) return e;
+            cap[g] = need;
+        }
+        off = 0;
+        return hipSuccess;
+    }
+    hipError_t put(void* dst, const void* src, size_t bytes, hipStream_t s) {
+        if (bytes == 0) return hipSuccess;
+        std::memcpy(buf[g] + off, src, bytes);
+        hipError_t e = hipMemcpyAsync(dst, buf[g] + off, bytes, hipMemcpyHostToDevice, s);
+        off += round(bytes);
+        return e;
+    }
+    hipError_t end(hipStream_t s) {
+        queued[g] = true;
+        return hipEventRecord(ev[g], s);
+    }
+    ~Staging() {
+        for (int i = 0; i < G; ++i) {
+            if (queued[i]) (void)hipEventSynchronize(ev[i]);
+            if (buf[i]) (void)hipHostFree(buf[i]);
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+        }
+    }
+};
+
 // Shared launch machinery for a set of instances of one dimension.
 struct Engine {
     int dim = 2;
@@ -151,6 +207,13 @@ struct Engine {
     double *d_norm = nullptr, *d_norm0 = nullptr, *d_partial = nullptr;
     int* h_ctrl = nullptr;  // pinned: done, steps, status (3 * cap)
     double* h_nrm = nullptr;  // pinned: norm, norm0 (2 * cap)
+    // serving: control snapshots taken after a step, two in flight
+    int* h_snap[2] = {nullptr, nullptr};    // pinned: done, steps, status (3 * cap)
+    double* h_snrm[2] = {nullptr, nullptr}; // pinned: norm, norm0 (2 * cap)
+    hipEvent_t snap_ev[2] = {nullptr, nullptr};
+    long long snap_step[2] = {-1, -1};
+    bool snap_pending[2] = {false, false};
+    Staging stage;
     GridDesc* d_gd = nullptr;
     size_t gd_cap = 0;
     IRDesc* d_ir = nullptr;
@@ -183,6 +246,11 @@ struct Engine {
             if (p) (void)hipFree(p);
         if (h_ctrl) (void)hipHostFree(h_ctrl);
         if (h_nrm) (void)hipHostFree(h_nrm);
+        for (int b = 0; b < 2; ++b) {
+            if (snap_ev[b]) (void)hipEventDestroy(snap_ev[b]);
+            if (h_snap[b]) (void)hipHostFree(h_snap[b]);
+            if (h_snrm[b]) (void)hipHostFree(h_snrm[b]);
+        }
     }
 
     int init(int dim_, const Problem& P, hipStream_t s_, int cap_, int max_n) {
@@ -208,6 +276,11 @@ struct Engine {
         BCK(hipMalloc((void**)&d_partial, sizeof(double) * (size_t)cap * (size_t)pstride));
         BCK(hipHostMalloc((void**)&h_ctrl, 3 * ci, hipHostMallocDefault));
         BCK(hipHostMalloc((void**)&h_nrm, 2 * sizeof(double) * (size_t)cap, hipHostMallocDefault));
+        for (int b = 0; b < 2; ++b) {
+            BCK(hipHostMalloc((void**)&h_snap[b], 3 * ci, hipHostMallocDefault));
+            BCK(hipHostMalloc((void**)&h_snrm[b], 2 * sizeof(double) * (size_t)cap, hipHostMallocDefault));
+            BCK(hipEventCreateWithFlags(&snap_ev[b], hipEventDisableTiming));
+        }
         BCK(launch_fill_int(d_done, 1, cap, s));  // empty slots are "done"
         BCK(launch_fill_int(d_steps, 0, cap, s));
         BCK(launch_fill_int(d_status, 0, cap, s));
@@ -307,10 +380,6 @@ struct Engine {
             tail_cap = std::max(h_tail.size(), 2 * tail_cap);
             BCK(hipMalloc((void**)&d_tail, sizeof(TailDesc) * tail_cap));
         }
-        if (!h_tail.empty()) {
-            BCK(hipMemcpyAsync(d_tail, h_tail.data(), sizeof(TailDesc) * h_tail.size(), hipMemcpyHostToDevice, s));
-            tailplan.d = d_tail;
-        }
         if (h_gd.size() > gd_cap) {
             if (d_gd) (void)hipFree(d_gd);
             gd_cap = std::max(h_gd.size(), 2 * gd_cap);
@@ -321,8 +390,27 @@ struct Engine {
             ir_cap = std::max(h_ir.size(), 2 * ir_cap);
             BCK(hipMalloc((void**)&d_ir, sizeof(IRDesc) * ir_cap));
         }
-        BCK(hipMemcpyAsync(d_gd, h_gd.data(), sizeof(GridDesc) * h_gd.size(), hipMemcpyHostToDevice, s));
-        BCK(hipMemcpyAsync(d_ir, h_ir.data(), sizeof(IRDesc) * h_ir.size(), hipMemcpyHostToDevice, s));
+        h_rows.clear();
+        for (const Inst* I : members) h_rows.push_back(I->slot);
+        h_newrows.clear();
+        for (const Inst* I : fresh) h_newrows.push_back(I->slot);
+        std::vector<int> np((size_t)cap, 0);
+        for (const Inst* I : members) np[(size_t)I->slot] = norm_tiles(dim, I->n, tiles[(size_t)I->a].norm);
+        // uploads are ordered behind the work already queued on the stream
+        BCK(stage.begin(Staging::round(sizeof(TailDesc) * h_tail.size()) +
+                        Staging::round(sizeof(GridDesc) * h_gd.size()) + Staging::round(sizeof(IRDesc) * h_ir.size()) +
+                        Staging::round(sizeof(int) * h_rows.size()) + Staging::round(sizeof(int) * h_newrows.size()) +
+                        Staging::round(sizeof(int) * np.size())));
+        if (!h_tail.empty()) {
+            BCK(stage.put(d_tail, h_tail.data(), sizeof(TailDesc) * h_tail.size(), s));
+            tailplan.d = d_tail;
+        }
+        BCK(stage.put(d_gd, h_gd.data(), sizeof(GridDesc) * h_gd.size(), s));
+        BCK(stage.put(d_ir, h_ir.data(), sizeof(IRDesc) * h_ir.size(), s));
+        BCK(stage.put(d_rows, h_rows.data(), sizeof(int) * h_rows.size(), s));
+        BCK(stage.put(d_newrows, h_newrows.data(), sizeof(int) * h_newrows.size(), s));
+        BCK(stage.put(d_nparts, np.data(), sizeof(int) * np.size(), s));
+        BCK(stage.end(s));
         for (size_t g = 0; g < goff.size(); ++g) {
             Group G;
             G.n = (1 << (amax - (int)g)) + 1;
@@ -334,18 +422,6 @@ struct Engine {
         for (auto& x : ioff) irg.push_back({x.first, (1 << x.first) + 1, (int)x.second.second, d_ir + x.second.first});
         for (auto& x : inew)
             irg_new.push_back({x.first, (1 << x.first) + 1, (int)x.second.second, d_ir + x.second.first});
-        h_rows.clear();
-        for (const Inst* I : members) h_rows.push_back(I->slot);
-        h_newrows.clear();
-        for (const Inst* I : fresh) h_newrows.push_back(I->slot);
-        std::vector<int> np((size_t)cap, 0);
-        for (const Inst* I : members) np[(size_t)I->slot] = norm_tiles(dim, I->n, tiles[(size_t)I->a].norm);
-        BCK(hipMemcpyAsync(d_rows, h_rows.data(), sizeof(int) * h_rows.size(), hipMemcpyHostToDevice, s));
-        if (!h_newrows.empty())
-            BCK(hipMemcpyAsync(d_newrows, h_newrows.data(), sizeof(int) * h_newrows.size(), hipMemcpyHostToDevice,
-                               s));
-        BCK(hipMemcpyAsync(d_nparts, np.data(), sizeof(int) * np.size(), hipMemcpyHostToDevice, s));
-        BCK(hipStreamSynchronize(s));  // host vectors are reused by the next rebuild
         return MG_OK;
     }
 
@@ -431,6 +507,24 @@ struct Engine {
     int done(int slot) const { return h_ctrl[slot]; }
     int steps(int slot) const { return h_ctrl[cap + slot]; }
     int status(int slot) const { return h_ctrl[2 * cap + slot]; }
+
+    // Serving: copy the control state after step 'step_no' into snapshot
+    // buffer step_no & 1 (the caller has consumed what it held).
+    hipError_t snapshot(long long step_no) {
+        const int b = (int)(step_no & 1);
+        const size_t ci = sizeof(int) * (size_t)cap, cd = sizeof(double) * (size_t)cap;
+        hipError_t e = hipMemcpyAsync(h_snap[b], d_done, ci, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_snap[b] + cap, d_steps, ci, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_snap[b] + 2 * cap, d_status, ci, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_snrm[b], d_norm, cd, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_snrm[b] + cap, d_norm0, cd, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(snap_ev[b], s);
+        if (e == hipSuccess) {
+            snap_step[b] = step_no;
+            snap_pending[b] = true;
+        }
+        return e;
+    }
 
     // After a finished solve: the iterate is in u2 when an odd number of update passes ran.
     hipError_t copy_back(const Inst& I) {
@@ -558,9 +652,16 @@ struct Server {
     size_t queued_pinned = 0;  // bytes of queued payloads held in pinned memory
     static constexpr size_t kMaxQueuedPinned = size_t(4) << 30;
     std::vector<Request*> copying;          // results on their way to the host
-    std::vector<std::pair<void*, size_t>> release_after_sync;  // uploaded payloads
-    std::vector<std::unique_ptr<double[]>> heap_after_sync;     // uploaded payloads (not pinned)
+    // payloads whose upload the compute stream waits for: released once it landed
+    struct Upload {
+        hipEvent_t ev;
+        void* pin;
+        size_t bytes;
+        std::unique_ptr<double[]> heap;
+    };
+    std::vector<Upload> uploading;
     std::vector<Request*> staged;  // admitted, upload in flight, not yet in an engine
+    long long step_no = 0;         // refinement steps enqueued so far
     hipStream_t s = nullptr;   // compute stream (the caller's)
     hipStream_t cs = nullptr;  // copy stream: uploads and result copies overlap compute
     std::unique_ptr<Engine> eng[2];  // 2D, 3D
@@ -580,7 +681,10 @@ struct Server {
             if (kv.second->f_pin) pinned.put(kv.second->f_pin, npts(kv.second->dim, kv.second->n) * 8);
             if (kv.second->u_pin) pinned.put(kv.second->u_pin, npts(kv.second->dim, kv.second->n) * 8);
         }
-        for (auto& pr : release_after_sync) pinned.put(pr.first, pr.second);
+        for (auto& u : uploading) {
+            pinned.put(u.pin, u.bytes);
+            (void)hipEventDestroy(u.ev);
+        }
         for (int d = 0; d < 2; ++d) eng[d].reset();
         sch.drain_pool(backend);
         for (auto& kv : reqs)
@@ -632,7 +736,7 @@ bool same_solver(const mg_params& a, const mg_params& b) {
 
 int server_admit(Server& S);
 int server_join(Server& S);
-int server_retire(Server& S, int d);
+int server_consume(Server& S, int d, long long upto, bool wait);
 void server_collect(Server& S);
 
 }  // namespace
@@ -822,19 +926,23 @@ int mg_server_step(mg_ctx* ctx, int* n_active, int* n_queued) {
     mg_batch_handle* h = as_handle(ctx);
     if (h->kind != 2) return MG_EINVAL;
     Server& S = *h->server;
+    // Pipelined: the step enqueued here runs while the host completes the
+    // previous one, so the device is not idle during admission and retirement.
     int r = server_admit(S);
+    for (int d = 0; d < 2 && r == MG_OK; ++d) r = server_consume(S, d, S.step_no - 1, false);  // landed ones
+    if (r == MG_OK) r = server_join(S);
     if (r != MG_OK) return r;
-    r = server_join(S);
-    if (r != MG_OK) return r;
+    const long long k = S.step_no++;
     for (int d = 0; d < 2; ++d) {
         Engine& E = *S.eng[d];
         if (E.members.empty()) continue;
         BCK(E.start_fresh());
         E.fresh.clear();
         BCK(E.enqueue_step(S.sp.tol, S.sp.max_cycles, S.s));
+        BCK(E.snapshot(k));
     }
     for (int d = 0; d < 2; ++d) {
-        r = server_retire(S, d);
+        r = server_consume(S, d, k - 1, true);  // at most step k stays in flight
         if (r != MG_OK) return r;
     }
     server_collect(S);
@@ -946,81 +1054,100 @@ int server_join(Server& S) {
             R->f_heap.reset();
         } else if (E.members.empty() && !any[d]) {
             BCK(hipStreamWaitEvent(S.s, R->up, 0));
-            if (R->f_pin) S.release_after_sync.push_back({R->f_pin, bytes});
-            if (R->f_heap) S.heap_after_sync.push_back(std::move(R->f_heap));
+            S.uploading.push_back({R->up, R->f_pin, bytes, std::move(R->f_heap)});  // takes the event
+            R->up = nullptr;
         } else {
             still.push_back(R);
             continue;
         }
         if (R->f_pin) S.queued_pinned -= bytes;
         R->f_pin = nullptr;
+        R->inst->join_step = S.step_no;
         E.members.push_back(R->inst);
         E.fresh.push_back(R->inst);
         any[d] = true;
     }
     S.staged.swap(still);
+    std::vector<Server::Upload> pend;
+    for (auto& u : S.uploading) {
+        const hipError_t q = hipEventQuery(u.ev);
+        if (q == hipSuccess) {
+            S.pinned.put(u.pin, u.bytes);
+            (void)hipEventDestroy(u.ev);
+        } else if (q == hipErrorNotReady) {
+            pend.push_back(std::move(u));
+        }
+        else return st(q);
+    }
+    S.uploading.swap(pend);
     for (int d = 0; d < 2; ++d)
         if (any[d]) {
-            int r = S.eng[d]->rebuild();  // synchronises the compute stream
+            int r = S.eng[d]->rebuild();
             if (r != MG_OK) return r;
         }
     return MG_OK;
 }
 
-// Complete the requests whose stop flag is set: copy u to the host, return
-// the hierarchy to the pool and free the slot.
-int server_retire(Server& S, int d) {
+// Complete the requests that a control snapshot shows finished: copy u to the
+// host on the copy stream, return the hierarchy to the pool and free the slot.
+// Snapshots of steps up to 'upto' are taken in step order; with 'wait' false
+// only those that have already landed.  A snapshot speaks only for members
+// that were in its step (later joiners may hold a reused slot).
+int server_consume(Server& S, int d, long long upto, bool wait) {
     Engine& E = *S.eng[d];
-    if (E.members.empty()) return MG_OK;
-    int r = E.read_ctrl(true);
-    if (r != MG_OK) return r;
-    // the compute stream is idle here: uploads it waited for have landed
-    for (auto& pr : S.release_after_sync) S.pinned.put(pr.first, pr.second);
-    S.release_after_sync.clear();
-    S.heap_after_sync.clear();
-    std::vector<Inst*> keep;
-    std::vector<Request*> out;
-    for (Inst* I : E.members) {
-        if (!E.done(I->slot)) {
-            keep.push_back(I);
-            continue;
+    for (;;) {
+        int b = -1;
+        for (int i = 0; i < 2; ++i)
+            if (E.snap_pending[i] && E.snap_step[i] <= upto && (b < 0 || E.snap_step[i] < E.snap_step[b])) b = i;
+        if (b < 0) return MG_OK;
+        if (wait) {
+            BCK(hipEventSynchronize(E.snap_ev[b]));
+        } else {
+            const hipError_t q = hipEventQuery(E.snap_ev[b]);
+            if (q == hipErrorNotReady) return MG_OK;
+            BCK(q);
         }
-        Request* R = nullptr;
-        for (auto& kv : S.reqs)
-            if (kv.second->inst == I) R = kv.second.get();
-        if (!R) return MG_EDEVICE;
-        const size_t bytes = npts(I->dim, I->n) * sizeof(double);
-        const double* src = (E.steps(I->slot) & 1) ? I->u2 : I->u64;
-        R->u_pin = (double*)S.pinned.get(bytes);
-        if (!R->u_pin) return MG_ENOMEM;
-        BCK(hipMemcpyAsync(R->u_pin, src, bytes, hipMemcpyDeviceToHost, S.cs));
-        const double n0 = E.h_nrm[E.cap + I->slot];
-        R->rel_res = n0 > 0.0 ? E.h_nrm[I->slot] / n0 : 0.0;
-        R->cycles = E.steps(I->slot);
-        R->status = E.status(I->slot);
-        R->inst = nullptr;
-        // the hierarchy may be reused at once: its next clear and upload are
-        // ordered after the copy on the copy stream
-        S.sch.retire(I->dim, I->slot, I->n, I);
-        out.push_back(R);
-    }
-    if (!out.empty()) {
-        hipEvent_t ev = nullptr;
-        BCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        BCK(hipEventRecord(ev, S.cs));
-        for (size_t i = 0; i < out.size(); ++i) {
-            if (i == 0) {
-                out[i]->ev = ev;
-            } else {
-                BCK(hipEventCreateWithFlags(&out[i]->ev, hipEventDisableTiming));
-                BCK(hipEventRecord(out[i]->ev, S.cs));
+        E.snap_pending[b] = false;
+        const long long j = E.snap_step[b];
+        const int* c = E.h_snap[b];
+        const double* nr = E.h_snrm[b];
+        std::vector<Inst*> keep;
+        std::vector<Request*> out;
+        for (Inst* I : E.members) {
+            if (I->join_step > j || !c[I->slot]) {
+                keep.push_back(I);
+                continue;
             }
-            S.copying.push_back(out[i]);
+            Request* R = nullptr;
+            for (auto& kv : S.reqs)
+                if (kv.second->inst == I) R = kv.second.get();
+            if (!R) return MG_EDEVICE;
+            const int steps = c[E.cap + I->slot];
+            const size_t bytes = npts(I->dim, I->n) * sizeof(double);
+            const double* src = (steps & 1) ? I->u2 : I->u64;  // later steps skip the finished slot
+            R->u_pin = (double*)S.pinned.get(bytes);
+            if (!R->u_pin) return MG_ENOMEM;
+            BCK(hipMemcpyAsync(R->u_pin, src, bytes, hipMemcpyDeviceToHost, S.cs));
+            const double n0 = nr[E.cap + I->slot];
+            R->rel_res = n0 > 0.0 ? nr[I->slot] / n0 : 0.0;
+            R->cycles = steps;
+            R->status = c[2 * E.cap + I->slot];
+            R->inst = nullptr;
+            // the hierarchy may be reused at once: its next clear and upload are
+            // ordered after the copy on the copy stream
+            S.sch.retire(I->dim, I->slot, I->n, I);
+            out.push_back(R);
+        }
+        if (out.empty()) continue;
+        for (Request* R : out) {
+            BCK(hipEventCreateWithFlags(&R->ev, hipEventDisableTiming));
+            BCK(hipEventRecord(R->ev, S.cs));
+            S.copying.push_back(R);
         }
         E.members = keep;
-        return E.rebuild();
+        const int r = E.rebuild();
+        if (r != MG_OK) return r;
     }
-    return MG_OK;
 }
 
 // Requests whose result copy has landed become complete.

@@ -129,3 +129,40 @@ def test_server_budget_blocks_then_admits(dev_ok):
         st, u, cyc, rr, lat = m.mg_server_fetch(ctx, rid)
         assert st == 0
     m.mg_destroy(ctx)
+
+
+def test_server_many_requests_reusing_few_slots(dev_ok):
+    """Forty requests through two slots per dimension, submitted in bursts of zero to
+    three between steps, including zero right-hand sides (finished before the first
+    cycle): slots and hierarchies are reused while earlier steps are still in flight,
+    and every result equals the oracle's solve of that request alone."""
+    m = mg()
+    sp = m.ServerParams(hbm_budget_bytes=512 << 20, max_slots=2, max_n2d=129, max_n3d=17, tol=1e-8, max_cycles=40)
+    ctx = m.mg_server_create(sp)
+    rng = np.random.default_rng(21)
+    sizes = [(2, 33), (2, 65), (2, 129), (3, 9), (3, 17)]
+    reqs = []
+    for i in range(40):
+        dim, n = sizes[int(rng.integers(len(sizes)))]
+        f = np.zeros((n,) * dim) if i % 13 == 5 else inputs.uniform_rhs(dim, n, 1200 + i)
+        reqs.append(f)
+    f_of, done, i, steps = {}, {}, 0, 0
+    while i < len(reqs) or len(done) < len(reqs):
+        for _ in range(int(rng.integers(0, 4))):
+            if i < len(reqs):
+                f_of[m.mg_server_submit(ctx, reqs[i])] = reqs[i]
+                i += 1
+        m.mg_server_step(ctx)
+        for rid in m.mg_server_poll(ctx):
+            st, u, cyc, rr, lat = m.mg_server_fetch(ctx, rid, shape=f_of[rid].shape)
+            done[rid] = (st, u, cyc)
+        steps += 1
+        assert steps < 3000
+    assert sorted(done) == sorted(f_of)
+    for rid, (st, u, cyc) in done.items():
+        f = f_of[rid]
+        assert st == 0
+        u_ref, h_ref, _ = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-8, max_cycles=40)
+        assert cyc == len(h_ref) - 1, rid
+        assert np.array_equal(u, u_ref), rid
+    m.mg_destroy(ctx)
