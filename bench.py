@@ -157,6 +157,8 @@ def bench_batched(args, mg, torch):
     mg.mg_destroy(ctx)
     t_batch = (t1 - t0) / args.steps
     log(f"[bench] batched FP32-IR: {t_batch * 1e3:.2f} ms per batch, status {st}, cycles {min(cyc)}..{max(cyc)}")
+    if args.no_fp64:
+        return {"metric": "batched only", "value": dof / t_batch, "unit": "DoF/s", "ms_per_step": t_batch * 1e3}
     # the same grids one at a time, plain FP64 (one context per size)
     ctxs = {n: mg.Solver(mg.Params(dim=2, n=n, precision=mg.PREC_FP64)) for n in set(edges)}
     for u in us:
@@ -281,6 +283,32 @@ def bench_serving(args, mg, torch):
         log(f"[bench] serving lambda={rec['lambda']:.1f}/s: {rec['solves_per_s']:.1f} solves/s, "
             f"p50 {rec['p50_ms']:.2f} ms, p99 {rec['p99_ms']:.2f} ms")
     mg.mg_destroy(ctx)
+    # the plain FP64 GPU solve of the same requests, one after another, with the
+    # same host transfers (rhs up, solution back); one context per size
+    seq = sat_reqs[: min(len(sat_reqs), args.serve_fp64_requests)]
+    ctxs = {}
+    for r in seq:
+        if (r.dim, r.n) not in ctxs:
+            ctxs[(r.dim, r.n)] = mg.Solver(mg.Params(dim=r.dim, n=r.n, precision=mg.PREC_FP64))
+
+    def solve64(r):
+        fd = torch.from_numpy(rhs_for(r)).to("cuda")
+        u = torch.zeros_like(fd)
+        ctxs[(r.dim, r.n)].solve(u, fd, tol=1e-8, max_cycles=50)
+        out_for(r.dim, r.n)[...] = u.cpu().numpy()
+
+    for r in seq[:8]:
+        solve64(r)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for r in seq:
+        solve64(r)
+    torch.cuda.synchronize()
+    fp64_rate = len(seq) / (time.perf_counter() - ta)
+    for c in ctxs.values():
+        c.close()
+    log(f"[bench] plain FP64 GPU solves of the same requests one by one: {fp64_rate:.1f} solves/s "
+        f"(served mix {mu_sat / fp64_rate:.1f}x)")
     mean_dof = float(np.mean([(r.n - 2) ** r.dim for r in sat_reqs]))
     return {
         "metric": "fine-grid DoF/s + HBM GB/s %peak; solves/s & p99 latency at 1e-8 residual",
@@ -301,6 +329,8 @@ def bench_serving(args, mg, torch):
                    "arrivals": "exponential inter-arrival, seed 4", "tol": 1e-8,
                    "budget_gib": args.serve_budget_gib, "slots_per_dim": args.serve_slots},
         "extra": {"saturated_solves_per_s": mu_sat, "mean_dof_per_request": mean_dof,
+                  "fp64_sequential_solves_per_s": fp64_rate, "fp64_sequential_requests": len(seq),
+                  "served_over_fp64_sequential": mu_sat / fp64_rate,
                   "saturated_host_seconds": host, "saturated_p50_ms": sat_p[0], "saturated_p99_ms": sat_p[1],
                   "saturated_dof_per_s": mu_sat * mean_dof, "lambda_sweep": sweep},
     }
@@ -320,6 +350,8 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-inflight", type=int, default=64, help="requests in flight in the saturated run")
+    ap.add_argument("--serve-fp64-requests", type=int, default=300,
+                    help="requests of the mix solved one by one in plain FP64 for comparison")
     ap.add_argument("--serve-budget-gib", type=int, default=48)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run the plain copy kernel over 1 GiB three times (counter calibration)")

@@ -425,6 +425,25 @@ struct Engine {
         return MG_OK;
     }
 
+    // Autotune the FP32 sweeps and restrictions of every level above the
+    // coarse tail for the current members (MG_AUTOTUNE=0 keeps the heuristic).
+    int tune() {
+        const char* at = std::getenv("MG_AUTOTUNE");
+        if ((at && at[0] == '0') || members.empty()) return MG_OK;
+        int r = rebuild();
+        if (r != MG_OK) return r;
+        const int amax = (int)groups.size();
+        const int stop = tailplan.ninst > 0 ? tailplan.first : amax;
+        BCK(launch_fill_int(d_done, 0, cap, s));  // kernels skip instances whose flag is set
+        for (int g = 0; g < stop; ++g) {
+            const int a = amax - g;
+            BCK(tune_group(dim, prob.smoother, groups[(size_t)g].d, groups[(size_t)g].ninst, groups[(size_t)g].n,
+                           tiles[(size_t)a], s));
+        }
+        BCK(launch_fill_int(d_done, 1, cap, s));
+        return rebuild();
+    }
+
     // Initial residual (rho_0) of the fresh members; their stop flags open.
     hipError_t start_fresh() {
         if (fresh.empty()) return hipSuccess;
@@ -792,6 +811,11 @@ int mg_batch_setup(int count, const mg_params* each, void* stream, mg_ctx** out)
         return r;
     }
     for (Inst& I : B->inst) B->eng->members.push_back(&I);
+    r = B->eng->tune();
+    if (r != MG_OK) {
+        delete B;
+        return r;
+    }
     if (hipStreamSynchronize(s) != hipSuccess) {
         delete B;
         return MG_EDEVICE;

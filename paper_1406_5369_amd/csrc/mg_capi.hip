@@ -326,7 +326,8 @@ int run_chunk(mg_ctx* c, int K, double tol, int max_cycles) {
 // tuning changes time only.  Choices are cached per process.
 // ---------------------------------------------------------------------------
 
-typedef std::tuple<int, int, int, int, int, int, int> TuneKey;  // dim, elem, n, family, smoother, var, mode
+// dim, elem, n, family, smoother, var, mode, batch (0: one grid; else bit length of the instance count)
+typedef std::tuple<int, int, int, int, int, int, int, int> TuneKey;
 std::mutex g_tune_mu;
 std::map<TuneKey, TileCfg> g_tune;
 
@@ -453,7 +454,7 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
         TileCfg* vcfg[3] = {&tl[(size_t)l].smooth, &tl[(size_t)l].smooth_zg, &tl[(size_t)l].smooth_pro};
         for (int v = 0; v < 3; ++v) {
             const int fl = vflags[v];
-            TuneKey ks{dim, L.elem, n, 0, sm, var ? 1 : 0, 10 + v};
+            TuneKey ks{dim, L.elem, n, 0, sm, var ? 1 : 0, 10 + v, 0};
             if (!tune_lookup(ks, &cfg)) {
                 cfg = pick_fastest(tune_candidates(dim, n - 2, true, 0, L.elem, var), *vcfg[v], [&](TileCfg t) {
                     return L.elem == 8 ? launch_smooth<double>(dim, sm, var, d, 1, n, 0, fl, t, s)
@@ -463,7 +464,7 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
             }
             *vcfg[v] = cfg;
         }
-        TuneKey kr{dim, L.elem, n, 1, 0, var ? 1 : 0, 0};
+        TuneKey kr{dim, L.elem, n, 1, 0, var ? 1 : 0, 0, 0};
         if (!tune_lookup(kr, &cfg)) {
             std::vector<TileCfg> cands;
             for (TileCfg t : tune_candidates(dim, (n - 1) / 2 - 1, false, 1, L.elem, var))
@@ -480,6 +481,48 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
     (void)hipFree(d);
     return e != hipSuccess ? e : e2;
 }
+
+}  // namespace
+
+// Batched launches: the three sweep variants and the restriction of one
+// absolute level, launched over all 'count' instances of that level as the
+// batched V-cycle launches them.  Runs on the instances' own level arrays
+// (clear at setup; sweeps and restrictions write inner nodes only).
+namespace mg {
+hipError_t tune_group(int dim, int smoother, const GridDesc* d, int count, int n, Tiles& t, hipStream_t s) {
+    if (count <= 0 || n <= 3 || npts(dim, n) * (size_t)count < kTuneMinPoints) return hipSuccess;
+    int bucket = 0;
+    for (int c = count; c; c >>= 1) ++bucket;
+    TileCfg cfg;
+    const int vflags[3] = {0, SWEEP_ZERO_GUESS, SWEEP_PROLONG};
+    TileCfg* vcfg[3] = {&t.smooth, &t.smooth_zg, &t.smooth_pro};
+    for (int v = 0; v < 3; ++v) {
+        const int fl = vflags[v];
+        TuneKey ks{dim, 4, n, 0, smoother, 0, 10 + v, bucket};
+        if (!tune_lookup(ks, &cfg)) {
+            cfg = pick_fastest(tune_candidates(dim, n - 2, true, 0, 4, false), *vcfg[v], [&](TileCfg c) {
+                return launch_smooth<float>(dim, smoother, false, d, count, n, 0, fl, c, s);
+            }, s);
+            tune_store(ks, cfg);
+        }
+        *vcfg[v] = cfg;
+    }
+    TuneKey kr{dim, 4, n, 1, 0, 0, 0, bucket};
+    if (!tune_lookup(kr, &cfg)) {
+        std::vector<TileCfg> cands;
+        for (TileCfg c : tune_candidates(dim, (n - 1) / 2 - 1, false, 1, 4, false))
+            if (c.by >= 8) cands.push_back(c);
+        cfg = pick_fastest(cands, t.restr, [&](TileCfg c) {
+            return launch_restrict<float>(dim, false, d, count, n, 0, c, s);
+        }, s);
+        tune_store(kr, cfg);
+    }
+    t.restr = cfg;
+    return hipStreamSynchronize(s);
+}
+}  // namespace mg
+
+namespace {
 
 hipError_t autotune(mg_ctx* c) {
     const int dim = c->p.dim, n = c->p.n;
@@ -500,7 +543,7 @@ hipError_t autotune(mg_ctx* c) {
     if (e == hipSuccess && N >= kTuneMinPoints) {
         const bool var = c->prob.var;
         const int mode = c->p.precision == MG_PREC_FP64 ? 0 : 1;
-        TuneKey kn{dim, 8, n, 2, 0, var ? 1 : 0, mode};
+        TuneKey kn{dim, 8, n, 2, 0, var ? 1 : 0, mode, 0};
         TileCfg cfg;
         if (!tune_lookup(kn, &cfg)) {
             const std::vector<TileCfg> cands = tune_candidates(dim, n - 2, true, 2, 8, var);

@@ -29,6 +29,9 @@ struct Tiles {
 // for levels too small to be worth timing): enough workgroups to cover the
 // chip (z-chunks in 3D) and the smallest tile height on small grids.
 Tiles default_tiles(int dim, int elem_bytes, int n, int smoother);
+// Autotune the FP32 sweeps and restriction of one absolute level of a batch:
+// 'count' instances of edge n, descriptors d (device).  Cached per process.
+hipError_t tune_group(int dim, int smoother, const GridDesc* d, int count, int n, Tiles& t, hipStream_t s);
 int heuristic_zchunk(int dim, int n, int by, int halo, int target_blocks);
 
 // Device buffers of one instance's hierarchy in working precision T
