@@ -54,6 +54,8 @@ def sweep_kernel(dim: int, word: int, by: int, pd: int, var: bool = False, wv: i
     v = "true" if var else "false"
     if dim == 2:
         return f"mg::k_smooth2d<{t}, 0, {v}, {by}, 0>"
+    if wv == 1:  # one wavefront per tile, rows in registers
+        return f"mg::k_smooth3d_rc<{t}, 0, {v}, {by}, {pd}, 0>"
     return f"mg::k_smooth3d<{t}, 0, {v}, {by}, {pd}, 0, {wv}>"
 
 
