@@ -8,9 +8,11 @@ boundary), by FP32 V(2,2) red-black Gauss-Seidel cycles inside FP64 iterative
 refinement.  Inputs are resident in HBM before the timed region.
 
 Printed: one JSON line with fine-grid DoF/s (value), the plain FP64 solve of
-the same problem for context, the roofline of the dominant kernel (finest-level
-FP32 smoothing sweep, timed with HIP events on the solver's stream over the
-timed region) and the CPU oracle timed on a bounded sample.
+the same problem for context, the roofline of the dominant kernel (of the
+finest-level FP32 smoothing sweep and the FP64 refinement pass, the one with
+the larger total time; both timed with HIP events on the solver's stream over
+the timed region, the other reported beside it) and the CPU oracle timed on a
+bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
 """
@@ -26,7 +28,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from paper_1406_5369_amd.profsum import kernel_source_hash, sweep_blocks, sweep_kernel  # noqa: E402
+from paper_1406_5369_amd.profsum import (  # noqa: E402
+    kernel_source_hash,
+    pass_blocks,
+    pass_kernel,
+    sweep_blocks,
+    sweep_kernel,
+)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, datasheet
 
@@ -60,11 +68,12 @@ def make_rhs(w):
     return inputs.uniform_rhs(w["dim"], w["n"], w["rhs"][1])
 
 
-def traffic_record(workload: str, tiles) -> dict | None:
-    """HBM bytes per launch of the dominant kernel (finest-level sweep with the
-    given tile geometry) from the committed rocprofv3 counter runs (FETCH_SIZE
-    and WRITE_SIZE, each calibrated on a 1 GiB copy), if they were taken on the
-    current kernel source; else None."""
+def traffic_record(workload: str, tiles, key: str = "configs") -> dict | None:
+    """HBM bytes per launch of a finest-level kernel (the sweep, key "configs",
+    or the refinement pass, key "pass_configs", with the given tile geometry)
+    from the committed rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, each
+    calibrated on a 1 GiB copy), if they were taken on the current kernel
+    source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -75,7 +84,7 @@ def traffic_record(workload: str, tiles) -> dict | None:
         return None
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec.get("configs", {}).get(",".join(str(int(t)) for t in tiles))
+    return rec.get(key, {}).get(",".join(str(int(t)) for t in tiles))
 
 
 def cpu_baseline(w, gpu_steps: int, budget_s: float):
@@ -441,45 +450,69 @@ def main(argv=None) -> int:
             log(f"[bench] step {i}: status {st}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    launches, sweep_ms = mg.mg_prof_read(solver.ctx)
+    launches, sweep_ms = mg.mg_prof_read(solver.ctx, 0)
+    pass_launches, pass_ms = mg.mg_prof_read(solver.ctx, 1)
     mg.mg_prof_enable(solver.ctx, False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = dof * args.steps / (t1 - t0)
     log(f"[bench] {args.steps} solves: {ms_per_step:.3f} ms/solve, cycles {cycles}, {value / 1e9:.3f} GDoF/s")
+    # The timed solves above launch eagerly (the event brackets need it); the
+    # same solves with the steps captured in HIP graphs, for comparison.
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for i in range(args.steps):
+        one(i)
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - tg0) * 1e3 / args.steps
+    log(f"[bench] same solves with graph-captured steps: {ms_graph:.3f} ms/solve")
 
-    # dominant kernel: finest-level smoothing sweep (reads u and f, writes u: 3 words per inner node);
-    # the zero-guess first sweep of each cycle is excluded from the event brackets.
+    # The two largest finest-level kernels, timed by the library with HIP events
+    # on the solver's stream over the timed solves (launches of steps after a
+    # solve finished, which do no work, not counted): the plain smoothing sweep
+    # (reads u and f, writes u: 3 words per inner node, 4 with k) and the FP64
+    # refinement pass (reads u, f, e, writes u, r: 32 B per inner node, +8 with
+    # k) or, in FP64 solves, the norm pass (reads u, f: 16 B, +8 with k).  The
+    # one with the larger total time is reported as the dominant kernel.
     word = 4 if w["precision"] == 1 else 8
     var = kd is not None
-    bytes_per_launch = (4 if var else 3) * word * dof  # u, f (and k) read, u written
-    avg_ms = sweep_ms / max(launches, 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    ir = w["precision"] == 1
+
+    def roof(kernel, blocks, note, n_launch, total_ms, bytes_per_launch, tr):
+        avg_ms = total_ms / max(n_launch, 1)
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if n_launch else 0.0
+        r = {"bound": "hbm", "kernel": kernel, "blocks": blocks, "note": note, "launches": n_launch,
+             "avg_launch_ms": avg_ms, "total_ms": total_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+             "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+             "copy_ceiling": copy_gbps, "frac_of_copy_ceiling": achieved / copy_gbps, "traffic": None}
+        if tr and tr.get("kernel") == kernel and tr.get("blocks") == blocks:
+            r["traffic"] = tr["bytes_per_launch"]
+            r["traffic_ratio_to_algorithmic"] = tr["ratio_to_algorithmic"]
+        return r
+
     by, zchunk, pd, wv = mg.mg_tile_config(solver.ctx, 0, 0)
     kname = sweep_kernel(dim, word, by, pd, var, wv)
-    kblocks = sweep_blocks(dim, n, by, zchunk)
-    roofline = {
-        "bound": "hbm",
-        "kernel": kname,
-        "blocks": kblocks,
-        "note": "finest-level RBGS sweeps that read the previous iterate (the zero-guess first sweep excluded)",
-        "launches": launches,
-        "avg_launch_ms": avg_ms,
-        "achieved": achieved,
-        "peak": HBM_PEAK_GBPS,
-        "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBPS,
-        "copy_ceiling": copy_gbps,
-        "frac_of_copy_ceiling": achieved / copy_gbps,
-        "traffic": None,
-    }
-
-    tr = traffic_record(args.workload, (by, zchunk, pd, wv))
-    if tr and tr.get("kernel") == kname and tr.get("blocks") == kblocks:
-        roofline["traffic"] = tr["bytes_per_launch"]
-        roofline["traffic_ratio_to_algorithmic"] = tr["ratio_to_algorithmic"]
+    sweep_roof = roof(kname, sweep_blocks(dim, n, by, zchunk),
+                      "finest-level RBGS sweeps that read the previous iterate (zero-iterate and fused-correction "
+                      "variants excluded)", launches, sweep_ms, (4 if var else 3) * word * dof,
+                      traffic_record(args.workload, (by, zchunk, pd, wv)))
+    pby, pzc, ppd, pwv = mg.mg_tile_config(solver.ctx, 0, 2)
+    pass_roof = roof(pass_kernel(dim, pby, ppd, var, ir, pwv), pass_blocks(dim, n, pby, pzc),
+                     "finest-level FP64 refinement pass (u += e, r = f - A u, r to FP32, norm partials)" if ir
+                     else "finest-level FP64 residual-norm pass", pass_launches, pass_ms,
+                     ((32 if ir else 16) + (8 if var else 0)) * dof,
+                     traffic_record(args.workload, (pby, pzc, ppd, pwv), key="pass_configs"))
+    if pass_roof["total_ms"] > sweep_roof["total_ms"]:
+        roofline, other = pass_roof, sweep_roof
+    else:
+        roofline, other = sweep_roof, pass_roof
+    log(f"[bench] finest sweep {sweep_roof['avg_launch_ms'] * 1e3:.1f} us x {launches}: "
+        f"{sweep_roof['achieved']:.0f} GB/s; refinement/norm pass {pass_roof['avg_launch_ms'] * 1e3:.1f} us x "
+        f"{pass_launches}: {pass_roof['achieved']:.0f} GB/s")
 
     extra = {"solves_per_s": args.steps / (t1 - t0), "cycles_per_solve": cycles[-1],
+             "ms_per_solve_graph_captured": ms_graph,
              "kernel_source_hash": kernel_source_hash(),
+             "roofline_other_kernel": other,
              "fine_tiles": {fam: mg.mg_tile_config(solver.ctx, 0, i) for i, fam in
                             enumerate(["smooth", "restrict", "norm_or_refinement", "smooth_zero_guess",
                                        "smooth_fused_correction"])}}

@@ -162,10 +162,11 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
 
 /* FP64 refinement pass: u_out = u_in + e on inner nodes, r = (float)(f - A u_out)
  * on inner nodes (FP64 operator, FP64 k or NULL), *norm_out (HOST) = ||f - A u_out||_2.
- * e and r are FP32 arrays; u_out's and r's boundaries are not written.
- * Synchronises the stream. */
+ * e and r are FP32 arrays; u_out's and r's boundaries are not written.  'by',
+ * 'zchunk' pick the tile (0 = default); 'waves' (3D) is 4 or 8 wavefronts per
+ * workgroup (8 needs by >= 16; 0 = 4).  Synchronises the stream. */
 int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
-                       double* u_out, float* r, double* norm_out, int by, int zchunk, void* stream);
+                       double* u_out, float* r, double* norm_out, int by, int zchunk, int waves, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched solves: many independent grids (sizes may differ) in one context.
@@ -229,10 +230,19 @@ int mg_server_info(mg_ctx* ctx, size_t* used_bytes, int* active, int* queued);
  * Measurement hooks.
  * ------------------------------------------------------------------------- */
 
-/* When on, every finest-level smoothing launch of the context is bracketed by
- * HIP events recorded on the context's stream; mg_prof_read returns the
- * number of such launches and their summed duration in ms (and resets). */
+/* When on, mg_solve runs without graph capture and brackets two kernels of
+ * every refinement step (or cycle) with HIP events on the context's stream:
+ * kernel 0, the finest-level smoothing sweeps that read the previous iterate
+ * (not the zero-iterate or fused-correction variants); kernel 1, the
+ * finest-level FP64 refinement pass (mixed precision) or norm pass (FP64).
+ * Launches of steps past the solve's last step (queued before the stop test
+ * was read; they find the stop flag set and do no work) are not counted.
+ * mg_prof_read_kernel returns the number of counted launches of one kernel
+ * and their summed duration in ms since the last read, and resets them;
+ * mg_prof_read is kernel 0.  MG_EINVAL for a batch or server handle or
+ * another kernel number. */
 int mg_prof_enable(mg_ctx* ctx, int on);
+int mg_prof_read_kernel(mg_ctx* ctx, int kernel, int* launches, double* total_ms);
 int mg_prof_read(mg_ctx* ctx, int* launches, double* total_ms);
 
 /* Plain device-to-device copy kernel of 'bytes' bytes (multiple of 16):

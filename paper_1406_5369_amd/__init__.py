@@ -88,9 +88,10 @@ def lib():
             "mg_level_residual_restrict": (i, [i, i, i, p, p, p, p, i, i, p]),
             "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
-            "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, p]),
+            "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, p]),
             "mg_prof_enable": (i, [p, i]),
             "mg_prof_read": (i, [p, C.POINTER(i), C.POINTER(d)]),
+            "mg_prof_read_kernel": (i, [p, i, C.POINTER(i), C.POINTER(d)]),
             "mg_copy_kernel": (i, [p, p, sz, p]),
             "mg_batch_setup": (i, [i, p, p, C.POINTER(p)]),
             "mg_batch_solve": (i, [p, p, p, d, i, p, p]),
@@ -291,7 +292,7 @@ def mg_level_coarsest(u, f, k=None, stream=None) -> None:
                                    _dptr(f, dt, (3,) * dim, "f"), _stream(stream)), "mg_level_coarsest")
 
 
-def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, stream=None) -> float:
+def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, waves=0, stream=None) -> float:
     import torch
 
     dim, n = f.dim(), f.shape[0]
@@ -300,7 +301,7 @@ def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, stream=None
     _check(lib().mg_level_ir_update(dim, n, _dptr(k, torch.float64, sh, "k"), _dptr(u_in, torch.float64, sh, "u_in"),
                                     _dptr(e, torch.float32, sh, "e"), _dptr(f, torch.float64, sh, "f"),
                                     _dptr(u_out, torch.float64, sh, "u_out"), _dptr(r, torch.float32, sh, "r"),
-                                    C.byref(out), by, zchunk, _stream(stream)), "mg_level_ir_update")
+                                    C.byref(out), by, zchunk, waves, _stream(stream)), "mg_level_ir_update")
     return out.value
 
 
@@ -308,11 +309,12 @@ def mg_prof_enable(ctx: int, on: bool = True) -> None:
     _check(lib().mg_prof_enable(ctx, int(on)), "mg_prof_enable")
 
 
-def mg_prof_read(ctx: int):
-    """(launches, total ms) of the finest-level smoothing launches since enabling."""
+def mg_prof_read(ctx: int, kernel: int = 0):
+    """(launches, total ms) since the last read of the measured finest-level launches of a kernel
+    (0: plain smoothing sweeps, 1: refinement / norm pass) in steps the solves really ran."""
     n = C.c_int(0)
     ms = C.c_double(0.0)
-    _check(lib().mg_prof_read(ctx, C.byref(n), C.byref(ms)), "mg_prof_read")
+    _check(lib().mg_prof_read_kernel(ctx, kernel, C.byref(n), C.byref(ms)), "mg_prof_read_kernel")
     return n.value, ms.value
 
 

@@ -226,38 +226,60 @@ int* ctl_steps(mg_ctx* c) { return c->d_ctrl + 1; }
 int* ctl_status(mg_ctx* c) { return c->d_ctrl + 2; }
 
 // FP64 norm of the bound (u, f) into d_norm (partials + fixed-order finalize).
-hipError_t enqueue_norm(mg_ctx* c, hipStream_t s) {
+// With 'step' > 0 and measurement on, the finest-level pass (not its
+// finalize) is bracketed by an event pair tagged (step, kernel 1).
+bool prof_begin(mg_ctx* c, int step, hipStream_t s) {
+    if (step <= 0 || !c->prof_on || c->prof_n + 2 > (int)c->prof_ev.size()) return false;
+    return hipEventRecord(c->prof_ev[(size_t)c->prof_n], s) == hipSuccess;
+}
+void prof_end(mg_ctx* c, int step, int kind, hipStream_t s) {
+    if (hipEventRecord(c->prof_ev[(size_t)c->prof_n + 1], s) != hipSuccess) return;
+    c->prof_n += 2;
+    c->prof_step.push_back(step);
+    c->prof_kind.push_back(kind);
+}
+
+hipError_t enqueue_norm(mg_ctx* c, hipStream_t s, int step = 0) {
     const bool var = c->prob.var;
     const int nparts = norm_tiles(c->p.dim, c->p.n, c->top.norm);
+    const bool timed = prof_begin(c, step, s);
     hipError_t e = launch_norm(c->p.dim, var, c->d_top, 1, c->p.n, 0, c->d_partial, c->pstride, c->top.norm, s);
+    if (timed) prof_end(c, step, 1, s);
     if (e != hipSuccess) return e;
     return launch_norm_finalize(c->d_partial, c->pstride, nparts, 0, 1, c->d_norm, s);
 }
 
-hipError_t enqueue_ir(mg_ctx* c, int sel, int flags, hipStream_t s) {
+hipError_t enqueue_ir(mg_ctx* c, int sel, int flags, hipStream_t s, int step = 0) {
     const int nparts = norm_tiles(c->p.dim, c->p.n, c->top.norm);
+    const bool timed = prof_begin(c, step, s);
     hipError_t e = launch_ir_update(c->p.dim, c->prob.var, c->d_ir, 1, c->p.n, sel, flags, c->d_partial, c->pstride,
                                     c->top.norm, s);
+    if (timed) prof_end(c, step, 1, s);
     if (e != hipSuccess) return e;
     return launch_norm_finalize(c->d_partial, c->pstride, nparts, 0, 1, c->d_norm, s);
 }
 
 // K solve steps (cycle + residual norm + stop test), IR steps alternate the
 // FP64 ping-pong starting from sel 0 (K even keeps the parity per chunk).
-hipError_t enqueue_steps(mg_ctx* c, int K, double tol, int max_cycles, hipStream_t s, bool prof) {
+// With 'prof', step0 + i + 1 tags the measured launches of step i.
+hipError_t enqueue_steps(mg_ctx* c, int K, double tol, int max_cycles, hipStream_t s, bool prof, int step0 = 0) {
     hipEvent_t* pev = prof ? c->prof_ev.data() : nullptr;
     int* pn = prof ? &c->prof_n : nullptr;
     const int pcap = (int)c->prof_ev.size();
     for (int i = 0; i < K; ++i) {
         hipError_t e;
+        const int step = prof ? step0 + i + 1 : 0;
+        const int n0 = c->prof_n;
         if (c->p.precision == MG_PREC_FP64) {
             e = vcycle<double>(c->prob, c->G64, false, c->tl64, s, pev, pn, pcap, &c->tail64);
+            for (int j = n0; prof && j < c->prof_n; j += 2) c->prof_step.push_back(step), c->prof_kind.push_back(0);
             if (e != hipSuccess) return e;
-            e = enqueue_norm(c, s);
+            e = enqueue_norm(c, s, step);
         } else {
             e = vcycle<float>(c->prob, c->G32, true, c->tl32, s, pev, pn, pcap, &c->tail32);
+            for (int j = n0; prof && j < c->prof_n; j += 2) c->prof_step.push_back(step), c->prof_kind.push_back(0);
             if (e != hipSuccess) return e;
-            e = enqueue_ir(c, i & 1, 0, s);
+            e = enqueue_ir(c, i & 1, 0, s, step);
         }
         if (e != hipSuccess) return e;
         e = launch_stop_test(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist,
@@ -285,10 +307,10 @@ int ensure_hist(mg_ctx* c, int cap) {
     return MG_OK;
 }
 
-int run_chunk(mg_ctx* c, int K, double tol, int max_cycles) {
+int run_chunk(mg_ctx* c, int K, double tol, int max_cycles, int step0) {
     const bool use_graph = !c->prof_on && c->use_graphs;
     if (!use_graph) {
-        CK(enqueue_steps(c, K, tol, max_cycles, c->stream, c->prof_on));
+        CK(enqueue_steps(c, K, tol, max_cycles, c->stream, c->prof_on, step0));
         return MG_OK;
     }
     if (!c->graph || c->graph_steps != K || c->graph_tol != tol || c->graph_max != max_cycles) {
@@ -333,14 +355,16 @@ std::map<TuneKey, TileCfg> g_tune;
 
 constexpr size_t kTuneMinPoints = 1u << 16;
 
-// Candidate launch geometries.  family 0 (3D smoothing) also varies the
-// wavefronts per workgroup (8 wavefronts for 16- and 32-row tiles).
+// Candidate launch geometries.  In 3D, smoothing (family 0) and the norm /
+// refinement pass (family 2) also vary the wavefronts per workgroup (8 for
+// 16- and 32-row tiles); smoothing also runs one wavefront per tile with 8 or
+// 12 rows in registers.
 std::vector<TileCfg> tune_candidates(int dim, int planes, bool with_pd, int family, int elem, bool var) {
     std::vector<TileCfg> v;
     const int geo[7][2] = {{8, 4}, {16, 4}, {32, 4}, {16, 8}, {32, 8}, {8, 1}, {12, 1}};
     for (const auto& g : geo) {
         const int by = g[0], wv = g[1];
-        if (wv != 4 && (dim == 2 || family != 0)) continue;
+        if (wv != 4 && (dim == 2 || family == 1 || (family == 2 && wv == 1))) continue;
         if (by > max_tile_rows(dim, elem, var, family, wv)) continue;
         if (dim == 2) {
             v.push_back({by, 1, 1, 4});
@@ -781,6 +805,9 @@ int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
     if (r != MG_OK) return r;
     hipStream_t s = c->stream;
     const bool ir = c->p.precision == MG_PREC_FP32_IR;
+    c->prof_n = 0;  // measured launches are tagged per solve
+    c->prof_step.clear();
+    c->prof_kind.clear();
     // rho_0 (clear the stop flag a previous solve left set first: every kernel honours it)
     CK(launch_fill_int(ctl_done(c), 0, 1, s));
     if (ir) CK(enqueue_ir(c, 0, IR_NO_UPDATE, s));
@@ -799,7 +826,7 @@ int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
     int enqueued = 0;
     while (!done && enqueued < max_cycles) {
         const int k = ir ? K : std::min(K, max_cycles - enqueued);
-        r = run_chunk(c, k, tol, max_cycles);
+        r = run_chunk(c, k, tol, max_cycles, enqueued);
         if (r != MG_OK) return r;
         enqueued += k;
         CK(hipMemcpyAsync(c->h_pin, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -821,6 +848,21 @@ int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
         CK(hipMemcpyAsync(u, c->u64_scratch, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         CK(hipStreamSynchronize(s));
     }
+    if (c->prof_on) {
+        // launches of steps past the last one the solve ran found the stop
+        // flag set and did no work: they are not counted
+        for (size_t j = 0; j < c->prof_step.size() && 2 * j + 1 < (size_t)c->prof_n; ++j) {
+            if (c->prof_step[j] > steps) continue;
+            float t = 0.f;
+            CK(hipEventElapsedTime(&t, c->prof_ev[2 * j], c->prof_ev[2 * j + 1]));
+            const int k = c->prof_kind[j] & 1;
+            c->prof_launches[k] += 1;
+            c->prof_ms[k] += (double)t;
+        }
+        c->prof_n = 0;
+        c->prof_step.clear();
+        c->prof_kind.clear();
+    }
     if (cycles_done) *cycles_done = steps;
     if (status == 0) return MG_OK;
     if (status == -5) return MG_EDIVERGED;
@@ -832,30 +874,24 @@ int mg_prof_enable(mg_ctx* c, int on) {
     if (is_batch_handle(c)) return MG_EINVAL;
     c->prof_on = on != 0;
     c->prof_n = 0;
-    c->prof_launches = 0;
-    c->prof_ms = 0.0;
+    c->prof_step.clear();
+    c->prof_kind.clear();
+    c->prof_launches[0] = c->prof_launches[1] = 0;
+    c->prof_ms[0] = c->prof_ms[1] = 0.0;
     return MG_OK;
 }
 
-int mg_prof_read(mg_ctx* c, int* launches, double* total_ms) {
-    if (!c) return MG_EINVAL;
+int mg_prof_read_kernel(mg_ctx* c, int kernel, int* launches, double* total_ms) {
+    if (!c || (kernel != 0 && kernel != 1)) return MG_EINVAL;
     if (is_batch_handle(c)) return MG_EINVAL;
-    CK(hipStreamSynchronize(c->stream));
-    double ms = 0.0;
-    for (int i = 0; i + 1 < c->prof_n; i += 2) {
-        float t = 0.f;
-        CK(hipEventElapsedTime(&t, c->prof_ev[(size_t)i], c->prof_ev[(size_t)i + 1]));
-        ms += (double)t;
-    }
-    c->prof_launches += c->prof_n / 2;
-    c->prof_ms += ms;
-    c->prof_n = 0;
-    if (launches) *launches = c->prof_launches;
-    if (total_ms) *total_ms = c->prof_ms;
-    c->prof_launches = 0;
-    c->prof_ms = 0.0;
+    if (launches) *launches = c->prof_launches[kernel];
+    if (total_ms) *total_ms = c->prof_ms[kernel];
+    c->prof_launches[kernel] = 0;
+    c->prof_ms[kernel] = 0.0;
     return MG_OK;
 }
+
+int mg_prof_read(mg_ctx* c, int* launches, double* total_ms) { return mg_prof_read_kernel(c, 0, launches, total_ms); }
 
 int mg_copy_kernel(void* dst, const void* src, size_t bytes, void* stream) {
     if (!dst || !src || bytes % 16 != 0) return MG_EINVAL;
@@ -880,7 +916,7 @@ static bool valid_cfg(TileCfg c, int dim, int elem, bool var, int family) {
         if (dim != 3 || family != 0 || (c.by != 8 && c.by != 12)) return false;
     } else {
         if (c.by != 8 && c.by != 16 && c.by != 32) return false;
-        if (c.wv != 4 && !(c.wv == 8 && dim == 3 && family == 0 && c.by >= 16)) return false;
+        if (c.wv != 4 && !(c.wv == 8 && dim == 3 && (family == 0 || family == 2) && c.by >= 16)) return false;
     }
     return c.by <= max_tile_rows(dim, elem, var, family, c.wv) && c.zchunk >= 1 && (c.pd == 1 || c.pd == 2);
 }
@@ -984,10 +1020,11 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
 }
 
 int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
-                       double* u_out, float* r, double* norm_out, int by, int zchunk, void* stream) {
+                       double* u_out, float* r, double* norm_out, int by, int zchunk, int waves, void* stream) {
     if (!valid_edge(dim, n) || n < 5) return MG_EINVAL;
     if (!u_in || !e || !f || !u_out || !r || !norm_out || u_in == u_out) return MG_EINVAL;
-    const TileCfg cfg = pick_cfg(dim, 8, n, 0, by, zchunk, 2);
+    TileCfg cfg = pick_cfg(dim, 8, n, 0, by, zchunk, 2);
+    if (waves) cfg.wv = waves;
     if (!valid_cfg(cfg, dim, 8, k != nullptr, 2)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     IRDesc h{};

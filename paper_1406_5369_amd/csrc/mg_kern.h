@@ -183,17 +183,23 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 }
 
 // Deterministic workgroup sum of one double per thread (fixed shuffle order,
-// then the four wave partials in order).  Result valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* red4) {
+// then the WV wave partials pairwise in order).  Result valid in thread 0.
+template <int WV>
+__device__ __forceinline__ double block_sum_w(double v, double* red) {
+    static_assert(WV == 4 || WV == 8, "four or eight wavefronts");
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red4[w] = v;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
     double s = 0.0;
-    if (threadIdx.x == 0) s = (red4[0] + red4[1]) + (red4[2] + red4[3]);
+    if (threadIdx.x == 0) {
+        s = (red[0] + red[1]) + (red[2] + red[3]);
+        if constexpr (WV == 8) s = s + ((red[4] + red[5]) + (red[6] + red[7]));
+    }
     return s;
 }
+__device__ __forceinline__ double block_sum(double v, double* red4) { return block_sum_w<4>(v, red4); }
 
 // Neighbours along x from the adjacent lanes of the same wavefront (DPP
 // full-wave shifts: lane i reads lane i-1 / i+1).  Lanes 0 and 63 get 0 and

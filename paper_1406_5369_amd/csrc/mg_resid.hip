@@ -54,10 +54,12 @@ __global__ __launch_bounds__(NT) void k_norm2d(const GridDesc* __restrict__ desc
 
 // 3D residual of the FP64 finest level, marching along z.  IR selects the
 // refinement variant: the plane entering the ring is u_in + e (inner nodes),
-// its owned part is written to u_out, and r is stored in FP32.
-template <bool VAR, int BY, int PD, bool IR>
+// its owned part is written to u_out, and r is stored in FP32.  WV wavefronts
+// per workgroup; a thread holds rows w, w + WV, ... of the tile.
+template <bool VAR, int BY, int PD, bool IR, int WV>
 struct Resid3D {
-    static constexpr int TX = BX - 2, TY = BY - 2, RPT = BY / 4;
+    static constexpr int TX = BX - 2, TY = BY - 2, RPT = BY / WV;
+    static_assert(RPT >= 1 && RPT * WV == BY, "tile rows must be a multiple of the wavefronts");
     double (*U)[BY][BX];
     double (*K)[BY][BX];
     const MG_GLOBAL double* __restrict__ uin;
@@ -75,7 +77,7 @@ struct Resid3D {
     float en[3][RPT];
     double acc = 0.0;
 
-    __device__ __forceinline__ int gy(int m) const { return y0 - 1 + w + 4 * m; }
+    __device__ __forceinline__ int gy(int m) const { return y0 - 1 + w + WV * m; }
 
     // Rows are wave-uniform (the wave index is read into a scalar register):
     // each row of a plane has a scalar base address and the per-lane part is
@@ -95,7 +97,7 @@ struct Resid3D {
         minner = mring = 0;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const int y = gy(m), ly = w + 4 * m;
+            const int y = gy(m), ly = w + WV * m;
             if (coli && y >= 1 && y <= n - 2) minner |= 1u << m;
             if (lane1 && ly >= 1 && ly <= BY - 2) mring |= 1u << m;
         }
@@ -119,10 +121,14 @@ struct Resid3D {
             if constexpr (VAR) dk[m] = ld_off(kf + zoff + rowoff(m), xb);
         }
     }
+    // f is read on the tile rows only (the halo rows have no residual).
     __device__ __forceinline__ void issue_f(int z, double (&dst)[RPT]) {
         const MG_GLOBAL double* __restrict__ fp = f + (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
-        for (int m = 0; m < RPT; ++m) dst[m] = ld_off(fp + rowoff(m), xb);
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + WV * m;  // wave-uniform
+            if (ly >= 1 && ly <= BY - 2) dst[m] = ld_off(fp + rowoff(m), xb);
+        }
     }
 
     template <int P>
@@ -132,7 +138,7 @@ struct Resid3D {
         const bool own = kk >= z0 && kk < z1;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const int ly = w + 4 * m, y = gy(m);
+            const int ly = w + WV * m, y = gy(m);
             double v = un[S0][m];
             if constexpr (IR) {
                 const bool inn = zin && coli && y >= 1 && y <= n - 2;
@@ -158,7 +164,7 @@ struct Resid3D {
         if (zz >= z0) {
 #pragma unroll
             for (int m = 0; m < RPT; ++m) {
-                const int ly = w + 4 * m, y = gy(m);
+                const int ly = w + WV * m;
                 const double uc = uo[S1][m];
                 const double uw = lane_prev(uc), ue = lane_next(uc);
                 double kc = 1.0, kw = 1.0, ke = 1.0, kb = 1.0, ka = 1.0, kS = 1.0, kN = 1.0;
@@ -188,6 +194,8 @@ struct Resid3D {
     __device__ __forceinline__ void run() {
         init_rows();
         int kk = kstart;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) fr[0][m] = fr[1][m] = fr[2][m] = 0.0;  // halo rows: f is not read
         issue(kk, un[0], en[0], kn[0]);
         if constexpr (PD == 2) issue(kk + 1, un[1], en[1], kn[1]);
         for (; kk + 2 <= kend; kk += 3) {
@@ -200,11 +208,11 @@ struct Resid3D {
     }
 };
 
-template <bool VAR, int BY, int PD, bool IR>
+template <bool VAR, int BY, int PD, bool IR, int WV>
 __device__ __forceinline__ void resid3d_body(const GridDesc* gd, const IRDesc* ird, int sel, int flags,
                                              double* __restrict__ part, int pstride, int zchunk) {
-    using S = Resid3D<VAR, BY, PD, IR>;
-    __shared__ double red4[4];
+    using S = Resid3D<VAR, BY, PD, IR, WV>;
+    __shared__ double red[WV];
     __shared__ double U[3][BY][BX];
     __shared__ double K[VAR ? 3 : 1][BY][BX];
     S s;
@@ -252,16 +260,16 @@ __device__ __forceinline__ void resid3d_body(const GridDesc* gd, const IRDesc* i
     s.coli = s.gx >= 1 && s.gx <= n - 2;
     s.lane1 = s.lane >= 1 && s.lane <= BX - 2;
     s.run();
-    const double t = block_sum(s.acc, red4);
+    const double t = block_sum_w<WV>(s.acc, red);
     if (threadIdx.x == 0) part[(size_t)inst * pstride + blockIdx.x] = t;
 }
 
-template <bool VAR, int BY, int PD>
-__global__ __launch_bounds__(NT) void k_norm3d(const GridDesc* __restrict__ descs, int sel, double* __restrict__ part,
-                                               int pstride, int zchunk) {
+template <bool VAR, int BY, int PD, int WV>
+__global__ __launch_bounds__(64 * WV) void k_norm3d(const GridDesc* __restrict__ descs, int sel,
+                                                    double* __restrict__ part, int pstride, int zchunk) {
     const GridDesc* d = descs + blockIdx.y;
     if (d->done && *gp(d->done)) return;
-    resid3d_body<VAR, BY, PD, false>(d, nullptr, sel, 0, part, pstride, zchunk);
+    resid3d_body<VAR, BY, PD, false, WV>(d, nullptr, sel, 0, part, pstride, zchunk);
 }
 
 // ---------------------------------------------------------------------------
@@ -324,12 +332,12 @@ __global__ __launch_bounds__(NT) void k_ir2d(const IRDesc* __restrict__ descs, i
     if (threadIdx.x == 0) part[(size_t)d.inst * pstride + blockIdx.x] = s;
 }
 
-template <bool VAR, int BY, int PD, int FL>
-__global__ __launch_bounds__(NT) void k_ir3d(const IRDesc* __restrict__ descs, int sel, double* __restrict__ part,
-                                             int pstride, int zchunk) {
+template <bool VAR, int BY, int PD, int FL, int WV>
+__global__ __launch_bounds__(64 * WV) void k_ir3d(const IRDesc* __restrict__ descs, int sel, double* __restrict__ part,
+                                                  int pstride, int zchunk) {
     const IRDesc* d = descs + blockIdx.y;
     if (d->done && *gp(d->done)) return;
-    resid3d_body<VAR, BY, PD, true>(nullptr, d, sel, FL, part, pstride, zchunk);
+    resid3d_body<VAR, BY, PD, true, WV>(nullptr, d, sel, FL, part, pstride, zchunk);
 }
 
 // Sum of np partials by one workgroup in a fixed order: thread t takes
@@ -454,6 +462,40 @@ __global__ void k_fill_int(int* __restrict__ p, int v, int count) {
 
 }  // namespace
 
+template <bool VARV, int BY, int PD>
+hipError_t launch_norm3d_w(const GridDesc* d, int sel, double* partial, int pstride, TileCfg cfg, dim3 grid,
+                           hipStream_t s) {
+    if (cfg.wv == 8) {
+        if constexpr (BY >= 16) {
+            k_norm3d<VARV, BY, PD, 8><<<grid, 512, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+            return hipSuccess;
+        }
+        return hipErrorInvalidValue;
+    }
+    if (cfg.wv != 4) return hipErrorInvalidValue;
+    if constexpr (VARV && BY > 16) return hipErrorInvalidValue;
+    else k_norm3d<VARV, BY, PD, 4><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+    return hipSuccess;
+}
+
+template <bool VARV>
+hipError_t launch_norm3d(const GridDesc* d, int sel, double* partial, int pstride, TileCfg cfg, dim3 grid,
+                         hipStream_t s) {
+    const bool p2 = cfg.pd == 2;
+    switch (cfg.by) {
+        case 8:
+            return p2 ? launch_norm3d_w<VARV, 8, 2>(d, sel, partial, pstride, cfg, grid, s)
+                      : launch_norm3d_w<VARV, 8, 1>(d, sel, partial, pstride, cfg, grid, s);
+        case 16:
+            return p2 ? launch_norm3d_w<VARV, 16, 2>(d, sel, partial, pstride, cfg, grid, s)
+                      : launch_norm3d_w<VARV, 16, 1>(d, sel, partial, pstride, cfg, grid, s);
+        case 32:
+            return p2 ? launch_norm3d_w<VARV, 32, 2>(d, sel, partial, pstride, cfg, grid, s)
+                      : launch_norm3d_w<VARV, 32, 1>(d, sel, partial, pstride, cfg, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_norm(int dim, bool var, const GridDesc* d, int ninst, int n, int sel, double* partial, int pstride,
                        TileCfg cfg, hipStream_t s) {
     const dim3 grid(norm_tiles(dim, n, cfg), ninst);
@@ -465,21 +507,29 @@ hipError_t launch_norm(int dim, bool var, const GridDesc* d, int ninst, int n, i
             MG_BY_SWITCH(cfg.by, (k_norm2d<false, BY><<<grid, NT, 0, s>>>(d, sel, partial, pstride)))
         }
     } else {
-        if (var) {
-            if (cfg.pd == 2) {
-                MG_BY_SWITCH16(cfg.by, (k_norm3d<true, BY, 2><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
-            } else {
-                MG_BY_SWITCH16(cfg.by, (k_norm3d<true, BY, 1><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
-            }
-        } else {
-            if (cfg.pd == 2) {
-                MG_BY_SWITCH(cfg.by, (k_norm3d<false, BY, 2><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
-            } else {
-                MG_BY_SWITCH(cfg.by, (k_norm3d<false, BY, 1><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
-            }
-        }
+        const hipError_t e = var ? launch_norm3d<true>(d, sel, partial, pstride, cfg, grid, s)
+                                 : launch_norm3d<false>(d, sel, partial, pstride, cfg, grid, s);
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
+}
+
+// 3D pass geometries (rows x wavefronts): 8x4, 16x4, 32x4 (at most 16 rows
+// with a coefficient field, four rows per thread), 16x8 and 32x8.
+template <bool VARV, int FL, int BY, int PD>
+hipError_t launch_ir3d_w(const IRDesc* d, int sel, double* partial, int pstride, TileCfg cfg, dim3 grid,
+                         hipStream_t s) {
+    if (cfg.wv == 8) {
+        if constexpr (BY >= 16) {
+            k_ir3d<VARV, BY, PD, FL, 8><<<grid, 512, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+            return hipSuccess;
+        }
+        return hipErrorInvalidValue;
+    }
+    if (cfg.wv != 4) return hipErrorInvalidValue;
+    if constexpr (VARV && BY > 16) return hipErrorInvalidValue;  // four rows per thread with k
+    else k_ir3d<VARV, BY, PD, FL, 4><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+    return hipSuccess;
 }
 
 template <bool VARV, int FL>
@@ -487,18 +537,21 @@ hipError_t launch_ir_fl(int dim, const IRDesc* d, int sel, double* partial, int 
                         hipStream_t s) {
     if (dim == 2) {
         MG_BY_SWITCH(cfg.by, (k_ir2d<VARV, BY, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride)))
-    } else if constexpr (VARV) {  // at most 16 rows (max_tile_rows)
-        if (cfg.pd == 2) {
-            MG_BY_SWITCH16(cfg.by, (k_ir3d<VARV, BY, 2, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
-        } else {
-            MG_BY_SWITCH16(cfg.by, (k_ir3d<VARV, BY, 1, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
-        }
-    } else if (cfg.pd == 2) {
-        MG_BY_SWITCH(cfg.by, (k_ir3d<VARV, BY, 2, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
-    } else {
-        MG_BY_SWITCH(cfg.by, (k_ir3d<VARV, BY, 1, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk)))
+        return hipSuccess;
     }
-    return hipSuccess;
+    const bool p2 = cfg.pd == 2;
+    switch (cfg.by) {
+        case 8:
+            return p2 ? launch_ir3d_w<VARV, FL, 8, 2>(d, sel, partial, pstride, cfg, grid, s)
+                      : launch_ir3d_w<VARV, FL, 8, 1>(d, sel, partial, pstride, cfg, grid, s);
+        case 16:
+            return p2 ? launch_ir3d_w<VARV, FL, 16, 2>(d, sel, partial, pstride, cfg, grid, s)
+                      : launch_ir3d_w<VARV, FL, 16, 1>(d, sel, partial, pstride, cfg, grid, s);
+        case 32:
+            return p2 ? launch_ir3d_w<VARV, FL, 32, 2>(d, sel, partial, pstride, cfg, grid, s)
+                      : launch_ir3d_w<VARV, FL, 32, 1>(d, sel, partial, pstride, cfg, grid, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_ir_update(int dim, bool var, const IRDesc* d, int ninst, int n, int sel, int flags,

@@ -172,10 +172,14 @@ struct Smooth3D {
             if constexpr (VAR) dk[m] = ld_off(kp + rowoff(m), xb);
         }
     }
+    // f is read on the rows that are relaxed (not the outermost halo rows).
     __device__ __forceinline__ void issue_f(int z, T (&dst)[RPT]) {
         const MG_GLOBAL T* __restrict__ fp = f + (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
-        for (int m = 0; m < RPT; ++m) dst[m] = ld_off(fp + rowoff(m), xb);
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + WV * m;  // wave-uniform
+            if (ly >= 1 && ly <= BY - 2) dst[m] = ld_off(fp + rowoff(m), xb);
+        }
     }
 
     // relaxation at row m of the thread, plane values: A (centre plane
@@ -312,6 +316,7 @@ struct Smooth3D {
         for (int m = 0; m < RPT; ++m) {
             uo[1][m] = uo[2][m] = T(0);
             ro[0][m] = ro[1][m] = ro[2][m] = T(0);
+            fr[0][m] = fr[1][m] = fr[2][m] = T(0);  // halo rows keep these (f is not read there)
             ko[1][m] = ko[2][m] = T(1);
             if constexpr (VAR) kbelow[m] = T(1);
         }

@@ -70,10 +70,11 @@ struct SweepRC {
             if constexpr (VAR) dk[m] = ld_off(kf + zoff + rowoff(m), xb);
         }
     }
+    // f is read on the rows that are relaxed (not the outermost halo rows).
     __device__ __forceinline__ void issue_f(int z, T (&dst)[BY]) {
         const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
-        for (int m = 0; m < BY; ++m) dst[m] = ld_off(f + zoff + rowoff(m), xb);
+        for (int m = 1; m < BY - 1; ++m) dst[m] = ld_off(f + zoff + rowoff(m), xb);
     }
 
     // ---- coarse-grid correction (SWEEP_PROLONG), as in the LDS variant ----
@@ -216,6 +217,7 @@ struct SweepRC {
         for (int m = 0; m < BY; ++m) {
             uo[1][m] = uo[2][m] = T(0);
             ro[0][m] = ro[1][m] = ro[2][m] = T(0);
+            fr[0][m] = fr[1][m] = fr[2][m] = T(0);  // halo rows keep these (f is not read there)
             ko[1][m] = ko[2][m] = T(1);
             if constexpr (VAR) kbelow[m] = T(1);
         }

@@ -138,9 +138,13 @@ struct mg_ctx {
     int graph_max = -1;
 
     // measurement
+    // measurement hooks: event pairs of the current solve, tagged with their
+    // refinement step and kernel (0 finest plain sweeps, 1 finest refinement /
+    // norm pass); only steps the solve really ran are added to the totals
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;
     int prof_n = 0;
-    int prof_launches = 0;
-    double prof_ms = 0.0;
+    std::vector<int> prof_step, prof_kind;  // per event pair
+    int prof_launches[2] = {0, 0};
+    double prof_ms[2] = {0.0, 0.0};
 };

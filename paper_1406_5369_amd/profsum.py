@@ -59,6 +59,25 @@ def sweep_kernel(dim: int, word: int, by: int, pd: int, var: bool = False, wv: i
     return f"mg::k_smooth3d<{t}, 0, {v}, {by}, {pd}, 0, {wv}>"
 
 
+def pass_kernel(dim: int, by: int, pd: int, var: bool = False, ir: bool = True, wv: int = 4) -> str:
+    """Demangled name of the finest-level FP64 refinement pass (updating, as
+    in a refinement step) or FP64 norm pass with the given tile height,
+    prefetch depth and wavefronts."""
+    v = "true" if var else "false"
+    if ir:
+        return f"mg::k_ir2d<{v}, {by}, 0>" if dim == 2 else f"mg::k_ir3d<{v}, {by}, {pd}, 0, {wv}>"
+    return f"mg::k_norm2d<{v}, {by}>" if dim == 2 else f"mg::k_norm3d<{v}, {by}, {pd}, {wv}>"
+
+
+def pass_blocks(dim: int, n: int, by: int, zchunk: int) -> int:
+    """Workgroups of a refinement / norm pass: tiles of (BX - 2) x (by - 2)
+    inner points (a one-point halo), times z-chunks in 3D."""
+    m = n - 2
+    cd = lambda a, b: -(-a // b)  # noqa: E731
+    b = cd(m, BX - 2) * cd(m, by - 2)
+    return b if dim == 2 else b * cd(m, zchunk)
+
+
 def sweep_blocks(dim: int, n: int, by: int, zchunk: int) -> int:
     """Workgroups of one RBGS sweep over an n^dim node grid: tiles of
     (BX - 4) x (by - 4) inner points (a two-point halo), times z-chunks in 3D."""
@@ -96,19 +115,28 @@ def load(path: str, from_kernel: str | None = None):
     return rows
 
 
+IDLE_FRAC = 0.25  # a dispatch under this fraction of its kernel's median did no work
+
+
 def summarize(rows, match: str | None = None):
-    agg = defaultdict(lambda: [0, 0.0])
+    """Per (kernel, grid): dispatches, total and average time.  Dispatches
+    shorter than IDLE_FRAC of the median of their kernel and grid are counted
+    apart as idle: launches of a step queued after the solve finished, whose
+    workgroups all exit at the stop flag; they stay in the totals."""
+    agg = defaultdict(list)
     for name, dur, gx, gy, gz, wx in rows:
         if match and match not in name:
             continue
-        key = (name, gx // max(wx, 1), gy, gz)
-        agg[key][0] += 1
-        agg[key][1] += dur
-    total = sum(v[1] for v in agg.values())
+        agg[(name, gx // max(wx, 1), gy, gz)].append(dur)
+    total = sum(sum(v) for v in agg.values())
     out = []
-    for (name, bx, gy, gz), (cnt, tot) in agg.items():
-        out.append(dict(kernel=name, blocks_x=bx, grid_y=gy, grid_z=gz, calls=cnt, total_ms=tot / 1e6,
-                        avg_us=tot / cnt / 1e3, pct=100.0 * tot / total if total else 0.0))
+    for (name, bx, gy, gz), durs in agg.items():
+        med = sorted(durs)[len(durs) // 2]
+        work = [d for d in durs if d >= IDLE_FRAC * med]
+        tot = sum(durs)
+        out.append(dict(kernel=name, blocks_x=bx, grid_y=gy, grid_z=gz, calls=len(work), idle=len(durs) - len(work),
+                        total_ms=tot / 1e6, avg_us=sum(work) / len(work) / 1e3,
+                        pct=100.0 * tot / total if total else 0.0))
     out.sort(key=lambda d: -d["total_ms"])
     return out
 
@@ -150,12 +178,33 @@ def _bench_line(path: str) -> dict:
     return json.loads(lines[-1])
 
 
+def _entry(runs, kname: str, blocks: int, algo: float) -> dict | None:
+    """Calibrated bytes per launch of one kernel and grid in both counter runs;
+    dispatches under IDLE_FRAC of the largest reading of their counter (stop
+    flag set, no work) are left out."""
+    ent = {"kernel": kname, "blocks": blocks}
+    total = 0.0
+    for cname, (per, calib_kib, factor) in runs.items():
+        vals = per.get((kname, blocks))
+        if not vals:
+            return None
+        keep = [v for v in vals if v >= IDLE_FRAC * max(vals)]
+        avg = sum(keep) / len(keep)
+        ent[cname] = {"kib_per_dispatch": avg, "dispatches": len(keep), "idle": len(vals) - len(keep),
+                      "factor": factor}
+        total += avg * 1024.0 * factor
+    ent["bytes_per_launch"] = total
+    ent["ratio_to_algorithmic"] = total / algo
+    return ent
+
+
 def traffic(fetch_db: str, write_db: str, bench_json: str) -> dict:
-    """HBM bytes per launch of the benchmark's finest-level sweep, from one
-    FETCH_SIZE and one WRITE_SIZE run (KiB per dispatch), each calibrated on the
-    1 GiB copies of the same run.  The tile autotuner launches every candidate
-    geometry on the finest level during setup, so the record holds one entry per
-    geometry present in both runs, keyed "by,zchunk,prefetch,waves"."""
+    """HBM bytes per launch of the benchmark's finest-level sweep and
+    refinement pass, from one FETCH_SIZE and one WRITE_SIZE run (KiB per
+    dispatch), each calibrated on the 1 GiB copies of the same run.  The tile
+    autotuner launches every candidate geometry on the finest level during
+    setup, so the record holds one entry per geometry present in both runs,
+    keyed "by,zchunk,prefetch,waves"."""
     b = _bench_line(bench_json)
     cfg = b["config"]
     dim, n = cfg["dim"], cfg["n"]
@@ -170,37 +219,43 @@ def traffic(fetch_db: str, write_db: str, bench_json: str) -> dict:
             raise SystemExit(f"{db}: no k_copy_bytes dispatches (run the benchmark with --calibrate-copy)")
         calib_kib = max(copies)
         runs[cname] = (per, calib_kib, COPY_BYTES / (calib_kib * 1024.0))
+    zcs = (4, 8, 16, 32, 64, 128, 256) if dim == 3 else (1,)
+    pds = (1, 2) if dim == 3 else (1,)
     configs = {}
-    for by, wv in ((8, 4), (16, 4), (32, 4), (16, 8), (32, 8)):
+    for by, wv in ((8, 4), (16, 4), (32, 4), (16, 8), (32, 8), (8, 1), (12, 1)):
         if dim == 2 and wv != 4:
             continue
-        for pd in ((1, 2) if dim == 3 else (1,)):
-            for zc in ((4, 8, 16, 32, 64, 128, 256) if dim == 3 else (1,)):
-                kname = sweep_kernel(dim, word, by, pd, var, wv)
-                blocks = sweep_blocks(dim, n, by, zc)
-                ent = {"kernel": kname, "blocks": blocks}
-                total = 0.0
-                for cname, (per, calib_kib, factor) in runs.items():
-                    vals = per.get((kname, blocks))
-                    if not vals:
-                        break
-                    avg = sum(vals) / len(vals)
-                    ent[cname] = {"kib_per_dispatch": avg, "dispatches": len(vals), "factor": factor}
-                    total += avg * 1024.0 * factor
-                else:
-                    ent["bytes_per_launch"] = total
-                    ent["ratio_to_algorithmic"] = total / algo
+        for pd in pds:
+            for zc in zcs:
+                ent = _entry(runs, sweep_kernel(dim, word, by, pd, var, wv), sweep_blocks(dim, n, by, zc), algo)
+                if ent:
                     configs[f"{by},{zc},{pd},{wv}"] = ent
     if not configs:
         raise SystemExit("no finest-level sweep dispatches found in both runs")
+    # refinement pass (mixed precision): FP64 u and f read, FP32 e read, FP64 u and FP32 r written
+    ir = word == 4
+    algo_pass = ((32 if ir else 16) + (8 if var else 0)) * (n - 2) ** dim
+    pass_configs = {}
+    for by, wv in ((8, 4), (16, 4), (32, 4), (16, 8), (32, 8)):
+        if dim == 2 and wv != 4:
+            continue
+        for pd in pds:
+            for zc in zcs:
+                ent = _entry(runs, pass_kernel(dim, by, pd, var, ir, wv), pass_blocks(dim, n, by, zc), algo_pass)
+                if ent:
+                    pass_configs[f"{by},{zc},{pd},{wv}"] = ent
     by, zc, pd, wv = b["extra"]["fine_tiles"]["smooth"]
+    pby, pzc, ppd, pwv = b["extra"]["fine_tiles"]["norm_or_refinement"]
     return {
         "workload": cfg["workload"],
         "source_hash": kernel_source_hash(),
         "algorithmic_bytes": algo,
+        "algorithmic_bytes_pass": algo_pass,
         "calibration": {c: {"copy_kib_per_GiB": v[1], "factor": v[2]} for c, v in runs.items()},
         "bench_tiles": f"{by},{zc},{pd},{wv}",
+        "bench_pass_tiles": f"{pby},{pzc},{ppd},{pwv}",
         "configs": configs,
+        "pass_configs": pass_configs,
     }
 
 
@@ -237,10 +292,10 @@ def main(argv=None) -> int:
             print(f"{d['counter']:>12} {d['avg']:16.1f} {d['dispatches']:5d} {d['blocks_x']:7d}  {d['kernel']}")
         return 0
     res = summarize(load(a.trace, a.from_kernel), a.match)
-    print(f"{'pct':>6} {'total_ms':>10} {'calls':>6} {'avg_us':>10} {'blocks':>7} {'gy':>4}  kernel")
+    print(f"{'pct':>6} {'total_ms':>10} {'calls':>6} {'idle':>5} {'avg_us':>10} {'blocks':>7} {'gy':>4}  kernel")
     for d in res[: a.top]:
-        print(f"{d['pct']:6.2f} {d['total_ms']:10.3f} {d['calls']:6d} {d['avg_us']:10.2f} {d['blocks_x']:7d} "
-              f"{d['grid_y']:4d}  {d['kernel']}")
+        print(f"{d['pct']:6.2f} {d['total_ms']:10.3f} {d['calls']:6d} {d['idle']:5d} {d['avg_us']:10.2f} "
+              f"{d['blocks_x']:7d} {d['grid_y']:4d}  {d['kernel']}")
     return 0
 
 
