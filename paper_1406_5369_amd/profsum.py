@@ -142,20 +142,22 @@ def summarize(rows, match: str | None = None):
 
 
 def counters(path: str, match: str | None = None):
-    """Average value per dispatch of every collected counter, per (kernel, blocks)."""
+    """Average value per dispatch of every collected counter, per (kernel,
+    blocks), over the dispatches that read at least IDLE_FRAC of the largest
+    reading (the others, stop-flag exits, are counted as idle)."""
     con = sqlite3.connect(path)
     q = ("select kernel_name, grid_size_x, workgroup_size_x, counter_name, value from counters_collection")
-    agg = defaultdict(lambda: [0, 0.0])
+    agg = defaultdict(list)
     for name, gx, wx, cname, val in con.execute(q):
         k = short_name(name)
         if match and match not in k:
             continue
-        key = (k, int(gx) // max(int(wx), 1), cname)
-        agg[key][0] += 1
-        agg[key][1] += float(val)
+        agg[(k, int(gx) // max(int(wx), 1), cname)].append(float(val))
     out = []
-    for (k, bx, cname), (cnt, tot) in agg.items():
-        out.append(dict(kernel=k, blocks_x=bx, counter=cname, dispatches=cnt, avg=tot / cnt))
+    for (k, bx, cname), vals in agg.items():
+        keep = [v for v in vals if v >= IDLE_FRAC * max(vals)] or vals
+        out.append(dict(kernel=k, blocks_x=bx, counter=cname, dispatches=len(keep), idle=len(vals) - len(keep),
+                        avg=sum(keep) / len(keep)))
     out.sort(key=lambda d: (d["kernel"], d["blocks_x"], d["counter"]))
     return out
 
@@ -287,9 +289,10 @@ def main(argv=None) -> int:
         return 0
     a.trace = a.trace[0]
     if a.counters:
-        print(f"{'counter':>12} {'avg/dispatch':>16} {'n':>5} {'blocks':>7}  kernel")
+        print(f"{'counter':>12} {'avg/dispatch':>16} {'n':>5} {'idle':>5} {'blocks':>7}  kernel")
         for d in counters(a.trace, a.match):
-            print(f"{d['counter']:>12} {d['avg']:16.1f} {d['dispatches']:5d} {d['blocks_x']:7d}  {d['kernel']}")
+            print(f"{d['counter']:>12} {d['avg']:16.1f} {d['dispatches']:5d} {d['idle']:5d} {d['blocks_x']:7d}  "
+                  f"{d['kernel']}")
         return 0
     res = summarize(load(a.trace, a.from_kernel), a.match)
     print(f"{'pct':>6} {'total_ms':>10} {'calls':>6} {'idle':>5} {'avg_us':>10} {'blocks':>7} {'gy':>4}  kernel")
