@@ -163,10 +163,12 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
 /* FP64 refinement pass: u_out = u_in + e on inner nodes, r = (float)(f - A u_out)
  * on inner nodes (FP64 operator, FP64 k or NULL), *norm_out (HOST) = ||f - A u_out||_2.
  * e and r are FP32 arrays; u_out's and r's boundaries are not written.  'by',
- * 'zchunk' pick the tile (0 = default); 'waves' (3D) is 4 or 8 wavefronts per
- * workgroup (8 needs by >= 16; 0 = 4).  Synchronises the stream. */
+ * 'zchunk' pick the tile (0 = default); in 3D 'prefetch' is 1 or 2 planes
+ * loaded ahead and 'waves' 4 or 8 wavefronts per workgroup (8 needs
+ * by >= 16); 0 = default.  Synchronises the stream. */
 int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
-                       double* u_out, float* r, double* norm_out, int by, int zchunk, int waves, void* stream);
+                       double* u_out, float* r, double* norm_out, int by, int zchunk, int prefetch, int waves,
+                       void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched solves: many independent grids (sizes may differ) in one context.

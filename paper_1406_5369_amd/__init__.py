@@ -88,7 +88,7 @@ def lib():
             "mg_level_residual_restrict": (i, [i, i, i, p, p, p, p, i, i, p]),
             "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
-            "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, p]),
+            "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, p]),
             "mg_prof_enable": (i, [p, i]),
             "mg_prof_read": (i, [p, C.POINTER(i), C.POINTER(d)]),
             "mg_prof_read_kernel": (i, [p, i, C.POINTER(i), C.POINTER(d)]),
@@ -292,7 +292,7 @@ def mg_level_coarsest(u, f, k=None, stream=None) -> None:
                                    _dptr(f, dt, (3,) * dim, "f"), _stream(stream)), "mg_level_coarsest")
 
 
-def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, waves=0, stream=None) -> float:
+def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, prefetch=0, waves=0, stream=None) -> float:
     import torch
 
     dim, n = f.dim(), f.shape[0]
@@ -301,7 +301,7 @@ def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, waves=0, st
     _check(lib().mg_level_ir_update(dim, n, _dptr(k, torch.float64, sh, "k"), _dptr(u_in, torch.float64, sh, "u_in"),
                                     _dptr(e, torch.float32, sh, "e"), _dptr(f, torch.float64, sh, "f"),
                                     _dptr(u_out, torch.float64, sh, "u_out"), _dptr(r, torch.float32, sh, "r"),
-                                    C.byref(out), by, zchunk, waves, _stream(stream)), "mg_level_ir_update")
+                                    C.byref(out), by, zchunk, prefetch, waves, _stream(stream)), "mg_level_ir_update")
     return out.value
 
 

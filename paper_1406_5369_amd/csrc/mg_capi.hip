@@ -1020,10 +1020,12 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
 }
 
 int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
-                       double* u_out, float* r, double* norm_out, int by, int zchunk, int waves, void* stream) {
+                       double* u_out, float* r, double* norm_out, int by, int zchunk, int prefetch, int waves,
+                       void* stream) {
     if (!valid_edge(dim, n) || n < 5) return MG_EINVAL;
     if (!u_in || !e || !f || !u_out || !r || !norm_out || u_in == u_out) return MG_EINVAL;
     TileCfg cfg = pick_cfg(dim, 8, n, 0, by, zchunk, 2);
+    if (prefetch) cfg.pd = prefetch;
     if (waves) cfg.wv = waves;
     if (!valid_cfg(cfg, dim, 8, k != nullptr, 2)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;

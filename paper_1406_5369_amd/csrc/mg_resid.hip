@@ -154,7 +154,10 @@ struct Resid3D {
                 K[S0][ly][lane] = kn[S0][m];
             }
         }
-        issue_f(kk, fr[S0]);
+        // f of the plane PD - 1 ahead: with PD = 2 into the slot of plane
+        // kk-2, whose f had its last use in the previous step
+        if constexpr (PD == 2) issue_f(kk + 1, fr[S2]);
+        else issue_f(kk, fr[S0]);
         issue(kk + PD, un[SN], en[SN], kn[SN]);
         __syncthreads();
         // residual of plane kk-1: z-neighbours from registers, x from the
@@ -197,7 +200,10 @@ struct Resid3D {
 #pragma unroll
         for (int m = 0; m < RPT; ++m) fr[0][m] = fr[1][m] = fr[2][m] = 0.0;  // halo rows: f is not read
         issue(kk, un[0], en[0], kn[0]);
-        if constexpr (PD == 2) issue(kk + 1, un[1], en[1], kn[1]);
+        if constexpr (PD == 2) {
+            issue(kk + 1, un[1], en[1], kn[1]);
+            issue_f(kk, fr[0]);
+        }
         for (; kk + 2 <= kend; kk += 3) {
             step<0>(kk);
             step<1>(kk + 1);

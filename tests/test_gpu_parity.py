@@ -183,10 +183,11 @@ def test_coarsest_bitwise(dim, varcoef, dev_ok):
     assert same(host(ud), expect)
 
 
-@pytest.mark.parametrize("dim,n,by,zc,wv", [(2, 65, 0, 0, 0), (2, 257, 8, 0, 0), (3, 33, 0, 0, 0), (3, 65, 16, 3, 0),
-                                           (3, 65, 16, 5, 8), (3, 129, 32, 16, 8), (3, 33, 32, 7, 8)])
+@pytest.mark.parametrize("dim,n,by,zc,pd,wv", [(2, 65, 0, 0, 0, 0), (2, 257, 8, 0, 0, 0), (3, 33, 0, 0, 0, 0),
+                                              (3, 65, 16, 3, 1, 0), (3, 65, 8, 7, 2, 4), (3, 65, 16, 5, 1, 8),
+                                              (3, 129, 32, 16, 2, 8), (3, 33, 32, 7, 2, 8), (3, 33, 16, 1, 2, 4)])
 @pytest.mark.parametrize("varcoef", [False, True])
-def test_refinement_pass(dim, n, by, zc, wv, varcoef, dev_ok):
+def test_refinement_pass(dim, n, by, zc, pd, wv, varcoef, dev_ok):
     import torch
 
     u, f, k = case_arrays(dim, n, np.float64, varcoef, seed=11)
@@ -195,7 +196,7 @@ def test_refinement_pass(dim, n, by, zc, wv, varcoef, dev_ok):
     uo = dev(np.zeros_like(u))
     r = torch.zeros(u.shape, dtype=torch.float32, device="cuda")
     rho = mg().mg_level_ir_update(dev(u), dev(e), dev(f), uo, r, k=dev(k) if k is not None else None, by=by,
-                                  zchunk=zc, waves=wv)
+                                  zchunk=zc, prefetch=pd, waves=wv)
     assert same(host(uo), u_exp)
     assert same(host(r), r_exp)
     assert rho == pytest.approx(rho_exp, rel=1e-13)
