@@ -176,7 +176,7 @@ int validate(const mg_params* p) {
 void destroy(mg_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     free_groups(c->G64);
     free_groups(c->G32);
@@ -261,8 +261,10 @@ hipError_t enqueue_ir(mg_ctx* c, int sel, int flags, hipStream_t s, int step = 0
 
 // K solve steps (cycle + residual norm + stop test), IR steps alternate the
 // FP64 ping-pong starting from sel 0 (K even keeps the parity per chunk).
-// With 'prof', step0 + i + 1 tags the measured launches of step i.
-hipError_t enqueue_steps(mg_ctx* c, int K, double tol, int max_cycles, hipStream_t s, bool prof, int step0 = 0) {
+// With 'prof', step0 + i + 1 tags the measured launches of step i.  Refinement
+// step i reads the FP64 iterate from ping-pong buffer (par0 + i) & 1.
+hipError_t enqueue_steps(mg_ctx* c, int K, double tol, int max_cycles, hipStream_t s, bool prof, int step0 = 0,
+                         int par0 = 0) {
     hipEvent_t* pev = prof ? c->prof_ev.data() : nullptr;
     int* pn = prof ? &c->prof_n : nullptr;
     const int pcap = (int)c->prof_ev.size();
@@ -279,7 +281,7 @@ hipError_t enqueue_steps(mg_ctx* c, int K, double tol, int max_cycles, hipStream
             e = vcycle<float>(c->prob, c->G32, true, c->tl32, s, pev, pn, pcap, &c->tail32);
             for (int j = n0; prof && j < c->prof_n; j += 2) c->prof_step.push_back(step), c->prof_kind.push_back(0);
             if (e != hipSuccess) return e;
-            e = enqueue_ir(c, i & 1, 0, s, step);
+            e = enqueue_ir(c, (par0 + i) & 1, 0, s, step);
         }
         if (e != hipSuccess) return e;
         e = launch_stop_test(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist,
@@ -300,27 +302,29 @@ int ensure_hist(mg_ctx* c, int cap) {
     CK(hipHostMalloc((void**)&c->h_pin, sizeof(double) * (size_t)(cap + 8), hipHostMallocDefault));
     c->hist_cap = cap;
     // the hist pointer is baked into captured graphs
-    if (c->graph) {
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
     return MG_OK;
 }
 
 int run_chunk(mg_ctx* c, int K, double tol, int max_cycles, int step0) {
     const bool use_graph = !c->prof_on && c->use_graphs;
+    const int par0 = c->p.precision == MG_PREC_FP32_IR ? (step0 & 1) : 0;
     if (!use_graph) {
-        CK(enqueue_steps(c, K, tol, max_cycles, c->stream, c->prof_on, step0));
+        CK(enqueue_steps(c, K, tol, max_cycles, c->stream, c->prof_on, step0, par0));
         return MG_OK;
     }
-    if (!c->graph || c->graph_steps != K || c->graph_tol != tol || c->graph_max != max_cycles) {
-        if (c->graph) {
-            (void)hipGraphExecDestroy(c->graph);
-            c->graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    for (const auto& g : c->graphs)
+        if (g.steps == K && g.par == par0 && g.tol == tol && g.max_cycles == max_cycles) exec = g.exec;
+    if (!exec) {
+        if (c->graphs.size() >= 16) {  // a new tolerance or limit: start over
+            for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+            c->graphs.clear();
         }
         if (!c->cap_stream) CK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         CK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_steps(c, K, tol, max_cycles, c->cap_stream, false);
+        hipError_t e = enqueue_steps(c, K, tol, max_cycles, c->cap_stream, false, 0, par0);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
         if (e != hipSuccess) {
@@ -328,15 +332,27 @@ int run_chunk(mg_ctx* c, int K, double tol, int max_cycles, int step0) {
             return dev_status(e);
         }
         CK(e2);
-        hipError_t e3 = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        hipError_t e3 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         CK(e3);
-        c->graph_steps = K;
-        c->graph_tol = tol;
-        c->graph_max = max_cycles;
+        c->graphs.push_back({K, par0, max_cycles, tol, exec});
     }
-    CK(hipGraphLaunch(c->graph, c->stream));
+    CK(hipGraphLaunch(exec, c->stream));
     return MG_OK;
+}
+
+// Steps of the next chunk: as many as the contraction of the last step
+// predicts are still needed to reach tol (at least one, at most kmax).  hist
+// holds the norms of steps 0 .. steps.
+int next_chunk(const double* hist, int steps, double tol, int kmax) {
+    if (steps < 1) return kmax;
+    const double r0 = hist[0], rk = hist[steps], rp = hist[steps - 1];
+    if (!(r0 > 0.0) || !(rk > 0.0) || !(rp > 0.0)) return kmax;
+    const double rate = rk / rp;
+    if (!(rate < 0.9)) return kmax;
+    const double need = std::log(tol * r0 / rk) / std::log(rate);
+    if (!(need > 0.0)) return 1;
+    return std::max(1, std::min(kmax, (int)std::ceil(need - 1e-9)));
 }
 
 
@@ -814,10 +830,11 @@ int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
     else CK(enqueue_norm(c, s));
     CK(launch_solve_init(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist, c->hist_cap, 1,
                          s));
-    // cycles in chunks of K; kernels of a finished solve exit at once
+    // steps in chunks: the first of kmax steps, later ones sized by
+    // next_chunk; kernels of a finished solve exit at once
     const size_t N = npts(c->p.dim, c->p.n);
-    int K = N > (size_t)(1 << 20) ? 4 : 10;
-    if (ir && (K & 1)) ++K;
+    const int kmax = N > (size_t)(1 << 20) ? 4 : 10;
+    int K = kmax;
     int steps = 0, status = 1, done = 0;
     CK(hipMemcpyAsync(c->h_pin, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
@@ -825,15 +842,18 @@ int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
     status = ((int*)c->h_pin)[2];
     int enqueued = 0;
     while (!done && enqueued < max_cycles) {
-        const int k = ir ? K : std::min(K, max_cycles - enqueued);
+        const int k = std::min(K, max_cycles - enqueued);
         r = run_chunk(c, k, tol, max_cycles, enqueued);
         if (r != MG_OK) return r;
         enqueued += k;
         CK(hipMemcpyAsync(c->h_pin, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(c->h_pin + 2, c->d_hist, sizeof(double) * (size_t)(enqueued + 1), hipMemcpyDeviceToHost,
+                          s));
         CK(hipStreamSynchronize(s));
         done = ((int*)c->h_pin)[0];
         steps = ((int*)c->h_pin)[1];
         status = ((int*)c->h_pin)[2];
+        K = next_chunk(c->h_pin + 2, steps, tol, kmax);
     }
     CK(hipMemcpyAsync(c->h_pin, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));

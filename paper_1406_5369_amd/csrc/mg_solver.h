@@ -128,14 +128,16 @@ struct mg_ctx {
     const void* bound_u = nullptr;
     const void* bound_f = nullptr;
 
-    // graph cache for a chunk of cycles
+    // captured chunks of solve steps, by step count, starting parity of the
+    // refinement ping-pong, tolerance and step limit
+    struct ChunkGraph {
+        int steps, par, max_cycles;
+        double tol;
+        hipGraphExec_t exec;
+    };
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph = nullptr;
-    int graph_steps = 0;
-    int graph_prec = -1;
-    double graph_tol = -1.0;
-    int graph_max = -1;
+    std::vector<ChunkGraph> graphs;
 
     // measurement
     // measurement hooks: event pairs of the current solve, tagged with their
