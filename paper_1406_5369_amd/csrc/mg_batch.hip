@@ -13,6 +13,7 @@
 // the kernels while the others continue, and per-instance arithmetic is
 // exactly that of a solve of the instance alone.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <chrono>
 #include <cstring>
@@ -231,14 +232,16 @@ struct Engine {
     std::vector<int> h_rows, h_newrows;
     std::vector<Inst*> members;
     std::vector<Inst*> fresh;  // members that still need their initial residual
-    hipGraphExec_t graph = nullptr;
-    int graph_k = 0;
-    double graph_tol = -1;
-    int graph_max = -1;
+    struct ChunkGraph {  // captured chunk of K steps for a tolerance and step limit
+        int k, max_steps;
+        double tol;
+        hipGraphExec_t exec;
+    };
+    std::vector<ChunkGraph> graphs;  // for the current descriptors (cleared by rebuild)
     hipStream_t cap_stream = nullptr;
 
     ~Engine() {
-        if (graph) (void)hipGraphExecDestroy(graph);
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void* p : {(void*)d_done, (void*)d_steps, (void*)d_status, (void*)d_par, (void*)d_nparts,
                         (void*)d_rows, (void*)d_newrows, (void*)d_norm, (void*)d_norm0, (void*)d_partial,
@@ -326,10 +329,8 @@ struct Engine {
 
     // Rebuild every descriptor for the current members and upload them.
     int rebuild() {
-        if (graph) {
-            (void)hipGraphExecDestroy(graph);
-            graph = nullptr;
-        }
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
         std::sort(members.begin(), members.end(), [](const Inst* x, const Inst* y) { return x->slot < y->slot; });
         groups.clear();
         gtiles.clear();
@@ -485,10 +486,13 @@ struct Engine {
             for (int i = 0; i < K; ++i) BCK(enqueue_step(tol, max_steps, s));
             return MG_OK;
         }
-        if (!graph || graph_k != K || graph_tol != tol || graph_max != max_steps) {
-            if (graph) {
-                (void)hipGraphExecDestroy(graph);
-                graph = nullptr;
+        hipGraphExec_t graph = nullptr;
+        for (const auto& g : graphs)
+            if (g.k == K && g.tol == tol && g.max_steps == max_steps) graph = g.exec;
+        if (!graph) {
+            if (graphs.size() >= 8) {  // a new tolerance or limit: start over
+                for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+                graphs.clear();
             }
             if (!cap_stream) BCK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
             BCK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
@@ -504,9 +508,7 @@ struct Engine {
             hipError_t e3 = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             BCK(e3);
-            graph_k = K;
-            graph_tol = tol;
-            graph_max = max_steps;
+            graphs.push_back({K, max_steps, tol, graph});
         }
         BCK(hipGraphLaunch(graph, s));
         return MG_OK;
@@ -849,20 +851,41 @@ int mg_batch_solve(mg_ctx* ctx, double* const* u, const double* const* f, double
     }
     BCK(E.start_fresh());
     int enq = 0;
-    const int K = 4;
-    int r = E.read_ctrl();
+    // chunks of steps: the first of kmax, later ones as many as the slowest
+    // unfinished instance's last chunk predicts it still needs
+    const int kmax = 4;
+    int K = kmax;
+    int r = E.read_ctrl(true);
     if (r != MG_OK) return r;
+    std::vector<double> prev(B.inst.size());
+    for (size_t i = 0; i < B.inst.size(); ++i) prev[i] = E.h_nrm[B.inst[i].slot];
     auto all_done = [&]() {
         for (int i = 0; i < B.count; ++i)
             if (!E.done(B.inst[(size_t)i].slot)) return false;
         return true;
     };
     while (!all_done() && enq < max_cycles) {
-        r = E.run_chunk(K, tol, max_cycles, B.use_graphs);
+        const int k = std::min(K, max_cycles - enq);
+        r = E.run_chunk(k, tol, max_cycles, B.use_graphs);
         if (r != MG_OK) return r;
-        enq += K;
-        r = E.read_ctrl();
+        enq += k;
+        r = E.read_ctrl(true);
         if (r != MG_OK) return r;
+        int need = 1;
+        for (size_t i = 0; i < B.inst.size(); ++i) {
+            const int sl = B.inst[i].slot;
+            const double cur = E.h_nrm[sl], r0 = E.h_nrm[E.cap + sl];
+            if (!E.done(sl)) {
+                int ni = kmax;
+                if (cur > 0.0 && prev[i] > 0.0 && r0 > 0.0) {
+                    const double rate = std::pow(cur / prev[i], 1.0 / k);
+                    if (rate < 0.9) ni = (int)std::ceil(std::log(tol * r0 / cur) / std::log(rate) - 1e-9);
+                }
+                need = std::max(need, std::min(kmax, std::max(1, ni)));
+            }
+            prev[i] = cur;
+        }
+        K = need;
     }
     int worst = MG_OK;
     for (int i = 0; i < B.count; ++i) {
