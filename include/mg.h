@@ -181,7 +181,9 @@ int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, cons
 
 /* count instances, each[i] their parameters: same dim, smoother, omega, nu1, nu2 for
  * all; precision MG_PREC_FP32_IR; op MG_OP_LAPLACE (MG_ENOTSUP otherwise); n may differ.
- * Allocates every instance's hierarchy.  Destroy with mg_destroy. */
+ * Allocates every instance's hierarchy and, unless the environment sets
+ * MG_AUTOTUNE=0, times the tile geometries of each level's batched launches
+ * on them (results never depend on the choice).  Destroy with mg_destroy. */
 int mg_batch_setup(int count, const mg_params* each, void* stream, mg_ctx** out);
 
 /* u[i], f[i]: DEVICE pointers (host array of count pointers) of instance i, as in
@@ -195,9 +197,13 @@ int mg_batch_solve(mg_ctx* ctx, double* const* u, const double* const* f, double
  * Serving: a request loop with continuous batching.  Requests (2D or 3D grids
  * of any accepted size) are queued; each mg_server_step admits queued requests
  * in arrival order while a slot and the HBM budget allow (hierarchies are kept
- * resident and reused from a per-size pool), then runs one refinement step
- * (FP32 V-cycle + FP64 pass) of every admitted request in shared per-level
- * launches, and completes the requests whose residual test passed.
+ * resident and reused from a per-size pool; the right-hand side is uploaded on
+ * a copy stream of the server and the request joins once it has landed),
+ * queues one refinement step (FP32 V-cycle + FP64 pass) of every joined
+ * request in shared per-level launches, and completes the requests whose
+ * residual test passed in the previous step (steps are pipelined: the call
+ * returns while the step it queued runs; results are copied back on the copy
+ * stream).
  * ------------------------------------------------------------------------- */
 
 typedef struct mg_server_params {
@@ -215,10 +221,13 @@ int mg_server_create(const mg_server_params* sp, void* stream, mg_ctx** out);
 /* Queue a request: dim 2/3, n = 2^L+1 (5 <= n <= max edge), f_host: HOST array of n^dim
  * doubles (copied).  MG_ENOMEM if the request alone exceeds the budget. */
 int mg_server_submit(mg_ctx* ctx, int dim, int n, const double* f_host, long long* req_id);
-/* Admit, one refinement step of every active request, complete finished ones.
- * Synchronises the stream.  n_active / n_queued (HOST, may be NULL) after the step. */
+/* Admit, queue one refinement step of every joined request, complete the ones
+ * the previous step finished.  Waits for the previous step only (not for the
+ * one it queues); the queued step runs on the server's stream.  n_active
+ * (admitted, not yet completed) / n_queued (HOST, may be NULL) after the call. */
 int mg_server_step(mg_ctx* ctx, int* n_active, int* n_queued);
-/* Ids of requests completed since the last poll (up to cap) into done_ids (HOST). */
+/* Ids of requests completed (result copied to host memory) since the last poll
+ * (up to cap) into done_ids (HOST).  Does not wait. */
 int mg_server_poll(mg_ctx* ctx, long long* done_ids, int cap, int* ndone);
 /* Result of a completed request: u_host (n^dim doubles, may be NULL), refinement steps,
  * final ||r||/||r0|| and seconds from submit to completion.  The request is released.
