@@ -133,8 +133,9 @@ const char* mg_strerror(int code);
  * zchunk >= 1 (3D only); 'prefetch' (3D smoothing) is 1 or 2 planes of u
  * loaded ahead and 'waves' (3D smoothing) 4 or 8 wavefronts per workgroup,
  * or 1: one wavefront per tile holding all of its rows in registers (by 8 or
- * 12) (0 = default).  3D sweeps hold by/waves rows per thread: at most 4 in
- * FP64 or with a coefficient field, 8 otherwise; with one wavefront, 12 rows
+ * 12) (0 = default).  3D sweeps hold by/waves rows per thread: at most 2 in
+ * FP64 with a coefficient field, 4 in FP64 or with one, 8 otherwise; with one
+ * wavefront, 12 rows
  * in FP32 without a coefficient field, 8 in FP32 with one or in FP64 without,
  * not available in FP64 with one (MG_EINVAL beyond).  Asynchronous on 'stream'.
  * ------------------------------------------------------------------------- */

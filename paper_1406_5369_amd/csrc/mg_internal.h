@@ -29,7 +29,10 @@ inline int max_tile_rows(int dim, int elem, bool var, int family, int wv = 4) {
         if (family != 0) return 0;
         return elem == 4 && !var ? 12 : (elem == 8 && var ? 0 : 8);
     }
-    const int rows_per_thread = (family == 0 ? (elem == 8 || var) : var) ? 4 : 8;
+    // 3D sweeps: FP64 with a coefficient field keeps six ring values per row
+    // (iterate, coefficient and four face rings) in 8-byte registers
+    const int rows_per_thread =
+        family == 0 ? (elem == 8 && var ? 2 : (elem == 8 || var ? 4 : 8)) : (var ? 4 : 8);
     return rows_per_thread * wv < 32 ? rows_per_thread * wv : 32;
 }
 

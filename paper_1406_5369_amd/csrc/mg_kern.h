@@ -96,15 +96,21 @@ __device__ __forceinline__ T res_var2(T uC, T uW, T uE, T uS, T uN, T kC, T kW, 
     return f - c * (dsum * uC - t);
 }
 
+// 3D variable-coefficient residual from the six face coefficients (each
+// kface of the lower and the upper node of its face).
 template <typename T>
-__device__ __forceinline__ T res_var3(T uC, T uW, T uE, T uS, T uN, T uB, T uT, T kC, T kW, T kE, T kS, T kN, T kB,
-                                      T kT, T f, T c, T& dsum) {
-    const T kxW = kface(kW, kC), kxC = kface(kC, kE);
-    const T kyS = kface(kS, kC), kyC = kface(kC, kN);
-    const T kzB = kface(kB, kC), kzC = kface(kC, kT);
+__device__ __forceinline__ T res_var3f(T uC, T uW, T uE, T uS, T uN, T uB, T uT, T kxW, T kxC, T kyS, T kyC, T kzB,
+                                       T kzC, T f, T c, T& dsum) {
     dsum = ((kxW + kxC) + (kyS + kyC)) + (kzB + kzC);
     const T t = ((kxW * uW + kxC * uE) + (kyS * uS + kyC * uN)) + (kzB * uB + kzC * uT);
     return f - c * (dsum * uC - t);
+}
+
+template <typename T>
+__device__ __forceinline__ T res_var3(T uC, T uW, T uE, T uS, T uN, T uB, T uT, T kC, T kW, T kE, T kS, T kN, T kB,
+                                      T kT, T f, T c, T& dsum) {
+    return res_var3f(uC, uW, uE, uS, uN, uB, uT, kface(kW, kC), kface(kC, kE), kface(kS, kC), kface(kC, kN),
+                     kface(kB, kC), kface(kC, kT), f, c, dsum);
 }
 
 // 2D stencil evaluation on an LDS box A (and coefficient box K), centre (ly, lx).

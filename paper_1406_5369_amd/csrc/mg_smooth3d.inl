@@ -20,7 +20,10 @@ namespace {
 // z-neighbours come from its own registers, x-neighbours from the adjacent
 // lanes (DPP), y-neighbours from LDS.  Register rings are indexed by
 // (plane - first plane) mod 3, resolved at compile time by unrolling three
-// steps; the coefficient ring for variable coefficients works the same way.
+// steps.  With variable coefficients the face coefficients of a plane (+x,
+// -y, +y of every node, and +z of the plane below) are formed once as the
+// plane enters and kept in rings of their own, so each is one division per
+// node and sweep rather than one per evaluation.
 //
 // With SWEEP_PROLONG the incoming iterate is u + P uc (trilinear correction
 // from the coarse grid, inner nodes only), formed as each plane enters.  A
@@ -54,6 +57,9 @@ struct Smooth3D {
     T ko[3][RPT];              // k of planes kk, kk-1, kk-2
     T ro[3][RPT];              // red-updated u of planes kk-1, kk-2, kk-3
     T fr[3][RPT];              // f of planes kk, kk-1, kk-2
+    // face coefficients (VAR) of planes kk, kk-1, kk-2: +x, -y, +y faces of
+    // the node, and the +z face (to the plane above)
+    T fxc[VAR ? 3 : 1][RPT], fys[VAR ? 3 : 1][RPT], fyn[VAR ? 3 : 1][RPT], fzc[VAR ? 3 : 1][RPT];
 
     __device__ __forceinline__ int gy(int m) const { return y0 - H + w + WV * m; }
 
@@ -183,18 +189,39 @@ struct Smooth3D {
     }
 
     // relaxation at row m of the thread, plane values: A (centre plane
-    // array in LDS for y-neighbours), own registers for centre / below / above
-    __device__ __forceinline__ T relax_at(const T (*A)[BX], T uc, T ub, T ua, T uw, T ue, int ly, T kc, T kb, T ka,
-                                          T kw, T ke, int kslot, T fv) const {
-        T ds;
+    // array in LDS for y-neighbours), own registers for centre / below / above;
+    // QC / QB: ring slots of the node's plane and of the plane below (faces);
+    // kxw: the -x face, from the neighbouring lane (taken with every lane active)
+    template <int QC, int QB>
+    __device__ __forceinline__ T relax_at(const T (*A)[BX], T uc, T ub, T ua, T uw, T ue, int ly, int m, T kxw,
+                                          T fv) const {
+        T ds, r;
         const T uS = A[ly - 1][lane], uN = A[ly + 1][lane];
-        T kS = T(1), kN = T(1);
         if constexpr (VAR) {
-            kS = K[kslot][ly - 1][lane];
-            kN = K[kslot][ly + 1][lane];
+            r = res_var3f(uc, uw, ue, uS, uN, ub, ua, kxw, fxc[QC][m], fys[QC][m], fyn[QC][m], fzc[QB][m],
+                          fzc[QC][m], fv, c, ds);
+        } else {
+            ds = T(0);
+            r = res_lap3(uc, uw, ue, uS, uN, ub, ua, fv, c);
         }
-        const T r = res3<T, VAR>(uc, uw, ue, uS, uN, ub, ua, kc, kw, ke, kS, kN, kb, ka, fv, c, ds);
         return relax<T, VAR>(uc, r, ds, c, wd, om);
+    }
+
+    // Faces of the plane that entered (slot S0; K holds its coefficients) and
+    // the +z faces of the plane below it (slot S1).
+    template <int S0, int S1>
+    __device__ __forceinline__ void faces() {
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + WV * m;  // wave-uniform
+            const T kc = ko[S0][m];
+            fxc[S0][m] = kface(kc, lane_next(kc));
+            if (ly >= 1 && ly <= BY - 2) {
+                fys[S0][m] = kface(K[S0][ly - 1][lane], kc);
+                fyn[S0][m] = kface(kc, K[S0][ly + 1][lane]);
+            }
+            fzc[S1][m] = kface(ko[S1][m], kc);
+        }
     }
 
     template <int P>
@@ -214,6 +241,7 @@ struct Smooth3D {
         issue_f(kk, fr[S0]);
         issue_u(kk + PD, un[SN], kn[SN]);
         __syncthreads();
+        if constexpr (VAR) faces<S0, S1>();
         if constexpr (SM == SM_RBGS) {
             const int m1 = kk - 1;  // red plane
             if (m1 >= z0 - 1) {
@@ -223,18 +251,10 @@ struct Smooth3D {
                     const int ly = w + WV * m, y = gy(m);
                     const T uc = uo[S1][m];
                     const T uw = lane_prev(uc), ue = lane_next(uc);
-                    T kc = T(1), kw = T(1), ke = T(1), kb = T(1), ka = T(1);
-                    if constexpr (VAR) {
-                        kc = ko[S1][m];
-                        kw = lane_prev(kc);
-                        ke = lane_next(kc);
-                        kb = ko[S2][m];
-                        ka = ko[S0][m];
-                    }
+                    const T kxw = VAR ? lane_prev(fxc[VAR ? S1 : 0][m]) : T(0);
                     T v = uc;
                     if (zin && ((mring >> m) & (minner >> m) & 1u) && ((gx + y + m1) & 1) == 0)
-                        v = relax_at(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, kc, kb, ka, kw, ke, S1,
-                                         fr[S1][m]);
+                        v = relax_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m]);
                     ro[S1][m] = v;
                     R[S1][ly][lane] = v;
                 }
@@ -247,27 +267,15 @@ struct Smooth3D {
                     const int ly = w + WV * m, y = gy(m);
                     const T rc = ro[S2][m];
                     const T rw = lane_prev(rc), re = lane_next(rc);
-                    T kc = T(1), kw = T(1), ke = T(1), kb = T(1), ka = T(1);
-                    if constexpr (VAR) {
-                        // planes kk-3 .. kk-1: ko slot P now holds plane kk, so plane kk-3 comes from kbelow
-                        kc = ko[S2][m];
-                        kw = lane_prev(kc);
-                        ke = lane_next(kc);
-                        kb = kbelow[m];
-                        ka = ko[S1][m];
-                    }
+                    const T kxw = VAR ? lane_prev(fxc[VAR ? S2 : 0][m]) : T(0);
                     if ((mtile >> m) & 1u) {
                         T v = rc;
+                        // faces of plane kk-2 (slot S2); +z faces of plane kk-3 in slot P
                         if (((gx + y + m2) & 1) == 1)
-                            v = relax_at(R[S2], rc, ro[P][m], ro[S1][m], rw, re, ly, kc, kb, ka, kw, ke, S2,
-                                             fr[S2][m]);
+                            v = relax_at<S2, P>(R[S2], rc, ro[P][m], ro[S1][m], rw, re, ly, m, kxw, fr[S2][m]);
                         st_off(uout + (size_t)m2 * pl + rowoff(m), xb, v);
                     }
                 }
-            }
-            if constexpr (VAR) {
-#pragma unroll
-                for (int m = 0; m < RPT; ++m) kbelow[m] = ko[S2][m];  // k of plane kk-2 = "below" next step
             }
         } else {
             const int m1 = kk - 1;
@@ -277,27 +285,16 @@ struct Smooth3D {
                     const int ly = w + WV * m, y = gy(m);
                     const T uc = uo[S1][m];
                     const T uw = lane_prev(uc), ue = lane_next(uc);
-                    T kc = T(1), kw = T(1), ke = T(1), kb = T(1), ka = T(1);
-                    if constexpr (VAR) {
-                        kc = ko[S1][m];
-                        kw = lane_prev(kc);
-                        ke = lane_next(kc);
-                        kb = ko[S2][m];
-                        ka = ko[S0][m];
-                    }
+                    const T kxw = VAR ? lane_prev(fxc[VAR ? S1 : 0][m]) : T(0);
                     if (((mring >> m) & (minner >> m) & 1u))
                         st_off(uout + (size_t)m1 * pl + rowoff(m), xb,
-                               relax_at(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, kc, kb, ka, kw, ke, S1,
-                                        fr[S1][m]));
+                               relax_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m]));
                 }
             }
         }
-        // LDS slots written next step: U and R never collide with this step's
-        // reads (three-slot rings); the coefficient slot of plane kk-2 does.
-        if constexpr (VAR) __syncthreads();
+        // LDS slots written next step never collide with this step's reads
+        // (three-slot rings; K is read only in the step its plane enters).
     }
-
-    T kbelow[VAR ? RPT : 1];  // k of plane kk-3 for the black relaxation
 
     __device__ __forceinline__ void run() {
         init_rows();
@@ -318,7 +315,10 @@ struct Smooth3D {
             ro[0][m] = ro[1][m] = ro[2][m] = T(0);
             fr[0][m] = fr[1][m] = fr[2][m] = T(0);  // halo rows keep these (f is not read there)
             ko[1][m] = ko[2][m] = T(1);
-            if constexpr (VAR) kbelow[m] = T(1);
+            if constexpr (VAR) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) fxc[q][m] = fys[q][m] = fyn[q][m] = fzc[q][m] = T(1);
+            }
         }
         for (; kk + 2 <= kend; kk += 3) {
             step<0>(kk);
@@ -393,6 +393,7 @@ hipError_t launch_smooth3d_rc(const GridDesc* d, int sel, TileCfg cfg, dim3 grid
 template <typename T, int SMV, bool VARV, int FL>
 hipError_t launch_smooth3d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
     constexpr bool wide = sizeof(T) == 4 && !VARV;
+    constexpr bool fp64var = sizeof(T) == 8 && VARV;  // two rows per thread at most
     if (cfg.wv == 1) {  // one wavefront per tile, rows in registers: 8 rows, or 12 in FP32 without coefficients
         if constexpr (sizeof(T) == 8 && VARV) return hipErrorInvalidValue;
         switch (cfg.by) {
@@ -406,7 +407,9 @@ hipError_t launch_smooth3d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid
     if (cfg.wv == 4) {
         switch (cfg.by) {
             case 8: return launch_smooth3d_g<T, SMV, VARV, FL, 8, 4>(d, sel, cfg, grid, s);
-            case 16: return launch_smooth3d_g<T, SMV, VARV, FL, 16, 4>(d, sel, cfg, grid, s);
+            case 16:
+                if constexpr (!fp64var) return launch_smooth3d_g<T, SMV, VARV, FL, 16, 4>(d, sel, cfg, grid, s);
+                return hipErrorInvalidValue;
             case 32:
                 if constexpr (wide) return launch_smooth3d_g<T, SMV, VARV, FL, 32, 4>(d, sel, cfg, grid, s);
                 return hipErrorInvalidValue;
@@ -416,7 +419,9 @@ hipError_t launch_smooth3d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid
     if (cfg.wv == 8) {
         switch (cfg.by) {
             case 16: return launch_smooth3d_g<T, SMV, VARV, FL, 16, 8>(d, sel, cfg, grid, s);
-            case 32: return launch_smooth3d_g<T, SMV, VARV, FL, 32, 8>(d, sel, cfg, grid, s);
+            case 32:
+                if constexpr (!fp64var) return launch_smooth3d_g<T, SMV, VARV, FL, 32, 8>(d, sel, cfg, grid, s);
+                return hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
     }

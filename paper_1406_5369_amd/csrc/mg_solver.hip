@@ -39,8 +39,9 @@ Tiles default_tiles(int dim, int elem_bytes, int n, int smoother) {
         t.norm = {by, 1};
         return t;
     }
+    // two rows per thread: within the register limit of every precision
     const int by = n >= 129 ? 16 : 8;
-    t.smooth = t.smooth_zg = t.smooth_pro = {by, heuristic_zchunk(3, n, by, H, target)};
+    t.smooth = t.smooth_zg = t.smooth_pro = {by, heuristic_zchunk(3, n, by, H, target), 1, by >= 16 ? 8 : 4};
     const int nc = (n - 1) / 2 + 1;
     const int rb = 16;
     // restriction tiles: 30 x ((rb-3)/2) coarse nodes per z-chunk of coarse planes

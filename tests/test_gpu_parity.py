@@ -44,16 +44,17 @@ def same(a, b):
 
 def over_row_limit(dim, by, dt, varcoef, waves=0):
     """3D sweeps hold by / waves rows per thread (4 wavefronts unless given): at
-    most 4 in FP64 or with a coefficient field, 8 otherwise; with one wavefront
-    per tile (waves = 1) the tile has 12 rows at most in FP32 without
-    coefficients, 8 in FP32 with them or FP64 without, none in FP64 with them.
-    The library rejects more (they would not fit the register file)."""
+    most 2 in FP64 with a coefficient field, 4 in FP64 or with one, 8
+    otherwise; with one wavefront per tile (waves = 1) the tile has 12 rows at
+    most in FP32 without coefficients, 8 in FP32 with them or FP64 without,
+    none in FP64 with them.  The library rejects more (they would not fit the
+    register file)."""
     if dim != 3 or not by:
         return False
     fp64 = dt == np.float64
     if waves == 1:
         return by > (0 if (fp64 and varcoef) else (8 if (fp64 or varcoef) else 12))
-    return by // (waves or 4) > (4 if (fp64 or varcoef) else 8)
+    return by // (waves or 4) > (2 if (fp64 and varcoef) else (4 if (fp64 or varcoef) else 8))
 
 
 def case_arrays(dim, n, dt, varcoef, seed=0):
