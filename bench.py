@@ -513,7 +513,7 @@ def main(argv=None) -> int:
              "ms_per_solve_graph_captured": ms_graph,
              "kernel_source_hash": kernel_source_hash(),
              "roofline_other_kernel": other,
-             "fine_tiles": {fam: mg.mg_tile_config(solver.ctx, 0, i) for i, fam in
+             "fine_tiles": {fam: mg.mg_tile_config(solver.ctx, 0, i, with_order=True) for i, fam in
                             enumerate(["smooth", "restrict", "norm_or_refinement", "smooth_zero_guess",
                                        "smooth_fused_correction"])}}
     if not args.no_fp64 and w["precision"] == 1:

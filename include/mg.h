@@ -114,12 +114,14 @@ int mg_num_levels(const mg_ctx* ctx);
  * (0 smoothing, 1 residual + restriction, 2 finest-level norm / refinement
  * pass, 3 smoothing from a zero iterate, 4 smoothing with the coarse-grid
  * correction fused in): tile rows *by, z-chunk *zchunk (3D planes per workgroup), for 3D
- * marching kernels *prefetch = planes of u loaded ahead (1 or 2), and *waves =
- * wavefronts per workgroup (4; 1 or 8 for 3D smoothing); prefetch and waves may
- * be NULL.  These are the autotuner's choices (measured at mg_setup unless the
- * environment sets MG_AUTOTUNE=0) or the built-in heuristic.  Results never
- * depend on them. */
-int mg_tile_config(const mg_ctx* ctx, int level, int family, int* by, int* zchunk, int* prefetch, int* waves);
+ * marching kernels *prefetch = planes of u loaded ahead (1 or 2), *waves =
+ * wavefronts per workgroup (4; 1 or 8 for 3D smoothing and the 3D pass), and
+ * for smoothing *order = block-to-tile order (0: each XCD takes a contiguous
+ * band of tiles, 1: linear); prefetch, waves and order may be NULL.  These are
+ * the autotuner's choices (measured at mg_setup unless the environment sets
+ * MG_AUTOTUNE=0) or the built-in heuristic.  Results never depend on them. */
+int mg_tile_config(const mg_ctx* ctx, int level, int family, int* by, int* zchunk, int* prefetch, int* waves,
+                   int* order);
 
 /* Human-readable name of a status code. */
 const char* mg_strerror(int code);
@@ -137,7 +139,8 @@ const char* mg_strerror(int code);
  * FP64 with a coefficient field, 4 in FP64 or with one, 8 otherwise; with one
  * wavefront, 12 rows
  * in FP32 without a coefficient field, 8 in FP32 with one or in FP64 without,
- * not available in FP64 with one (MG_EINVAL beyond).  Asynchronous on 'stream'.
+ * not available in FP64 with one (MG_EINVAL beyond).  'order' is the
+ * block-to-tile order: 0 XCD bands, 1 linear.  Asynchronous on 'stream'.
  * ------------------------------------------------------------------------- */
 
 /* One smoothing sweep (Section 2.4 GaussSeidel / Section 2.3 Jacobi) from u_in
@@ -148,7 +151,7 @@ const char* mg_strerror(int code);
  * followed by post-smoothing). */
 int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const void* k, const void* u_in,
                     const void* f, void* u_out, const void* ec, int zero_guess, int by, int zchunk, int prefetch,
-                    int waves, void* stream);
+                    int waves, int order, void* stream);
 
 /* fc = full weighting of r = f - A u (Algorithm 1: residual and restriction)
  * on the inner nodes of the coarse grid ((n-1)/2+1 per axis); fc's boundary is not written. */

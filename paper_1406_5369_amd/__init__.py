@@ -82,9 +82,9 @@ def lib():
             "mg_solve": (i, [p, p, p, d, i, C.POINTER(i), p]),
             "mg_residual_norm": (i, [p, p, p, C.POINTER(d)]),
             "mg_num_levels": (i, [p]),
-            "mg_tile_config": (i, [p, i, i, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i)]),
+            "mg_tile_config": (i, [p, i, i, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i)]),
             "mg_strerror": (C.c_char_p, [i]),
-            "mg_level_smooth": (i, [i, i, i, i, d, p, p, p, p, p, i, i, i, i, i, p]),
+            "mg_level_smooth": (i, [i, i, i, i, d, p, p, p, p, p, i, i, i, i, i, i, p]),
             "mg_level_residual_restrict": (i, [i, i, i, p, p, p, p, i, i, p]),
             "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
@@ -208,12 +208,15 @@ def mg_num_levels(ctx: int) -> int:
     return lib().mg_num_levels(ctx)
 
 
-def mg_tile_config(ctx: int, level: int, family: int):
+def mg_tile_config(ctx: int, level: int, family: int, with_order: bool = False):
     """(by, zchunk, prefetch, waves) used on a level by a kernel family (0 smooth, 1 restrict, 2 norm,
-    3 smooth from a zero iterate, 4 smooth with the fused coarse-grid correction)."""
-    by, zc, pd, wv = C.c_int(0), C.c_int(0), C.c_int(0), C.c_int(0)
-    _check(lib().mg_tile_config(ctx, level, family, C.byref(by), C.byref(zc), C.byref(pd), C.byref(wv)),
-           "mg_tile_config")
+    3 smooth from a zero iterate, 4 smooth with the fused coarse-grid correction); with_order adds the
+    block order (0 XCD bands, 1 linear)."""
+    by, zc, pd, wv, od = C.c_int(0), C.c_int(0), C.c_int(0), C.c_int(0), C.c_int(0)
+    _check(lib().mg_tile_config(ctx, level, family, C.byref(by), C.byref(zc), C.byref(pd), C.byref(wv),
+                                C.byref(od)), "mg_tile_config")
+    if with_order:
+        return by.value, zc.value, pd.value, wv.value, od.value
     return by.value, zc.value, pd.value, wv.value
 
 
@@ -255,7 +258,7 @@ def _dtype_code(t):
 
 
 def mg_level_smooth(u_in, f, u_out, smoother=SMOOTH_RBGS, omega=0.0, k=None, ec=None, zero_guess=False, by=0,
-                    zchunk=0, prefetch=0, waves=0, stream=None) -> None:
+                    zchunk=0, prefetch=0, waves=0, order=0, stream=None) -> None:
     dim, n = f.dim(), f.shape[0]
     if omega <= 0.0:
         omega = 1.0 if smoother == SMOOTH_RBGS else 0.8
@@ -263,7 +266,7 @@ def mg_level_smooth(u_in, f, u_out, smoother=SMOOTH_RBGS, omega=0.0, k=None, ec=
     _check(lib().mg_level_smooth(dim, n, _dtype_code(f), smoother, float(omega), _dptr(k, dt, f.shape, "k"),
                                  _dptr(u_in, dt, f.shape, "u_in"), _dptr(f, dt, None, "f"),
                                  _dptr(u_out, dt, f.shape, "u_out"), _dptr(ec, dt, ((n - 1) // 2 + 1,) * dim, "ec"), int(zero_guess),
-                                 by, zchunk, prefetch, waves, _stream(stream)), "mg_level_smooth")
+                                 by, zchunk, prefetch, waves, order, _stream(stream)), "mg_level_smooth")
 
 
 def mg_level_residual_restrict(u, f, fc, k=None, by=0, zchunk=0, stream=None) -> None:

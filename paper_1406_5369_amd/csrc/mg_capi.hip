@@ -448,6 +448,15 @@ TileCfg pick_fastest(const std::vector<TileCfg>& cands, TileCfg fallback, Launch
     return best;
 }
 
+// Block order of a chosen smoothing geometry: XCD bands or linear, whichever
+// times faster.
+template <class Launch>
+TileCfg pick_order(TileCfg best, Launch&& launch, hipStream_t s) {
+    TileCfg lin = best;
+    lin.order = 1;
+    return pick_fastest(std::vector<TileCfg>{best, lin}, best, launch, s);
+}
+
 bool tune_lookup(const TuneKey& k, TileCfg* out) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune.find(k);
@@ -496,10 +505,12 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
             const int fl = vflags[v];
             TuneKey ks{dim, L.elem, n, 0, sm, var ? 1 : 0, 10 + v, 0};
             if (!tune_lookup(ks, &cfg)) {
-                cfg = pick_fastest(tune_candidates(dim, n - 2, true, 0, L.elem, var), *vcfg[v], [&](TileCfg t) {
+                auto run = [&](TileCfg t) {
                     return L.elem == 8 ? launch_smooth<double>(dim, sm, var, d, 1, n, 0, fl, t, s)
                                        : launch_smooth<float>(dim, sm, var, d, 1, n, 0, fl, t, s);
-                }, s);
+                };
+                cfg = pick_fastest(tune_candidates(dim, n - 2, true, 0, L.elem, var), *vcfg[v], run, s);
+                cfg = pick_order(cfg, run, s);
                 tune_store(ks, cfg);
             }
             *vcfg[v] = cfg;
@@ -540,9 +551,9 @@ hipError_t tune_group(int dim, int smoother, const GridDesc* d, int count, int n
         const int fl = vflags[v];
         TuneKey ks{dim, 4, n, 0, smoother, 0, 10 + v, bucket};
         if (!tune_lookup(ks, &cfg)) {
-            cfg = pick_fastest(tune_candidates(dim, n - 2, true, 0, 4, false), *vcfg[v], [&](TileCfg c) {
-                return launch_smooth<float>(dim, smoother, false, d, count, n, 0, fl, c, s);
-            }, s);
+            auto run = [&](TileCfg c) { return launch_smooth<float>(dim, smoother, false, d, count, n, 0, fl, c, s); };
+            cfg = pick_fastest(tune_candidates(dim, n - 2, true, 0, 4, false), *vcfg[v], run, s);
+            cfg = pick_order(cfg, run, s);
             tune_store(ks, cfg);
         }
         *vcfg[v] = cfg;
@@ -764,7 +775,8 @@ void mg_destroy(mg_ctx* c) {
 
 int mg_num_levels(const mg_ctx* c) { return c && !is_batch_handle(c) ? c->nlev : MG_EINVAL; }
 
-int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch, int* waves) {
+int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch, int* waves,
+                   int* order) {
     if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 4)
         return MG_EINVAL;
     const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
@@ -779,6 +791,7 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
     *zchunk = t.zchunk;
     if (prefetch) *prefetch = t.pd;
     if (waves) *waves = t.wv;
+    if (order) *order = t.order;
     return MG_OK;
 }
 
@@ -957,13 +970,15 @@ static int finish_desc(void* d, hipStream_t s, hipError_t launch) {
 
 int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const void* k, const void* u_in,
                     const void* f, void* u_out, const void* ec, int zero_guess, int by, int zchunk, int prefetch,
-                    int waves, void* stream) {
+                    int waves, int order, void* stream) {
     if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
     if ((smoother != 0 && smoother != 1) || !f || !u_out || (!u_in && !zero_guess)) return MG_EINVAL;
     if (ec && zero_guess) return MG_EINVAL;
     TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, n, smoother, by, zchunk, 0);
     if (prefetch) cfg.pd = prefetch;
     if (waves) cfg.wv = waves;
+    if (order != 0 && order != 1) return MG_EINVAL;
+    cfg.order = order;
     if (!valid_cfg(cfg, dim, dtype == 0 ? 8 : 4, k != nullptr, 0)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};

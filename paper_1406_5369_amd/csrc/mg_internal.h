@@ -92,7 +92,12 @@ struct TileCfg {
     int zchunk;  // 3D: output planes per workgroup (ignored in 2D)
     int pd = 1;  // 3D smoothing: planes of old u prefetched ahead (1 or 2)
     int wv = 4;  // 3D smoothing: wavefronts per workgroup (1, 4 or 8); a thread holds by/wv rows
+    int order = 0;  // smoothing: block-to-tile order, 0 XCD bands (see xcd_tile), 1 linear
 };
+
+// Smoothing kernels take the input-buffer select and the block order in one
+// argument: bit 0 the select, bit 1 linear block order.
+inline int sweep_arg(int sel, const TileCfg& c) { return (sel & 1) | (c.order ? 2 : 0); }
 
 // Number of workgroups in x for a level of n nodes per axis (one instance).
 int smooth_tiles(int dim, int sm, int n, TileCfg cfg);

@@ -188,6 +188,10 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
     return x * q + (x < r ? x : r) + i;
 }
 
+// Tile of block b in a smoothing launch: XCD bands, or linear order when bit 1
+// of the kernel's select argument is set (the autotuner's choice).
+__device__ __forceinline__ int sweep_tile(int arg, int b, int G) { return (arg & 2) ? b : xcd_tile(b, G); }
+
 // Deterministic workgroup sum of one double per thread (fixed shuffle order,
 // then the WV wave partials pairwise in order).  Result valid in thread 0.
 template <int WV>

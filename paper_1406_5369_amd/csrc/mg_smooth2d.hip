@@ -17,10 +17,10 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
     constexpr int TX = BX - 2 * H, TY = BY - 2 * H, RPT = BY / 4;
     const int n = d.n;
     const int ntx = (n - 2 + TX - 1) / TX;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = sweep_tile(sel, blockIdx.x, gridDim.x);
     const int x0 = 1 + (tile % ntx) * TX, y0 = 1 + (tile / ntx) * TY;
-    const MG_GLOBAL T* __restrict__ uin = gp((const T*)(sel ? d.t : d.u));
-    MG_GLOBAL T* __restrict__ uout = gp((T*)(sel ? d.u : d.t));
+    const MG_GLOBAL T* __restrict__ uin = gp((const T*)((sel & 1) ? d.t : d.u));
+    MG_GLOBAL T* __restrict__ uout = gp((T*)((sel & 1) ? d.u : d.t));
     const MG_GLOBAL T* __restrict__ f = gp((const T*)d.f);
     const MG_GLOBAL T* __restrict__ kf = gp((const T*)d.k);
     const MG_GLOBAL T* __restrict__ ec = gp((const T*)d.uc);
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
 
 template <typename T, int SMV, bool VARV, int FL>
 hipError_t launch_smooth2d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
-    MG_BY_SWITCH(cfg.by, (k_smooth2d<T, SMV, VARV, BY, FL><<<grid, NT, 0, s>>>(d, sel)))
+    MG_BY_SWITCH(cfg.by, (k_smooth2d<T, SMV, VARV, BY, FL><<<grid, NT, 0, s>>>(d, sweep_arg(sel, cfg))))
     return hipSuccess;
 }
 

@@ -344,7 +344,7 @@ __global__ __launch_bounds__(64 * WV) void k_smooth3d(const GridDesc* __restrict
     s.K = K;
     const int n = d.n;
     const int ntx = (n - 2 + S::TX - 1) / S::TX, nty = (n - 2 + S::TY - 1) / S::TY;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = sweep_tile(sel, blockIdx.x, gridDim.x);
     const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
     s.n = n;
     s.x0 = 1 + tx * S::TX;
@@ -353,8 +353,8 @@ __global__ __launch_bounds__(64 * WV) void k_smooth3d(const GridDesc* __restrict
     s.z1 = min(s.z0 + zchunk, n - 1);
     s.kstart = s.z0 - S::H;
     s.kend = s.z1 - 1 + S::H;
-    s.uin = gp((const T*)(sel ? d.t : d.u));
-    s.uout = gp((T*)(sel ? d.u : d.t));
+    s.uin = gp((const T*)((sel & 1) ? d.t : d.u));
+    s.uout = gp((T*)((sel & 1) ? d.u : d.t));
     s.f = gp((const T*)d.f);
     s.kf = gp((const T*)d.k);
     s.ec = gp((const T*)d.uc);
@@ -375,15 +375,17 @@ __global__ __launch_bounds__(64 * WV) void k_smooth3d(const GridDesc* __restrict
 
 template <typename T, int SMV, bool VARV, int FL, int BY, int WV>
 hipError_t launch_smooth3d_g(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
-    if (cfg.pd == 2) k_smooth3d<T, SMV, VARV, BY, 2, FL, WV><<<grid, 64 * WV, 0, s>>>(d, sel, cfg.zchunk);
-    else k_smooth3d<T, SMV, VARV, BY, 1, FL, WV><<<grid, 64 * WV, 0, s>>>(d, sel, cfg.zchunk);
+    const int arg = sweep_arg(sel, cfg);
+    if (cfg.pd == 2) k_smooth3d<T, SMV, VARV, BY, 2, FL, WV><<<grid, 64 * WV, 0, s>>>(d, arg, cfg.zchunk);
+    else k_smooth3d<T, SMV, VARV, BY, 1, FL, WV><<<grid, 64 * WV, 0, s>>>(d, arg, cfg.zchunk);
     return hipSuccess;
 }
 
 template <typename T, int SMV, bool VARV, int FL, int BY>
 hipError_t launch_smooth3d_rc(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
-    if (cfg.pd == 2) k_smooth3d_rc<T, SMV, VARV, BY, 2, FL><<<grid, 64, 0, s>>>(d, sel, cfg.zchunk);
-    else k_smooth3d_rc<T, SMV, VARV, BY, 1, FL><<<grid, 64, 0, s>>>(d, sel, cfg.zchunk);
+    const int arg = sweep_arg(sel, cfg);
+    if (cfg.pd == 2) k_smooth3d_rc<T, SMV, VARV, BY, 2, FL><<<grid, 64, 0, s>>>(d, arg, cfg.zchunk);
+    else k_smooth3d_rc<T, SMV, VARV, BY, 1, FL><<<grid, 64, 0, s>>>(d, arg, cfg.zchunk);
     return hipSuccess;
 }
 

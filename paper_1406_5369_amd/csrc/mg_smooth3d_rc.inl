@@ -239,7 +239,7 @@ __global__ __launch_bounds__(64) void k_smooth3d_rc(const GridDesc* __restrict__
     S s;
     const int n = d.n;
     const int ntx = (n - 2 + S::TX - 1) / S::TX, nty = (n - 2 + S::TY - 1) / S::TY;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = sweep_tile(sel, blockIdx.x, gridDim.x);
     const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
     s.n = n;
     s.nc = (n - 1) / 2 + 1;
@@ -249,8 +249,8 @@ __global__ __launch_bounds__(64) void k_smooth3d_rc(const GridDesc* __restrict__
     s.z1 = min(s.z0 + zchunk, n - 1);
     s.kstart = s.z0 - S::H;
     s.kend = s.z1 - 1 + S::H;
-    s.uin = gp((const T*)(sel ? d.t : d.u));
-    s.uout = gp((T*)(sel ? d.u : d.t));
+    s.uin = gp((const T*)((sel & 1) ? d.t : d.u));
+    s.uout = gp((T*)((sel & 1) ? d.u : d.t));
     s.f = gp((const T*)d.f);
     s.kf = gp((const T*)d.k);
     s.ec = gp((const T*)d.uc);

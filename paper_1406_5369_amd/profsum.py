@@ -246,8 +246,8 @@ def traffic(fetch_db: str, write_db: str, bench_json: str) -> dict:
                 ent = _entry(runs, pass_kernel(dim, by, pd, var, ir, wv), pass_blocks(dim, n, by, zc), algo_pass)
                 if ent:
                     pass_configs[f"{by},{zc},{pd},{wv}"] = ent
-    by, zc, pd, wv = b["extra"]["fine_tiles"]["smooth"]
-    pby, pzc, ppd, pwv = b["extra"]["fine_tiles"]["norm_or_refinement"]
+    by, zc, pd, wv = b["extra"]["fine_tiles"]["smooth"][:4]
+    pby, pzc, ppd, pwv = b["extra"]["fine_tiles"]["norm_or_refinement"][:4]
     return {
         "workload": cfg["workload"],
         "source_hash": kernel_source_hash(),

@@ -93,6 +93,11 @@ def test_smooth_sweep_bitwise(dim, n, by, zc, pd, wv, smoother, dt, varcoef, dev
         return
     mg().mg_level_smooth(ud, fd, out, smoother=smoother, omega=omega, k=kd, by=by, zchunk=zc, prefetch=pd, waves=wv)
     assert same(host(out), expect)
+    # the other block-to-tile order: the same sweep, bit for bit
+    out2 = dev(np.zeros_like(u))
+    mg().mg_level_smooth(ud, fd, out2, smoother=smoother, omega=omega, k=kd, by=by, zchunk=zc, prefetch=pd, waves=wv,
+                         order=1)
+    assert same(host(out2), expect)
 
 
 @pytest.mark.parametrize("dim,n,by,zc,pd,wv", [(2, 65, 16, 0, 0, 0), (3, 33, 16, 5, 1, 8), (3, 17, 8, 0, 2, 0),
