@@ -84,7 +84,7 @@ def traffic_record(workload: str, tiles, key: str = "configs") -> dict | None:
         return None
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec.get(key, {}).get(",".join(str(int(t)) for t in tiles))
+    return rec.get(key, {}).get(",".join(str(t) for t in tiles))
 
 
 def cpu_baseline(w, gpu_steps: int, budget_s: float):
@@ -495,12 +495,13 @@ def main(argv=None) -> int:
                       "finest-level RBGS sweeps that read the previous iterate (zero-iterate and fused-correction "
                       "variants excluded)", launches, sweep_ms, (4 if var else 3) * word * dof,
                       traffic_record(args.workload, (by, zchunk, pd, wv)))
-    pby, pzc, ppd, pwv = mg.mg_tile_config(solver.ctx, 0, 2)
-    pass_roof = roof(pass_kernel(dim, pby, ppd, var, ir, pwv), pass_blocks(dim, n, pby, pzc),
+    pby, pzc, ppd, pwv, _, ppr = mg.mg_tile_config(solver.ctx, 0, 2, with_order=True)
+    pass_roof = roof(pass_kernel(dim, pby, ppd, var, ir, pwv, ppr), pass_blocks(dim, n, pby, pzc, ppr),
                      "finest-level FP64 refinement pass (u += e, r = f - A u, r to FP32, norm partials)" if ir
                      else "finest-level FP64 residual-norm pass", pass_launches, pass_ms,
                      ((32 if ir else 16) + (8 if var else 0)) * dof,
-                     traffic_record(args.workload, (pby, pzc, ppd, pwv), key="pass_configs"))
+                     traffic_record(args.workload, (pby, pzc, ppd, pwv) + (("p",) if ppr else ()),
+                                    key="pass_configs"))
     if pass_roof["total_ms"] > sweep_roof["total_ms"]:
         roofline, other = pass_roof, sweep_roof
     else:

@@ -115,13 +115,15 @@ int mg_num_levels(const mg_ctx* ctx);
  * pass, 3 smoothing from a zero iterate, 4 smoothing with the coarse-grid
  * correction fused in): tile rows *by, z-chunk *zchunk (3D planes per workgroup), for 3D
  * marching kernels *prefetch = planes of u loaded ahead (1 or 2), *waves =
- * wavefronts per workgroup (4; 1 or 8 for 3D smoothing and the 3D pass), and
- * for smoothing *order = block-to-tile order (0: each XCD takes a contiguous
- * band of tiles, 1: linear); prefetch, waves and order may be NULL.  These are
- * the autotuner's choices (measured at mg_setup unless the environment sets
- * MG_AUTOTUNE=0) or the built-in heuristic.  Results never depend on them. */
+ * wavefronts per workgroup (4; 1 or 8 for 3D smoothing and the 3D pass), for
+ * smoothing *order = block-to-tile order (0: each XCD takes a contiguous band
+ * of tiles, 1: linear), and for the 3D pass *pairs = 1 if each lane holds two
+ * adjacent nodes of a row (128-node-wide tiles, Laplacian only); prefetch,
+ * waves, order and pairs may be NULL.  These are the autotuner's choices
+ * (measured at mg_setup unless the environment sets MG_AUTOTUNE=0) or the
+ * built-in heuristic.  Results never depend on them. */
 int mg_tile_config(const mg_ctx* ctx, int level, int family, int* by, int* zchunk, int* prefetch, int* waves,
-                   int* order);
+                   int* order, int* pairs);
 
 /* Human-readable name of a status code. */
 const char* mg_strerror(int code);
@@ -169,10 +171,11 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
  * e and r are FP32 arrays; u_out's and r's boundaries are not written.  'by',
  * 'zchunk' pick the tile (0 = default); in 3D 'prefetch' is 1 or 2 planes
  * loaded ahead and 'waves' 4 or 8 wavefronts per workgroup (8 needs
- * by >= 16); 0 = default.  Synchronises the stream. */
+ * by >= 16); 0 = default; 'pairs' != 0 (3D, k NULL) runs the variant with two
+ * adjacent nodes per lane.  Synchronises the stream. */
 int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
                        double* u_out, float* r, double* norm_out, int by, int zchunk, int prefetch, int waves,
-                       void* stream);
+                       int pairs, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched solves: many independent grids (sizes may differ) in one context.

@@ -82,13 +82,14 @@ def lib():
             "mg_solve": (i, [p, p, p, d, i, C.POINTER(i), p]),
             "mg_residual_norm": (i, [p, p, p, C.POINTER(d)]),
             "mg_num_levels": (i, [p]),
-            "mg_tile_config": (i, [p, i, i, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i)]),
+            "mg_tile_config": (i, [p, i, i, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i),
+                                   C.POINTER(i)]),
             "mg_strerror": (C.c_char_p, [i]),
             "mg_level_smooth": (i, [i, i, i, i, d, p, p, p, p, p, i, i, i, i, i, i, p]),
             "mg_level_residual_restrict": (i, [i, i, i, p, p, p, p, i, i, p]),
             "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
-            "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, p]),
+            "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, i, p]),
             "mg_prof_enable": (i, [p, i]),
             "mg_prof_read": (i, [p, C.POINTER(i), C.POINTER(d)]),
             "mg_prof_read_kernel": (i, [p, i, C.POINTER(i), C.POINTER(d)]),
@@ -211,12 +212,12 @@ def mg_num_levels(ctx: int) -> int:
 def mg_tile_config(ctx: int, level: int, family: int, with_order: bool = False):
     """(by, zchunk, prefetch, waves) used on a level by a kernel family (0 smooth, 1 restrict, 2 norm,
     3 smooth from a zero iterate, 4 smooth with the fused coarse-grid correction); with_order adds the
-    block order (0 XCD bands, 1 linear)."""
-    by, zc, pd, wv, od = C.c_int(0), C.c_int(0), C.c_int(0), C.c_int(0), C.c_int(0)
+    block order (0 XCD bands, 1 linear) and the pairs flag (3D pass with two nodes per lane)."""
+    by, zc, pd, wv, od, xp = (C.c_int(0) for _ in range(6))
     _check(lib().mg_tile_config(ctx, level, family, C.byref(by), C.byref(zc), C.byref(pd), C.byref(wv),
-                                C.byref(od)), "mg_tile_config")
+                                C.byref(od), C.byref(xp)), "mg_tile_config")
     if with_order:
-        return by.value, zc.value, pd.value, wv.value, od.value
+        return by.value, zc.value, pd.value, wv.value, od.value, xp.value
     return by.value, zc.value, pd.value, wv.value
 
 
@@ -295,7 +296,8 @@ def mg_level_coarsest(u, f, k=None, stream=None) -> None:
                                    _dptr(f, dt, (3,) * dim, "f"), _stream(stream)), "mg_level_coarsest")
 
 
-def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, prefetch=0, waves=0, stream=None) -> float:
+def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, prefetch=0, waves=0, pairs=0,
+                       stream=None) -> float:
     import torch
 
     dim, n = f.dim(), f.shape[0]
@@ -304,7 +306,8 @@ def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, prefetch=0,
     _check(lib().mg_level_ir_update(dim, n, _dptr(k, torch.float64, sh, "k"), _dptr(u_in, torch.float64, sh, "u_in"),
                                     _dptr(e, torch.float32, sh, "e"), _dptr(f, torch.float64, sh, "f"),
                                     _dptr(u_out, torch.float64, sh, "u_out"), _dptr(r, torch.float32, sh, "r"),
-                                    C.byref(out), by, zchunk, prefetch, waves, _stream(stream)), "mg_level_ir_update")
+                                    C.byref(out), by, zchunk, prefetch, waves, pairs, _stream(stream)),
+           "mg_level_ir_update")
     return out.value
 
 

@@ -390,6 +390,10 @@ std::vector<TileCfg> tune_candidates(int dim, int planes, bool with_pd, int fami
             if (zc > std::max(4, planes)) break;
             v.push_back({by, zc, 1, wv});
             if (with_pd) v.push_back({by, zc, 2, wv});
+            if (family == 2 && !var) {  // the pass with two nodes per lane
+                v.push_back({by, zc, 1, wv, 0, 2});
+                if (with_pd) v.push_back({by, zc, 2, wv, 0, 2});
+            }
         }
     }
     return v;
@@ -776,7 +780,7 @@ void mg_destroy(mg_ctx* c) {
 int mg_num_levels(const mg_ctx* c) { return c && !is_batch_handle(c) ? c->nlev : MG_EINVAL; }
 
 int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch, int* waves,
-                   int* order) {
+                   int* order, int* pairs) {
     if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 4)
         return MG_EINVAL;
     const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
@@ -792,6 +796,7 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
     if (prefetch) *prefetch = t.pd;
     if (waves) *waves = t.wv;
     if (order) *order = t.order;
+    if (pairs) *pairs = t.xp == 2 ? 1 : 0;
     return MG_OK;
 }
 
@@ -945,6 +950,7 @@ static TileCfg pick_cfg(int dim, int elem, int n, int smoother, int by, int zchu
 }
 
 static bool valid_cfg(TileCfg c, int dim, int elem, bool var, int family) {
+    if (c.xp != 1 && !(c.xp == 2 && dim == 3 && family == 2 && !var)) return false;
     if (c.wv == 1) {  // 3D sweep, one wavefront per tile
         if (dim != 3 || family != 0 || (c.by != 8 && c.by != 12)) return false;
     } else {
@@ -1056,12 +1062,13 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
 
 int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
                        double* u_out, float* r, double* norm_out, int by, int zchunk, int prefetch, int waves,
-                       void* stream) {
+                       int pairs, void* stream) {
     if (!valid_edge(dim, n) || n < 5) return MG_EINVAL;
     if (!u_in || !e || !f || !u_out || !r || !norm_out || u_in == u_out) return MG_EINVAL;
     TileCfg cfg = pick_cfg(dim, 8, n, 0, by, zchunk, 2);
     if (prefetch) cfg.pd = prefetch;
     if (waves) cfg.wv = waves;
+    cfg.xp = pairs ? 2 : 1;
     if (!valid_cfg(cfg, dim, 8, k != nullptr, 2)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     IRDesc h{};

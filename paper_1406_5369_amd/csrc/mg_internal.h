@@ -93,6 +93,7 @@ struct TileCfg {
     int pd = 1;  // 3D smoothing: planes of old u prefetched ahead (1 or 2)
     int wv = 4;  // 3D smoothing: wavefronts per workgroup (1, 4 or 8); a thread holds by/wv rows
     int order = 0;  // smoothing: block-to-tile order, 0 XCD bands (see xcd_tile), 1 linear
+    int xp = 1;     // 3D norm / refinement pass (Laplacian): nodes per lane along x (1 or 2)
 };
 
 // Smoothing kernels take the input-buffer select and the block order in one

@@ -270,6 +270,285 @@ __device__ __forceinline__ void resid3d_body(const GridDesc* gd, const IRDesc* i
     if (threadIdx.x == 0) part[(size_t)inst * pstride + blockIdx.x] = t;
 }
 
+// Paired variant of the 3D pass (Laplacian): a lane owns two adjacent nodes
+// of a box row, a at even x and b = a + 1, so a box row is 128 nodes wide and
+// every load and store of a pair moves 16 bytes (FP64) or 8 bytes (FP32).
+// Pair offsets start at an even x clamped to n-3 (the pair stays in the row);
+// the boundary node x = n-1, outside every such pair, is loaded on its own by
+// the lane whose a it is.  The update and residual take the same values and
+// the same per-point expressions as the one-node-per-lane pass.
+// Pairs are accessed field by field through pointers of the word's own
+// alignment; the compiler merges them into one 16- or 8-byte access.
+struct __attribute__((aligned(8))) Dbl2 {
+    double a, b;
+};
+struct __attribute__((aligned(4))) Flt2 {
+    float a, b;
+};
+__device__ __forceinline__ Dbl2 ld_d2(const MG_GLOBAL double* base, unsigned boff) {
+    const MG_GLOBAL Dbl2* q = (const MG_GLOBAL Dbl2*)((const MG_GLOBAL char*)base + boff);
+    Dbl2 v;
+    v.a = q->a;
+    v.b = q->b;
+    return v;
+}
+__device__ __forceinline__ Flt2 ld_f2(const MG_GLOBAL float* base, unsigned boff) {
+    const MG_GLOBAL Flt2* q = (const MG_GLOBAL Flt2*)((const MG_GLOBAL char*)base + boff);
+    Flt2 v;
+    v.a = q->a;
+    v.b = q->b;
+    return v;
+}
+__device__ __forceinline__ void st_d2(MG_GLOBAL double* base, unsigned boff, const Dbl2& v) {
+    MG_GLOBAL Dbl2* q = (MG_GLOBAL Dbl2*)((MG_GLOBAL char*)base + boff);
+    q->a = v.a;
+    q->b = v.b;
+}
+__device__ __forceinline__ void st_f2(MG_GLOBAL float* base, unsigned boff, const Flt2& v) {
+    MG_GLOBAL Flt2* q = (MG_GLOBAL Flt2*)((MG_GLOBAL char*)base + boff);
+    q->a = v.a;
+    q->b = v.b;
+}
+
+template <int BY, int PD, bool IR, int WV>
+struct Pair3D {
+    static constexpr int BW = 2 * BX, TX = BW - 2, TY = BY - 2, RPT = BY / WV;
+    static_assert(RPT >= 1 && RPT * WV == BY, "tile rows must be a multiple of the wavefronts");
+    Dbl2 (*U)[BY][BX];
+    const MG_GLOBAL double* __restrict__ uin;
+    MG_GLOBAL double* __restrict__ uout;
+    const MG_GLOBAL float* __restrict__ e;
+    const MG_GLOBAL double* __restrict__ f;
+    MG_GLOBAL float* __restrict__ r32;
+    int n, x0, y0, z0, z1, kstart, kend, flags;
+    double c;
+    int lane, w, xa;
+    unsigned inx;   // bit 0: a inner in x, bit 1: b inner in x
+    unsigned rng;   // bit 0 / 1: a / b in the residual region of the box (positions 1 .. BW-2)
+    bool redge;     // the box reaches x = n-1 (uniform over the workgroup)
+    bool isedge;    // this lane's a is x = n-1
+    unsigned xp8, xp4, xe8, xe4;  // byte offsets: the pair (8- / 4-byte words), the node x = n-1
+    unsigned minner, mring;       // bit m: row m inner in y / in the tile rows 1 .. BY-2
+    size_t pl;
+    Dbl2 un[3][RPT], fr[3][RPT], uo[3][RPT];
+    Flt2 en[3][RPT];
+    double acc = 0.0;
+
+    __device__ __forceinline__ int gy(int m) const { return y0 - 1 + w + WV * m; }
+    __device__ __forceinline__ int rowoff(int m) const { return min(max(gy(m), 0), n - 1) * n; }
+
+    __device__ __forceinline__ void init_rows() {
+        pl = (size_t)n * n;
+        xa = x0 - 1 + 2 * lane;
+        const int xb = xa + 1;
+        inx = (xa >= 1 && xa <= n - 2 ? 1u : 0u) | (xb >= 1 && xb <= n - 2 ? 2u : 0u);
+        rng = (lane >= 1 ? 1u : 0u) | (lane <= BX - 2 ? 2u : 0u);
+        const unsigned xp = (unsigned)min(xa, n - 3);
+        xp8 = xp * 8u;
+        xp4 = xp * 4u;
+        xe8 = (unsigned)(n - 1) * 8u;
+        xe4 = (unsigned)(n - 1) * 4u;
+        redge = x0 - 1 + BW - 1 >= n - 1;
+        isedge = xa == n - 1;
+        minner = mring = 0;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int y = gy(m), ly = w + WV * m;
+            if (y >= 1 && y <= n - 2) minner |= 1u << m;
+            if (ly >= 1 && ly <= BY - 2) mring |= 1u << m;
+        }
+    }
+
+    __device__ __forceinline__ Dbl2 ld_row(const MG_GLOBAL double* row) const {
+        Dbl2 v = ld_d2(row, xp8);
+        if (redge) {
+            const double ve = ld_off(row, xe8);
+            if (isedge) v.a = ve;
+        }
+        return v;
+    }
+    __device__ __forceinline__ Flt2 ld_erow(const MG_GLOBAL float* row) const {
+        Flt2 v = ld_f2(row, xp4);
+        if (redge) {
+            const float ve = ld_off(row, xe4);
+            if (isedge) v.a = ve;
+        }
+        return v;
+    }
+
+    __device__ __forceinline__ void issue(int z, Dbl2 (&du)[RPT], Flt2 (&de)[RPT]) {
+        const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            du[m] = ld_row(uin + zoff + rowoff(m));
+            if constexpr (IR) {
+                if (!(flags & IR_NO_UPDATE)) de[m] = ld_erow(e + zoff + rowoff(m));
+                else de[m] = Flt2{0.0f, 0.0f};
+            }
+        }
+    }
+    // f on the tile rows only; f of x = n-1 is never used (a boundary node)
+    __device__ __forceinline__ void issue_f(int z, Dbl2 (&dst)[RPT]) {
+        const MG_GLOBAL double* __restrict__ fp = f + (size_t)min(max(z, 0), n - 1) * pl;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + WV * m;  // wave-uniform
+            if (ly >= 1 && ly <= BY - 2) dst[m] = ld_d2(fp + rowoff(m), xp8);
+        }
+    }
+
+    template <int P>
+    __device__ __forceinline__ void step(int kk) {
+        constexpr int S0 = P, S1 = (P + 2) % 3, S2 = (P + 1) % 3, SN = (P + PD) % 3;
+        const bool zin = kk >= 1 && kk <= n - 2;
+        const bool own = kk >= z0 && kk < z1;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + WV * m;
+            Dbl2 v = un[S0][m];
+            if constexpr (IR) {
+                if (!(flags & IR_NO_UPDATE)) {
+                    const bool iny = zin && ((minner >> m) & 1u);
+                    if (iny && (inx & 1u)) v.a = v.a + (double)en[S0][m].a;
+                    if (iny && (inx & 2u)) v.b = v.b + (double)en[S0][m].b;
+                    if (own && iny && ((mring >> m) & 1u)) {
+                        MG_GLOBAL double* row = uout + (size_t)kk * pl + rowoff(m);
+                        const unsigned wm = inx & rng;
+                        if (wm == 3u) {
+                            st_d2(row, xp8, v);
+                        } else {
+                            if (wm & 1u) st_off(row, xp8, v.a);
+                            if (wm & 2u) st_off(row, xp8 + 8u, v.b);
+                        }
+                    }
+                }
+            }
+            uo[S0][m] = v;
+            U[S0][ly][lane] = v;
+        }
+        if constexpr (PD == 2) issue_f(kk + 1, fr[S2]);
+        else issue_f(kk, fr[S0]);
+        issue(kk + PD, un[SN], en[SN]);
+        __syncthreads();
+        const int zz = kk - 1;
+        if (zz >= z0) {
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) {
+                const int ly = w + WV * m;
+                const Dbl2 uc = uo[S1][m];
+                const double wa = lane_prev(uc.b), eb = lane_next(uc.a);  // every lane active
+                if (((mring >> m) & (minner >> m) & 1u)) {
+                    const Dbl2 dn = U[S1][ly - 1][lane], up = U[S1][ly + 1][lane];
+                    const unsigned rm = inx & rng;
+                    const double ra = res_lap3<double>(uc.a, wa, uc.b, dn.a, up.a, uo[S2][m].a, uo[S0][m].a,
+                                                       fr[S1][m].a, c);
+                    const double rb = res_lap3<double>(uc.b, uc.a, eb, dn.b, up.b, uo[S2][m].b, uo[S0][m].b,
+                                                       fr[S1][m].b, c);
+                    if constexpr (IR) {
+                        MG_GLOBAL float* row = r32 + (size_t)zz * pl + rowoff(m);
+                        const Flt2 rv{(float)ra, (float)rb};
+                        if (rm == 3u) {
+                            st_f2(row, xp4, rv);
+                        } else {
+                            if (rm & 1u) st_off(row, xp4, rv.a);
+                            if (rm & 2u) st_off(row, xp4 + 4u, rv.b);
+                        }
+                    }
+                    if (rm & 1u) acc += ra * ra;
+                    if (rm & 2u) acc += rb * rb;
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ void run() {
+        init_rows();
+        int kk = kstart;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            fr[0][m] = fr[1][m] = fr[2][m] = Dbl2{0.0, 0.0};
+            uo[1][m] = uo[2][m] = Dbl2{0.0, 0.0};
+        }
+        issue(kk, un[0], en[0]);
+        if constexpr (PD == 2) {
+            issue(kk + 1, un[1], en[1]);
+            issue_f(kk, fr[0]);
+        }
+        for (; kk + 2 <= kend; kk += 3) {
+            step<0>(kk);
+            step<1>(kk + 1);
+            step<2>(kk + 2);
+        }
+        if (kk <= kend) step<0>(kk);
+        if (kk + 1 <= kend) step<1>(kk + 1);
+    }
+};
+
+template <int BY, int PD, bool IR, int WV>
+__device__ __forceinline__ void pair3d_body(const GridDesc* gd, const IRDesc* ird, int sel, int flags,
+                                            double* __restrict__ part, int pstride, int zchunk) {
+    using S = Pair3D<BY, PD, IR, WV>;
+    __shared__ double red[WV];
+    __shared__ Dbl2 U[3][BY][BX];
+    S s;
+    int n, inst;
+    if constexpr (IR) {
+        const IRDesc d = *ird;
+        if (d.par) sel = *gp(d.par);
+        n = d.n;
+        inst = d.inst;
+        s.uin = gp((const double*)(sel ? d.u[1] : d.u[0]));
+        s.uout = gp(sel ? d.u[0] : d.u[1]);
+        s.e = gp(d.e);
+        s.f = gp(d.f);
+        s.r32 = gp(d.r);
+        s.c = d.c;
+    } else {
+        const GridDesc d = *gd;
+        n = d.n;
+        inst = d.inst;
+        s.uin = gp((const double*)(sel ? d.t : d.u));
+        s.uout = nullptr;
+        s.e = nullptr;
+        s.f = gp((const double*)d.f);
+        s.r32 = nullptr;
+        s.c = d.c;
+    }
+    s.U = U;
+    const int ntx = (n - 2 + S::TX - 1) / S::TX, nty = (n - 2 + S::TY - 1) / S::TY;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
+    s.n = n;
+    s.x0 = 1 + tx * S::TX;
+    s.y0 = 1 + ty * S::TY;
+    s.z0 = 1 + tz * zchunk;
+    s.z1 = min(s.z0 + zchunk, n - 1);
+    s.kstart = s.z0 - 1;
+    s.kend = s.z1;
+    s.flags = flags;
+    s.lane = threadIdx.x & 63;
+    s.w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    s.run();
+    const double t = block_sum_w<WV>(s.acc, red);
+    if (threadIdx.x == 0) part[(size_t)inst * pstride + blockIdx.x] = t;
+}
+
+template <int BY, int PD, int WV>
+__global__ __launch_bounds__(64 * WV) void k_norm3d_p(const GridDesc* __restrict__ descs, int sel,
+                                                      double* __restrict__ part, int pstride, int zchunk) {
+    const GridDesc* d = descs + blockIdx.y;
+    if (d->done && *gp(d->done)) return;
+    pair3d_body<BY, PD, false, WV>(d, nullptr, sel, 0, part, pstride, zchunk);
+}
+
+template <int BY, int PD, int FL, int WV>
+__global__ __launch_bounds__(64 * WV) void k_ir3d_p(const IRDesc* __restrict__ descs, int sel,
+                                                    double* __restrict__ part, int pstride, int zchunk) {
+    const IRDesc* d = descs + blockIdx.y;
+    if (d->done && *gp(d->done)) return;
+    pair3d_body<BY, PD, true, WV>(nullptr, d, sel, FL, part, pstride, zchunk);
+}
+
 template <bool VAR, int BY, int PD, int WV>
 __global__ __launch_bounds__(64 * WV) void k_norm3d(const GridDesc* __restrict__ descs, int sel,
                                                     double* __restrict__ part, int pstride, int zchunk) {
@@ -471,6 +750,19 @@ __global__ void k_fill_int(int* __restrict__ p, int v, int count) {
 template <bool VARV, int BY, int PD>
 hipError_t launch_norm3d_w(const GridDesc* d, int sel, double* partial, int pstride, TileCfg cfg, dim3 grid,
                            hipStream_t s) {
+    if (cfg.xp == 2) {  // two nodes per lane: Laplacian only
+        if constexpr (VARV) return hipErrorInvalidValue;
+        if (cfg.wv == 8) {
+            if constexpr (BY >= 16) {
+                k_norm3d_p<BY, PD, 8><<<grid, 512, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+                return hipSuccess;
+            }
+            return hipErrorInvalidValue;
+        }
+        if (cfg.wv != 4) return hipErrorInvalidValue;
+        k_norm3d_p<BY, PD, 4><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+        return hipSuccess;
+    }
     if (cfg.wv == 8) {
         if constexpr (BY >= 16) {
             k_norm3d<VARV, BY, PD, 8><<<grid, 512, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
@@ -525,6 +817,19 @@ hipError_t launch_norm(int dim, bool var, const GridDesc* d, int ninst, int n, i
 template <bool VARV, int FL, int BY, int PD>
 hipError_t launch_ir3d_w(const IRDesc* d, int sel, double* partial, int pstride, TileCfg cfg, dim3 grid,
                          hipStream_t s) {
+    if (cfg.xp == 2) {  // two nodes per lane: Laplacian only
+        if constexpr (VARV) return hipErrorInvalidValue;
+        if (cfg.wv == 8) {
+            if constexpr (BY >= 16) {
+                k_ir3d_p<BY, PD, FL, 8><<<grid, 512, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+                return hipSuccess;
+            }
+            return hipErrorInvalidValue;
+        }
+        if (cfg.wv != 4) return hipErrorInvalidValue;
+        k_ir3d_p<BY, PD, FL, 4><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+        return hipSuccess;
+    }
     if (cfg.wv == 8) {
         if constexpr (BY >= 16) {
             k_ir3d<VARV, BY, PD, FL, 8><<<grid, 512, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);

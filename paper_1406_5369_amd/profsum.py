@@ -59,22 +59,25 @@ def sweep_kernel(dim: int, word: int, by: int, pd: int, var: bool = False, wv: i
     return f"mg::k_smooth3d<{t}, 0, {v}, {by}, {pd}, 0, {wv}>"
 
 
-def pass_kernel(dim: int, by: int, pd: int, var: bool = False, ir: bool = True, wv: int = 4) -> str:
+def pass_kernel(dim: int, by: int, pd: int, var: bool = False, ir: bool = True, wv: int = 4, pairs: int = 0) -> str:
     """Demangled name of the finest-level FP64 refinement pass (updating, as
     in a refinement step) or FP64 norm pass with the given tile height,
-    prefetch depth and wavefronts."""
+    prefetch depth and wavefronts (pairs: the 3D variant with two nodes per lane)."""
     v = "true" if var else "false"
+    if pairs and dim == 3:
+        return f"mg::k_ir3d_p<{by}, {pd}, 0, {wv}>" if ir else f"mg::k_norm3d_p<{by}, {pd}, {wv}>"
     if ir:
         return f"mg::k_ir2d<{v}, {by}, 0>" if dim == 2 else f"mg::k_ir3d<{v}, {by}, {pd}, 0, {wv}>"
     return f"mg::k_norm2d<{v}, {by}>" if dim == 2 else f"mg::k_norm3d<{v}, {by}, {pd}, {wv}>"
 
 
-def pass_blocks(dim: int, n: int, by: int, zchunk: int) -> int:
+def pass_blocks(dim: int, n: int, by: int, zchunk: int, pairs: int = 0) -> int:
     """Workgroups of a refinement / norm pass: tiles of (BX - 2) x (by - 2)
-    inner points (a one-point halo), times z-chunks in 3D."""
+    inner points (a one-point halo; 2 BX - 2 wide with two nodes per lane),
+    times z-chunks in 3D."""
     m = n - 2
     cd = lambda a, b: -(-a // b)  # noqa: E731
-    b = cd(m, BX - 2) * cd(m, by - 2)
+    b = cd(m, (2 * BX if pairs and dim == 3 else BX) - 2) * cd(m, by - 2)
     return b if dim == 2 else b * cd(m, zchunk)
 
 
@@ -243,11 +246,14 @@ def traffic(fetch_db: str, write_db: str, bench_json: str) -> dict:
             continue
         for pd in pds:
             for zc in zcs:
-                ent = _entry(runs, pass_kernel(dim, by, pd, var, ir, wv), pass_blocks(dim, n, by, zc), algo_pass)
-                if ent:
-                    pass_configs[f"{by},{zc},{pd},{wv}"] = ent
+                for pr in ((0, 1) if dim == 3 and not var else (0,)):
+                    ent = _entry(runs, pass_kernel(dim, by, pd, var, ir, wv, pr), pass_blocks(dim, n, by, zc, pr),
+                                 algo_pass)
+                    if ent:
+                        pass_configs[f"{by},{zc},{pd},{wv}" + (",p" if pr else "")] = ent
     by, zc, pd, wv = b["extra"]["fine_tiles"]["smooth"][:4]
     pby, pzc, ppd, pwv = b["extra"]["fine_tiles"]["norm_or_refinement"][:4]
+    ppr = b["extra"]["fine_tiles"]["norm_or_refinement"][5] if len(b["extra"]["fine_tiles"]["norm_or_refinement"]) > 5 else 0
     return {
         "workload": cfg["workload"],
         "source_hash": kernel_source_hash(),
@@ -255,7 +261,7 @@ def traffic(fetch_db: str, write_db: str, bench_json: str) -> dict:
         "algorithmic_bytes_pass": algo_pass,
         "calibration": {c: {"copy_kib_per_GiB": v[1], "factor": v[2]} for c, v in runs.items()},
         "bench_tiles": f"{by},{zc},{pd},{wv}",
-        "bench_pass_tiles": f"{pby},{pzc},{ppd},{pwv}",
+        "bench_pass_tiles": f"{pby},{pzc},{ppd},{pwv}" + (",p" if ppr else ""),
         "configs": configs,
         "pass_configs": pass_configs,
     }

@@ -189,20 +189,32 @@ def test_coarsest_bitwise(dim, varcoef, dev_ok):
     assert same(host(ud), expect)
 
 
-@pytest.mark.parametrize("dim,n,by,zc,pd,wv", [(2, 65, 0, 0, 0, 0), (2, 257, 8, 0, 0, 0), (3, 33, 0, 0, 0, 0),
-                                              (3, 65, 16, 3, 1, 0), (3, 65, 8, 7, 2, 4), (3, 65, 16, 5, 1, 8),
-                                              (3, 129, 32, 16, 2, 8), (3, 33, 32, 7, 2, 8), (3, 33, 16, 1, 2, 4)])
+@pytest.mark.parametrize("dim,n,by,zc,pd,wv,pr", [(2, 65, 0, 0, 0, 0, 0), (2, 257, 8, 0, 0, 0, 0),
+                                                 (3, 33, 0, 0, 0, 0, 0), (3, 65, 16, 3, 1, 0, 0),
+                                                 (3, 65, 8, 7, 2, 4, 0), (3, 65, 16, 5, 1, 8, 0),
+                                                 (3, 129, 32, 16, 2, 8, 0), (3, 33, 32, 7, 2, 8, 0),
+                                                 (3, 33, 16, 1, 2, 4, 0), (3, 5, 8, 1, 1, 4, 1), (3, 33, 8, 4, 1, 4, 1),
+                                                 (3, 129, 8, 16, 2, 4, 1), (3, 257, 16, 9, 1, 8, 1),
+                                                 (3, 65, 32, 5, 2, 8, 1)])
 @pytest.mark.parametrize("varcoef", [False, True])
-def test_refinement_pass(dim, n, by, zc, pd, wv, varcoef, dev_ok):
+def test_refinement_pass(dim, n, by, zc, pd, wv, pr, varcoef, dev_ok):
+    """pr: two nodes per lane (128-node-wide tiles, 16-byte pair accesses, the
+    grid's last node loaded on its own); Laplacian only."""
     import torch
 
     u, f, k = case_arrays(dim, n, np.float64, varcoef, seed=11)
     e = (inputs.random_guess(dim, n, 12) * 1e-3).astype(np.float32)
-    u_exp, r_exp, rho_exp = oracle.ir_update(u, e, f, k=k)
     uo = dev(np.zeros_like(u))
     r = torch.zeros(u.shape, dtype=torch.float32, device="cuda")
+    if pr and varcoef:
+        with pytest.raises(mg().MGError) as ei:
+            mg().mg_level_ir_update(dev(u), dev(e), dev(f), uo, r, k=dev(k), by=by, zchunk=zc, prefetch=pd,
+                                    waves=wv, pairs=pr)
+        assert ei.value.code == mg().MG_EINVAL
+        return
+    u_exp, r_exp, rho_exp = oracle.ir_update(u, e, f, k=k)
     rho = mg().mg_level_ir_update(dev(u), dev(e), dev(f), uo, r, k=dev(k) if k is not None else None, by=by,
-                                  zchunk=zc, prefetch=pd, waves=wv)
+                                  zchunk=zc, prefetch=pd, waves=wv, pairs=pr)
     assert same(host(uo), u_exp)
     assert same(host(r), r_exp)
     assert rho == pytest.approx(rho_exp, rel=1e-13)
