@@ -390,7 +390,7 @@ std::vector<TileCfg> tune_candidates(int dim, int planes, bool with_pd, int fami
             if (zc > std::max(4, planes)) break;
             v.push_back({by, zc, 1, wv});
             if (with_pd) v.push_back({by, zc, 2, wv});
-            if (family == 2 && !var) {  // the pass with two nodes per lane
+            if (family == 2 && !var && by <= 4 * wv) {  // two nodes per lane, at most four rows per thread
                 v.push_back({by, zc, 1, wv, 0, 2});
                 if (with_pd) v.push_back({by, zc, 2, wv, 0, 2});
             }
@@ -950,7 +950,7 @@ static TileCfg pick_cfg(int dim, int elem, int n, int smoother, int by, int zchu
 }
 
 static bool valid_cfg(TileCfg c, int dim, int elem, bool var, int family) {
-    if (c.xp != 1 && !(c.xp == 2 && dim == 3 && family == 2 && !var)) return false;
+    if (c.xp != 1 && !(c.xp == 2 && dim == 3 && family == 2 && !var && c.by <= 4 * c.wv)) return false;
     if (c.wv == 1) {  // 3D sweep, one wavefront per tile
         if (dim != 3 || family != 0 || (c.by != 8 && c.by != 12)) return false;
     } else {

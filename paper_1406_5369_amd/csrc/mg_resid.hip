@@ -271,12 +271,14 @@ __device__ __forceinline__ void resid3d_body(const GridDesc* gd, const IRDesc* i
 }
 
 // Paired variant of the 3D pass (Laplacian): a lane owns two adjacent nodes
-// of a box row, a at even x and b = a + 1, so a box row is 128 nodes wide and
-// every load and store of a pair moves 16 bytes (FP64) or 8 bytes (FP32).
-// Pair offsets start at an even x clamped to n-3 (the pair stays in the row);
-// the boundary node x = n-1, outside every such pair, is loaded on its own by
-// the lane whose a it is.  The update and residual take the same values and
-// the same per-point expressions as the one-node-per-lane pass.
+// of a box row, a at odd x and b = a + 1, so a wavefront computes 128 nodes of
+// a row and every load and store of a pair moves 16 bytes (FP64) or 8 bytes
+// (FP32).  The inner nodes 1 .. n-2 of a row (n-2 = 2^L - 1) split into whole
+// 128-node tiles; pairs (x, x+1) with odd x never cross the row's end (the
+// last is (n-2, n-1)), and pairs of lanes past the grid are clamped onto it.
+// The two x-neighbours outside the box (x0-1 for lane 0, x0+128 for lane 63)
+// are loaded on their own, one word per row.  The update and residual take the
+// same values and the same per-point expressions as the one-node-per-lane pass.
 // Pairs are accessed field by field through pointers of the word's own
 // alignment; the compiler merges them into one 16- or 8-byte access.
 struct __attribute__((aligned(8))) Dbl2 {
@@ -312,7 +314,7 @@ __device__ __forceinline__ void st_f2(MG_GLOBAL float* base, unsigned boff, cons
 
 template <int BY, int PD, bool IR, int WV>
 struct Pair3D {
-    static constexpr int BW = 2 * BX, TX = BW - 2, TY = BY - 2, RPT = BY / WV;
+    static constexpr int TX = 2 * BX, TY = BY - 2, RPT = BY / WV;
     static_assert(RPT >= 1 && RPT * WV == BY, "tile rows must be a multiple of the wavefronts");
     Dbl2 (*U)[BY][BX];
     const MG_GLOBAL double* __restrict__ uin;
@@ -322,16 +324,16 @@ struct Pair3D {
     MG_GLOBAL float* __restrict__ r32;
     int n, x0, y0, z0, z1, kstart, kend, flags;
     double c;
-    int lane, w, xa;
-    unsigned inx;   // bit 0: a inner in x, bit 1: b inner in x
-    unsigned rng;   // bit 0 / 1: a / b in the residual region of the box (positions 1 .. BW-2)
-    bool redge;     // the box reaches x = n-1 (uniform over the workgroup)
-    bool isedge;    // this lane's a is x = n-1
-    unsigned xp8, xp4, xe8, xe4;  // byte offsets: the pair (8- / 4-byte words), the node x = n-1
+    int lane, w;
+    unsigned inx;     // bit 0: a inner in x, bit 1: b inner in x
+    bool hin;         // the lane's outside neighbour (lane 0: x0-1, lane 63: x0+128) is an inner node
+    unsigned xp8, xp4, xh8, xh4;  // byte offsets: the pair, the outside neighbour (8- / 4-byte words)
     unsigned minner, mring;       // bit m: row m inner in y / in the tile rows 1 .. BY-2
     size_t pl;
     Dbl2 un[3][RPT], fr[3][RPT], uo[3][RPT];
     Flt2 en[3][RPT];
+    double hn[3][RPT], ho[3][RPT];  // outside neighbour: as loaded / updated
+    float he[3][RPT];
     double acc = 0.0;
 
     __device__ __forceinline__ int gy(int m) const { return y0 - 1 + w + WV * m; }
@@ -339,17 +341,18 @@ struct Pair3D {
 
     __device__ __forceinline__ void init_rows() {
         pl = (size_t)n * n;
-        xa = x0 - 1 + 2 * lane;
-        const int xb = xa + 1;
-        inx = (xa >= 1 && xa <= n - 2 ? 1u : 0u) | (xb >= 1 && xb <= n - 2 ? 2u : 0u);
-        rng = (lane >= 1 ? 1u : 0u) | (lane <= BX - 2 ? 2u : 0u);
-        const unsigned xp = (unsigned)min(xa, n - 3);
+        const int xa = x0 + 2 * lane;  // >= 1
+        inx = (xa <= n - 2 ? 1u : 0u) | (xa + 1 <= n - 2 ? 2u : 0u);
+        const unsigned xp = (unsigned)min(xa, n - 2);
         xp8 = xp * 8u;
         xp4 = xp * 4u;
-        xe8 = (unsigned)(n - 1) * 8u;
-        xe4 = (unsigned)(n - 1) * 4u;
-        redge = x0 - 1 + BW - 1 >= n - 1;
-        isedge = xa == n - 1;
+        // lanes 0 .. 31 read the left neighbour of the box, 32 .. 63 the right
+        // one (clamped into the row); only lanes 0 and 63 use them
+        const int xl = x0 - 1, xr = min(x0 + TX, n - 1);
+        const unsigned xh = (unsigned)(lane < 32 ? xl : xr);
+        xh8 = xh * 8u;
+        xh4 = xh * 4u;
+        hin = lane == 0 ? xl >= 1 : (x0 + TX <= n - 2);
         minner = mring = 0;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
@@ -359,35 +362,27 @@ struct Pair3D {
         }
     }
 
-    __device__ __forceinline__ Dbl2 ld_row(const MG_GLOBAL double* row) const {
-        Dbl2 v = ld_d2(row, xp8);
-        if (redge) {
-            const double ve = ld_off(row, xe8);
-            if (isedge) v.a = ve;
-        }
-        return v;
-    }
-    __device__ __forceinline__ Flt2 ld_erow(const MG_GLOBAL float* row) const {
-        Flt2 v = ld_f2(row, xp4);
-        if (redge) {
-            const float ve = ld_off(row, xe4);
-            if (isedge) v.a = ve;
-        }
-        return v;
-    }
-
-    __device__ __forceinline__ void issue(int z, Dbl2 (&du)[RPT], Flt2 (&de)[RPT]) {
+    __device__ __forceinline__ void issue(int z, Dbl2 (&du)[RPT], Flt2 (&de)[RPT], double (&dh)[RPT],
+                                          float (&dhe)[RPT]) {
         const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            du[m] = ld_row(uin + zoff + rowoff(m));
+            const MG_GLOBAL double* row = uin + zoff + rowoff(m);
+            du[m] = ld_d2(row, xp8);
+            dh[m] = ld_off(row, xh8);
             if constexpr (IR) {
-                if (!(flags & IR_NO_UPDATE)) de[m] = ld_erow(e + zoff + rowoff(m));
-                else de[m] = Flt2{0.0f, 0.0f};
+                if (!(flags & IR_NO_UPDATE)) {
+                    const MG_GLOBAL float* erow = e + zoff + rowoff(m);
+                    de[m] = ld_f2(erow, xp4);
+                    dhe[m] = ld_off(erow, xh4);
+                } else {
+                    de[m] = Flt2{0.0f, 0.0f};
+                    dhe[m] = 0.0f;
+                }
             }
         }
     }
-    // f on the tile rows only; f of x = n-1 is never used (a boundary node)
+    // f on the tile rows only
     __device__ __forceinline__ void issue_f(int z, Dbl2 (&dst)[RPT]) {
         const MG_GLOBAL double* __restrict__ fp = f + (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
@@ -406,29 +401,27 @@ struct Pair3D {
         for (int m = 0; m < RPT; ++m) {
             const int ly = w + WV * m;
             Dbl2 v = un[S0][m];
+            double h = hn[S0][m];
             if constexpr (IR) {
                 if (!(flags & IR_NO_UPDATE)) {
                     const bool iny = zin && ((minner >> m) & 1u);
                     if (iny && (inx & 1u)) v.a = v.a + (double)en[S0][m].a;
                     if (iny && (inx & 2u)) v.b = v.b + (double)en[S0][m].b;
+                    if (iny && hin) h = h + (double)he[S0][m];
                     if (own && iny && ((mring >> m) & 1u)) {
                         MG_GLOBAL double* row = uout + (size_t)kk * pl + rowoff(m);
-                        const unsigned wm = inx & rng;
-                        if (wm == 3u) {
-                            st_d2(row, xp8, v);
-                        } else {
-                            if (wm & 1u) st_off(row, xp8, v.a);
-                            if (wm & 2u) st_off(row, xp8 + 8u, v.b);
-                        }
+                        if (inx == 3u) st_d2(row, xp8, v);
+                        else if (inx & 1u) st_off(row, xp8, v.a);
                     }
                 }
             }
             uo[S0][m] = v;
+            ho[S0][m] = h;
             U[S0][ly][lane] = v;
         }
         if constexpr (PD == 2) issue_f(kk + 1, fr[S2]);
         else issue_f(kk, fr[S0]);
-        issue(kk + PD, un[SN], en[SN]);
+        issue(kk + PD, un[SN], en[SN], hn[SN], he[SN]);
         __syncthreads();
         const int zz = kk - 1;
         if (zz >= z0) {
@@ -436,10 +429,11 @@ struct Pair3D {
             for (int m = 0; m < RPT; ++m) {
                 const int ly = w + WV * m;
                 const Dbl2 uc = uo[S1][m];
-                const double wa = lane_prev(uc.b), eb = lane_next(uc.a);  // every lane active
+                double wa = lane_prev(uc.b), eb = lane_next(uc.a);  // every lane active
+                if (lane == 0) wa = ho[S1][m];
+                if (lane == BX - 1) eb = ho[S1][m];
                 if (((mring >> m) & (minner >> m) & 1u)) {
                     const Dbl2 dn = U[S1][ly - 1][lane], up = U[S1][ly + 1][lane];
-                    const unsigned rm = inx & rng;
                     const double ra = res_lap3<double>(uc.a, wa, uc.b, dn.a, up.a, uo[S2][m].a, uo[S0][m].a,
                                                        fr[S1][m].a, c);
                     const double rb = res_lap3<double>(uc.b, uc.a, eb, dn.b, up.b, uo[S2][m].b, uo[S0][m].b,
@@ -447,15 +441,11 @@ struct Pair3D {
                     if constexpr (IR) {
                         MG_GLOBAL float* row = r32 + (size_t)zz * pl + rowoff(m);
                         const Flt2 rv{(float)ra, (float)rb};
-                        if (rm == 3u) {
-                            st_f2(row, xp4, rv);
-                        } else {
-                            if (rm & 1u) st_off(row, xp4, rv.a);
-                            if (rm & 2u) st_off(row, xp4 + 4u, rv.b);
-                        }
+                        if (inx == 3u) st_f2(row, xp4, rv);
+                        else if (inx & 1u) st_off(row, xp4, rv.a);
                     }
-                    if (rm & 1u) acc += ra * ra;
-                    if (rm & 2u) acc += rb * rb;
+                    if (inx & 1u) acc += ra * ra;
+                    if (inx & 2u) acc += rb * rb;
                 }
             }
         }
@@ -468,10 +458,11 @@ struct Pair3D {
         for (int m = 0; m < RPT; ++m) {
             fr[0][m] = fr[1][m] = fr[2][m] = Dbl2{0.0, 0.0};
             uo[1][m] = uo[2][m] = Dbl2{0.0, 0.0};
+            ho[1][m] = ho[2][m] = 0.0;
         }
-        issue(kk, un[0], en[0]);
+        issue(kk, un[0], en[0], hn[0], he[0]);
         if constexpr (PD == 2) {
-            issue(kk + 1, un[1], en[1]);
+            issue(kk + 1, un[1], en[1], hn[1], he[1]);
             issue_f(kk, fr[0]);
         }
         for (; kk + 2 <= kend; kk += 3) {
@@ -750,7 +741,7 @@ __global__ void k_fill_int(int* __restrict__ p, int v, int count) {
 template <bool VARV, int BY, int PD>
 hipError_t launch_norm3d_w(const GridDesc* d, int sel, double* partial, int pstride, TileCfg cfg, dim3 grid,
                            hipStream_t s) {
-    if (cfg.xp == 2) {  // two nodes per lane: Laplacian only
+    if (cfg.xp == 2) {  // two nodes per lane: Laplacian only, at most four rows per thread
         if constexpr (VARV) return hipErrorInvalidValue;
         if (cfg.wv == 8) {
             if constexpr (BY >= 16) {
@@ -760,8 +751,11 @@ hipError_t launch_norm3d_w(const GridDesc* d, int sel, double* partial, int pstr
             return hipErrorInvalidValue;
         }
         if (cfg.wv != 4) return hipErrorInvalidValue;
-        k_norm3d_p<BY, PD, 4><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
-        return hipSuccess;
+        if constexpr (BY <= 16) {
+            k_norm3d_p<BY, PD, 4><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+            return hipSuccess;
+        }
+        return hipErrorInvalidValue;
     }
     if (cfg.wv == 8) {
         if constexpr (BY >= 16) {
@@ -817,7 +811,7 @@ hipError_t launch_norm(int dim, bool var, const GridDesc* d, int ninst, int n, i
 template <bool VARV, int FL, int BY, int PD>
 hipError_t launch_ir3d_w(const IRDesc* d, int sel, double* partial, int pstride, TileCfg cfg, dim3 grid,
                          hipStream_t s) {
-    if (cfg.xp == 2) {  // two nodes per lane: Laplacian only
+    if (cfg.xp == 2) {  // two nodes per lane: Laplacian only, at most four rows per thread
         if constexpr (VARV) return hipErrorInvalidValue;
         if (cfg.wv == 8) {
             if constexpr (BY >= 16) {
@@ -827,8 +821,11 @@ hipError_t launch_ir3d_w(const IRDesc* d, int sel, double* partial, int pstride,
             return hipErrorInvalidValue;
         }
         if (cfg.wv != 4) return hipErrorInvalidValue;
-        k_ir3d_p<BY, PD, FL, 4><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
-        return hipSuccess;
+        if constexpr (BY <= 16) {
+            k_ir3d_p<BY, PD, FL, 4><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+            return hipSuccess;
+        }
+        return hipErrorInvalidValue;
     }
     if (cfg.wv == 8) {
         if constexpr (BY >= 16) {

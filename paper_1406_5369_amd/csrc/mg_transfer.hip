@@ -308,7 +308,7 @@ int restrict_tiles(int dim, int nf, TileCfg cfg) {
 }
 
 int norm_tiles(int dim, int n, TileCfg cfg) {
-    const int TX = (dim == 3 && cfg.xp == 2 ? 2 * BX : BX) - 2, TY = cfg.by - 2, m = n - 2;
+    const int TX = dim == 3 && cfg.xp == 2 ? 2 * BX : BX - 2, TY = cfg.by - 2, m = n - 2;
     if (dim == 2) return cdiv(m, TX) * cdiv(m, TY);
     return cdiv(m, TX) * cdiv(m, TY) * nzchunks(m, cfg.zchunk);
 }

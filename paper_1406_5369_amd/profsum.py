@@ -77,7 +77,7 @@ def pass_blocks(dim: int, n: int, by: int, zchunk: int, pairs: int = 0) -> int:
     times z-chunks in 3D."""
     m = n - 2
     cd = lambda a, b: -(-a // b)  # noqa: E731
-    b = cd(m, (2 * BX if pairs and dim == 3 else BX) - 2) * cd(m, by - 2)
+    b = cd(m, 2 * BX if pairs and dim == 3 else BX - 2) * cd(m, by - 2)
     return b if dim == 2 else b * cd(m, zchunk)
 
 

@@ -195,11 +195,13 @@ def test_coarsest_bitwise(dim, varcoef, dev_ok):
                                                  (3, 129, 32, 16, 2, 8, 0), (3, 33, 32, 7, 2, 8, 0),
                                                  (3, 33, 16, 1, 2, 4, 0), (3, 5, 8, 1, 1, 4, 1), (3, 33, 8, 4, 1, 4, 1),
                                                  (3, 129, 8, 16, 2, 4, 1), (3, 257, 16, 9, 1, 8, 1),
-                                                 (3, 65, 32, 5, 2, 8, 1)])
+                                                 (3, 65, 32, 5, 2, 8, 1), (3, 257, 16, 31, 2, 4, 1),
+                                                 (3, 9, 16, 2, 2, 4, 1)])
 @pytest.mark.parametrize("varcoef", [False, True])
 def test_refinement_pass(dim, n, by, zc, pd, wv, pr, varcoef, dev_ok):
-    """pr: two nodes per lane (128-node-wide tiles, 16-byte pair accesses, the
-    grid's last node loaded on its own); Laplacian only."""
+    """pr: two nodes per lane (128 computed nodes per tile row, 16-byte pair
+    accesses, the two x-neighbours outside the tile loaded on their own);
+    Laplacian only."""
     import torch
 
     u, f, k = case_arrays(dim, n, np.float64, varcoef, seed=11)
@@ -218,6 +220,20 @@ def test_refinement_pass(dim, n, by, zc, pd, wv, pr, varcoef, dev_ok):
     assert same(host(uo), u_exp)
     assert same(host(r), r_exp)
     assert rho == pytest.approx(rho_exp, rel=1e-13)
+
+
+def test_refinement_pass_pairs_row_limit(dev_ok):
+    """Two nodes per lane hold at most four rows per thread (32 rows need
+    eight wavefronts): other shapes are rejected before any launch."""
+    import torch
+
+    u, f, _ = case_arrays(3, 33, np.float64, False, seed=11)
+    e = np.zeros(u.shape, np.float32)
+    uo = dev(np.zeros_like(u))
+    r = torch.zeros(u.shape, dtype=torch.float32, device="cuda")
+    with pytest.raises(mg().MGError) as ei:
+        mg().mg_level_ir_update(dev(u), dev(e), dev(f), uo, r, by=32, zchunk=4, prefetch=1, waves=4, pairs=1)
+    assert ei.value.code == mg().MG_EINVAL
 
 
 # ---------------------------------------------------------------- full solves
