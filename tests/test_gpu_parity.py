@@ -102,9 +102,12 @@ def test_smooth_sweep_bitwise(dim, n, by, zc, pd, wv, smoother, dt, varcoef, dev
 
 @pytest.mark.parametrize("dim,n,by,zc,pd,wv", [(2, 65, 16, 0, 0, 0), (3, 33, 16, 5, 1, 8), (3, 17, 8, 0, 2, 0),
                                               (3, 65, 32, 9, 2, 8), (3, 129, 16, 11, 1, 4), (3, 65, 12, 9, 1, 1),
-                                              (3, 33, 8, 3, 2, 1)])
+                                              (3, 33, 8, 3, 2, 1), (3, 129, 8, 7, 1, 1), (3, 9, 12, 2, 2, 1),
+                                              (3, 257, 8, 33, 1, 1)])
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 def test_smooth_zero_guess_bitwise(dim, n, by, zc, pd, wv, dt, dev_ok):
+    """wv = 1 (3D): one wavefront per tile, rows in registers (several x
+    tiles with a ragged last one at n = 129 and 257)."""
     _, f, _ = case_arrays(dim, n, dt, False, seed=3)
     expect = oracle.smooth(np.zeros_like(f), f)
     out = dev(np.zeros_like(f))
