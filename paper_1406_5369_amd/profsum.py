@@ -73,8 +73,9 @@ def pass_kernel(dim: int, by: int, pd: int, var: bool = False, ir: bool = True, 
 
 def pass_blocks(dim: int, n: int, by: int, zchunk: int, pairs: int = 0) -> int:
     """Workgroups of a refinement / norm pass: tiles of (BX - 2) x (by - 2)
-    inner points (a one-point halo; 2 BX - 2 wide with two nodes per lane),
-    times z-chunks in 3D."""
+    inner points (a one-point halo; 2 BX wide with two nodes per lane, whose
+    x-neighbours outside the tile are loaded on their own), times z-chunks in
+    3D."""
     m = n - 2
     cd = lambda a, b: -(-a // b)  # noqa: E731
     b = cd(m, 2 * BX if pairs and dim == 3 else BX - 2) * cd(m, by - 2)
