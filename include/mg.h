@@ -117,8 +117,9 @@ int mg_num_levels(const mg_ctx* ctx);
  * marching kernels *prefetch = planes of u loaded ahead (1 or 2), *waves =
  * wavefronts per workgroup (4; 1 or 8 for 3D smoothing and the 3D pass), for
  * smoothing *order = block-to-tile order (0: each XCD takes a contiguous band
- * of tiles, 1: linear), and for the 3D pass *pairs = 1 if each lane holds two
- * adjacent nodes of a row (128-node-wide tiles, Laplacian only); prefetch,
+ * of tiles, 1: linear), and for the pass *pairs = 1 if each lane holds two
+ * adjacent nodes of a row (128-node-wide tiles, Laplacian only; in 2D *zchunk
+ * is then the rows each wavefront marches); prefetch,
  * waves, order and pairs may be NULL.  These are the autotuner's choices
  * (measured at mg_setup unless the environment sets MG_AUTOTUNE=0) or the
  * built-in heuristic.  Results never depend on them. */
@@ -171,9 +172,10 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
  * e and r are FP32 arrays; u_out's and r's boundaries are not written.  'by',
  * 'zchunk' pick the tile (0 = default); in 3D 'prefetch' is 1 or 2 planes
  * loaded ahead and 'waves' 4 or 8 wavefronts per workgroup (8 needs
- * by >= 16); 0 = default; 'pairs' != 0 (3D, k NULL) runs the variant with two
- * adjacent nodes per lane (128 nodes per tile row; by <= 4 * waves, else
- * MG_EINVAL).  Synchronises the stream. */
+ * by >= 16); 0 = default; 'pairs' != 0 (k NULL) runs the variant with two
+ * adjacent nodes per lane (128 nodes per tile row; 3D: by <= 4 * waves, else
+ * MG_EINVAL; 2D: each of four wavefronts marches 'zchunk' rows along y, by
+ * ignored).  Synchronises the stream. */
 int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
                        double* u_out, float* r, double* norm_out, int by, int zchunk, int prefetch, int waves,
                        int pairs, void* stream);

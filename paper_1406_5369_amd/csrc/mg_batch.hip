@@ -263,7 +263,12 @@ struct Engine {
         cap = cap_;
         max_a = log2edge(max_n);
         tiles.resize((size_t)max_a + 1);
-        for (int a = 1; a <= max_a; ++a) tiles[(size_t)a] = default_tiles(dim, 4, (1 << a) + 1, P.smoother);
+        for (int a = 1; a <= max_a; ++a) {
+            tiles[(size_t)a] = default_tiles(dim, 4, (1 << a) + 1, P.smoother);
+            // 2D refinement pass (batches are Laplacian): two nodes per lane,
+            // each wavefront marching 64 rows
+            if (dim == 2) tiles[(size_t)a].norm = TileCfg{16, 64, 2, 4, 0, 2};
+        }
         for (int a = 2; a <= max_a; ++a)
             pstride = std::max(pstride, norm_tiles(dim, (1 << a) + 1, tiles[(size_t)a].norm));
         const size_t ci = sizeof(int) * (size_t)cap;

@@ -384,6 +384,12 @@ std::vector<TileCfg> tune_candidates(int dim, int planes, bool with_pd, int fami
         if (by > max_tile_rows(dim, elem, var, family, wv)) continue;
         if (dim == 2) {
             v.push_back({by, 1, 1, 4});
+            if (family == 2 && !var && by == 16) {  // two nodes per lane, marching chunks of rows
+                for (int yc = 8; yc <= 256 && yc <= std::max(8, planes); yc *= 2) {
+                    v.push_back({16, yc, 1, 4, 0, 2});
+                    if (with_pd) v.push_back({16, yc, 2, 4, 0, 2});
+                }
+            }
             continue;
         }
         for (int zc = 4; zc <= 256; zc *= 2) {
@@ -950,7 +956,8 @@ static TileCfg pick_cfg(int dim, int elem, int n, int smoother, int by, int zchu
 }
 
 static bool valid_cfg(TileCfg c, int dim, int elem, bool var, int family) {
-    if (c.xp != 1 && !(c.xp == 2 && dim == 3 && family == 2 && !var && c.by <= 4 * c.wv)) return false;
+    if (c.xp != 1 && !(c.xp == 2 && family == 2 && !var && (dim == 2 ? c.wv == 4 : c.by <= 4 * c.wv)))
+        return false;
     if (c.wv == 1) {  // 3D sweep, one wavefront per tile
         if (dim != 3 || family != 0 || (c.by != 8 && c.by != 12)) return false;
     } else {

@@ -89,11 +89,11 @@ struct TailDesc {
 // Launch geometry of one kernel family (picked by the autotuner).
 struct TileCfg {
     int by;      // LDS box rows (2D) / rows of the x-y box (3D): 8, 16 or 32
-    int zchunk;  // 3D: output planes per workgroup (ignored in 2D)
+    int zchunk;  // 3D: output planes per workgroup; 2D pass with xp 2: rows per wavefront
     int pd = 1;  // 3D smoothing: planes of old u prefetched ahead (1 or 2)
     int wv = 4;  // 3D smoothing: wavefronts per workgroup (1, 4 or 8); a thread holds by/wv rows
     int order = 0;  // smoothing: block-to-tile order, 0 XCD bands (see xcd_tile), 1 linear
-    int xp = 1;     // 3D norm / refinement pass (Laplacian): nodes per lane along x (1 or 2)
+    int xp = 1;     // norm / refinement pass (Laplacian): nodes per lane along x (1 or 2)
 };
 
 // Smoothing kernels take the input-buffer select and the block order in one

@@ -475,6 +475,184 @@ struct Pair3D {
     }
 };
 
+// 2D paired pass (Laplacian): a wavefront marches a strip of 128 nodes of x
+// (pairs as in the 3D paired pass, the two outside x-neighbours loaded as one
+// extra word per row) along y through a chunk of rows.  y-neighbours are the
+// thread's own three-row ring, so there is no LDS and no barrier; the four
+// wavefronts of a workgroup take four consecutive chunks of one strip.
+template <int PD, bool IR>
+struct Pair2D {
+    static constexpr int TX = 2 * BX;
+    const MG_GLOBAL double* __restrict__ uin;
+    MG_GLOBAL double* __restrict__ uout;
+    const MG_GLOBAL float* __restrict__ e;
+    const MG_GLOBAL double* __restrict__ f;
+    MG_GLOBAL float* __restrict__ r32;
+    int n, x0, y0, y1, flags;
+    double c;
+    int lane;
+    unsigned inx;
+    bool hin;
+    unsigned xp8, xp4, xh8, xh4;
+    Dbl2 un[3], fr[3], uo[3];
+    Flt2 en[3];
+    double hn[3], ho[3];
+    float he[3];
+    double acc = 0.0;
+
+    __device__ __forceinline__ void init() {
+        const int xa = x0 + 2 * lane;
+        inx = (xa <= n - 2 ? 1u : 0u) | (xa + 1 <= n - 2 ? 2u : 0u);
+        const unsigned xp = (unsigned)min(xa, n - 2);
+        xp8 = xp * 8u;
+        xp4 = xp * 4u;
+        const int xl = x0 - 1, xr = min(x0 + TX, n - 1);
+        const unsigned xh = (unsigned)(lane < 32 ? xl : xr);
+        xh8 = xh * 8u;
+        xh4 = xh * 4u;
+        hin = lane == 0 ? xl >= 1 : (x0 + TX <= n - 2);
+    }
+    __device__ __forceinline__ void issue(int y, Dbl2& du, Flt2& de, double& dh, float& dhe) {
+        const size_t off = (size_t)min(max(y, 0), n - 1) * n;
+        du = ld_d2(uin + off, xp8);
+        dh = ld_off(uin + off, xh8);
+        if constexpr (IR) {
+            if (!(flags & IR_NO_UPDATE)) {
+                de = ld_f2(e + off, xp4);
+                dhe = ld_off(e + off, xh4);
+            } else {
+                de = Flt2{0.0f, 0.0f};
+                dhe = 0.0f;
+            }
+        }
+    }
+    __device__ __forceinline__ void issue_f(int y, Dbl2& dst) { dst = ld_d2(f + (size_t)min(max(y, 0), n - 1) * n, xp8); }
+
+    template <int P>
+    __device__ __forceinline__ void step(int j) {
+        constexpr int S0 = P, S1 = (P + 2) % 3, S2 = (P + 1) % 3, SN = (P + PD) % 3;
+        const bool yin = j >= 1 && j <= n - 2;
+        Dbl2 v = un[S0];
+        double h = hn[S0];
+        if constexpr (IR) {
+            if (!(flags & IR_NO_UPDATE)) {
+                if (yin && (inx & 1u)) v.a = v.a + (double)en[S0].a;
+                if (yin && (inx & 2u)) v.b = v.b + (double)en[S0].b;
+                if (yin && hin) h = h + (double)he[S0];
+                if (yin && j >= y0 && j < y1) {
+                    MG_GLOBAL double* row = uout + (size_t)j * n;
+                    if (inx == 3u) st_d2(row, xp8, v);
+                    else if (inx & 1u) st_off(row, xp8, v.a);
+                }
+            }
+        }
+        uo[S0] = v;
+        ho[S0] = h;
+        if constexpr (PD == 2) issue_f(j + 1, fr[S2]);
+        else issue_f(j, fr[S0]);
+        issue(j + PD, un[SN], en[SN], hn[SN], he[SN]);
+        const int jj = j - 1;  // residual row
+        const Dbl2 uc = uo[S1];
+        double wa = lane_prev(uc.b), eb = lane_next(uc.a);  // every lane active
+        if (lane == 0) wa = ho[S1];
+        if (lane == BX - 1) eb = ho[S1];
+        if (jj >= y0) {
+            const double ra = res_lap2<double>(uc.a, wa, uc.b, uo[S2].a, uo[S0].a, fr[S1].a, c);
+            const double rb = res_lap2<double>(uc.b, uc.a, eb, uo[S2].b, uo[S0].b, fr[S1].b, c);
+            if constexpr (IR) {
+                MG_GLOBAL float* row = r32 + (size_t)jj * n;
+                const Flt2 rv{(float)ra, (float)rb};
+                if (inx == 3u) st_f2(row, xp4, rv);
+                else if (inx & 1u) st_off(row, xp4, rv.a);
+            }
+            if (inx & 1u) acc += ra * ra;
+            if (inx & 2u) acc += rb * rb;
+        }
+    }
+
+    __device__ __forceinline__ void run() {
+        init();
+        if (y0 >= y1) return;  // a wavefront past the last chunk
+        int j = y0 - 1;
+        const int jend = y1;
+        fr[0] = fr[1] = fr[2] = Dbl2{0.0, 0.0};
+        uo[1] = uo[2] = Dbl2{0.0, 0.0};
+        ho[1] = ho[2] = 0.0;
+        issue(j, un[0], en[0], hn[0], he[0]);
+        if constexpr (PD == 2) {
+            issue(j + 1, un[1], en[1], hn[1], he[1]);
+            issue_f(j, fr[0]);
+        }
+        for (; j + 2 <= jend; j += 3) {
+            step<0>(j);
+            step<1>(j + 1);
+            step<2>(j + 2);
+        }
+        if (j <= jend) step<0>(j);
+        if (j + 1 <= jend) step<1>(j + 1);
+    }
+};
+
+template <int PD, bool IR>
+__device__ __forceinline__ void pair2d_body(const GridDesc* gd, const IRDesc* ird, int sel, int flags,
+                                            double* __restrict__ part, int pstride, int ychunk) {
+    using S = Pair2D<PD, IR>;
+    __shared__ double red[4];
+    S s;
+    int n, inst;
+    if constexpr (IR) {
+        const IRDesc d = *ird;
+        if (d.par) sel = *gp(d.par);
+        n = d.n;
+        inst = d.inst;
+        s.uin = gp((const double*)(sel ? d.u[1] : d.u[0]));
+        s.uout = gp(sel ? d.u[0] : d.u[1]);
+        s.e = gp(d.e);
+        s.f = gp(d.f);
+        s.r32 = gp(d.r);
+        s.c = d.c;
+    } else {
+        const GridDesc d = *gd;
+        n = d.n;
+        inst = d.inst;
+        s.uin = gp((const double*)(sel ? d.t : d.u));
+        s.uout = nullptr;
+        s.e = nullptr;
+        s.f = gp((const double*)d.f);
+        s.r32 = nullptr;
+        s.c = d.c;
+    }
+    const int ntx = (n - 2 + S::TX - 1) / S::TX;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % ntx, tb = tile / ntx;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    s.n = n;
+    s.x0 = 1 + tx * S::TX;
+    s.y0 = min(1 + (tb * 4 + w) * ychunk, n - 1);
+    s.y1 = min(s.y0 + ychunk, n - 1);
+    s.flags = flags;
+    s.lane = threadIdx.x & 63;
+    s.run();
+    const double t = block_sum_w<4>(s.acc, red);
+    if (threadIdx.x == 0) part[(size_t)inst * pstride + blockIdx.x] = t;
+}
+
+template <int PD>
+__global__ __launch_bounds__(NT) void k_norm2d_p(const GridDesc* __restrict__ descs, int sel,
+                                                 double* __restrict__ part, int pstride, int ychunk) {
+    const GridDesc* d = descs + blockIdx.y;
+    if (d->done && *gp(d->done)) return;
+    pair2d_body<PD, false>(d, nullptr, sel, 0, part, pstride, ychunk);
+}
+
+template <int PD, int FL>
+__global__ __launch_bounds__(NT) void k_ir2d_p(const IRDesc* __restrict__ descs, int sel, double* __restrict__ part,
+                                               int pstride, int ychunk) {
+    const IRDesc* d = descs + blockIdx.y;
+    if (d->done && *gp(d->done)) return;
+    pair2d_body<PD, true>(nullptr, d, sel, FL, part, pstride, ychunk);
+}
+
 template <int BY, int PD, bool IR, int WV>
 __device__ __forceinline__ void pair3d_body(const GridDesc* gd, const IRDesc* ird, int sel, int flags,
                                             double* __restrict__ part, int pstride, int zchunk) {
@@ -792,7 +970,11 @@ hipError_t launch_norm(int dim, bool var, const GridDesc* d, int ninst, int n, i
                        TileCfg cfg, hipStream_t s) {
     const dim3 grid(norm_tiles(dim, n, cfg), ninst);
     if ((int)grid.x > pstride) return hipErrorInvalidValue;
-    if (dim == 2) {
+    if (dim == 2 && cfg.xp == 2) {  // two nodes per lane, marching along y: Laplacian only
+        if (var) return hipErrorInvalidValue;
+        if (cfg.pd == 2) k_norm2d_p<2><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+        else k_norm2d_p<1><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+    } else if (dim == 2) {
         if (var) {
             MG_BY_SWITCH(cfg.by, (k_norm2d<true, BY><<<grid, NT, 0, s>>>(d, sel, partial, pstride)))
         } else {
@@ -843,6 +1025,12 @@ hipError_t launch_ir3d_w(const IRDesc* d, int sel, double* partial, int pstride,
 template <bool VARV, int FL>
 hipError_t launch_ir_fl(int dim, const IRDesc* d, int sel, double* partial, int pstride, TileCfg cfg, dim3 grid,
                         hipStream_t s) {
+    if (dim == 2 && cfg.xp == 2) {  // two nodes per lane, marching along y: Laplacian only
+        if constexpr (VARV) return hipErrorInvalidValue;
+        if (cfg.pd == 2) k_ir2d_p<2, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+        else k_ir2d_p<1, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);
+        return hipSuccess;
+    }
     if (dim == 2) {
         MG_BY_SWITCH(cfg.by, (k_ir2d<VARV, BY, FL><<<grid, NT, 0, s>>>(d, sel, partial, pstride)))
         return hipSuccess;

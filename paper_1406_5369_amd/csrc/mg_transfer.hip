@@ -308,7 +308,10 @@ int restrict_tiles(int dim, int nf, TileCfg cfg) {
 }
 
 int norm_tiles(int dim, int n, TileCfg cfg) {
-    const int TX = dim == 3 && cfg.xp == 2 ? 2 * BX : BX - 2, TY = cfg.by - 2, m = n - 2;
+    const int TX = cfg.xp == 2 ? 2 * BX : BX - 2, TY = cfg.by - 2, m = n - 2;
+    // 2D with two nodes per lane: each of the four wavefronts of a workgroup
+    // marches its own chunk of cfg.zchunk rows
+    if (dim == 2 && cfg.xp == 2) return cdiv(m, TX) * cdiv(cdiv(m, cfg.zchunk), 4);
     if (dim == 2) return cdiv(m, TX) * cdiv(m, TY);
     return cdiv(m, TX) * cdiv(m, TY) * nzchunks(m, cfg.zchunk);
 }

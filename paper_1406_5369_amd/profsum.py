@@ -66,6 +66,8 @@ def pass_kernel(dim: int, by: int, pd: int, var: bool = False, ir: bool = True, 
     v = "true" if var else "false"
     if pairs and dim == 3:
         return f"mg::k_ir3d_p<{by}, {pd}, 0, {wv}>" if ir else f"mg::k_norm3d_p<{by}, {pd}, {wv}>"
+    if pairs:
+        return f"mg::k_ir2d_p<{pd}, 0>" if ir else f"mg::k_norm2d_p<{pd}>"
     if ir:
         return f"mg::k_ir2d<{v}, {by}, 0>" if dim == 2 else f"mg::k_ir3d<{v}, {by}, {pd}, 0, {wv}>"
     return f"mg::k_norm2d<{v}, {by}>" if dim == 2 else f"mg::k_norm3d<{v}, {by}, {pd}, {wv}>"
@@ -75,10 +77,13 @@ def pass_blocks(dim: int, n: int, by: int, zchunk: int, pairs: int = 0) -> int:
     """Workgroups of a refinement / norm pass: tiles of (BX - 2) x (by - 2)
     inner points (a one-point halo; 2 BX wide with two nodes per lane, whose
     x-neighbours outside the tile are loaded on their own), times z-chunks in
-    3D."""
+    3D; in 2D with two nodes per lane, strips of 2 BX nodes in chunks of
+    zchunk rows, four chunks per workgroup."""
     m = n - 2
     cd = lambda a, b: -(-a // b)  # noqa: E731
-    b = cd(m, 2 * BX if pairs and dim == 3 else BX - 2) * cd(m, by - 2)
+    if pairs and dim == 2:  # four wavefronts per workgroup, each marching zchunk rows
+        return cd(m, 2 * BX) * cd(cd(m, zchunk), 4)
+    b = cd(m, 2 * BX if pairs else BX - 2) * cd(m, by - 2)
     return b if dim == 2 else b * cd(m, zchunk)
 
 

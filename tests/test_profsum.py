@@ -13,8 +13,10 @@ def test_pass_blocks_paired_and_single():
     assert profsum.pass_blocks(3, 513, 16, 64, pairs=1) == 4 * 37 * 8 == 1184
     # one node per lane: 62 nodes per tile row -> 9 x-tiles; 30 rows -> 18; 32 planes -> 16
     assert profsum.pass_blocks(3, 513, 32, 32) == 9 * 18 * 16
-    # 2D passes have no pairs variant and no z-chunks
-    assert profsum.pass_blocks(2, 4097, 16, 0, pairs=1) == 67 * 293
+    # 2D: 62 x 14 LDS tiles; with pairs, 128-node strips in 32-row chunks, four per workgroup
+    assert profsum.pass_blocks(2, 4097, 16, 0) == 67 * 293
+    assert profsum.pass_blocks(2, 4097, 16, 32, pairs=1) == 32 * 32
+    assert profsum.pass_blocks(2, 1025, 16, 32, pairs=1) == 8 * 8
     # smallest grid: one tile
     assert profsum.pass_blocks(3, 5, 8, 1, pairs=1) == 1 * 1 * 3
 
@@ -29,6 +31,8 @@ def test_kernel_names():
     assert profsum.pass_kernel(3, 16, 2, ir=True, wv=8, pairs=1) == "mg::k_ir3d_p<16, 2, 0, 8>"
     assert profsum.pass_kernel(3, 8, 1, ir=False, wv=4, pairs=1) == "mg::k_norm3d_p<8, 1, 4>"
     assert profsum.pass_kernel(3, 16, 1, var=True, ir=True, wv=4) == "mg::k_ir3d<true, 16, 1, 0, 4>"
+    assert profsum.pass_kernel(2, 16, 2, ir=True, pairs=1) == "mg::k_ir2d_p<2, 0>"
+    assert profsum.pass_kernel(2, 16, 1, ir=False, pairs=1) == "mg::k_norm2d_p<1>"
     assert profsum.sweep_kernel(3, 4, 16, 1, wv=4) == "mg::k_smooth3d<float, 0, false, 16, 1, 0, 4>"
     assert profsum.sweep_kernel(3, 4, 8, 2, wv=1) == "mg::k_smooth3d_rc<float, 0, false, 8, 2, 0>"
     assert profsum.sweep_kernel(3, 8, 32, 1, wv=8) == "mg::k_smooth3d<double, 0, false, 32, 1, 0, 8>"
