@@ -266,8 +266,9 @@ struct Engine {
         for (int a = 1; a <= max_a; ++a) {
             tiles[(size_t)a] = default_tiles(dim, 4, (1 << a) + 1, P.smoother);
             // 2D refinement pass (batches are Laplacian): two nodes per lane,
-            // each wavefront marching 64 rows
-            if (dim == 2) tiles[(size_t)a].norm = TileCfg{16, 64, 2, 4, 0, 2};
+            // each wavefront marching 32 rows (longer chunks leave the smaller
+            // grids of a batch too few workgroups)
+            if (dim == 2) tiles[(size_t)a].norm = TileCfg{16, 32, 2, 4, 0, 2};
         }
         for (int a = 2; a <= max_a; ++a)
             pstride = std::max(pstride, norm_tiles(dim, (1 << a) + 1, tiles[(size_t)a].norm));
