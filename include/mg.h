@@ -174,8 +174,8 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
  * loaded ahead and 'waves' 4 or 8 wavefronts per workgroup (8 needs
  * by >= 16); 0 = default; 'pairs' != 0 (k NULL) runs the variant with two
  * adjacent nodes per lane (128 nodes per tile row; 3D: by <= 4 * waves, else
- * MG_EINVAL; 2D: each of four wavefronts marches 'zchunk' rows along y, by
- * ignored).  Synchronises the stream. */
+ * MG_EINVAL; 2D: each of four wavefronts marches 'zchunk' rows along y, 0 =
+ * 32, by ignored).  Synchronises the stream. */
 int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
                        double* u_out, float* r, double* norm_out, int by, int zchunk, int prefetch, int waves,
                        int pairs, void* stream);

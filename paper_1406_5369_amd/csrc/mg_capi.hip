@@ -1076,6 +1076,7 @@ int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, cons
     if (prefetch) cfg.pd = prefetch;
     if (waves) cfg.wv = waves;
     cfg.xp = pairs ? 2 : 1;
+    if (cfg.xp == 2 && dim == 2 && !zchunk) cfg.zchunk = 32;  // rows each wavefront marches
     if (!valid_cfg(cfg, dim, 8, k != nullptr, 2)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     IRDesc h{};

@@ -201,7 +201,8 @@ def test_coarsest_bitwise(dim, varcoef, dev_ok):
                                                  (3, 65, 32, 5, 2, 8, 1), (3, 257, 16, 31, 2, 4, 1),
                                                  (3, 9, 16, 2, 2, 4, 1), (2, 65, 16, 8, 1, 4, 1),
                                                  (2, 257, 16, 32, 2, 4, 1), (2, 129, 16, 5, 1, 4, 1),
-                                                 (2, 5, 16, 1, 2, 4, 1), (2, 1025, 16, 100, 2, 4, 1)])
+                                                 (2, 5, 16, 1, 2, 4, 1), (2, 1025, 16, 100, 2, 4, 1),
+                                                 (2, 513, 0, 0, 0, 0, 1)])
 @pytest.mark.parametrize("varcoef", [False, True])
 def test_refinement_pass(dim, n, by, zc, pd, wv, pr, varcoef, dev_ok):
     """pr: two nodes per lane (128 computed nodes per tile row, 16-byte pair
