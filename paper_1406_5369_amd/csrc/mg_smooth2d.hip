@@ -35,6 +35,17 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
     const int gx = x0 - H + lane;
     const bool colg = gx >= 0 && gx < n, coli = gx >= 1 && gx <= n - 2;
     const bool lane1 = lane >= 1 && lane <= BX - 2;  // tile + 1 ring (RBGS) / tile (Jacobi)
+    // Coarse-grid correction (bilinear, as interp2): each lane loads its
+    // coarse column in the coarse rows y/2 and y/2 + (y odd) from clamped
+    // addresses; an odd-x node takes the other coarse column from the
+    // neighbouring lane.  x0 is odd, so with the two-node halo (RBGS) even
+    // lanes hold odd x and their partner is the next lane (loaded at x/2), and
+    // with the one-node halo (Jacobi) odd lanes hold odd x and their partner
+    // is the previous lane (loaded at (x+1)/2): no lane needs one outside the
+    // wavefront.
+    const int xcl = min(max(gx, 0), n - 1);
+    const int cx = H == 2 ? xcl >> 1 : (xcl + 1) >> 1;
+    const bool xo = (gx & 1) != 0;
     T fr[RPT];
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
@@ -44,7 +55,23 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
         const size_t p = (size_t)gy * n + gx;
         T v = T(0);
         if (ing && !(flags & SWEEP_ZERO_GUESS)) v = uin[p];
-        if (inn && (flags & SWEEP_PROLONG)) v = v + interp2<T>(ec, nc, gx, gy);
+        if constexpr ((flags & SWEEP_PROLONG) != 0) {
+            const int ycl = min(max(gy, 0), n - 1);
+            const MG_GLOBAL T* __restrict__ r0 = ec + (size_t)(ycl >> 1) * nc;
+            const T a = r0[cx], b = r0[(ycl & 1) ? nc + cx : cx];
+            T sa, sb;
+            if constexpr (H == 2) {
+                const T an = lane_next(a), bn = lane_next(b);  // every lane active
+                sa = xo ? a + an : a;
+                sb = xo ? b + bn : b;
+            } else {
+                const T ap = lane_prev(a), bp = lane_prev(b);
+                sa = xo ? ap + a : a;
+                sb = xo ? bp + b : b;
+            }
+            const T corr = (ycl & 1) ? (xo ? T(0.25) * (sa + sb) : T(0.5) * (sa + sb)) : (xo ? T(0.5) * sa : sa);
+            if (inn) v = v + corr;
+        }
         U[ly][lane] = v;
         if constexpr (VAR) K[ly][lane] = ing ? kf[p] : T(1);
         fr[m] = (inn && lane1 && ly >= 1 && ly <= BY - 2) ? f[p] : T(0);

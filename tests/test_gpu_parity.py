@@ -119,7 +119,8 @@ def test_smooth_zero_guess_bitwise(dim, n, by, zc, pd, wv, dt, dev_ok):
     assert same(host(out), expect)
 
 
-FUSED_CASES = [(2, 9, 0, 0, 0, 0), (2, 65, 0, 0, 0, 0), (2, 257, 0, 0, 0, 0),
+FUSED_CASES = [(2, 9, 0, 0, 0, 0), (2, 65, 0, 0, 0, 0), (2, 257, 0, 0, 0, 0), (2, 5, 8, 0, 0, 0),
+               (2, 129, 8, 0, 0, 0), (2, 129, 32, 0, 0, 0), (2, 513, 16, 0, 0, 0),
                (3, 5, 0, 0, 0, 0), (3, 9, 8, 1, 1, 0), (3, 17, 16, 3, 2, 8), (3, 33, 8, 5, 1, 0),
                (3, 33, 32, 2, 2, 8), (3, 65, 16, 7, 1, 8), (3, 65, 0, 0, 0, 0), (3, 129, 16, 13, 1, 8),
                (3, 33, 16, 5, 2, 4), (3, 129, 32, 7, 1, 8), (3, 65, 8, 7, 2, 1), (3, 129, 12, 13, 1, 1),
