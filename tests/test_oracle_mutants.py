@@ -35,11 +35,20 @@ MUTANTS = {
                            "const T kyS = kface(k[p - sx], kp), kyC = kface(kp, k[p + sy]);"),
     "coarsest_diag": ("diag = g.c * (g.dim == 2 ? T(4) : T(6));", "diag = g.c * (g.dim == 2 ? T(4) : T(4));"),
     "jacobi_in_place": ("tmp[p] = smooth_at(g, u, f, p);", "u[p] = smooth_at(g, u, f, p); tmp[p] = u[p];"),
+    "norm_skips_last_row": ("for (int j = 1; j < n - 1; ++j)\n            for (int i = 1; i < n - 1; ++i) {\n"
+                            "                const double r = (double)residual_at",
+                            "for (int j = 1; j < n - 2; ++j)\n            for (int i = 1; i < n - 1; ++i) {\n"
+                            "                const double r = (double)residual_at"),
+    "norm_no_sqrt": ("return std::sqrt(s);", "return s;"),
+    "norm_abs_not_square": ("s += r * r;", "s += std::fabs(r);"),
+    "norm_plain_sum": ("s += r * r;", "s += r;"),
 }
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_planted_mistake(name, tmp_path):
+    """Only the pin suite runs against the mutant: the golden histories, which
+    the oracle itself wrote, take no part in catching it."""
     old, new = MUTANTS[name]
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"

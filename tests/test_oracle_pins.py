@@ -353,3 +353,48 @@ def test_mixed_precision_refinement_reaches_fp64_solution(dim, n, varcoef):
     n64 = int(np.argmax(h64 <= 1e-8 * h64[0]))
     nir = int(np.argmax(hir <= 1e-8 * hir[0]))
     assert nir <= n64 + 2
+
+
+# ------------------------------------------------ residual norm (Section 2.4 Application, L2 residual)
+@pytest.mark.parametrize("dim,n,modes", [(2, 17, MODES2), (2, 33, MODES2[:3]), (3, 9, MODES3[:3]), (3, 17, MODES3)])
+def test_norm_of_eigenmode_residual_closed_form(dim, n, modes):
+    """With f = 0 and u = phi_k the residual is -lambda_k phi_k; over the inner
+    nodes sum_i sin^2(k pi i h) = (n-1)/2 for every axis, so the unscaled
+    Euclidean norm is lambda_k ((n-1)/2)^(d/2) (closed form)."""
+    h = 1.0 / (n - 1)
+    f0 = np.zeros((n,) * dim)
+    for kv in modes:
+        phi = mode(dim, n, kv)
+        got = oracle.residual_norm(phi, f0)
+        want = lam(kv, h) * ((n - 1) / 2.0) ** (dim / 2.0)
+        assert got == pytest.approx(want, rel=1e-12)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 5), (2, 17), (2, 65), (3, 5), (3, 9), (3, 33)])
+@pytest.mark.parametrize("varcoef", [False, True])
+def test_norm_is_euclidean_norm_of_pinned_residual(dim, n, varcoef):
+    """The norm is the 2-norm of the residual array (itself pinned by P1, P9
+    and P12) over every inner node: compared with numpy's Euclidean norm,
+    random u and f, Laplacian and variable coefficients."""
+    rng = np.random.default_rng(40 + n + dim)
+    k = inputs.varcoef_k(n, 41, dim=dim) if varcoef else None
+    for _ in range(2):
+        u = inputs.zero_boundary(rng.uniform(-1, 1, (n,) * dim))
+        f = inputs.zero_boundary(rng.uniform(-1, 1, (n,) * dim))
+        r = oracle.residual(u, f, k=k)
+        want = float(np.linalg.norm(r.ravel()))
+        assert oracle.residual_norm(u, f, k=k) == pytest.approx(want, rel=1e-14)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 9), (3, 9)])
+def test_norm_counts_every_inner_node_once(dim, n):
+    """A residual of 3 at one inner node has norm 3, wherever the node is
+    (corners, edges and faces of the inner region included)."""
+    u = np.zeros((n,) * dim)
+    for ix in [(1,) * dim, (n - 2,) * dim, (1,) + (n - 2,) * (dim - 1), (n - 2,) + (1,) * (dim - 1),
+               (n // 2,) * dim]:
+        f = np.zeros((n,) * dim)
+        f[ix] = 3.0
+        assert oracle.residual_norm(u, f) == 3.0
+    f = inputs.zero_boundary(np.ones((n,) * dim))
+    assert oracle.residual_norm(u, f) == pytest.approx(math.sqrt((n - 2) ** dim), rel=1e-15)
