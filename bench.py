@@ -14,7 +14,12 @@ the larger total time; both timed with HIP events on the solver's stream over
 the timed region, the other reported beside it) and the CPU oracle timed on a
 bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+The default line also carries, in `extra`, shorter runs of the batched form
+(512 uneven 2D grids, solves/s and DoF/s beside the same grids solved one by
+one in FP64) and of the serving form (saturated solves/s, p50/p99 latency per
+arrival rate), and the CPU oracle on one thread and on all physical cores.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--no-forms]
 """
 
 from __future__ import annotations
@@ -22,6 +27,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -87,9 +93,10 @@ def traffic_record(workload: str, tiles, key: str = "configs") -> dict | None:
     return rec.get(key, {}).get(",".join(str(t) for t in tiles))
 
 
-def cpu_baseline(w, gpu_steps: int, budget_s: float):
+def cpu_baseline(w, gpu_steps: int, budget_s: float, min_steps: int = 3):
     """Time the oracle (as it stands) on one refinement step / one V-cycle of
-    the same workload on this host; scale to the solve's step count."""
+    the same workload on this host; scale to the solve's step count.  Runs
+    with the OpenMP thread count of the environment."""
     import numpy as np
 
     import oracle
@@ -102,6 +109,11 @@ def cpu_baseline(w, gpu_steps: int, budget_s: float):
     threads = oracle.num_threads()
     t_steps = []
     t0 = time.perf_counter()
+
+    def enough():
+        el = time.perf_counter() - t0
+        return el > budget_s or (len(t_steps) >= min_steps and el > 1.0)
+
     if w["precision"] == 1:
         e = np.zeros(f.shape, np.float32)
         while True:
@@ -109,7 +121,7 @@ def cpu_baseline(w, gpu_steps: int, budget_s: float):
             u, r32, _ = oracle.ir_update(u, e, f, k=k)
             e = oracle.vcycle(np.zeros(f.shape, np.float32), r32, k=k32)
             t_steps.append(time.perf_counter() - ts)
-            if time.perf_counter() - t0 > budget_s or (len(t_steps) >= 3 and time.perf_counter() - t0 > 1.0):
+            if enough():
                 break
         sample = "FP64 refinement pass + FP32 V(2,2) cycle"
     else:
@@ -118,7 +130,7 @@ def cpu_baseline(w, gpu_steps: int, budget_s: float):
             u = oracle.vcycle(u, f, k=k)
             oracle.residual_norm(u, f, k=k)
             t_steps.append(time.perf_counter() - ts)
-            if time.perf_counter() - t0 > budget_s or (len(t_steps) >= 3 and time.perf_counter() - t0 > 1.0):
+            if enough():
                 break
         sample = "FP64 V(2,2) cycle + residual norm"
     t_step = float(np.median(t_steps))
@@ -131,6 +143,66 @@ def cpu_baseline(w, gpu_steps: int, budget_s: float):
         "kind": "oracle",
         "sample": f"{len(t_steps)} x ({sample}) on the {n}^{dim} workload, median {t_step:.3f} s per step, "
                   f"scaled by the {gpu_steps} steps of the solve",
+    }
+
+
+def cpu_info() -> dict:
+    """CPU model and core counts of this host (lscpu), and the CPUs this process may use."""
+    info = {"model": None, "sockets": None, "cores_per_socket": None, "threads_per_core": None}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        keys = {"Model name": "model", "Socket(s)": "sockets", "Core(s) per socket": "cores_per_socket",
+                "Thread(s) per core": "threads_per_core"}
+        for line in out.splitlines():
+            name, _, val = line.partition(":")
+            if name.strip() in keys and info[keys[name.strip()]] is None:
+                v = val.strip()
+                info[keys[name.strip()]] = int(v) if v.isdigit() else v
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if isinstance(info["sockets"], int) and isinstance(info["cores_per_socket"], int):
+        info["physical_cores"] = info["sockets"] * info["cores_per_socket"]
+    else:
+        info["physical_cores"] = None
+    info["cpus_allowed"] = len(os.sched_getaffinity(0))
+    return info
+
+
+def cpu_baseline_legs(workload: str, gpu_steps: int, budget_s: float) -> dict:
+    """The oracle on one thread and on all physical cores this process may use
+    (OMP_PROC_BIND=close, OMP_PLACES=cores), each in a child process (which
+    never touches the GPU).  A thread limit set in the environment
+    (OMP_NUM_THREADS) caps the all-core leg."""
+    info = cpu_info()
+    allc = info["physical_cores"] or info["cpus_allowed"]
+    allc = min(allc, info["cpus_allowed"])
+    env_cap = os.environ.get("OMP_NUM_THREADS", "")
+    if env_cap.isdigit() and int(env_cap) > 0:
+        allc = min(allc, int(env_cap))
+    legs = []
+    for threads, budget, min_steps in ((1, budget_s * 0.6, 1), (allc, budget_s * 0.4, 3)):
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads), OMP_PROC_BIND="close", OMP_PLACES="cores")
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", "--workload", workload,
+               "--gpu-steps", str(gpu_steps), "--cpu-budget", str(budget), "--cpu-min-steps", str(min_steps)]
+        res = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+        if res.returncode != 0:
+            raise RuntimeError(f"CPU leg with {threads} threads failed: {res.stderr[-2000:]}")
+        leg = json.loads(res.stdout.strip().splitlines()[-1])
+        leg["threads"] = threads
+        legs.append(leg)
+    main_leg = legs[-1]
+    return {
+        "value": main_leg["value"],
+        "unit": "DoF/s",
+        "cores": main_leg["cores"],
+        "kind": "oracle",
+        "sample": main_leg["sample"],
+        "cpu_model": info["model"],
+        "physical_cores": info["physical_cores"],
+        "cpus_allowed": info["cpus_allowed"],
+        "legs": [{"threads": g["threads"], "value": g["value"], "cores": g["cores"], "sample": g["sample"]}
+                 for g in legs],
+        "gpu_over_cpu_one_thread": None,
     }
 
 
@@ -364,7 +436,19 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-budget-gib", type=int, default=48)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run the plain copy kernel over 1 GiB three times (counter calibration)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched and serving legs of the default workload's line")
+    ap.add_argument("--forms-requests", type=int, default=1000,
+                    help="requests per arrival rate of the serving leg in the default workload's line")
+    # child-process mode of the CPU baseline (never touches the GPU)
+    ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--gpu-steps", type=int, default=7, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-min-steps", type=int, default=3, help=argparse.SUPPRESS)
     args = ap.parse_args(argv)
+    if args.cpu_leg:
+        print(json.dumps(cpu_baseline(WORKLOADS[args.workload], args.gpu_steps, args.cpu_budget,
+                                      args.cpu_min_steps)), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
               file=sys.stderr)
@@ -380,9 +464,11 @@ def main(argv=None) -> int:
         return 2
     if args.workload == "batched_2d":
         print(json.dumps(bench_batched(args, mg, torch)), flush=True)
+        mg.shutdown()
         return 0
     if args.workload == "serving_mix":
         print(json.dumps(bench_serving(args, mg, torch)), flush=True)
+        mg.shutdown()
         return 0
     w = WORKLOADS[args.workload]
     dim, n = w["dim"], w["n"]
@@ -536,12 +622,36 @@ def main(argv=None) -> int:
         extra["mixed_over_fp64_speedup"] = value / extra["fp64_solve"]["dof_per_s"]
         log(f"[bench] FP64 solve: {(tb - ta) * 1e3 / reps:.3f} ms, {cyc64} cycles")
     solver.close()
+    del us, f, kd
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    # The other forms of the solver in the same line (default workload only):
+    # the 512-grid batch and the serving sweep, each a shorter run of its own
+    # workload (--workload batched_2d / serving_mix run them in full).
+    if args.workload == "poisson3d_513_fp32ir" and not args.no_forms:
+        bargs = argparse.Namespace(**vars(args))
+        bargs.steps, bargs.warmup, bargs.no_fp64 = 3, 1, False
+        b = bench_batched(bargs, mg, torch)
+        extra["batched_2d"] = {"workload": b["config"]["workload"], "grids": b["config"]["grids"],
+                               "dof": b["config"]["dof"], "ms_per_batch": b["ms_per_step"],
+                               "dof_per_s": b["value"], "batches_timed": bargs.steps, **b["extra"]}
+        torch.cuda.empty_cache()
+        sargs = argparse.Namespace(**vars(args))
+        sargs.serve_requests = args.forms_requests
+        sargs.serve_fp64_requests = min(args.serve_fp64_requests, 200)
+        sv = bench_serving(sargs, mg, torch)
+        extra["serving_mix"] = {"requests_per_lambda": sargs.serve_requests, "config": sv["config"],
+                                "saturated_solves_per_s": sv["value"], **sv["extra"]}
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu:
-        log("[bench] CPU oracle baseline ...")
-        cpu = cpu_baseline(w, cycles[-1], args.cpu_budget)
-        log(f"[bench] CPU oracle: {cpu['value'] / 1e6:.3f} MDoF/s on {cpu['cores']} threads")
+        log("[bench] CPU oracle baseline (1 thread, all physical cores) ...")
+        cpu = cpu_baseline_legs(args.workload, cycles[-1], args.cpu_budget)
+        cpu["gpu_over_cpu_one_thread"] = value / cpu["legs"][0]["value"]
+        log(f"[bench] CPU oracle ({cpu['cpu_model']}): " + ", ".join(
+            f"{g['value'] / 1e6:.3f} MDoF/s on {g['cores']} threads" for g in cpu["legs"]))
 
     out = {
         "metric": "fine-grid DoF/s + HBM GB/s %peak; solves/s & p99 latency at 1e-8 residual",
@@ -571,6 +681,7 @@ def main(argv=None) -> int:
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+    mg.shutdown()
     return 0
 
 

@@ -28,6 +28,8 @@ CXXFLAGS = ["-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-mat
 
 SMOOTH_RBGS = 0
 SMOOTH_JACOBI = 1
+SMOOTH_RBGS_SYM = 2  # symmetric red-black: red first before the correction, black first after it
+CYCLE_V, CYCLE_W, CYCLE_F = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -72,9 +74,15 @@ def _load():
         "orc_residual_norm_f64": (_d, [_i, _i, _p, _p, _p]),
         "orc_vcycle_f64": (_i, [_i, _i, _p, _i, _d, _i, _i, _p, _p]),
         "orc_vcycle_f32": (_i, [_i, _i, _p, _i, _d, _i, _i, _p, _p]),
+        "orc_cycle_f64": (_i, [_i, _i, _p, _i, _d, _i, _i, _i, _i, _i, _p, _p]),
+        "orc_cycle_f32": (_i, [_i, _i, _p, _i, _d, _i, _i, _i, _i, _i, _p, _p]),
+        "orc_coarsest_cg_f64": (None, [_i, _i, _p, _i, _p, _p]),
+        "orc_coarsest_cg_f32": (None, [_i, _i, _p, _i, _p, _p]),
         "orc_solve_f64": (_i, [_i, _i, _p, _i, _d, _i, _i, _p, _p, _d, _i, _p, _p]),
+        "orc_solve_mg_f64": (_i, [_i, _i, _p, _i, _d, _i, _i, _i, _i, _i, _p, _p, _d, _i, _p, _p]),
         "orc_ir_update_f32": (_d, [_i, _i, _p, _p, _p, _p, _p]),
         "orc_solve_ir_f32": (_i, [_i, _i, _p, _i, _d, _i, _i, _p, _p, _d, _i, _p, _p]),
+        "orc_solve_ir_mg_f32": (_i, [_i, _i, _p, _i, _d, _i, _i, _i, _i, _i, _p, _p, _d, _i, _p, _p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -181,28 +189,44 @@ def residual_norm(u, f, k=None) -> float:
     return float(_load().orc_residual_norm_f64(dim, n, _ptr(k), _ptr(u), _ptr(f)))
 
 
-def vcycle(u, f, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None):
-    """One V(nu1, nu2) cycle; FP64 or FP32 by dtype; returns a new array."""
+def coarsest_cg(u, f, k=None, iters=0):
+    """Conjugate gradients on a coarsest grid (any n = 2^L+1) from u = 0, `iters`
+    steps (0: 4(n-1)); FP64 or FP32 by dtype; returns a new array (u is only
+    used for its shape)."""
+    dt = f.dtype
+    _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, dt, "k")
+    dim, n = _dims(f)
+    out = np.zeros_like(f)
+    fn = _load().orc_coarsest_cg_f64 if dt == np.float64 else _load().orc_coarsest_cg_f32
+    fn(dim, n, _ptr(k), int(iters), _ptr(out), _ptr(f))
+    return out
+
+
+def vcycle(u, f, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None, cycle=CYCLE_V, coarse_n=3, cg_iters=0):
+    """One multigrid cycle (V by default; W, F with `cycle`; coarsest level of
+    edge `coarse_n`, solved by conjugate gradients when larger than 3);
+    FP64 or FP32 by dtype; returns a new array."""
     dt = u.dtype
     _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, dt, "k")
     dim, n = _dims(u)
     out = u.copy()
-    fn = _load().orc_vcycle_f64 if dt == np.float64 else _load().orc_vcycle_f32
-    rc = fn(dim, n, _ptr(k), smoother, omega, nu1, nu2, _ptr(out), _ptr(f))
+    fn = _load().orc_cycle_f64 if dt == np.float64 else _load().orc_cycle_f32
+    rc = fn(dim, n, _ptr(k), smoother, omega, nu1, nu2, cycle, coarse_n, cg_iters, _ptr(out), _ptr(f))
     if rc != 0:
-        raise ValueError(f"oracle vcycle rejected its arguments (rc={rc})")
+        raise ValueError(f"oracle cycle rejected its arguments (rc={rc})")
     return out
 
 
-def solve(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None):
-    """FP64 V-cycle solve.  Returns (u, history of ||f - A u||_2, status)."""
+def solve(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None, cycle=CYCLE_V,
+          coarse_n=3, cg_iters=0):
+    """FP64 multigrid solve.  Returns (u, history of ||f - A u||_2, status)."""
     _chk(u0, np.float64, "u0"), _chk(f, np.float64, "f"), _chk(k, np.float64, "k")
     dim, n = _dims(u0)
     u = u0.copy()
     hist = np.zeros(max_cycles + 1)
     cyc = C.c_int(0)
-    rc = _load().orc_solve_f64(dim, n, _ptr(k), smoother, omega, nu1, nu2, _ptr(u), _ptr(f), tol,
-                               max_cycles, _ptr(hist), C.addressof(cyc))
+    rc = _load().orc_solve_mg_f64(dim, n, _ptr(k), smoother, omega, nu1, nu2, cycle, coarse_n, cg_iters, _ptr(u),
+                                  _ptr(f), tol, max_cycles, _ptr(hist), C.addressof(cyc))
     if rc < 0:
         raise ValueError(f"oracle solve rejected its arguments (rc={rc})")
     return u, hist[: cyc.value + 1].copy(), rc
@@ -218,15 +242,16 @@ def ir_update(u, e, f, k=None):
     return out, r32, float(rho)
 
 
-def solve_ir_f32(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None):
-    """FP32 V-cycles inside FP64 iterative refinement.  Returns (u, history, status)."""
+def solve_ir_f32(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None,
+                 cycle=CYCLE_V, coarse_n=3, cg_iters=0):
+    """FP32 cycles inside FP64 iterative refinement.  Returns (u, history, status)."""
     _chk(u0, np.float64, "u0"), _chk(f, np.float64, "f"), _chk(k, np.float64, "k")
     dim, n = _dims(u0)
     u = u0.copy()
     hist = np.zeros(max_cycles + 1)
     cyc = C.c_int(0)
-    rc = _load().orc_solve_ir_f32(dim, n, _ptr(k), smoother, omega, nu1, nu2, _ptr(u), _ptr(f), tol,
-                                  max_cycles, _ptr(hist), C.addressof(cyc))
+    rc = _load().orc_solve_ir_mg_f32(dim, n, _ptr(k), smoother, omega, nu1, nu2, cycle, coarse_n, cg_iters,
+                                     _ptr(u), _ptr(f), tol, max_cycles, _ptr(hist), C.addressof(cyc))
     if rc < 0:
         raise ValueError(f"oracle solve rejected its arguments (rc={rc})")
     return u, hist[: cyc.value + 1].copy(), rc

@@ -153,12 +153,15 @@ inline idx_t at(int dim, int n, int i, int j, int k) {
 /* Smoothers (Section 2.3 component list; Section 2.4 GaussSeidel)      */
 /* ------------------------------------------------------------------ */
 
-/* One red-black Gauss-Seidel sweep in place: all red nodes, then all black. */
+/* One red-black Gauss-Seidel sweep in place: all red nodes, then all black
+ * (first = 1: all black, then all red -- the second half of a symmetric
+ * red-black smoother, Table 1 "red-black variants"). */
 template <typename T>
-void rbgs_sweep(const Grid<T>& g, T* u, const T* f) {
+void rbgs_sweep(const Grid<T>& g, T* u, const T* f, int first = 0) {
     const int n = g.n;
     const int k0 = g.dim == 3 ? 1 : 0, k1 = g.dim == 3 ? n - 1 : 1; /* one pass of k in 2D */
-    for (int colour = 0; colour < 2; ++colour) {
+    for (int half = 0; half < 2; ++half) {
+        const int colour = half ^ first;
 #pragma omp parallel for schedule(static)
         for (int k = k0; k < k1; ++k)
             for (int j = 1; j < n - 1; ++j)
@@ -319,7 +322,13 @@ void coarsest_solve(const Grid<T>& g, T* u, const T* f) {
 /* Level hierarchy and the recursive V-cycle (Algorithm 1)              */
 /* ------------------------------------------------------------------ */
 
-enum { SMOOTH_RBGS = 0, SMOOTH_JACOBI = 1 };
+/* Smoothers: red-black GS (red first in every sweep), omega-Jacobi, and the
+ * symmetric red-black variant (red first before the coarse-grid correction,
+ * black first after it). */
+enum { SMOOTH_RBGS = 0, SMOOTH_JACOBI = 1, SMOOTH_RBGS_SYM = 2 };
+/* Cycle types: V (one recursive call per level, Algorithm 1), W (two calls),
+ * F (an F-cycle call followed by a V-cycle call). */
+enum { CYCLE_V = 0, CYCLE_W = 1, CYCLE_F = 2 };
 
 inline size_t npts(int dim, int n) { return dim == 3 ? (size_t)n * n * n : (size_t)n * n; }
 
@@ -337,6 +346,9 @@ template <typename T>
 struct Hierarchy {
     int dim, nlev, smoother, nu1, nu2;
     double omega;
+    int cycle = CYCLE_V;   /* enum above */
+    int coarse_n = 3;      /* edge of the coarsest level */
+    int cg_iters = 0;      /* conjugate-gradient steps on a coarsest level with n > 3 */
     std::vector<int> n;               /* n[0] finest */
     std::vector<std::vector<T>> u, f, r, k;
     std::vector<T> tmp;
@@ -357,16 +369,18 @@ struct Hierarchy {
  * empty: the caller's arrays are used there.  k (if given) is converted to T
  * and injected to coarse levels. */
 template <typename T>
-void build(Hierarchy<T>& H, int dim, int n, const double* k64, int smoother, double omega, int nu1, int nu2) {
+void build(Hierarchy<T>& H, int dim, int n, const double* k64, int smoother, double omega, int nu1, int nu2,
+           int coarse_n = 3) {
     H.dim = dim;
     H.smoother = smoother;
     H.omega = omega;
     H.nu1 = nu1;
     H.nu2 = nu2;
+    H.coarse_n = coarse_n < 3 ? 3 : coarse_n;
     H.n.clear();
     for (int m = n; m >= 3; m = (m - 1) / 2 + 1) {
         H.n.push_back(m);
-        if (m == 3) break;
+        if (m <= H.coarse_n) break;
     }
     H.nlev = (int)H.n.size();
     H.u.assign((size_t)H.nlev, {});
@@ -398,33 +412,127 @@ void build(Hierarchy<T>& H, int dim, int n, const double* k64, int smoother, dou
     }
 }
 
+/* post = 1 for the smoothing sweeps after the coarse-grid correction */
 template <typename T>
-void smooth(Hierarchy<T>& H, int l, T* u, const T* f) {
+void smooth(Hierarchy<T>& H, int l, T* u, const T* f, int post = 0) {
     const Grid<T> g = H.grid(l);
     if (H.smoother == SMOOTH_RBGS)
-        rbgs_sweep(g, u, f);
+        rbgs_sweep(g, u, f, 0);
+    else if (H.smoother == SMOOTH_RBGS_SYM)
+        rbgs_sweep(g, u, f, post);
     else
         jacobi_sweep(g, u, f, H.tmp);
 }
 
-/* Algorithm 1 on level l with solution u and right-hand side f */
+/* <a, b> over inner nodes, products and sum in FP64 */
 template <typename T>
-void vcycle(Hierarchy<T>& H, int l, T* u, const T* f) {
+double dot_inner(int dim, int n, const T* a, const T* b) {
+    double s = 0.0;
+    const int k0 = dim == 3 ? 1 : 0, k1 = dim == 3 ? n - 1 : 1;
+    for (int k = k0; k < k1; ++k)
+        for (int j = 1; j < n - 1; ++j)
+            for (int i = 1; i < n - 1; ++i) {
+                const idx_t p = at(dim, n, i, j, k);
+                s += (double)a[p] * (double)b[p];
+            }
+    return s;
+}
+
+/* Coarsest level with more than one unknown: conjugate gradients (the
+ * iterative option of Algorithm 1's coarsest-grid solve) on A u = f from
+ * u = 0, a fixed number of steps (fewer only if the residual becomes exactly
+ * zero).  Vectors in T; inner products in FP64, alpha and beta formed in
+ * FP64 and rounded to T for the updates. */
+template <typename T>
+void coarsest_cg(const Grid<T>& g, T* u, const T* f, int iters) {
+    const int n = g.n, dim = g.dim;
+    const size_t total = npts(dim, n);
+    std::vector<T> r(total, T(0)), p(total, T(0)), q(total, T(0));
+    const int k0 = dim == 3 ? 1 : 0, k1 = dim == 3 ? n - 1 : 1;
+    for (size_t i = 0; i < total; ++i) u[i] = T(0);
+    for (int k = k0; k < k1; ++k)
+        for (int j = 1; j < n - 1; ++j)
+            for (int i = 1; i < n - 1; ++i) {
+                const idx_t x = at(dim, n, i, j, k);
+                r[(size_t)x] = f[x];
+                p[(size_t)x] = f[x];
+            }
+    double rr = dot_inner(dim, n, r.data(), r.data());
+    for (int it = 0; it < iters && rr > 0.0; ++it) {
+        for (int k = k0; k < k1; ++k)
+            for (int j = 1; j < n - 1; ++j)
+                for (int i = 1; i < n - 1; ++i) {
+                    const idx_t x = at(dim, n, i, j, k);
+                    if (g.k) {
+                        T dsum;
+                        q[(size_t)x] = apply_varcoef(g, p.data(), x, &dsum);
+                    } else {
+                        q[(size_t)x] = apply_poisson(g, p.data(), x);
+                    }
+                }
+        const double pq = dot_inner(dim, n, p.data(), q.data());
+        if (!(pq > 0.0)) break;
+        const T alpha = (T)(rr / pq);
+        for (int k = k0; k < k1; ++k)
+            for (int j = 1; j < n - 1; ++j)
+                for (int i = 1; i < n - 1; ++i) {
+                    const size_t x = (size_t)at(dim, n, i, j, k);
+                    u[x] = u[x] + alpha * p[x];
+                    r[x] = r[x] - alpha * q[x];
+                }
+        const double rr_new = dot_inner(dim, n, r.data(), r.data());
+        const T beta = (T)(rr_new / rr);
+        for (int k = k0; k < k1; ++k)
+            for (int j = 1; j < n - 1; ++j)
+                for (int i = 1; i < n - 1; ++i) {
+                    const size_t x = (size_t)at(dim, n, i, j, k);
+                    p[x] = r[x] + beta * p[x];
+                }
+        rr = rr_new;
+    }
+}
+
+/* default number of conjugate-gradient steps on a coarsest level of edge n */
+inline int cg_default_iters(int n) { return 4 * (n - 1); }
+
+/* Multigrid cycle on level l (Algorithm 1 with gamma recursive calls):
+ * kind V calls itself once, W twice, F an F-cycle then a V-cycle.  Each
+ * call after the first continues from the coarse iterate the previous call
+ * left (the zero guess precedes the first call only). */
+template <typename T>
+void mgcycle(Hierarchy<T>& H, int l, T* u, const T* f, int kind) {
     const Grid<T> g = H.grid(l);
     if (l == H.nlev - 1) {
-        coarsest_solve(g, u, f);
+        if (g.n == 3)
+            coarsest_solve(g, u, f);
+        else
+            coarsest_cg(g, u, f, H.cg_iters > 0 ? H.cg_iters : cg_default_iters(g.n));
         return;
     }
-    for (int s = 0; s < H.nu1; ++s) smooth(H, l, u, f);          /* presmoothing */
+    for (int s = 0; s < H.nu1; ++s) smooth(H, l, u, f, 0);       /* presmoothing */
     T* r = H.r[(size_t)l].data();
     residual(g, u, f, r);                                         /* residual */
     T* fc = H.f[(size_t)l + 1].data();
     restrict_fw(H.dim, g.n, r, fc);                               /* restriction */
     T* uc = H.u[(size_t)l + 1].data();
     std::fill(H.u[(size_t)l + 1].begin(), H.u[(size_t)l + 1].end(), T(0)); /* zero guess */
-    vcycle(H, l + 1, uc, fc);                                     /* recursion */
+    if (kind == CYCLE_V) {
+        mgcycle(H, l + 1, uc, fc, CYCLE_V);                       /* recursion */
+    } else if (kind == CYCLE_W) {
+        mgcycle(H, l + 1, uc, fc, CYCLE_W);
+        mgcycle(H, l + 1, uc, fc, CYCLE_W);
+    } else {
+        mgcycle(H, l + 1, uc, fc, CYCLE_F);
+        mgcycle(H, l + 1, uc, fc, CYCLE_V);
+    }
     prolong_correct(H.dim, g.n, u, uc);                           /* coarse-grid correction */
-    for (int s = 0; s < H.nu2; ++s) smooth(H, l, u, f);        /* postsmoothing */
+    for (int s = 0; s < H.nu2; ++s) smooth(H, l, u, f, 1);        /* postsmoothing */
+}
+
+/* Algorithm 1 on level l with solution u and right-hand side f */
+template <typename T>
+void vcycle(Hierarchy<T>& H, int l, T* u, const T* f) {
+    mgcycle(H, l, u, f, H.cycle);
 }
 
 template <typename T>
@@ -471,18 +579,29 @@ void orc_residual_f32(int dim, int n, const float* k, const float* u, const floa
     residual(g, u, f, r);
 }
 
-/* one smoothing sweep in place (smoother 0 = RBGS, 1 = Jacobi) */
+/* one smoothing sweep in place (smoother 0 = RBGS red first, 1 = Jacobi,
+ * 2 = RBGS black first: the post-smoothing sweep of the symmetric variant) */
 void orc_smooth_f64(int dim, int n, const double* k, int smoother, double omega, double* u, const double* f) {
     const Grid<double> g = make_grid<double>(dim, n, k, omega);
     std::vector<double> tmp;
-    if (smoother == SMOOTH_RBGS) rbgs_sweep(g, u, f);
-    else jacobi_sweep(g, u, f, tmp);
+    if (smoother == SMOOTH_JACOBI) jacobi_sweep(g, u, f, tmp);
+    else rbgs_sweep(g, u, f, smoother == SMOOTH_RBGS_SYM ? 1 : 0);
 }
 void orc_smooth_f32(int dim, int n, const float* k, int smoother, double omega, float* u, const float* f) {
     const Grid<float> g = make_grid<float>(dim, n, k, omega);
     std::vector<float> tmp;
-    if (smoother == SMOOTH_RBGS) rbgs_sweep(g, u, f);
-    else jacobi_sweep(g, u, f, tmp);
+    if (smoother == SMOOTH_JACOBI) jacobi_sweep(g, u, f, tmp);
+    else rbgs_sweep(g, u, f, smoother == SMOOTH_RBGS_SYM ? 1 : 0);
+}
+
+/* Coarsest-level conjugate gradients alone (n >= 3), iters steps (0: default 4(n-1)). */
+void orc_coarsest_cg_f64(int dim, int n, const double* k, int iters, double* u, const double* f) {
+    const Grid<double> g = make_grid<double>(dim, n, k, 1.0);
+    coarsest_cg(g, u, f, iters > 0 ? iters : cg_default_iters(n));
+}
+void orc_coarsest_cg_f32(int dim, int n, const float* k, int iters, float* u, const float* f) {
+    const Grid<float> g = make_grid<float>(dim, n, k, 1.0);
+    coarsest_cg(g, u, f, iters > 0 ? iters : cg_default_iters(n));
 }
 
 /* only the red (colour 0) or black (colour 1) half of an RBGS sweep */
@@ -520,36 +639,63 @@ double orc_residual_norm_f64(int dim, int n, const double* k, const double* u, c
     return residual_norm(g, u, f);
 }
 
-/* One V(nu1,nu2) cycle on the finest grid, u updated in place. */
-int orc_vcycle_f64(int dim, int n, const double* k, int smoother, double omega, int nu1, int nu2, double* u,
-                   const double* f) {
-    if ((dim != 2 && dim != 3) || !valid_edge(n)) return -1;
+/* Cycle options beyond Algorithm 1's V-cycle with an exact 3-point coarsest
+ * solve: cycle type (0 V, 1 W, 2 F), edge of the coarsest level (3 = one
+ * unknown, solved exactly; larger: conjugate gradients, cg_iters steps, 0 =
+ * default). */
+static bool valid_opts(int n, int cycle, int coarse_n) {
+    return cycle >= CYCLE_V && cycle <= CYCLE_F && valid_edge(coarse_n) && coarse_n <= n;
+}
+
+/* One multigrid cycle on the finest grid, u updated in place. */
+int orc_cycle_f64(int dim, int n, const double* k, int smoother, double omega, int nu1, int nu2, int cycle,
+                  int coarse_n, int cg_iters, double* u, const double* f) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || !valid_opts(n, cycle, coarse_n)) return -1;
     Hierarchy<double> H;
-    build(H, dim, n, k, smoother, omega, nu1, nu2);
+    build(H, dim, n, k, smoother, omega, nu1, nu2, coarse_n);
+    H.cycle = cycle;
+    H.cg_iters = cg_iters;
     vcycle(H, 0, u, f);
     return 0;
 }
 
 /* Same cycle in single precision (u, f, k in float). */
-int orc_vcycle_f32(int dim, int n, const float* k32, int smoother, double omega, int nu1, int nu2, float* u,
-                   const float* f) {
-    if ((dim != 2 && dim != 3) || !valid_edge(n)) return -1;
+int orc_cycle_f32(int dim, int n, const float* k32, int smoother, double omega, int nu1, int nu2, int cycle,
+                  int coarse_n, int cg_iters, float* u, const float* f) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || !valid_opts(n, cycle, coarse_n)) return -1;
     Hierarchy<float> H;
     std::vector<double> k64;
     if (k32) k64.assign(k32, k32 + npts(dim, n));
-    build(H, dim, n, k32 ? k64.data() : nullptr, smoother, omega, nu1, nu2);
+    build(H, dim, n, k32 ? k64.data() : nullptr, smoother, omega, nu1, nu2, coarse_n);
+    H.cycle = cycle;
+    H.cg_iters = cg_iters;
     vcycle(H, 0, u, f);
     return 0;
 }
 
+/* One V(nu1,nu2) cycle on the finest grid, u updated in place. */
+int orc_vcycle_f64(int dim, int n, const double* k, int smoother, double omega, int nu1, int nu2, double* u,
+                   const double* f) {
+    return orc_cycle_f64(dim, n, k, smoother, omega, nu1, nu2, CYCLE_V, 3, 0, u, f);
+}
+
+/* Same cycle in single precision (u, f, k in float). */
+int orc_vcycle_f32(int dim, int n, const float* k32, int smoother, double omega, int nu1, int nu2, float* u,
+                   const float* f) {
+    return orc_cycle_f32(dim, n, k32, smoother, omega, nu1, nu2, CYCLE_V, 3, 0, u, f);
+}
+
 /* Solve loop of the Layer-4 Application function: rho_0 = ||f - A u||, then
- * V-cycles until rho_k <= tol * rho_0 or max_cycles.  hist (len max_cycles+1,
+ * cycles until rho_k <= tol * rho_0 or max_cycles.  hist (len max_cycles+1,
  * may be NULL) receives rho_0..rho_k; *cycles the number of cycles done. */
-int orc_solve_f64(int dim, int n, const double* k, int smoother, double omega, int nu1, int nu2, double* u,
-                  const double* f, double tol, int max_cycles, double* hist, int* cycles) {
-    if ((dim != 2 && dim != 3) || !valid_edge(n) || max_cycles < 0) return -1;
+int orc_solve_mg_f64(int dim, int n, const double* k, int smoother, double omega, int nu1, int nu2, int cycle,
+                     int coarse_n, int cg_iters, double* u, const double* f, double tol, int max_cycles,
+                     double* hist, int* cycles) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || max_cycles < 0 || !valid_opts(n, cycle, coarse_n)) return -1;
     Hierarchy<double> H;
-    build(H, dim, n, k, smoother, omega, nu1, nu2);
+    build(H, dim, n, k, smoother, omega, nu1, nu2, coarse_n);
+    H.cycle = cycle;
+    H.cg_iters = cg_iters;
     const Grid<double> g0 = H.grid(0);
     const double rho0 = residual_norm(g0, u, f);
     if (hist) hist[0] = rho0;
@@ -565,6 +711,12 @@ int orc_solve_f64(int dim, int n, const double* k, int smoother, double omega, i
     }
     if (cycles) *cycles = it;
     return status;
+}
+
+int orc_solve_f64(int dim, int n, const double* k, int smoother, double omega, int nu1, int nu2, double* u,
+                  const double* f, double tol, int max_cycles, double* hist, int* cycles) {
+    return orc_solve_mg_f64(dim, n, k, smoother, omega, nu1, nu2, CYCLE_V, 3, 0, u, f, tol, max_cycles, hist,
+                            cycles);
 }
 
 /* One FP64 refinement pass: u += e (inner nodes), r = f - A u in FP64,
@@ -585,15 +737,18 @@ double orc_ir_update_f32(int dim, int n, const double* k64, double* u, const flo
     return residual_norm(g, u, f);
 }
 
-/* Mixed precision: single-precision V-cycles on the correction equation
+/* Mixed precision: single-precision cycles on the correction equation
  * A e = r inside FP64 iterative refinement.  Each outer step: u += e, r = f -
- * A u and ||r|| in FP64, r rounded to float, then one float V-cycle from
+ * A u and ||r|| in FP64, r rounded to float, then one float cycle from
  * e = 0.  hist[0..] holds the FP64 residual norms; stop as in orc_solve_f64. */
-int orc_solve_ir_f32(int dim, int n, const double* k64, int smoother, double omega, int nu1, int nu2, double* u,
-                     const double* f, double tol, int max_cycles, double* hist, int* cycles) {
-    if ((dim != 2 && dim != 3) || !valid_edge(n) || max_cycles < 0) return -1;
+int orc_solve_ir_mg_f32(int dim, int n, const double* k64, int smoother, double omega, int nu1, int nu2, int cycle,
+                        int coarse_n, int cg_iters, double* u, const double* f, double tol, int max_cycles,
+                        double* hist, int* cycles) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || max_cycles < 0 || !valid_opts(n, cycle, coarse_n)) return -1;
     Hierarchy<float> H;
-    build(H, dim, n, k64, smoother, omega, nu1, nu2);
+    build(H, dim, n, k64, smoother, omega, nu1, nu2, coarse_n);
+    H.cycle = cycle;
+    H.cg_iters = cg_iters;
     const size_t total = npts(dim, n);
     std::vector<float> e(total, 0.0f), r32(total, 0.0f);
     double rho0 = orc_ir_update_f32(dim, n, k64, u, e.data(), f, r32.data());
@@ -610,6 +765,12 @@ int orc_solve_ir_f32(int dim, int n, const double* k64, int smoother, double ome
     }
     if (cycles) *cycles = it;
     return status;
+}
+
+int orc_solve_ir_f32(int dim, int n, const double* k64, int smoother, double omega, int nu1, int nu2, double* u,
+                     const double* f, double tol, int max_cycles, double* hist, int* cycles) {
+    return orc_solve_ir_mg_f32(dim, n, k64, smoother, omega, nu1, nu2, CYCLE_V, 3, 0, u, f, tol, max_cycles, hist,
+                               cycles);
 }
 
 } /* extern "C" */

@@ -10,6 +10,7 @@ it has not been built (``python -m paper_1406_5369_amd.build``).
 
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import re
@@ -191,18 +192,54 @@ class Params:
                        self.precision)
 
 
+# Handles created through this module and not yet destroyed, in creation
+# order.  They are destroyed explicitly (newest first, after the device has
+# finished its work) when the interpreter exits, while the HIP runtime is
+# still fully alive, instead of being left to object finalizers that may run
+# during interpreter teardown.
+_live: dict = {}
+
+
+def _track(ctx: int) -> int:
+    _live[ctx] = True
+    return ctx
+
+
 def mg_setup(params: Params, stream=None) -> int:
     """Create a context (returns the opaque handle as an int)."""
     cp = params.to_c()
     out = C.c_void_p()
     _check(lib().mg_setup(C.byref(cp), _stream(stream), C.byref(out)), "mg_setup")
-    return out.value
+    return _track(out.value)
 
 
 def mg_destroy(ctx: int) -> None:
+    if not ctx:
+        return
+    _live.pop(ctx, None)
     lib().mg_destroy(ctx)
     for key in [k for k in _server_shapes if k[0] == ctx]:
         del _server_shapes[key]
+
+
+def shutdown() -> None:
+    """Destroy every handle still alive (newest first) after the device has
+    drained.  Registered with atexit; safe to call more than once."""
+    if not _live or _lib is None:
+        _live.clear()
+        return
+    try:
+        import torch
+
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for ctx in reversed(list(_live)):
+        mg_destroy(ctx)
+
+
+atexit.register(shutdown)
 
 
 def mg_num_levels(ctx: int) -> int:
@@ -356,9 +393,18 @@ class Solver:
             mg_destroy(self.ctx)
             self.ctx = 0
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        # Only while the interpreter runs normally; at exit the registry's
+        # shutdown() has already destroyed the context.
         try:
-            self.close()
+            if self.ctx and self.ctx in _live:
+                self.close()
         except Exception:
             pass
 
@@ -369,7 +415,7 @@ def mg_batch_setup(params_list, stream=None) -> int:
     arr = (_Params * len(params_list))(*[p.to_c() for p in params_list])
     out = C.c_void_p()
     _check(lib().mg_batch_setup(len(params_list), arr, _stream(stream), C.byref(out)), "mg_batch_setup")
-    return out.value
+    return _track(out.value)
 
 
 def mg_batch_solve(ctx: int, us, fs, tol: float = 1e-8, max_cycles: int = 50):
@@ -409,7 +455,7 @@ def mg_server_create(sp: ServerParams, stream=None) -> int:
     cp = sp.to_c()
     out = C.c_void_p()
     _check(lib().mg_server_create(C.byref(cp), _stream(stream), C.byref(out)), "mg_server_create")
-    return out.value
+    return _track(out.value)
 
 
 def mg_server_submit(ctx: int, f_host) -> int:

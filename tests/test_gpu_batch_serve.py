@@ -61,6 +61,27 @@ def test_batch_matches_alone_and_oracle(dim, edges, dev_ok):
     m.mg_destroy(ctx)
 
 
+@pytest.mark.parametrize("dim,edges", [(2, [65, 33, 129, 9, 257]), (3, [17, 33, 9, 65])])
+def test_batch_jacobi_matches_oracle(dim, edges, dev_ok):
+    """Batched weighted-Jacobi (omega 0.8) solves equal the oracle's refinement with the same smoother."""
+    import torch
+
+    m = mg()
+    fs = [inputs.uniform_rhs(dim, n, 760 + i) for i, n in enumerate(edges)]
+    ctx = m.mg_batch_setup([m.Params(dim=dim, n=n, precision=m.PREC_FP32_IR, smoother=m.SMOOTH_JACOBI)
+                            for n in edges])
+    us = [dev(np.zeros_like(f)) for f in fs]
+    st, cyc, stt = m.mg_batch_solve(ctx, us, [dev(f) for f in fs], tol=1e-8, max_cycles=60)
+    torch.cuda.synchronize()
+    m.mg_destroy(ctx)
+    assert st == 0 and all(x == 0 for x in stt)
+    for i, f in enumerate(fs):
+        u_ref, h_ref, rc = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-8, max_cycles=60,
+                                               smoother=oracle.SMOOTH_JACOBI, omega=0.8)
+        assert rc == 0 and cyc[i] == len(h_ref) - 1, i
+        assert np.array_equal(us[i].cpu().numpy(), u_ref), i
+
+
 def test_batch_rejects_mixed_solver_settings(dev_ok):
     m = mg()
     with pytest.raises(m.MGError):
@@ -166,3 +187,36 @@ def test_server_many_requests_reusing_few_slots(dev_ok):
         assert cyc == len(h_ref) - 1, rid
         assert np.array_equal(u, u_ref), rid
     m.mg_destroy(ctx)
+
+
+def test_server_mix_at_full_request_sizes(dev_ok):
+    """The served mix at its full edge range (2D up to 2049^2, 3D up to 257^3):
+    requests of every size arrive while others run, and each result equals the
+    oracle's FP32-in-FP64 solve of that request alone, bit for bit."""
+    m = mg()
+    sp = m.ServerParams(hbm_budget_bytes=16 << 30, max_slots=4, max_n2d=2049, max_n3d=257, tol=1e-8, max_cycles=40)
+    ctx = m.mg_server_create(sp)
+    reqs = [(2, 2049, 1), (3, 257, 2), (2, 257, 3), (3, 33, 4), (2, 1025, 5), (3, 65, 6), (2, 513, 7),
+            (3, 129, 8), (2, 2049, 9), (3, 257, 10)]
+    pending = list(reqs)
+    f_of, done, steps = {}, {}, 0
+    while pending or len(done) < len(reqs):
+        for _ in range(3):
+            if pending:
+                dim, n, seed = pending.pop(0)
+                f = inputs.uniform_rhs(dim, n, 1500 + seed)
+                f_of[m.mg_server_submit(ctx, f)] = f
+        m.mg_server_step(ctx)
+        for rid in m.mg_server_poll(ctx):
+            st, u, cyc, rr, lat = m.mg_server_fetch(ctx, rid, shape=f_of[rid].shape)
+            done[rid] = (st, u, cyc, rr)
+        steps += 1
+        assert steps < 2000
+    m.mg_destroy(ctx)
+    print(f"[serve] {len(done)} full-size requests served in {steps} steps; oracle solves", flush=True)
+    for rid, (st, u, cyc, rr) in done.items():
+        f = f_of[rid]
+        assert st == 0 and rr <= 1e-8, rid
+        u_ref, h_ref, rc = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-8, max_cycles=40)
+        assert rc == 0 and cyc == len(h_ref) - 1, (rid, f.shape)
+        assert np.array_equal(u, u_ref), (rid, f.shape)

@@ -6,9 +6,8 @@ the degenerate and the largest accepted grids.
   solve is compared with the oracle's (history to 1e-12 per step, field bit for
   bit).
 * 257^3 variable-coefficient problem (k in [1, 100]), same solver: same bar.
-* 512 batched 2D grids with edges 65..1025: a sample of instances (always
-  including the largest ones) is compared with the oracle bit for bit; every
-  instance must report convergence.
+* 512 batched 2D grids with edges 65..1025: every instance is compared with
+  the oracle (refinement steps, field bit for bit).
 * n = 3 (one unknown: the coarsest solve alone) and a zero right-hand side.
 * The largest grids the library accepts (2D 32769^2 and 3D 1025^3, each about
   1.07e9 nodes): the oracle's FP64 residual of the GPU answer is checked against
@@ -79,7 +78,8 @@ def test_varcoef3d_257_fp32ir_matches_oracle(dev_ok):
     assert np.array_equal(u, u_exp)
 
 
-def test_batched_512_grids_sampled_against_oracle(dev_ok):
+def test_batched_512_grids_against_oracle(dev_ok):
+    """Every one of the 512 instances: refinement steps and field bit for bit."""
     import torch
 
     m = mg()
@@ -88,18 +88,18 @@ def test_batched_512_grids_sampled_against_oracle(dev_ok):
     ctx = m.mg_batch_setup([m.Params(dim=2, n=int(n), precision=m.PREC_FP32_IR) for n in edges])
     us = [torch.zeros((int(n), int(n)), dtype=torch.float64, device="cuda") for n in edges]
     fd = [dev(f) for f in fs]
+    print("[fullsize] 512-grid batch: GPU solve", flush=True)
     st, cyc, stt = m.mg_batch_solve(ctx, us, fd, tol=1e-8, max_cycles=50)
     torch.cuda.synchronize()
-    assert st == 0 and all(x == 0 for x in stt)
-    rng = np.random.default_rng(11)
-    big = [i for i, n in enumerate(edges) if n == max(edges)][:3]
-    small = [i for i, n in enumerate(edges) if n == min(edges)][:2]
-    sample = sorted(set(big + small + list(rng.choice(512, 8, replace=False))))
-    for i in sample:
-        u_ref, h_ref, rc = oracle.solve_ir_f32(np.zeros_like(fs[i]), fs[i], tol=1e-8, max_cycles=50)
-        assert cyc[i] == len(h_ref) - 1, i
-        assert np.array_equal(us[i].cpu().numpy(), u_ref), i
     m.mg_destroy(ctx)
+    assert st == 0 and all(x == 0 for x in stt)
+    print("[fullsize] 512-grid batch: oracle solves", flush=True)
+    bad = []
+    for i in range(512):
+        u_ref, h_ref, rc = oracle.solve_ir_f32(np.zeros_like(fs[i]), fs[i], tol=1e-8, max_cycles=50)
+        if rc != 0 or cyc[i] != len(h_ref) - 1 or not np.array_equal(us[i].cpu().numpy(), u_ref):
+            bad.append((i, int(edges[i])))
+    assert not bad, f"instances differing from the oracle: {bad[:10]} ({len(bad)} in all)"
 
 
 @pytest.mark.parametrize("dim", [2, 3])

@@ -135,8 +135,6 @@ def test_smooth_with_fused_correction_bitwise(dim, n, by, zc, pd, wv, dt, smooth
     """First post-smoothing sweep with the coarse-grid correction added while
     loading: equals interpolation + correction followed by the sweep.  Odd
     z-chunks put the first plane of a chunk on both parities."""
-    if varcoef and n > 65:
-        pytest.skip("var-coef covered at the smaller sizes")
     u, f, k = case_arrays(dim, n, dt, varcoef, seed=5)
     nc = (n - 1) // 2 + 1
     ec = inputs.random_guess(dim, nc, 77).astype(dt)

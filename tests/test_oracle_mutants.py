@@ -42,12 +42,24 @@ MUTANTS = {
     "norm_no_sqrt": ("return std::sqrt(s);", "return s;"),
     "norm_abs_not_square": ("s += r * r;", "s += std::fabs(r);"),
     "norm_plain_sum": ("s += r * r;", "s += r;"),
+    "symmetric_post_red_first": ("rbgs_sweep(g, u, f, post);", "rbgs_sweep(g, u, f, 0);"),
+    "w_cycle_restarts_from_zero": ("        mgcycle(H, l + 1, uc, fc, CYCLE_W);\n        mgcycle(H, l + 1, uc, fc, CYCLE_W);",
+                                   "        mgcycle(H, l + 1, uc, fc, CYCLE_W);\n"
+                                   "        std::fill(H.u[(size_t)l + 1].begin(), H.u[(size_t)l + 1].end(), T(0));\n"
+                                   "        mgcycle(H, l + 1, uc, fc, CYCLE_W);"),
+    "f_cycle_second_call_f": ("        mgcycle(H, l + 1, uc, fc, CYCLE_V);\n    }\n    prolong_correct",
+                              "        mgcycle(H, l + 1, uc, fc, CYCLE_F);\n    }\n    prolong_correct"),
+    "cg_beta_sign": ("p[x] = r[x] + beta * p[x];", "p[x] = r[x] - beta * p[x];"),
+    "cg_alpha_inverted": ("const T alpha = (T)(rr / pq);", "const T alpha = (T)(pq / rr);"),
+    "cg_residual_not_updated": ("r[x] = r[x] - alpha * q[x];", "r[x] = r[x];"),
 }
+
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_pins_variants.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_planted_mistake(name, tmp_path):
-    """Only the pin suite runs against the mutant: the golden histories, which
+    """Only the pin suites run against the mutant: the golden histories, which
     the oracle itself wrote, take no part in catching it."""
     old, new = MUTANTS[name]
     src = open(SRC).read()
@@ -59,6 +71,6 @@ def test_pins_catch_planted_mistake(name, tmp_path):
                     str(mut), "-o", str(lib)], check=True)
     env = dict(os.environ, MG_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                          *[os.path.join(ROOT, "tests", f) for f in PIN_FILES]],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert res.returncode != 0, f"pins did not catch mutant {name}:\n{res.stdout[-2000:]}"
