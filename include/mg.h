@@ -180,6 +180,23 @@ int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, cons
                        double* u_out, float* r, double* norm_out, int by, int zchunk, int prefetch, int waves,
                        int pairs, void* stream);
 
+/* The refinement pass of mg_level_ir_update (same arguments, same kernels,
+ * same results bit for bit) for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It calls no hipMalloc / hipFree and no allocating library
+ * routine: its scratch (launch descriptor, one FP64 norm partial per
+ * workgroup, the finalized norm) is a static 1 MiB device array that each
+ * device holds from the library's first use on it until the process ends.
+ * Launch shapes with more than 131008 workgroups (norm partials) are rejected
+ * with MG_ENOMEM before anything is enqueued (the default shapes stay far
+ * below: 3D n = 1025 needs about 1.1e4).  Every call on one device uses the
+ * same array: calls that overlap on one device (other streams or host
+ * threads) race and must be serialised by the caller.  Synchronises the
+ * stream. */
+int mg_level_ir_update_noalloc(int dim, int n, const double* k, const double* u_in, const float* e,
+                               const double* f, double* u_out, float* r, double* norm_out, int by, int zchunk,
+                               int prefetch, int waves, int pairs, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Batched solves: many independent grids (sizes may differ) in one context.
  * Every instance is solved with FP32 V-cycles inside FP64 refinement; each V-cycle

@@ -91,6 +91,7 @@ def lib():
             "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
             "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, i, p]),
+            "mg_level_ir_update_noalloc": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, i, p]),
             "mg_prof_enable": (i, [p, i]),
             "mg_prof_read": (i, [p, C.POINTER(i), C.POINTER(d)]),
             "mg_prof_read_kernel": (i, [p, i, C.POINTER(i), C.POINTER(d)]),
@@ -334,17 +335,19 @@ def mg_level_coarsest(u, f, k=None, stream=None) -> None:
 
 
 def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, prefetch=0, waves=0, pairs=0,
-                       stream=None) -> float:
+                       stream=None, noalloc=False) -> float:
+    """FP64 refinement pass; noalloc selects mg_level_ir_update_noalloc (static scratch)."""
     import torch
 
     dim, n = f.dim(), f.shape[0]
     sh = f.shape
     out = C.c_double(0.0)
-    _check(lib().mg_level_ir_update(dim, n, _dptr(k, torch.float64, sh, "k"), _dptr(u_in, torch.float64, sh, "u_in"),
+    fn = lib().mg_level_ir_update_noalloc if noalloc else lib().mg_level_ir_update
+    _check(fn(dim, n, _dptr(k, torch.float64, sh, "k"), _dptr(u_in, torch.float64, sh, "u_in"),
                                     _dptr(e, torch.float32, sh, "e"), _dptr(f, torch.float64, sh, "f"),
                                     _dptr(u_out, torch.float64, sh, "u_out"), _dptr(r, torch.float32, sh, "r"),
                                     C.byref(out), by, zchunk, prefetch, waves, pairs, _stream(stream)),
-           "mg_level_ir_update")
+           "mg_level_ir_update_noalloc" if noalloc else "mg_level_ir_update")
     return out.value
 
 

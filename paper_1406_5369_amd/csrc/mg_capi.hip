@@ -1107,4 +1107,89 @@ int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, cons
     return dev_status(e2);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free refinement pass.  Its scratch (the launch descriptor, one
+// norm partial per workgroup and the finalized norm) lives in a static device
+// array of fixed size instead of hipMalloc'd buffers.  Each device holds its
+// own copy of the array; its address is looked up once per device with
+// hipGetSymbolAddress and only that address is handed to the kernels and
+// copies.  Calls on one device share the array.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(1) << 20;  // per device
+constexpr size_t kScratchNormOff = 256;            // finalized norm (one double)
+constexpr size_t kScratchPartOff = 512;            // norm partials
+constexpr int kScratchMaxParts = (int)((kScratchBytes - kScratchPartOff) / sizeof(double));
+static_assert(sizeof(mg::IRDesc) <= kScratchNormOff, "descriptor must fit before the norm");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per device).
+int scratch_ptr(unsigned char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return dev_status(e);
+    if (dev < 0 || dev >= kMaxDevices) return MG_EDEVICE;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return e != hipSuccess ? dev_status(e) : MG_EDEVICE;
+        g_scratch[dev] = (unsigned char*)p;
+    }
+    *out = g_scratch[dev];
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_level_ir_update_noalloc(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
+                               double* u_out, float* r, double* norm_out, int by, int zchunk, int prefetch,
+                               int waves, int pairs, void* stream) {
+    if (!valid_edge(dim, n) || n < 5) return MG_EINVAL;
+    if (!u_in || !e || !f || !u_out || !r || !norm_out || u_in == u_out) return MG_EINVAL;
+    TileCfg cfg = pick_cfg(dim, 8, n, 0, by, zchunk, 2);
+    if (prefetch) cfg.pd = prefetch;
+    if (waves) cfg.wv = waves;
+    cfg.xp = pairs ? 2 : 1;
+    if (cfg.xp == 2 && dim == 2 && !zchunk) cfg.zchunk = 32;
+    if (!valid_cfg(cfg, dim, 8, k != nullptr, 2)) return MG_EINVAL;
+    const int nparts = norm_tiles(dim, n, cfg);
+    if (nparts > kScratchMaxParts) return MG_ENOMEM;
+    unsigned char* base = nullptr;
+    const int rs = scratch_ptr(&base);
+    if (rs != MG_OK) return rs;
+    hipStream_t s = (hipStream_t)stream;
+    IRDesc h{};
+    h.u[0] = const_cast<double*>(u_in);
+    h.u[1] = u_out;
+    h.e = e;
+    h.f = f;
+    h.k = k;
+    h.r = r;
+    h.n = n;
+    h.c = level_c(n);
+    IRDesc* d = (IRDesc*)base;
+    double* nrm = (double*)(base + kScratchNormOff);
+    double* part = (double*)(base + kScratchPartOff);
+    // Every partial the finalize step reads is written by the pass (one per
+    // workgroup), so nothing in the array has to start at zero.
+    hipError_t err = hipMemcpyAsync(d, &h, sizeof(IRDesc), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = launch_ir_update(dim, k != nullptr, d, 1, n, 0, 0, part, nparts, cfg, s);
+    if (err == hipSuccess) err = launch_norm_finalize(part, nparts, nparts, 0, 1, nrm, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(norm_out, nrm, sizeof(double), hipMemcpyDeviceToHost, s);
+    const hipError_t e2 = hipStreamSynchronize(s);
+    if (err != hipSuccess) return dev_status(err);
+    return dev_status(e2);
+}
+
 }  // extern "C"
