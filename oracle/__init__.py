@@ -83,6 +83,16 @@ def _load():
         "orc_ir_update_f32": (_d, [_i, _i, _p, _p, _p, _p, _p]),
         "orc_solve_ir_f32": (_i, [_i, _i, _p, _i, _d, _i, _i, _p, _p, _d, _i, _p, _p]),
         "orc_solve_ir_mg_f32": (_i, [_i, _i, _p, _i, _d, _i, _i, _i, _i, _i, _p, _p, _d, _i, _p, _p]),
+        "orc_half_from_float": (None, [_p, _p, C.c_longlong]),
+        "orc_half_to_float": (None, [_p, _p, C.c_longlong]),
+        "orc_residual_f16": (None, [_i, _i, _p, _p, _p, _p]),
+        "orc_smooth_f16": (None, [_i, _i, _p, _i, _d, _p, _p]),
+        "orc_restrict_f16": (None, [_i, _i, _p, _p]),
+        "orc_prolong_correct_f16": (None, [_i, _i, _p, _p]),
+        "orc_cycle_f16": (_i, [_i, _i, _p, _i, _d, _i, _i, _i, _i, _i, _p, _p]),
+        "orc_fp16_scale": (_d, [_d]),
+        "orc_ir_update_f16": (_d, [_i, _i, _p, _p, _p, _d, _p, _d, _p, _p]),
+        "orc_solve_ir_mg_f16": (_i, [_i, _i, _p, _i, _d, _i, _i, _i, _i, _i, _p, _p, _d, _i, _p, _p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -117,8 +127,15 @@ def num_threads() -> int:
 
 
 def residual(u, f, k=None):
-    """r = f - A u on inner nodes, 0 on the boundary (FP64 or FP32 by dtype)."""
+    """r = f - A u on inner nodes, 0 on the boundary (FP64 or FP32 by dtype;
+    float16 u, f give a float32 residual computed in float, k float32)."""
     dt = u.dtype
+    if dt == np.float16:
+        _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, np.float32, "k")
+        dim, n = _dims(u)
+        r = np.zeros(u.shape, dtype=np.float32)
+        _load().orc_residual_f16(dim, n, _ptr(k), _ptr(u), _ptr(f), _ptr(r))
+        return r
     _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, dt, "k")
     dim, n = _dims(u)
     r = np.zeros_like(u)
@@ -128,12 +145,14 @@ def residual(u, f, k=None):
 
 
 def smooth(u, f, smoother=SMOOTH_RBGS, omega=1.0, k=None):
-    """One smoothing sweep; returns a new array."""
+    """One smoothing sweep; returns a new array (float16: binary16 cells,
+    float arithmetic, k float32)."""
     dt = u.dtype
-    _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, dt, "k")
+    _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, np.float32 if dt == np.float16 else dt, "k")
     dim, n = _dims(u)
     out = u.copy()
-    fn = _load().orc_smooth_f64 if dt == np.float64 else _load().orc_smooth_f32
+    fn = {np.dtype(np.float64): _load().orc_smooth_f64, np.dtype(np.float32): _load().orc_smooth_f32,
+          np.dtype(np.float16): _load().orc_smooth_f16}[dt]
     fn(dim, n, _ptr(k), smoother, omega, _ptr(out), _ptr(f))
     return out
 
@@ -147,12 +166,19 @@ def rbgs_colour(u, f, colour, omega=1.0, reverse=False, k=None):
     return out
 
 
-def restrict(r):
-    """Full-weighting restriction of a fine residual to the next coarser grid."""
+def restrict(r, out_dtype=None):
+    """Full-weighting restriction of a fine residual to the next coarser grid
+    (out_dtype float16: a float32 residual restricted in float into binary16
+    cells)."""
     dt = r.dtype
     _chk(r, dt, "r")
     dim, nf = _dims(r)
     nc = (nf - 1) // 2 + 1
+    if out_dtype is not None and np.dtype(out_dtype) == np.float16:
+        _chk(r, np.float32, "r")
+        fc = np.zeros((nc,) * dim, dtype=np.float16)
+        _load().orc_restrict_f16(dim, nf, _ptr(r), _ptr(fc))
+        return fc
     fc = np.zeros((nc,) * dim, dtype=dt)
     fn = _load().orc_restrict_f64 if dt == np.float64 else _load().orc_restrict_f32
     fn(dim, nf, _ptr(r), _ptr(fc))
@@ -167,7 +193,8 @@ def prolong_correct(u, ec):
     if ec.shape != ((nf - 1) // 2 + 1,) * dim:
         raise ValueError("coarse array has the wrong shape")
     out = u.copy()
-    fn = _load().orc_prolong_correct_f64 if dt == np.float64 else _load().orc_prolong_correct_f32
+    fn = {np.dtype(np.float64): _load().orc_prolong_correct_f64, np.dtype(np.float32): _load().orc_prolong_correct_f32,
+          np.dtype(np.float16): _load().orc_prolong_correct_f16}[dt]
     fn(dim, nf, _ptr(out), _ptr(ec))
     return out
 
@@ -207,10 +234,11 @@ def vcycle(u, f, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None, cycle=CY
     edge `coarse_n`, solved by conjugate gradients when larger than 3);
     FP64 or FP32 by dtype; returns a new array."""
     dt = u.dtype
-    _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, dt, "k")
+    _chk(u, dt, "u"), _chk(f, dt, "f"), _chk(k, np.float32 if dt == np.float16 else dt, "k")
     dim, n = _dims(u)
     out = u.copy()
-    fn = _load().orc_cycle_f64 if dt == np.float64 else _load().orc_cycle_f32
+    fn = {np.dtype(np.float64): _load().orc_cycle_f64, np.dtype(np.float32): _load().orc_cycle_f32,
+          np.dtype(np.float16): _load().orc_cycle_f16}[dt]
     rc = fn(dim, n, _ptr(k), smoother, omega, nu1, nu2, cycle, coarse_n, cg_iters, _ptr(out), _ptr(f))
     if rc != 0:
         raise ValueError(f"oracle cycle rejected its arguments (rc={rc})")
@@ -253,5 +281,57 @@ def solve_ir_f32(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0
     rc = _load().orc_solve_ir_mg_f32(dim, n, _ptr(k), smoother, omega, nu1, nu2, cycle, coarse_n, cg_iters,
                                      _ptr(u), _ptr(f), tol, max_cycles, _ptr(hist), C.addressof(cyc))
     if rc < 0:
+        raise ValueError(f"oracle solve rejected its arguments (rc={rc})")
+    return u, hist[: cyc.value + 1].copy(), rc
+
+
+def half_from_float(x):
+    """float32 array -> nearest binary16 values (ties to even), as numpy float16."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.zeros(x.shape, dtype=np.float16)
+    _load().orc_half_from_float(_ptr(x), _ptr(out), x.size)
+    return out
+
+
+def half_to_float(h):
+    h = np.ascontiguousarray(h, dtype=np.float16)
+    out = np.zeros(h.shape, dtype=np.float32)
+    _load().orc_half_to_float(_ptr(h), _ptr(out), h.size)
+    return out
+
+
+def fp16_scale(mx: float) -> float:
+    """Power of two s with 8 <= s*mx < 16, exponent within -126..127 (1 for mx zero or not finite)."""
+    return float(_load().orc_fp16_scale(float(mx)))
+
+
+def ir_update_f16(u, e16, s_prev, f, s_next, k=None):
+    """One FP64 refinement pass of the half-precision form.  e16 (float16, the
+    correction scaled by s_prev) may be None (no update).  Returns (u_new,
+    r16 = half(float(s_next) * float(r)), ||r||_2, max |r|)."""
+    _chk(u, np.float64, "u"), _chk(e16, np.float16, "e16"), _chk(f, np.float64, "f"), _chk(k, np.float64, "k")
+    dim, n = _dims(u)
+    out = u.copy()
+    r16 = np.zeros(u.shape, dtype=np.float16)
+    mx = C.c_double(0.0)
+    rho = _load().orc_ir_update_f16(dim, n, _ptr(k), _ptr(out), _ptr(e16), float(s_prev), _ptr(f), float(s_next),
+                                    _ptr(r16), C.addressof(mx))
+    return out, r16, float(rho), float(mx.value)
+
+
+def solve_ir_f16(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, k=None,
+                 cycle=CYCLE_V, coarse_n=3, cg_iters=0):
+    """Half-precision-storage cycles (float arithmetic) inside FP64 iterative
+    refinement, with a power-of-two residual scale per step.  Returns (u,
+    history, status); status -5 if the residual turns non-finite or grows
+    1e6-fold."""
+    _chk(u0, np.float64, "u0"), _chk(f, np.float64, "f"), _chk(k, np.float64, "k")
+    dim, n = _dims(u0)
+    u = u0.copy()
+    hist = np.zeros(max_cycles + 1)
+    cyc = C.c_int(0)
+    rc = _load().orc_solve_ir_mg_f16(dim, n, _ptr(k), smoother, omega, nu1, nu2, cycle, coarse_n, cg_iters,
+                                     _ptr(u), _ptr(f), tol, max_cycles, _ptr(hist), C.addressof(cyc))
+    if rc == -1:
         raise ValueError(f"oracle solve rejected its arguments (rc={rc})")
     return u, hist[: cyc.value + 1].copy(), rc

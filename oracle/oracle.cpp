@@ -51,6 +51,7 @@
  *
  * Layout: x fastest, idx = (k*n + j)*n + i (3D) or j*n + i (2D).
  */
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
@@ -66,17 +67,78 @@ namespace {
 typedef std::ptrdiff_t idx_t;
 
 /* ------------------------------------------------------------------ */
+/* Storage types.  FP64 and FP32 hierarchies compute in their storage    */
+/* type; the half-precision hierarchy stores IEEE 754 binary16 values and */
+/* computes in float (Table 1's data-type choice taken one step below    */
+/* single precision, for storage only).                                  */
+/* ------------------------------------------------------------------ */
+
+/* binary16 bits -> float (exact): 1 sign bit, 5 exponent bits (bias 15),
+ * 10 fraction bits; exponent 0 holds the subnormals fraction * 2^-24. */
+inline float half_to_float(uint16_t h) {
+    const int sign = (h >> 15) & 1, ex = (h >> 10) & 31, fr = h & 1023;
+    double a;
+    if (ex == 0) a = std::ldexp((double)fr, -24);
+    else if (ex == 31) a = fr ? NAN : INFINITY;
+    else a = std::ldexp((double)(1024 + fr), ex - 25);
+    return (float)(sign ? -a : a);
+}
+
+/* float -> nearest binary16 (ties to even), by the definition: below 2^-14
+ * the representable values are the multiples of 2^-24; in the binade
+ * [2^E, 2^(E+1)) they are the multiples of 2^(E-10); magnitudes from 65520
+ * on (half-way between the largest finite value 65504 and 2^16) become
+ * infinity.  std::nearbyint rounds to the nearest integer, ties to even, in
+ * the default rounding mode. */
+inline uint16_t float_to_half(float x) {
+    if (std::isnan(x)) return 0x7e00;
+    const uint16_t sign = std::signbit(x) ? 0x8000 : 0;
+    const double a = std::fabs((double)x);
+    if (a >= 65520.0) return (uint16_t)(sign | 0x7c00);
+    if (a < std::ldexp(1.0, -14)) return (uint16_t)(sign | (uint16_t)std::nearbyint(std::ldexp(a, 24)));
+    int e;
+    (void)std::frexp(a, &e); /* a = m 2^e, 1/2 <= m < 1: leading bit 2^(e-1) */
+    int E = e - 1;
+    double q = std::nearbyint(std::ldexp(a, 10 - E)); /* 1024 .. 2048 */
+    if (q == 2048.0) {
+        q = 1024.0;
+        ++E;
+    }
+    return (uint16_t)(sign | (uint16_t)((E + 15) << 10) | (uint16_t)(q - 1024.0));
+}
+
+/* A binary16 storage cell: stores the rounded value of what is assigned to
+ * it, reads back as float. */
+struct Half {
+    uint16_t bits;
+    Half() = default;
+    Half(float x) : bits(float_to_half(x)) {}
+    operator float() const { return half_to_float(bits); }
+};
+static_assert(sizeof(Half) == 2, "binary16 cells are two bytes");
+
+template <typename S>
+struct Arith {
+    typedef S type;
+};
+template <>
+struct Arith<Half> {
+    typedef float type;
+};
+
+/* ------------------------------------------------------------------ */
 /* Per-point operator: (A u)_p for inner node p.                        */
 /* ------------------------------------------------------------------ */
 
-template <typename T>
+template <typename S>
 struct Grid {
+    typedef typename Arith<S>::type T;
     int dim;      /* 2 or 3 */
     int n;        /* nodes per axis, boundary included */
     T c;          /* 1/h^2 in working precision */
     T wd;         /* omega*h^2/(2d): inverse diagonal times omega (Poisson) */
     T omega;      /* smoother weight */
-    const T* k;   /* nodal coefficient (variable coefficients) or nullptr */
+    const T* k;   /* nodal coefficient (variable coefficients), in the arithmetic type, or nullptr */
 };
 
 /* harmonic-mean face coefficient between nodes with values a and b */
@@ -86,8 +148,9 @@ inline T kface(T a, T b) {
 }
 
 /* Poisson: (A u)_p = c * (2d u_p - sum of neighbours), fixed summation order */
-template <typename T>
-inline T apply_poisson(const Grid<T>& g, const T* u, idx_t p) {
+template <typename S>
+inline typename Arith<S>::type apply_poisson(const Grid<S>& g, const S* u, idx_t p) {
+    typedef typename Arith<S>::type T;
     const idx_t sx = 1, sy = g.n, sz = (idx_t)g.n * g.n;
     const T uC = u[p];
     if (g.dim == 2) {
@@ -99,8 +162,9 @@ inline T apply_poisson(const Grid<T>& g, const T* u, idx_t p) {
 }
 
 /* Variable coefficients: (A u)_p = c * (dsum u_p - t); also returns dsum */
-template <typename T>
-inline T apply_varcoef(const Grid<T>& g, const T* u, idx_t p, T* dsum_out) {
+template <typename S>
+inline typename Arith<S>::type apply_varcoef(const Grid<S>& g, const S* u, idx_t p, typename Arith<S>::type* dsum_out) {
+    typedef typename Arith<S>::type T;
     const idx_t sx = 1, sy = g.n, sz = (idx_t)g.n * g.n;
     const T* k = g.k;
     const T kp = k[p];
@@ -121,8 +185,9 @@ inline T apply_varcoef(const Grid<T>& g, const T* u, idx_t p, T* dsum_out) {
 }
 
 /* residual r_p = f_p - (A u)_p */
-template <typename T>
-inline T residual_at(const Grid<T>& g, const T* u, const T* f, idx_t p) {
+template <typename S>
+inline typename Arith<S>::type residual_at(const Grid<S>& g, const S* u, const S* f, idx_t p) {
+    typedef typename Arith<S>::type T;
     if (g.k) {
         T dsum;
         const T Au = apply_varcoef(g, u, p, &dsum);
@@ -132,8 +197,9 @@ inline T residual_at(const Grid<T>& g, const T* u, const T* f, idx_t p) {
 }
 
 /* smoother update of Section 2.4: u + omega * diag^-1 * (f - A u) */
-template <typename T>
-inline T smooth_at(const Grid<T>& g, const T* u, const T* f, idx_t p) {
+template <typename S>
+inline typename Arith<S>::type smooth_at(const Grid<S>& g, const S* u, const S* f, idx_t p) {
+    typedef typename Arith<S>::type T;
     if (g.k) {
         T dsum;
         const T Au = apply_varcoef(g, u, p, &dsum);
@@ -156,8 +222,8 @@ inline idx_t at(int dim, int n, int i, int j, int k) {
 /* One red-black Gauss-Seidel sweep in place: all red nodes, then all black
  * (first = 1: all black, then all red -- the second half of a symmetric
  * red-black smoother, Table 1 "red-black variants"). */
-template <typename T>
-void rbgs_sweep(const Grid<T>& g, T* u, const T* f, int first = 0) {
+template <typename S>
+void rbgs_sweep(const Grid<S>& g, S* u, const S* f, int first = 0) {
     const int n = g.n;
     const int k0 = g.dim == 3 ? 1 : 0, k1 = g.dim == 3 ? n - 1 : 1; /* one pass of k in 2D */
     for (int half = 0; half < 2; ++half) {
@@ -174,8 +240,8 @@ void rbgs_sweep(const Grid<T>& g, T* u, const T* f, int first = 0) {
 }
 
 /* One omega-Jacobi sweep: every new value from old values only. */
-template <typename T>
-void jacobi_sweep(const Grid<T>& g, T* u, const T* f, std::vector<T>& tmp) {
+template <typename S>
+void jacobi_sweep(const Grid<S>& g, S* u, const S* f, std::vector<S>& tmp) {
     const int n = g.n;
     const size_t total = g.dim == 3 ? (size_t)n * n * n : (size_t)n * n;
     tmp.assign(u, u + total);
@@ -187,12 +253,13 @@ void jacobi_sweep(const Grid<T>& g, T* u, const T* f, std::vector<T>& tmp) {
                 const idx_t p = at(g.dim, n, i, j, k);
                 tmp[p] = smooth_at(g, u, f, p);
             }
-    std::memcpy(u, tmp.data(), total * sizeof(T));
+    std::memcpy(u, tmp.data(), total * sizeof(S));
 }
 
 /* r = f - A u on inner nodes, 0 on the boundary (Algorithm 1, residual) */
-template <typename T>
-void residual(const Grid<T>& g, const T* u, const T* f, T* r) {
+template <typename S>
+void residual(const Grid<S>& g, const S* u, const S* f, typename Arith<S>::type* r) {
+    typedef typename Arith<S>::type T;
     const int n = g.n;
     const size_t total = g.dim == 3 ? (size_t)n * n * n : (size_t)n * n;
     std::memset(r, 0, total * sizeof(T));
@@ -209,8 +276,8 @@ void residual(const Grid<T>& g, const T* u, const T* f, T* r) {
 /* Unscaled Euclidean norm of f - A u over inner nodes, summed in FP64.
  * Partial sums per outer index, then added in index order (deterministic
  * whatever the thread count). */
-template <typename T>
-double residual_norm(const Grid<T>& g, const T* u, const T* f) {
+template <typename S>
+double residual_norm(const Grid<S>& g, const S* u, const S* f) {
     const int n = g.n;
     const int k0 = g.dim == 3 ? 1 : 0, k1 = g.dim == 3 ? n - 1 : 1;
     std::vector<double> part((size_t)n, 0.0);
@@ -236,11 +303,12 @@ double residual_norm(const Grid<T>& g, const T* u, const T* f) {
 
 /* fc(I) = sum over the 3^d fine neighbours of 2I of w(delta) r(2I+delta),
  * w = prod_a 2^-|delta_a| / 2^d; coarse boundary set to 0. */
-template <typename T>
-void restrict_fw(int dim, int nf, const T* r, T* fc) {
+template <typename S>
+void restrict_fw(int dim, int nf, const typename Arith<S>::type* r, S* fc) {
+    typedef typename Arith<S>::type T;
     const int nc = (nf - 1) / 2 + 1;
     const size_t total = dim == 3 ? (size_t)nc * nc * nc : (size_t)nc * nc;
-    std::memset(fc, 0, total * sizeof(T));
+    std::memset(fc, 0, total * sizeof(S));
     const idx_t sx = 1, sy = nf, sz = (idx_t)nf * nf;
     const int K0 = dim == 3 ? 1 : 0, K1 = dim == 3 ? nc - 1 : 1;
 #pragma omp parallel for schedule(static)
@@ -270,8 +338,9 @@ void restrict_fw(int dim, int nf, const T* r, T* fc) {
 
 /* Interpolated coarse value at fine node (i,j,k): bilinear / trilinear.
  * Along an odd axis the node lies midway between coarse nodes I and I+1. */
-template <typename T>
-T interp_at(int dim, int nc, const T* e, int i, int j, int k) {
+template <typename S>
+typename Arith<S>::type interp_at(int dim, int nc, const S* e, int i, int j, int k) {
+    typedef typename Arith<S>::type T;
     const int I = i / 2, J = j / 2, K = k / 2;
     const int oi = i & 1, oj = j & 1, ok = dim == 3 ? (k & 1) : 0;
     const idx_t sx = 1, sy = nc, sz = (idx_t)nc * nc;
@@ -290,8 +359,8 @@ T interp_at(int dim, int nc, const T* e, int i, int j, int k) {
 }
 
 /* u_fine += P e_coarse on inner fine nodes */
-template <typename T>
-void prolong_correct(int dim, int nf, T* u, const T* ec) {
+template <typename S>
+void prolong_correct(int dim, int nf, S* u, const S* ec) {
     const int nc = (nf - 1) / 2 + 1;
     const int k0 = dim == 3 ? 1 : 0, k1 = dim == 3 ? nf - 1 : 1;
 #pragma omp parallel for schedule(static)
@@ -304,8 +373,9 @@ void prolong_correct(int dim, int nf, T* u, const T* ec) {
 }
 
 /* Coarsest grid n = 3: a single unknown, solved exactly: u = f / diag. */
-template <typename T>
-void coarsest_solve(const Grid<T>& g, T* u, const T* f) {
+template <typename S>
+void coarsest_solve(const Grid<S>& g, S* u, const S* f) {
+    typedef typename Arith<S>::type T;
     const idx_t p = at(g.dim, 3, 1, 1, 1);
     T diag;
     if (g.k) {
@@ -342,19 +412,21 @@ inline double level_wd(int dim, int n, double omega) {
     return (omega * (h * h)) / (2.0 * (double)dim);
 }
 
-template <typename T>
+template <typename S>
 struct Hierarchy {
+    typedef typename Arith<S>::type T;
     int dim, nlev, smoother, nu1, nu2;
     double omega;
     int cycle = CYCLE_V;   /* enum above */
     int coarse_n = 3;      /* edge of the coarsest level */
     int cg_iters = 0;      /* conjugate-gradient steps on a coarsest level with n > 3 */
     std::vector<int> n;               /* n[0] finest */
-    std::vector<std::vector<T>> u, f, r, k;
-    std::vector<T> tmp;
+    std::vector<std::vector<S>> u, f;  /* iterate and right-hand side, storage type */
+    std::vector<std::vector<T>> r, k;  /* residual and coefficient, arithmetic type */
+    std::vector<S> tmp;
 
-    Grid<T> grid(int l) const {
-        Grid<T> g;
+    Grid<S> grid(int l) const {
+        Grid<S> g;
         g.dim = dim;
         g.n = n[(size_t)l];
         g.c = (T)level_c(g.n);
@@ -368,9 +440,10 @@ struct Hierarchy {
 /* Build levels n, (n-1)/2+1, ..., 3.  Level 0 arrays u[0], f[0] are left
  * empty: the caller's arrays are used there.  k (if given) is converted to T
  * and injected to coarse levels. */
-template <typename T>
-void build(Hierarchy<T>& H, int dim, int n, const double* k64, int smoother, double omega, int nu1, int nu2,
+template <typename S>
+void build(Hierarchy<S>& H, int dim, int n, const double* k64, int smoother, double omega, int nu1, int nu2,
            int coarse_n = 3) {
+    typedef typename Arith<S>::type T;
     H.dim = dim;
     H.smoother = smoother;
     H.omega = omega;
@@ -413,9 +486,9 @@ void build(Hierarchy<T>& H, int dim, int n, const double* k64, int smoother, dou
 }
 
 /* post = 1 for the smoothing sweeps after the coarse-grid correction */
-template <typename T>
-void smooth(Hierarchy<T>& H, int l, T* u, const T* f, int post = 0) {
-    const Grid<T> g = H.grid(l);
+template <typename S>
+void smooth(Hierarchy<S>& H, int l, S* u, const S* f, int post = 0) {
+    const Grid<S> g = H.grid(l);
     if (H.smoother == SMOOTH_RBGS)
         rbgs_sweep(g, u, f, 0);
     else if (H.smoother == SMOOTH_RBGS_SYM)
@@ -425,8 +498,8 @@ void smooth(Hierarchy<T>& H, int l, T* u, const T* f, int post = 0) {
 }
 
 /* <a, b> over inner nodes, products and sum in FP64 */
-template <typename T>
-double dot_inner(int dim, int n, const T* a, const T* b) {
+template <typename S>
+double dot_inner(int dim, int n, const S* a, const S* b) {
     double s = 0.0;
     const int k0 = dim == 3 ? 1 : 0, k1 = dim == 3 ? n - 1 : 1;
     for (int k = k0; k < k1; ++k)
@@ -443,11 +516,12 @@ double dot_inner(int dim, int n, const T* a, const T* b) {
  * u = 0, a fixed number of steps (fewer only if the residual becomes exactly
  * zero).  Vectors in T; inner products in FP64, alpha and beta formed in
  * FP64 and rounded to T for the updates. */
-template <typename T>
-void coarsest_cg(const Grid<T>& g, T* u, const T* f, int iters) {
+template <typename S>
+void coarsest_cg(const Grid<S>& g, S* u, const S* f, int iters) {
+    typedef typename Arith<S>::type T;
     const int n = g.n, dim = g.dim;
     const size_t total = npts(dim, n);
-    std::vector<T> r(total, T(0)), p(total, T(0)), q(total, T(0));
+    std::vector<S> r(total, T(0)), p(total, T(0)), q(total, T(0));
     const int k0 = dim == 3 ? 1 : 0, k1 = dim == 3 ? n - 1 : 1;
     for (size_t i = 0; i < total; ++i) u[i] = T(0);
     for (int k = k0; k < k1; ++k)
@@ -499,9 +573,10 @@ inline int cg_default_iters(int n) { return 4 * (n - 1); }
  * kind V calls itself once, W twice, F an F-cycle then a V-cycle.  Each
  * call after the first continues from the coarse iterate the previous call
  * left (the zero guess precedes the first call only). */
-template <typename T>
-void mgcycle(Hierarchy<T>& H, int l, T* u, const T* f, int kind) {
-    const Grid<T> g = H.grid(l);
+template <typename S>
+void mgcycle(Hierarchy<S>& H, int l, S* u, const S* f, int kind) {
+    typedef typename Arith<S>::type T;
+    const Grid<S> g = H.grid(l);
     if (l == H.nlev - 1) {
         if (g.n == 3)
             coarsest_solve(g, u, f);
@@ -512,9 +587,9 @@ void mgcycle(Hierarchy<T>& H, int l, T* u, const T* f, int kind) {
     for (int s = 0; s < H.nu1; ++s) smooth(H, l, u, f, 0);       /* presmoothing */
     T* r = H.r[(size_t)l].data();
     residual(g, u, f, r);                                         /* residual */
-    T* fc = H.f[(size_t)l + 1].data();
+    S* fc = H.f[(size_t)l + 1].data();
     restrict_fw(H.dim, g.n, r, fc);                               /* restriction */
-    T* uc = H.u[(size_t)l + 1].data();
+    S* uc = H.u[(size_t)l + 1].data();
     std::fill(H.u[(size_t)l + 1].begin(), H.u[(size_t)l + 1].end(), T(0)); /* zero guess */
     if (kind == CYCLE_V) {
         mgcycle(H, l + 1, uc, fc, CYCLE_V);                       /* recursion */
@@ -530,14 +605,15 @@ void mgcycle(Hierarchy<T>& H, int l, T* u, const T* f, int kind) {
 }
 
 /* Algorithm 1 on level l with solution u and right-hand side f */
-template <typename T>
-void vcycle(Hierarchy<T>& H, int l, T* u, const T* f) {
+template <typename S>
+void vcycle(Hierarchy<S>& H, int l, S* u, const S* f) {
     mgcycle(H, l, u, f, H.cycle);
 }
 
-template <typename T>
-Grid<T> make_grid(int dim, int n, const T* kf, double omega) {
-    Grid<T> g;
+template <typename S>
+Grid<S> make_grid(int dim, int n, const typename Arith<S>::type* kf, double omega) {
+    typedef typename Arith<S>::type T;
+    Grid<S> g;
     g.dim = dim;
     g.n = n;
     g.c = (T)level_c(n);
@@ -771,6 +847,131 @@ int orc_solve_ir_f32(int dim, int n, const double* k64, int smoother, double ome
                      const double* f, double tol, int max_cycles, double* hist, int* cycles) {
     return orc_solve_ir_mg_f32(dim, n, k64, smoother, omega, nu1, nu2, CYCLE_V, 3, 0, u, f, tol, max_cycles, hist,
                                cycles);
+}
+
+/* ------------------------------------------------------------------ */
+/* Half-precision storage form of the refinement (FP16 cells, float     */
+/* arithmetic, FP64 outer residual).  Arrays of binary16 cells are passed */
+/* as their 16-bit patterns.                                             */
+/* ------------------------------------------------------------------ */
+
+void orc_half_from_float(const float* x, uint16_t* out, long long count) {
+    for (long long i = 0; i < count; ++i) out[i] = float_to_half(x[i]);
+}
+void orc_half_to_float(const uint16_t* h, float* out, long long count) {
+    for (long long i = 0; i < count; ++i) out[i] = half_to_float(h[i]);
+}
+
+/* r = f - A u (float) from binary16 u, f; k32 the float coefficient or NULL */
+void orc_residual_f16(int dim, int n, const float* k32, const uint16_t* u, const uint16_t* f, float* r) {
+    const Grid<Half> g = make_grid<Half>(dim, n, k32, 1.0);
+    residual(g, (const Half*)u, (const Half*)f, r);
+}
+/* one smoothing sweep in place on binary16 u (smoother as orc_smooth_f64) */
+void orc_smooth_f16(int dim, int n, const float* k32, int smoother, double omega, uint16_t* u, const uint16_t* f) {
+    const Grid<Half> g = make_grid<Half>(dim, n, k32, omega);
+    std::vector<Half> tmp;
+    if (smoother == SMOOTH_JACOBI) jacobi_sweep(g, (Half*)u, (const Half*)f, tmp);
+    else rbgs_sweep(g, (Half*)u, (const Half*)f, smoother == SMOOTH_RBGS_SYM ? 1 : 0);
+}
+/* full weighting of a float residual into binary16 coarse cells */
+void orc_restrict_f16(int dim, int nf, const float* r, uint16_t* fc) { restrict_fw(dim, nf, r, (Half*)fc); }
+void orc_prolong_correct_f16(int dim, int nf, uint16_t* u, const uint16_t* ec) {
+    prolong_correct(dim, nf, (Half*)u, (const Half*)ec);
+}
+int orc_cycle_f16(int dim, int n, const float* k32, int smoother, double omega, int nu1, int nu2, int cycle,
+                  int coarse_n, int cg_iters, uint16_t* u, const uint16_t* f) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || !valid_opts(n, cycle, coarse_n)) return -1;
+    Hierarchy<Half> H;
+    std::vector<double> k64;
+    if (k32) k64.assign(k32, k32 + npts(dim, n));
+    build(H, dim, n, k32 ? k64.data() : nullptr, smoother, omega, nu1, nu2, coarse_n);
+    H.cycle = cycle;
+    H.cg_iters = cg_iters;
+    vcycle(H, 0, (Half*)u, (const Half*)f);
+    return 0;
+}
+
+/* Scale of a residual whose largest magnitude is mx: the power of two s with
+ * 8 <= s mx < 16, so that the scaled residual and the correction it induces
+ * stay far inside binary16's range (largest finite value 65504, smallest
+ * normal 2^-14) whatever the size of the residual; the exponent is kept in
+ * [-126, 127] so that s is a normal float (the relation holds for
+ * 2^-123 <= mx < 2^130); 1 for a zero or non-finite mx. */
+double orc_fp16_scale(double mx) {
+    if (!(mx > 0.0) || !std::isfinite(mx)) return 1.0;
+    int e;
+    (void)std::frexp(mx, &e); /* mx = m 2^e, 1/2 <= m < 1 */
+    return std::ldexp(1.0, std::min(127, std::max(-126, 4 - e)));
+}
+
+/* One FP64 refinement pass of the half-precision form: when e16 is given,
+ * u += e16 / s_prev on inner nodes (e16 holds the correction scaled by
+ * s_prev); r = f - A u in FP64; r16 = half(float(s_next) * float(r)) (the
+ * residual rounded to float as in the single-precision form, then scaled by
+ * a power of two and stored in binary16); *mx = max |r|; returns ||r||_2. */
+double orc_ir_update_f16(int dim, int n, const double* k64, double* u, const uint16_t* e16, double s_prev,
+                         const double* f, double s_next, uint16_t* r16, double* mx) {
+    const Grid<double> g = make_grid<double>(dim, n, k64, 1.0);
+    const size_t total = npts(dim, n);
+    const int k0 = dim == 3 ? 1 : 0, k1 = dim == 3 ? n - 1 : 1;
+    if (e16) {
+        const double inv = 1.0 / s_prev;
+        for (int k = k0; k < k1; ++k)
+            for (int j = 1; j < n - 1; ++j)
+                for (int i = 1; i < n - 1; ++i) {
+                    const idx_t p = at(dim, n, i, j, k);
+                    u[p] = u[p] + (double)half_to_float(e16[p]) * inv;
+                }
+    }
+    std::vector<double> r(total);
+    residual(g, u, f, r.data());
+    const float s32 = (float)s_next;
+    double m = 0.0;
+    for (size_t p = 0; p < total; ++p) {
+        r16[p] = float_to_half(s32 * (float)r[p]);
+        m = std::max(m, std::fabs(r[p]));
+    }
+    *mx = m;
+    return residual_norm(g, u, f);
+}
+
+/* Half-precision cycles inside FP64 iterative refinement.  The right-hand
+ * side of every cycle is the FP64 residual scaled by orc_fp16_scale of the
+ * largest residual magnitude of the previous pass (of the same pass for the
+ * first cycle, which is measured once beforehand); the correction is
+ * unscaled when it is added.  hist as in orc_solve_ir_mg_f32. */
+int orc_solve_ir_mg_f16(int dim, int n, const double* k64, int smoother, double omega, int nu1, int nu2, int cycle,
+                        int coarse_n, int cg_iters, double* u, const double* f, double tol, int max_cycles,
+                        double* hist, int* cycles) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || max_cycles < 0 || !valid_opts(n, cycle, coarse_n)) return -1;
+    Hierarchy<Half> H;
+    build(H, dim, n, k64, smoother, omega, nu1, nu2, coarse_n);
+    H.cycle = cycle;
+    H.cg_iters = cg_iters;
+    const size_t total = npts(dim, n);
+    std::vector<Half> e(total, Half(0.0f)), r16(total, Half(0.0f));
+    double mx = 0.0;
+    (void)orc_ir_update_f16(dim, n, k64, u, nullptr, 1.0, f, 1.0, (uint16_t*)r16.data(), &mx);
+    double s = orc_fp16_scale(mx);
+    const double rho0 = orc_ir_update_f16(dim, n, k64, u, nullptr, 1.0, f, s, (uint16_t*)r16.data(), &mx);
+    if (hist) hist[0] = rho0;
+    int it = 0;
+    int status = rho0 == 0.0 ? 0 : 1;
+    while (status == 1 && it < max_cycles) {
+        std::fill(e.begin(), e.end(), Half(0.0f));
+        vcycle(H, 0, e.data(), r16.data());
+        ++it;
+        const double s_next = orc_fp16_scale(mx);
+        const double rho = orc_ir_update_f16(dim, n, k64, u, (const uint16_t*)e.data(), s, f, s_next,
+                                             (uint16_t*)r16.data(), &mx);
+        s = s_next;
+        if (hist) hist[it] = rho;
+        if (rho <= tol * rho0) status = 0;
+        else if (!(rho == rho) || rho > 1e6 * rho0) status = -5;
+    }
+    if (cycles) *cycles = it;
+    return status;
 }
 
 } /* extern "C" */

@@ -52,9 +52,16 @@ MUTANTS = {
     "cg_beta_sign": ("p[x] = r[x] + beta * p[x];", "p[x] = r[x] - beta * p[x];"),
     "cg_alpha_inverted": ("const T alpha = (T)(rr / pq);", "const T alpha = (T)(pq / rr);"),
     "cg_residual_not_updated": ("r[x] = r[x] - alpha * q[x];", "r[x] = r[x];"),
+    "half_rounds_toward_zero": ("double q = std::nearbyint(std::ldexp(a, 10 - E));",
+                                "double q = std::trunc(std::ldexp(a, 10 - E));"),
+    "half_subnormal_quantum": ("(uint16_t)std::nearbyint(std::ldexp(a, 24))", "(uint16_t)std::nearbyint(std::ldexp(a, 23))"),
+    "fp16_scale_off_by_one": ("std::max(-126, 4 - e)", "std::max(-126, 5 - e)"),
+    "fp16_correction_not_unscaled": ("u[p] = u[p] + (double)half_to_float(e16[p]) * inv;",
+                                     "u[p] = u[p] + (double)half_to_float(e16[p]);"),
+    "fp16_residual_not_scaled": ("r16[p] = float_to_half(s32 * (float)r[p]);", "r16[p] = float_to_half((float)r[p]);"),
 }
 
-PIN_FILES = ["test_oracle_pins.py", "test_oracle_pins_variants.py"]
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_pins_variants.py", "test_oracle_pins_fp16.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
