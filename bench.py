@@ -48,6 +48,8 @@ WORKLOADS = {
     # name: dim, n, precision, rhs, tol
     "poisson3d_513_fp32ir": dict(dim=3, n=513, precision=1, rhs=("uniform", 0), tol=1e-8),
     "poisson3d_513_fp64": dict(dim=3, n=513, precision=0, rhs=("uniform", 0), tol=1e-8),
+    # the same problem with binary16 cycle fields (float arithmetic) in FP64 refinement
+    "poisson3d_513_fp16ir": dict(dim=3, n=513, precision=2, rhs=("uniform", 0), tol=1e-8),
     "poisson2d_129_sine_fp64": dict(dim=2, n=129, precision=0, rhs=("sine",), tol=0.0, cycles=10),
     "poisson3d_257_fp32ir": dict(dim=3, n=257, precision=1, rhs=("uniform", 0), tol=1e-8),
     "poisson2d_4097_fp32ir": dict(dim=2, n=4097, precision=1, rhs=("uniform", 0), tol=1e-8),
@@ -124,6 +126,17 @@ def cpu_baseline(w, gpu_steps: int, budget_s: float, min_steps: int = 3):
             if enough():
                 break
         sample = "FP64 refinement pass + FP32 V(2,2) cycle"
+    elif w["precision"] == 2:
+        e16, s_e, mx = None, 1.0, 0.0
+        while True:
+            ts = time.perf_counter()
+            s_r = oracle.fp16_scale(mx)
+            u, r16, _, mx = oracle.ir_update_f16(u, e16, s_e, f, s_r)
+            e16, s_e = oracle.vcycle(np.zeros(f.shape, np.float16), r16), s_r
+            t_steps.append(time.perf_counter() - ts)
+            if enough():
+                break
+        sample = "FP64 refinement pass + binary16-storage V(2,2) cycle"
     else:
         while True:
             ts = time.perf_counter()
@@ -426,6 +439,7 @@ def main(argv=None) -> int:
                     choices=sorted(WORKLOADS) + ["batched_2d", "serving_mix"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 context solve")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the binary16-cycle solve of the same problem")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the baseline")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -559,9 +573,11 @@ def main(argv=None) -> int:
     # refinement pass (reads u, f, e, writes u, r: 32 B per inner node, +8 with
     # k) or, in FP64 solves, the norm pass (reads u, f: 16 B, +8 with k).  The
     # one with the larger total time is reported as the dominant kernel.
-    word = 4 if w["precision"] == 1 else 8
+    word = {0: 8, 1: 4, 2: 2}[w["precision"]]
     var = kd is not None
-    ir = w["precision"] == 1
+    ir = w["precision"] in (1, 2)
+    # refinement pass: FP64 u and f read, e read (float or binary16), FP64 u and r (float / binary16) written
+    pass_bytes = (8 + 8 + 8 + 2 * word) if ir else 16
 
     def roof(kernel, blocks, note, n_launch, total_ms, bytes_per_launch, tr):
         avg_ms = total_ms / max(n_launch, 1)
@@ -582,10 +598,11 @@ def main(argv=None) -> int:
                       "variants excluded)", launches, sweep_ms, (4 if var else 3) * word * dof,
                       traffic_record(args.workload, (by, zchunk, pd, wv)))
     pby, pzc, ppd, pwv, _, ppr = mg.mg_tile_config(solver.ctx, 0, 2, with_order=True)
-    pass_roof = roof(pass_kernel(dim, pby, ppd, var, ir, pwv, ppr), pass_blocks(dim, n, pby, pzc, ppr),
-                     "finest-level FP64 refinement pass (u += e, r = f - A u, r to FP32, norm partials)" if ir
+    pass_roof = roof(pass_kernel(dim, pby, ppd, var, ir, pwv, ppr, word=word), pass_blocks(dim, n, pby, pzc, ppr),
+                     ("finest-level FP64 refinement pass (u += e, r = f - A u, r to "
+                      + ("FP32" if word == 4 else "scaled binary16") + ", norm partials)") if ir
                      else "finest-level FP64 residual-norm pass", pass_launches, pass_ms,
-                     ((32 if ir else 16) + (8 if var else 0)) * dof,
+                     (pass_bytes + (8 if var else 0)) * dof,
                      traffic_record(args.workload, (pby, pzc, ppd, pwv) + (("p",) if ppr else ()),
                                     key="pass_configs"))
     if pass_roof["total_ms"] > sweep_roof["total_ms"]:
@@ -621,6 +638,48 @@ def main(argv=None) -> int:
                                "cycles": cyc64, "status": st64}
         extra["mixed_over_fp64_speedup"] = value / extra["fp64_solve"]["dof_per_s"]
         log(f"[bench] FP64 solve: {(tb - ta) * 1e3 / reps:.3f} ms, {cyc64} cycles")
+    if not args.no_fp16 and w["precision"] == 1 and kd is None:
+        # the binary16 form of the same solve: cycle fields stored as IEEE
+        # binary16, float arithmetic, FP64 refinement; its finest sweep and
+        # refinement pass timed by the library's event brackets
+        u32 = us[0]
+        u32.zero_()
+        solver.solve(u32, f, tol=tol, max_cycles=max_cycles)
+        s16 = mg.Solver(mg.Params(dim=dim, n=n, precision=mg.PREC_FP16_IR))
+        u = us[1 % len(us)]
+        u.zero_()
+        s16.solve(u, f, tol=tol, max_cycles=max_cycles)  # warm
+        reps = 3
+        mg.mg_prof_enable(s16.ctx, True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(reps):
+            u.zero_()
+            st16, cyc16, h16 = s16.solve(u, f, tol=tol, max_cycles=max_cycles)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        n16s, ms16s = mg.mg_prof_read(s16.ctx, 0)
+        n16p, ms16p = mg.mg_prof_read(s16.ctx, 1)
+        mg.mg_prof_enable(s16.ctx, False)
+        s16_tiles = {fam: mg.mg_tile_config(s16.ctx, 0, i, with_order=True) for i, fam in
+                     enumerate(["smooth", "restrict", "norm_or_refinement", "smooth_zero_guess",
+                                "smooth_fused_correction"])}
+        s16.close()
+        rel = float(torch.linalg.vector_norm(u - u32) / torch.linalg.vector_norm(u32))
+        sw_us = ms16s / max(n16s, 1) * 1e3
+        ps_us = ms16p / max(n16p, 1) * 1e3
+        extra["fp16_solve"] = {
+            "dof_per_s": dof * reps / (tb - ta), "ms_per_solve": (tb - ta) * 1e3 / reps, "cycles": cyc16,
+            "status": st16, "final_rel_residual": h16[-1] / h16[0],
+            "rel_diff_vs_fp32ir_solution": rel,
+            "finest_sweep": {"avg_launch_us": sw_us, "launches": n16s,
+                             "achieved_gbps": 3 * 2 * dof / (sw_us * 1e-6) / 1e9 if n16s else None},
+            "finest_refinement_pass": {"avg_launch_us": ps_us, "launches": n16p,
+                                       "achieved_gbps": 28 * dof / (ps_us * 1e-6) / 1e9 if n16p else None},
+            "fine_tiles": s16_tiles}
+        extra["fp16_over_fp32ir_speedup"] = extra["fp16_solve"]["dof_per_s"] / value
+        log(f"[bench] binary16 solve: {(tb - ta) * 1e3 / reps:.3f} ms, {cyc16} steps, "
+            f"|u16 - u32| / |u32| = {rel:.2e}")
     solver.close()
     del us, f, kd
     torch.cuda.synchronize()
@@ -664,7 +723,7 @@ def main(argv=None) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if w["precision"] == 1 else "f64",
+        "dtype": {0: "f64", 1: "f32+f64", 2: "f16+f32+f64"}[w["precision"]],
         "data": "synthetic",
         "config": {
             "workload": args.workload,
@@ -673,7 +732,9 @@ def main(argv=None) -> int:
             "dof": dof,
             "tol": tol,
             "solver": "V(2,2) RBGS, full weighting, linear interpolation, exact 3-point coarsest solve"
-                      + (", FP32 cycles in FP64 iterative refinement" if w["precision"] == 1 else ", FP64"),
+                      + {0: ", FP64", 1: ", FP32 cycles in FP64 iterative refinement",
+                         2: ", binary16-storage cycles (FP32 arithmetic) in FP64 iterative refinement"}[
+                          w["precision"]],
             "parallelism": "single GPU",
         },
         "roofline": roofline,

@@ -60,8 +60,15 @@ enum mg_smoother {
     MG_SMOOTH_WJACOBI = 1  /* weighted Jacobi, Section 2.3; omega 0.8 in Table 2 */
 };
 enum mg_precision {
-    MG_PREC_FP64 = 0,    /* every step in FP64 */
-    MG_PREC_FP32_IR = 1  /* FP32 V-cycles on the correction equation inside FP64 iterative refinement */
+    MG_PREC_FP64 = 0,     /* every step in FP64 */
+    MG_PREC_FP32_IR = 1,  /* FP32 V-cycles on the correction equation inside FP64 iterative refinement */
+    MG_PREC_FP16_IR = 2   /* the same with every V-cycle field stored as IEEE binary16 and computed in
+                             FP32 (Table 1's data-type choice below single precision): each refinement
+                             step hands the cycle its FP64 residual scaled by a power of two s, chosen
+                             so that 8 <= s * max|r| < 16 with max|r| taken from the previous step's
+                             residual (the first step measures its own; s is kept within 2^-126 ..
+                             2^127), and adds the correction divided by s.  MG_OP_LAPLACE only (MG_ENOTSUP otherwise).  An overflow
+                             of binary16 shows as MG_EDIVERGED. */
 };
 
 typedef struct mg_params {
@@ -167,6 +174,11 @@ int mg_level_prolong_correct(int dim, int n, int dtype, void* u, const void* ec,
 /* Coarsest grid (n = 3): u = f / diag at the single inner node. */
 int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f, void* stream);
 
+/* dtype 2 in the four calls above: binary16 arrays (u, f, the coarse arrays),
+ * arithmetic in FP32, each value the method stores rounded to binary16 (the
+ * fields of MG_PREC_FP16_IR); Laplacian only (k must be NULL, else
+ * MG_ENOTSUP). */
+
 /* FP64 refinement pass: u_out = u_in + e on inner nodes, r = (float)(f - A u_out)
  * on inner nodes (FP64 operator, FP64 k or NULL), *norm_out (HOST) = ||f - A u_out||_2.
  * e and r are FP32 arrays; u_out's and r's boundaries are not written.  'by',
@@ -179,6 +191,19 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
 int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, const float* e, const double* f,
                        double* u_out, float* r, double* norm_out, int by, int zchunk, int prefetch, int waves,
                        int pairs, void* stream);
+
+/* Refinement pass of MG_PREC_FP16_IR (Laplacian): when e16 (binary16, the
+ * correction scaled by e_scale, a power of two) is not NULL, u_out = u_in +
+ * e16 / e_scale on inner nodes, else u_out is not written and the pass reads
+ * u_in; r = f - A u in FP64; r16 (binary16) = half(float(s) * float(r)) on
+ * inner nodes, s the power of two with 8 <= s * prev_max < 16 and exponent
+ * within -126 .. 127 (1 if prev_max is 0 or not finite); *norm_out = ||r||_2
+ * and *max_out = max |r| (HOST).
+ * Two nodes per lane: 3D tiles by x waves of 8x4 / 16x4 / 16x8 / 32x8, 2D
+ * 'zchunk' rows per wavefront (0 = 32).  Synchronises the stream. */
+int mg_level_ir_update_f16(int dim, int n, const double* u_in, const void* e16, double e_scale, double prev_max,
+                           const double* f, double* u_out, void* r16, double* norm_out, double* max_out, int by,
+                           int zchunk, int prefetch, int waves, void* stream);
 
 /* The refinement pass of mg_level_ir_update (same arguments, same kernels,
  * same results bit for bit) for callers that cannot allocate device memory:

@@ -26,7 +26,7 @@ MG_OK, MG_ENOTCONV, MG_EINVAL, MG_ENOTSUP, MG_ENOMEM, MG_EDEVICE, MG_EDIVERGED, 
 OP_LAPLACE, OP_VARCOEF_NODAL = 0, 2
 BC_DIRICHLET_ZERO = 0
 SMOOTH_RBGS, SMOOTH_JACOBI = 0, 1
-PREC_FP64, PREC_FP32_IR = 0, 1
+PREC_FP64, PREC_FP32_IR, PREC_FP16_IR = 0, 1, 2
 
 
 class MGError(RuntimeError):
@@ -92,6 +92,7 @@ def lib():
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
             "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, i, p]),
             "mg_level_ir_update_noalloc": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, i, p]),
+            "mg_level_ir_update_f16": (i, [i, i, p, p, d, d, p, p, p, C.POINTER(d), C.POINTER(d), i, i, i, i, p]),
             "mg_prof_enable": (i, [p, i]),
             "mg_prof_read": (i, [p, C.POINTER(i), C.POINTER(d)]),
             "mg_prof_read_kernel": (i, [p, i, C.POINTER(i), C.POINTER(d)]),
@@ -293,7 +294,9 @@ def _dtype_code(t):
         return 0
     if t.dtype == torch.float32:
         return 1
-    raise TypeError("arrays must be float64 or float32")
+    if t.dtype == torch.float16:
+        return 2
+    raise TypeError("arrays must be float64, float32 or float16")
 
 
 def mg_level_smooth(u_in, f, u_out, smoother=SMOOTH_RBGS, omega=0.0, k=None, ec=None, zero_guess=False, by=0,
@@ -349,6 +352,22 @@ def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, prefetch=0,
                                     C.byref(out), by, zchunk, prefetch, waves, pairs, _stream(stream)),
            "mg_level_ir_update_noalloc" if noalloc else "mg_level_ir_update")
     return out.value
+
+
+def mg_level_ir_update_f16(u_in, e16, e_scale, prev_max, f, u_out, r16, by=0, zchunk=0, prefetch=0, waves=0,
+                           stream=None):
+    """Refinement pass of the binary16 form; e16 None: no update.  Returns (||r||, max |r|)."""
+    import torch
+
+    dim, n = f.dim(), f.shape[0]
+    sh = f.shape
+    nrm, mx = C.c_double(0.0), C.c_double(0.0)
+    _check(lib().mg_level_ir_update_f16(dim, n, _dptr(u_in, torch.float64, sh, "u_in"),
+                                        _dptr(e16, torch.float16, sh, "e16"), float(e_scale), float(prev_max),
+                                        _dptr(f, torch.float64, sh, "f"), _dptr(u_out, torch.float64, sh, "u_out"),
+                                        _dptr(r16, torch.float16, sh, "r16"), C.byref(nrm), C.byref(mx), by, zchunk,
+                                        prefetch, waves, _stream(stream)), "mg_level_ir_update_f16")
+    return nrm.value, mx.value
 
 
 def mg_prof_enable(ctx: int, on: bool = True) -> None:

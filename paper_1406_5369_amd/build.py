@@ -22,6 +22,7 @@ LIB = os.path.join(HERE, "libmg.so")
 SOURCES = [
     "mg_smooth3d_f64.hip",
     "mg_smooth3d_f32.hip",
+    "mg_smooth3d_f16.hip",
     "mg_resid.hip",
     "mg_transfer.hip",
     "mg_smooth2d.hip",

@@ -50,6 +50,12 @@ void ffree(void* p) {
     if (p) (void)hipFree(p);
 }
 
+// Refinement forms (FP32 or binary16 cycles inside FP64 refinement).
+bool is_ir(const mg_params& p) { return p.precision == MG_PREC_FP32_IR || p.precision == MG_PREC_FP16_IR; }
+bool is_h16(const mg_params& p) { return p.precision == MG_PREC_FP16_IR; }
+// word size of the cycle fields of a refinement form
+int ir_elem(const mg_params& p) { return is_h16(p) ? 2 : 4; }
+
 // Build a hierarchy of 'elem'-byte values.  Level 0 u/f are left null when
 // caller-owned (own0 = false).  k0: device nodal coefficient of level 0 in the
 // same precision (or null).
@@ -168,7 +174,9 @@ int validate(const mg_params* p) {
     if (p->op == MG_OP_VARCOEF_NODAL && !p->k) return MG_EINVAL;
     if (p->smoother != MG_SMOOTH_RBGS && p->smoother != MG_SMOOTH_WJACOBI) return MG_EINVAL;
     if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 > 16 || p->nu2 > 16) return MG_EINVAL;
-    if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_FP32_IR) return MG_ENOTSUP;
+    if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_FP32_IR && p->precision != MG_PREC_FP16_IR)
+        return MG_ENOTSUP;
+    if (p->precision == MG_PREC_FP16_IR && p->op != MG_OP_LAPLACE) return MG_ENOTSUP;
     if (!(p->omega == p->omega) || p->omega > 2.0) return MG_EINVAL;
     return MG_OK;
 }
@@ -185,6 +193,8 @@ void destroy(mg_ctx* c) {
     free_levels(c->L64);
     free_levels(c->L32);
     ffree(c->d_ir);
+    ffree(c->d_scl);
+    ffree(c->d_pmax);
     ffree(c->d_top);
     ffree(c->u64_scratch);
     ffree(c->k64);
@@ -252,11 +262,26 @@ hipError_t enqueue_norm(mg_ctx* c, hipStream_t s, int step = 0) {
 hipError_t enqueue_ir(mg_ctx* c, int sel, int flags, hipStream_t s, int step = 0) {
     const int nparts = norm_tiles(c->p.dim, c->p.n, c->top.norm);
     const bool timed = prof_begin(c, step, s);
-    hipError_t e = launch_ir_update(c->p.dim, c->prob.var, c->d_ir, 1, c->p.n, sel, flags, c->d_partial, c->pstride,
-                                    c->top.norm, s);
+    const bool h16 = is_h16(c->p);
+    hipError_t e = h16 ? launch_ir_update_f16(c->p.dim, c->d_ir, 1, c->p.n, sel, flags, c->d_partial, c->pstride,
+                                              c->top.norm, s)
+                       : launch_ir_update(c->p.dim, c->prob.var, c->d_ir, 1, c->p.n, sel, flags, c->d_partial,
+                                          c->pstride, c->top.norm, s);
     if (timed) prof_end(c, step, 1, s);
     if (e != hipSuccess) return e;
+    if (h16) return launch_norm_finalize_f16(c->d_partial, c->d_pmax, nparts, c->d_norm, c->d_scl, ctl_done(c), s);
     return launch_norm_finalize(c->d_partial, c->pstride, nparts, 0, 1, c->d_norm, s);
+}
+
+// Residual of the bound (u, f) handed to the refinement's first cycle, with
+// rho_0 in d_norm.  The binary16 form first measures the residual's largest
+// magnitude, then writes the residual with the scale that magnitude gives.
+hipError_t enqueue_ir_start(mg_ctx* c, hipStream_t s) {
+    if (is_h16(c->p)) {
+        hipError_t e = enqueue_ir(c, 0, IR_NO_UPDATE, s);
+        if (e != hipSuccess) return e;
+    }
+    return enqueue_ir(c, 0, IR_NO_UPDATE, s);
 }
 
 // K solve steps (cycle + residual norm + stop test), IR steps alternate the
@@ -278,7 +303,8 @@ hipError_t enqueue_steps(mg_ctx* c, int K, double tol, int max_cycles, hipStream
             if (e != hipSuccess) return e;
             e = enqueue_norm(c, s, step);
         } else {
-            e = vcycle<float>(c->prob, c->G32, true, c->tl32, s, pev, pn, pcap, &c->tail32);
+            e = is_h16(c->p) ? vcycle<half_t>(c->prob, c->G32, true, c->tl32, s, pev, pn, pcap, &c->tail32)
+                             : vcycle<float>(c->prob, c->G32, true, c->tl32, s, pev, pn, pcap, &c->tail32);
             for (int j = n0; prof && j < c->prof_n; j += 2) c->prof_step.push_back(step), c->prof_kind.push_back(0);
             if (e != hipSuccess) return e;
             e = enqueue_ir(c, (par0 + i) & 1, 0, s, step);
@@ -309,7 +335,7 @@ int ensure_hist(mg_ctx* c, int cap) {
 
 int run_chunk(mg_ctx* c, int K, double tol, int max_cycles, int step0) {
     const bool use_graph = !c->prof_on && c->use_graphs;
-    const int par0 = c->p.precision == MG_PREC_FP32_IR ? (step0 & 1) : 0;
+    const int par0 = is_ir(c->p) ? (step0 & 1) : 0;
     if (!use_graph) {
         CK(enqueue_steps(c, K, tol, max_cycles, c->stream, c->prof_on, step0, par0));
         return MG_OK;
@@ -516,8 +542,9 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
             TuneKey ks{dim, L.elem, n, 0, sm, var ? 1 : 0, 10 + v, 0};
             if (!tune_lookup(ks, &cfg)) {
                 auto run = [&](TileCfg t) {
-                    return L.elem == 8 ? launch_smooth<double>(dim, sm, var, d, 1, n, 0, fl, t, s)
-                                       : launch_smooth<float>(dim, sm, var, d, 1, n, 0, fl, t, s);
+                    return L.elem == 8   ? launch_smooth<double>(dim, sm, var, d, 1, n, 0, fl, t, s)
+                           : L.elem == 4 ? launch_smooth<float>(dim, sm, var, d, 1, n, 0, fl, t, s)
+                                         : launch_smooth<half_t>(dim, sm, var, d, 1, n, 0, fl, t, s);
                 };
                 cfg = pick_fastest(tune_candidates(dim, n - 2, true, 0, L.elem, var), *vcfg[v], run, s);
                 cfg = pick_order(cfg, run, s);
@@ -531,8 +558,9 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
             for (TileCfg t : tune_candidates(dim, (n - 1) / 2 - 1, false, 1, L.elem, var))
                 if (t.by >= 8) cands.push_back(t);
             cfg = pick_fastest(cands, tl[(size_t)l].restr, [&](TileCfg t) {
-                return L.elem == 8 ? launch_restrict<double>(dim, var, d, 1, n, 0, t, s)
-                                   : launch_restrict<float>(dim, var, d, 1, n, 0, t, s);
+                return L.elem == 8   ? launch_restrict<double>(dim, var, d, 1, n, 0, t, s)
+                       : L.elem == 4 ? launch_restrict<float>(dim, var, d, 1, n, 0, t, s)
+                                     : launch_restrict<half_t>(dim, var, d, 1, n, 0, t, s);
             }, s);
             tune_store(kr, cfg);
         }
@@ -603,13 +631,17 @@ hipError_t autotune(mg_ctx* c) {
     // finest-level FP64 norm (FP64 solves) or refinement pass (mixed precision)
     if (e == hipSuccess && N >= kTuneMinPoints) {
         const bool var = c->prob.var;
-        const int mode = c->p.precision == MG_PREC_FP64 ? 0 : 1;
+        const int mode = c->p.precision == MG_PREC_FP64 ? 0 : (is_h16(c->p) ? 2 : 1);
         TuneKey kn{dim, 8, n, 2, 0, var ? 1 : 0, mode, 0};
         TileCfg cfg;
         if (!tune_lookup(kn, &cfg)) {
-            const std::vector<TileCfg> cands = tune_candidates(dim, n - 2, true, 2, 8, var);
+            std::vector<TileCfg> cands;
+            for (TileCfg t : tune_candidates(dim, n - 2, true, 2, 8, var))
+                if (mode != 2 || t.xp == 2) cands.push_back(t);  // the binary16 pass has two nodes per lane
+            const double* scl = nullptr;
             int maxparts = 1;
             for (TileCfg t : cands) maxparts = std::max(maxparts, norm_tiles(dim, n, t));
+            (void)scl;
             double* part = nullptr;
             e = hipMalloc((void**)&part, sizeof(double) * (size_t)maxparts);
             if (e == hipSuccess) {
@@ -631,15 +663,28 @@ hipError_t autotune(mg_ctx* c) {
                     h.u[0] = (double*)su;
                     h.f = (const double*)sf;
                     h.done = nullptr;
+                    double* tscl = nullptr;
+                    double* tmax = nullptr;
+                    const double scl0[2] = {1.0, 1.0};
+                    if (mode == 2) {  // scale state and partial maxima of the binary16 pass
+                        e = hipMalloc((void**)&tscl, 2 * sizeof(double));
+                        if (e == hipSuccess) e = hipMemcpy(tscl, scl0, sizeof(scl0), hipMemcpyHostToDevice);
+                        if (e == hipSuccess) e = hipMalloc((void**)&tmax, sizeof(double) * (size_t)maxparts);
+                        h.scl = tscl;
+                        h.pmax = tmax;
+                    }
                     IRDesc* d = nullptr;
-                    e = hipMalloc((void**)&d, sizeof(IRDesc));
+                    if (e == hipSuccess) e = hipMalloc((void**)&d, sizeof(IRDesc));
                     if (e == hipSuccess) e = hipMemcpyAsync(d, &h, sizeof(IRDesc), hipMemcpyHostToDevice, s);
                     if (e == hipSuccess)
                         cfg = pick_fastest(cands, c->top.norm, [&](TileCfg t) {
-                            return launch_ir_update(dim, var, d, 1, n, 0, 0, part, maxparts, t, s);
+                            return mode == 2 ? launch_ir_update_f16(dim, d, 1, n, 0, 0, part, maxparts, t, s)
+                                             : launch_ir_update(dim, var, d, 1, n, 0, 0, part, maxparts, t, s);
                         }, s);
                     (void)hipStreamSynchronize(s);
                     ffree(d);
+                    ffree(tscl);
+                    ffree(tmax);
                 }
                 ffree(part);
                 if (e == hipSuccess) tune_store(kn, cfg);
@@ -695,6 +740,11 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
         c->tl32.push_back(default_tiles(dim, 4, c->n[(size_t)l], p->smoother));
     }
     c->top = c->tl64[0];
+    if (is_h16(c->p)) {  // the binary16 refinement pass has two nodes per lane
+        c->top.norm.xp = 2;
+        if (dim == 2) c->top.norm.zchunk = 32;
+        else c->top.norm.by = std::min(c->top.norm.by, 4 * c->top.norm.wv);
+    }
     const char* at = std::getenv("MG_AUTOTUNE");
     c->autotune = !(at && at[0] == '0');
     hipStream_t s = c->stream;
@@ -719,7 +769,7 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
         SETUP_CK(build_groups(c->G64, c->L64, c->prob, ctl_done(c), s));
         SETUP_CK(build_tail(c->tail64, c->G64, tail_first_level(dim, 8, c->n, false), s));
     } else {
-        SETUP_CK(build_levels(c->L32, dim, c->n, 4, true, nullptr, s));
+        SETUP_CK(build_levels(c->L32, dim, c->n, ir_elem(c->p), true, nullptr, s));
         if (c->prob.var) {
             void* k32 = nullptr;
             SETUP_CK(zalloc(&k32, N * sizeof(float), s));
@@ -734,15 +784,19 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
             c->L32.own_k0 = true;
         }
         SETUP_CK(build_groups(c->G32, c->L32, c->prob, ctl_done(c), s));
-        SETUP_CK(build_tail(c->tail32, c->G32, tail_first_level(dim, 4, c->n, true), s));
+        SETUP_CK(build_tail(c->tail32, c->G32, tail_first_level(dim, ir_elem(c->p), c->n, true), s));
         SETUP_CK(zalloc((void**)&c->u64_scratch, N * sizeof(double), s));
         c->h_ir = IRDesc{};
         c->h_ir.u[0] = nullptr;
         c->h_ir.u[1] = c->u64_scratch;
-        c->h_ir.e = (const float*)c->L32.u[0];
+        c->h_ir.e = c->L32.u[0];
         c->h_ir.f = nullptr;
         c->h_ir.k = c->k64;
-        c->h_ir.r = (float*)c->L32.f[0];
+        c->h_ir.r = c->L32.f[0];
+        if (is_h16(c->p)) {
+            SETUP_CK(zalloc((void**)&c->d_scl, 2 * sizeof(double), s));
+            c->h_ir.scl = c->d_scl;
+        }
         c->h_ir.done = ctl_done(c);
         c->h_ir.n = p->n;
         c->h_ir.inst = 0;
@@ -763,6 +817,11 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
     if (c->autotune) SETUP_CK(autotune(c));
     c->pstride = std::max(1, norm_tiles(dim, p->n, c->top.norm));
     SETUP_CK(hipMalloc((void**)&c->d_partial, sizeof(double) * (size_t)c->pstride));
+    if (is_h16(c->p)) {
+        SETUP_CK(hipMalloc((void**)&c->d_pmax, sizeof(double) * (size_t)c->pstride));
+        c->h_ir.pmax = c->d_pmax;
+        SETUP_CK(hipMemcpyAsync(c->d_ir, &c->h_ir, sizeof(IRDesc), hipMemcpyHostToDevice, s));
+    }
     SETUP_CK(hipMalloc((void**)&c->d_norm, sizeof(double)));
     SETUP_CK(hipMalloc((void**)&c->d_norm0, sizeof(double)));
     c->prof_ev.resize(512);
@@ -815,8 +874,9 @@ int mg_vcycle(mg_ctx* c, double* u, const double* f) {
     if (c->p.precision == MG_PREC_FP64) {
         CK(vcycle<double>(c->prob, c->G64, false, c->tl64, c->stream, nullptr, nullptr, 0, &c->tail64));
     } else {
-        CK(enqueue_ir(c, 0, IR_NO_UPDATE, c->stream));
-        CK(vcycle<float>(c->prob, c->G32, true, c->tl32, c->stream, nullptr, nullptr, 0, &c->tail32));
+        CK(enqueue_ir_start(c, c->stream));
+        if (is_h16(c->p)) CK(vcycle<half_t>(c->prob, c->G32, true, c->tl32, c->stream, nullptr, nullptr, 0, &c->tail32));
+        else CK(vcycle<float>(c->prob, c->G32, true, c->tl32, c->stream, nullptr, nullptr, 0, &c->tail32));
         CK(enqueue_ir(c, 0, 0, c->stream));
         CK(hipMemcpyAsync(u, c->u64_scratch, npts(c->p.dim, c->p.n) * sizeof(double), hipMemcpyDeviceToDevice,
                           c->stream));
@@ -844,13 +904,13 @@ int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
     r = ensure_hist(c, max_cycles + 1);
     if (r != MG_OK) return r;
     hipStream_t s = c->stream;
-    const bool ir = c->p.precision == MG_PREC_FP32_IR;
+    const bool ir = is_ir(c->p);
     c->prof_n = 0;  // measured launches are tagged per solve
     c->prof_step.clear();
     c->prof_kind.clear();
     // rho_0 (clear the stop flag a previous solve left set first: every kernel honours it)
     CK(launch_fill_int(ctl_done(c), 0, 1, s));
-    if (ir) CK(enqueue_ir(c, 0, IR_NO_UPDATE, s));
+    if (ir) CK(enqueue_ir_start(c, s));
     else CK(enqueue_norm(c, s));
     CK(launch_solve_init(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist, c->hist_cap, 1,
                          s));
@@ -981,18 +1041,23 @@ static int finish_desc(void* d, hipStream_t s, hipError_t launch) {
     return dev_status(e);
 }
 
+// word size of a level-operation dtype (0 FP64, 1 FP32, 2 binary16), 0 if invalid
+static int dtype_elem(int dtype) { return dtype == 0 ? 8 : (dtype == 1 ? 4 : (dtype == 2 ? 2 : 0)); }
+
 int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const void* k, const void* u_in,
                     const void* f, void* u_out, const void* ec, int zero_guess, int by, int zchunk, int prefetch,
                     int waves, int order, void* stream) {
-    if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
+    const int elem = dtype_elem(dtype);
+    if (!valid_edge(dim, n) || n < 5 || !elem) return MG_EINVAL;
     if ((smoother != 0 && smoother != 1) || !f || !u_out || (!u_in && !zero_guess)) return MG_EINVAL;
     if (ec && zero_guess) return MG_EINVAL;
-    TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, n, smoother, by, zchunk, 0);
+    if (elem == 2 && k) return MG_ENOTSUP;
+    TileCfg cfg = pick_cfg(dim, elem, n, smoother, by, zchunk, 0);
     if (prefetch) cfg.pd = prefetch;
     if (waves) cfg.wv = waves;
     if (order != 0 && order != 1) return MG_EINVAL;
     cfg.order = order;
-    if (!valid_cfg(cfg, dim, dtype == 0 ? 8 : 4, k != nullptr, 0)) return MG_EINVAL;
+    if (!valid_cfg(cfg, dim, elem, k != nullptr, 0)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
     h.u = const_cast<void*>(u_in);
@@ -1008,17 +1073,20 @@ int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const
     int r = with_desc(h, s, &d);
     if (r != MG_OK) return r;
     const int flags = (zero_guess ? SWEEP_ZERO_GUESS : 0) | (ec ? SWEEP_PROLONG : 0);
-    hipError_t e = dtype == 0 ? launch_smooth<double>(dim, smoother, k != nullptr, d, 1, n, 0, flags, cfg, s)
-                              : launch_smooth<float>(dim, smoother, k != nullptr, d, 1, n, 0, flags, cfg, s);
+    hipError_t e = elem == 8   ? launch_smooth<double>(dim, smoother, k != nullptr, d, 1, n, 0, flags, cfg, s)
+                   : elem == 4 ? launch_smooth<float>(dim, smoother, k != nullptr, d, 1, n, 0, flags, cfg, s)
+                               : launch_smooth<half_t>(dim, smoother, false, d, 1, n, 0, flags, cfg, s);
     return finish_desc(d, s, e);
 }
 
 int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const void* u, const void* f, void* fc,
                                int by, int zchunk, void* stream) {
-    if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
+    const int elem = dtype_elem(dtype);
+    if (!valid_edge(dim, n) || n < 5 || !elem) return MG_EINVAL;
     if (!u || !f || !fc) return MG_EINVAL;
-    const TileCfg cfg = pick_cfg(dim, dtype == 0 ? 8 : 4, n, 0, by, zchunk, 1);
-    if (!valid_cfg(cfg, dim, dtype == 0 ? 8 : 4, k != nullptr, 1)) return MG_EINVAL;
+    if (elem == 2 && k) return MG_ENOTSUP;
+    const TileCfg cfg = pick_cfg(dim, elem, n, 0, by, zchunk, 1);
+    if (!valid_cfg(cfg, dim, elem, k != nullptr, 1)) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
     h.u = const_cast<void*>(u);
@@ -1030,13 +1098,15 @@ int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const v
     GridDesc* d = nullptr;
     int r = with_desc(h, s, &d);
     if (r != MG_OK) return r;
-    hipError_t e = dtype == 0 ? launch_restrict<double>(dim, k != nullptr, d, 1, n, 0, cfg, s)
-                              : launch_restrict<float>(dim, k != nullptr, d, 1, n, 0, cfg, s);
+    hipError_t e = elem == 8   ? launch_restrict<double>(dim, k != nullptr, d, 1, n, 0, cfg, s)
+                   : elem == 4 ? launch_restrict<float>(dim, k != nullptr, d, 1, n, 0, cfg, s)
+                               : launch_restrict<half_t>(dim, false, d, 1, n, 0, cfg, s);
     return finish_desc(d, s, e);
 }
 
 int mg_level_prolong_correct(int dim, int n, int dtype, void* u, const void* ec, void* stream) {
-    if (!valid_edge(dim, n) || n < 5 || (dtype != 0 && dtype != 1)) return MG_EINVAL;
+    const int elem = dtype_elem(dtype);
+    if (!valid_edge(dim, n) || n < 5 || !elem) return MG_EINVAL;
     if (!u || !ec) return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
@@ -1046,12 +1116,16 @@ int mg_level_prolong_correct(int dim, int n, int dtype, void* u, const void* ec,
     GridDesc* d = nullptr;
     int r = with_desc(h, s, &d);
     if (r != MG_OK) return r;
-    hipError_t e = dtype == 0 ? launch_prolong<double>(dim, d, 1, n, 0, s) : launch_prolong<float>(dim, d, 1, n, 0, s);
+    hipError_t e = elem == 8   ? launch_prolong<double>(dim, d, 1, n, 0, s)
+                   : elem == 4 ? launch_prolong<float>(dim, d, 1, n, 0, s)
+                               : launch_prolong<half_t>(dim, d, 1, n, 0, s);
     return finish_desc(d, s, e);
 }
 
 int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f, void* stream) {
-    if ((dim != 2 && dim != 3) || (dtype != 0 && dtype != 1) || !u || !f) return MG_EINVAL;
+    const int elem = dtype_elem(dtype);
+    if ((dim != 2 && dim != 3) || !elem || !u || !f) return MG_EINVAL;
+    if (elem == 2 && k) return MG_ENOTSUP;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
     h.u = u;
@@ -1062,8 +1136,9 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
     GridDesc* d = nullptr;
     int r = with_desc(h, s, &d);
     if (r != MG_OK) return r;
-    hipError_t e = dtype == 0 ? launch_coarsest<double>(dim, k != nullptr, d, 1, s)
-                              : launch_coarsest<float>(dim, k != nullptr, d, 1, s);
+    hipError_t e = elem == 8   ? launch_coarsest<double>(dim, k != nullptr, d, 1, s)
+                   : elem == 4 ? launch_coarsest<float>(dim, k != nullptr, d, 1, s)
+                               : launch_coarsest<half_t>(dim, false, d, 1, s);
     return finish_desc(d, s, e);
 }
 
@@ -1105,6 +1180,58 @@ int mg_level_ir_update(int dim, int n, const double* k, const double* u_in, cons
     ffree(nrm);
     if (err != hipSuccess) return dev_status(err);
     return dev_status(e2);
+}
+
+int mg_level_ir_update_f16(int dim, int n, const double* u_in, const void* e16, double e_scale, double prev_max,
+                           const double* f, double* u_out, void* r16, double* norm_out, double* max_out, int by,
+                           int zchunk, int prefetch, int waves, void* stream) {
+    if (!valid_edge(dim, n) || n < 5) return MG_EINVAL;
+    if (!u_in || !f || !r16 || !norm_out || !max_out || (e16 && (!u_out || u_in == u_out))) return MG_EINVAL;
+    if (e16 && !(e_scale > 0.0)) return MG_EINVAL;
+    TileCfg cfg = pick_cfg(dim, 8, n, 0, by, zchunk, 2);
+    if (prefetch) cfg.pd = prefetch;
+    if (waves) cfg.wv = waves;
+    cfg.xp = 2;
+    if (dim == 2 && !zchunk) cfg.zchunk = 32;
+    if (dim == 3 && !by) cfg.by = std::min(cfg.by, 4 * cfg.wv);
+    if (!valid_cfg(cfg, dim, 8, false, 2)) return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int nparts = norm_tiles(dim, n, cfg);
+    IRDesc h{};
+    h.u[0] = const_cast<double*>(u_in);
+    h.u[1] = e16 ? u_out : const_cast<double*>(u_in);
+    h.e = e16;
+    h.f = f;
+    h.r = r16;
+    h.n = n;
+    h.c = level_c(n);
+    const double hs[2] = {e16 ? e_scale : 1.0, prev_max};
+    IRDesc* d = nullptr;
+    double* buf = nullptr;  // part[nparts], pmax[nparts], scl[2], norm
+    CK(hipMalloc((void**)&d, sizeof(IRDesc)));
+    hipError_t err = hipMalloc((void**)&buf, sizeof(double) * (size_t)(2 * nparts + 3));
+    double* part = buf;
+    double* pmax = buf ? buf + nparts : nullptr;
+    double* scl = buf ? buf + 2 * nparts : nullptr;
+    double* nrm = buf ? buf + 2 * nparts + 2 : nullptr;
+    h.scl = scl;
+    h.pmax = pmax;
+    double host[2] = {0.0, 0.0};
+    if (err == hipSuccess) err = hipMemcpyAsync(scl, hs, sizeof(hs), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(d, &h, sizeof(IRDesc), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess)
+        err = launch_ir_update_f16(dim, d, 1, n, 0, e16 ? 0 : IR_NO_UPDATE, part, nparts, cfg, s);
+    if (err == hipSuccess) err = launch_norm_finalize_f16(part, pmax, nparts, nrm, scl, nullptr, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(&host[0], nrm, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(&host[1], scl + 1, sizeof(double), hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    ffree(d);
+    ffree(buf);
+    if (err != hipSuccess) return dev_status(err);
+    if (e2 != hipSuccess) return dev_status(e2);
+    *norm_out = host[0];
+    *max_out = host[1];
+    return MG_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -9,6 +9,9 @@
 
 namespace mg {
 
+// binary16 storage cell of the half-precision hierarchy (arithmetic in float)
+typedef _Float16 half_t;
+
 // Largest accepted grid edges: every node index of a grid (and of each level)
 // then fits in 32 bits (32769^2 and 1025^3 are both below 2^31).
 constexpr int kMaxEdge2D = 32769, kMaxEdge3D = 1025;
@@ -27,7 +30,7 @@ inline int max_tile_rows(int dim, int elem, bool var, int family, int wv = 4) {
     if (dim == 2 || family == 1) return 32;
     if (wv == 1) {  // 3D sweep with one wavefront per tile: the thread holds every row
         if (family != 0) return 0;
-        return elem == 4 && !var ? 12 : (elem == 8 && var ? 0 : 8);
+        return elem <= 4 && !var ? 12 : (elem == 8 && var ? 0 : 8);
     }
     // 3D sweeps: FP64 with a coefficient field keeps six ring values per row
     // (iterate, coefficient and four face rings) in 8-byte registers
@@ -65,17 +68,23 @@ struct GridDesc {
 
 // FP64 refinement pass of one grid: u_out = u_in + e (inner nodes),
 // r = f - A u_out in FP64, r32 = (float) r, per-block partial sums of r^2.
+// Half-precision form: e and r are binary16 cells scaled by powers of two,
+// u_out = u_in + e / scl[0] and r16 = half(float(s) * float(r)) with s the
+// scale of scl[1] (the largest |r| of the previous pass); the pass also writes
+// per-block partial maxima of |r| to pmax.
 struct IRDesc {
     double* u[2];     // ping-pong FP64 iterate; kernel argument 'sel' names the input
-    const float* e;   // single-precision correction (zero boundary)
+    const void* e;    // correction, float (or binary16), zero boundary
     const double* f;  // FP64 right-hand side
     const double* k;  // FP64 nodal coefficient or null
-    float* r;         // single-precision residual out (boundary left untouched, zero)
+    void* r;          // residual out, float (or binary16) (boundary left untouched, zero)
     const int* done;  // stop flag or null
     const int* par;   // per-instance ping-pong parity (overrides 'sel') or null
     int n;
     int inst;
     double c;
+    const double* scl = nullptr;  // half-precision form: {scale of e, largest |r| of the previous pass}
+    double* pmax = nullptr;       // half-precision form: partial maxima of |r|, same layout as the sums
 };
 
 // Coarse tail of a V-cycle for one instance: its levels from the tail's finest
@@ -142,6 +151,15 @@ hipError_t launch_norm(int dim, bool var, const GridDesc* d, int ninst, int n, i
 enum IRFlags { IR_NO_UPDATE = 1 };
 hipError_t launch_ir_update(int dim, bool var, const IRDesc* d, int ninst, int n, int sel, int flags,
                             double* partial, int pstride, TileCfg cfg, hipStream_t s);
+// Half-precision form of the pass (binary16 e and r, Laplacian, two nodes per
+// lane: cfg.xp must be 2); also writes partial maxima of |r| to d->pmax.
+hipError_t launch_ir_update_f16(int dim, const IRDesc* d, int ninst, int n, int sel, int flags, double* partial,
+                                int pstride, TileCfg cfg, hipStream_t s);
+// After a half-precision pass: norm = sqrt(sum of the partials) as
+// launch_norm_finalize; unless *done: scl[0] = fp16 scale of scl[1] (the
+// scale that pass wrote r with), scl[1] = max of the partial maxima.
+hipError_t launch_norm_finalize_f16(const double* partial, const double* pmax, int nparts, double* norm, double* scl,
+                                    const int* done, hipStream_t s);
 // norm[inst] = sqrt(sum of partial[inst*pstride + 0 .. nparts-1]) in a fixed order; for
 // each of 'ninst' rows starting at row 'row0'.
 hipError_t launch_norm_finalize(const double* partial, int pstride, int nparts, int row0, int ninst,

@@ -44,6 +44,28 @@
 namespace mg {
 namespace {
 
+// Storage and arithmetic types.  FP64 and FP32 fields compute in their own
+// type; binary16 fields (the half-precision form of the refinement) are
+// stored as _Float16 and computed in float, and every value the method stores
+// is rounded to binary16 at the point where it would be written, also when a
+// fused kernel keeps it in registers (the red half of a sweep, the corrected
+// iterate): stored<S>(v) is v rounded to S and read back.
+template <typename S>
+struct ArithOf {
+    using type = S;
+};
+template <>
+struct ArithOf<half_t> {
+    using type = float;
+};
+template <typename S>
+using arith_t = typename ArithOf<S>::type;
+template <typename S, typename T>
+__device__ __forceinline__ T stored(T v) {
+    if constexpr (sizeof(S) == sizeof(T)) return v;
+    else return (T)(S)v;
+}
+
 template <typename T>
 __device__ __forceinline__ MG_GLOBAL T* gp(T* p) {
     return (MG_GLOBAL T*)p;

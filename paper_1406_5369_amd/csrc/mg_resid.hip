@@ -230,10 +230,10 @@ __device__ __forceinline__ void resid3d_body(const GridDesc* gd, const IRDesc* i
         inst = d.inst;
         s.uin = gp((const double*)(sel ? d.u[1] : d.u[0]));  // a select: indexing the copy would spill it
         s.uout = gp(sel ? d.u[0] : d.u[1]);
-        s.e = gp(d.e);
+        s.e = gp((const float*)d.e);
         s.f = gp(d.f);
         s.kf = gp(d.k);
-        s.r32 = gp(d.r);
+        s.r32 = gp((float*)d.r);
         s.c = d.c;
     } else {
         const GridDesc d = *gd;
@@ -287,6 +287,18 @@ struct __attribute__((aligned(8))) Dbl2 {
 struct __attribute__((aligned(4))) Flt2 {
     float a, b;
 };
+struct __attribute__((aligned(2))) Hlf2 {
+    half_t a, b;
+};
+// pair type of the correction / residual words
+template <typename E>
+struct PairOf {
+    using type = Flt2;
+};
+template <>
+struct PairOf<half_t> {
+    using type = Hlf2;
+};
 __device__ __forceinline__ Dbl2 ld_d2(const MG_GLOBAL double* base, unsigned boff) {
     const MG_GLOBAL Dbl2* q = (const MG_GLOBAL Dbl2*)((const MG_GLOBAL char*)base + boff);
     Dbl2 v;
@@ -294,9 +306,11 @@ __device__ __forceinline__ Dbl2 ld_d2(const MG_GLOBAL double* base, unsigned bof
     v.b = q->b;
     return v;
 }
-__device__ __forceinline__ Flt2 ld_f2(const MG_GLOBAL float* base, unsigned boff) {
-    const MG_GLOBAL Flt2* q = (const MG_GLOBAL Flt2*)((const MG_GLOBAL char*)base + boff);
-    Flt2 v;
+template <typename E>
+__device__ __forceinline__ typename PairOf<E>::type ld_f2(const MG_GLOBAL E* base, unsigned boff) {
+    using P2 = typename PairOf<E>::type;
+    const MG_GLOBAL P2* q = (const MG_GLOBAL P2*)((const MG_GLOBAL char*)base + boff);
+    P2 v;
     v.a = q->a;
     v.b = q->b;
     return v;
@@ -306,35 +320,83 @@ __device__ __forceinline__ void st_d2(MG_GLOBAL double* base, unsigned boff, con
     q->a = v.a;
     q->b = v.b;
 }
-__device__ __forceinline__ void st_f2(MG_GLOBAL float* base, unsigned boff, const Flt2& v) {
-    MG_GLOBAL Flt2* q = (MG_GLOBAL Flt2*)((MG_GLOBAL char*)base + boff);
+template <typename E>
+__device__ __forceinline__ void st_f2(MG_GLOBAL E* base, unsigned boff, const typename PairOf<E>::type& v) {
+    using P2 = typename PairOf<E>::type;
+    MG_GLOBAL P2* q = (MG_GLOBAL P2*)((MG_GLOBAL char*)base + boff);
     q->a = v.a;
     q->b = v.b;
 }
 
-template <int BY, int PD, bool IR, int WV>
+// Half-precision form: the scale for a residual of largest magnitude mx, the
+// power of two s with 8 <= s mx < 16, its exponent kept in [-126, 127] so that
+// s is a normal float (1 for zero or non-finite mx).
+__device__ __forceinline__ double fp16_scale(double mx) {
+    if (!(mx > 0.0) || !(mx <= 1.7976931348623157e308)) return 1.0;
+    int e;
+    (void)frexp(mx, &e);  // mx = m 2^e, 1/2 <= m < 1
+    return ldexp(1.0, min(127, max(-126, 4 - e)));
+}
+
+// Correction word -> FP64 increment, residual -> stored word: plain
+// conversions for float words; binary16 words carry the power-of-two scale
+// (the increment e / s_e, the stored residual half(float(s_r) * float(r))).
+template <typename E>
+struct IRWords {
+    double inv = 1.0;  // 1 / scale of the correction read
+    float sr = 1.0f;   // scale of the residual written
+    __device__ __forceinline__ double incr(E x) const {
+        if constexpr (sizeof(E) == 4) return (double)x;
+        else return (double)(float)x * inv;
+    }
+    __device__ __forceinline__ E res(double r) const {
+        if constexpr (sizeof(E) == 4) return (float)r;
+        else return (E)(sr * (float)r);
+    }
+};
+
+// Deterministic workgroup maximum (result valid in thread 0).
+template <int WV>
+__device__ __forceinline__ double block_max_w(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();  // red may still be read by the preceding block sum
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double m = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < WV; ++i) m = fmax(m, red[i]);
+    return m;
+}
+
+template <int BY, int PD, bool IR, int WV, typename E = float>
 struct Pair3D {
     static constexpr int TX = 2 * BX, TY = BY - 2, RPT = BY / WV;
     static_assert(RPT >= 1 && RPT * WV == BY, "tile rows must be a multiple of the wavefronts");
+    using E2 = typename PairOf<E>::type;
+    static constexpr bool H16 = sizeof(E) == 2;
     Dbl2 (*U)[BY][BX];
     const MG_GLOBAL double* __restrict__ uin;
     MG_GLOBAL double* __restrict__ uout;
-    const MG_GLOBAL float* __restrict__ e;
+    const MG_GLOBAL E* __restrict__ e;
     const MG_GLOBAL double* __restrict__ f;
-    MG_GLOBAL float* __restrict__ r32;
+    MG_GLOBAL E* __restrict__ r32;
+    IRWords<E> wd;
     int n, x0, y0, z0, z1, kstart, kend, flags;
     double c;
     int lane, w;
     unsigned inx;     // bit 0: a inner in x, bit 1: b inner in x
     bool hin;         // the lane's outside neighbour (lane 0: x0-1, lane 63: x0+128) is an inner node
-    unsigned xp8, xp4, xh8, xh4;  // byte offsets: the pair, the outside neighbour (8- / 4-byte words)
+    unsigned xp8, xp4, xh8, xh4;  // byte offsets: the pair, the outside neighbour (8-byte / correction words)
     unsigned minner, mring;       // bit m: row m inner in y / in the tile rows 1 .. BY-2
     size_t pl;
     Dbl2 un[3][RPT], fr[3][RPT], uo[3][RPT];
-    Flt2 en[3][RPT];
+    E2 en[3][RPT];
     double hn[3][RPT], ho[3][RPT];  // outside neighbour: as loaded / updated
-    float he[3][RPT];
+    E he[3][RPT];
     double acc = 0.0;
+    double mxr = 0.0;  // half-precision form: largest |r|
 
     __device__ __forceinline__ int gy(int m) const { return y0 - 1 + w + WV * m; }
     __device__ __forceinline__ int rowoff(int m) const { return min(max(gy(m), 0), n - 1) * n; }
@@ -345,13 +407,13 @@ struct Pair3D {
         inx = (xa <= n - 2 ? 1u : 0u) | (xa + 1 <= n - 2 ? 2u : 0u);
         const unsigned xp = (unsigned)min(xa, n - 2);
         xp8 = xp * 8u;
-        xp4 = xp * 4u;
+        xp4 = xp * (unsigned)sizeof(E);
         // lanes 0 .. 31 read the left neighbour of the box, 32 .. 63 the right
         // one (clamped into the row); only lanes 0 and 63 use them
         const int xl = x0 - 1, xr = min(x0 + TX, n - 1);
         const unsigned xh = (unsigned)(lane < 32 ? xl : xr);
         xh8 = xh * 8u;
-        xh4 = xh * 4u;
+        xh4 = xh * (unsigned)sizeof(E);
         hin = lane == 0 ? xl >= 1 : (x0 + TX <= n - 2);
         minner = mring = 0;
 #pragma unroll
@@ -362,8 +424,8 @@ struct Pair3D {
         }
     }
 
-    __device__ __forceinline__ void issue(int z, Dbl2 (&du)[RPT], Flt2 (&de)[RPT], double (&dh)[RPT],
-                                          float (&dhe)[RPT]) {
+    __device__ __forceinline__ void issue(int z, Dbl2 (&du)[RPT], E2 (&de)[RPT], double (&dh)[RPT],
+                                          E (&dhe)[RPT]) {
         const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
@@ -372,12 +434,12 @@ struct Pair3D {
             dh[m] = ld_off(row, xh8);
             if constexpr (IR) {
                 if (!(flags & IR_NO_UPDATE)) {
-                    const MG_GLOBAL float* erow = e + zoff + rowoff(m);
+                    const MG_GLOBAL E* erow = e + zoff + rowoff(m);
                     de[m] = ld_f2(erow, xp4);
                     dhe[m] = ld_off(erow, xh4);
                 } else {
-                    de[m] = Flt2{0.0f, 0.0f};
-                    dhe[m] = 0.0f;
+                    de[m] = E2{(E)0, (E)0};
+                    dhe[m] = (E)0;
                 }
             }
         }
@@ -405,9 +467,9 @@ struct Pair3D {
             if constexpr (IR) {
                 if (!(flags & IR_NO_UPDATE)) {
                     const bool iny = zin && ((minner >> m) & 1u);
-                    if (iny && (inx & 1u)) v.a = v.a + (double)en[S0][m].a;
-                    if (iny && (inx & 2u)) v.b = v.b + (double)en[S0][m].b;
-                    if (iny && hin) h = h + (double)he[S0][m];
+                    if (iny && (inx & 1u)) v.a = v.a + wd.incr(en[S0][m].a);
+                    if (iny && (inx & 2u)) v.b = v.b + wd.incr(en[S0][m].b);
+                    if (iny && hin) h = h + wd.incr(he[S0][m]);
                     if (own && iny && ((mring >> m) & 1u)) {
                         MG_GLOBAL double* row = uout + (size_t)kk * pl + rowoff(m);
                         if (inx == 3u) st_d2(row, xp8, v);
@@ -439,13 +501,17 @@ struct Pair3D {
                     const double rb = res_lap3<double>(uc.b, uc.a, eb, dn.b, up.b, uo[S2][m].b, uo[S0][m].b,
                                                        fr[S1][m].b, c);
                     if constexpr (IR) {
-                        MG_GLOBAL float* row = r32 + (size_t)zz * pl + rowoff(m);
-                        const Flt2 rv{(float)ra, (float)rb};
+                        MG_GLOBAL E* row = r32 + (size_t)zz * pl + rowoff(m);
+                        const E2 rv{wd.res(ra), wd.res(rb)};
                         if (inx == 3u) st_f2(row, xp4, rv);
                         else if (inx & 1u) st_off(row, xp4, rv.a);
                     }
                     if (inx & 1u) acc += ra * ra;
                     if (inx & 2u) acc += rb * rb;
+                    if constexpr (H16) {
+                        if (inx & 1u) mxr = fmax(mxr, fabs(ra));
+                        if (inx & 2u) mxr = fmax(mxr, fabs(rb));
+                    }
                 }
             }
         }
@@ -480,14 +546,17 @@ struct Pair3D {
 // extra word per row) along y through a chunk of rows.  y-neighbours are the
 // thread's own three-row ring, so there is no LDS and no barrier; the four
 // wavefronts of a workgroup take four consecutive chunks of one strip.
-template <int PD, bool IR>
+template <int PD, bool IR, typename E = float>
 struct Pair2D {
     static constexpr int TX = 2 * BX;
+    using E2 = typename PairOf<E>::type;
+    static constexpr bool H16 = sizeof(E) == 2;
     const MG_GLOBAL double* __restrict__ uin;
     MG_GLOBAL double* __restrict__ uout;
-    const MG_GLOBAL float* __restrict__ e;
+    const MG_GLOBAL E* __restrict__ e;
     const MG_GLOBAL double* __restrict__ f;
-    MG_GLOBAL float* __restrict__ r32;
+    MG_GLOBAL E* __restrict__ r32;
+    IRWords<E> wd;
     int n, x0, y0, y1, flags;
     double c;
     int lane;
@@ -495,24 +564,25 @@ struct Pair2D {
     bool hin;
     unsigned xp8, xp4, xh8, xh4;
     Dbl2 un[3], fr[3], uo[3];
-    Flt2 en[3];
+    E2 en[3];
     double hn[3], ho[3];
-    float he[3];
+    E he[3];
     double acc = 0.0;
+    double mxr = 0.0;
 
     __device__ __forceinline__ void init() {
         const int xa = x0 + 2 * lane;
         inx = (xa <= n - 2 ? 1u : 0u) | (xa + 1 <= n - 2 ? 2u : 0u);
         const unsigned xp = (unsigned)min(xa, n - 2);
         xp8 = xp * 8u;
-        xp4 = xp * 4u;
+        xp4 = xp * (unsigned)sizeof(E);
         const int xl = x0 - 1, xr = min(x0 + TX, n - 1);
         const unsigned xh = (unsigned)(lane < 32 ? xl : xr);
         xh8 = xh * 8u;
-        xh4 = xh * 4u;
+        xh4 = xh * (unsigned)sizeof(E);
         hin = lane == 0 ? xl >= 1 : (x0 + TX <= n - 2);
     }
-    __device__ __forceinline__ void issue(int y, Dbl2& du, Flt2& de, double& dh, float& dhe) {
+    __device__ __forceinline__ void issue(int y, Dbl2& du, E2& de, double& dh, E& dhe) {
         const size_t off = (size_t)min(max(y, 0), n - 1) * n;
         du = ld_d2(uin + off, xp8);
         dh = ld_off(uin + off, xh8);
@@ -521,8 +591,8 @@ struct Pair2D {
                 de = ld_f2(e + off, xp4);
                 dhe = ld_off(e + off, xh4);
             } else {
-                de = Flt2{0.0f, 0.0f};
-                dhe = 0.0f;
+                de = E2{(E)0, (E)0};
+                dhe = (E)0;
             }
         }
     }
@@ -536,9 +606,9 @@ struct Pair2D {
         double h = hn[S0];
         if constexpr (IR) {
             if (!(flags & IR_NO_UPDATE)) {
-                if (yin && (inx & 1u)) v.a = v.a + (double)en[S0].a;
-                if (yin && (inx & 2u)) v.b = v.b + (double)en[S0].b;
-                if (yin && hin) h = h + (double)he[S0];
+                if (yin && (inx & 1u)) v.a = v.a + wd.incr(en[S0].a);
+                if (yin && (inx & 2u)) v.b = v.b + wd.incr(en[S0].b);
+                if (yin && hin) h = h + wd.incr(he[S0]);
                 if (yin && j >= y0 && j < y1) {
                     MG_GLOBAL double* row = uout + (size_t)j * n;
                     if (inx == 3u) st_d2(row, xp8, v);
@@ -560,13 +630,17 @@ struct Pair2D {
             const double ra = res_lap2<double>(uc.a, wa, uc.b, uo[S2].a, uo[S0].a, fr[S1].a, c);
             const double rb = res_lap2<double>(uc.b, uc.a, eb, uo[S2].b, uo[S0].b, fr[S1].b, c);
             if constexpr (IR) {
-                MG_GLOBAL float* row = r32 + (size_t)jj * n;
-                const Flt2 rv{(float)ra, (float)rb};
+                MG_GLOBAL E* row = r32 + (size_t)jj * n;
+                const E2 rv{wd.res(ra), wd.res(rb)};
                 if (inx == 3u) st_f2(row, xp4, rv);
                 else if (inx & 1u) st_off(row, xp4, rv.a);
             }
             if (inx & 1u) acc += ra * ra;
             if (inx & 2u) acc += rb * rb;
+            if constexpr (H16) {
+                if (inx & 1u) mxr = fmax(mxr, fabs(ra));
+                if (inx & 2u) mxr = fmax(mxr, fabs(rb));
+            }
         }
     }
 
@@ -593,13 +667,14 @@ struct Pair2D {
     }
 };
 
-template <int PD, bool IR>
+template <int PD, bool IR, typename E = float>
 __device__ __forceinline__ void pair2d_body(const GridDesc* gd, const IRDesc* ird, int sel, int flags,
                                             double* __restrict__ part, int pstride, int ychunk) {
-    using S = Pair2D<PD, IR>;
+    using S = Pair2D<PD, IR, E>;
     __shared__ double red[4];
     S s;
     int n, inst;
+    double* pmax = nullptr;
     if constexpr (IR) {
         const IRDesc d = *ird;
         if (d.par) sel = *gp(d.par);
@@ -607,10 +682,16 @@ __device__ __forceinline__ void pair2d_body(const GridDesc* gd, const IRDesc* ir
         inst = d.inst;
         s.uin = gp((const double*)(sel ? d.u[1] : d.u[0]));
         s.uout = gp(sel ? d.u[0] : d.u[1]);
-        s.e = gp(d.e);
+        s.e = gp((const E*)d.e);
         s.f = gp(d.f);
-        s.r32 = gp(d.r);
+        s.r32 = gp((E*)d.r);
         s.c = d.c;
+        if constexpr (S::H16) {
+            const MG_GLOBAL double* scl = gp(d.scl);
+            s.wd.inv = 1.0 / scl[0];
+            s.wd.sr = (float)fp16_scale(scl[1]);
+            pmax = d.pmax;
+        }
     } else {
         const GridDesc d = *gd;
         n = d.n;
@@ -635,6 +716,10 @@ __device__ __forceinline__ void pair2d_body(const GridDesc* gd, const IRDesc* ir
     s.run();
     const double t = block_sum_w<4>(s.acc, red);
     if (threadIdx.x == 0) part[(size_t)inst * pstride + blockIdx.x] = t;
+    if constexpr (S::H16) {
+        const double mx = block_max_w<4>(s.mxr, red);
+        if (threadIdx.x == 0) pmax[(size_t)inst * pstride + blockIdx.x] = mx;
+    }
 }
 
 template <int PD>
@@ -645,22 +730,23 @@ __global__ __launch_bounds__(NT) void k_norm2d_p(const GridDesc* __restrict__ de
     pair2d_body<PD, false>(d, nullptr, sel, 0, part, pstride, ychunk);
 }
 
-template <int PD, int FL>
+template <int PD, int FL, typename E = float>
 __global__ __launch_bounds__(NT) void k_ir2d_p(const IRDesc* __restrict__ descs, int sel, double* __restrict__ part,
                                                int pstride, int ychunk) {
     const IRDesc* d = descs + blockIdx.y;
     if (d->done && *gp(d->done)) return;
-    pair2d_body<PD, true>(nullptr, d, sel, FL, part, pstride, ychunk);
+    pair2d_body<PD, true, E>(nullptr, d, sel, FL, part, pstride, ychunk);
 }
 
-template <int BY, int PD, bool IR, int WV>
+template <int BY, int PD, bool IR, int WV, typename E = float>
 __device__ __forceinline__ void pair3d_body(const GridDesc* gd, const IRDesc* ird, int sel, int flags,
                                             double* __restrict__ part, int pstride, int zchunk) {
-    using S = Pair3D<BY, PD, IR, WV>;
+    using S = Pair3D<BY, PD, IR, WV, E>;
     __shared__ double red[WV];
     __shared__ Dbl2 U[3][BY][BX];
     S s;
     int n, inst;
+    double* pmax = nullptr;
     if constexpr (IR) {
         const IRDesc d = *ird;
         if (d.par) sel = *gp(d.par);
@@ -668,10 +754,16 @@ __device__ __forceinline__ void pair3d_body(const GridDesc* gd, const IRDesc* ir
         inst = d.inst;
         s.uin = gp((const double*)(sel ? d.u[1] : d.u[0]));
         s.uout = gp(sel ? d.u[0] : d.u[1]);
-        s.e = gp(d.e);
+        s.e = gp((const E*)d.e);
         s.f = gp(d.f);
-        s.r32 = gp(d.r);
+        s.r32 = gp((E*)d.r);
         s.c = d.c;
+        if constexpr (S::H16) {
+            const MG_GLOBAL double* scl = gp(d.scl);
+            s.wd.inv = 1.0 / scl[0];
+            s.wd.sr = (float)fp16_scale(scl[1]);
+            pmax = d.pmax;
+        }
     } else {
         const GridDesc d = *gd;
         n = d.n;
@@ -700,6 +792,10 @@ __device__ __forceinline__ void pair3d_body(const GridDesc* gd, const IRDesc* ir
     s.run();
     const double t = block_sum_w<WV>(s.acc, red);
     if (threadIdx.x == 0) part[(size_t)inst * pstride + blockIdx.x] = t;
+    if constexpr (S::H16) {
+        const double mx = block_max_w<WV>(s.mxr, red);
+        if (threadIdx.x == 0) pmax[(size_t)inst * pstride + blockIdx.x] = mx;
+    }
 }
 
 template <int BY, int PD, int WV>
@@ -710,12 +806,12 @@ __global__ __launch_bounds__(64 * WV) void k_norm3d_p(const GridDesc* __restrict
     pair3d_body<BY, PD, false, WV>(d, nullptr, sel, 0, part, pstride, zchunk);
 }
 
-template <int BY, int PD, int FL, int WV>
+template <int BY, int PD, int FL, int WV, typename E = float>
 __global__ __launch_bounds__(64 * WV) void k_ir3d_p(const IRDesc* __restrict__ descs, int sel,
                                                     double* __restrict__ part, int pstride, int zchunk) {
     const IRDesc* d = descs + blockIdx.y;
     if (d->done && *gp(d->done)) return;
-    pair3d_body<BY, PD, true, WV>(nullptr, d, sel, FL, part, pstride, zchunk);
+    pair3d_body<BY, PD, true, WV, E>(nullptr, d, sel, FL, part, pstride, zchunk);
 }
 
 template <bool VAR, int BY, int PD, int WV>
@@ -746,10 +842,10 @@ __global__ __launch_bounds__(NT) void k_ir2d(const IRDesc* __restrict__ descs, i
     const int x0 = 1 + (tile % ntx) * TX, y0 = 1 + (tile / ntx) * TY;
     const MG_GLOBAL double* __restrict__ uin = gp((const double*)(sel ? d.u[1] : d.u[0]));
     MG_GLOBAL double* __restrict__ uout = gp(sel ? d.u[0] : d.u[1]);
-    const MG_GLOBAL float* __restrict__ e = gp(d.e);
+    const MG_GLOBAL float* __restrict__ e = gp((const float*)d.e);
     const MG_GLOBAL double* __restrict__ f = gp(d.f);
     const MG_GLOBAL double* __restrict__ kf = gp(d.k);
-    MG_GLOBAL float* __restrict__ r32 = gp(d.r);
+    MG_GLOBAL float* __restrict__ r32 = gp((float*)d.r);
     const double c = d.c;
     __shared__ double U[BY][BX];
     __shared__ double K[VAR ? BY : 1][BX];
@@ -817,6 +913,26 @@ __global__ __launch_bounds__(NT) void k_norm_finalize(const double* __restrict__
     const int row = row0 + blockIdx.x;
     const double t = sum_parts(part + (size_t)row * pstride, nparts, red4);
     if (threadIdx.x == 0) norm[row] = sqrt(t);
+}
+
+// Half-precision form: norm as k_norm_finalize (one row), the largest |r| of
+// the pass from its partial maxima, and the scale state for the next pass.
+__global__ __launch_bounds__(NT) void k_norm_finalize_f16(const double* __restrict__ part,
+                                                          const double* __restrict__ pmax, int nparts,
+                                                          double* __restrict__ norm, double* __restrict__ scl,
+                                                          const int* __restrict__ done) {
+    __shared__ double red4[4];
+    const double t = sum_parts(part, nparts, red4);
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += NT) m = fmax(m, pmax[i]);
+    const double mx = block_max_w<4>(m, red4);
+    if (threadIdx.x == 0) {
+        norm[0] = sqrt(t);
+        if (!(done && *done)) {
+            scl[0] = fp16_scale(scl[1]);
+            scl[1] = mx;
+        }
+    }
 }
 
 __global__ __launch_bounds__(NT) void k_norm_finalize_rows(const double* __restrict__ part, int pstride,
@@ -1065,6 +1181,45 @@ hipError_t launch_ir_update(int dim, bool var, const IRDesc* d, int ninst, int n
         return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_update_f16(int dim, const IRDesc* d, int ninst, int n, int sel, int flags, double* partial,
+                                int pstride, TileCfg cfg, hipStream_t s) {
+    const dim3 grid(norm_tiles(dim, n, cfg), ninst);
+    if ((int)grid.x > pstride || cfg.xp != 2) return hipErrorInvalidValue;
+    if (flags != 0 && flags != IR_NO_UPDATE) return hipErrorInvalidValue;
+    const bool nu = flags == IR_NO_UPDATE, p2 = cfg.pd == 2;
+#define MG_IR16(FLV, PDV)                                                                                     \
+    do {                                                                                                      \
+        if (dim == 2) {                                                                                       \
+            k_ir2d_p<PDV, FLV, half_t><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);             \
+        } else if (cfg.wv == 8 && cfg.by == 16) {                                                             \
+            k_ir3d_p<16, PDV, FLV, 8, half_t><<<grid, 512, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);     \
+        } else if (cfg.wv == 8 && cfg.by == 32) {                                                             \
+            k_ir3d_p<32, PDV, FLV, 8, half_t><<<grid, 512, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);     \
+        } else if (cfg.wv == 4 && cfg.by == 8) {                                                              \
+            k_ir3d_p<8, PDV, FLV, 4, half_t><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);       \
+        } else if (cfg.wv == 4 && cfg.by == 16) {                                                             \
+            k_ir3d_p<16, PDV, FLV, 4, half_t><<<grid, NT, 0, s>>>(d, sel, partial, pstride, cfg.zchunk);      \
+        } else {                                                                                              \
+            return hipErrorInvalidValue;                                                                      \
+        }                                                                                                     \
+    } while (0)
+    if (nu) {
+        if (p2) MG_IR16(IR_NO_UPDATE, 2);
+        else MG_IR16(IR_NO_UPDATE, 1);
+    } else {
+        if (p2) MG_IR16(0, 2);
+        else MG_IR16(0, 1);
+    }
+#undef MG_IR16
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_finalize_f16(const double* partial, const double* pmax, int nparts, double* norm, double* scl,
+                                    const int* done, hipStream_t s) {
+    k_norm_finalize_f16<<<1, NT, 0, s>>>(partial, pmax, nparts, norm, scl, done);
     return hipGetLastError();
 }
 

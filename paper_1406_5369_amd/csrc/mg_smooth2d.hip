@@ -8,8 +8,10 @@ namespace {
 // 2D smoothing sweep (one LDS tile per workgroup, no marching)
 // ---------------------------------------------------------------------------
 
-template <typename T, int SM, bool VAR, int BY, int FL>
+template <typename ST, int SM, bool VAR, int BY, int FL>
 __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ descs, int sel) {
+    using T = arith_t<ST>;  // arithmetic type; ST is the storage type of u, f and the coarse correction
+    static_assert(!VAR || sizeof(ST) == sizeof(T), "coefficient fields are stored in the arithmetic type");
     constexpr int flags = FL;
     const GridDesc d = descs[blockIdx.y];
     if (d.done && *gp(d.done)) return;
@@ -19,11 +21,11 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
     const int ntx = (n - 2 + TX - 1) / TX;
     const int tile = sweep_tile(sel, blockIdx.x, gridDim.x);
     const int x0 = 1 + (tile % ntx) * TX, y0 = 1 + (tile / ntx) * TY;
-    const MG_GLOBAL T* __restrict__ uin = gp((const T*)((sel & 1) ? d.t : d.u));
-    MG_GLOBAL T* __restrict__ uout = gp((T*)((sel & 1) ? d.u : d.t));
-    const MG_GLOBAL T* __restrict__ f = gp((const T*)d.f);
+    const MG_GLOBAL ST* __restrict__ uin = gp((const ST*)((sel & 1) ? d.t : d.u));
+    MG_GLOBAL ST* __restrict__ uout = gp((ST*)((sel & 1) ? d.u : d.t));
+    const MG_GLOBAL ST* __restrict__ f = gp((const ST*)d.f);
     const MG_GLOBAL T* __restrict__ kf = gp((const T*)d.k);
-    const MG_GLOBAL T* __restrict__ ec = gp((const T*)d.uc);
+    const MG_GLOBAL ST* __restrict__ ec = gp((const ST*)d.uc);
     const int nc = (n - 1) / 2 + 1;
     const T c = (T)d.c, wd = (T)d.wd, om = (T)d.omega;
 
@@ -57,7 +59,7 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
         if (ing && !(flags & SWEEP_ZERO_GUESS)) v = uin[p];
         if constexpr ((flags & SWEEP_PROLONG) != 0) {
             const int ycl = min(max(gy, 0), n - 1);
-            const MG_GLOBAL T* __restrict__ r0 = ec + (size_t)(ycl >> 1) * nc;
+            const MG_GLOBAL ST* __restrict__ r0 = ec + (size_t)(ycl >> 1) * nc;
             const T a = r0[cx], b = r0[(ycl & 1) ? nc + cx : cx];
             T sa, sb;
             if constexpr (H == 2) {
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
                 sb = xo ? bp + b : b;
             }
             const T corr = (ycl & 1) ? (xo ? T(0.25) * (sa + sb) : T(0.5) * (sa + sb)) : (xo ? T(0.5) * sa : sa);
-            if (inn) v = v + corr;
+            if (inn) v = stored<ST>(v + corr);
         }
         U[ly][lane] = v;
         if constexpr (VAR) K[ly][lane] = ing ? kf[p] : T(1);
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
                 if (inn && ((gx + gy) & 1) == 0) {
                     T ds;
                     const T r = lds_res2<T, VAR>(U, K, ly, lane, fr[m], c, ds);
-                    v = relax<T, VAR>(v, r, ds, c, wd, om);
+                    v = stored<ST>(relax<T, VAR>(v, r, ds, c, wd, om));
                 }
                 R[ly][lane] = v;
             }
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
                     const T r = lds_res2<T, VAR>(R, K, ly, lane, fr[m], c, ds);
                     v = relax<T, VAR>(v, r, ds, c, wd, om);
                 }
-                uout[(size_t)gy * n + gx] = v;
+                uout[(size_t)gy * n + gx] = (ST)v;
             }
         }
     } else {
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
             if (lane1 && ly >= 1 && ly <= BY - 2 && gx <= n - 2 && gy <= n - 2) {
                 T ds;
                 const T r = lds_res2<T, VAR>(U, K, ly, lane, fr[m], c, ds);
-                uout[(size_t)gy * n + gx] = relax<T, VAR>(U[ly][lane], r, ds, c, wd, om);
+                uout[(size_t)gy * n + gx] = (ST)relax<T, VAR>(U[ly][lane], r, ds, c, wd, om);
             }
         }
     }
@@ -139,15 +141,21 @@ hipError_t launch_smooth2d(int sm, bool var, const GridDesc* d, int sel, int fla
         case SWEEP_PROLONG: return launch_smooth2d_fl<T, SMV, VARV, SWEEP_PROLONG>(d, sel, cfg, grid, s);   \
         default: return hipErrorInvalidValue;                                                              \
     }
-    if (sm == SM_RBGS) {
-        if (var) MG_FL(SM_RBGS, true) else MG_FL(SM_RBGS, false)
+    if constexpr (sizeof(T) == 2) {  // binary16 storage: Laplacian only
+        if (var) return hipErrorInvalidValue;
+        if (sm == SM_RBGS) MG_FL(SM_RBGS, false) else MG_FL(SM_JACOBI, false)
     } else {
-        if (var) MG_FL(SM_JACOBI, true) else MG_FL(SM_JACOBI, false)
+        if (sm == SM_RBGS) {
+            if (var) MG_FL(SM_RBGS, true) else MG_FL(SM_RBGS, false)
+        } else {
+            if (var) MG_FL(SM_JACOBI, true) else MG_FL(SM_JACOBI, false)
+        }
     }
 #undef MG_FL
 }
 
 template hipError_t launch_smooth2d<double>(int, bool, const GridDesc*, int, int, TileCfg, dim3, hipStream_t);
 template hipError_t launch_smooth2d<float>(int, bool, const GridDesc*, int, int, TileCfg, dim3, hipStream_t);
+template hipError_t launch_smooth2d<half_t>(int, bool, const GridDesc*, int, int, TileCfg, dim3, hipStream_t);
 
 }  // namespace mg

@@ -32,8 +32,10 @@ namespace {
 // its x-then-y partial sum; the odd-x partner value comes from the next lane.
 // ---------------------------------------------------------------------------
 
-template <typename T, int SM, bool VAR, int BY, int PD, int FL, int WV>
+template <typename ST, int SM, bool VAR, int BY, int PD, int FL, int WV>
 struct Smooth3D {
+    using T = arith_t<ST>;  // arithmetic type; ST is the storage type of u, f and the coarse correction
+    static_assert(!VAR || sizeof(ST) == sizeof(T), "coefficient fields are stored in the arithmetic type");
     static constexpr int flags = FL;
     static constexpr int H = SM == SM_RBGS ? 2 : 1;
     static constexpr int TX = BX - 2 * H, TY = BY - 2 * H, RPT = BY / WV;  // WV wavefronts, RPT rows each
@@ -44,9 +46,9 @@ struct Smooth3D {
     T (*U)[BY][BX];   // old u of recent planes (y-neighbour exchange)
     T (*R)[BY][BX];   // red-updated u of recent planes
     T (*K)[BY][BX];   // coefficient of recent planes
-    const MG_GLOBAL T* __restrict__ uin;
-    MG_GLOBAL T* __restrict__ uout;
-    const MG_GLOBAL T* __restrict__ f;
+    const MG_GLOBAL ST* __restrict__ uin;
+    MG_GLOBAL ST* __restrict__ uout;
+    const MG_GLOBAL ST* __restrict__ f;
     const MG_GLOBAL T* __restrict__ kf;
     int n, x0, y0, z0, z1, kstart, kend;
     T c, wd, om;
@@ -67,7 +69,7 @@ struct Smooth3D {
     // into a scalar register), so each row of a plane has a scalar base
     // address and the only per-lane part is the byte offset of the lane's
     // (clamped, always in-bounds) x position.
-    unsigned xb;         // clamp(x) * sizeof(T)
+    unsigned xb;         // clamp(x) * sizeof(ST)
     unsigned minner;     // bit m: row m an inner node (x and y)
     unsigned mring;      // bit m: row m in the relaxed region of the first half-sweep
     unsigned mtile;      // bit m: row m in the output tile (second half-sweep)
@@ -76,7 +78,7 @@ struct Smooth3D {
     __device__ __forceinline__ int rowoff(int m) const { return min(max(gy(m), 0), n - 1) * n; }
 
     // coarse-grid correction (SWEEP_PROLONG)
-    const MG_GLOBAL T* __restrict__ ec;  // coarse correction, edge nc
+    const MG_GLOBAL ST* __restrict__ ec;  // coarse correction, edge nc
     int nc;
     unsigned codd;                       // bit m: row m has odd y
     unsigned cxb;                        // byte offset of the lane's coarse column
@@ -88,7 +90,7 @@ struct Smooth3D {
     __device__ __forceinline__ void init_rows() {
         pl = (size_t)n * n;
         const int xc = min(max(gx, 0), n - 1);
-        xb = (unsigned)xc * (unsigned)sizeof(T);
+        xb = (unsigned)xc * (unsigned)sizeof(ST);
         minner = mring = mtile = 0;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
@@ -99,7 +101,7 @@ struct Smooth3D {
                 mtile |= 1u << m;
         }
         if constexpr (PRO) {
-            cxb = (unsigned)(H == 2 ? xc >> 1 : (xc + 1) >> 1) * (unsigned)sizeof(T);
+            cxb = (unsigned)(H == 2 ? xc >> 1 : (xc + 1) >> 1) * (unsigned)sizeof(ST);
             codd = 0;
 #pragma unroll
             for (int m = 0; m < RPT; ++m)
@@ -110,10 +112,10 @@ struct Smooth3D {
     // Coarse plane K (clamped): for each row, the coarse row y/2 and, for odd
     // y, the row above it (the same row again for even y).
     __device__ __forceinline__ void issue_c(int K) {
-        const MG_GLOBAL T* __restrict__ cp = ec + (size_t)min(max(K, 0), nc - 1) * ((size_t)nc * nc);
+        const MG_GLOBAL ST* __restrict__ cp = ec + (size_t)min(max(K, 0), nc - 1) * ((size_t)nc * nc);
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const MG_GLOBAL T* __restrict__ row = cp + crowoff(m);
+            const MG_GLOBAL ST* __restrict__ row = cp + crowoff(m);
             craw[m][0] = ld_off(row, cxb);
             craw[m][1] = ld_off(row + (((codd >> m) & 1u) ? nc : 0), cxb);
         }
@@ -157,7 +159,7 @@ struct Smooth3D {
             }
             const int nodd = (gx & 1) + (int)((codd >> m) & 1u) + (zo ? 1 : 0);
             const T corr = nodd == 0 ? sum : (nodd == 1 ? T(0.5) * sum : (nodd == 2 ? T(0.25) * sum : T(0.125) * sum));
-            if (zin && ((minner >> m) & 1u)) un[S0][m] = un[S0][m] + corr;
+            if (zin && ((minner >> m) & 1u)) un[S0][m] = stored<ST>(un[S0][m] + corr);
         }
         if (!zo) issue_c((kk + 2) >> 1);
     }
@@ -169,7 +171,7 @@ struct Smooth3D {
     // no branch around the loads, so the prefetches stay in flight across steps.
     __device__ __forceinline__ void issue_u(int z, T (&du)[RPT], T (&dk)[RPT]) {
         const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
-        const MG_GLOBAL T* __restrict__ up = uin + zoff;
+        const MG_GLOBAL ST* __restrict__ up = uin + zoff;
         const MG_GLOBAL T* __restrict__ kp = kf + zoff;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
@@ -180,7 +182,7 @@ struct Smooth3D {
     }
     // f is read on the rows that are relaxed (not the outermost halo rows).
     __device__ __forceinline__ void issue_f(int z, T (&dst)[RPT]) {
-        const MG_GLOBAL T* __restrict__ fp = f + (size_t)min(max(z, 0), n - 1) * pl;
+        const MG_GLOBAL ST* __restrict__ fp = f + (size_t)min(max(z, 0), n - 1) * pl;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const int ly = w + WV * m;  // wave-uniform
@@ -254,7 +256,7 @@ struct Smooth3D {
                     const T kxw = VAR ? lane_prev(fxc[VAR ? S1 : 0][m]) : T(0);
                     T v = uc;
                     if (zin && ((mring >> m) & (minner >> m) & 1u) && ((gx + y + m1) & 1) == 0)
-                        v = relax_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m]);
+                        v = stored<ST>(relax_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m]));
                     ro[S1][m] = v;
                     R[S1][ly][lane] = v;
                 }
@@ -273,7 +275,7 @@ struct Smooth3D {
                         // faces of plane kk-2 (slot S2); +z faces of plane kk-3 in slot P
                         if (((gx + y + m2) & 1) == 1)
                             v = relax_at<S2, P>(R[S2], rc, ro[P][m], ro[S1][m], rw, re, ly, m, kxw, fr[S2][m]);
-                        st_off(uout + (size_t)m2 * pl + rowoff(m), xb, v);
+                        st_off(uout + (size_t)m2 * pl + rowoff(m), xb, (ST)v);
                     }
                 }
             }
@@ -288,7 +290,7 @@ struct Smooth3D {
                     const T kxw = VAR ? lane_prev(fxc[VAR ? S1 : 0][m]) : T(0);
                     if (((mring >> m) & (minner >> m) & 1u))
                         st_off(uout + (size_t)m1 * pl + rowoff(m), xb,
-                               relax_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m]));
+                               (ST)relax_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m]));
                 }
             }
         }
@@ -330,11 +332,12 @@ struct Smooth3D {
     }
 };
 
-template <typename T, int SM, bool VAR, int BY, int PD, int FL, int WV>
+template <typename ST, int SM, bool VAR, int BY, int PD, int FL, int WV>
 __global__ __launch_bounds__(64 * WV) void k_smooth3d(const GridDesc* __restrict__ descs, int sel, int zchunk) {
     const GridDesc d = descs[blockIdx.y];
     if (d.done && *gp(d.done)) return;
-    using S = Smooth3D<T, SM, VAR, BY, PD, FL, WV>;
+    using S = Smooth3D<ST, SM, VAR, BY, PD, FL, WV>;
+    using T = arith_t<ST>;
     __shared__ T U[3][BY][BX];
     __shared__ T R[SM == SM_RBGS ? 3 : 1][BY][BX];
     __shared__ T K[VAR ? 3 : 1][BY][BX];
@@ -353,11 +356,11 @@ __global__ __launch_bounds__(64 * WV) void k_smooth3d(const GridDesc* __restrict
     s.z1 = min(s.z0 + zchunk, n - 1);
     s.kstart = s.z0 - S::H;
     s.kend = s.z1 - 1 + S::H;
-    s.uin = gp((const T*)((sel & 1) ? d.t : d.u));
-    s.uout = gp((T*)((sel & 1) ? d.u : d.t));
-    s.f = gp((const T*)d.f);
+    s.uin = gp((const ST*)((sel & 1) ? d.t : d.u));
+    s.uout = gp((ST*)((sel & 1) ? d.u : d.t));
+    s.f = gp((const ST*)d.f);
     s.kf = gp((const T*)d.k);
-    s.ec = gp((const T*)d.uc);
+    s.ec = gp((const ST*)d.uc);
     s.nc = (n - 1) / 2 + 1;
     s.c = (T)d.c;
     s.wd = (T)d.wd;
@@ -394,10 +397,10 @@ hipError_t launch_smooth3d_rc(const GridDesc* d, int sel, TileCfg cfg, dim3 grid
 
 template <typename T, int SMV, bool VARV, int FL>
 hipError_t launch_smooth3d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {
-    constexpr bool wide = sizeof(T) == 4 && !VARV;
-    constexpr bool fp64var = sizeof(T) == 8 && VARV;  // two rows per thread at most
+    constexpr bool wide = sizeof(arith_t<T>) == 4 && !VARV;
+    constexpr bool fp64var = sizeof(arith_t<T>) == 8 && VARV;  // two rows per thread at most
     if (cfg.wv == 1) {  // one wavefront per tile, rows in registers: 8 rows, or 12 in FP32 without coefficients
-        if constexpr (sizeof(T) == 8 && VARV) return hipErrorInvalidValue;
+        if constexpr (sizeof(arith_t<T>) == 8 && VARV) return hipErrorInvalidValue;
         switch (cfg.by) {
             case 8: return launch_smooth3d_rc<T, SMV, VARV, FL, 8>(d, sel, cfg, grid, s);
             case 12:
@@ -440,10 +443,15 @@ hipError_t launch_smooth3d(int sm, bool var, const GridDesc* d, int sel, int fla
         case SWEEP_PROLONG: return launch_smooth3d_fl<T, SMV, VARV, SWEEP_PROLONG>(d, sel, cfg, grid, s);       \
         default: return hipErrorInvalidValue;                                                              \
     }
-    if (sm == SM_RBGS) {
-        if (var) MG_FL(SM_RBGS, true) else MG_FL(SM_RBGS, false)
+    if constexpr (sizeof(T) == 2) {  // binary16 storage: Laplacian only
+        if (var) return hipErrorInvalidValue;
+        if (sm == SM_RBGS) MG_FL(SM_RBGS, false) else MG_FL(SM_JACOBI, false)
     } else {
-        if (var) MG_FL(SM_JACOBI, true) else MG_FL(SM_JACOBI, false)
+        if (sm == SM_RBGS) {
+            if (var) MG_FL(SM_RBGS, true) else MG_FL(SM_RBGS, false)
+        } else {
+            if (var) MG_FL(SM_JACOBI, true) else MG_FL(SM_JACOBI, false)
+        }
     }
 #undef MG_FL
 }

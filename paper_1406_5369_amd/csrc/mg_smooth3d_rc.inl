@@ -17,18 +17,20 @@ namespace {
 // black nodes keep their old values in the red half-sweep.
 // ---------------------------------------------------------------------------
 
-template <typename T, int SM, bool VAR, int BY, int PD, int FL>
+template <typename ST, int SM, bool VAR, int BY, int PD, int FL>
 struct SweepRC {
+    using T = arith_t<ST>;  // arithmetic type; ST is the storage type of u, f and the coarse correction
+    static_assert(!VAR || sizeof(ST) == sizeof(T), "coefficient fields are stored in the arithmetic type");
     static constexpr int flags = FL;
     static constexpr int H = SM == SM_RBGS ? 2 : 1;
     static constexpr int TX = BX - 2 * H, TY = BY - 2 * H;
     static constexpr bool PRO = (FL & SWEEP_PROLONG) != 0;
 
-    const MG_GLOBAL T* __restrict__ uin;
-    MG_GLOBAL T* __restrict__ uout;
-    const MG_GLOBAL T* __restrict__ f;
+    const MG_GLOBAL ST* __restrict__ uin;
+    MG_GLOBAL ST* __restrict__ uout;
+    const MG_GLOBAL ST* __restrict__ f;
     const MG_GLOBAL T* __restrict__ kf;
-    const MG_GLOBAL T* __restrict__ ec;
+    const MG_GLOBAL ST* __restrict__ ec;
     int n, nc, x0, y0, z0, z1, kstart, kend;
     T c, wd, om;
     int lane, gx;
@@ -52,11 +54,11 @@ struct SweepRC {
     __device__ __forceinline__ void init() {
         pl = (size_t)n * n;
         const int xc = min(max(gx, 0), n - 1);
-        xb = (unsigned)xc * (unsigned)sizeof(T);
+        xb = (unsigned)xc * (unsigned)sizeof(ST);
         coli = gx >= 1 && gx <= n - 2;
         lane1 = lane >= 1 && lane <= BX - 2;
         lanet = lane >= 2 && lane <= BX - 3;
-        if constexpr (PRO) cxb = (unsigned)(H == 2 ? xc >> 1 : (xc + 1) >> 1) * (unsigned)sizeof(T);
+        if constexpr (PRO) cxb = (unsigned)(H == 2 ? xc >> 1 : (xc + 1) >> 1) * (unsigned)sizeof(ST);
     }
 
     // Loads are unconditional from clamped (always in-bounds) addresses and
@@ -79,11 +81,11 @@ struct SweepRC {
 
     // ---- coarse-grid correction (SWEEP_PROLONG), as in the LDS variant ----
     __device__ __forceinline__ void issue_c(int K) {
-        const MG_GLOBAL T* __restrict__ cp = ec + (size_t)min(max(K, 0), nc - 1) * ((size_t)nc * nc);
+        const MG_GLOBAL ST* __restrict__ cp = ec + (size_t)min(max(K, 0), nc - 1) * ((size_t)nc * nc);
 #pragma unroll
         for (int m = 0; m < BY; ++m) {
             const int yc = min(max(gy(m), 0), n - 1);
-            const MG_GLOBAL T* __restrict__ r0 = cp + (yc >> 1) * nc;
+            const MG_GLOBAL ST* __restrict__ r0 = cp + (yc >> 1) * nc;
             craw[m][0] = ld_off(r0, cxb);
             craw[m][1] = ld_off(r0 + ((yc & 1) ? nc : 0), cxb);
         }
@@ -119,7 +121,7 @@ struct SweepRC {
             }
             const int nodd = (gx & 1) + (gy(m) & 1) + (zo ? 1 : 0);
             const T corr = nodd == 0 ? sum : (nodd == 1 ? T(0.5) * sum : (nodd == 2 ? T(0.25) * sum : T(0.125) * sum));
-            if (zin && coli && yin(m)) un[S0][m] = un[S0][m] + corr;
+            if (zin && coli && yin(m)) un[S0][m] = stored<ST>(un[S0][m] + corr);
         }
         if (!zo) issue_c((kk + 2) >> 1);
     }
@@ -168,20 +170,20 @@ struct SweepRC {
                 const bool ok = zin && lane1 && coli;
 #pragma unroll
                 for (int m = 1; m < BY - 1; ++m) {
-                    const T v = relax_row(uo[S1], ro[S2], uo[S0], ko[S1], ko[S2], ko[S0], m, fr[S1][m]);
+                    const T v = stored<ST>(relax_row(uo[S1], ro[S2], uo[S0], ko[S1], ko[S2], ko[S0], m, fr[S1][m]));
                     if (ok && yin(m) && ((gx + gy(m) + m1) & 1) == 0) ro[S1][m] = v;
                 }
             }
             const int m2 = kk - 2;  // black plane (output)
             if (m2 >= z0 && m2 < z1) {
                 const bool ok = lanet && coli;
-                MG_GLOBAL T* __restrict__ out = uout + (size_t)m2 * pl;
+                MG_GLOBAL ST* __restrict__ out = uout + (size_t)m2 * pl;
 #pragma unroll
                 for (int m = 2; m < BY - 2; ++m) {
                     T v = ro[S2][m];
                     const T b = relax_row(ro[S2], ro[P], ro[S1], ko[S2], kbelow, ko[S1], m, fr[S2][m]);
                     if (((gx + gy(m) + m2) & 1) == 1) v = b;
-                    if (ok && yin(m)) st_off(out + rowoff(m), xb, v);
+                    if (ok && yin(m)) st_off(out + rowoff(m), xb, (ST)v);
                 }
             }
             if constexpr (VAR) {
@@ -192,11 +194,11 @@ struct SweepRC {
             const int m1 = kk - 1;
             if (m1 >= z0 && m1 < z1) {
                 const bool ok = lane1 && coli;
-                MG_GLOBAL T* __restrict__ out = uout + (size_t)m1 * pl;
+                MG_GLOBAL ST* __restrict__ out = uout + (size_t)m1 * pl;
 #pragma unroll
                 for (int m = 1; m < BY - 1; ++m) {
                     const T v = relax_row(uo[S1], uo[S2], uo[S0], ko[S1], ko[S2], ko[S0], m, fr[S1][m]);
-                    if (ok && yin(m)) st_off(out + rowoff(m), xb, v);
+                    if (ok && yin(m)) st_off(out + rowoff(m), xb, (ST)v);
                 }
             }
         }
@@ -231,11 +233,12 @@ struct SweepRC {
     }
 };
 
-template <typename T, int SM, bool VAR, int BY, int PD, int FL>
+template <typename ST, int SM, bool VAR, int BY, int PD, int FL>
 __global__ __launch_bounds__(64) void k_smooth3d_rc(const GridDesc* __restrict__ descs, int sel, int zchunk) {
     const GridDesc d = descs[blockIdx.y];
     if (d.done && *gp(d.done)) return;
-    using S = SweepRC<T, SM, VAR, BY, PD, FL>;
+    using S = SweepRC<ST, SM, VAR, BY, PD, FL>;
+    using T = arith_t<ST>;
     S s;
     const int n = d.n;
     const int ntx = (n - 2 + S::TX - 1) / S::TX, nty = (n - 2 + S::TY - 1) / S::TY;
@@ -249,11 +252,11 @@ __global__ __launch_bounds__(64) void k_smooth3d_rc(const GridDesc* __restrict__
     s.z1 = min(s.z0 + zchunk, n - 1);
     s.kstart = s.z0 - S::H;
     s.kend = s.z1 - 1 + S::H;
-    s.uin = gp((const T*)((sel & 1) ? d.t : d.u));
-    s.uout = gp((T*)((sel & 1) ? d.u : d.t));
-    s.f = gp((const T*)d.f);
+    s.uin = gp((const ST*)((sel & 1) ? d.t : d.u));
+    s.uout = gp((ST*)((sel & 1) ? d.u : d.t));
+    s.f = gp((const ST*)d.f);
     s.kf = gp((const T*)d.k);
-    s.ec = gp((const T*)d.uc);
+    s.ec = gp((const ST*)d.uc);
     s.c = (T)d.c;
     s.wd = (T)d.wd;
     s.om = (T)d.omega;

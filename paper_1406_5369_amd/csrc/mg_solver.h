@@ -106,7 +106,11 @@ struct mg_ctx {
     mg::Levels L32;
     std::vector<mg::Group> G32;
     mg::TailPlan tail32;
+    // FP32_IR and FP16_IR share these members: L32 / G32 / tail32 / tl32 hold
+    // the hierarchy of the refinement's cycles, in FP32 or binary16 (L32.elem)
     // FP64 refinement state
+    double* d_scl = nullptr;   // FP16_IR: {scale of the correction, largest |r| of the last pass}
+    double* d_pmax = nullptr;  // FP16_IR: partial maxima of |r| (pstride)
     mg::IRDesc* d_ir = nullptr;
     mg::IRDesc h_ir{};
     double* u64_scratch = nullptr;

@@ -68,6 +68,7 @@ hipError_t launch_smooth(int dim, int sm, bool var, const GridDesc* d, int ninst
 }
 template hipError_t launch_smooth<double>(int, int, bool, const GridDesc*, int, int, int, int, TileCfg, hipStream_t);
 template hipError_t launch_smooth<float>(int, int, bool, const GridDesc*, int, int, int, int, TileCfg, hipStream_t);
+template hipError_t launch_smooth<half_t>(int, int, bool, const GridDesc*, int, int, int, int, TileCfg, hipStream_t);
 
 namespace {
 
@@ -165,5 +166,7 @@ template hipError_t vcycle<double>(const Problem&, const std::vector<Group>&, bo
                                    hipStream_t, hipEvent_t*, int*, int, const TailPlan*);
 template hipError_t vcycle<float>(const Problem&, const std::vector<Group>&, bool, const std::vector<Tiles>&,
                                   hipStream_t, hipEvent_t*, int*, int, const TailPlan*);
+template hipError_t vcycle<half_t>(const Problem&, const std::vector<Group>&, bool, const std::vector<Tiles>&,
+                                   hipStream_t, hipEvent_t*, int*, int, const TailPlan*);
 
 }  // namespace mg

@@ -80,8 +80,10 @@ __device__ __forceinline__ int tail_inner(int n) {
     return DIM == 2 ? (n - 2) * (n - 2) : (n - 2) * (n - 2) * (n - 2);
 }
 
-// One smoothing sweep of a level (arrays already offset to the level).
-template <typename T, int DIM, int SM, bool VAR>
+// One smoothing sweep of a level (arrays already offset to the level).  The
+// LDS arrays hold arithmetic-type values; every iterate value is rounded to
+// the storage type ST where the level kernels would store it.
+template <typename ST, typename T, int DIM, int SM, bool VAR>
 __device__ void tail_sweep(T* u, const T* f, T* w, const T* k, const Lvl<T>& L) {
     const int cnt = tail_inner<DIM>(L.n);
     if constexpr (SM == SM_RBGS) {
@@ -92,7 +94,7 @@ __device__ void tail_sweep(T* u, const T* f, T* w, const T* k, const Lvl<T>& L) 
                 if (cl != colour) continue;
                 T ds;
                 const T r = tail_res<T, DIM, VAR>(u, f, k, L.n, L.c, p, ds);
-                u[p] = relax<T, VAR>(u[p], r, ds, L.c, L.wd, L.om);
+                u[p] = stored<ST>(relax<T, VAR>(u[p], r, ds, L.c, L.wd, L.om));
             }
             __syncthreads();
         }
@@ -102,7 +104,7 @@ __device__ void tail_sweep(T* u, const T* f, T* w, const T* k, const Lvl<T>& L) 
             const int p = tail_node<DIM>(q, L.n, cl);
             T ds;
             const T r = tail_res<T, DIM, VAR>(u, f, k, L.n, L.c, p, ds);
-            w[p] = relax<T, VAR>(u[p], r, ds, L.c, L.wd, L.om);
+            w[p] = stored<ST>(relax<T, VAR>(u[p], r, ds, L.c, L.wd, L.om));
         }
         __syncthreads();
         for (int q = threadIdx.x; q < cnt; q += TNT) {
@@ -138,8 +140,9 @@ __device__ __forceinline__ T tail_fw(const T* R, int nf, int fp) {
     }
 }
 
-template <typename T, int DIM, int SM, bool VAR, int NMAX>
+template <typename ST, int DIM, int SM, bool VAR, int NMAX>
 __global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs, int nu1, int nu2) {
+    using T = arith_t<ST>;
     constexpr int TOT = tail_nodes(DIM, NMAX);
     __shared__ T Us[TOT];
     __shared__ T Fs[TOT];
@@ -170,11 +173,11 @@ __global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs
     // coefficients of all levels come from device memory
     const int n0 = td.lv[0].n;
     const int np0 = DIM == 2 ? n0 * n0 : n0 * n0 * n0;
-    const MG_GLOBAL T* __restrict__ f0 = gp((const T*)td.lv[0].f);
+    const MG_GLOBAL ST* __restrict__ f0 = gp((const ST*)td.lv[0].f);
     for (int p = threadIdx.x; p < tot; p += TNT) {
         Us[p] = T(0);
         Ws[p] = T(0);
-        Fs[p] = p < np0 ? f0[p] : T(0);
+        Fs[p] = p < np0 ? (T)f0[p] : T(0);
     }
     if constexpr (VAR) {
         for (int j = 0; j < nl; ++j) {
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs
         T* w = Ws + lv.off;
         const T* f = Fs + lv.off;
         const T* k = Ks + (VAR ? lv.off : 0);
-        for (int s = 0; s < nu1; ++s) tail_sweep<T, DIM, SM, VAR>(u, f, w, k, lv);
+        for (int s = 0; s < nu1; ++s) tail_sweep<ST, T, DIM, SM, VAR>(u, f, w, k, lv);
         const int cnt = tail_inner<DIM>(lv.n);
         for (int q = threadIdx.x; q < cnt; q += TNT) {
             int cl;
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs
             int cl;
             const int P = tail_node<DIM>(q, nc, cl);
             const int I = P % nc, J = (P / nc) % nc, K = DIM == 2 ? 0 : P / (nc * nc);
-            fc[P] = tail_fw<T, DIM>(w, nf, ((2 * K) * nf + 2 * J) * nf + 2 * I);
+            fc[P] = stored<ST>(tail_fw<T, DIM>(w, nf, ((2 * K) * nf + 2 * J) * nf + 2 * I));
         }
         __syncthreads();
     }
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs
         } else {
             diag = lv.c * (DIM == 2 ? T(4) : T(6));
         }
-        Us[lv.off + p] = Fs[lv.off + p] / diag;
+        Us[lv.off + p] = stored<ST>(Fs[lv.off + p] / diag);
     }
     __syncthreads();
     // ascending leg
@@ -251,33 +254,35 @@ __global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs
             const int p = tail_node<DIM>(q, n, cl);
             const int i = p % n, jj = (p / n) % n, kk = DIM == 2 ? 0 : p / (n * n);
             const T corr = DIM == 2 ? interp2<T>(uc, nc, i, jj) : interp3<T>(uc, nc, i, jj, kk);
-            u[p] = u[p] + corr;
+            u[p] = stored<ST>(u[p] + corr);
         }
         __syncthreads();
-        for (int s = 0; s < nu2; ++s) tail_sweep<T, DIM, SM, VAR>(u, f, w, k, lv);
+        for (int s = 0; s < nu2; ++s) tail_sweep<ST, T, DIM, SM, VAR>(u, f, w, k, lv);
     }
     // the tail's finest iterate back to device memory (inner nodes; its
     // boundary there is zero already)
-    MG_GLOBAL T* __restrict__ u0 = gp((T*)td.lv[0].u);
+    MG_GLOBAL ST* __restrict__ u0 = gp((ST*)td.lv[0].u);
     const int cnt = tail_inner<DIM>(n0);
     for (int q = threadIdx.x; q < cnt; q += TNT) {
         int cl;
         const int p = tail_node<DIM>(q, n0, cl);
-        u0[p] = Us[p];
+        u0[p] = (ST)Us[p];
     }
 }
 
 }  // namespace
 
+// The tail's LDS holds arithmetic-type values: 4 bytes for FP32 and binary16
+// fields, 8 for FP64.
 int tail_max_edge(int dim, int elem) {
-    if (dim == 2) return elem == 4 ? 65 : 33;
-    return elem == 4 ? 17 : 9;
+    if (dim == 2) return elem <= 4 ? 65 : 33;
+    return elem <= 4 ? 17 : 9;
 }
 
 template <typename T>
 hipError_t launch_tail(int dim, int sm, bool var, const TailDesc* d, int ninst, int nu1, int nu2, hipStream_t s) {
     if (ninst <= 0) return hipSuccess;
-    constexpr bool F = sizeof(T) == 4;
+    constexpr bool F = sizeof(arith_t<T>) == 4;
 #define MG_TAIL(DIMV, NMAXV)                                                                                     \
     do {                                                                                                      \
         if (sm == SM_RBGS) {                                                                                  \
@@ -288,6 +293,17 @@ hipError_t launch_tail(int dim, int sm, bool var, const TailDesc* d, int ninst, 
             else k_tail<T, DIMV, SM_JACOBI, false, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2);                \
         }                                                                                                     \
     } while (0)
+    if constexpr (sizeof(T) == 2) {  // binary16 storage: Laplacian only
+        if (var) return hipErrorInvalidValue;
+        if (dim == 2) {
+            if (sm == SM_RBGS) k_tail<T, 2, SM_RBGS, false, 65><<<ninst, TNT, 0, s>>>(d, nu1, nu2);
+            else k_tail<T, 2, SM_JACOBI, false, 65><<<ninst, TNT, 0, s>>>(d, nu1, nu2);
+        } else {
+            if (sm == SM_RBGS) k_tail<T, 3, SM_RBGS, false, 17><<<ninst, TNT, 0, s>>>(d, nu1, nu2);
+            else k_tail<T, 3, SM_JACOBI, false, 17><<<ninst, TNT, 0, s>>>(d, nu1, nu2);
+        }
+        return hipGetLastError();
+    }
     if (dim == 2) MG_TAIL(2, (F ? 65 : 33));
     else MG_TAIL(3, (F ? 17 : 9));
 #undef MG_TAIL
@@ -296,5 +312,6 @@ hipError_t launch_tail(int dim, int sm, bool var, const TailDesc* d, int ninst, 
 
 template hipError_t launch_tail<double>(int, int, bool, const TailDesc*, int, int, int, hipStream_t);
 template hipError_t launch_tail<float>(int, int, bool, const TailDesc*, int, int, int, hipStream_t);
+template hipError_t launch_tail<half_t>(int, int, bool, const TailDesc*, int, int, int, hipStream_t);
 
 }  // namespace mg

@@ -35,8 +35,9 @@ __device__ __forceinline__ T fw3(const T (*Rb)[BX], const T (*Rc)[BX], const T (
     return ((T(0.125) * Rc[ly][lx] + T(0.0625) * faces) + T(0.03125) * edges) + T(0.015625) * corners;
 }
 
-template <typename T, bool VAR, int BY>
+template <typename ST, bool VAR, int BY>
 __global__ __launch_bounds__(NT) void k_restrict2d(const GridDesc* __restrict__ descs, int sel) {
+    using T = arith_t<ST>;
     const GridDesc d = descs[blockIdx.y];
     if (d.done && *gp(d.done)) return;
     constexpr int CX = (BX - 3) / 2, CY = (BY - 3) / 2, RPT = BY / 4;
@@ -45,10 +46,10 @@ __global__ __launch_bounds__(NT) void k_restrict2d(const GridDesc* __restrict__ 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int X0 = 1 + (tile % ncx) * CX, Y0 = 1 + (tile / ncx) * CY;
     const int fx0 = 2 * X0 - 2, fy0 = 2 * Y0 - 2;
-    const MG_GLOBAL T* __restrict__ u = gp((const T*)(sel ? d.t : d.u));
-    const MG_GLOBAL T* __restrict__ f = gp((const T*)d.f);
+    const MG_GLOBAL ST* __restrict__ u = gp((const ST*)(sel ? d.t : d.u));
+    const MG_GLOBAL ST* __restrict__ f = gp((const ST*)d.f);
     const MG_GLOBAL T* __restrict__ kf = gp((const T*)d.k);
-    MG_GLOBAL T* __restrict__ fc = gp((T*)d.fc);
+    MG_GLOBAL ST* __restrict__ fc = gp((ST*)d.fc);
     const T c = (T)d.c;
     __shared__ T U[BY][BX];
     __shared__ T Rr[BY][BX];
@@ -63,9 +64,9 @@ __global__ __launch_bounds__(NT) void k_restrict2d(const GridDesc* __restrict__ 
         const bool ing = gx < nf && gy < nf && ly <= 2 * CY + 2 && lane <= 2 * CX + 2;
         const bool inn = gx >= 1 && gx <= nf - 2 && gy >= 1 && gy <= nf - 2;
         const size_t p = (size_t)gy * nf + gx;
-        U[ly][lane] = ing ? u[p] : T(0);
+        U[ly][lane] = ing ? (T)u[p] : T(0);
         if constexpr (VAR) K[ly][lane] = ing ? kf[p] : T(1);
-        fr[m] = (inn && lres && ly >= 1 && ly <= 2 * CY + 1) ? f[p] : T(0);
+        fr[m] = (inn && lres && ly >= 1 && ly <= 2 * CY + 1) ? (T)f[p] : T(0);
     }
     __syncthreads();
 #pragma unroll
@@ -80,15 +81,16 @@ __global__ __launch_bounds__(NT) void k_restrict2d(const GridDesc* __restrict__ 
     __syncthreads();
     for (int t = threadIdx.x; t < CX * CY; t += NT) {
         const int X = X0 + t % CX, Y = Y0 + t / CX;
-        if (X <= nc - 2 && Y <= nc - 2) fc[(size_t)Y * nc + X] = fw2<T>(Rr, 2 * (Y - Y0) + 2, 2 * (X - X0) + 2);
+        if (X <= nc - 2 && Y <= nc - 2) fc[(size_t)Y * nc + X] = (ST)fw2<T>(Rr, 2 * (Y - Y0) + 2, 2 * (X - X0) + 2);
     }
 }
 
 // 3D: marching over fine planes; step m publishes u plane m, computes the
 // residual of plane m-1 and, once planes 2K-1..2K+1 are in the residual ring,
 // the coarse plane K.
-template <typename T, bool VAR, int BY>
+template <typename ST, bool VAR, int BY>
 __global__ __launch_bounds__(NT) void k_restrict3d(const GridDesc* __restrict__ descs, int sel, int zchunk) {
+    using T = arith_t<ST>;
     const GridDesc d = descs[blockIdx.y];
     if (d.done && *gp(d.done)) return;
     constexpr int CX = (BX - 3) / 2, CY = (BY - 3) / 2, RPT = BY / 4;
@@ -98,10 +100,10 @@ __global__ __launch_bounds__(NT) void k_restrict3d(const GridDesc* __restrict__ 
     const int tx = tile % ncx, t2 = tile / ncx, ty = t2 % ncy, tz = t2 / ncy;
     const int X0 = 1 + tx * CX, Y0 = 1 + ty * CY, Z0 = 1 + tz * zchunk, Z1 = min(Z0 + zchunk, nc - 1);
     const int fx0 = 2 * X0 - 2, fy0 = 2 * Y0 - 2;
-    const MG_GLOBAL T* __restrict__ u = gp((const T*)(sel ? d.t : d.u));
-    const MG_GLOBAL T* __restrict__ f = gp((const T*)d.f);
+    const MG_GLOBAL ST* __restrict__ u = gp((const ST*)(sel ? d.t : d.u));
+    const MG_GLOBAL ST* __restrict__ f = gp((const ST*)d.f);
     const MG_GLOBAL T* __restrict__ kf = gp((const T*)d.k);
-    MG_GLOBAL T* __restrict__ fc = gp((T*)d.fc);
+    MG_GLOBAL ST* __restrict__ fc = gp((ST*)d.fc);
     const T c = (T)d.c;
     __shared__ T U[3][BY][BX];
     __shared__ T Rr[3][BY][BX];
@@ -173,8 +175,8 @@ __global__ __launch_bounds__(NT) void k_restrict3d(const GridDesc* __restrict__ 
             for (int t = threadIdx.x; t < CX * CY; t += NT) {
                 const int X = X0 + t % CX, Y = Y0 + t / CX;
                 if (X <= nc - 2 && Y <= nc - 2)
-                    fc[((size_t)Kz * nc + Y) * nc + X] = fw3<T>(Rr[sb], Rr[sc], Rr[s1], 2 * (Y - Y0) + 2,
-                                                               2 * (X - X0) + 2);
+                    fc[((size_t)Kz * nc + Y) * nc + X] = (ST)fw3<T>(Rr[sb], Rr[sc], Rr[s1], 2 * (Y - Y0) + 2,
+                                                                   2 * (X - X0) + 2);
             }
         }
     };
@@ -196,8 +198,9 @@ __global__ __launch_bounds__(NT) void k_restrict3d(const GridDesc* __restrict__ 
 // wave, so only the x parity varies across lanes.  The sum is formed along x,
 // then y, then z, and scaled by 1/2 per odd axis, which is the order of the
 // bilinear / trilinear formulas (odd axes taken in x, y, z order).
-template <typename T, int DIM>
+template <typename ST, int DIM>
 __global__ __launch_bounds__(NT) void k_prolong(const GridDesc* __restrict__ descs, int sel) {
+    using T = arith_t<ST>;
     const GridDesc d = descs[blockIdx.y];
     if (d.done && *gp(d.done)) return;
     const int n = d.n, nc = (n - 1) / 2 + 1, m = n - 2;
@@ -206,12 +209,12 @@ __global__ __launch_bounds__(NT) void k_prolong(const GridDesc* __restrict__ des
     if (row >= nrows) return;
     const int j = 1 + row % m, k = DIM == 2 ? 0 : 1 + row / m;
     const int oj = j & 1, ok = k & 1;
-    MG_GLOBAL T* __restrict__ u = gp((T*)(sel ? d.t : d.u)) + ((size_t)k * n + j) * n;
-    const MG_GLOBAL T* __restrict__ ec = gp((const T*)d.uc);
-    const MG_GLOBAL T* __restrict__ q00 = ec + ((size_t)(k >> 1) * nc + (j >> 1)) * nc;  // rows (J0, K0)
-    const MG_GLOBAL T* __restrict__ q10 = q00 + (size_t)oj * nc;                      // (J1, K0)
-    const MG_GLOBAL T* __restrict__ q01 = q00 + (size_t)ok * nc * nc;                 // (J0, K1)
-    const MG_GLOBAL T* __restrict__ q11 = q01 + (size_t)oj * nc;                      // (J1, K1)
+    MG_GLOBAL ST* __restrict__ u = gp((ST*)(sel ? d.t : d.u)) + ((size_t)k * n + j) * n;
+    const MG_GLOBAL ST* __restrict__ ec = gp((const ST*)d.uc);
+    const MG_GLOBAL ST* __restrict__ q00 = ec + ((size_t)(k >> 1) * nc + (j >> 1)) * nc;  // rows (J0, K0)
+    const MG_GLOBAL ST* __restrict__ q10 = q00 + (size_t)oj * nc;                      // (J1, K0)
+    const MG_GLOBAL ST* __restrict__ q01 = q00 + (size_t)ok * nc * nc;                 // (J0, K1)
+    const MG_GLOBAL ST* __restrict__ q11 = q01 + (size_t)oj * nc;                      // (J1, K1)
     const int lane = threadIdx.x & 63;
     for (int i = 1 + lane; i <= m; i += 64) {
         const int oi = i & 1, i0 = i >> 1, i1 = i0 + oi;
@@ -233,18 +236,19 @@ __global__ __launch_bounds__(NT) void k_prolong(const GridDesc* __restrict__ des
         }
         const int nodd = oi + oj + ok;
         const T corr = nodd == 0 ? s : (nodd == 1 ? T(0.5) * s : (nodd == 2 ? T(0.25) * s : T(0.125) * s));
-        u[i] = u[i] + corr;
+        u[i] = (ST)((T)u[i] + corr);
     }
 }
 
 // n = 3: one unknown, u = f / diag (diag = c*2d, or c*dsum).
-template <typename T, int DIM, bool VAR>
+template <typename ST, int DIM, bool VAR>
 __global__ void k_coarsest(const GridDesc* __restrict__ descs) {
+    using T = arith_t<ST>;
     const GridDesc d = descs[blockIdx.x];
     if (threadIdx.x != 0 || (d.done && *gp(d.done))) return;
     const int p = DIM == 2 ? 4 : 13;
-    MG_GLOBAL T* u = gp((T*)d.u);
-    const MG_GLOBAL T* f = gp((const T*)d.f);
+    MG_GLOBAL ST* u = gp((ST*)d.u);
+    const MG_GLOBAL ST* f = gp((const ST*)d.f);
     const T c = (T)d.c;
     T diag;
     if constexpr (VAR) {
@@ -264,7 +268,7 @@ __global__ void k_coarsest(const GridDesc* __restrict__ descs) {
     } else {
         diag = c * (DIM == 2 ? T(4) : T(6));
     }
-    u[p] = f[p] / diag;
+    u[p] = (ST)((T)f[p] / diag);
 }
 
 template <typename T>
@@ -281,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_zero_u(const GridDesc* __restrict__ desc
     const GridDesc d = descs[blockIdx.y];
     if (d.done && *gp(d.done)) return;
     MG_GLOBAL T* __restrict__ u = gp((T*)d.u);
-    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) u[q] = T(0);
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) u[q] = (T)0;
 }
 
 __global__ __launch_bounds__(NT) void k_copy_bytes(uint4* __restrict__ dst, const uint4* __restrict__ src,
@@ -321,6 +325,14 @@ hipError_t launch_restrict(int dim, bool var, const GridDesc* d, int ninst, int 
                            hipStream_t s) {
     if (nf < 5 || ninst <= 0) return hipErrorInvalidValue;
     const dim3 grid(restrict_tiles(dim, nf, cfg), ninst);
+    if constexpr (sizeof(T) == 2) {  // binary16 storage: Laplacian only
+        if (dim == 2) {
+            MG_BY_SWITCH(cfg.by, (k_restrict2d<T, false, BY><<<grid, NT, 0, s>>>(d, sel)))
+        } else {
+            MG_BY_SWITCH(cfg.by, (k_restrict3d<T, false, BY><<<grid, NT, 0, s>>>(d, sel, cfg.zchunk)))
+        }
+        return var ? hipErrorInvalidValue : hipGetLastError();
+    }
     if (dim == 2) {
         if (var) {
             MG_BY_SWITCH(cfg.by, (k_restrict2d<T, true, BY><<<grid, NT, 0, s>>>(d, sel)))
@@ -349,6 +361,12 @@ hipError_t launch_prolong(int dim, const GridDesc* d, int ninst, int nf, int sel
 
 template <typename T>
 hipError_t launch_coarsest(int dim, bool var, const GridDesc* d, int ninst, hipStream_t s) {
+    if constexpr (sizeof(T) == 2) {  // binary16 storage: Laplacian only
+        if (var) return hipErrorInvalidValue;
+        if (dim == 2) k_coarsest<T, 2, false><<<ninst, 64, 0, s>>>(d);
+        else k_coarsest<T, 3, false><<<ninst, 64, 0, s>>>(d);
+        return hipGetLastError();
+    }
     if (dim == 2) {
         if (var) k_coarsest<T, 2, true><<<ninst, 64, 0, s>>>(d);
         else k_coarsest<T, 2, false><<<ninst, 64, 0, s>>>(d);
@@ -392,6 +410,7 @@ hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream
     template hipError_t launch_zero_u<T>(int, const GridDesc*, int, int, hipStream_t);
 MG_INST(double)
 MG_INST(float)
+MG_INST(half_t)
 #undef MG_INST
 
 }  // namespace mg

@@ -50,7 +50,7 @@ def kernel_source_hash() -> str:
 def sweep_kernel(dim: int, word: int, by: int, pd: int, var: bool = False, wv: int = 4) -> str:
     """Demangled name of a plain (not zero-guess, no fused correction) RBGS
     sweep with the given tile height, prefetch depth and wavefronts."""
-    t = "float" if word == 4 else "double"
+    t = {2: "_Float16", 4: "float", 8: "double"}[word]
     v = "true" if var else "false"
     if dim == 2:
         return f"mg::k_smooth2d<{t}, 0, {v}, {by}, 0>"
@@ -59,15 +59,18 @@ def sweep_kernel(dim: int, word: int, by: int, pd: int, var: bool = False, wv: i
     return f"mg::k_smooth3d<{t}, 0, {v}, {by}, {pd}, 0, {wv}>"
 
 
-def pass_kernel(dim: int, by: int, pd: int, var: bool = False, ir: bool = True, wv: int = 4, pairs: int = 0) -> str:
+def pass_kernel(dim: int, by: int, pd: int, var: bool = False, ir: bool = True, wv: int = 4, pairs: int = 0,
+                word: int = 4) -> str:
     """Demangled name of the finest-level FP64 refinement pass (updating, as
     in a refinement step) or FP64 norm pass with the given tile height,
-    prefetch depth and wavefronts (pairs: the 3D variant with two nodes per lane)."""
+    prefetch depth and wavefronts (pairs: the variant with two nodes per lane,
+    whose correction / residual words are float, or binary16 with word 2)."""
     v = "true" if var else "false"
+    e = "_Float16" if word == 2 else "float"
     if pairs and dim == 3:
-        return f"mg::k_ir3d_p<{by}, {pd}, 0, {wv}>" if ir else f"mg::k_norm3d_p<{by}, {pd}, {wv}>"
+        return f"mg::k_ir3d_p<{by}, {pd}, 0, {wv}, {e}>" if ir else f"mg::k_norm3d_p<{by}, {pd}, {wv}>"
     if pairs:
-        return f"mg::k_ir2d_p<{pd}, 0>" if ir else f"mg::k_norm2d_p<{pd}>"
+        return f"mg::k_ir2d_p<{pd}, 0, {e}>" if ir else f"mg::k_norm2d_p<{pd}>"
     if ir:
         return f"mg::k_ir2d<{v}, {by}, 0>" if dim == 2 else f"mg::k_ir3d<{v}, {by}, {pd}, 0, {wv}>"
     return f"mg::k_norm2d<{v}, {by}>" if dim == 2 else f"mg::k_norm3d<{v}, {by}, {pd}, {wv}>"

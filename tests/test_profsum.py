@@ -28,11 +28,13 @@ def test_sweep_blocks():
 
 
 def test_kernel_names():
-    assert profsum.pass_kernel(3, 16, 2, ir=True, wv=8, pairs=1) == "mg::k_ir3d_p<16, 2, 0, 8>"
+    assert profsum.pass_kernel(3, 16, 2, ir=True, wv=8, pairs=1) == "mg::k_ir3d_p<16, 2, 0, 8, float>"
+    assert profsum.pass_kernel(3, 16, 2, ir=True, wv=8, pairs=1, word=2) == "mg::k_ir3d_p<16, 2, 0, 8, _Float16>"
     assert profsum.pass_kernel(3, 8, 1, ir=False, wv=4, pairs=1) == "mg::k_norm3d_p<8, 1, 4>"
     assert profsum.pass_kernel(3, 16, 1, var=True, ir=True, wv=4) == "mg::k_ir3d<true, 16, 1, 0, 4>"
-    assert profsum.pass_kernel(2, 16, 2, ir=True, pairs=1) == "mg::k_ir2d_p<2, 0>"
+    assert profsum.pass_kernel(2, 16, 2, ir=True, pairs=1) == "mg::k_ir2d_p<2, 0, float>"
     assert profsum.pass_kernel(2, 16, 1, ir=False, pairs=1) == "mg::k_norm2d_p<1>"
     assert profsum.sweep_kernel(3, 4, 16, 1, wv=4) == "mg::k_smooth3d<float, 0, false, 16, 1, 0, 4>"
     assert profsum.sweep_kernel(3, 4, 8, 2, wv=1) == "mg::k_smooth3d_rc<float, 0, false, 8, 2, 0>"
     assert profsum.sweep_kernel(3, 8, 32, 1, wv=8) == "mg::k_smooth3d<double, 0, false, 32, 1, 0, 8>"
+    assert profsum.sweep_kernel(3, 2, 16, 2, wv=8) == "mg::k_smooth3d<_Float16, 0, false, 16, 2, 0, 8>"
