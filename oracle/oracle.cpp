@@ -497,17 +497,21 @@ void smooth(Hierarchy<S>& H, int l, S* u, const S* f, int post = 0) {
         jacobi_sweep(g, u, f, H.tmp);
 }
 
-/* <a, b> over inner nodes, products and sum in FP64 */
+/* <a, b> over inner nodes, products and sums in FP64: each x-row summed from
+ * left to right, the row sums added in row order (k, then j) */
 template <typename S>
 double dot_inner(int dim, int n, const S* a, const S* b) {
     double s = 0.0;
     const int k0 = dim == 3 ? 1 : 0, k1 = dim == 3 ? n - 1 : 1;
     for (int k = k0; k < k1; ++k)
-        for (int j = 1; j < n - 1; ++j)
+        for (int j = 1; j < n - 1; ++j) {
+            double row = 0.0;
             for (int i = 1; i < n - 1; ++i) {
                 const idx_t p = at(dim, n, i, j, k);
-                s += (double)a[p] * (double)b[p];
+                row += (double)a[p] * (double)b[p];
             }
+            s += row;
+        }
     return s;
 }
 
