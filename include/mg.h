@@ -56,8 +56,15 @@ enum mg_operator {
 };
 enum mg_bc { MG_BC_DIRICHLET_ZERO = 0 };
 enum mg_smoother {
-    MG_SMOOTH_RBGS = 0,    /* red-black Gauss-Seidel, red ((i+j[+k]) even) first, Section 2.4 */
-    MG_SMOOTH_WJACOBI = 1  /* weighted Jacobi, Section 2.3; omega 0.8 in Table 2 */
+    MG_SMOOTH_RBGS = 0,     /* red-black Gauss-Seidel, red ((i+j[+k]) even) first, Section 2.4 */
+    MG_SMOOTH_WJACOBI = 1,  /* weighted Jacobi, Section 2.3; omega 0.8 in Table 2 */
+    MG_SMOOTH_RBGS_SYM = 2  /* symmetric red-black Gauss-Seidel (Table 1's red-black variants): red first
+                               before the coarse-grid correction, black first after it */
+};
+enum mg_cycle {
+    MG_CYCLE_V = 0,  /* Algorithm 1: one recursive call per level */
+    MG_CYCLE_W = 1,  /* two recursive calls per level (the second from the first's coarse iterate) */
+    MG_CYCLE_F = 2   /* an F-cycle call followed by a V-cycle call per level */
 };
 enum mg_precision {
     MG_PREC_FP64 = 0,     /* every step in FP64 */
@@ -83,6 +90,14 @@ typedef struct mg_params {
     double omega;    /* relaxation weight; <= 0 selects the paper's value (1.0 RBGS, 0.8 Jacobi) */
     int nu1, nu2;    /* pre- and post-smoothing sweeps (paper: 2, 2); 0..16 */
     int precision;   /* enum mg_precision */
+    int cycle;       /* enum mg_cycle (0: the V-cycle of Algorithm 1) */
+    int coarse_n;    /* edge of the coarsest level, 2^c + 1 with 3 <= coarse_n <= n (0 or 3: the single
+                        unknown of the 3-node grid, solved exactly); larger: conjugate gradients there
+                        (Algorithm 1: "direct solver or CG"), from a zero iterate, with inner products
+                        in FP64 (each x-row summed in order, then the rows); at most 33 (2D) / 9 (3D)
+                        with MG_PREC_FP64, 65 / 17 otherwise (MG_ENOTSUP beyond) */
+    int cg_iters;    /* CG steps on a coarsest level with coarse_n > 3 (0: 4 (coarse_n - 1)); fewer only
+                        if the residual or p^T A p becomes zero */
 } mg_params;
 
 /* Build the level hierarchy n, (n-1)/2+1, ..., 3 (Section 2.2 coarsening by 2;
@@ -154,7 +169,9 @@ const char* mg_strerror(int code);
  * ------------------------------------------------------------------------- */
 
 /* One smoothing sweep (Section 2.4 GaussSeidel / Section 2.3 Jacobi) from u_in
- * to u_out (out of place; u_out's boundary is not written).  zero_guess != 0
+ * to u_out (out of place; u_out's boundary is not written); smoother 2 is a
+ * red-black sweep that relaxes black first (the post-smoothing sweep of
+ * MG_SMOOTH_RBGS_SYM).  zero_guess != 0
  * treats u_in as identically zero (u_in may then be NULL).  ec, if not NULL,
  * is the coarse-grid correction ((n-1)/2+1 nodes per axis) added by
  * interpolation to u_in before the sweep (Algorithm 1: coarse-grid correction
@@ -173,6 +190,13 @@ int mg_level_prolong_correct(int dim, int n, int dtype, void* u, const void* ec,
 
 /* Coarsest grid (n = 3): u = f / diag at the single inner node. */
 int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f, void* stream);
+
+/* Conjugate gradients on a coarsest grid of n = 2^c + 1 nodes per axis
+ * (mg_params.coarse_n): 'iters' steps (0: 4 (n - 1)) from u = 0 on A u = f;
+ * u's boundary is written with zeros.  n at most 33 (2D) / 9 (3D) for dtype 0,
+ * 65 / 17 otherwise (MG_ENOTSUP beyond). */
+int mg_level_coarsest_cg(int dim, int n, int dtype, const void* k, void* u, const void* f, int iters,
+                         void* stream);
 
 /* dtype 2 in the four calls above: binary16 arrays (u, f, the coarse arrays),
  * arithmetic in FP32, each value the method stores rounded to binary16 (the

@@ -25,7 +25,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mg.h")
 MG_OK, MG_ENOTCONV, MG_EINVAL, MG_ENOTSUP, MG_ENOMEM, MG_EDEVICE, MG_EDIVERGED, MG_EBUSY = 0, 1, -1, -2, -3, -4, -5, -6
 OP_LAPLACE, OP_VARCOEF_NODAL = 0, 2
 BC_DIRICHLET_ZERO = 0
-SMOOTH_RBGS, SMOOTH_JACOBI = 0, 1
+SMOOTH_RBGS, SMOOTH_JACOBI, SMOOTH_RBGS_SYM = 0, 1, 2
+CYCLE_V, CYCLE_W, CYCLE_F = 0, 1, 2
 PREC_FP64, PREC_FP32_IR, PREC_FP16_IR = 0, 1, 2
 
 
@@ -47,6 +48,9 @@ class _Params(C.Structure):
         ("nu1", C.c_int),
         ("nu2", C.c_int),
         ("precision", C.c_int),
+        ("cycle", C.c_int),
+        ("coarse_n", C.c_int),
+        ("cg_iters", C.c_int),
     ]
 
 
@@ -90,6 +94,7 @@ def lib():
             "mg_level_residual_restrict": (i, [i, i, i, p, p, p, p, i, i, p]),
             "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
+            "mg_level_coarsest_cg": (i, [i, i, i, p, p, p, i, p]),
             "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, i, p]),
             "mg_level_ir_update_noalloc": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, i, p]),
             "mg_level_ir_update_f16": (i, [i, i, p, p, d, d, p, p, p, C.POINTER(d), C.POINTER(d), i, i, i, i, p]),
@@ -177,10 +182,13 @@ class Params:
     nu1: int = 2
     nu2: int = 2
     precision: int = PREC_FP64
+    cycle: int = CYCLE_V
+    coarse_n: int = 0  # 0 / 3: exact 3-node coarsest solve; larger: conjugate gradients there
+    cg_iters: int = 0  # 0: 4 (coarse_n - 1)
 
     def __post_init__(self):
         if self.omega <= 0.0:
-            self.omega = 1.0 if self.smoother == SMOOTH_RBGS else 0.8
+            self.omega = 0.8 if self.smoother == SMOOTH_JACOBI else 1.0
 
     @property
     def shape(self):
@@ -191,7 +199,7 @@ class Params:
 
         kp = _dptr(self.k, torch.float64, self.shape, "k") if self.k is not None else None
         return _Params(self.dim, self.n, self.op, kp, self.bc, self.smoother, self.omega, self.nu1, self.nu2,
-                       self.precision)
+                       self.precision, self.cycle, self.coarse_n, self.cg_iters)
 
 
 # Handles created through this module and not yet destroyed, in creation
@@ -303,7 +311,7 @@ def mg_level_smooth(u_in, f, u_out, smoother=SMOOTH_RBGS, omega=0.0, k=None, ec=
                     zchunk=0, prefetch=0, waves=0, order=0, stream=None) -> None:
     dim, n = f.dim(), f.shape[0]
     if omega <= 0.0:
-        omega = 1.0 if smoother == SMOOTH_RBGS else 0.8
+        omega = 0.8 if smoother == SMOOTH_JACOBI else 1.0
     dt = f.dtype
     _check(lib().mg_level_smooth(dim, n, _dtype_code(f), smoother, float(omega), _dptr(k, dt, f.shape, "k"),
                                  _dptr(u_in, dt, f.shape, "u_in"), _dptr(f, dt, None, "f"),
@@ -335,6 +343,14 @@ def mg_level_coarsest(u, f, k=None, stream=None) -> None:
     dt = f.dtype
     _check(lib().mg_level_coarsest(dim, _dtype_code(f), _dptr(k, dt, (3,) * dim, "k"), _dptr(u, dt, (3,) * dim, "u"),
                                    _dptr(f, dt, (3,) * dim, "f"), _stream(stream)), "mg_level_coarsest")
+
+
+def mg_level_coarsest_cg(u, f, k=None, iters=0, stream=None) -> None:
+    """Conjugate gradients on a coarsest grid (any n = 2^c + 1 within the limits), from u = 0."""
+    dim, n = f.dim(), f.shape[0]
+    dt = f.dtype
+    _check(lib().mg_level_coarsest_cg(dim, n, _dtype_code(f), _dptr(k, dt, f.shape, "k"), _dptr(u, dt, f.shape, "u"),
+                                      _dptr(f, dt, f.shape, "f"), int(iters), _stream(stream)), "mg_level_coarsest_cg")
 
 
 def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, prefetch=0, waves=0, pairs=0,

@@ -758,7 +758,8 @@ void reg_remove(mg_batch_handle* h) {
 
 bool same_solver(const mg_params& a, const mg_params& b) {
     return a.dim == b.dim && a.smoother == b.smoother && a.nu1 == b.nu1 && a.nu2 == b.nu2 && a.omega == b.omega &&
-           a.precision == b.precision && a.op == b.op && a.bc == b.bc;
+           a.precision == b.precision && a.op == b.op && a.bc == b.bc && a.cycle == b.cycle &&
+           a.coarse_n == b.coarse_n;
 }
 
 int server_admit(Server& S);
@@ -790,6 +791,7 @@ int mg_batch_setup(int count, const mg_params* each, void* stream, mg_ctx** out)
     if (p0.precision != MG_PREC_FP32_IR || p0.op != MG_OP_LAPLACE || p0.bc != MG_BC_DIRICHLET_ZERO) return MG_ENOTSUP;
     if (p0.smoother != MG_SMOOTH_RBGS && p0.smoother != MG_SMOOTH_WJACOBI) return MG_EINVAL;
     if (p0.nu1 < 0 || p0.nu2 < 0 || p0.nu1 > 16 || p0.nu2 > 16) return MG_EINVAL;
+    if (p0.cycle != MG_CYCLE_V || p0.coarse_n > 3) return MG_ENOTSUP;  // batches run V-cycles down to n = 3
     int max_n = 3;
     for (int i = 0; i < count; ++i) {
         mg_params q = each[i];

@@ -172,8 +172,12 @@ int validate(const mg_params* p) {
     if (p->bc != MG_BC_DIRICHLET_ZERO) return MG_ENOTSUP;
     if (p->op != MG_OP_LAPLACE && p->op != MG_OP_VARCOEF_NODAL) return MG_ENOTSUP;
     if (p->op == MG_OP_VARCOEF_NODAL && !p->k) return MG_EINVAL;
-    if (p->smoother != MG_SMOOTH_RBGS && p->smoother != MG_SMOOTH_WJACOBI) return MG_EINVAL;
+    if (p->smoother != MG_SMOOTH_RBGS && p->smoother != MG_SMOOTH_WJACOBI && p->smoother != MG_SMOOTH_RBGS_SYM)
+        return MG_EINVAL;
     if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 > 16 || p->nu2 > 16) return MG_EINVAL;
+    if (p->cycle < MG_CYCLE_V || p->cycle > MG_CYCLE_F || p->cg_iters < 0) return MG_EINVAL;
+    if (p->coarse_n != 0 && (!valid_edge(p->dim, p->coarse_n) || p->coarse_n > p->n)) return MG_EINVAL;
+    if (p->coarse_n > tail_max_edge(p->dim, p->precision == MG_PREC_FP64 ? 8 : 4)) return MG_ENOTSUP;
     if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_FP32_IR && p->precision != MG_PREC_FP16_IR)
         return MG_ENOTSUP;
     if (p->precision == MG_PREC_FP16_IR && p->op != MG_OP_LAPLACE) return MG_ENOTSUP;
@@ -531,7 +535,7 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
         e = hipMemcpyAsync(d, &h, sizeof(GridDesc), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) break;
         const bool var = c->prob.var;
-        const int sm = c->p.smoother;
+        const int sm = c->prob.smoother;
         TileCfg cfg;
         // the three sweep variants (plain, from a zero iterate, with the fused
         // coarse-grid correction) load different data and are tuned separately
@@ -724,20 +728,25 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
     mg_ctx* c = new (std::nothrow) mg_ctx();
     if (!c) return MG_ENOMEM;
     c->p = *p;
-    if (c->p.omega <= 0.0) c->p.omega = p->smoother == MG_SMOOTH_RBGS ? 1.0 : 0.8;
+    if (c->p.omega <= 0.0) c->p.omega = p->smoother == MG_SMOOTH_WJACOBI ? 0.8 : 1.0;
     c->stream = (hipStream_t)stream;
     c->use_graphs = std::getenv("MG_NO_GRAPHS") == nullptr;
     (void)hipGetDevice(&c->device);
     const int dim = p->dim;
-    c->prob = Problem{dim, p->smoother, p->nu1, p->nu2, c->p.omega, p->op == MG_OP_VARCOEF_NODAL};
+    c->prob = Problem{dim, p->smoother == MG_SMOOTH_WJACOBI ? SM_JACOBI : SM_RBGS, p->nu1, p->nu2, c->p.omega,
+                      p->op == MG_OP_VARCOEF_NODAL};
+    c->prob.sym = p->smoother == MG_SMOOTH_RBGS_SYM;
+    c->prob.cycle = p->cycle;
+    c->prob.cg_iters = p->cg_iters;
+    const int coarse_n = p->coarse_n > 3 ? p->coarse_n : 3;
     for (int m = p->n;; m = (m - 1) / 2 + 1) {
         c->n.push_back(m);
-        if (m == 3) break;
+        if (m <= coarse_n) break;
     }
     c->nlev = (int)c->n.size();
     for (int l = 0; l < c->nlev; ++l) {
-        c->tl64.push_back(default_tiles(dim, 8, c->n[(size_t)l], p->smoother));
-        c->tl32.push_back(default_tiles(dim, 4, c->n[(size_t)l], p->smoother));
+        c->tl64.push_back(default_tiles(dim, 8, c->n[(size_t)l], c->prob.smoother));
+        c->tl32.push_back(default_tiles(dim, 4, c->n[(size_t)l], c->prob.smoother));
     }
     c->top = c->tl64[0];
     if (is_h16(c->p)) {  // the binary16 refinement pass has two nodes per lane
@@ -1049,9 +1058,11 @@ int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const
                     int waves, int order, void* stream) {
     const int elem = dtype_elem(dtype);
     if (!valid_edge(dim, n) || n < 5 || !elem) return MG_EINVAL;
-    if ((smoother != 0 && smoother != 1) || !f || !u_out || (!u_in && !zero_guess)) return MG_EINVAL;
+    if ((smoother != 0 && smoother != 1 && smoother != 2) || !f || !u_out || (!u_in && !zero_guess)) return MG_EINVAL;
     if (ec && zero_guess) return MG_EINVAL;
     if (elem == 2 && k) return MG_ENOTSUP;
+    const int sel = smoother == 2 ? SEL_BLACK_FIRST : 0;
+    if (smoother == 2) smoother = SM_RBGS;
     TileCfg cfg = pick_cfg(dim, elem, n, smoother, by, zchunk, 0);
     if (prefetch) cfg.pd = prefetch;
     if (waves) cfg.wv = waves;
@@ -1073,9 +1084,9 @@ int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const
     int r = with_desc(h, s, &d);
     if (r != MG_OK) return r;
     const int flags = (zero_guess ? SWEEP_ZERO_GUESS : 0) | (ec ? SWEEP_PROLONG : 0);
-    hipError_t e = elem == 8   ? launch_smooth<double>(dim, smoother, k != nullptr, d, 1, n, 0, flags, cfg, s)
-                   : elem == 4 ? launch_smooth<float>(dim, smoother, k != nullptr, d, 1, n, 0, flags, cfg, s)
-                               : launch_smooth<half_t>(dim, smoother, false, d, 1, n, 0, flags, cfg, s);
+    hipError_t e = elem == 8   ? launch_smooth<double>(dim, smoother, k != nullptr, d, 1, n, sel, flags, cfg, s)
+                   : elem == 4 ? launch_smooth<float>(dim, smoother, k != nullptr, d, 1, n, sel, flags, cfg, s)
+                               : launch_smooth<half_t>(dim, smoother, false, d, 1, n, sel, flags, cfg, s);
     return finish_desc(d, s, e);
 }
 
@@ -1139,6 +1150,29 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
     hipError_t e = elem == 8   ? launch_coarsest<double>(dim, k != nullptr, d, 1, s)
                    : elem == 4 ? launch_coarsest<float>(dim, k != nullptr, d, 1, s)
                                : launch_coarsest<half_t>(dim, false, d, 1, s);
+    return finish_desc(d, s, e);
+}
+
+int mg_level_coarsest_cg(int dim, int n, int dtype, const void* k, void* u, const void* f, int iters,
+                         void* stream) {
+    const int elem = dtype_elem(dtype);
+    if (!valid_edge(dim, n) || !elem || !u || !f || iters < 0) return MG_EINVAL;
+    if (elem == 2 && k) return MG_ENOTSUP;
+    if (n > tail_max_edge(dim, elem)) return MG_ENOTSUP;
+    hipStream_t s = (hipStream_t)stream;
+    GridDesc h{};
+    h.u = u;
+    h.f = f;
+    h.k = k;
+    h.n = n;
+    h.c = level_c(n);
+    GridDesc* d = nullptr;
+    int r = with_desc(h, s, &d);
+    if (r != MG_OK) return r;
+    const int it = iters > 0 ? iters : 4 * (n - 1);
+    hipError_t e = elem == 8   ? launch_cg<double>(dim, k != nullptr, d, 1, n, it, s)
+                   : elem == 4 ? launch_cg<float>(dim, k != nullptr, d, 1, n, it, s)
+                               : launch_cg<half_t>(dim, false, d, 1, n, it, s);
     return finish_desc(d, s, e);
 }
 

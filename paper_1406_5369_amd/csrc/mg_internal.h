@@ -105,9 +105,13 @@ struct TileCfg {
     int xp = 1;     // norm / refinement pass (Laplacian): nodes per lane along x (1 or 2)
 };
 
-// Smoothing kernels take the input-buffer select and the block order in one
-// argument: bit 0 the select, bit 1 linear block order.
-inline int sweep_arg(int sel, const TileCfg& c) { return (sel & 1) | (c.order ? 2 : 0); }
+// Smoothing kernels take the input-buffer select, the block order and the
+// colour order in one argument: bit 0 the select, bit 1 linear block order,
+// bit 2 black first (red-black Gauss-Seidel: the colour (i+j[+k]) mod 2 = 1
+// is relaxed before colour 0, the post-smoothing sweeps of the symmetric
+// red-black smoother).  Callers pass bits 0 and 2 in 'sel'.
+constexpr int SEL_BLACK_FIRST = 4;
+inline int sweep_arg(int sel, const TileCfg& c) { return (sel & (1 | SEL_BLACK_FIRST)) | (c.order ? 2 : 0); }
 
 // Number of workgroups in x for a level of n nodes per axis (one instance).
 int smooth_tiles(int dim, int sm, int n, TileCfg cfg);
@@ -135,7 +139,13 @@ hipError_t launch_prolong(int dim, const GridDesc* d, int ninst, int nf, int sel
 // run in the single-workgroup tail kernel).
 int tail_max_edge(int dim, int elem);
 template <typename T>
-hipError_t launch_tail(int dim, int sm, bool var, const TailDesc* d, int ninst, int nu1, int nu2, hipStream_t s);
+// post_first: colour relaxed first in the post-smoothing sweeps (0 red, 1 black).
+hipError_t launch_tail(int dim, int sm, bool var, const TailDesc* d, int ninst, int nu1, int nu2, int post_first,
+                       hipStream_t s);
+// Conjugate gradients on a coarsest level of edge n (3 <= n <= tail_max_edge),
+// 'iters' steps from u = 0, one workgroup per instance.
+template <typename T>
+hipError_t launch_cg(int dim, bool var, const GridDesc* d, int ninst, int n, int iters, hipStream_t s);
 template <typename T>
 hipError_t launch_coarsest(int dim, bool var, const GridDesc* d, int ninst, hipStream_t s);
 template <typename T>

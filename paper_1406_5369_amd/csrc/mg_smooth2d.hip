@@ -35,6 +35,7 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int gx = x0 - H + lane;
+    const int cfirst = (sel & SEL_BLACK_FIRST) ? 1 : 0;  // colour of the first half-sweep
     const bool colg = gx >= 0 && gx < n, coli = gx >= 1 && gx <= n - 2;
     const bool lane1 = lane >= 1 && lane <= BX - 2;  // tile + 1 ring (RBGS) / tile (Jacobi)
     // Coarse-grid correction (bilinear, as interp2): each lane loads its
@@ -80,14 +81,14 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
     }
     __syncthreads();
     if constexpr (SM == SM_RBGS) {
-        // red half-sweep on the tile plus a one-node ring
+        // first colour (red unless black first) on the tile plus a one-node ring
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const int ly = w + 4 * m, gy = y0 - H + ly;
             if (lane1 && ly >= 1 && ly <= BY - 2) {
                 const bool inn = coli && gy >= 1 && gy <= n - 2;
                 T v = U[ly][lane];
-                if (inn && ((gx + gy) & 1) == 0) {
+                if (inn && ((gx + gy) & 1) == cfirst) {
                     T ds;
                     const T r = lds_res2<T, VAR>(U, K, ly, lane, fr[m], c, ds);
                     v = stored<ST>(relax<T, VAR>(v, r, ds, c, wd, om));
@@ -96,13 +97,13 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
             }
         }
         __syncthreads();
-        // black half-sweep on the tile, written out of place
+        // second colour on the tile, written out of place
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const int ly = w + 4 * m, gy = y0 - H + ly;
             if (lane >= 2 && lane <= BX - 3 && ly >= 2 && ly <= BY - 3 && gx <= n - 2 && gy <= n - 2) {
                 T v = R[ly][lane];
-                if (((gx + gy) & 1) == 1) {
+                if (((gx + gy) & 1) != cfirst) {
                     T ds;
                     const T r = lds_res2<T, VAR>(R, K, ly, lane, fr[m], c, ds);
                     v = relax<T, VAR>(v, r, ds, c, wd, om);

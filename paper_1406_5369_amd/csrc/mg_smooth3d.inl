@@ -15,6 +15,8 @@ namespace {
 //      to LDS for the y-neighbours of other threads
 //   B  red relaxation of plane kk-1 on the tile + one-node ring
 //   C  black relaxation of plane kk-2 on the tile, written to the output
+// (with the black-first bit of the select argument the two colours swap
+// roles: the post-smoothing sweeps of the symmetric red-black smoother).
 // Jacobi step kk: A as above, B relaxes plane kk-1 on the tile.
 // A thread owns one x position (its lane) and rows w, w+4, ... of the box;
 // z-neighbours come from its own registers, x-neighbours from the adjacent
@@ -53,6 +55,7 @@ struct Smooth3D {
     int n, x0, y0, z0, z1, kstart, kend;
     T c, wd, om;
     int lane, w, gx;
+    int cfirst;  // colour relaxed in the first half-sweep (0 red, 1 black)
     bool colg, coli, lane1;
     T un[3][RPT], kn[3][RPT];  // prefetched raw u (and k) of planes up to kk+PD
     T uo[3][RPT];              // old u of planes kk, kk-1, kk-2 (own positions)
@@ -255,7 +258,7 @@ struct Smooth3D {
                     const T uw = lane_prev(uc), ue = lane_next(uc);
                     const T kxw = VAR ? lane_prev(fxc[VAR ? S1 : 0][m]) : T(0);
                     T v = uc;
-                    if (zin && ((mring >> m) & (minner >> m) & 1u) && ((gx + y + m1) & 1) == 0)
+                    if (zin && ((mring >> m) & (minner >> m) & 1u) && ((gx + y + m1) & 1) == cfirst)
                         v = stored<ST>(relax_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m]));
                     ro[S1][m] = v;
                     R[S1][ly][lane] = v;
@@ -273,7 +276,7 @@ struct Smooth3D {
                     if ((mtile >> m) & 1u) {
                         T v = rc;
                         // faces of plane kk-2 (slot S2); +z faces of plane kk-3 in slot P
-                        if (((gx + y + m2) & 1) == 1)
+                        if (((gx + y + m2) & 1) != cfirst)
                             v = relax_at<S2, P>(R[S2], rc, ro[P][m], ro[S1][m], rw, re, ly, m, kxw, fr[S2][m]);
                         st_off(uout + (size_t)m2 * pl + rowoff(m), xb, (ST)v);
                     }
@@ -367,6 +370,7 @@ __global__ __launch_bounds__(64 * WV) void k_smooth3d(const GridDesc* __restrict
     s.om = (T)d.omega;
     s.lane = threadIdx.x & 63;
     s.w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    s.cfirst = (sel & SEL_BLACK_FIRST) ? 1 : 0;
     s.gx = s.x0 - S::H + s.lane;
     s.colg = s.gx >= 0 && s.gx < n;
     s.coli = s.gx >= 1 && s.gx <= n - 2;

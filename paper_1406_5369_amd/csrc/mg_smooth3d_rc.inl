@@ -34,6 +34,7 @@ struct SweepRC {
     int n, nc, x0, y0, z0, z1, kstart, kend;
     T c, wd, om;
     int lane, gx;
+    int cfirst;  // colour relaxed in the first half-sweep (0 red, 1 black)
     bool coli, lane1, lanet;
     unsigned xb, cxb;
     size_t pl;
@@ -171,7 +172,7 @@ struct SweepRC {
 #pragma unroll
                 for (int m = 1; m < BY - 1; ++m) {
                     const T v = stored<ST>(relax_row(uo[S1], ro[S2], uo[S0], ko[S1], ko[S2], ko[S0], m, fr[S1][m]));
-                    if (ok && yin(m) && ((gx + gy(m) + m1) & 1) == 0) ro[S1][m] = v;
+                    if (ok && yin(m) && ((gx + gy(m) + m1) & 1) == cfirst) ro[S1][m] = v;
                 }
             }
             const int m2 = kk - 2;  // black plane (output)
@@ -182,7 +183,7 @@ struct SweepRC {
                 for (int m = 2; m < BY - 2; ++m) {
                     T v = ro[S2][m];
                     const T b = relax_row(ro[S2], ro[P], ro[S1], ko[S2], kbelow, ko[S1], m, fr[S2][m]);
-                    if (((gx + gy(m) + m2) & 1) == 1) v = b;
+                    if (((gx + gy(m) + m2) & 1) != cfirst) v = b;
                     if (ok && yin(m)) st_off(out + rowoff(m), xb, (ST)v);
                 }
             }
@@ -261,6 +262,7 @@ __global__ __launch_bounds__(64) void k_smooth3d_rc(const GridDesc* __restrict__
     s.wd = (T)d.wd;
     s.om = (T)d.omega;
     s.lane = threadIdx.x;
+    s.cfirst = (sel & SEL_BLACK_FIRST) ? 1 : 0;
     s.gx = s.x0 - S::H + s.lane;
     s.run();
 }

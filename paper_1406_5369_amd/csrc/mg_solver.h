@@ -53,9 +53,12 @@ struct Group {
 };
 
 struct Problem {
-    int dim, smoother, nu1, nu2;
+    int dim, smoother, nu1, nu2;  // smoother: SM_RBGS or SM_JACOBI (the kernels' relaxations)
     double omega;
     bool var;
+    bool sym = false;   // symmetric red-black: the post-smoothing sweeps relax black first
+    int cycle = 0;      // 0 V, 1 W, 2 F (Algorithm 1 with one / two recursive calls; F: F then V)
+    int cg_iters = 0;   // conjugate-gradient steps on a coarsest level with n > 3 (0: 4 (n - 1))
 };
 
 // Coarse levels of a V-cycle run by the single-workgroup tail kernel:

@@ -100,10 +100,69 @@ struct Prof {
 
 int tail_first_level(int dim, int elem, const std::vector<int>& n, bool zero_top) {
     if (std::getenv("MG_NO_TAIL")) return -1;
+    if (n.empty() || n.back() != 3) return -1;  // the tail ends in the exact 3-node solve
     const int tmax = tail_max_edge(dim, elem);
     for (int l = zero_top ? 0 : 1; l < (int)n.size(); ++l)
         if (n[(size_t)l] <= tmax && (int)n.size() - l <= kMaxTailLevels) return l;
     return -1;
+}
+
+// Coarsest level: exact solve of the single unknown (n = 3) or conjugate
+// gradients (n > 3), from a zero iterate.
+template <typename T>
+hipError_t coarse_solve(const Problem& P, const Group& g, hipStream_t s) {
+    if (g.n == 3) return launch_coarsest<T>(P.dim, P.var, g.d, g.ninst, s);
+    return launch_cg<T>(P.dim, P.var, g.d, g.ninst, g.n, P.cg_iters > 0 ? P.cg_iters : 4 * (g.n - 1), s);
+}
+
+// Post-smoothing select bits: the symmetric red-black smoother relaxes black first.
+inline int post_sel(const Problem& P, int cur) { return cur | (P.sym ? SEL_BLACK_FIRST : 0); }
+
+// Algorithm 1 on level l with gamma recursive calls: kind 0 V (one call), 1 W
+// (two), 2 F (an F-cycle then a V-cycle).  The zero guess precedes the first
+// call only; later calls continue from the coarse iterate the previous call
+// left.  Level by level (no coarse tail).
+template <typename T>
+hipError_t cycle_rec(const Problem& P, const std::vector<Group>& G, int l, int kind, bool zero,
+                     const std::vector<Tiles>& tiles, hipStream_t s, Prof& prof) {
+    const int L = (int)G.size();
+    const int dim = P.dim;
+    const Group& g = G[(size_t)l];
+    if (l == L - 1) return coarse_solve<T>(P, g, s);
+    int cur = 0;
+    for (int i = 0; i < P.nu1; ++i) {
+        const int flags = (i == 0 && zero) ? SWEEP_ZERO_GUESS : 0;
+        const bool timed = l == 0 && flags == 0;
+        if (timed) prof.begin();
+        MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags, tiles[(size_t)l].sweep(flags),
+                                s));
+        if (timed) prof.end();
+        cur ^= 1;
+    }
+    if (P.nu1 == 0 && zero) MG_TRY(launch_zero_u<T>(dim, g.d, g.ninst, g.n, s));
+    MG_TRY(launch_restrict<T>(dim, P.var, g.d, g.ninst, g.n, cur, tiles[(size_t)l].restr, s));
+    if (kind == 0) {
+        MG_TRY(cycle_rec<T>(P, G, l + 1, 0, true, tiles, s, prof));
+    } else if (kind == 1) {
+        MG_TRY(cycle_rec<T>(P, G, l + 1, 1, true, tiles, s, prof));
+        MG_TRY(cycle_rec<T>(P, G, l + 1, 1, false, tiles, s, prof));
+    } else {
+        MG_TRY(cycle_rec<T>(P, G, l + 1, 2, true, tiles, s, prof));
+        MG_TRY(cycle_rec<T>(P, G, l + 1, 0, false, tiles, s, prof));
+    }
+    const bool fuse = P.nu2 > 0;
+    if (!fuse) MG_TRY(launch_prolong<T>(dim, g.d, g.ninst, g.n, cur, s));
+    for (int i = 0; i < P.nu2; ++i) {
+        const int flags = (i == 0 && fuse) ? SWEEP_PROLONG : 0;
+        const bool timed = l == 0 && flags == 0;
+        if (timed) prof.begin();
+        MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, post_sel(P, cur), flags,
+                                tiles[(size_t)l].sweep(flags), s));
+        if (timed) prof.end();
+        cur ^= 1;
+    }
+    if (cur == 1) MG_TRY(launch_copy_t_to_u<T>(dim, g.d, g.ninst, g.n, s));
+    return hipSuccess;
 }
 
 template <typename T>
@@ -112,10 +171,11 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
     const int L = (int)G.size();
     const int dim = P.dim;
     Prof prof{prof_ev, prof_n, prof_cap, s};
+    if (P.cycle != 0) return cycle_rec<T>(P, G, 0, P.cycle, zero_top, tiles, s, prof);
     const bool use_tail = tail && tail->first >= 0 && tail->first < L && tail->d;
     // levels [0, stop) run level by level; the rest is the tail (or the coarsest solve)
     const int stop = use_tail ? tail->first : L - 1;
-    if (stop == 0 && !use_tail) return launch_coarsest<T>(dim, P.var, G[0].d, G[0].ninst, s);
+    if (stop == 0 && !use_tail) return coarse_solve<T>(P, G[0], s);
     std::vector<int> sel((size_t)L, 0);
     // descending leg: presmoothing, residual, restriction (Algorithm 1)
     for (int l = 0; l < stop; ++l) {
@@ -137,10 +197,10 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
     }
     if (use_tail) {
         // every level from 'stop' to the coarsest in one launch, from a zero guess
-        MG_TRY(launch_tail<T>(dim, P.smoother, P.var, tail->d, tail->ninst, P.nu1, P.nu2, s));
+        MG_TRY(launch_tail<T>(dim, P.smoother, P.var, tail->d, tail->ninst, P.nu1, P.nu2, P.sym ? 1 : 0, s));
     } else {
-        // coarsest grid: exact solve from the zero guess
-        MG_TRY(launch_coarsest<T>(dim, P.var, G[(size_t)L - 1].d, G[(size_t)L - 1].ninst, s));
+        // coarsest grid from the zero guess
+        MG_TRY(coarse_solve<T>(P, G[(size_t)L - 1], s));
     }
     // ascending leg: interpolation + correction, postsmoothing
     for (int l = stop - 1; l >= 0; --l) {
@@ -152,7 +212,7 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
             const int flags = (i == 0 && fuse) ? SWEEP_PROLONG : 0;
             const bool timed = l == 0 && flags == 0;
             if (timed) prof.begin();
-            MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags,
+            MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, post_sel(P, cur), flags,
                                     tiles[(size_t)l].sweep(flags), s));
             if (timed) prof.end();
             cur ^= 1;

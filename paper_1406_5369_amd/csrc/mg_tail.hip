@@ -82,12 +82,14 @@ __device__ __forceinline__ int tail_inner(int n) {
 
 // One smoothing sweep of a level (arrays already offset to the level).  The
 // LDS arrays hold arithmetic-type values; every iterate value is rounded to
-// the storage type ST where the level kernels would store it.
+// the storage type ST where the level kernels would store it.  RBGS relaxes
+// colour 'first' (0 red, 1 black), then the other one.
 template <typename ST, typename T, int DIM, int SM, bool VAR>
-__device__ void tail_sweep(T* u, const T* f, T* w, const T* k, const Lvl<T>& L) {
+__device__ void tail_sweep(T* u, const T* f, T* w, const T* k, const Lvl<T>& L, int first = 0) {
     const int cnt = tail_inner<DIM>(L.n);
     if constexpr (SM == SM_RBGS) {
-        for (int colour = 0; colour < 2; ++colour) {
+        for (int half = 0; half < 2; ++half) {
+            const int colour = half ^ first;
             for (int q = threadIdx.x; q < cnt; q += TNT) {
                 int cl;
                 const int p = tail_node<DIM>(q, L.n, cl);
@@ -141,7 +143,7 @@ __device__ __forceinline__ T tail_fw(const T* R, int nf, int fp) {
 }
 
 template <typename ST, int DIM, int SM, bool VAR, int NMAX>
-__global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs, int nu1, int nu2) {
+__global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs, int nu1, int nu2, int post_first) {
     using T = arith_t<ST>;
     constexpr int TOT = tail_nodes(DIM, NMAX);
     __shared__ T Us[TOT];
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs
             u[p] = stored<ST>(u[p] + corr);
         }
         __syncthreads();
-        for (int s = 0; s < nu2; ++s) tail_sweep<ST, T, DIM, SM, VAR>(u, f, w, k, lv);
+        for (int s = 0; s < nu2; ++s) tail_sweep<ST, T, DIM, SM, VAR>(u, f, w, k, lv, post_first);
     }
     // the tail's finest iterate back to device memory (inner nodes; its
     // boundary there is zero already)
@@ -270,6 +272,135 @@ __global__ __launch_bounds__(TNT) void k_tail(const TailDesc* __restrict__ descs
     }
 }
 
+// ---------------------------------------------------------------------------
+// Conjugate gradients on a coarsest level with more than one unknown
+// (Algorithm 1: the coarsest grid is solved by a direct solver or by CG), one
+// workgroup per instance, every vector in LDS.  From u = 0: r = p = f on the
+// inner nodes, then a fixed number of steps (fewer only if r or p^T A p
+// becomes zero): q = A p, alpha = (r^T r) / (p^T q), u += alpha p,
+// r -= alpha q, beta = (r_new^T r_new) / (r^T r), p = r + beta p.  Inner
+// products are formed in FP64 from the vectors' values, each x-row summed
+// left to right and the row sums added in row order; alpha and beta are the
+// FP64 quotients rounded to the arithmetic type; the vector updates are in
+// the arithmetic type and every stored vector value is rounded to the
+// storage type ST.
+// ---------------------------------------------------------------------------
+
+template <typename T, int DIM, bool VAR>
+__device__ __forceinline__ T cg_apply(const T* v, const T* k, int n, T c, int p) {
+    const int sy = n, sz = n * n;
+    if constexpr (VAR) {
+        const T kp = k[p];
+        const T kxW = kface(k[p - 1], kp), kxC = kface(kp, k[p + 1]);
+        const T kyS = kface(k[p - sy], kp), kyC = kface(kp, k[p + sy]);
+        if constexpr (DIM == 2) {
+            const T dsum = (kxW + kxC) + (kyS + kyC);
+            const T t = (kxW * v[p - 1] + kxC * v[p + 1]) + (kyS * v[p - sy] + kyC * v[p + sy]);
+            return c * (dsum * v[p] - t);
+        } else {
+            const T kzB = kface(k[p - sz], kp), kzC = kface(kp, k[p + sz]);
+            const T dsum = ((kxW + kxC) + (kyS + kyC)) + (kzB + kzC);
+            const T t = ((kxW * v[p - 1] + kxC * v[p + 1]) + (kyS * v[p - sy] + kyC * v[p + sy])) +
+                        (kzB * v[p - sz] + kzC * v[p + sz]);
+            return c * (dsum * v[p] - t);
+        }
+    } else if constexpr (DIM == 2) {
+        const T s = (v[p - 1] + v[p + 1]) + (v[p - sy] + v[p + sy]);
+        return c * (T(4) * v[p] - s);
+    } else {
+        const T s = ((v[p - 1] + v[p + 1]) + (v[p - sy] + v[p + sy])) + (v[p - sz] + v[p + sz]);
+        return c * (T(6) * v[p] - s);
+    }
+}
+
+// FP64 inner product over the inner nodes: thread t sums inner row t (x from
+// 1 to n-2), thread 0 adds the row sums in order.  Result in every thread.
+template <typename T, int DIM>
+__device__ __forceinline__ double cg_dot(const T* a, const T* b, int n, double* rows, double* bc) {
+    const int m = n - 2;
+    const int nrows = DIM == 2 ? m : m * m;
+    for (int t = threadIdx.x; t < nrows; t += TNT) {
+        const int j = 1 + t % m, k = DIM == 2 ? 0 : 1 + t / m;
+        const int base = (k * n + j) * n;
+        double s = 0.0;
+        for (int i = 1; i <= m; ++i) s += (double)a[base + i] * (double)b[base + i];
+        rows[t] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int t = 0; t < nrows; ++t) s += rows[t];
+        *bc = s;
+    }
+    __syncthreads();
+    const double v = *bc;
+    __syncthreads();  // bc and rows are written again by the next product
+    return v;
+}
+
+template <typename ST, int DIM, bool VAR, int NMAX>
+__global__ __launch_bounds__(TNT) void k_cg(const GridDesc* __restrict__ descs, int iters) {
+    using T = arith_t<ST>;
+    constexpr int TOT = DIM == 2 ? NMAX * NMAX : NMAX * NMAX * NMAX;
+    constexpr int NROWS = DIM == 2 ? NMAX : NMAX * NMAX;
+    __shared__ T U[TOT], R[TOT], Pv[TOT], Q[TOT];
+    __shared__ T K[VAR ? TOT : 1];
+    __shared__ double rows[NROWS];
+    __shared__ double bc;
+    const GridDesc d = descs[blockIdx.x];
+    if (d.done && *gp(d.done)) return;
+    const int n = d.n;
+    const int np = DIM == 2 ? n * n : n * n * n;
+    const T c = (T)d.c;
+    const MG_GLOBAL ST* __restrict__ f = gp((const ST*)d.f);
+    const int cnt = tail_inner<DIM>(n);
+    for (int p = threadIdx.x; p < np; p += TNT) {
+        U[p] = T(0);
+        R[p] = T(0);
+        Pv[p] = T(0);
+        Q[p] = T(0);
+        if constexpr (VAR) K[p] = gp((const T*)d.k)[p];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < cnt; q += TNT) {
+        int cl;
+        const int p = tail_node<DIM>(q, n, cl);
+        R[p] = (T)f[p];
+        Pv[p] = (T)f[p];
+    }
+    __syncthreads();
+    double rr = cg_dot<T, DIM>(R, R, n, rows, &bc);
+    for (int it = 0; it < iters && rr > 0.0; ++it) {
+        for (int q = threadIdx.x; q < cnt; q += TNT) {
+            int cl;
+            const int p = tail_node<DIM>(q, n, cl);
+            Q[p] = stored<ST>(cg_apply<T, DIM, VAR>(Pv, K, n, c, p));
+        }
+        __syncthreads();
+        const double pq = cg_dot<T, DIM>(Pv, Q, n, rows, &bc);
+        if (!(pq > 0.0)) break;
+        const T alpha = (T)(rr / pq);
+        for (int q = threadIdx.x; q < cnt; q += TNT) {
+            int cl;
+            const int p = tail_node<DIM>(q, n, cl);
+            U[p] = stored<ST>(U[p] + alpha * Pv[p]);
+            R[p] = stored<ST>(R[p] - alpha * Q[p]);
+        }
+        __syncthreads();
+        const double rr_new = cg_dot<T, DIM>(R, R, n, rows, &bc);
+        const T beta = (T)(rr_new / rr);
+        for (int q = threadIdx.x; q < cnt; q += TNT) {
+            int cl;
+            const int p = tail_node<DIM>(q, n, cl);
+            Pv[p] = stored<ST>(R[p] + beta * Pv[p]);
+        }
+        __syncthreads();
+        rr = rr_new;
+    }
+    MG_GLOBAL ST* __restrict__ u = gp((ST*)d.u);
+    for (int p = threadIdx.x; p < np; p += TNT) u[p] = (ST)U[p];
+}
+
 }  // namespace
 
 // The tail's LDS holds arithmetic-type values: 4 bytes for FP32 and binary16
@@ -280,27 +411,28 @@ int tail_max_edge(int dim, int elem) {
 }
 
 template <typename T>
-hipError_t launch_tail(int dim, int sm, bool var, const TailDesc* d, int ninst, int nu1, int nu2, hipStream_t s) {
+hipError_t launch_tail(int dim, int sm, bool var, const TailDesc* d, int ninst, int nu1, int nu2, int post_first,
+                       hipStream_t s) {
     if (ninst <= 0) return hipSuccess;
     constexpr bool F = sizeof(arith_t<T>) == 4;
 #define MG_TAIL(DIMV, NMAXV)                                                                                     \
     do {                                                                                                      \
         if (sm == SM_RBGS) {                                                                                  \
-            if (var) k_tail<T, DIMV, SM_RBGS, true, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2);               \
-            else k_tail<T, DIMV, SM_RBGS, false, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2);                  \
+            if (var) k_tail<T, DIMV, SM_RBGS, true, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2, post_first);               \
+            else k_tail<T, DIMV, SM_RBGS, false, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2, post_first);                  \
         } else {                                                                                              \
-            if (var) k_tail<T, DIMV, SM_JACOBI, true, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2);             \
-            else k_tail<T, DIMV, SM_JACOBI, false, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2);                \
+            if (var) k_tail<T, DIMV, SM_JACOBI, true, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2, post_first);             \
+            else k_tail<T, DIMV, SM_JACOBI, false, NMAXV><<<ninst, TNT, 0, s>>>(d, nu1, nu2, post_first);                \
         }                                                                                                     \
     } while (0)
     if constexpr (sizeof(T) == 2) {  // binary16 storage: Laplacian only
         if (var) return hipErrorInvalidValue;
         if (dim == 2) {
-            if (sm == SM_RBGS) k_tail<T, 2, SM_RBGS, false, 65><<<ninst, TNT, 0, s>>>(d, nu1, nu2);
-            else k_tail<T, 2, SM_JACOBI, false, 65><<<ninst, TNT, 0, s>>>(d, nu1, nu2);
+            if (sm == SM_RBGS) k_tail<T, 2, SM_RBGS, false, 65><<<ninst, TNT, 0, s>>>(d, nu1, nu2, post_first);
+            else k_tail<T, 2, SM_JACOBI, false, 65><<<ninst, TNT, 0, s>>>(d, nu1, nu2, post_first);
         } else {
-            if (sm == SM_RBGS) k_tail<T, 3, SM_RBGS, false, 17><<<ninst, TNT, 0, s>>>(d, nu1, nu2);
-            else k_tail<T, 3, SM_JACOBI, false, 17><<<ninst, TNT, 0, s>>>(d, nu1, nu2);
+            if (sm == SM_RBGS) k_tail<T, 3, SM_RBGS, false, 17><<<ninst, TNT, 0, s>>>(d, nu1, nu2, post_first);
+            else k_tail<T, 3, SM_JACOBI, false, 17><<<ninst, TNT, 0, s>>>(d, nu1, nu2, post_first);
         }
         return hipGetLastError();
     }
@@ -310,8 +442,40 @@ hipError_t launch_tail(int dim, int sm, bool var, const TailDesc* d, int ninst, 
     return hipGetLastError();
 }
 
-template hipError_t launch_tail<double>(int, int, bool, const TailDesc*, int, int, int, hipStream_t);
-template hipError_t launch_tail<float>(int, int, bool, const TailDesc*, int, int, int, hipStream_t);
-template hipError_t launch_tail<half_t>(int, int, bool, const TailDesc*, int, int, int, hipStream_t);
+template <typename T>
+hipError_t launch_cg(int dim, bool var, const GridDesc* d, int ninst, int n, int iters, hipStream_t s) {
+    const bool f = sizeof(arith_t<T>) == 4;
+    if (ninst <= 0) return hipSuccess;
+    if (n > tail_max_edge(dim, f ? 4 : 8) || n < 3 || iters < 0) return hipErrorInvalidValue;
+    if constexpr (sizeof(T) == 2) {
+        if (var) return hipErrorInvalidValue;
+        if (dim == 2) k_cg<T, 2, false, 65><<<ninst, TNT, 0, s>>>(d, iters);
+        else k_cg<T, 3, false, 17><<<ninst, TNT, 0, s>>>(d, iters);
+    } else if constexpr (sizeof(T) == 4) {
+        if (dim == 2) {
+            if (var) k_cg<T, 2, true, 65><<<ninst, TNT, 0, s>>>(d, iters);
+            else k_cg<T, 2, false, 65><<<ninst, TNT, 0, s>>>(d, iters);
+        } else {
+            if (var) k_cg<T, 3, true, 17><<<ninst, TNT, 0, s>>>(d, iters);
+            else k_cg<T, 3, false, 17><<<ninst, TNT, 0, s>>>(d, iters);
+        }
+    } else {
+        if (dim == 2) {
+            if (var) k_cg<T, 2, true, 33><<<ninst, TNT, 0, s>>>(d, iters);
+            else k_cg<T, 2, false, 33><<<ninst, TNT, 0, s>>>(d, iters);
+        } else {
+            if (var) k_cg<T, 3, true, 9><<<ninst, TNT, 0, s>>>(d, iters);
+            else k_cg<T, 3, false, 9><<<ninst, TNT, 0, s>>>(d, iters);
+        }
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_cg<double>(int, bool, const GridDesc*, int, int, int, hipStream_t);
+template hipError_t launch_cg<float>(int, bool, const GridDesc*, int, int, int, hipStream_t);
+template hipError_t launch_cg<half_t>(int, bool, const GridDesc*, int, int, int, hipStream_t);
+template hipError_t launch_tail<double>(int, int, bool, const TailDesc*, int, int, int, int, hipStream_t);
+template hipError_t launch_tail<float>(int, int, bool, const TailDesc*, int, int, int, int, hipStream_t);
+template hipError_t launch_tail<half_t>(int, int, bool, const TailDesc*, int, int, int, int, hipStream_t);
 
 }  // namespace mg
