@@ -93,6 +93,14 @@ def _load():
         "orc_fp16_scale": (_d, [_d]),
         "orc_ir_update_f16": (_d, [_i, _i, _p, _p, _p, _d, _p, _d, _p, _p]),
         "orc_solve_ir_mg_f16": (_i, [_i, _i, _p, _i, _d, _i, _i, _i, _i, _i, _p, _p, _d, _i, _p, _p]),
+        "orc_cc_residual": (None, [_i, _i, _p, _p, _p]),
+        "orc_cc_smooth": (None, [_i, _i, _i, _d, _p, _p]),
+        "orc_cc_restrict": (None, [_i, _i, _p, _p]),
+        "orc_cc_prolong_correct": (None, [_i, _i, _p, _p]),
+        "orc_cc_sum": (_d, [_i, _i, _p]),
+        "orc_cc_residual_norm": (_d, [_i, _i, _p, _p]),
+        "orc_cc_cycle": (_i, [_i, _i, _i, _d, _i, _i, _i, _p, _p]),
+        "orc_cc_solve": (_i, [_i, _i, _i, _d, _i, _i, _i, _p, _p, _d, _i, _p, _p, _p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -335,3 +343,85 @@ def solve_ir_f16(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0
     if rc == -1:
         raise ValueError(f"oracle solve rejected its arguments (rc={rc})")
     return u, hist[: cyc.value + 1].copy(), rc
+
+
+# ------------------------------------------------------------------ cell-centred Neumann grids
+# Arrays hold the n^dim cell values (n = 2^L cells per axis, h = 1/n), x fastest.
+
+
+def _cc_dims(a):
+    dim = a.ndim
+    n = a.shape[0]
+    if dim not in (2, 3) or any(s != n for s in a.shape) or n < 1 or (n & (n - 1)):
+        raise ValueError(f"expected a square/cubic cell array of 2^L cells per axis, got shape {a.shape}")
+    return dim, n
+
+
+def cc_residual(u, f):
+    _chk(u, np.float64, "u"), _chk(f, np.float64, "f")
+    dim, n = _cc_dims(u)
+    r = np.zeros_like(u)
+    _load().orc_cc_residual(dim, n, _ptr(u), _ptr(f), _ptr(r))
+    return r
+
+
+def cc_smooth(u, f, smoother=SMOOTH_RBGS, omega=1.0):
+    _chk(u, np.float64, "u"), _chk(f, np.float64, "f")
+    dim, n = _cc_dims(u)
+    out = u.copy()
+    _load().orc_cc_smooth(dim, n, smoother, omega, _ptr(out), _ptr(f))
+    return out
+
+
+def cc_restrict(r):
+    _chk(r, np.float64, "r")
+    dim, nf = _cc_dims(r)
+    fc = np.zeros((nf // 2,) * dim)
+    _load().orc_cc_restrict(dim, nf, _ptr(r), _ptr(fc))
+    return fc
+
+
+def cc_prolong_correct(u, ec):
+    _chk(u, np.float64, "u"), _chk(ec, np.float64, "ec")
+    dim, nf = _cc_dims(u)
+    if ec.shape != (nf // 2,) * dim:
+        raise ValueError("coarse array has the wrong shape")
+    out = u.copy()
+    _load().orc_cc_prolong_correct(dim, nf, _ptr(out), _ptr(ec))
+    return out
+
+
+def cc_sum(u) -> float:
+    _chk(u, np.float64, "u")
+    dim, n = _cc_dims(u)
+    return float(_load().orc_cc_sum(dim, n, _ptr(u)))
+
+
+def cc_residual_norm(u, f) -> float:
+    _chk(u, np.float64, "u"), _chk(f, np.float64, "f")
+    dim, n = _cc_dims(u)
+    return float(_load().orc_cc_residual_norm(dim, n, _ptr(u), _ptr(f)))
+
+
+def cc_cycle(u, f, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, cycle=CYCLE_V):
+    _chk(u, np.float64, "u"), _chk(f, np.float64, "f")
+    dim, n = _cc_dims(u)
+    out = u.copy()
+    if _load().orc_cc_cycle(dim, n, smoother, omega, nu1, nu2, cycle, _ptr(out), _ptr(f)) != 0:
+        raise ValueError("oracle cycle rejected its arguments")
+    return out
+
+
+def cc_solve(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2, cycle=CYCLE_V):
+    """Cell-centred Neumann solve (FP64).  Returns (u, history, status, projected f)."""
+    _chk(u0, np.float64, "u0"), _chk(f, np.float64, "f")
+    dim, n = _cc_dims(u0)
+    u = u0.copy()
+    hist = np.zeros(max_cycles + 1)
+    fh = np.zeros_like(f)
+    cyc = C.c_int(0)
+    rc = _load().orc_cc_solve(dim, n, smoother, omega, nu1, nu2, cycle, _ptr(u), _ptr(f), tol, max_cycles,
+                              _ptr(hist), C.addressof(cyc), _ptr(fh))
+    if rc == -1:
+        raise ValueError("oracle solve rejected its arguments")
+    return u, hist[: cyc.value + 1].copy(), rc, fh

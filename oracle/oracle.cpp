@@ -629,6 +629,232 @@ Grid<S> make_grid(int dim, int n, const typename Arith<S>::type* kf, double omeg
 
 bool valid_edge(int n) { return n >= 3 && ((n - 1) & (n - 2)) == 0; }
 
+/* ------------------------------------------------------------------ */
+/* Cell-centred grids with a homogeneous Neumann boundary (Table 1's    */
+/* cell-centred discretisation, Neumann boundary condition, constant    */
+/* interpolation; the boundary of the paper's complex-diffusion         */
+/* application, Section 4).  n = 2^L cells per axis, h = 1/n, cell        */
+/* (i, j[, k]) centred at ((i+1/2)h, ...); values stored without ghost    */
+/* cells, x fastest.  Zero flux across the boundary: a neighbour outside  */
+/* the domain takes the cell's own value (ghost = mirror).  The operator  */
+/* is singular (constants are in its kernel): the right-hand side is      */
+/* projected onto mean zero and the iterate is kept at mean zero.         */
+/* ------------------------------------------------------------------ */
+
+inline idx_t cc_at(int dim, int n, int i, int j, int k) {
+    return dim == 2 ? (idx_t)j * n + i : ((idx_t)k * n + j) * n + i;
+}
+
+/* number of faces of cell (i, j, k) on the boundary */
+inline int cc_missing(int dim, int n, int i, int j, int k) {
+    int m = (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1);
+    if (dim == 3) m += (k == 0) + (k == n - 1);
+    return m;
+}
+
+/* (A u)_p = c (2d u_p - s), s the neighbour sum with ghost = own value,
+ * summed as ((W+E)+(S+N))+(B+T) */
+inline double cc_apply(int dim, int n, double c, const double* u, int i, int j, int k) {
+    const idx_t p = cc_at(dim, n, i, j, k);
+    const double uC = u[p];
+    const double uW = i > 0 ? u[p - 1] : uC, uE = i < n - 1 ? u[p + 1] : uC;
+    const double uS = j > 0 ? u[p - n] : uC, uN = j < n - 1 ? u[p + n] : uC;
+    if (dim == 2) return c * (4.0 * uC - ((uW + uE) + (uS + uN)));
+    const idx_t sz = (idx_t)n * n;
+    const double uB = k > 0 ? u[p - sz] : uC, uT = k < n - 1 ? u[p + sz] : uC;
+    return c * (6.0 * uC - (((uW + uE) + (uS + uN)) + (uB + uT)));
+}
+
+/* per-level constants: c = 1/h^2, wd[m] = omega h^2 / (2d - m): omega times
+ * the inverse of the true diagonal c (2d - m) of a cell with m boundary
+ * faces (m <= d) */
+struct CCLevel {
+    int dim, n;
+    double c, wd[4];
+};
+inline CCLevel cc_level(int dim, int n, double omega) {
+    CCLevel L;
+    L.dim = dim;
+    L.n = n;
+    const double h = 1.0 / (double)n;
+    L.c = 1.0 / (h * h);
+    for (int m = 0; m < 4; ++m) L.wd[m] = (omega * (h * h)) / (double)(2 * dim - m);
+    return L;
+}
+
+inline int cc_k1(int dim, int n) { return dim == 3 ? n : 1; }
+
+/* relaxation u + omega diag^-1 (f - A u) at one cell */
+inline double cc_relax(const CCLevel& L, const double* u, const double* f, int i, int j, int k) {
+    const idx_t p = cc_at(L.dim, L.n, i, j, k);
+    const double r = f[p] - cc_apply(L.dim, L.n, L.c, u, i, j, k);
+    return u[p] + L.wd[cc_missing(L.dim, L.n, i, j, k)] * r;
+}
+
+void cc_rbgs(const CCLevel& L, double* u, const double* f) {
+    const int n = L.n;
+    for (int colour = 0; colour < 2; ++colour)
+        for (int k = 0; k < cc_k1(L.dim, n); ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i)
+                    if (((i + j + k) & 1) == colour) u[cc_at(L.dim, n, i, j, k)] = cc_relax(L, u, f, i, j, k);
+}
+
+void cc_jacobi(const CCLevel& L, double* u, const double* f, std::vector<double>& tmp) {
+    const int n = L.n;
+    const size_t N = L.dim == 3 ? (size_t)n * n * n : (size_t)n * n;
+    tmp.assign(u, u + N);
+    for (int k = 0; k < cc_k1(L.dim, n); ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) tmp[(size_t)cc_at(L.dim, n, i, j, k)] = cc_relax(L, u, f, i, j, k);
+    std::memcpy(u, tmp.data(), N * sizeof(double));
+}
+
+void cc_residual(const CCLevel& L, const double* u, const double* f, double* r) {
+    const int n = L.n;
+    for (int k = 0; k < cc_k1(L.dim, n); ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const idx_t p = cc_at(L.dim, n, i, j, k);
+                r[p] = f[p] - cc_apply(L.dim, n, L.c, u, i, j, k);
+            }
+}
+
+/* coarse cell = average of its 2^d children (cell-centred restriction) */
+void cc_restrict(int dim, int nf, const double* r, double* fc) {
+    const int nc = nf / 2;
+    for (int K = 0; K < cc_k1(dim, nc); ++K)
+        for (int J = 0; J < nc; ++J)
+            for (int I = 0; I < nc; ++I) {
+                const int i = 2 * I, j = 2 * J, k = 2 * K;
+                const double q0 = (r[cc_at(dim, nf, i, j, k)] + r[cc_at(dim, nf, i + 1, j, k)]) +
+                                  (r[cc_at(dim, nf, i, j + 1, k)] + r[cc_at(dim, nf, i + 1, j + 1, k)]);
+                if (dim == 2) {
+                    fc[cc_at(dim, nc, I, J, K)] = 0.25 * q0;
+                } else {
+                    const double q1 = (r[cc_at(dim, nf, i, j, k + 1)] + r[cc_at(dim, nf, i + 1, j, k + 1)]) +
+                                      (r[cc_at(dim, nf, i, j + 1, k + 1)] + r[cc_at(dim, nf, i + 1, j + 1, k + 1)]);
+                    fc[cc_at(dim, nc, I, J, K)] = 0.125 * (q0 + q1);
+                }
+            }
+}
+
+/* constant interpolation and correction: each fine cell gets its parent's value */
+void cc_prolong_correct(int dim, int nf, double* u, const double* ec) {
+    const int nc = nf / 2;
+    for (int k = 0; k < cc_k1(dim, nf); ++k)
+        for (int j = 0; j < nf; ++j)
+            for (int i = 0; i < nf; ++i) {
+                const idx_t p = cc_at(dim, nf, i, j, k);
+                u[p] = u[p] + ec[cc_at(dim, nc, i / 2, j / 2, dim == 3 ? k / 2 : 0)];
+            }
+}
+
+/* sum of all cells: each x-row left to right, the rows of a plane in order,
+ * the planes in order */
+double cc_sum(int dim, int n, const double* u) {
+    double total = 0.0;
+    for (int k = 0; k < cc_k1(dim, n); ++k) {
+        double plane = 0.0;
+        for (int j = 0; j < n; ++j) {
+            double row = 0.0;
+            for (int i = 0; i < n; ++i) row += u[cc_at(dim, n, i, j, k)];
+            plane += row;
+        }
+        total += plane;
+    }
+    return total;
+}
+
+inline size_t cc_cells(int dim, int n) { return dim == 3 ? (size_t)n * n * n : (size_t)n * n; }
+
+/* v -= mean(v) (mean = sum / number of cells) */
+void cc_remove_mean(int dim, int n, double* v) {
+    const size_t N = cc_cells(dim, n);
+    const double mean = cc_sum(dim, n, v) / (double)N;
+    for (size_t p = 0; p < N; ++p) v[p] = v[p] - mean;
+}
+
+double cc_residual_norm(const CCLevel& L, const double* u, const double* f) {
+    const int n = L.n;
+    double s = 0.0;
+    for (int k = 0; k < cc_k1(L.dim, n); ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const double r = f[cc_at(L.dim, n, i, j, k)] - cc_apply(L.dim, n, L.c, u, i, j, k);
+                s += r * r;
+            }
+    return std::sqrt(s);
+}
+
+struct CCHierarchy {
+    int dim, nlev, smoother, nu1, nu2, cycle;
+    double omega;
+    std::vector<int> n;
+    std::vector<std::vector<double>> u, f, r;
+    std::vector<double> tmp;
+};
+
+void cc_build(CCHierarchy& H, int dim, int n, int smoother, double omega, int nu1, int nu2, int cycle) {
+    H.dim = dim;
+    H.smoother = smoother;
+    H.omega = omega;
+    H.nu1 = nu1;
+    H.nu2 = nu2;
+    H.cycle = cycle;
+    H.n.clear();
+    for (int m = n; m >= 1; m /= 2) H.n.push_back(m);
+    H.nlev = (int)H.n.size();
+    H.u.assign((size_t)H.nlev, {});
+    H.f.assign((size_t)H.nlev, {});
+    H.r.assign((size_t)H.nlev, {});
+    for (int l = 0; l < H.nlev; ++l) {
+        const size_t N = cc_cells(dim, H.n[(size_t)l]);
+        if (l > 0) {
+            H.u[(size_t)l].assign(N, 0.0);
+            H.f[(size_t)l].assign(N, 0.0);
+        }
+        H.r[(size_t)l].assign(N, 0.0);
+    }
+}
+
+void cc_smooth(CCHierarchy& H, const CCLevel& L, double* u, const double* f) {
+    if (H.smoother == SMOOTH_JACOBI) cc_jacobi(L, u, f, H.tmp);
+    else cc_rbgs(L, u, f);
+}
+
+/* Algorithm 1 on a cell-centred level; the coarsest level is a single cell,
+ * whose operator is zero: its correction is 0 (the constant is fixed by the
+ * mean-zero condition). */
+void cc_cycle(CCHierarchy& H, int l, double* u, const double* f, int kind) {
+    const int n = H.n[(size_t)l];
+    if (l == H.nlev - 1) {
+        for (size_t p = 0; p < cc_cells(H.dim, n); ++p) u[p] = 0.0;
+        return;
+    }
+    const CCLevel L = cc_level(H.dim, n, H.omega);
+    for (int s = 0; s < H.nu1; ++s) cc_smooth(H, L, u, f);
+    double* r = H.r[(size_t)l].data();
+    cc_residual(L, u, f, r);
+    double* fc = H.f[(size_t)l + 1].data();
+    cc_restrict(H.dim, n, r, fc);
+    double* uc = H.u[(size_t)l + 1].data();
+    std::fill(H.u[(size_t)l + 1].begin(), H.u[(size_t)l + 1].end(), 0.0);
+    if (kind == CYCLE_V) {
+        cc_cycle(H, l + 1, uc, fc, CYCLE_V);
+    } else if (kind == CYCLE_W) {
+        cc_cycle(H, l + 1, uc, fc, CYCLE_W);
+        cc_cycle(H, l + 1, uc, fc, CYCLE_W);
+    } else {
+        cc_cycle(H, l + 1, uc, fc, CYCLE_F);
+        cc_cycle(H, l + 1, uc, fc, CYCLE_V);
+    }
+    cc_prolong_correct(H.dim, n, u, uc);
+    for (int s = 0; s < H.nu2; ++s) cc_smooth(H, L, u, f);
+}
+
+bool cc_valid(int dim, int n) { return (dim == 2 || dim == 3) && n >= 2 && (n & (n - 1)) == 0; }
+
 } /* namespace */
 
 /* ==================================================================== */
@@ -970,6 +1196,65 @@ int orc_solve_ir_mg_f16(int dim, int n, const double* k64, int smoother, double 
         const double rho = orc_ir_update_f16(dim, n, k64, u, (const uint16_t*)e.data(), s, f, s_next,
                                              (uint16_t*)r16.data(), &mx);
         s = s_next;
+        if (hist) hist[it] = rho;
+        if (rho <= tol * rho0) status = 0;
+        else if (!(rho == rho) || rho > 1e6 * rho0) status = -5;
+    }
+    if (cycles) *cycles = it;
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Cell-centred Neumann problems (FP64).  Arrays hold n^dim cell values. */
+/* ------------------------------------------------------------------ */
+
+void orc_cc_residual(int dim, int n, const double* u, const double* f, double* r) {
+    cc_residual(cc_level(dim, n, 1.0), u, f, r);
+}
+/* one smoothing sweep in place (0 RBGS red first, 1 Jacobi) */
+void orc_cc_smooth(int dim, int n, int smoother, double omega, double* u, const double* f) {
+    const CCLevel L = cc_level(dim, n, omega);
+    std::vector<double> tmp;
+    if (smoother == SMOOTH_JACOBI) cc_jacobi(L, u, f, tmp);
+    else cc_rbgs(L, u, f);
+}
+void orc_cc_restrict(int dim, int nf, const double* r, double* fc) { cc_restrict(dim, nf, r, fc); }
+void orc_cc_prolong_correct(int dim, int nf, double* u, const double* ec) { cc_prolong_correct(dim, nf, u, ec); }
+double orc_cc_sum(int dim, int n, const double* u) { return cc_sum(dim, n, u); }
+double orc_cc_residual_norm(int dim, int n, const double* u, const double* f) {
+    return cc_residual_norm(cc_level(dim, n, 1.0), u, f);
+}
+/* one cycle on u (no mean handling) */
+int orc_cc_cycle(int dim, int n, int smoother, double omega, int nu1, int nu2, int cycle, double* u,
+                 const double* f) {
+    if (!cc_valid(dim, n) || cycle < CYCLE_V || cycle > CYCLE_F) return -1;
+    CCHierarchy H;
+    cc_build(H, dim, n, smoother, omega, nu1, nu2, cycle);
+    cc_cycle(H, 0, u, f, cycle);
+    return 0;
+}
+/* Solve: fh = f - mean(f) (the compatible right-hand side), u -= mean(u);
+ * rho_0 = ||fh - A u||; then cycles, each followed by u -= mean(u), until
+ * rho_k <= tol rho_0 or max_cycles.  fh_out (may be NULL) receives fh. */
+int orc_cc_solve(int dim, int n, int smoother, double omega, int nu1, int nu2, int cycle, double* u,
+                 const double* f, double tol, int max_cycles, double* hist, int* cycles, double* fh_out) {
+    if (!cc_valid(dim, n) || cycle < CYCLE_V || cycle > CYCLE_F || max_cycles < 0) return -1;
+    CCHierarchy H;
+    cc_build(H, dim, n, smoother, omega, nu1, nu2, cycle);
+    const size_t N = cc_cells(dim, n);
+    std::vector<double> fh(f, f + N);
+    cc_remove_mean(dim, n, fh.data());
+    if (fh_out) std::memcpy(fh_out, fh.data(), N * sizeof(double));
+    cc_remove_mean(dim, n, u);
+    const CCLevel L0 = cc_level(dim, n, omega);
+    const double rho0 = cc_residual_norm(L0, u, fh.data());
+    if (hist) hist[0] = rho0;
+    int it = 0, status = rho0 == 0.0 ? 0 : 1;
+    while (status == 1 && it < max_cycles) {
+        cc_cycle(H, 0, u, fh.data(), cycle);
+        cc_remove_mean(dim, n, u);
+        ++it;
+        const double rho = cc_residual_norm(L0, u, fh.data());
         if (hist) hist[it] = rho;
         if (rho <= tol * rho0) status = 0;
         else if (!(rho == rho) || rho > 1e6 * rho0) status = -5;

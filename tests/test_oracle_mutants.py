@@ -59,9 +59,21 @@ MUTANTS = {
     "fp16_correction_not_unscaled": ("u[p] = u[p] + (double)half_to_float(e16[p]) * inv;",
                                      "u[p] = u[p] + (double)half_to_float(e16[p]);"),
     "fp16_residual_not_scaled": ("r16[p] = float_to_half(s32 * (float)r[p]);", "r16[p] = float_to_half((float)r[p]);"),
+    "cc_ghost_zero": ("const double uW = i > 0 ? u[p - 1] : uC, uE = i < n - 1 ? u[p + 1] : uC;",
+                      "const double uW = i > 0 ? u[p - 1] : 0.0, uE = i < n - 1 ? u[p + 1] : uC;"),
+    "cc_diagonal_not_reduced": ("L.wd[m] = (omega * (h * h)) / (double)(2 * dim - m);",
+                                "L.wd[m] = (omega * (h * h)) / (double)(2 * dim);"),
+    "cc_restrict_3d_weight": ("fc[cc_at(dim, nc, I, J, K)] = 0.125 * (q0 + q1);",
+                              "fc[cc_at(dim, nc, I, J, K)] = 0.25 * (q0 + q1);"),
+    "cc_prolong_transposed": ("u[p] = u[p] + ec[cc_at(dim, nc, i / 2, j / 2, dim == 3 ? k / 2 : 0)];",
+                              "u[p] = u[p] + ec[cc_at(dim, nc, j / 2, i / 2, dim == 3 ? k / 2 : 0)];"),
+    "cc_rhs_mean_kept": ("    cc_remove_mean(dim, n, fh.data());\n", ""),
+    "cc_sum_skips_last_cell": ("for (int i = 0; i < n; ++i) row += u[cc_at(dim, n, i, j, k)];",
+                               "for (int i = 0; i < n - 1; ++i) row += u[cc_at(dim, n, i, j, k)];"),
 }
 
-PIN_FILES = ["test_oracle_pins.py", "test_oracle_pins_variants.py", "test_oracle_pins_fp16.py"]
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_pins_variants.py", "test_oracle_pins_fp16.py",
+             "test_oracle_pins_cc.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
