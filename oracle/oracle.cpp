@@ -775,15 +775,23 @@ void cc_remove_mean(int dim, int n, double* v) {
     for (size_t p = 0; p < N; ++p) v[p] = v[p] - mean;
 }
 
+/* ||f - A u||_2 over all cells, squares summed per x-row, then the rows of a
+ * plane, then the planes (partial sums keep the rounding of the sum small) */
 double cc_residual_norm(const CCLevel& L, const double* u, const double* f) {
     const int n = L.n;
     double s = 0.0;
-    for (int k = 0; k < cc_k1(L.dim, n); ++k)
-        for (int j = 0; j < n; ++j)
+    for (int k = 0; k < cc_k1(L.dim, n); ++k) {
+        double plane = 0.0;
+        for (int j = 0; j < n; ++j) {
+            double row = 0.0;
             for (int i = 0; i < n; ++i) {
                 const double r = f[cc_at(L.dim, n, i, j, k)] - cc_apply(L.dim, n, L.c, u, i, j, k);
-                s += r * r;
+                row += r * r;
             }
+            plane += row;
+        }
+        s += plane;
+    }
     return std::sqrt(s);
 }
 
