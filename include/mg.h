@@ -54,7 +54,19 @@ enum mg_operator {
     MG_OP_LAPLACE = 0,       /* constant 5-point (2D) / 7-point (3D) stencil, Section 2.2 */
     MG_OP_VARCOEF_NODAL = 2  /* -div(k grad u): nodal k, face k = 2 k_p k_q / (k_p + k_q) */
 };
-enum mg_bc { MG_BC_DIRICHLET_ZERO = 0 };
+enum mg_bc {
+    MG_BC_DIRICHLET_ZERO = 0,  /* node-based grid, n = 2^L + 1 nodes per axis, zero boundary values */
+    MG_BC_NEUMANN_CC = 1       /* cell-centred grid (Table 1), n = 2^L cells per axis (L >= 1; at most
+                                  8192 in 2D, 512 in 3D), h = 1/n, homogeneous Neumann boundary (zero
+                                  flux: a neighbour outside the domain takes the cell's own value);
+                                  arrays hold n^dim cell values, no boundary entries.  Restriction
+                                  averages the 2^d children, interpolation is constant, the coarsest
+                                  level is one cell (zero correction).  The operator is singular:
+                                  mg_solve projects f onto mean zero (a context copy; the residual
+                                  history is that of the projected f) and keeps u at mean zero after
+                                  every cycle, sums in a fixed order.  MG_OP_LAPLACE, MG_PREC_FP64,
+                                  RBGS or Jacobi smoothing, coarse_n 0 (MG_ENOTSUP otherwise). */
+};
 enum mg_smoother {
     MG_SMOOTH_RBGS = 0,     /* red-black Gauss-Seidel, red ((i+j[+k]) even) first, Section 2.4 */
     MG_SMOOTH_WJACOBI = 1,  /* weighted Jacobi, Section 2.3; omega 0.8 in Table 2 */
@@ -197,6 +209,19 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
  * 65 / 17 otherwise (MG_ENOTSUP beyond). */
 int mg_level_coarsest_cg(int dim, int n, int dtype, const void* k, void* u, const void* f, int iters,
                          void* stream);
+
+/* Cell-centred Neumann grids (MG_BC_NEUMANN_CC), FP64, n = 2^L cells per axis
+ * (n >= 2), the operations of a cycle: one smoothing sweep u_in -> u_out
+ * (smoother 0 RBGS red first, 1 Jacobi); fc = average of the children's
+ * residuals (n/2 cells per axis); u += constant interpolation of ec; and
+ * v -= mean(v), *mean_out (HOST) = the mean removed (sum in the fixed order:
+ * each x-row, the rows of a plane, the planes).  The first three are
+ * asynchronous; the last synchronises the stream. */
+int mg_level_cc_smooth(int dim, int n, int smoother, double omega, const double* u_in, const double* f,
+                       double* u_out, void* stream);
+int mg_level_cc_residual_restrict(int dim, int n, const double* u, const double* f, double* fc, void* stream);
+int mg_level_cc_prolong_correct(int dim, int n, double* u, const double* ec, void* stream);
+int mg_level_cc_remove_mean(int dim, int n, double* v, double* mean_out, void* stream);
 
 /* dtype 2 in the four calls above: binary16 arrays (u, f, the coarse arrays),
  * arithmetic in FP32, each value the method stores rounded to binary16 (the

@@ -24,7 +24,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mg.h")
 # status codes (enum mg_status)
 MG_OK, MG_ENOTCONV, MG_EINVAL, MG_ENOTSUP, MG_ENOMEM, MG_EDEVICE, MG_EDIVERGED, MG_EBUSY = 0, 1, -1, -2, -3, -4, -5, -6
 OP_LAPLACE, OP_VARCOEF_NODAL = 0, 2
-BC_DIRICHLET_ZERO = 0
+BC_DIRICHLET_ZERO, BC_NEUMANN_CC = 0, 1
 SMOOTH_RBGS, SMOOTH_JACOBI, SMOOTH_RBGS_SYM = 0, 1, 2
 CYCLE_V, CYCLE_W, CYCLE_F = 0, 1, 2
 PREC_FP64, PREC_FP32_IR, PREC_FP16_IR = 0, 1, 2
@@ -95,6 +95,10 @@ def lib():
             "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
             "mg_level_coarsest_cg": (i, [i, i, i, p, p, p, i, p]),
+            "mg_level_cc_smooth": (i, [i, i, i, d, p, p, p, p]),
+            "mg_level_cc_residual_restrict": (i, [i, i, p, p, p, p]),
+            "mg_level_cc_prolong_correct": (i, [i, i, p, p, p]),
+            "mg_level_cc_remove_mean": (i, [i, i, p, C.POINTER(d), p]),
             "mg_level_ir_update": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, i, p]),
             "mg_level_ir_update_noalloc": (i, [i, i, p, p, p, p, p, p, C.POINTER(d), i, i, i, i, i, p]),
             "mg_level_ir_update_f16": (i, [i, i, p, p, d, d, p, p, p, C.POINTER(d), C.POINTER(d), i, i, i, i, p]),
@@ -351,6 +355,45 @@ def mg_level_coarsest_cg(u, f, k=None, iters=0, stream=None) -> None:
     dt = f.dtype
     _check(lib().mg_level_coarsest_cg(dim, n, _dtype_code(f), _dptr(k, dt, f.shape, "k"), _dptr(u, dt, f.shape, "u"),
                                       _dptr(f, dt, f.shape, "f"), int(iters), _stream(stream)), "mg_level_coarsest_cg")
+
+
+# cell-centred Neumann grids (FP64, n = 2^L cells per axis)
+def mg_level_cc_smooth(u_in, f, u_out, smoother=SMOOTH_RBGS, omega=0.0, stream=None) -> None:
+    import torch
+
+    dim, n = f.dim(), f.shape[0]
+    _check(lib().mg_level_cc_smooth(dim, n, smoother, float(omega), _dptr(u_in, torch.float64, f.shape, "u_in"),
+                                    _dptr(f, torch.float64, None, "f"), _dptr(u_out, torch.float64, f.shape, "u_out"),
+                                    _stream(stream)), "mg_level_cc_smooth")
+
+
+def mg_level_cc_residual_restrict(u, f, fc, stream=None) -> None:
+    import torch
+
+    dim, n = f.dim(), f.shape[0]
+    _check(lib().mg_level_cc_residual_restrict(dim, n, _dptr(u, torch.float64, f.shape, "u"),
+                                               _dptr(f, torch.float64, None, "f"),
+                                               _dptr(fc, torch.float64, (n // 2,) * dim, "fc"), _stream(stream)),
+           "mg_level_cc_residual_restrict")
+
+
+def mg_level_cc_prolong_correct(u, ec, stream=None) -> None:
+    import torch
+
+    dim, n = u.dim(), u.shape[0]
+    _check(lib().mg_level_cc_prolong_correct(dim, n, _dptr(u, torch.float64, None, "u"),
+                                             _dptr(ec, torch.float64, (n // 2,) * dim, "ec"), _stream(stream)),
+           "mg_level_cc_prolong_correct")
+
+
+def mg_level_cc_remove_mean(v, stream=None) -> float:
+    import torch
+
+    dim, n = v.dim(), v.shape[0]
+    out = C.c_double(0.0)
+    _check(lib().mg_level_cc_remove_mean(dim, n, _dptr(v, torch.float64, None, "v"), C.byref(out), _stream(stream)),
+           "mg_level_cc_remove_mean")
+    return out.value
 
 
 def mg_level_ir_update(u_in, e, f, u_out, r, k=None, by=0, zchunk=0, prefetch=0, waves=0, pairs=0,

@@ -30,6 +30,7 @@ SOURCES = [
     "mg_capi.hip",
     "mg_batch.hip",
     "mg_tail.hip",
+    "mg_cc.hip",
 ]
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -8,6 +8,7 @@
 #include <new>
 #include <tuple>
 
+#include "mg_cc.h"
 #include "mg_solver.h"
 
 using namespace mg;
@@ -165,9 +166,23 @@ void free_groups(std::vector<Group>& G) {
     G.clear();
 }
 
+// Cell-centred Neumann grids: n = 2^L cells per axis (L >= 1).
+bool valid_cc(int dim, int n) { return n >= 2 && (n & (n - 1)) == 0 && n <= (dim == 2 ? 8192 : 512); }
+
+int validate_cc(const mg_params* p) {
+    if (!valid_cc(p->dim, p->n)) return MG_EINVAL;
+    if (p->smoother != MG_SMOOTH_RBGS && p->smoother != MG_SMOOTH_WJACOBI) return MG_EINVAL;
+    if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 > 16 || p->nu2 > 16) return MG_EINVAL;
+    if (p->cycle < MG_CYCLE_V || p->cycle > MG_CYCLE_F || p->cg_iters < 0) return MG_EINVAL;
+    if (!(p->omega == p->omega) || p->omega > 2.0) return MG_EINVAL;
+    if (p->op != MG_OP_LAPLACE || p->precision != MG_PREC_FP64 || p->coarse_n != 0) return MG_ENOTSUP;
+    return MG_OK;
+}
+
 int validate(const mg_params* p) {
     if (!p) return MG_EINVAL;
     if (p->dim != 2 && p->dim != 3) return MG_EINVAL;
+    if (p->bc == MG_BC_NEUMANN_CC) return validate_cc(p);
     if (!valid_edge(p->dim, p->n)) return MG_EINVAL;
     if (p->bc != MG_BC_DIRICHLET_ZERO) return MG_ENOTSUP;
     if (p->op != MG_OP_LAPLACE && p->op != MG_OP_VARCOEF_NODAL) return MG_ENOTSUP;
@@ -196,6 +211,14 @@ void destroy(mg_ctx* c) {
     ffree(c->tail32.d);
     free_levels(c->L64);
     free_levels(c->L32);
+    for (size_t l = 0; l < c->ccn.size(); ++l) {
+        if (l > 0) ffree(c->ccu[l]);
+        ffree(c->cct[l]);
+        if (l > 0) ffree(c->ccf[l]);
+    }
+    ffree(c->ccfh);
+    ffree(c->cc_work);
+    ffree(c->cc_mean);
     ffree(c->d_ir);
     ffree(c->d_scl);
     ffree(c->d_pmax);
@@ -385,6 +408,140 @@ int next_chunk(const double* hist, int steps, double tol, int kmax) {
     return std::max(1, std::min(kmax, (int)std::ceil(need - 1e-9)));
 }
 
+
+// ---------------------------------------------------------------------------
+// Cell-centred Neumann grids: Algorithm 1 level by level (V, W or F), plain
+// kernels; the iterate of level l is in 'cur' (the other buffer of the level
+// is the Jacobi partner).  Returns the buffer that holds the result.
+// ---------------------------------------------------------------------------
+hipError_t cc_smooth_level(mg_ctx* c, int l, double*& cur, double*& other, const double* f, CCConst L) {
+    const int dim = c->p.dim;
+    hipStream_t s = c->stream;
+    if (c->p.smoother == MG_SMOOTH_WJACOBI) {
+        hipError_t e = cc_relax(dim, true, cur, other, f, L, 0, s);
+        std::swap(cur, other);
+        return e;
+    }
+    hipError_t e = cc_relax(dim, false, cur, cur, f, L, 0, s);
+    if (e != hipSuccess) return e;
+    return cc_relax(dim, false, cur, cur, f, L, 1, s);
+}
+
+hipError_t cc_cycle(mg_ctx* c, int l, int kind, double*& cur, double*& other, const double* f) {
+    const int dim = c->p.dim, n = c->ccn[(size_t)l];
+    hipStream_t s = c->stream;
+    hipError_t e = hipSuccess;
+    if (l + 1 == (int)c->ccn.size()) return cc_fill(cur, cc_cells(dim, n), 0.0, s);  // one cell: zero correction
+    const CCConst L = cc_const(dim, n, c->p.omega);
+    for (int i = 0; i < c->p.nu1 && e == hipSuccess; ++i) e = cc_smooth_level(c, l, cur, other, f, L);
+    if (e != hipSuccess) return e;
+    double* fc = c->ccf[(size_t)l + 1];
+    e = cc_restrict(dim, cur, f, fc, L, s);
+    if (e != hipSuccess) return e;
+    double* ucur = c->ccu[(size_t)l + 1];
+    double* uoth = c->cct[(size_t)l + 1];
+    e = cc_fill(ucur, cc_cells(dim, n / 2), 0.0, s);
+    if (e != hipSuccess) return e;
+    if (kind == MG_CYCLE_V) {
+        e = cc_cycle(c, l + 1, MG_CYCLE_V, ucur, uoth, fc);
+    } else if (kind == MG_CYCLE_W) {
+        e = cc_cycle(c, l + 1, MG_CYCLE_W, ucur, uoth, fc);
+        if (e == hipSuccess) e = cc_cycle(c, l + 1, MG_CYCLE_W, ucur, uoth, fc);
+    } else {
+        e = cc_cycle(c, l + 1, MG_CYCLE_F, ucur, uoth, fc);
+        if (e == hipSuccess) e = cc_cycle(c, l + 1, MG_CYCLE_V, ucur, uoth, fc);
+    }
+    if (e != hipSuccess) return e;
+    // the coarse buffers keep their roles for the next cycle
+    c->ccu[(size_t)l + 1] = ucur;
+    c->cct[(size_t)l + 1] = uoth;
+    e = cc_prolong(dim, cur, ucur, n, s);
+    for (int i = 0; i < c->p.nu2 && e == hipSuccess; ++i) e = cc_smooth_level(c, l, cur, other, f, L);
+    return e;
+}
+
+// One cycle on the caller's u (level 0), the result back in u.
+hipError_t cc_cycle_top(mg_ctx* c, double* u, const double* f) {
+    double* cur = u;
+    double* other = c->cct[0];
+    hipError_t e = cc_cycle(c, 0, c->p.cycle, cur, other, f);
+    if (e == hipSuccess && cur != u)
+        e = hipMemcpyAsync(u, cur, cc_cells(c->p.dim, c->p.n) * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    return e;
+}
+
+int cc_setup(mg_ctx* c) {
+    const int dim = c->p.dim;
+    hipStream_t s = c->stream;
+    c->cc = true;
+    for (int m = c->p.n; m >= 1; m /= 2) c->ccn.push_back(m);
+    const size_t L = c->ccn.size();
+    c->ccu.assign(L, nullptr);
+    c->cct.assign(L, nullptr);
+    c->ccf.assign(L, nullptr);
+    for (size_t l = 0; l < L; ++l) {
+        const size_t bytes = cc_cells(dim, c->ccn[l]) * sizeof(double);
+        if (l > 0) CK(zalloc((void**)&c->ccu[l], bytes, s));
+        CK(zalloc((void**)&c->cct[l], bytes, s));
+        if (l > 0) CK(zalloc((void**)&c->ccf[l], bytes, s));
+    }
+    CK(zalloc((void**)&c->ccfh, cc_cells(dim, c->p.n) * sizeof(double), s));
+    CK(hipMalloc((void**)&c->cc_work, cc_work_doubles(dim, c->p.n) * sizeof(double)));
+    CK(hipMalloc((void**)&c->cc_mean, sizeof(double)));
+    c->nlev = (int)L;
+    c->pstride = cc_norm_parts(dim, c->p.n);
+    CK(hipMalloc((void**)&c->d_partial, sizeof(double) * (size_t)c->pstride));
+    CK(hipMalloc((void**)&c->d_norm, sizeof(double)));
+    CK(hipMalloc((void**)&c->d_norm0, sizeof(double)));
+    CK(hipMalloc((void**)&c->d_ctrl, 3 * sizeof(int)));
+    CK(launch_fill_int(c->d_ctrl, 0, 3, s));
+    int r = ensure_hist(c, 64);
+    if (r != MG_OK) return r;
+    CK(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
+int cc_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, int* cycles_done, double* res_hist) {
+    const int dim = c->p.dim, n = c->p.n;
+    hipStream_t s = c->stream;
+    const CCConst L0 = cc_const(dim, n, c->p.omega);
+    int r = ensure_hist(c, max_cycles + 1);
+    if (r != MG_OK) return r;
+    CK(hipMemcpyAsync(c->ccfh, f, cc_cells(dim, n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CK(cc_remove_mean(dim, n, c->ccfh, c->cc_work, c->cc_mean, s));
+    CK(cc_remove_mean(dim, n, u, c->cc_work, c->cc_mean, s));
+    CK(launch_fill_int(ctl_done(c), 0, 1, s));
+    CK(cc_norm(dim, u, c->ccfh, L0, c->d_partial, c->d_norm, s));
+    CK(launch_solve_init(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist, c->hist_cap, 1,
+                         s));
+    int* ctl = (int*)c->h_pin;
+    CK(hipMemcpyAsync(ctl, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    int steps = 0;
+    // one cycle per round trip: the host keeps the Jacobi buffer roles, so no
+    // cycle is queued past the stop test
+    while (!ctl[0] && steps < max_cycles) {
+        CK(cc_cycle_top(c, u, c->ccfh));
+        CK(cc_remove_mean(dim, n, u, c->cc_work, c->cc_mean, s));
+        CK(cc_norm(dim, u, c->ccfh, L0, c->d_partial, c->d_norm, s));
+        CK(launch_stop_test(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist, c->hist_cap,
+                            tol, max_cycles, 1, s));
+        CK(hipMemcpyAsync(ctl, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        ++steps;
+    }
+    steps = ctl[1];
+    const int status = ctl[2];
+    if (res_hist) {
+        CK(hipMemcpyAsync(c->h_pin, c->d_hist, sizeof(double) * (size_t)(steps + 1), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        std::memcpy(res_hist, c->h_pin, sizeof(double) * (size_t)(steps + 1));
+    }
+    if (cycles_done) *cycles_done = steps;
+    if (status == 0) return MG_OK;
+    if (status == -5) return MG_EDIVERGED;
+    return MG_ENOTCONV;
+}
 
 // ---------------------------------------------------------------------------
 // Autotuner: for every level large enough to matter, time each candidate
@@ -730,6 +887,16 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
     c->p = *p;
     if (c->p.omega <= 0.0) c->p.omega = p->smoother == MG_SMOOTH_WJACOBI ? 0.8 : 1.0;
     c->stream = (hipStream_t)stream;
+    if (p->bc == MG_BC_NEUMANN_CC) {
+        (void)hipGetDevice(&c->device);
+        const int r = cc_setup(c);
+        if (r != MG_OK) {
+            destroy(c);
+            return r;
+        }
+        *out = c;
+        return MG_OK;
+    }
     c->use_graphs = std::getenv("MG_NO_GRAPHS") == nullptr;
     (void)hipGetDevice(&c->device);
     const int dim = p->dim;
@@ -877,6 +1044,11 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
 int mg_vcycle(mg_ctx* c, double* u, const double* f) {
     if (!c) return MG_EINVAL;
     if (is_batch_handle(c)) return MG_EINVAL;
+    if (c->cc) {
+        if (!u || !f) return MG_EINVAL;
+        CK(cc_cycle_top(c, u, f));
+        return MG_OK;
+    }
     int r = bind(c, u, f);
     if (r != MG_OK) return r;
     CK(launch_fill_int(ctl_done(c), 0, 1, c->stream));
@@ -896,6 +1068,14 @@ int mg_vcycle(mg_ctx* c, double* u, const double* f) {
 int mg_residual_norm(mg_ctx* c, const double* u, const double* f, double* out) {
     if (!c || !out) return MG_EINVAL;
     if (is_batch_handle(c)) return MG_EINVAL;
+    if (c->cc) {
+        if (!u || !f) return MG_EINVAL;
+        CK(cc_norm(c->p.dim, u, f, cc_const(c->p.dim, c->p.n, c->p.omega), c->d_partial, c->d_norm, c->stream));
+        CK(hipMemcpyAsync(c->h_pin, c->d_norm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        CK(hipStreamSynchronize(c->stream));
+        *out = c->h_pin[0];
+        return MG_OK;
+    }
     int r = bind(c, u, f);
     if (r != MG_OK) return r;
     CK(enqueue_norm(c, c->stream));
@@ -908,6 +1088,10 @@ int mg_residual_norm(mg_ctx* c, const double* u, const double* f, double* out) {
 int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, int* cycles_done, double* res_hist) {
     if (!c || max_cycles < 0 || !(tol >= 0.0)) return MG_EINVAL;
     if (is_batch_handle(c)) return MG_EINVAL;
+    if (c->cc) {
+        if (!u || !f) return MG_EINVAL;
+        return cc_solve(c, u, f, tol, max_cycles, cycles_done, res_hist);
+    }
     int r = bind(c, u, f);
     if (r != MG_OK) return r;
     r = ensure_hist(c, max_cycles + 1);
@@ -1265,6 +1449,53 @@ int mg_level_ir_update_f16(int dim, int n, const double* u_in, const void* e16, 
     if (e2 != hipSuccess) return dev_status(e2);
     *norm_out = host[0];
     *max_out = host[1];
+    return MG_OK;
+}
+
+int mg_level_cc_smooth(int dim, int n, int smoother, double omega, const double* u_in, const double* f,
+                       double* u_out, void* stream) {
+    if ((dim != 2 && dim != 3) || !valid_cc(dim, n) || !u_in || !f || !u_out || (smoother != 0 && smoother != 1))
+        return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (omega <= 0.0) omega = smoother == 1 ? 0.8 : 1.0;
+    const CCConst L = cc_const(dim, n, omega);
+    if (smoother == 1) {
+        if (u_in == u_out) return MG_EINVAL;
+        CK(cc_relax(dim, true, u_in, u_out, f, L, 0, s));
+        return MG_OK;
+    }
+    if (u_in != u_out)
+        CK(hipMemcpyAsync(u_out, u_in, cc_cells(dim, n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CK(cc_relax(dim, false, u_out, u_out, f, L, 0, s));
+    CK(cc_relax(dim, false, u_out, u_out, f, L, 1, s));
+    return MG_OK;
+}
+
+int mg_level_cc_residual_restrict(int dim, int n, const double* u, const double* f, double* fc, void* stream) {
+    if ((dim != 2 && dim != 3) || !valid_cc(dim, n) || !u || !f || !fc) return MG_EINVAL;
+    CK(cc_restrict(dim, u, f, fc, cc_const(dim, n, 1.0), (hipStream_t)stream));
+    return MG_OK;
+}
+
+int mg_level_cc_prolong_correct(int dim, int n, double* u, const double* ec, void* stream) {
+    if ((dim != 2 && dim != 3) || !valid_cc(dim, n) || !u || !ec) return MG_EINVAL;
+    CK(cc_prolong(dim, u, ec, n, (hipStream_t)stream));
+    return MG_OK;
+}
+
+int mg_level_cc_remove_mean(int dim, int n, double* v, double* mean_out, void* stream) {
+    if ((dim != 2 && dim != 3) || !valid_cc(dim, n) || !v || !mean_out) return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    double* buf = nullptr;
+    CK(hipMalloc((void**)&buf, (cc_work_doubles(dim, n) + 1) * sizeof(double)));
+    hipError_t e = cc_remove_mean(dim, n, v, buf + 1, buf, s);
+    double m = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&m, buf, sizeof(double), hipMemcpyDeviceToHost, s);
+    const hipError_t e2 = hipStreamSynchronize(s);
+    ffree(buf);
+    if (e != hipSuccess) return dev_status(e);
+    if (e2 != hipSuccess) return dev_status(e2);
+    *mean_out = m;
     return MG_OK;
 }
 

@@ -146,6 +146,16 @@ struct mg_ctx {
     hipStream_t cap_stream = nullptr;
     std::vector<ChunkGraph> graphs;
 
+    // cell-centred Neumann grid (bc MG_BC_NEUMANN_CC): levels n, n/2, ..., 1 cells
+    // per axis; level 0's iterate is the caller's, its right-hand side the
+    // context's mean-zero copy ccfh
+    bool cc = false;
+    std::vector<int> ccn;
+    std::vector<double*> ccu, cct, ccf;
+    double* ccfh = nullptr;
+    double* cc_work = nullptr;  // fixed-order sums (row and plane sums)
+    double* cc_mean = nullptr;  // [1]
+
     // measurement
     // measurement hooks: event pairs of the current solve, tagged with their
     // refinement step and kernel (0 finest plain sweeps, 1 finest refinement /

@@ -73,7 +73,8 @@ def test_black_first_sweep_bitwise(dim, n, by, zc, pd, wv, dt, fused, dev_ok):
     """The post-smoothing sweep of the symmetric smoother (black first), plain
     and with the coarse-grid correction fused in."""
     u, f, _ = arrays(dim, n, dt, n)
-    if dt == np.float64 and dim == 3 and (by // (wv or 4) > 4 or (wv == 1 and by > 8)):
+    over = (by > 8) if wv == 1 else (by // (wv or 4) > 4)
+    if dt == np.float64 and dim == 3 and over:
         # beyond the FP64 register limit of the 3D sweeps: rejected before any launch
         with pytest.raises(mg().MGError) as ei:
             mg().mg_level_smooth(dev(u), dev(f), dev(np.zeros_like(u)), smoother=SYM, by=by, zchunk=zc, prefetch=pd,
