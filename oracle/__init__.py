@@ -101,6 +101,12 @@ def _load():
         "orc_cc_residual_norm": (_d, [_i, _i, _p, _p]),
         "orc_cc_cycle": (_i, [_i, _i, _i, _d, _i, _i, _i, _p, _p]),
         "orc_cc_solve": (_i, [_i, _i, _i, _d, _i, _i, _i, _p, _p, _d, _i, _p, _p, _p]),
+        "orc_cd_apply": (None, [_i, _i, _d, _d, _d, _d, _d, _p, _p]),
+        "orc_cd_g": (None, [_i, _i, _d, _d, _d, _d, _p, _p]),
+        "orc_cd_sweep": (None, [_i, _i, _d, _d, _d, _d, _d, _i, _d, _p, _p]),
+        "orc_cd_residual_norm": (_d, [_i, _i, _d, _d, _d, _d, _d, _p, _p]),
+        "orc_cd_fas": (_i, [_i, _i, _d, _d, _d, _d, _d, _i, _d, _i, _i, _p, _p]),
+        "orc_cd_run": (_i, [_i, _i, _d, _d, _d, _d, _d, _i, _d, _i, _i, _p, _i, _d, _i, _p, _p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -425,3 +431,81 @@ def cc_solve(u0, f, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0, nu
     if rc == -1:
         raise ValueError("oracle solve rejected its arguments")
     return u, hist[: cyc.value + 1].copy(), rc, fh
+
+
+# ------------------------------------------------------------------ complex diffusion
+# Complex cell arrays are numpy complex128 (re, im pairs), n = 2^L cells per axis.
+# The diffusivity g(s) = e^{i theta} / (1 + (s / (k theta))^2) takes cos(theta)
+# and sin(theta) as evaluated here (math.cos / math.sin), the same numbers the
+# library's host code passes to its kernels.
+import math as _math  # noqa: E402
+
+
+class CD:
+    """Parameters of the complex-diffusion problem."""
+
+    def __init__(self, tau, theta=_math.pi / 30, k=1.0):
+        self.tau, self.theta, self.k = float(tau), float(theta), float(k)
+        self.ct, self.st = _math.cos(self.theta), _math.sin(self.theta)
+
+    def args(self):
+        return (self.tau, self.theta, self.k, self.ct, self.st)
+
+
+def _cchk(a, name):
+    return _chk(a, np.complex128, name)
+
+
+def cd_apply(u, P: CD):
+    """N(u) = u / tau - div(g(Im u) grad u) (cell-centred, Neumann)."""
+    _cchk(u, "u")
+    dim, n = _cc_dims(u)
+    out = np.zeros_like(u)
+    _load().orc_cd_apply(dim, n, *P.args(), _ptr(u), _ptr(out))
+    return out
+
+
+def cd_g(u, P: CD):
+    _cchk(u, "u")
+    dim, n = _cc_dims(u)
+    g = np.zeros_like(u)
+    _load().orc_cd_g(dim, n, P.theta, P.k, P.ct, P.st, _ptr(u), _ptr(g))
+    return g
+
+
+def cd_sweep(u, f, P: CD, smoother=SMOOTH_RBGS, omega=1.0):
+    _cchk(u, "u"), _cchk(f, "f")
+    dim, n = _cc_dims(u)
+    out = u.copy()
+    _load().orc_cd_sweep(dim, n, *P.args(), smoother, omega, _ptr(out), _ptr(f))
+    return out
+
+
+def cd_residual_norm(u, f, P: CD) -> float:
+    _cchk(u, "u"), _cchk(f, "f")
+    dim, n = _cc_dims(u)
+    return float(_load().orc_cd_residual_norm(dim, n, *P.args(), _ptr(u), _ptr(f)))
+
+
+def cd_fas(u, f, P: CD, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2):
+    _cchk(u, "u"), _cchk(f, "f")
+    dim, n = _cc_dims(u)
+    out = u.copy()
+    if _load().orc_cd_fas(dim, n, *P.args(), smoother, omega, nu1, nu2, _ptr(out), _ptr(f)) != 0:
+        raise ValueError("oracle FAS cycle rejected its arguments")
+    return out
+
+
+def cd_run(u0, P: CD, steps=1, tol=1e-5, max_cycles=20, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2):
+    """Implicit-Euler time steps with FAS per step.  Returns (u, cycles per step,
+    residual histories per step (list of arrays), status)."""
+    _cchk(u0, "u0")
+    dim, n = _cc_dims(u0)
+    u = u0.copy()
+    cyc = np.zeros(max(steps, 1), dtype=np.int32)
+    hist = np.zeros((max(steps, 1), max_cycles + 1))
+    rc = _load().orc_cd_run(dim, n, *P.args(), smoother, omega, nu1, nu2, _ptr(u), steps, tol, max_cycles,
+                            _ptr(cyc), _ptr(hist))
+    if rc == -1:
+        raise ValueError("oracle run rejected its arguments")
+    return u, cyc[:steps].copy(), [hist[m, : cyc[m] + 1].copy() for m in range(steps)], rc

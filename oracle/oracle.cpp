@@ -863,6 +863,266 @@ void cc_cycle(CCHierarchy& H, int l, double* u, const double* f, int kind) {
 
 bool cc_valid(int dim, int n) { return (dim == 2 || dim == 3) && n >= 2 && (n & (n - 1)) == 0; }
 
+/* ------------------------------------------------------------------ */
+/* Complex diffusion (Section 4, Eq. (2)): u_t = div(g(Im u) grad u) on   */
+/* the unit square / cube with a homogeneous Neumann boundary,            */
+/* g(s) = e^{i theta} / (1 + (s / (k theta))^2).  Cell-centred averaged   */
+/* finite differences (face diffusivity = mean of the two cells' values), */
+/* implicit Euler in time, and per time step the full approximation       */
+/* scheme (FAS) with lagged diffusivity: every smoothing sweep and every  */
+/* residual uses g of the iterate it starts from.  Transfers: averaging   */
+/* restriction, constant interpolation.  Complex values are (re, im)      */
+/* pairs of doubles with the arithmetic written out in a fixed order.     */
+/* ------------------------------------------------------------------ */
+
+struct Cx {
+    double re, im;
+};
+inline Cx cx_add(Cx a, Cx b) { return Cx{a.re + b.re, a.im + b.im}; }
+inline Cx cx_sub(Cx a, Cx b) { return Cx{a.re - b.re, a.im - b.im}; }
+inline Cx cx_mul(Cx a, Cx b) { return Cx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+inline Cx cx_div(Cx a, Cx b) {
+    const double den = b.re * b.re + b.im * b.im;
+    return Cx{(a.re * b.re + a.im * b.im) / den, (a.im * b.re - a.re * b.im) / den};
+}
+inline Cx cx_scale(double s, Cx a) { return Cx{s * a.re, s * a.im}; }
+
+/* parameters of the complex-diffusion problem; ct, st = cos theta, sin theta */
+struct CDParams {
+    int dim;
+    double tau, itau, ktheta, ct, st;
+};
+
+/* g(Im u) = (cos theta, sin theta) / (1 + (Im u / (k theta))^2) */
+inline Cx cd_g(const CDParams& P, Cx u) {
+    const double s = u.im / P.ktheta;
+    const double q = 1.0 / (1.0 + s * s);
+    return Cx{P.ct * q, P.st * q};
+}
+
+/* flux sum F = sum over faces of g_face (u_q - u_p) and diagonal sum S of the
+ * face coefficients, faces W, E, S, N[, B, T] paired as ((W+E)+(S+N))+(B+T);
+ * a face on the boundary carries no flux (its terms are 0) */
+inline void cd_faces(int dim, int n, const Cx* u, const Cx* g, int i, int j, int k, Cx* F, Cx* S) {
+    const idx_t p = cc_at(dim, n, i, j, k);
+    const idx_t sz = (idx_t)n * n;
+    const Cx zero{0.0, 0.0};
+    const Cx up = u[p], gp = g[p];
+    auto face = [&](bool inside, idx_t q, Cx* t, Cx* gf) {
+        if (!inside) {
+            *t = zero;
+            *gf = zero;
+            return;
+        }
+        const Cx gq = g[q];
+        *gf = Cx{0.5 * (gp.re + gq.re), 0.5 * (gp.im + gq.im)};
+        *t = cx_mul(*gf, cx_sub(u[q], up));
+    };
+    Cx tW, tE, tS, tN, gW, gE, gS, gN;
+    face(i > 0, p - 1, &tW, &gW);
+    face(i < n - 1, p + 1, &tE, &gE);
+    face(j > 0, p - n, &tS, &gS);
+    face(j < n - 1, p + n, &tN, &gN);
+    Cx f2 = cx_add(cx_add(tW, tE), cx_add(tS, tN));
+    Cx s2 = cx_add(cx_add(gW, gE), cx_add(gS, gN));
+    if (dim == 3) {
+        Cx tB, tT, gB, gT;
+        face(k > 0, p - sz, &tB, &gB);
+        face(k < n - 1, p + sz, &tT, &gT);
+        f2 = cx_add(f2, cx_add(tB, tT));
+        s2 = cx_add(s2, cx_add(gB, gT));
+    }
+    *F = f2;
+    *S = s2;
+}
+
+/* N(u)_p = u_p / tau - c F (the implicit-Euler operator with diffusivity g) */
+inline Cx cd_apply(const CDParams& P, int n, double c, const Cx* u, const Cx* g, int i, int j, int k) {
+    Cx F, S;
+    cd_faces(P.dim, n, u, g, i, j, k, &F, &S);
+    const Cx up = u[cc_at(P.dim, n, i, j, k)];
+    return Cx{P.itau * up.re - c * F.re, P.itau * up.im - c * F.im};
+}
+
+void cd_compute_g(const CDParams& P, int n, const Cx* u, Cx* g) {
+    const size_t N = cc_cells(P.dim, n);
+    for (size_t p = 0; p < N; ++p) g[p] = cd_g(P, u[p]);
+}
+
+/* one smoothing sweep with the diffusivity frozen at the iterate the sweep
+ * starts from: RBGS (red cells, then black, in place) or Jacobi (out of place);
+ * update u + omega r / D with D = 1/tau + c S the diagonal */
+void cd_sweep(const CDParams& P, int n, double c, int smoother, double omega, Cx* u, const Cx* f,
+              std::vector<Cx>& g, std::vector<Cx>& tmp) {
+    const int dim = P.dim;
+    const size_t N = cc_cells(dim, n);
+    g.resize(N);
+    cd_compute_g(P, n, u, g.data());
+    auto relax = [&](const Cx* src, int i, int j, int k) {
+        const idx_t p = cc_at(dim, n, i, j, k);
+        Cx F, S;
+        cd_faces(dim, n, src, g.data(), i, j, k, &F, &S);
+        const Cx up = src[p];
+        const Cx Nu{P.itau * up.re - c * F.re, P.itau * up.im - c * F.im};
+        const Cx r = cx_sub(f[p], Nu);
+        const Cx D{P.itau + c * S.re, c * S.im};
+        return cx_add(up, cx_scale(omega, cx_div(r, D)));
+    };
+    if (smoother == SMOOTH_JACOBI) {
+        tmp.assign(u, u + N);
+        for (int k = 0; k < cc_k1(dim, n); ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) tmp[(size_t)cc_at(dim, n, i, j, k)] = relax(u, i, j, k);
+        std::memcpy(u, tmp.data(), N * sizeof(Cx));
+        return;
+    }
+    for (int colour = 0; colour < 2; ++colour)
+        for (int k = 0; k < cc_k1(dim, n); ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i)
+                    if (((i + j + k) & 1) == colour) u[cc_at(dim, n, i, j, k)] = relax(u, i, j, k);
+}
+
+/* r = f - N(u) with g of u */
+void cd_residual(const CDParams& P, int n, double c, const Cx* u, const Cx* f, std::vector<Cx>& g, Cx* r) {
+    const size_t N = cc_cells(P.dim, n);
+    g.resize(N);
+    cd_compute_g(P, n, u, g.data());
+    for (int k = 0; k < cc_k1(P.dim, n); ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const idx_t p = cc_at(P.dim, n, i, j, k);
+                r[p] = cx_sub(f[p], cd_apply(P, n, c, u, g.data(), i, j, k));
+            }
+}
+
+/* average of the 2^d children, componentwise (as cc_restrict) */
+void cd_average(int dim, int nf, const Cx* a, Cx* out) {
+    const int nc = nf / 2;
+    const size_t Nf = cc_cells(dim, nf), Nc = cc_cells(dim, nc);
+    std::vector<double> re(Nf), im(Nf), cre(Nc), cim(Nc);
+    for (size_t p = 0; p < Nf; ++p) {
+        re[p] = a[p].re;
+        im[p] = a[p].im;
+    }
+    cc_restrict(dim, nf, re.data(), cre.data());
+    cc_restrict(dim, nf, im.data(), cim.data());
+    for (size_t q = 0; q < Nc; ++q) out[q] = Cx{cre[q], cim[q]};
+}
+
+/* ||r||_2 with |r_p|^2 = re^2 + im^2, summed per x-row, plane, all */
+double cd_norm(int dim, int n, const Cx* r) {
+    double s = 0.0;
+    for (int k = 0; k < cc_k1(dim, n); ++k) {
+        double plane = 0.0;
+        for (int j = 0; j < n; ++j) {
+            double row = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const Cx v = r[cc_at(dim, n, i, j, k)];
+                row += v.re * v.re + v.im * v.im;
+            }
+            plane += row;
+        }
+        s += plane;
+    }
+    return std::sqrt(s);
+}
+
+struct CDHierarchy {
+    CDParams P;
+    int nlev, smoother, nu1, nu2;
+    double omega;
+    std::vector<int> n;
+    std::vector<std::vector<Cx>> u, f, uh, r;
+    std::vector<Cx> g, tmp;
+};
+
+void cd_build(CDHierarchy& H, const CDParams& P, int n, int smoother, double omega, int nu1, int nu2) {
+    H.P = P;
+    H.smoother = smoother;
+    H.omega = omega;
+    H.nu1 = nu1;
+    H.nu2 = nu2;
+    H.n.clear();
+    for (int m = n; m >= 1; m /= 2) H.n.push_back(m);
+    H.nlev = (int)H.n.size();
+    H.u.assign((size_t)H.nlev, {});
+    H.f.assign((size_t)H.nlev, {});
+    H.uh.assign((size_t)H.nlev, {});
+    H.r.assign((size_t)H.nlev, {});
+    for (int l = 0; l < H.nlev; ++l) {
+        const size_t N = cc_cells(P.dim, H.n[(size_t)l]);
+        H.r[(size_t)l].assign(N, Cx{0.0, 0.0});
+        if (l > 0) {
+            H.u[(size_t)l].assign(N, Cx{0.0, 0.0});
+            H.f[(size_t)l].assign(N, Cx{0.0, 0.0});
+            H.uh[(size_t)l].assign(N, Cx{0.0, 0.0});
+        }
+    }
+}
+
+inline double cd_c(int n) {
+    const double h = 1.0 / (double)n;
+    return 1.0 / (h * h);
+}
+
+/* One FAS V-cycle on level l for N(u) = f (the coarse problem of level l+1
+ * is N_c(u_c) = N_c(R u) + R (f - N(u)) from u_c = R u; the correction
+ * u_c - R u is interpolated back).  Coarsest level (one cell): N(u) = u/tau,
+ * solved exactly: u = tau f. */
+void cd_fas(CDHierarchy& H, int l, Cx* u, const Cx* f) {
+    const CDParams& P = H.P;
+    const int n = H.n[(size_t)l];
+    const double c = cd_c(n);
+    if (l == H.nlev - 1) {
+        for (size_t p = 0; p < cc_cells(P.dim, n); ++p) u[p] = cx_scale(P.tau, f[p]);
+        return;
+    }
+    for (int s = 0; s < H.nu1; ++s) cd_sweep(P, n, c, H.smoother, H.omega, u, f, H.g, H.tmp);
+    Cx* r = H.r[(size_t)l].data();
+    cd_residual(P, n, c, u, f, H.g, r);
+    const int nc = H.n[(size_t)l + 1];
+    const size_t Nc = cc_cells(P.dim, nc);
+    Cx* uh = H.uh[(size_t)l + 1].data();
+    Cx* fc = H.f[(size_t)l + 1].data();
+    Cx* uc = H.u[(size_t)l + 1].data();
+    cd_average(P.dim, n, u, uh);
+    std::vector<Cx> rc(Nc);
+    cd_average(P.dim, n, r, rc.data());
+    /* fc = N_c(uh) + R r, with g of uh */
+    std::vector<Cx> gc(Nc);
+    cd_compute_g(P, nc, uh, gc.data());
+    const double cc = cd_c(nc);
+    for (int k = 0; k < cc_k1(P.dim, nc); ++k)
+        for (int j = 0; j < nc; ++j)
+            for (int i = 0; i < nc; ++i) {
+                const idx_t q = cc_at(P.dim, nc, i, j, k);
+                fc[q] = cx_add(cd_apply(P, nc, cc, uh, gc.data(), i, j, k), rc[(size_t)q]);
+            }
+    for (size_t q = 0; q < Nc; ++q) uc[q] = uh[q];
+    cd_fas(H, l + 1, uc, fc);
+    /* u += P (u_c - uh) (constant interpolation of the coarse correction) */
+    for (int k = 0; k < cc_k1(P.dim, n); ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const idx_t p = cc_at(P.dim, n, i, j, k);
+                const idx_t q = cc_at(P.dim, nc, i / 2, j / 2, P.dim == 3 ? k / 2 : 0);
+                u[p] = cx_add(u[p], cx_sub(uc[q], uh[q]));
+            }
+    for (int s = 0; s < H.nu2; ++s) cd_sweep(P, n, c, H.smoother, H.omega, u, f, H.g, H.tmp);
+}
+
+CDParams cd_params(int dim, double tau, double theta, double k, double ct, double st) {
+    CDParams P;
+    P.dim = dim;
+    P.tau = tau;
+    P.itau = 1.0 / tau;
+    P.ktheta = k * theta;
+    P.ct = ct;
+    P.st = st;
+    return P;
+}
+
 } /* namespace */
 
 /* ==================================================================== */
@@ -1268,6 +1528,86 @@ int orc_cc_solve(int dim, int n, int smoother, double omega, int nu1, int nu2, i
         else if (!(rho == rho) || rho > 1e6 * rho0) status = -5;
     }
     if (cycles) *cycles = it;
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Complex diffusion (FP64).  Complex arrays hold n^dim (re, im) pairs.    */
+/* ct, st: cos(theta), sin(theta) as the caller evaluated them.          */
+/* ------------------------------------------------------------------ */
+
+/* N(u) with g of u */
+void orc_cd_apply(int dim, int n, double tau, double theta, double k, double ct, double st, const double* u,
+                  double* out) {
+    const CDParams P = cd_params(dim, tau, theta, k, ct, st);
+    std::vector<Cx> g;
+    const size_t N = cc_cells(dim, n);
+    std::vector<Cx> zero(N, Cx{0.0, 0.0});
+    std::vector<Cx> r(N);
+    cd_residual(P, n, cd_c(n), (const Cx*)u, zero.data(), g, r.data());
+    for (size_t p = 0; p < N; ++p) ((Cx*)out)[p] = Cx{-r[p].re, -r[p].im};
+}
+void orc_cd_g(int dim, int n, double theta, double k, double ct, double st, const double* u, double* g) {
+    const CDParams P = cd_params(dim, 1.0, theta, k, ct, st);
+    cd_compute_g(P, n, (const Cx*)u, (Cx*)g);
+}
+void orc_cd_sweep(int dim, int n, double tau, double theta, double k, double ct, double st, int smoother,
+                  double omega, double* u, const double* f) {
+    const CDParams P = cd_params(dim, tau, theta, k, ct, st);
+    std::vector<Cx> g, tmp;
+    cd_sweep(P, n, cd_c(n), smoother, omega, (Cx*)u, (const Cx*)f, g, tmp);
+}
+double orc_cd_residual_norm(int dim, int n, double tau, double theta, double k, double ct, double st,
+                            const double* u, const double* f) {
+    const CDParams P = cd_params(dim, tau, theta, k, ct, st);
+    std::vector<Cx> g, r(cc_cells(dim, n));
+    cd_residual(P, n, cd_c(n), (const Cx*)u, (const Cx*)f, g, r.data());
+    return cd_norm(dim, n, r.data());
+}
+/* one FAS cycle on u for N(u) = f */
+int orc_cd_fas(int dim, int n, double tau, double theta, double k, double ct, double st, int smoother, double omega,
+               int nu1, int nu2, double* u, const double* f) {
+    if (!cc_valid(dim, n) || !(tau > 0.0)) return -1;
+    CDHierarchy H;
+    cd_build(H, cd_params(dim, tau, theta, k, ct, st), n, smoother, omega, nu1, nu2);
+    cd_fas(H, 0, (Cx*)u, (const Cx*)f);
+    return 0;
+}
+/* Implicit Euler: 'steps' time steps from u (in: u^0, out: u^steps); step m
+ * solves N(u) = u^m / tau by FAS cycles from u^m until ||f - N(u)|| <= tol
+ * ||f - N(u^m)|| or max_cycles.  cycles[m] (may be NULL) receives the cycle
+ * count of step m, hist (may be NULL, steps * (max_cycles + 1)) the residual
+ * norms of each step.  Returns 0, or 1 if some step missed the tolerance. */
+int orc_cd_run(int dim, int n, double tau, double theta, double k, double ct, double st, int smoother, double omega,
+               int nu1, int nu2, double* u, int steps, double tol, int max_cycles, int* cycles, double* hist) {
+    if (!cc_valid(dim, n) || !(tau > 0.0) || steps < 0 || max_cycles < 0) return -1;
+    const CDParams P = cd_params(dim, tau, theta, k, ct, st);
+    CDHierarchy H;
+    cd_build(H, P, n, smoother, omega, nu1, nu2);
+    const size_t N = cc_cells(dim, n);
+    Cx* U = (Cx*)u;
+    std::vector<Cx> f(N), r(N);
+    const double c = cd_c(n);
+    int status = 0;
+    for (int m = 0; m < steps; ++m) {
+        for (size_t p = 0; p < N; ++p) f[p] = cx_scale(P.itau, U[p]);
+        cd_residual(P, n, c, U, f.data(), H.g, r.data());
+        const double rho0 = cd_norm(dim, n, r.data());
+        double* hm = hist ? hist + (size_t)m * (size_t)(max_cycles + 1) : nullptr;
+        if (hm) hm[0] = rho0;
+        int it = 0;
+        bool done = rho0 == 0.0;
+        while (!done && it < max_cycles) {
+            cd_fas(H, 0, U, f.data());
+            ++it;
+            cd_residual(P, n, c, U, f.data(), H.g, r.data());
+            const double rho = cd_norm(dim, n, r.data());
+            if (hm) hm[it] = rho;
+            done = rho <= tol * rho0;
+        }
+        if (!done) status = 1;
+        if (cycles) cycles[m] = it;
+    }
     return status;
 }
 

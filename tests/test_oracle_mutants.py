@@ -68,12 +68,20 @@ MUTANTS = {
     "cc_prolong_transposed": ("u[p] = u[p] + ec[cc_at(dim, nc, i / 2, j / 2, dim == 3 ? k / 2 : 0)];",
                               "u[p] = u[p] + ec[cc_at(dim, nc, j / 2, i / 2, dim == 3 ? k / 2 : 0)];"),
     "cc_rhs_mean_kept": ("    cc_remove_mean(dim, n, fh.data());\n", ""),
+    "cd_face_not_averaged": ("*gf = Cx{0.5 * (gp.re + gq.re), 0.5 * (gp.im + gq.im)};", "*gf = gp;"),
+    "cd_g_square_dropped": ("const double q = 1.0 / (1.0 + s * s);", "const double q = 1.0 / (1.0 + s);"),
+    "cd_diag_without_time_term": ("const Cx D{P.itau + c * S.re, c * S.im};", "const Cx D{c * S.re, c * S.im};"),
+    "cd_fas_coarse_rhs_linear": ("fc[q] = cx_add(cd_apply(P, nc, cc, uh, gc.data(), i, j, k), rc[(size_t)q]);",
+                                 "fc[q] = rc[(size_t)q];"),
+    "cd_correction_not_differenced": ("u[p] = cx_add(u[p], cx_sub(uc[q], uh[q]));", "u[p] = cx_add(u[p], uc[q]);"),
+    "cd_complex_product_sign": ("return Cx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};",
+                                "return Cx{a.re * b.re + a.im * b.im, a.re * b.im + a.im * b.re};"),
     "cc_sum_skips_last_cell": ("for (int i = 0; i < n; ++i) row += u[cc_at(dim, n, i, j, k)];",
                                "for (int i = 0; i < n - 1; ++i) row += u[cc_at(dim, n, i, j, k)];"),
 }
 
 PIN_FILES = ["test_oracle_pins.py", "test_oracle_pins_variants.py", "test_oracle_pins_fp16.py",
-             "test_oracle_pins_cc.py"]
+             "test_oracle_pins_cc.py", "test_oracle_pins_cd.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
