@@ -210,6 +210,47 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
 int mg_level_coarsest_cg(int dim, int n, int dtype, const void* k, void* u, const void* f, int iters,
                          void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Complex diffusion (Section 4, Eq. (2)): u_t = div(g(Im u) grad u) on the unit
+ * square / cube with a homogeneous Neumann boundary, complex diffusivity
+ * g(s) = e^{i theta} / (1 + (s / (k theta))^2); averaged finite differences on
+ * a cell-centred grid of n = 2^L cells per axis (face diffusivity = mean of the
+ * two cells' g; a face on the boundary carries no flux), implicit Euler in
+ * time, and per time step the full approximation scheme (FAS) with lagged
+ * diffusivity (each smoothing sweep and each residual uses g of the iterate
+ * it starts from), averaging restriction of the residual and of the full
+ * approximation, constant interpolation of the coarse correction, a single-
+ * cell coarsest level solved exactly.  Complex arrays are device arrays of
+ * n^dim (re, im) FP64 pairs, x fastest, 16-byte aligned (MG_EINVAL otherwise).
+ * ------------------------------------------------------------------------- */
+typedef struct mg_cdiff_params {
+    int dim;        /* 2 or 3 */
+    int n;          /* cells per axis, 2^L, L >= 1 (at most 4096 in 2D, 256 in 3D) */
+    double tau;     /* time step, > 0 */
+    double theta;   /* angle of the diffusivity, 0 < theta < pi/2 */
+    double k;       /* scaling parameter, > 0 */
+    int smoother;   /* MG_SMOOTH_RBGS or MG_SMOOTH_WJACOBI */
+    double omega;   /* <= 0: 1.0 (RBGS) / 0.8 (Jacobi) */
+    int nu1, nu2;   /* smoothing sweeps, 0..16 */
+} mg_cdiff_params;
+
+/* Build the hierarchy (n, n/2, ..., 1 cells per axis) and its work arrays on
+ * the current device; cos theta and sin theta are evaluated once here.
+ * Errors: MG_EINVAL, MG_ENOMEM, MG_EDEVICE.  Release with mg_destroy. */
+int mg_cdiff_setup(const mg_cdiff_params* p, void* stream, mg_ctx** out);
+/* One FAS cycle on u (in/out) for N(u) = f, N(u) = u / tau - div(g(Im u) grad u).
+ * Asynchronous. */
+int mg_cdiff_fas(mg_ctx* ctx, double* u, const double* f);
+/* out = N(u). Asynchronous. */
+int mg_cdiff_apply(mg_ctx* ctx, const double* u, double* out);
+/* 'steps' implicit-Euler steps on u (in: u^0, out: u^steps); step m solves
+ * N(u) = u^m / tau by FAS cycles from u^m until ||f - N(u)|| <= tol ||f - N(u^m)||
+ * or max_cycles.  cycles (HOST, may be NULL) receives each step's cycle count,
+ * res_hist (HOST, may be NULL, steps * (max_cycles + 1) doubles) each step's
+ * residual norms (row m starts at m * (max_cycles + 1)).  Synchronises the
+ * stream.  Returns MG_OK, or MG_ENOTCONV if a step missed the tolerance. */
+int mg_cdiff_run(mg_ctx* ctx, double* u, int steps, double tol, int max_cycles, int* cycles, double* res_hist);
+
 /* Cell-centred Neumann grids (MG_BC_NEUMANN_CC), FP64, n = 2^L cells per axis
  * (n >= 2), the operations of a cycle: one smoothing sweep u_in -> u_out
  * (smoother 0 RBGS red first, 1 Jacobi); fc = average of the children's

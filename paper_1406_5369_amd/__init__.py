@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import atexit
 import ctypes as C
+import math
 import os
 import re
 from dataclasses import dataclass
@@ -51,6 +52,20 @@ class _Params(C.Structure):
         ("cycle", C.c_int),
         ("coarse_n", C.c_int),
         ("cg_iters", C.c_int),
+    ]
+
+
+class _CDiffParams(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int),
+        ("n", C.c_int),
+        ("tau", C.c_double),
+        ("theta", C.c_double),
+        ("k", C.c_double),
+        ("smoother", C.c_int),
+        ("omega", C.c_double),
+        ("nu1", C.c_int),
+        ("nu2", C.c_int),
     ]
 
 
@@ -95,6 +110,10 @@ def lib():
             "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
             "mg_level_coarsest_cg": (i, [i, i, i, p, p, p, i, p]),
+            "mg_cdiff_setup": (i, [C.POINTER(_CDiffParams), p, C.POINTER(p)]),
+            "mg_cdiff_fas": (i, [p, p, p]),
+            "mg_cdiff_apply": (i, [p, p, p]),
+            "mg_cdiff_run": (i, [p, p, i, d, i, p, p]),
             "mg_level_cc_smooth": (i, [i, i, i, d, p, p, p, p]),
             "mg_level_cc_residual_restrict": (i, [i, i, p, p, p, p]),
             "mg_level_cc_prolong_correct": (i, [i, i, p, p, p]),
@@ -355,6 +374,49 @@ def mg_level_coarsest_cg(u, f, k=None, iters=0, stream=None) -> None:
     dt = f.dtype
     _check(lib().mg_level_coarsest_cg(dim, n, _dtype_code(f), _dptr(k, dt, f.shape, "k"), _dptr(u, dt, f.shape, "u"),
                                       _dptr(f, dt, f.shape, "f"), int(iters), _stream(stream)), "mg_level_coarsest_cg")
+
+
+# complex diffusion (FP64 complex, n = 2^L cells per axis, Neumann boundary)
+def mg_cdiff_setup(dim, n, tau, theta=math.pi / 30, k=1.0, smoother=SMOOTH_RBGS, omega=0.0, nu1=2, nu2=2,
+                   stream=None) -> int:
+    """Context for the implicit-Euler FAS solver of the complex diffusion equation."""
+    cp = _CDiffParams(int(dim), int(n), float(tau), float(theta), float(k), int(smoother), float(omega), int(nu1),
+                      int(nu2))
+    out = C.c_void_p()
+    _check(lib().mg_cdiff_setup(C.byref(cp), _stream(stream), C.byref(out)), "mg_cdiff_setup")
+    return _track(out.value)
+
+
+def _cd_ptr(t, name):
+    """Device pointer of a contiguous complex128 tensor ((re, im) FP64 pairs)."""
+    import torch
+
+    return _dptr(t, torch.complex128, None, name)
+
+
+def mg_cdiff_fas(ctx: int, u, f) -> None:
+    """One FAS cycle on u (complex128, in place) for N(u) = f."""
+    if u.shape != f.shape:
+        raise ValueError("u and f must have the same shape")
+    _check(lib().mg_cdiff_fas(ctx, _cd_ptr(u, "u"), _cd_ptr(f, "f")), "mg_cdiff_fas")
+
+
+def mg_cdiff_apply(ctx: int, u, out) -> None:
+    """out = N(u) = u / tau - div(g(Im u) grad u)."""
+    if u.shape != out.shape:
+        raise ValueError("u and out must have the same shape")
+    _check(lib().mg_cdiff_apply(ctx, _cd_ptr(u, "u"), _cd_ptr(out, "out")), "mg_cdiff_apply")
+
+
+def mg_cdiff_run(ctx: int, u, steps: int, tol: float = 1e-5, max_cycles: int = 20):
+    """Implicit-Euler steps on u (in place).  Returns (status, [cycles per step],
+    [[residual norms] per step])."""
+    nc = (C.c_int * max(1, steps))()
+    hist = (C.c_double * max(1, steps * (max_cycles + 1)))()
+    st = lib().mg_cdiff_run(ctx, _cd_ptr(u, "u"), int(steps), float(tol), int(max_cycles), nc, hist)
+    _check(st, "mg_cdiff_run", ok=(MG_OK, MG_ENOTCONV))
+    w = max_cycles + 1
+    return st, list(nc)[:steps], [list(hist[m * w:m * w + nc[m] + 1]) for m in range(steps)]
 
 
 # cell-centred Neumann grids (FP64, n = 2^L cells per axis)

@@ -31,6 +31,7 @@ SOURCES = [
     "mg_batch.hip",
     "mg_tail.hip",
     "mg_cc.hip",
+    "mg_cd.hip",
 ]
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -9,9 +9,36 @@
 #include <tuple>
 
 #include "mg_cc.h"
+#include "mg_cd.h"
 #include "mg_solver.h"
 
 using namespace mg;
+
+// Complex-diffusion hierarchy: levels n, n/2, ..., 1 cells per axis; per level
+// the iterate and its Jacobi partner (level 0's iterate is the caller's), the
+// right-hand side, the diffusivity and the restricted full approximation.
+struct CDState {
+    int dim = 0, n = 0;
+    double tau = 0.0;
+    CDConst K{};
+    bool jacobi = false;
+    int nu1 = 2, nu2 = 2;
+    std::vector<int> ln;
+    std::vector<void*> u, t, f, g, uh;
+    double* part = nullptr;
+    double* norm = nullptr;
+    double* h_norm = nullptr;  // pinned
+    ~CDState() {
+        for (size_t l = 0; l < ln.size(); ++l) {
+            if (l > 0 && u[l]) (void)hipFree(u[l]);
+            for (void* p : {t[l], f[l], g[l], uh[l]})
+                if (p) (void)hipFree(p);
+        }
+        if (part) (void)hipFree(part);
+        if (norm) (void)hipFree(norm);
+        if (h_norm) (void)hipHostFree(h_norm);
+    }
+};
 
 namespace {
 
@@ -219,6 +246,7 @@ void destroy(mg_ctx* c) {
     ffree(c->ccfh);
     ffree(c->cc_work);
     ffree(c->cc_mean);
+    delete c->cd;
     ffree(c->d_ir);
     ffree(c->d_scl);
     ffree(c->d_pmax);
@@ -541,6 +569,68 @@ int cc_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
     if (status == 0) return MG_OK;
     if (status == -5) return MG_EDIVERGED;
     return MG_ENOTCONV;
+}
+
+// ---------------------------------------------------------------------------
+// Complex diffusion: FAS level by level.
+// ---------------------------------------------------------------------------
+size_t cd_cells(const CDState& S, int l) {
+    const size_t n = (size_t)S.ln[(size_t)l];
+    return S.dim == 2 ? n * n : n * n * n;
+}
+
+hipError_t cd_sweep_level(CDState& S, int l, void*& cur, void*& other, const void* f, hipStream_t s) {
+    const CDLevel L = cd_level(S.ln[(size_t)l]);
+    hipError_t e = cd_compute_g(cur, S.g[(size_t)l], cd_cells(S, l), S.K, s);
+    if (e != hipSuccess) return e;
+    if (S.jacobi) {
+        e = cd_relax(S.dim, true, cur, other, f, S.g[(size_t)l], S.K, L, 0, s);
+        std::swap(cur, other);
+        return e;
+    }
+    e = cd_relax(S.dim, false, cur, cur, f, S.g[(size_t)l], S.K, L, 0, s);
+    if (e != hipSuccess) return e;
+    return cd_relax(S.dim, false, cur, cur, f, S.g[(size_t)l], S.K, L, 1, s);
+}
+
+hipError_t cd_fas_level(CDState& S, int l, void*& cur, void*& other, const void* f, hipStream_t s) {
+    const size_t N = cd_cells(S, l);
+    if (l + 1 == (int)S.ln.size()) return cd_scale(f, cur, N, S.tau, s);  // one cell: N(u) = u / tau
+    const CDLevel L = cd_level(S.ln[(size_t)l]), Lc = cd_level(S.ln[(size_t)l + 1]);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < S.nu1 && e == hipSuccess; ++i) e = cd_sweep_level(S, l, cur, other, f, s);
+    if (e != hipSuccess) return e;
+    const size_t c1 = (size_t)l + 1;
+    void* ucur = S.u[c1];
+    void* uoth = S.t[c1];
+    if ((e = cd_compute_g(cur, S.g[(size_t)l], N, S.K, s)) != hipSuccess) return e;
+    if ((e = cd_restrict(S.dim, cur, f, S.g[(size_t)l], S.uh[c1], S.f[c1], S.K, L, s)) != hipSuccess) return e;
+    if ((e = cd_compute_g(S.uh[c1], S.g[c1], cd_cells(S, l + 1), S.K, s)) != hipSuccess) return e;
+    if ((e = cd_coarse_rhs(S.dim, S.uh[c1], S.g[c1], S.f[c1], ucur, S.K, Lc, s)) != hipSuccess) return e;
+    if ((e = cd_fas_level(S, l + 1, ucur, uoth, S.f[c1], s)) != hipSuccess) return e;
+    S.u[c1] = ucur;
+    S.t[c1] = uoth;
+    if ((e = cd_prolong(S.dim, cur, ucur, S.uh[c1], S.ln[(size_t)l], s)) != hipSuccess) return e;
+    for (int i = 0; i < S.nu2 && e == hipSuccess; ++i) e = cd_sweep_level(S, l, cur, other, f, s);
+    return e;
+}
+
+hipError_t cd_fas_top(CDState& S, void* u, const void* f, hipStream_t s) {
+    void* cur = u;
+    void* other = S.t[0];
+    hipError_t e = cd_fas_level(S, 0, cur, other, f, s);
+    if (e == hipSuccess && cur != u) e = hipMemcpyAsync(u, cur, cd_cells(S, 0) * 16, hipMemcpyDeviceToDevice, s);
+    return e;
+}
+
+// ||f - N(u)|| (g of u) to the host
+int cd_norm_host(CDState& S, const void* u, const void* f, hipStream_t s, double* out) {
+    CK(cd_compute_g(u, S.g[0], cd_cells(S, 0), S.K, s));
+    CK(cd_norm(S.dim, u, f, S.g[0], S.K, cd_level(S.n), S.part, S.norm, s));
+    CK(hipMemcpyAsync(S.h_norm, S.norm, sizeof(double), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    *out = S.h_norm[0];
+    return MG_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1018,7 +1108,10 @@ void mg_destroy(mg_ctx* c) {
     else destroy(c);
 }
 
-int mg_num_levels(const mg_ctx* c) { return c && !is_batch_handle(c) ? c->nlev : MG_EINVAL; }
+int mg_num_levels(const mg_ctx* c) {
+    if (!c || is_batch_handle(c)) return MG_EINVAL;
+    return c->cd ? (int)c->cd->ln.size() : c->nlev;
+}
 
 int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch, int* waves,
                    int* order, int* pairs) {
@@ -1044,6 +1137,7 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
 int mg_vcycle(mg_ctx* c, double* u, const double* f) {
     if (!c) return MG_EINVAL;
     if (is_batch_handle(c)) return MG_EINVAL;
+    if (c->cd) return MG_EINVAL;  // complex-diffusion handles take the mg_cdiff_* calls
     if (c->cc) {
         if (!u || !f) return MG_EINVAL;
         CK(cc_cycle_top(c, u, f));
@@ -1068,6 +1162,7 @@ int mg_vcycle(mg_ctx* c, double* u, const double* f) {
 int mg_residual_norm(mg_ctx* c, const double* u, const double* f, double* out) {
     if (!c || !out) return MG_EINVAL;
     if (is_batch_handle(c)) return MG_EINVAL;
+    if (c->cd) return MG_EINVAL;  // complex-diffusion handles take the mg_cdiff_* calls
     if (c->cc) {
         if (!u || !f) return MG_EINVAL;
         CK(cc_norm(c->p.dim, u, f, cc_const(c->p.dim, c->p.n, c->p.omega), c->d_partial, c->d_norm, c->stream));
@@ -1088,6 +1183,7 @@ int mg_residual_norm(mg_ctx* c, const double* u, const double* f, double* out) {
 int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, int* cycles_done, double* res_hist) {
     if (!c || max_cycles < 0 || !(tol >= 0.0)) return MG_EINVAL;
     if (is_batch_handle(c)) return MG_EINVAL;
+    if (c->cd) return MG_EINVAL;  // complex-diffusion handles take the mg_cdiff_* calls
     if (c->cc) {
         if (!u || !f) return MG_EINVAL;
         return cc_solve(c, u, f, tol, max_cycles, cycles_done, res_hist);
@@ -1450,6 +1546,116 @@ int mg_level_ir_update_f16(int dim, int n, const double* u_in, const void* e16, 
     *norm_out = host[0];
     *max_out = host[1];
     return MG_OK;
+}
+
+int mg_cdiff_setup(const mg_cdiff_params* p, void* stream, mg_ctx** out) {
+    if (!out) return MG_EINVAL;
+    *out = nullptr;
+    if (!p || (p->dim != 2 && p->dim != 3) || p->n < 2 || (p->n & (p->n - 1)) ||
+        p->n > (p->dim == 2 ? 4096 : 256))
+        return MG_EINVAL;
+    if (!(p->tau > 0.0) || !(p->theta > 0.0) || !(p->theta < 1.5707963267948966) || !(p->k > 0.0)) return MG_EINVAL;
+    if (p->smoother != MG_SMOOTH_RBGS && p->smoother != MG_SMOOTH_WJACOBI) return MG_EINVAL;
+    if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 > 16 || p->nu2 > 16 || !(p->omega <= 2.0)) return MG_EINVAL;
+    mg_ctx* c = new (std::nothrow) mg_ctx();
+    if (!c) return MG_ENOMEM;
+    c->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&c->device);
+    c->p = mg_params{};
+    c->p.dim = p->dim;
+    c->p.n = p->n;
+    c->cd = new (std::nothrow) CDState();
+    if (!c->cd) {
+        delete c;
+        return MG_ENOMEM;
+    }
+    CDState& S = *c->cd;
+    S.dim = p->dim;
+    S.n = p->n;
+    S.tau = p->tau;
+    S.jacobi = p->smoother == MG_SMOOTH_WJACOBI;
+    S.nu1 = p->nu1;
+    S.nu2 = p->nu2;
+    S.K.itau = 1.0 / p->tau;
+    S.K.ktheta = p->k * p->theta;
+    S.K.ct = std::cos(p->theta);
+    S.K.st = std::sin(p->theta);
+    S.K.omega = p->omega > 0.0 ? p->omega : (S.jacobi ? 0.8 : 1.0);
+    for (int m = p->n; m >= 1; m /= 2) S.ln.push_back(m);
+    const size_t L = S.ln.size();
+    S.u.assign(L, nullptr);
+    S.t.assign(L, nullptr);
+    S.f.assign(L, nullptr);
+    S.g.assign(L, nullptr);
+    S.uh.assign(L, nullptr);
+    hipStream_t s = c->stream;
+    hipError_t e = hipSuccess;
+    for (size_t l = 0; l < L && e == hipSuccess; ++l) {
+        const size_t bytes = cd_cells(S, (int)l) * 16;
+        if (l > 0) e = zalloc(&S.u[l], bytes, s);
+        if (e == hipSuccess) e = zalloc(&S.t[l], bytes, s);
+        if (e == hipSuccess) e = zalloc(&S.f[l], bytes, s);
+        if (e == hipSuccess) e = zalloc(&S.g[l], bytes, s);
+        if (e == hipSuccess && l > 0) e = zalloc(&S.uh[l], bytes, s);
+    }
+    const int np = cd_norm_parts(S.dim, S.n);
+    if (e == hipSuccess) e = hipMalloc((void**)&S.part, sizeof(double) * (size_t)np);
+    if (e == hipSuccess) e = hipMalloc((void**)&S.norm, sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&S.h_norm, sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        destroy(c);
+        return dev_status(e);
+    }
+    *out = c;
+    return MG_OK;
+}
+
+inline bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int mg_cdiff_fas(mg_ctx* c, double* u, const double* f) {
+    if (!c || is_batch_handle(c) || !c->cd || !u || !f || !al16(u) || !al16(f)) return MG_EINVAL;
+    CK(cd_fas_top(*c->cd, u, f, c->stream));
+    return MG_OK;
+}
+
+int mg_cdiff_apply(mg_ctx* c, const double* u, double* out) {
+    if (!c || is_batch_handle(c) || !c->cd || !u || !out || !al16(u) || !al16(out)) return MG_EINVAL;
+    CDState& S = *c->cd;
+    CK(cd_compute_g(u, S.g[0], cd_cells(S, 0), S.K, c->stream));
+    CK(cd_apply_op(S.dim, u, S.g[0], out, S.K, cd_level(S.n), c->stream));
+    return MG_OK;
+}
+
+int mg_cdiff_run(mg_ctx* c, double* u, int steps, double tol, int max_cycles, int* cycles, double* res_hist) {
+    if (!c || is_batch_handle(c) || !c->cd || !u || !al16(u) || steps < 0 || max_cycles < 0 || !(tol >= 0.0)) return MG_EINVAL;
+    CDState& S = *c->cd;
+    hipStream_t s = c->stream;
+    const size_t N = cd_cells(S, 0);
+    void* f0 = S.f[0];
+    int status = MG_OK;
+    for (int m = 0; m < steps; ++m) {
+        CK(cd_scale(u, f0, N, S.K.itau, s));  // right-hand side u^m / tau
+        double rho0 = 0.0;
+        int r = cd_norm_host(S, u, f0, s, &rho0);
+        if (r != MG_OK) return r;
+        double* hm = res_hist ? res_hist + (size_t)m * (size_t)(max_cycles + 1) : nullptr;
+        if (hm) hm[0] = rho0;
+        int it = 0;
+        bool done = rho0 == 0.0;
+        while (!done && it < max_cycles) {
+            CK(cd_fas_top(S, u, f0, s));
+            ++it;
+            double rho = 0.0;
+            r = cd_norm_host(S, u, f0, s, &rho);
+            if (r != MG_OK) return r;
+            if (hm) hm[it] = rho;
+            done = rho <= tol * rho0;
+        }
+        if (!done) status = MG_ENOTCONV;
+        if (cycles) cycles[m] = it;
+    }
+    return status;
 }
 
 int mg_level_cc_smooth(int dim, int n, int smoother, double omega, const double* u_in, const double* f,

@@ -1,0 +1,35 @@
+// Kernels of the complex-diffusion form (see mg_cd.hip).  Complex arrays are
+// (re, im) pairs of doubles, n^dim cells, x fastest.
+#pragma once
+
+#include "mg_internal.h"
+
+namespace mg {
+
+// Problem constants: 1/tau, k theta, cos theta, sin theta (as the host
+// evaluated them), relaxation weight.
+struct CDConst {
+    double itau, ktheta, ct, st, omega;
+};
+// Level constants: n cells per axis, c = 1/h^2 (h = 1/n).
+struct CDLevel {
+    int n;
+    double c;
+};
+CDLevel cd_level(int n);
+
+hipError_t cd_compute_g(const void* u, void* g, size_t N, CDConst K, hipStream_t s);
+hipError_t cd_relax(int dim, bool jacobi, const void* uin, void* uout, const void* f, const void* g, CDConst K,
+                    CDLevel L, int colour, hipStream_t s);
+hipError_t cd_restrict(int dim, const void* u, const void* f, const void* g, void* uh, void* rc, CDConst K,
+                       CDLevel L, hipStream_t s);
+hipError_t cd_coarse_rhs(int dim, const void* uh, const void* gc, void* fc, void* uc, CDConst K, CDLevel Lc,
+                         hipStream_t s);
+hipError_t cd_prolong(int dim, void* u, const void* uc, const void* uh, int n, hipStream_t s);
+hipError_t cd_scale(const void* a, void* out, size_t N, double sc, hipStream_t s);
+hipError_t cd_apply_op(int dim, const void* u, const void* g, void* out, CDConst K, CDLevel L, hipStream_t s);
+int cd_norm_parts(int dim, int n);
+hipError_t cd_norm(int dim, const void* u, const void* f, const void* g, CDConst K, CDLevel L, double* part,
+                   double* norm, hipStream_t s);
+
+}  // namespace mg

@@ -156,6 +156,9 @@ struct mg_ctx {
     double* cc_work = nullptr;  // fixed-order sums (row and plane sums)
     double* cc_mean = nullptr;  // [1]
 
+    // complex diffusion (mg_cdiff_setup): its level hierarchy
+    struct CDState* cd = nullptr;
+
     // measurement
     // measurement hooks: event pairs of the current solve, tagged with their
     // refinement step and kernel (0 finest plain sweeps, 1 finest refinement /
