@@ -31,6 +31,10 @@ __all__ = [
     "batch_problem",
     "serving_requests",
     "Request",
+    "cell_centres",
+    "random_cells",
+    "noisy_image",
+    "random_complex",
 ]
 
 
@@ -198,3 +202,34 @@ def serving_requests(count: int, rate: float, seed: int = 4,
             dim, n = 3, int(rng.choice(np.asarray(edges3d)))
         out.append(Request(t, dim, n, seed * 1_000_003 + r))
     return out
+
+
+# Cell-centred grids: n = 2**L cells per axis, cell i centred at (i + 1/2) / n,
+# C-ordered (n, n) / (n, n, n) arrays, x fastest, no boundary entries.
+def cell_centres(n: int) -> np.ndarray:
+    """Cell-centre coordinates (i + 1/2) / n."""
+    return (np.arange(n, dtype=np.float64) + 0.5) / float(n)
+
+
+def random_cells(dim: int, n: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """U[-scale, scale] on every cell."""
+    return np.random.default_rng(seed).uniform(-1, 1, (n,) * dim) * scale
+
+
+def noisy_image(dim: int, n: int, seed: int, sigma: float = 0.1) -> np.ndarray:
+    """The denoising workload of the complex-diffusion form, synthetic: value 1
+    inside the disc (2D) or ball (3D) of radius 0.3 about the centre, 0
+    outside, plus N(0, sigma^2) noise per cell; complex128 with zero imaginary
+    part (the initial state of the diffusion)."""
+    rng = np.random.default_rng(seed)
+    grids = np.meshgrid(*([cell_centres(n)] * dim), indexing="ij")[::-1]  # x, y[, z]
+    r2 = sum((g - 0.5) ** 2 for g in grids)
+    img = (r2 < 0.09).astype(np.float64)
+    return np.ascontiguousarray((img + sigma * rng.standard_normal(img.shape)).astype(np.complex128))
+
+
+def random_complex(dim: int, n: int, seed: int, scale: float = 1.0, im: float = 0.3) -> np.ndarray:
+    """scale * (U[-1, 1] + i U[-im, im]) on every cell (complex128)."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1, 1, (n,) * dim) + 1j * rng.uniform(-im, im, (n,) * dim)
+    return np.ascontiguousarray(a * scale)

@@ -9,6 +9,7 @@ relative per cycle (the norm's partial sums are summed in another order).
 import numpy as np
 import pytest
 
+import inputs
 import oracle
 
 pytestmark = pytest.mark.gpu
@@ -35,17 +36,13 @@ def host(t):
     return t.cpu().numpy()
 
 
-def cells(dim, n, seed, scale=1.0):
-    return np.random.default_rng(seed).uniform(-1, 1, (n,) * dim) * scale
-
-
 SIZES = [(2, 2), (2, 4), (2, 64), (2, 256), (3, 2), (3, 8), (3, 32), (3, 64)]
 
 
 @pytest.mark.parametrize("dim,n", SIZES)
 @pytest.mark.parametrize("smoother", [RB, JAC])
 def test_cc_sweep_bitwise(dim, n, smoother, dev_ok):
-    u, f = cells(dim, n, 1), cells(dim, n, 2, 50.0)
+    u, f = inputs.random_cells(dim, n, 1), inputs.random_cells(dim, n, 2, 50.0)
     omega = 1.0 if smoother == RB else 0.8
     expect = oracle.cc_smooth(u, f, smoother, omega)
     out = dev(np.zeros_like(u))
@@ -55,12 +52,12 @@ def test_cc_sweep_bitwise(dim, n, smoother, dev_ok):
 
 @pytest.mark.parametrize("dim,n", SIZES)
 def test_cc_restrict_and_prolong_bitwise(dim, n, dev_ok):
-    u, f = cells(dim, n, 3), cells(dim, n, 4, 50.0)
+    u, f = inputs.random_cells(dim, n, 3), inputs.random_cells(dim, n, 4, 50.0)
     expect = oracle.cc_restrict(oracle.cc_residual(u, f))
     fc = dev(np.zeros((n // 2,) * dim))
     mg().mg_level_cc_residual_restrict(dev(u), dev(f), fc)
     assert np.array_equal(host(fc), expect)
-    ec = cells(dim, n // 2, 5)
+    ec = inputs.random_cells(dim, n // 2, 5)
     ud = dev(u)
     mg().mg_level_cc_prolong_correct(ud, dev(ec))
     assert np.array_equal(host(ud), oracle.cc_prolong_correct(u, ec))
@@ -68,7 +65,7 @@ def test_cc_restrict_and_prolong_bitwise(dim, n, dev_ok):
 
 @pytest.mark.parametrize("dim,n", [(2, 2), (2, 512), (3, 4), (3, 128)])
 def test_cc_remove_mean_bitwise(dim, n, dev_ok):
-    v = cells(dim, n, 6) + 0.3
+    v = inputs.random_cells(dim, n, 6) + 0.3
     mean = oracle.cc_sum(v) / v.size
     vd = dev(v)
     got = mg().mg_level_cc_remove_mean(vd)
@@ -90,7 +87,7 @@ def cc_solve_gpu(dim, n, f, smoother=RB, cycle=0, tol=1e-10, max_cycles=60, u0=N
                                                   (2, 32, JAC, 2), (3, 16, RB, 0), (3, 64, RB, 0), (3, 32, JAC, 1),
                                                   (3, 128, RB, 0), (3, 8, RB, 2), (2, 2, RB, 0)])
 def test_cc_solve_matches_oracle(dim, n, smoother, cycle, dev_ok):
-    f = cells(dim, n, 7) + 0.25  # a mean the solve projects away
+    f = inputs.random_cells(dim, n, 7) + 0.25  # a mean the solve projects away
     omega = 1.0 if smoother == RB else 0.8
     u_exp, h_exp, rc, _ = oracle.cc_solve(np.zeros_like(f), f, tol=1e-10, max_cycles=60, smoother=smoother,
                                           omega=omega, cycle=cycle)
@@ -103,8 +100,8 @@ def test_cc_solve_matches_oracle(dim, n, smoother, cycle, dev_ok):
 def test_cc_solve_from_nonzero_guess_and_vcycle_entry(dev_ok):
     m = mg()
     dim, n = 3, 32
-    f = cells(dim, n, 8)
-    u0 = cells(dim, n, 9, 3.0)
+    f = inputs.random_cells(dim, n, 8)
+    u0 = inputs.random_cells(dim, n, 9, 3.0)
     u_exp, h_exp, _, _ = oracle.cc_solve(u0, f, tol=1e-9, max_cycles=40)
     st, cyc, h, u = cc_solve_gpu(dim, n, f, tol=1e-9, max_cycles=40, u0=u0)
     np.testing.assert_allclose(h, h_exp, rtol=1e-12, atol=0)

@@ -15,6 +15,7 @@ import math
 import numpy as np
 import pytest
 
+import inputs
 import oracle
 
 pytestmark = pytest.mark.gpu
@@ -41,27 +42,13 @@ def host(t):
     return t.cpu().numpy()
 
 
-def noisy_image(dim, n, seed, sigma=0.1):
-    rng = np.random.default_rng(seed)
-    x = (np.arange(n) + 0.5) / n
-    grids = np.meshgrid(*([x] * dim), indexing="ij")[::-1]
-    r2 = sum((g - 0.5) ** 2 for g in grids)
-    img = (r2 < 0.09).astype(float)
-    return np.ascontiguousarray((img + sigma * rng.standard_normal(img.shape)).astype(np.complex128))
-
-
-def rand_c(dim, n, seed, scale=1.0):
-    rng = np.random.default_rng(seed)
-    return np.ascontiguousarray((rng.uniform(-1, 1, (n,) * dim) + 1j * rng.uniform(-0.3, 0.3, (n,) * dim)) * scale)
-
-
 SIZES = [(2, 2), (2, 4), (2, 64), (2, 256), (3, 2), (3, 8), (3, 32)]
 
 
 @pytest.mark.parametrize("dim,n", SIZES)
 def test_cd_apply_bitwise(dim, n, dev_ok):
     P = oracle.CD(tau=10.0 / n**2, k=0.1)
-    u = rand_c(dim, n, 1)
+    u = inputs.random_complex(dim, n, 1)
     expect = oracle.cd_apply(u, P)
     ctx = mg().mg_cdiff_setup(dim, n, P.tau, P.theta, P.k)
     try:
@@ -76,8 +63,8 @@ def test_cd_apply_bitwise(dim, n, dev_ok):
 @pytest.mark.parametrize("smoother,nu", [(RB, (2, 2)), (RB, (1, 0)), (RB, (0, 3)), (JAC, (2, 2)), (JAC, (3, 1))])
 def test_cd_fas_cycle_bitwise(dim, n, smoother, nu, dev_ok):
     P = oracle.CD(tau=10.0 / n**2, k=0.1)
-    u0 = noisy_image(dim, n, 2)
-    f = u0 / P.tau + 0.05 * rand_c(dim, n, 3)
+    u0 = inputs.noisy_image(dim, n, 2)
+    f = u0 / P.tau + 0.05 * inputs.random_complex(dim, n, 3)
     omega = 1.0 if smoother == RB else 0.8
     expect = u0
     for _ in range(2):
@@ -98,7 +85,7 @@ def test_cd_run_matches_oracle(dim, n, steps, smoother, dev_ok):
     """Implicit-Euler steps with FAS per step: cycle counts equal, the final
     field bit for bit, the residual histories to 1e-12 relative."""
     P = oracle.CD(tau=10.0 / n**2, k=0.1)
-    u0 = noisy_image(dim, n, 5)
+    u0 = inputs.noisy_image(dim, n, 5)
     omega = 1.0 if smoother == RB else 0.8
     tol, mc = 1e-5, 12
     u_exp, cyc_exp, hist_exp, rc_exp = oracle.cd_run(u0, P, steps=steps, tol=tol, max_cycles=mc, smoother=smoother,
@@ -123,7 +110,7 @@ def test_cd_run_reduces_residual_by_1e5_within_five_cycles(dev_ok):
     the remaining residual's sum."""
     n = 1024
     P = oracle.CD(tau=10.0 / n**2, k=0.1)
-    u0 = noisy_image(2, n, 7)
+    u0 = inputs.noisy_image(2, n, 7)
     ctx = mg().mg_cdiff_setup(2, n, P.tau, P.theta, P.k)
     try:
         u = dev(u0)

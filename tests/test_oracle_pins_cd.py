@@ -27,25 +27,17 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+import inputs
 import oracle
 
 RB, JAC = oracle.SMOOTH_RBGS, oracle.SMOOTH_JACOBI
 
 
-def cell_centres(n):
-    return (np.arange(n) + 0.5) / n
-
-
 def cos_mode(dim, n, kv):
-    c = [np.cos(ka * np.pi * cell_centres(n)) for ka in kv]
+    c = [np.cos(ka * np.pi * inputs.cell_centres(n)) for ka in kv]
     if dim == 2:
         return np.ascontiguousarray(np.multiply.outer(c[1], c[0]))
     return np.ascontiguousarray(np.multiply.outer(np.multiply.outer(c[2], c[1]), c[0]))
-
-
-def rand_c(dim, n, seed, scale=1.0):
-    rng = np.random.default_rng(seed)
-    return np.ascontiguousarray((rng.uniform(-1, 1, (n,) * dim) + 0.3j * rng.uniform(-1, 1, (n,) * dim)) * scale)
 
 
 def matrix_of(u, P, dim, n):
@@ -76,7 +68,7 @@ def matrix_of(u, P, dim, n):
 
 def test_diffusivity_matches_definition():
     P = oracle.CD(tau=1e-3, k=0.1)
-    u = rand_c(2, 32, 1, 0.05)
+    u = inputs.random_complex(2, 32, 1, 0.05)
     g = oracle.cd_g(u, P)
     ref = np.exp(1j * P.theta) / (1.0 + (u.imag / (P.k * P.theta)) ** 2)
     np.testing.assert_allclose(g, ref, rtol=2e-16 * 8, atol=0)
@@ -85,7 +77,7 @@ def test_diffusivity_matches_definition():
 @pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
 def test_operator_equals_face_assembled_matrix(dim, n):
     P = oracle.CD(tau=10.0 / n**2, k=0.1)
-    u = rand_c(dim, n, 2, 0.05)
+    u = inputs.random_complex(dim, n, 2, 0.05)
     M = matrix_of(u, P, dim, n)
     got = oracle.cd_apply(u, P).ravel()
     ref = M @ u.ravel()
@@ -106,7 +98,7 @@ def test_constant_diffusivity_cosine_eigenmodes(dim, n):
 @pytest.mark.parametrize("dim,n,smoother", [(2, 16, RB), (3, 8, RB), (2, 16, JAC)])
 def test_linear_fas_solve_equals_dense_solve(dim, n, smoother):
     P = oracle.CD(tau=100.0 / n**2, k=1e300)
-    f = rand_c(dim, n, 3)
+    f = inputs.random_complex(dim, n, 3)
     u = np.zeros_like(f)
     omega = 1.0 if smoother == RB else 0.8
     for _ in range(60):
@@ -130,19 +122,10 @@ def test_heat_limit_one_time_step():
     np.testing.assert_allclose(u, phi / (1.0 + P.tau * lam), rtol=0, atol=1e-11)
 
 
-def noisy_image(dim, n, seed, sigma=0.1):
-    rng = np.random.default_rng(seed)
-    x = cell_centres(n)
-    grids = np.meshgrid(*([x] * dim), indexing="ij")[::-1]  # x, y[, z]
-    r2 = sum((g - 0.5) ** 2 for g in grids)
-    img = (r2 < 0.09).astype(float)
-    return np.ascontiguousarray((img + sigma * rng.standard_normal(img.shape)).astype(np.complex128))
-
-
 @pytest.mark.parametrize("dim,n", [(2, 32), (3, 16)])
 def test_nonlinear_step_solves_assembled_system_and_conserves_mass(dim, n):
     P = oracle.CD(tau=10.0 / n**2, k=0.1)
-    u0 = noisy_image(dim, n, 4)
+    u0 = inputs.noisy_image(dim, n, 4)
     u1, cyc, hist, rc = oracle.cd_run(u0, P, steps=1, tol=1e-12, max_cycles=60)
     assert rc == 0
     f = u0 / P.tau
@@ -158,7 +141,7 @@ def test_fas_reduces_residual_by_1e5_within_five_cycles(dim, n):
     """Section 4: for complex diffusion the residual is reduced by 1e5 (within
     the five V(2,2) cycles of its Poisson statement)."""
     P = oracle.CD(tau=10.0 / n**2, k=0.1)
-    u0 = noisy_image(dim, n, 5)
+    u0 = inputs.noisy_image(dim, n, 5)
     u, cyc, hist, rc = oracle.cd_run(u0, P, steps=3, tol=1e-5, max_cycles=5)
     assert rc == 0 and all(c <= 5 for c in cyc)
     for h in hist:
