@@ -430,13 +430,62 @@ def bench_serving(args, mg, torch):
     }
 
 
+# Table 2's complex-diffusion rows: one V(2,2) cycle on N = 4096^2 (2D) and
+# 256^3 (3D) cells; the paper's generated GPU code in double precision, in ms
+# (GTX 680: the 1-core time divided by the GPU speed-up of the Double column).
+CDIFF_PAPER_MS = {(2, 1): 9235 / 23.99, (2, 0): 7504 / 11.62, (3, 1): 8799 / 15.94, (3, 0): 9048 / 10.28}
+
+
+def bench_cdiff(mg, torch, inputs, cycles: int = 5) -> dict:
+    """Complex diffusion (implicit Euler, FAS with lagged diffusivity) at
+    Table 2's sizes: the time of one FAS V(2,2) cycle (RBGS and Jacobi, FP64
+    complex), inputs resident, and one whole time step to a 1e5 reduction."""
+    import math
+
+    out = {}
+    for dim, n in ((2, 4096), (3, 256)):
+        u0 = torch.from_numpy(inputs.noisy_image(dim, n, 11)).to("cuda")
+        tau = 10.0 / n**2
+        f = u0 * (1.0 / tau)
+        cells = n**dim
+        for sm, name in ((0, "rbgs"), (1, "jacobi")):
+            ctx = mg.mg_cdiff_setup(dim, n, tau, math.pi / 30, 0.1, smoother=sm)
+            u = u0.clone()
+            mg.mg_cdiff_fas(ctx, u, f)  # warm
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(cycles):
+                mg.mg_cdiff_fas(ctx, u, f)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_cycle = e0.elapsed_time(e1) / cycles
+            u.copy_(u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, cyc, hist = mg.mg_cdiff_run(ctx, u, 1, 1e-5, 10)
+            t1 = time.perf_counter()
+            mg.mg_destroy(ctx)
+            paper = CDIFF_PAPER_MS[(dim, sm)]
+            out[f"cdiff{dim}d_{n}_{name}"] = {
+                "cells": cells, "ms_per_fas_cycle": ms_cycle, "cells_per_s": cells / (ms_cycle * 1e-3),
+                "time_step": {"ms": (t1 - t0) * 1e3, "cycles": cyc[0], "status": st,
+                              "reduction": hist[0][-1] / hist[0][0]},
+                "paper_gtx680_fp64_ms_per_cycle": paper, "speedup_vs_paper_context": paper / ms_cycle}
+            log(f"[bench] complex diffusion {dim}D {n}^{dim} {name}: {ms_cycle:.3f} ms per FAS V(2,2) cycle, "
+                f"time step {cyc[0]} cycles in {(t1 - t0) * 1e3:.2f} ms")
+        del u0, f, u
+        torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="poisson3d_513_fp32ir",
-                    choices=sorted(WORKLOADS) + ["batched_2d", "serving_mix"])
+                    choices=sorted(WORKLOADS) + ["batched_2d", "serving_mix", "complex_diffusion"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 context solve")
     ap.add_argument("--no-fp16", action="store_true", help="skip the binary16-cycle solve of the same problem")
@@ -450,6 +499,8 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-budget-gib", type=int, default=48)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run the plain copy kernel over 1 GiB three times (counter calibration)")
+    ap.add_argument("--no-cdiff", action="store_true",
+                    help="skip the complex-diffusion leg of the default workload's line")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and serving legs of the default workload's line")
     ap.add_argument("--forms-requests", type=int, default=1000,
@@ -482,6 +533,13 @@ def main(argv=None) -> int:
         return 0
     if args.workload == "serving_mix":
         print(json.dumps(bench_serving(args, mg, torch)), flush=True)
+        mg.shutdown()
+        return 0
+    if args.workload == "complex_diffusion":
+        import inputs
+
+        print(json.dumps({"workload": "complex_diffusion", "unit": "ms per FAS V(2,2) cycle",
+                          "legs": bench_cdiff(mg, torch, inputs, cycles=args.steps)}), flush=True)
         mg.shutdown()
         return 0
     w = WORKLOADS[args.workload]
@@ -703,6 +761,10 @@ def main(argv=None) -> int:
         extra["serving_mix"] = {"requests_per_lambda": sargs.serve_requests, "config": sv["config"],
                                 "saturated_solves_per_s": sv["value"], **sv["extra"]}
         torch.cuda.empty_cache()
+    if args.workload == "poisson3d_513_fp32ir" and not args.no_cdiff:
+        import inputs
+
+        extra["complex_diffusion"] = bench_cdiff(mg, torch, inputs)
 
     cpu = None
     if not args.no_cpu:
