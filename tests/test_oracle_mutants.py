@@ -39,7 +39,8 @@ MUTANTS = {
                             "                const double r = (double)residual_at",
                             "for (int j = 1; j < n - 2; ++j)\n            for (int i = 1; i < n - 1; ++i) {\n"
                             "                const double r = (double)residual_at"),
-    "norm_no_sqrt": ("return std::sqrt(s);", "return s;"),
+    "norm_no_sqrt": ("for (int k = k0; k < k1; ++k) s += part[(size_t)k];\n    return std::sqrt(s);",
+                     "for (int k = k0; k < k1; ++k) s += part[(size_t)k];\n    return s;"),
     "norm_abs_not_square": ("s += r * r;", "s += std::fabs(r);"),
     "norm_plain_sum": ("s += r * r;", "s += r;"),
     "symmetric_post_red_first": ("rbgs_sweep(g, u, f, post);", "rbgs_sweep(g, u, f, 0);"),
