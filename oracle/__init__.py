@@ -101,6 +101,11 @@ def _load():
         "orc_cc_residual_norm": (_d, [_i, _i, _p, _p]),
         "orc_cc_cycle": (_i, [_i, _i, _i, _d, _i, _i, _i, _p, _p]),
         "orc_cc_solve": (_i, [_i, _i, _i, _d, _i, _i, _i, _p, _p, _d, _i, _p, _p, _p]),
+        "orc_st_residual": (None, [_i, _i, _p, _p, _p, _p]),
+        "orc_st_smooth": (None, [_i, _i, _p, _i, _d, _p, _p]),
+        "orc_st_coarsest": (None, [_i, _p, _p, _p]),
+        "orc_st_residual_norm": (_d, [_i, _i, _p, _p, _p]),
+        "orc_st_solve": (_i, [_i, _i, _p, _i, _d, _i, _i, _i, _p, _p, _d, _i, _p, _p]),
         "orc_cd_apply": (None, [_i, _i, _d, _d, _d, _d, _d, _p, _p]),
         "orc_cd_g": (None, [_i, _i, _d, _d, _d, _d, _p, _p]),
         "orc_cd_sweep": (None, [_i, _i, _d, _d, _d, _d, _d, _i, _d, _p, _p]),
@@ -509,3 +514,65 @@ def cd_run(u0, P: CD, steps=1, tol=1e-5, max_cycles=20, smoother=SMOOTH_RBGS, om
     if rc == -1:
         raise ValueError("oracle run rejected its arguments")
     return u, cyc[:steps].copy(), [hist[m, : cyc[m] + 1].copy() for m in range(steps)], rc
+
+
+# ------------------------------------------------------------------ constant stencil
+# A = (1/h^2) stencil on node-based Dirichlet grids (FP64); the stencil is a
+# sequence of 2d+1 coefficients, centre first, then -x, +x, -y, +y[, -z, +z].
+def _st(stencil, dim):
+    a = np.ascontiguousarray(np.asarray(stencil, dtype=np.float64))
+    if a.shape != (2 * dim + 1,):
+        raise ValueError(f"a {dim}D stencil has {2 * dim + 1} coefficients")
+    return a
+
+
+def st_residual(u, f, stencil):
+    _chk(u, np.float64, "u"), _chk(f, np.float64, "f")
+    dim, n = _dims(u)
+    a = _st(stencil, dim)
+    r = np.zeros_like(u)
+    _load().orc_st_residual(dim, n, _ptr(a), _ptr(u), _ptr(f), _ptr(r))
+    return r
+
+
+def st_smooth(u, f, stencil, smoother=SMOOTH_RBGS, omega=1.0):
+    _chk(u, np.float64, "u"), _chk(f, np.float64, "f")
+    dim, n = _dims(u)
+    a = _st(stencil, dim)
+    out = u.copy()
+    _load().orc_st_smooth(dim, n, _ptr(a), smoother, omega, _ptr(out), _ptr(f))
+    return out
+
+
+def st_coarsest(f, stencil):
+    _chk(f, np.float64, "f")
+    dim, n = _dims(f)
+    if n != 3:
+        raise ValueError("the coarsest grid has n = 3")
+    a = _st(stencil, dim)
+    u = np.zeros_like(f)
+    _load().orc_st_coarsest(dim, _ptr(a), _ptr(u), _ptr(f))
+    return u
+
+
+def st_residual_norm(u, f, stencil) -> float:
+    _chk(u, np.float64, "u"), _chk(f, np.float64, "f")
+    dim, n = _dims(u)
+    a = _st(stencil, dim)
+    return float(_load().orc_st_residual_norm(dim, n, _ptr(a), _ptr(u), _ptr(f)))
+
+
+def st_solve(u0, f, stencil, tol=1e-8, max_cycles=50, smoother=SMOOTH_RBGS, omega=1.0, nu1=2, nu2=2,
+             cycle=CYCLE_V):
+    """FP64 multigrid solve with a constant stencil.  Returns (u, history, status)."""
+    _chk(u0, np.float64, "u0"), _chk(f, np.float64, "f")
+    dim, n = _dims(u0)
+    a = _st(stencil, dim)
+    u = u0.copy()
+    hist = np.zeros(max_cycles + 1)
+    cyc = C.c_int(0)
+    rc = _load().orc_st_solve(dim, n, _ptr(a), smoother, omega, nu1, nu2, cycle, _ptr(u), _ptr(f), tol, max_cycles,
+                              _ptr(hist), C.addressof(cyc))
+    if rc < 0:
+        raise ValueError(f"oracle solve rejected its arguments (rc={rc})")
+    return u, hist[: cyc.value + 1].copy(), rc

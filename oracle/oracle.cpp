@@ -49,6 +49,12 @@
  * coarse k is taken by injection k_{l+1}(I) = k_l(2I) and the operator is
  * re-discretised on every level (Table 1, "direct (re-discretization)").
  *
+ * Constant stencil (Section 2.2: the discretisation is a stencil declared
+ * with constant entries; the Laplacian's 5-/7-point stencil is one choice):
+ * (A u)_p = (1/h^2) (s0 u_p + sW u_W + sE u_E + sS u_S + sN u_N [+ sB u_B + sT u_T]),
+ * coefficients given centre first, then -x, +x, -y, +y[, -z, +z]; the same
+ * stencil on every level with that level's h ("direct" coarse operators).
+ *
  * Layout: x fastest, idx = (k*n + j)*n + i (3D) or j*n + i (2D).
  */
 #include <algorithm>
@@ -139,6 +145,7 @@ struct Grid {
     T wd;         /* omega*h^2/(2d): inverse diagonal times omega (Poisson) */
     T omega;      /* smoother weight */
     const T* k;   /* nodal coefficient (variable coefficients), in the arithmetic type, or nullptr */
+    const T* st = nullptr; /* constant stencil (2d+1 entries, centre first), or nullptr */
 };
 
 /* harmonic-mean face coefficient between nodes with values a and b */
@@ -184,10 +191,23 @@ inline typename Arith<S>::type apply_varcoef(const Grid<S>& g, const S* u, idx_t
     return g.c * (dsum * u[p] - t);
 }
 
+/* Constant stencil: (A u)_p = c * (s0 u_p + t), t the weighted neighbours
+ * paired as ((W+E)+(S+N))+(B+T) */
+template <typename S>
+inline typename Arith<S>::type apply_stencil(const Grid<S>& g, const S* u, idx_t p) {
+    typedef typename Arith<S>::type T;
+    const idx_t sx = 1, sy = g.n, sz = (idx_t)g.n * g.n;
+    const T* a = g.st;
+    T t = (a[1] * u[p - sx] + a[2] * u[p + sx]) + (a[3] * u[p - sy] + a[4] * u[p + sy]);
+    if (g.dim == 3) t = t + (a[5] * u[p - sz] + a[6] * u[p + sz]);
+    return g.c * (a[0] * u[p] + t);
+}
+
 /* residual r_p = f_p - (A u)_p */
 template <typename S>
 inline typename Arith<S>::type residual_at(const Grid<S>& g, const S* u, const S* f, idx_t p) {
     typedef typename Arith<S>::type T;
+    if (g.st) return f[p] - apply_stencil(g, u, p);
     if (g.k) {
         T dsum;
         const T Au = apply_varcoef(g, u, p, &dsum);
@@ -206,7 +226,8 @@ inline typename Arith<S>::type smooth_at(const Grid<S>& g, const S* u, const S* 
         const T r = f[p] - Au;
         return u[p] + (g.omega * r) / (g.c * dsum);
     }
-    const T r = f[p] - apply_poisson(g, u, p);
+    /* constant stencils: wd = omega h^2 / s0 (the Laplacian's s0 = 2d) */
+    const T r = f[p] - (g.st ? apply_stencil(g, u, p) : apply_poisson(g, u, p));
     return u[p] + g.wd * r;
 }
 
@@ -378,7 +399,9 @@ void coarsest_solve(const Grid<S>& g, S* u, const S* f) {
     typedef typename Arith<S>::type T;
     const idx_t p = at(g.dim, 3, 1, 1, 1);
     T diag;
-    if (g.k) {
+    if (g.st) {
+        diag = g.c * g.st[0];
+    } else if (g.k) {
         T dsum;
         (void)apply_varcoef(g, u, p, &dsum);
         diag = g.c * dsum;
@@ -411,6 +434,11 @@ inline double level_wd(int dim, int n, double omega) {
     const double h = 1.0 / (double)(n - 1);
     return (omega * (h * h)) / (2.0 * (double)dim);
 }
+/* constant stencil with centre entry s0: omega h^2 / s0 */
+inline double level_wd_st(int n, double omega, double s0) {
+    const double h = 1.0 / (double)(n - 1);
+    return (omega * (h * h)) / s0;
+}
 
 template <typename S>
 struct Hierarchy {
@@ -423,6 +451,8 @@ struct Hierarchy {
     std::vector<int> n;               /* n[0] finest */
     std::vector<std::vector<S>> u, f;  /* iterate and right-hand side, storage type */
     std::vector<std::vector<T>> r, k;  /* residual and coefficient, arithmetic type */
+    std::vector<T> st;                 /* constant stencil (same on every level), or empty */
+    double st0 = 0.0;                  /* its centre entry as given */
     std::vector<S> tmp;
 
     Grid<S> grid(int l) const {
@@ -430,10 +460,17 @@ struct Hierarchy {
         g.dim = dim;
         g.n = n[(size_t)l];
         g.c = (T)level_c(g.n);
-        g.wd = (T)level_wd(dim, g.n, omega);
+        g.wd = st.empty() ? (T)level_wd(dim, g.n, omega) : (T)level_wd_st(g.n, omega, st0);
         g.omega = (T)omega;
         g.k = k.empty() ? nullptr : k[(size_t)l].data();
+        g.st = st.empty() ? nullptr : st.data();
         return g;
+    }
+    void set_stencil(const double* s64) {
+        st.clear();
+        if (!s64) return;
+        for (int q = 0; q < 2 * dim + 1; ++q) st.push_back((T)s64[q]);
+        st0 = s64[0];
     }
 };
 
@@ -541,7 +578,9 @@ void coarsest_cg(const Grid<S>& g, S* u, const S* f, int iters) {
             for (int j = 1; j < n - 1; ++j)
                 for (int i = 1; i < n - 1; ++i) {
                     const idx_t x = at(dim, n, i, j, k);
-                    if (g.k) {
+                    if (g.st) {
+                        q[(size_t)x] = apply_stencil(g, p.data(), x);
+                    } else if (g.k) {
                         T dsum;
                         q[(size_t)x] = apply_varcoef(g, p.data(), x, &dsum);
                     } else {
@@ -1291,6 +1330,60 @@ int orc_solve_f64(int dim, int n, const double* k, int smoother, double omega, i
                   const double* f, double tol, int max_cycles, double* hist, int* cycles) {
     return orc_solve_mg_f64(dim, n, k, smoother, omega, nu1, nu2, CYCLE_V, 3, 0, u, f, tol, max_cycles, hist,
                             cycles);
+}
+
+/* ------------------------------------------------------------------ */
+/* Constant stencil (FP64): st holds 2d+1 coefficients, centre first,    */
+/* then -x, +x, -y, +y[, -z, +z]; A = (1/h^2) stencil on every level.     */
+/* ------------------------------------------------------------------ */
+
+static Grid<double> st_grid(int dim, int n, const double* st, double omega) {
+    Grid<double> g = make_grid<double>(dim, n, nullptr, omega);
+    g.st = st;
+    g.wd = level_wd_st(n, omega, st[0]);
+    return g;
+}
+void orc_st_residual(int dim, int n, const double* st, const double* u, const double* f, double* r) {
+    residual(st_grid(dim, n, st, 1.0), u, f, r);
+}
+/* one sweep in place: smoother 0 RBGS red first, 1 Jacobi, 2 RBGS black first */
+void orc_st_smooth(int dim, int n, const double* st, int smoother, double omega, double* u, const double* f) {
+    const Grid<double> g = st_grid(dim, n, st, omega);
+    std::vector<double> tmp;
+    if (smoother == SMOOTH_JACOBI) jacobi_sweep(g, u, f, tmp);
+    else rbgs_sweep(g, u, f, smoother == SMOOTH_RBGS_SYM ? 1 : 0);
+}
+void orc_st_coarsest(int dim, const double* st, double* u, const double* f) {
+    coarsest_solve(st_grid(dim, 3, st, 1.0), u, f);
+}
+double orc_st_residual_norm(int dim, int n, const double* st, const double* u, const double* f) {
+    return residual_norm(st_grid(dim, n, st, 1.0), u, f);
+}
+/* cycles (V 0, W 1, F 2) down to n = 3 until ||f - A u|| <= tol rho_0 or
+ * max_cycles, as orc_solve_mg_f64 */
+int orc_st_solve(int dim, int n, const double* st, int smoother, double omega, int nu1, int nu2, int cycle,
+                 double* u, const double* f, double tol, int max_cycles, double* hist, int* cycles) {
+    if ((dim != 2 && dim != 3) || !valid_edge(n) || max_cycles < 0 || !valid_opts(n, cycle, 3) || !st ||
+        !(st[0] > 0.0))
+        return -1;
+    Hierarchy<double> H;
+    build(H, dim, n, nullptr, smoother, omega, nu1, nu2, 3);
+    H.set_stencil(st);
+    H.cycle = cycle;
+    const Grid<double> g0 = H.grid(0);
+    const double rho0 = residual_norm(g0, u, f);
+    if (hist) hist[0] = rho0;
+    int it = 0;
+    int status = rho0 == 0.0 ? 0 : 1;
+    while (status == 1 && it < max_cycles) {
+        vcycle(H, 0, u, f);
+        ++it;
+        const double rho = residual_norm(g0, u, f);
+        if (hist) hist[it] = rho;
+        if (rho <= tol * rho0) status = 0;
+    }
+    if (cycles) *cycles = it;
+    return status;
 }
 
 /* One FP64 refinement pass: u += e (inner nodes), r = f - A u in FP64,

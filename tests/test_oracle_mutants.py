@@ -77,12 +77,17 @@ MUTANTS = {
     "cd_correction_not_differenced": ("u[p] = cx_add(u[p], cx_sub(uc[q], uh[q]));", "u[p] = cx_add(u[p], uc[q]);"),
     "cd_complex_product_sign": ("return Cx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};",
                                 "return Cx{a.re * b.re + a.im * b.im, a.re * b.im + a.im * b.re};"),
+    "st_west_east_swapped": ("T t = (a[1] * u[p - sx] + a[2] * u[p + sx])", "T t = (a[2] * u[p - sx] + a[1] * u[p + sx])"),
+    "st_bottom_top_swapped": ("t = t + (a[5] * u[p - sz] + a[6] * u[p + sz]);",
+                              "t = t + (a[6] * u[p - sz] + a[5] * u[p + sz]);"),
+    "st_weight_laplacian_diagonal": ("return (omega * (h * h)) / s0;", "return (omega * (h * h)) / 4.0;"),
+    "st_coarsest_laplacian_diagonal": ("diag = g.c * g.st[0];", "diag = g.c * (g.dim == 2 ? T(4) : T(6));"),
     "cc_sum_skips_last_cell": ("for (int i = 0; i < n; ++i) row += u[cc_at(dim, n, i, j, k)];",
                                "for (int i = 0; i < n - 1; ++i) row += u[cc_at(dim, n, i, j, k)];"),
 }
 
 PIN_FILES = ["test_oracle_pins.py", "test_oracle_pins_variants.py", "test_oracle_pins_fp16.py",
-             "test_oracle_pins_cc.py", "test_oracle_pins_cd.py"]
+             "test_oracle_pins_cc.py", "test_oracle_pins_cd.py", "test_oracle_pins_stencil.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
