@@ -51,8 +51,15 @@ enum mg_status {
 };
 
 enum mg_operator {
-    MG_OP_LAPLACE = 0,       /* constant 5-point (2D) / 7-point (3D) stencil, Section 2.2 */
-    MG_OP_VARCOEF_NODAL = 2  /* -div(k grad u): nodal k, face k = 2 k_p k_q / (k_p + k_q) */
+    MG_OP_LAPLACE = 0,        /* constant 5-point (2D) / 7-point (3D) stencil, Section 2.2 */
+    MG_OP_CONST_STENCIL = 1,  /* a constant stencil of the caller's (Section 2.2 declares the discretisation
+                                 as a stencil with constant entries): (A u)_p = (1/h^2)(s0 u_p + sW u_W +
+                                 sE u_E + sS u_S + sN u_N [+ sB u_B + sT u_T]), the same stencil with each
+                                 level's h (re-discretisation; consistent for a second-order operator,
+                                 entries summing to zero, e.g. anisotropic diffusion); smoothing
+                                 u + omega h^2 / s0 (f - A u).  MG_PREC_FP64 and coarse_n 0 or 3 only
+                                 (MG_ENOTSUP otherwise); plain one-node-per-thread kernels, level by level */
+    MG_OP_VARCOEF_NODAL = 2   /* -div(k grad u): nodal k, face k = 2 k_p k_q / (k_p + k_q) */
 };
 enum mg_bc {
     MG_BC_DIRICHLET_ZERO = 0,  /* node-based grid, n = 2^L + 1 nodes per axis, zero boundary values */
@@ -110,6 +117,12 @@ typedef struct mg_params {
                         with MG_PREC_FP64, 65 / 17 otherwise (MG_ENOTSUP beyond) */
     int cg_iters;    /* CG steps on a coarsest level with coarse_n > 3 (0: 4 (coarse_n - 1)); fewer only
                         if the residual or p^T A p becomes zero */
+    const double* stencil; /* MG_OP_CONST_STENCIL: HOST pointer to 2*dim + 1 finite coefficients, centre
+                        first (> 0), then -x, +x, -y, +y[, -z, +z]; copied during mg_setup; otherwise
+                        ignored */
+    double h;        /* grid spacing: 0 selects the unit domain's (1/(n-1) on node grids, 1/n on
+                        cell-centred grids); any other positive value must equal it (MG_ENOTSUP:
+                        other domain sizes are not built), negative or non-finite: MG_EINVAL */
 } mg_params;
 
 /* Build the level hierarchy n, (n-1)/2+1, ..., 3 (Section 2.2 coarsening by 2;
@@ -250,6 +263,19 @@ int mg_cdiff_apply(mg_ctx* ctx, const double* u, double* out);
  * residual norms (row m starts at m * (max_cycles + 1)).  Synchronises the
  * stream.  Returns MG_OK, or MG_ENOTCONV if a step missed the tolerance. */
 int mg_cdiff_run(mg_ctx* ctx, double* u, int steps, double tol, int max_cycles, int* cycles, double* res_hist);
+
+/* Constant stencil (MG_OP_CONST_STENCIL), FP64, node grids of n = 2^L + 1
+ * nodes per axis; 'stencil' is a HOST pointer to 2*dim + 1 coefficients
+ * (centre first, > 0, then -x, +x, -y, +y[, -z, +z]).  One smoothing sweep
+ * u_in -> u_out (smoother 0 RBGS red first, 1 Jacobi (u_out != u_in), 2
+ * RBGS black first; omega <= 0: 1.0 / 0.8); fc (inner coarse nodes, edge
+ * (n-1)/2+1, n >= 5) = full weighting of f - A u; and the exact solve of the
+ * single unknown of a 3-node grid, u = f / (c s0).  Asynchronous. */
+int mg_level_st_smooth(int dim, int n, const double* stencil, int smoother, double omega, const double* u_in,
+                       const double* f, double* u_out, void* stream);
+int mg_level_st_residual_restrict(int dim, int n, const double* stencil, const double* u, const double* f,
+                                  double* fc, void* stream);
+int mg_level_st_coarsest(int dim, const double* stencil, double* u, const double* f, void* stream);
 
 /* Cell-centred Neumann grids (MG_BC_NEUMANN_CC), FP64, n = 2^L cells per axis
  * (n >= 2), the operations of a cycle: one smoothing sweep u_in -> u_out

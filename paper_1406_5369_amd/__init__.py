@@ -24,7 +24,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mg.h")
 
 # status codes (enum mg_status)
 MG_OK, MG_ENOTCONV, MG_EINVAL, MG_ENOTSUP, MG_ENOMEM, MG_EDEVICE, MG_EDIVERGED, MG_EBUSY = 0, 1, -1, -2, -3, -4, -5, -6
-OP_LAPLACE, OP_VARCOEF_NODAL = 0, 2
+OP_LAPLACE, OP_CONST_STENCIL, OP_VARCOEF_NODAL = 0, 1, 2
 BC_DIRICHLET_ZERO, BC_NEUMANN_CC = 0, 1
 SMOOTH_RBGS, SMOOTH_JACOBI, SMOOTH_RBGS_SYM = 0, 1, 2
 CYCLE_V, CYCLE_W, CYCLE_F = 0, 1, 2
@@ -52,6 +52,8 @@ class _Params(C.Structure):
         ("cycle", C.c_int),
         ("coarse_n", C.c_int),
         ("cg_iters", C.c_int),
+        ("stencil", C.c_void_p),
+        ("h", C.c_double),
     ]
 
 
@@ -114,6 +116,9 @@ def lib():
             "mg_cdiff_fas": (i, [p, p, p]),
             "mg_cdiff_apply": (i, [p, p, p]),
             "mg_cdiff_run": (i, [p, p, i, d, i, p, p]),
+            "mg_level_st_smooth": (i, [i, i, p, i, d, p, p, p, p]),
+            "mg_level_st_residual_restrict": (i, [i, i, p, p, p, p, p]),
+            "mg_level_st_coarsest": (i, [i, p, p, p, p]),
             "mg_level_cc_smooth": (i, [i, i, i, d, p, p, p, p]),
             "mg_level_cc_residual_restrict": (i, [i, i, p, p, p, p]),
             "mg_level_cc_prolong_correct": (i, [i, i, p, p, p]),
@@ -208,6 +213,8 @@ class Params:
     cycle: int = CYCLE_V
     coarse_n: int = 0  # 0 / 3: exact 3-node coarsest solve; larger: conjugate gradients there
     cg_iters: int = 0  # 0: 4 (coarse_n - 1)
+    stencil: object = None  # OP_CONST_STENCIL: 2*dim + 1 coefficients, centre first, then -x, +x, -y, +y[, -z, +z]
+    h: float = 0.0  # 0: the unit domain's spacing
 
     def __post_init__(self):
         if self.omega <= 0.0:
@@ -221,8 +228,15 @@ class Params:
         import torch
 
         kp = _dptr(self.k, torch.float64, self.shape, "k") if self.k is not None else None
-        return _Params(self.dim, self.n, self.op, kp, self.bc, self.smoother, self.omega, self.nu1, self.nu2,
-                       self.precision, self.cycle, self.coarse_n, self.cg_iters)
+        st = None
+        if self.stencil is not None:
+            vals = [float(x) for x in self.stencil]
+            st = (C.c_double * len(vals))(*vals)
+        cp = _Params(self.dim, self.n, self.op, kp, self.bc, self.smoother, self.omega, self.nu1, self.nu2,
+                     self.precision, self.cycle, self.coarse_n, self.cg_iters,
+                     C.cast(st, C.c_void_p) if st is not None else None, float(self.h))
+        cp._stencil_buf = st  # keeps the host array alive while the structure is in use
+        return cp
 
 
 # Handles created through this module and not yet destroyed, in creation
@@ -374,6 +388,44 @@ def mg_level_coarsest_cg(u, f, k=None, iters=0, stream=None) -> None:
     dt = f.dtype
     _check(lib().mg_level_coarsest_cg(dim, n, _dtype_code(f), _dptr(k, dt, f.shape, "k"), _dptr(u, dt, f.shape, "u"),
                                       _dptr(f, dt, f.shape, "f"), int(iters), _stream(stream)), "mg_level_coarsest_cg")
+
+
+# constant stencil (FP64, node grids): host stencil of 2*dim + 1 coefficients
+def _st_host(stencil, dim):
+    vals = [float(x) for x in stencil]
+    if len(vals) != 2 * dim + 1:
+        raise ValueError(f"a {dim}D stencil has {2 * dim + 1} coefficients")
+    return (C.c_double * len(vals))(*vals)
+
+
+def mg_level_st_smooth(u_in, f, u_out, stencil, smoother=SMOOTH_RBGS, omega=0.0, stream=None) -> None:
+    import torch
+
+    dim, n = f.dim(), f.shape[0]
+    _check(lib().mg_level_st_smooth(dim, n, _st_host(stencil, dim), smoother, float(omega),
+                                    _dptr(u_in, torch.float64, f.shape, "u_in"), _dptr(f, torch.float64, None, "f"),
+                                    _dptr(u_out, torch.float64, f.shape, "u_out"), _stream(stream)),
+           "mg_level_st_smooth")
+
+
+def mg_level_st_residual_restrict(u, f, fc, stencil, stream=None) -> None:
+    import torch
+
+    dim, n = f.dim(), f.shape[0]
+    nc = (n - 1) // 2 + 1
+    _check(lib().mg_level_st_residual_restrict(dim, n, _st_host(stencil, dim), _dptr(u, torch.float64, f.shape, "u"),
+                                               _dptr(f, torch.float64, None, "f"),
+                                               _dptr(fc, torch.float64, (nc,) * dim, "fc"), _stream(stream)),
+           "mg_level_st_residual_restrict")
+
+
+def mg_level_st_coarsest(u, f, stencil, stream=None) -> None:
+    import torch
+
+    dim = f.dim()
+    _check(lib().mg_level_st_coarsest(dim, _st_host(stencil, dim), _dptr(u, torch.float64, (3,) * dim, "u"),
+                                      _dptr(f, torch.float64, (3,) * dim, "f"), _stream(stream)),
+           "mg_level_st_coarsest")
 
 
 # complex diffusion (FP64 complex, n = 2^L cells per axis, Neumann boundary)

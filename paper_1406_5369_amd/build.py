@@ -32,6 +32,7 @@ SOURCES = [
     "mg_tail.hip",
     "mg_cc.hip",
     "mg_cd.hip",
+    "mg_st.hip",
 ]
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -10,6 +10,7 @@
 
 #include "mg_cc.h"
 #include "mg_cd.h"
+#include "mg_st.h"
 #include "mg_solver.h"
 
 using namespace mg;
@@ -206,14 +207,40 @@ int validate_cc(const mg_params* p) {
     return MG_OK;
 }
 
+// Grid spacing: 0 selects the unit domain's h; any other value must be it
+// (1/(n-1) on node grids, 1/n on cell-centred grids).
+int validate_h(const mg_params* p) {
+    if (p->h == 0.0) return MG_OK;
+    if (!(p->h > 0.0) || !std::isfinite(p->h)) return MG_EINVAL;
+    const double h = p->bc == MG_BC_NEUMANN_CC ? 1.0 / (double)p->n : 1.0 / (double)(p->n - 1);
+    return p->h == h ? MG_OK : MG_ENOTSUP;
+}
+
+// A constant stencil: 2d+1 finite FP64 coefficients on the host, centre > 0.
+int validate_stencil(const mg_params* p) {
+    if (!p->stencil) return MG_EINVAL;
+    for (int q = 0; q < 2 * p->dim + 1; ++q)
+        if (!std::isfinite(p->stencil[q])) return MG_EINVAL;
+    if (!(p->stencil[0] > 0.0)) return MG_EINVAL;
+    if (p->precision != MG_PREC_FP64 || p->coarse_n > 3) return MG_ENOTSUP;
+    return MG_OK;
+}
+
 int validate(const mg_params* p) {
     if (!p) return MG_EINVAL;
     if (p->dim != 2 && p->dim != 3) return MG_EINVAL;
-    if (p->bc == MG_BC_NEUMANN_CC) return validate_cc(p);
+    if (p->bc == MG_BC_NEUMANN_CC) {
+        const int v = validate_cc(p);
+        return v != MG_OK ? v : validate_h(p);
+    }
     if (!valid_edge(p->dim, p->n)) return MG_EINVAL;
     if (p->bc != MG_BC_DIRICHLET_ZERO) return MG_ENOTSUP;
-    if (p->op != MG_OP_LAPLACE && p->op != MG_OP_VARCOEF_NODAL) return MG_ENOTSUP;
+    if (p->op != MG_OP_LAPLACE && p->op != MG_OP_VARCOEF_NODAL && p->op != MG_OP_CONST_STENCIL) return MG_ENOTSUP;
     if (p->op == MG_OP_VARCOEF_NODAL && !p->k) return MG_EINVAL;
+    {
+        const int vh = validate_h(p);
+        if (vh != MG_OK) return vh;
+    }
     if (p->smoother != MG_SMOOTH_RBGS && p->smoother != MG_SMOOTH_WJACOBI && p->smoother != MG_SMOOTH_RBGS_SYM)
         return MG_EINVAL;
     if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 > 16 || p->nu2 > 16) return MG_EINVAL;
@@ -224,6 +251,7 @@ int validate(const mg_params* p) {
         return MG_ENOTSUP;
     if (p->precision == MG_PREC_FP16_IR && p->op != MG_OP_LAPLACE) return MG_ENOTSUP;
     if (!(p->omega == p->omega) || p->omega > 2.0) return MG_EINVAL;
+    if (p->op == MG_OP_CONST_STENCIL) return validate_stencil(p);
     return MG_OK;
 }
 
@@ -247,6 +275,11 @@ void destroy(mg_ctx* c) {
     ffree(c->cc_work);
     ffree(c->cc_mean);
     delete c->cd;
+    for (size_t l = 0; l < c->stn.size(); ++l) {
+        if (l > 0) ffree(c->stu[l]);
+        ffree(c->stt[l]);
+        if (l > 0) ffree(c->stf[l]);
+    }
     ffree(c->d_ir);
     ffree(c->d_scl);
     ffree(c->d_pmax);
@@ -552,6 +585,134 @@ int cc_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
         CK(cc_cycle_top(c, u, c->ccfh));
         CK(cc_remove_mean(dim, n, u, c->cc_work, c->cc_mean, s));
         CK(cc_norm(dim, u, c->ccfh, L0, c->d_partial, c->d_norm, s));
+        CK(launch_stop_test(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist, c->hist_cap,
+                            tol, max_cycles, 1, s));
+        CK(hipMemcpyAsync(ctl, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        ++steps;
+    }
+    steps = ctl[1];
+    const int status = ctl[2];
+    if (res_hist) {
+        CK(hipMemcpyAsync(c->h_pin, c->d_hist, sizeof(double) * (size_t)(steps + 1), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        std::memcpy(res_hist, c->h_pin, sizeof(double) * (size_t)(steps + 1));
+    }
+    if (cycles_done) *cycles_done = steps;
+    if (status == 0) return MG_OK;
+    if (status == -5) return MG_EDIVERGED;
+    return MG_ENOTCONV;
+}
+
+// ---------------------------------------------------------------------------
+// Constant stencil: Algorithm 1 level by level (V, W or F), plain kernels,
+// levels n, (n-1)/2+1, ..., 3; the iterate of level l is in 'cur' (the other
+// buffer of the level is the Jacobi partner).
+// ---------------------------------------------------------------------------
+hipError_t st_smooth_level(mg_ctx* c, double*& cur, double*& other, const double* f, const STConst& L, bool post) {
+    const int dim = c->p.dim;
+    hipStream_t s = c->stream;
+    if (c->p.smoother == MG_SMOOTH_WJACOBI) {
+        hipError_t e = st_relax(dim, true, cur, other, f, L, 0, s);
+        std::swap(cur, other);
+        return e;
+    }
+    const int first = (post && c->p.smoother == MG_SMOOTH_RBGS_SYM) ? 1 : 0;
+    hipError_t e = st_relax(dim, false, cur, cur, f, L, first, s);
+    if (e != hipSuccess) return e;
+    return st_relax(dim, false, cur, cur, f, L, 1 - first, s);
+}
+
+hipError_t st_cycle(mg_ctx* c, int l, int kind, double*& cur, double*& other, const double* f) {
+    const int dim = c->p.dim, n = c->stn[(size_t)l];
+    hipStream_t s = c->stream;
+    const STConst L = st_const(dim, n, c->st_coef, c->p.omega);
+    if (l + 1 == (int)c->stn.size()) return st_coarsest(dim, cur, f, L, s);  // n = 3: one unknown
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < c->p.nu1 && e == hipSuccess; ++i) e = st_smooth_level(c, cur, other, f, L, false);
+    if (e != hipSuccess) return e;
+    double* fc = c->stf[(size_t)l + 1];
+    if ((e = st_restrict(dim, cur, f, fc, L, s)) != hipSuccess) return e;
+    double* ucur = c->stu[(size_t)l + 1];
+    double* uoth = c->stt[(size_t)l + 1];
+    const int nc = c->stn[(size_t)l + 1];
+    if ((e = cc_fill(ucur, npts(dim, nc), 0.0, s)) != hipSuccess) return e;  // zero guess
+    if (kind == MG_CYCLE_V) {
+        e = st_cycle(c, l + 1, MG_CYCLE_V, ucur, uoth, fc);
+    } else if (kind == MG_CYCLE_W) {
+        e = st_cycle(c, l + 1, MG_CYCLE_W, ucur, uoth, fc);
+        if (e == hipSuccess) e = st_cycle(c, l + 1, MG_CYCLE_W, ucur, uoth, fc);
+    } else {
+        e = st_cycle(c, l + 1, MG_CYCLE_F, ucur, uoth, fc);
+        if (e == hipSuccess) e = st_cycle(c, l + 1, MG_CYCLE_V, ucur, uoth, fc);
+    }
+    if (e != hipSuccess) return e;
+    c->stu[(size_t)l + 1] = ucur;
+    c->stt[(size_t)l + 1] = uoth;
+    e = st_prolong(dim, cur, ucur, n, s);
+    for (int i = 0; i < c->p.nu2 && e == hipSuccess; ++i) e = st_smooth_level(c, cur, other, f, L, true);
+    return e;
+}
+
+hipError_t st_cycle_top(mg_ctx* c, double* u, const double* f) {
+    double* cur = u;
+    double* other = c->stt[0];
+    hipError_t e = st_cycle(c, 0, c->p.cycle, cur, other, f);
+    if (e == hipSuccess && cur != u)
+        e = hipMemcpyAsync(u, cur, npts(c->p.dim, c->p.n) * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    return e;
+}
+
+int st_setup(mg_ctx* c) {
+    const int dim = c->p.dim;
+    hipStream_t s = c->stream;
+    c->st = true;
+    for (int q = 0; q < 2 * dim + 1; ++q) c->st_coef[q] = c->p.stencil[q];
+    c->p.stencil = nullptr;  // the context keeps its own copy
+    for (int m = c->p.n; m >= 3; m = (m - 1) / 2 + 1) {
+        c->stn.push_back(m);
+        if (m == 3) break;
+    }
+    const size_t L = c->stn.size();
+    c->stu.assign(L, nullptr);
+    c->stt.assign(L, nullptr);
+    c->stf.assign(L, nullptr);
+    for (size_t l = 0; l < L; ++l) {
+        const size_t bytes = npts(dim, c->stn[l]) * sizeof(double);
+        if (l > 0) CK(zalloc((void**)&c->stu[l], bytes, s));
+        CK(zalloc((void**)&c->stt[l], bytes, s));
+        if (l > 0) CK(zalloc((void**)&c->stf[l], bytes, s));
+    }
+    c->nlev = (int)L;
+    c->pstride = st_norm_parts(dim, c->p.n);
+    CK(hipMalloc((void**)&c->d_partial, sizeof(double) * (size_t)c->pstride));
+    CK(hipMalloc((void**)&c->d_norm, sizeof(double)));
+    CK(hipMalloc((void**)&c->d_norm0, sizeof(double)));
+    CK(hipMalloc((void**)&c->d_ctrl, 3 * sizeof(int)));
+    CK(launch_fill_int(c->d_ctrl, 0, 3, s));
+    int r = ensure_hist(c, 64);
+    if (r != MG_OK) return r;
+    CK(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
+int st_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, int* cycles_done, double* res_hist) {
+    const int dim = c->p.dim, n = c->p.n;
+    hipStream_t s = c->stream;
+    const STConst L0 = st_const(dim, n, c->st_coef, c->p.omega);
+    int r = ensure_hist(c, max_cycles + 1);
+    if (r != MG_OK) return r;
+    CK(launch_fill_int(ctl_done(c), 0, 1, s));
+    CK(st_norm(dim, u, f, L0, c->d_partial, c->d_norm, s));
+    CK(launch_solve_init(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist, c->hist_cap, 1,
+                         s));
+    int* ctl = (int*)c->h_pin;
+    CK(hipMemcpyAsync(ctl, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    int steps = 0;
+    while (!ctl[0] && steps < max_cycles) {
+        CK(st_cycle_top(c, u, f));
+        CK(st_norm(dim, u, f, L0, c->d_partial, c->d_norm, s));
         CK(launch_stop_test(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist, c->hist_cap,
                             tol, max_cycles, 1, s));
         CK(hipMemcpyAsync(ctl, c->d_ctrl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -977,6 +1138,16 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
     c->p = *p;
     if (c->p.omega <= 0.0) c->p.omega = p->smoother == MG_SMOOTH_WJACOBI ? 0.8 : 1.0;
     c->stream = (hipStream_t)stream;
+    if (p->op == MG_OP_CONST_STENCIL) {
+        (void)hipGetDevice(&c->device);
+        const int r = st_setup(c);
+        if (r != MG_OK) {
+            destroy(c);
+            return r;
+        }
+        *out = c;
+        return MG_OK;
+    }
     if (p->bc == MG_BC_NEUMANN_CC) {
         (void)hipGetDevice(&c->device);
         const int r = cc_setup(c);
@@ -1117,6 +1288,7 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
                    int* order, int* pairs) {
     if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 4)
         return MG_EINVAL;
+    if (c->cc || c->st || c->cd) return MG_ENOTSUP;  // plain kernels, no tiles
     const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
     const Tiles& tv = tl[(size_t)level];
     const TileCfg t = family == 0   ? tv.smooth
@@ -1141,6 +1313,11 @@ int mg_vcycle(mg_ctx* c, double* u, const double* f) {
     if (c->cc) {
         if (!u || !f) return MG_EINVAL;
         CK(cc_cycle_top(c, u, f));
+        return MG_OK;
+    }
+    if (c->st) {
+        if (!u || !f) return MG_EINVAL;
+        CK(st_cycle_top(c, u, f));
         return MG_OK;
     }
     int r = bind(c, u, f);
@@ -1171,6 +1348,15 @@ int mg_residual_norm(mg_ctx* c, const double* u, const double* f, double* out) {
         *out = c->h_pin[0];
         return MG_OK;
     }
+    if (c->st) {
+        if (!u || !f) return MG_EINVAL;
+        CK(st_norm(c->p.dim, u, f, st_const(c->p.dim, c->p.n, c->st_coef, c->p.omega), c->d_partial, c->d_norm,
+                   c->stream));
+        CK(hipMemcpyAsync(c->h_pin, c->d_norm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        CK(hipStreamSynchronize(c->stream));
+        *out = c->h_pin[0];
+        return MG_OK;
+    }
     int r = bind(c, u, f);
     if (r != MG_OK) return r;
     CK(enqueue_norm(c, c->stream));
@@ -1187,6 +1373,10 @@ int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
     if (c->cc) {
         if (!u || !f) return MG_EINVAL;
         return cc_solve(c, u, f, tol, max_cycles, cycles_done, res_hist);
+    }
+    if (c->st) {
+        if (!u || !f) return MG_EINVAL;
+        return st_solve(c, u, f, tol, max_cycles, cycles_done, res_hist);
     }
     int r = bind(c, u, f);
     if (r != MG_OK) return r;
@@ -1656,6 +1846,41 @@ int mg_cdiff_run(mg_ctx* c, double* u, int steps, double tol, int max_cycles, in
         if (cycles) cycles[m] = it;
     }
     return status;
+}
+
+int mg_level_st_smooth(int dim, int n, const double* stencil, int smoother, double omega, const double* u_in,
+                       const double* f, double* u_out, void* stream) {
+    if ((dim != 2 && dim != 3) || !valid_edge(dim, n) || !stencil || !u_in || !f || !u_out) return MG_EINVAL;
+    if (smoother != MG_SMOOTH_RBGS && smoother != MG_SMOOTH_WJACOBI && smoother != MG_SMOOTH_RBGS_SYM)
+        return MG_EINVAL;
+    if (!(stencil[0] > 0.0)) return MG_EINVAL;
+    if (omega <= 0.0) omega = smoother == MG_SMOOTH_WJACOBI ? 0.8 : 1.0;
+    hipStream_t s = (hipStream_t)stream;
+    const STConst L = st_const(dim, n, stencil, omega);
+    if (u_out != u_in)
+        CK(hipMemcpyAsync(u_out, u_in, npts(dim, n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (smoother == MG_SMOOTH_WJACOBI) {
+        if (u_out == u_in) return MG_EINVAL;
+        CK(st_relax(dim, true, u_in, u_out, f, L, 0, s));
+        return MG_OK;
+    }
+    const int first = smoother == MG_SMOOTH_RBGS_SYM ? 1 : 0;
+    CK(st_relax(dim, false, u_out, u_out, f, L, first, s));
+    CK(st_relax(dim, false, u_out, u_out, f, L, 1 - first, s));
+    return MG_OK;
+}
+
+int mg_level_st_residual_restrict(int dim, int n, const double* stencil, const double* u, const double* f,
+                                  double* fc, void* stream) {
+    if ((dim != 2 && dim != 3) || !valid_edge(dim, n) || n < 5 || !stencil || !u || !f || !fc) return MG_EINVAL;
+    CK(st_restrict(dim, u, f, fc, st_const(dim, n, stencil, 1.0), (hipStream_t)stream));
+    return MG_OK;
+}
+
+int mg_level_st_coarsest(int dim, const double* stencil, double* u, const double* f, void* stream) {
+    if ((dim != 2 && dim != 3) || !stencil || !u || !f || !(stencil[0] > 0.0)) return MG_EINVAL;
+    CK(st_coarsest(dim, u, f, st_const(dim, 3, stencil, 1.0), (hipStream_t)stream));
+    return MG_OK;
 }
 
 int mg_level_cc_smooth(int dim, int n, int smoother, double omega, const double* u_in, const double* f,

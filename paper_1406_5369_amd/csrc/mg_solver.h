@@ -159,6 +159,14 @@ struct mg_ctx {
     // complex diffusion (mg_cdiff_setup): its level hierarchy
     struct CDState* cd = nullptr;
 
+    // constant stencil (op MG_OP_CONST_STENCIL): the stencil and levels n, ...,
+    // 3 with their iterate (level 0: the caller's), Jacobi partner and
+    // right-hand side (level 0: the caller's)
+    bool st = false;
+    double st_coef[7] = {0, 0, 0, 0, 0, 0, 0};
+    std::vector<int> stn;
+    std::vector<double*> stu, stt, stf;
+
     // measurement
     // measurement hooks: event pairs of the current solve, tagged with their
     // refinement step and kernel (0 finest plain sweeps, 1 finest refinement /

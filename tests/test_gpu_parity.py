@@ -339,9 +339,12 @@ def test_setup_rejects_bad_arguments(dev_ok):
         with pytest.raises(m.MGError) as ei:
             m.mg_setup(m.Params(**kw))
         assert ei.value.code == m.MG_EINVAL
-    with pytest.raises(m.MGError) as ei:
-        m.mg_setup(m.Params(dim=2, n=9, bc=1))
+    with pytest.raises(m.MGError) as ei:  # no such boundary condition
+        m.mg_setup(m.Params(dim=2, n=9, bc=7))
     assert ei.value.code == m.MG_ENOTSUP
+    with pytest.raises(m.MGError) as ei:  # a cell-centred grid has 2^L cells per axis
+        m.mg_setup(m.Params(dim=2, n=9, bc=m.BC_NEUMANN_CC))
+    assert ei.value.code == m.MG_EINVAL
 
 
 def test_nan_rhs_reports_divergence(dev_ok):
