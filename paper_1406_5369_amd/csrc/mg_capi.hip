@@ -138,10 +138,29 @@ void free_levels(Levels& L) {
         ffree(L.t[l]);
         if (l > 0 || L.own_k0) ffree(L.k[l]);
     }
+    for (void* p : L.fx) ffree(p);
     L.u.clear();
     L.t.clear();
     L.f.clear();
     L.k.clear();
+    L.fx.clear();
+}
+
+// Face coefficients of every 3D variable-coefficient level with inner nodes
+// to sweep (n >= 5), from the level's k in its arithmetic type.
+hipError_t build_faces(Levels& L, hipStream_t s) {
+    L.fx.assign((size_t)L.nlev, nullptr);
+    if (L.dim != 3 || L.k.empty() || !L.k[0]) return hipSuccess;
+    for (int l = 0; l < L.nlev; ++l) {
+        const int n = L.n[(size_t)l];
+        if (n < 5) continue;
+        hipError_t e = hipMalloc(&L.fx[(size_t)l], 3 * npts(3, n) * (size_t)L.elem);
+        if (e != hipSuccess) return e;
+        e = L.elem == 8 ? launch_faces3d<double>((const double*)L.k[(size_t)l], (double*)L.fx[(size_t)l], n, s)
+                        : launch_faces3d<float>((const float*)L.k[(size_t)l], (float*)L.fx[(size_t)l], n, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // One descriptor per level for a single-instance hierarchy.
@@ -156,6 +175,7 @@ hipError_t build_groups(std::vector<Group>& G, const Levels& L, const Problem& P
         d.t = L.t[(size_t)l];
         d.f = L.f[(size_t)l];
         d.k = L.k[(size_t)l];
+        d.fx = (size_t)l < L.fx.size() ? L.fx[(size_t)l] : nullptr;
         d.uc = l + 1 < L.nlev ? L.u[(size_t)l + 1] : nullptr;
         d.fc = l + 1 < L.nlev ? L.f[(size_t)l + 1] : nullptr;
         d.done = done;
@@ -934,6 +954,7 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
         h.t = L.t[(size_t)l];
         h.f = L.f[(size_t)l] ? L.f[(size_t)l] : scratch_f;
         h.k = L.k[(size_t)l];
+        h.fx = (size_t)l < L.fx.size() ? L.fx[(size_t)l] : nullptr;
         h.fc = L.f[(size_t)l + 1];
         h.uc = L.u[(size_t)l + 1];
         h.n = n;
@@ -1203,6 +1224,7 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
     SETUP_CK(launch_fill_int(c->d_ctrl, 0, 3, s));
     if (p->precision == MG_PREC_FP64) {
         SETUP_CK(build_levels(c->L64, dim, c->n, 8, false, c->k64, s));
+        SETUP_CK(build_faces(c->L64, s));
         SETUP_CK(build_groups(c->G64, c->L64, c->prob, ctl_done(c), s));
         SETUP_CK(build_tail(c->tail64, c->G64, tail_first_level(dim, 8, c->n, false), s));
     } else {
@@ -1220,6 +1242,7 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
             }
             c->L32.own_k0 = true;
         }
+        SETUP_CK(build_faces(c->L32, s));
         SETUP_CK(build_groups(c->G32, c->L32, c->prob, ctl_done(c), s));
         SETUP_CK(build_tail(c->tail32, c->G32, tail_first_level(dim, ir_elem(c->p), c->n, true), s));
         SETUP_CK(zalloc((void**)&c->u64_scratch, N * sizeof(double), s));
@@ -1550,14 +1573,32 @@ int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const
     h.c = level_c(n);
     h.wd = level_wd(dim, n, omega);
     h.omega = omega;
+    void* fxt = nullptr;  // face coefficients of a 3D variable-coefficient grid (freed after the sweep)
+    if (k && dim == 3) {
+        CK(hipMalloc(&fxt, 3 * npts(3, n) * (size_t)elem));
+        const hipError_t ef = elem == 8 ? launch_faces3d<double>((const double*)k, (double*)fxt, n, s)
+                                        : launch_faces3d<float>((const float*)k, (float*)fxt, n, s);
+        if (ef != hipSuccess) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(fxt);
+            return dev_status(ef);
+        }
+        h.fx = fxt;
+    }
     GridDesc* d = nullptr;
     int r = with_desc(h, s, &d);
-    if (r != MG_OK) return r;
+    if (r != MG_OK) {
+        (void)hipStreamSynchronize(s);
+        if (fxt) (void)hipFree(fxt);
+        return r;
+    }
     const int flags = (zero_guess ? SWEEP_ZERO_GUESS : 0) | (ec ? SWEEP_PROLONG : 0);
     hipError_t e = elem == 8   ? launch_smooth<double>(dim, smoother, k != nullptr, d, 1, n, sel, flags, cfg, s)
                    : elem == 4 ? launch_smooth<float>(dim, smoother, k != nullptr, d, 1, n, sel, flags, cfg, s)
                                : launch_smooth<half_t>(dim, smoother, false, d, 1, n, sel, flags, cfg, s);
-    return finish_desc(d, s, e);
+    r = finish_desc(d, s, e);  // synchronises the stream
+    if (fxt) (void)hipFree(fxt);
+    return r;
 }
 
 int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const void* u, const void* f, void* fc,

@@ -56,6 +56,9 @@ struct GridDesc {
     void* t;          // ping-pong partner of u (same shape)
     const void* f;    // right-hand side
     const void* k;    // nodal diffusion coefficient, or null for the Laplacian
+    const void* fx;   // 3D with k: face coefficients in the arithmetic type, three arrays of n^3
+                      // values (+x, +y, +z face of every node; 1 where the face leaves the grid),
+                      // read by the LDS sweeps; null otherwise
     void* uc;         // next coarser level's u (prolongation source), or null
     void* fc;         // next coarser level's f (restriction target), or null
     const int* done;  // per-instance stop flag (non-zero: skip), or null
@@ -195,6 +198,10 @@ hipError_t launch_set_rows(int* arr, int v, const int* rows, int nrows, hipStrea
 hipError_t launch_solve_init_rows(const double* norm, double* norm0, int* done, int* steps, int* status, int* par,
                                   const int* rows, int nrows, hipStream_t s);
 
+// Face coefficients of a 3D level (GridDesc::fx) from its nodal k:
+// fx[p] = kface(k_p, k_{p+x}), fx[N+p] = kface(k_p, k_{p+y}), fx[2N+p] = kface(k_p, k_{p+z}).
+template <typename T>
+hipError_t launch_faces3d(const T* k, T* fx, int n, hipStream_t s);
 // Coarse coefficient by injection: dst(I) = (TD) src(2I) over every coarse node,
 // nf = 2*nc - 1 nodes per axis on the fine side.
 template <typename TS, typename TD>

@@ -1020,6 +1020,23 @@ __global__ __launch_bounds__(NT) void k_inject(const TS* __restrict__ src, int n
     }
 }
 
+// Face coefficients of a 3D level: +x, +y, +z face of every node by the
+// harmonic mean of its two nodes (1 where the face leaves the grid).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_faces3d(const T* __restrict__ k, T* __restrict__ fx, int n) {
+    const size_t N = (size_t)n * n * n, sz = (size_t)n * n;
+    for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < N; p += (size_t)gridDim.x * NT) {
+        const int i = (int)(p % n);
+        const size_t r = p / n;
+        const int j = (int)(r % n);
+        const int kz = (int)(r / n);
+        const T kp = k[p];
+        fx[p] = i < n - 1 ? kface(kp, k[p + 1]) : T(1);
+        fx[N + p] = j < n - 1 ? kface(kp, k[p + n]) : T(1);
+        fx[2 * N + p] = kz < n - 1 ? kface(kp, k[p + sz]) : T(1);
+    }
+}
+
 template <typename TS, typename TD>
 __global__ __launch_bounds__(NT) void k_convert(const TS* __restrict__ src, TD* __restrict__ dst, size_t total) {
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) dst[q] = (TD)src[q];
@@ -1272,6 +1289,16 @@ hipError_t launch_inject(int dim, int nf, const TS* src, int nc, TD* dst, hipStr
 template hipError_t launch_inject<double, double>(int, int, const double*, int, double*, hipStream_t);
 template hipError_t launch_inject<double, float>(int, int, const double*, int, float*, hipStream_t);
 template hipError_t launch_inject<float, float>(int, int, const float*, int, float*, hipStream_t);
+
+template <typename T>
+hipError_t launch_faces3d(const T* k, T* fx, int n, hipStream_t s) {
+    const size_t total = (size_t)n * n * n;
+    const int blocks = (int)std::min<size_t>((total + NT - 1) / NT, 8192);
+    k_faces3d<T><<<blocks, NT, 0, s>>>(k, fx, n);
+    return hipGetLastError();
+}
+template hipError_t launch_faces3d<double>(const double*, double*, int, hipStream_t);
+template hipError_t launch_faces3d<float>(const float*, float*, int, hipStream_t);
 
 template <typename TS, typename TD>
 hipError_t launch_convert(size_t total, const TS* src, TD* dst, hipStream_t s) {

@@ -22,10 +22,12 @@ namespace {
 // z-neighbours come from its own registers, x-neighbours from the adjacent
 // lanes (DPP), y-neighbours from LDS.  Register rings are indexed by
 // (plane - first plane) mod 3, resolved at compile time by unrolling three
-// steps.  With variable coefficients the face coefficients of a plane (+x,
-// -y, +y of every node, and +z of the plane below) are formed once as the
-// plane enters and kept in rings of their own, so each is one division per
-// node and sweep rather than one per evaluation.
+// steps.  With variable coefficients the level's face coefficients (the +x,
+// +y and +z face of every node, formed once per level at setup by the same
+// harmonic mean) are prefetched with u and kept in rings of their own: +x
+// and +y as the plane enters (the -x face from the neighbouring lane, the -y
+// face through LDS from the row below), +z one step later (the -z face is
+// the +z face of the plane below), so a sweep divides nothing.
 //
 // With SWEEP_PROLONG the incoming iterate is u + P uc (trilinear correction
 // from the coarse grid, inner nodes only), formed as each plane enters.  A
@@ -47,23 +49,25 @@ struct Smooth3D {
 
     T (*U)[BY][BX];   // old u of recent planes (y-neighbour exchange)
     T (*R)[BY][BX];   // red-updated u of recent planes
-    T (*K)[BY][BX];   // coefficient of recent planes
+    T (*K)[BY][BX];   // +y face coefficients of recent planes (-y faces of the rows above)
     const MG_GLOBAL ST* __restrict__ uin;
     MG_GLOBAL ST* __restrict__ uout;
     const MG_GLOBAL ST* __restrict__ f;
-    const MG_GLOBAL T* __restrict__ kf;
+    const MG_GLOBAL T* __restrict__ fxa;  // face coefficients: +x at fxa, +y at fxa + n^3, +z at fxa + 2 n^3
     int n, x0, y0, z0, z1, kstart, kend;
     T c, wd, om;
     int lane, w, gx;
     int cfirst;  // colour relaxed in the first half-sweep (0 red, 1 black)
     bool colg, coli, lane1;
-    T un[3][RPT], kn[3][RPT];  // prefetched raw u (and k) of planes up to kk+PD
+    T un[3][RPT];              // prefetched raw u of planes up to kk+PD
+    // prefetched +x, +y, +z face coefficients (VAR) of planes up to kk+PD
+    T px[VAR ? 3 : 1][RPT], py[VAR ? 3 : 1][RPT], pz[VAR ? 3 : 1][RPT];
     T uo[3][RPT];              // old u of planes kk, kk-1, kk-2 (own positions)
-    T ko[3][RPT];              // k of planes kk, kk-1, kk-2
     T ro[3][RPT];              // red-updated u of planes kk-1, kk-2, kk-3
     T fr[3][RPT];              // f of planes kk, kk-1, kk-2
     // face coefficients (VAR) of planes kk, kk-1, kk-2: +x, -y, +y faces of
-    // the node, and the +z face (to the plane above)
+    // the node, and the +z face (to the plane above; set one step after the
+    // plane enters, when the +z face of the plane three below is no longer read)
     T fxc[VAR ? 3 : 1][RPT], fys[VAR ? 3 : 1][RPT], fyn[VAR ? 3 : 1][RPT], fzc[VAR ? 3 : 1][RPT];
 
     __device__ __forceinline__ int gy(int m) const { return y0 - H + w + WV * m; }
@@ -172,15 +176,25 @@ struct Smooth3D {
     // never used, because every relaxation is taken at an inner node, whose
     // neighbours all lie in the grid.  With no select on loaded values there is
     // no branch around the loads, so the prefetches stay in flight across steps.
-    __device__ __forceinline__ void issue_u(int z, T (&du)[RPT], T (&dk)[RPT]) {
+    template <int SL>
+    __device__ __forceinline__ void issue_u(int z) {
         const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
         const MG_GLOBAL ST* __restrict__ up = uin + zoff;
-        const MG_GLOBAL T* __restrict__ kp = kf + zoff;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            if constexpr (!(flags & SWEEP_ZERO_GUESS)) du[m] = ld_off(up + rowoff(m), xb);
-            else du[m] = T(0);
-            if constexpr (VAR) dk[m] = ld_off(kp + rowoff(m), xb);
+            if constexpr (!(flags & SWEEP_ZERO_GUESS)) un[SL][m] = ld_off(up + rowoff(m), xb);
+            else un[SL][m] = T(0);
+        }
+        if constexpr (VAR) {
+            const size_t N = pl * (size_t)n;
+            const MG_GLOBAL T* __restrict__ xp = fxa + zoff;
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) {
+                const MG_GLOBAL T* __restrict__ row = xp + rowoff(m);
+                px[SL][m] = ld_off(row, xb);
+                py[SL][m] = ld_off(row + N, xb);
+                pz[SL][m] = ld_off(row + 2 * N, xb);
+            }
         }
     }
     // f is read on the rows that are relaxed (not the outermost halo rows).
@@ -212,20 +226,14 @@ struct Smooth3D {
         return relax<T, VAR>(uc, r, ds, c, wd, om);
     }
 
-    // Faces of the plane that entered (slot S0; K holds its coefficients) and
-    // the +z faces of the plane below it (slot S1).
-    template <int S0, int S1>
-    __device__ __forceinline__ void faces() {
+    // -y faces of the plane that entered (slot S0): the +y faces of the rows
+    // below, published in K.
+    template <int S0>
+    __device__ __forceinline__ void faces_below() {
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const int ly = w + WV * m;  // wave-uniform
-            const T kc = ko[S0][m];
-            fxc[S0][m] = kface(kc, lane_next(kc));
-            if (ly >= 1 && ly <= BY - 2) {
-                fys[S0][m] = kface(K[S0][ly - 1][lane], kc);
-                fyn[S0][m] = kface(kc, K[S0][ly + 1][lane]);
-            }
-            fzc[S1][m] = kface(ko[S1][m], kc);
+            if (ly >= 1 && ly <= BY - 2) fys[S0][m] = K[S0][ly - 1][lane];
         }
     }
 
@@ -239,14 +247,17 @@ struct Smooth3D {
             uo[S0][m] = un[S0][m];
             U[S0][w + WV * m][lane] = uo[S0][m];
             if constexpr (VAR) {
-                ko[S0][m] = kn[S0][m];
-                K[S0][w + WV * m][lane] = ko[S0][m];
+                // before this step's prefetch reuses slot S1 (PD = 2)
+                fxc[S0][m] = px[S0][m];
+                fyn[S0][m] = py[S0][m];
+                K[S0][w + WV * m][lane] = py[S0][m];
+                fzc[S1][m] = pz[S1][m];
             }
         }
         issue_f(kk, fr[S0]);
-        issue_u(kk + PD, un[SN], kn[SN]);
+        issue_u<SN>(kk + PD);
         __syncthreads();
-        if constexpr (VAR) faces<S0, S1>();
+        if constexpr (VAR) faces_below<S0>();
         if constexpr (SM == SM_RBGS) {
             const int m1 = kk - 1;  // red plane
             if (m1 >= z0 - 1) {
@@ -312,19 +323,21 @@ struct Smooth3D {
             for (int m = 0; m < RPT; ++m) sylast[m] = coarse_sum(m);
             if (kk & 1) issue_c((kk + 1) >> 1);
         }
-        issue_u(kk, un[0], kn[0]);
-        if constexpr (PD == 2) issue_u(kk + 1, un[1], kn[1]);
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             uo[1][m] = uo[2][m] = T(0);
             ro[0][m] = ro[1][m] = ro[2][m] = T(0);
             fr[0][m] = fr[1][m] = fr[2][m] = T(0);  // halo rows keep these (f is not read there)
-            ko[1][m] = ko[2][m] = T(1);
             if constexpr (VAR) {
 #pragma unroll
-                for (int q = 0; q < 3; ++q) fxc[q][m] = fys[q][m] = fyn[q][m] = fzc[q][m] = T(1);
+                for (int q = 0; q < 3; ++q) {
+                    fxc[q][m] = fys[q][m] = fyn[q][m] = fzc[q][m] = T(1);
+                    px[q][m] = py[q][m] = pz[q][m] = T(1);  // planes before the march: never read
+                }
             }
         }
+        issue_u<0>(kk);
+        if constexpr (PD == 2) issue_u<1>(kk + 1);
         for (; kk + 2 <= kend; kk += 3) {
             step<0>(kk);
             step<1>(kk + 1);
@@ -362,7 +375,7 @@ __global__ __launch_bounds__(64 * WV) void k_smooth3d(const GridDesc* __restrict
     s.uin = gp((const ST*)((sel & 1) ? d.t : d.u));
     s.uout = gp((ST*)((sel & 1) ? d.u : d.t));
     s.f = gp((const ST*)d.f);
-    s.kf = gp((const T*)d.k);
+    s.fxa = gp((const T*)d.fx);
     s.ec = gp((const ST*)d.uc);
     s.nc = (n - 1) / 2 + 1;
     s.c = (T)d.c;

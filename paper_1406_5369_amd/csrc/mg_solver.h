@@ -40,6 +40,7 @@ struct Levels {
     int dim = 0, nlev = 0, elem = 8;
     std::vector<int> n;           // n[0] finest
     std::vector<void*> u, t, f, k;  // per level; k empty when Laplacian
+    std::vector<void*> fx;          // 3D with k: face coefficients of levels the sweeps run on (GridDesc::fx)
     std::vector<char> own_u, own_f; // level owns u / f
     bool own_k0 = false;            // level-0 coefficient allocated by the hierarchy
 };
