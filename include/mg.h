@@ -160,7 +160,9 @@ int mg_num_levels(const mg_ctx* ctx);
 /* Launch geometry the context uses on 'level' (0 = finest) for kernel 'family'
  * (0 smoothing, 1 residual + restriction, 2 finest-level norm / refinement
  * pass, 3 smoothing from a zero iterate, 4 smoothing with the coarse-grid
- * correction fused in): tile rows *by, z-chunk *zchunk (3D planes per workgroup), for 3D
+ * correction fused in, 5 the last pre-smoothing sweep fused with the residual
+ * and restriction: *zchunk coarse planes per workgroup, 0 when the level runs
+ * the sweep and the restriction apart): tile rows *by, z-chunk *zchunk (3D planes per workgroup), for 3D
  * marching kernels *prefetch = planes of u loaded ahead (1 or 2), *waves =
  * wavefronts per workgroup (4; 1 or 8 for 3D smoothing and the 3D pass), for
  * smoothing *order = block-to-tile order (0: each XCD takes a contiguous band
@@ -216,6 +218,17 @@ int mg_level_prolong_correct(int dim, int n, int dtype, void* u, const void* ec,
 /* Coarsest grid (n = 3): u = f / diag at the single inner node. */
 int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f, void* stream);
 
+/* The last pre-smoothing sweep fused with the residual and full weighting
+ * (Algorithm 1: presmoothing, residual, restriction), 3D Laplacian, dtype 1
+ * (FP32) or 2 (binary16), omega 1: one red-first red-black sweep u_in -> u_out
+ * (inner nodes; u_out != u_in) and fc (inner coarse nodes, edge (n-1)/2+1) =
+ * full weighting of f - A u_out, bit for bit the sweep of mg_level_smooth
+ * followed by mg_level_residual_restrict.  zchunk: coarse planes per
+ * workgroup (>= 1); order: 0 XCD bands, 1 linear block order.  The solver
+ * uses it in V-cycles where the autotuner times it faster than the two
+ * kernels it replaces.  Synchronises the stream. */
+int mg_level_smooth_restrict(int dim, int n, int dtype, const void* u_in, const void* f, void* u_out, void* fc,
+                             int zchunk, int order, void* stream);
 /* Conjugate gradients on a coarsest grid of n = 2^c + 1 nodes per axis
  * (mg_params.coarse_n): 'iters' steps (0: 4 (n - 1)) from u = 0 on A u = f;
  * u's boundary is written with zeros.  n at most 33 (2D) / 9 (3D) for dtype 0,

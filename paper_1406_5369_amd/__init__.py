@@ -111,6 +111,7 @@ def lib():
             "mg_level_residual_restrict": (i, [i, i, i, p, p, p, p, i, i, p]),
             "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
+            "mg_level_smooth_restrict": (i, [i, i, i, p, p, p, p, i, i, p]),
             "mg_level_coarsest_cg": (i, [i, i, i, p, p, p, i, p]),
             "mg_cdiff_setup": (i, [C.POINTER(_CDiffParams), p, C.POINTER(p)]),
             "mg_cdiff_fas": (i, [p, p, p]),
@@ -364,6 +365,17 @@ def mg_level_residual_restrict(u, f, fc, k=None, by=0, zchunk=0, stream=None) ->
                                             _dptr(u, dt, f.shape, "u"), _dptr(f, dt, None, "f"),
                                             _dptr(fc, dt, (nc,) * dim, "fc"), by, zchunk, _stream(stream)),
            "mg_level_residual_restrict")
+
+
+def mg_level_smooth_restrict(u_in, f, u_out, fc, zchunk=4, order=0, stream=None) -> None:
+    """Fused last pre-smoothing sweep + residual + full weighting (3D, float32 or float16)."""
+    dim, n = f.dim(), f.shape[0]
+    dt = f.dtype
+    nc = (n - 1) // 2 + 1
+    _check(lib().mg_level_smooth_restrict(dim, n, _dtype_code(f), _dptr(u_in, dt, f.shape, "u_in"),
+                                          _dptr(f, dt, f.shape, "f"), _dptr(u_out, dt, f.shape, "u_out"),
+                                          _dptr(fc, dt, (nc,) * dim, "fc"), int(zchunk), int(order),
+                                          _stream(stream)), "mg_level_smooth_restrict")
 
 
 def mg_level_prolong_correct(u, ec, stream=None) -> None:

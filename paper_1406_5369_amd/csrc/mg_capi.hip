@@ -916,6 +916,32 @@ TileCfg pick_fastest(const std::vector<TileCfg>& cands, TileCfg fallback, Launch
     return best;
 }
 
+// Time of one configuration as pick_fastest measures it (best of three
+// rounds of three launches, in ms), or a huge value if it fails.
+template <class Launch>
+float time_launch(Launch&& launch, TileCfg cfg, hipStream_t s) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return 1e30f;
+    float best = 1e30f;
+    for (int round = 0; round < 3; ++round) {
+        if (launch(cfg) != hipSuccess) {
+            (void)hipGetLastError();
+            best = 1e30f;
+            break;
+        }
+        (void)hipEventRecord(a, s);
+        for (int r = 0; r < 3; ++r) (void)launch(cfg);
+        (void)hipEventRecord(b, s);
+        if (hipEventSynchronize(b) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return best;
+}
+
 // Block order of a chosen smoothing geometry: XCD bands or linear, whichever
 // times faster.
 template <class Launch>
@@ -998,6 +1024,41 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
             tune_store(kr, cfg);
         }
         tl[(size_t)l].restr = cfg;
+        // the last pre-smoothing sweep fused with the residual and restriction,
+        // kept if it beats the plain sweep and the restriction it replaces
+        if (dim == 3 && !var && sm == SM_RBGS && L.elem <= 4 && c->p.nu1 >= 1) {
+            TuneKey kf{dim, L.elem, n, 5, sm, 0, 0, 0};
+            if (!tune_lookup(kf, &cfg)) {
+                std::vector<TileCfg> cands;
+                for (int zc : {2, 4, 8, 16})
+                    for (int order : {0, 1}) {
+                        TileCfg t{16, zc};
+                        t.order = order;
+                        cands.push_back(t);
+                    }
+                auto runf = [&](TileCfg t) {
+                    return L.elem == 4 ? launch_smooth_restrict3d<float>(d, 1, n, 0, t, s)
+                                       : launch_smooth_restrict3d<half_t>(d, 1, n, 0, t, s);
+                };
+                TileCfg best = pick_fastest(cands, cands[0], runf, s);
+                const float t_fused = time_launch(runf, best, s);
+                const TileCfg sw = tl[(size_t)l].smooth, rs = tl[(size_t)l].restr;
+                const float t_sep =
+                    time_launch([&](TileCfg) {
+                        if (L.elem == 4) {
+                            (void)launch_smooth<float>(dim, sm, false, d, 1, n, 0, 0, sw, s);
+                            return launch_restrict<float>(dim, false, d, 1, n, 1, rs, s);
+                        }
+                        (void)launch_smooth<half_t>(dim, sm, false, d, 1, n, 0, 0, sw, s);
+                        return launch_restrict<half_t>(dim, false, d, 1, n, 1, rs, s);
+                    }, sw, s);
+                cfg = best;
+                if (!(t_fused < t_sep)) cfg.zchunk = -best.zchunk;  // declined (depth kept for forcing)
+                tune_store(kf, cfg);
+            }
+            tl[(size_t)l].fused = cfg;
+            if (cfg.zchunk < 0) tl[(size_t)l].fused.zchunk = std::getenv("MG_FUSED_RESTRICT") ? -cfg.zchunk : 0;
+        }
     }
     hipError_t e2 = hipStreamSynchronize(s);
     (void)hipFree(d);
@@ -1309,7 +1370,7 @@ int mg_num_levels(const mg_ctx* c) {
 
 int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch, int* waves,
                    int* order, int* pairs) {
-    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 4)
+    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 5)
         return MG_EINVAL;
     if (c->cc || c->st || c->cd) return MG_ENOTSUP;  // plain kernels, no tiles
     const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
@@ -1318,7 +1379,8 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
                       : family == 1 ? tv.restr
                       : family == 2 ? c->top.norm
                       : family == 3 ? tv.smooth_zg
-                                    : tv.smooth_pro;
+                      : family == 4 ? tv.smooth_pro
+                                    : tv.fused;
     if (family == 2 && level != 0) return MG_EINVAL;
     *by = t.by;
     *zchunk = t.zchunk;
@@ -1599,6 +1661,31 @@ int mg_level_smooth(int dim, int n, int dtype, int smoother, double omega, const
     r = finish_desc(d, s, e);  // synchronises the stream
     if (fxt) (void)hipFree(fxt);
     return r;
+}
+
+int mg_level_smooth_restrict(int dim, int n, int dtype, const void* u_in, const void* f, void* u_out, void* fc,
+                             int zchunk, int order, void* stream) {
+    const int elem = dtype_elem(dtype);
+    if (dim != 3 || !valid_edge(dim, n) || n < 5 || (elem != 4 && elem != 2)) return MG_EINVAL;
+    if (!u_in || !f || !u_out || !fc || u_in == u_out || zchunk < 1 || (order != 0 && order != 1)) return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    GridDesc h{};
+    h.u = const_cast<void*>(u_in);
+    h.t = u_out;
+    h.f = f;
+    h.fc = fc;
+    h.n = n;
+    h.c = level_c(n);
+    h.wd = level_wd(dim, n, 1.0);
+    h.omega = 1.0;
+    GridDesc* d = nullptr;
+    int r = with_desc(h, s, &d);
+    if (r != MG_OK) return r;
+    TileCfg cfg{16, zchunk};
+    cfg.order = order;
+    const hipError_t e = elem == 4 ? launch_smooth_restrict3d<float>(d, 1, n, 0, cfg, s)
+                                   : launch_smooth_restrict3d<half_t>(d, 1, n, 0, cfg, s);
+    return finish_desc(d, s, e);
 }
 
 int mg_level_residual_restrict(int dim, int n, int dtype, const void* k, const void* u, const void* f, void* fc,

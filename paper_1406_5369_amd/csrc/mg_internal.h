@@ -119,6 +119,7 @@ inline int sweep_arg(int sel, const TileCfg& c) { return (sel & (1 | SEL_BLACK_F
 // Number of workgroups in x for a level of n nodes per axis (one instance).
 int smooth_tiles(int dim, int sm, int n, TileCfg cfg);
 int restrict_tiles(int dim, int nf, TileCfg cfg);
+int smooth_restrict_tiles(int nf, TileCfg cfg);
 int norm_tiles(int dim, int n, TileCfg cfg);
 
 // Kernel launchers.  'ninst' grids with equal n are processed by one launch
@@ -133,6 +134,12 @@ hipError_t launch_smooth2d(int sm, bool var, const GridDesc* d, int sel, int fla
 template <typename T>
 hipError_t launch_smooth3d(int sm, bool var, const GridDesc* d, int sel, int flags, TileCfg cfg, dim3 grid,
                            hipStream_t s);
+// 3D Laplacian, FP32 or binary16 storage: the last red-first RBGS pre-smoothing
+// sweep of input 'sel' fused with the residual of its result and full
+// weighting into fc (cfg.by 16 rows, cfg.zchunk coarse planes per workgroup,
+// cfg.order the block order).
+template <typename T>
+hipError_t launch_smooth_restrict3d(const GridDesc* d, int ninst, int nf, int sel, TileCfg cfg, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(int dim, bool var, const GridDesc* d, int ninst, int nf, int sel, TileCfg cfg,
                            hipStream_t s);

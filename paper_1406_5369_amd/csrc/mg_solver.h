@@ -20,6 +20,10 @@ struct Tiles {
     TileCfg smooth_pro{16, 128};  // sweep with the coarse-grid correction fused in (first postsmoothing sweep)
     TileCfg restr{16, 64};
     TileCfg norm{16, 128};
+    // last pre-smoothing sweep fused with the residual and restriction (3D
+    // Laplacian RBGS, FP32 / binary16): zchunk coarse planes per workgroup,
+    // 0 = separate sweep and restriction (the autotuner's choice)
+    TileCfg fused{16, 0};
     const TileCfg& sweep(int flags) const {
         return (flags & SWEEP_ZERO_GUESS) ? smooth_zg : ((flags & SWEEP_PROLONG) ? smooth_pro : smooth);
     }

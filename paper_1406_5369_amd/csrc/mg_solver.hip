@@ -115,6 +115,14 @@ hipError_t coarse_solve(const Problem& P, const Group& g, hipStream_t s) {
     return launch_cg<T>(P.dim, P.var, g.d, g.ninst, g.n, P.cg_iters > 0 ? P.cg_iters : 4 * (g.n - 1), s);
 }
 
+// The fused last pre-smoothing sweep + restriction applies to 3D Laplacian
+// red-black levels in FP32 or binary16 storage whose tiles chose it.
+template <typename T>
+bool fused_restrict_ok(const Problem& P, int dim, const Tiles& t) {
+    return sizeof(T) <= 4 && dim == 3 && !P.var && P.smoother == SM_RBGS && t.fused.zchunk > 0 &&
+           std::getenv("MG_NO_FUSED_RESTRICT") == nullptr;
+}
+
 // Post-smoothing select bits: the symmetric red-black smoother relaxes black first.
 inline int post_sel(const Problem& P, int cur) { return cur | (P.sym ? SEL_BLACK_FIRST : 0); }
 
@@ -181,9 +189,16 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
     for (int l = 0; l < stop; ++l) {
         const Group& g = G[(size_t)l];
         const bool zero = l == 0 ? zero_top : true;
+        // the last sweep may carry the residual and restriction (a plain red-first sweep)
+        const bool fuse = fused_restrict_ok<T>(P, dim, tiles[(size_t)l]) && P.nu1 >= (zero ? 2 : 1);
         int cur = 0;
         for (int i = 0; i < P.nu1; ++i) {
             const int flags = (i == 0 && zero) ? SWEEP_ZERO_GUESS : 0;
+            if (fuse && i == P.nu1 - 1) {
+                MG_TRY(launch_smooth_restrict3d<T>(g.d, g.ninst, g.n, cur, tiles[(size_t)l].fused, s));
+                cur ^= 1;
+                continue;
+            }
             const bool timed = l == 0 && flags == 0;  // plain finest-level sweeps only
             if (timed) prof.begin();
             MG_TRY(launch_smooth<T>(dim, P.smoother, P.var, g.d, g.ninst, g.n, cur, flags,
@@ -192,7 +207,7 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
             cur ^= 1;
         }
         if (P.nu1 == 0 && zero) MG_TRY(launch_zero_u<T>(dim, g.d, g.ninst, g.n, s));
-        MG_TRY(launch_restrict<T>(dim, P.var, g.d, g.ninst, g.n, cur, tiles[(size_t)l].restr, s));
+        if (!fuse) MG_TRY(launch_restrict<T>(dim, P.var, g.d, g.ninst, g.n, cur, tiles[(size_t)l].restr, s));
         sel[(size_t)l] = cur;
     }
     if (use_tail) {

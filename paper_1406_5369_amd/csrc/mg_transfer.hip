@@ -190,6 +190,137 @@ __global__ __launch_bounds__(NT) void k_restrict3d(const GridDesc* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Last pre-smoothing sweep fused with the residual and full weighting
+// (Algorithm 1: presmoothing, residual, restriction), 3D Laplacian, red-black
+// Gauss-Seidel with red first.  A workgroup owns CX x CY coarse nodes of a
+// chunk of zc coarse planes and the fine nodes of their cells (fine x in
+// [2X0-1, 2X0+2CX-1), likewise y and z).  On a fine box of (2CX+7) x (2CY+7)
+// nodes it relaxes red on the box minus one ring, black on the box minus two
+// rings (the final values; the owned ones are written out), forms the
+// residual of the final values on the box minus three rings and full
+// weighting at its coarse nodes.  The march along z lags: plane kk enters,
+// red on kk-1, black on kk-2, residual on kk-3, coarse plane (kk-4)/2.  The
+// colour updates are in place in an LDS ring of five planes (a colour reads
+// only the other colour), with rings of three residual planes and four
+// right-hand-side planes.  Every value is the one the separate sweep and
+// restriction compute, by the same expressions.
+// ---------------------------------------------------------------------------
+template <typename ST, int BY>
+__global__ __launch_bounds__(NT) void k_smooth_restrict3d(const GridDesc* __restrict__ descs, int arg, int zc) {
+    using T = arith_t<ST>;
+    constexpr int CX = 28, CY = (BY - 7) / 2, RPT = BY / 4;
+    static_assert(2 * CX + 7 <= BX && 2 * CY + 7 <= BY && RPT * 4 == BY, "box fits the tile");
+    const GridDesc d = descs[blockIdx.y];
+    if (d.done && *gp(d.done)) return;
+    const int nf = d.n, nc = (nf - 1) / 2 + 1;
+    const int ncx = (nc - 1 + CX - 1) / CX, ncy = (nc - 1 + CY - 1) / CY;
+    const int tile = sweep_tile(arg, blockIdx.x, gridDim.x);
+    const int tx = tile % ncx, t2 = tile / ncx, ty = t2 % ncy, tz = t2 / ncy;
+    const int X0 = 1 + tx * CX, Y0 = 1 + ty * CY, Z0 = 1 + tz * zc, Z1 = min(Z0 + zc, nc);
+    const int fx0 = 2 * X0 - 4, fy0 = 2 * Y0 - 4;  // fine position of lane 0, row 0
+    const int za = 2 * Z0 - 1, zb = 2 * Z1 - 1;     // owned fine planes [za, zb); residual on [za, zb]
+    const int kstart = za - 3, kend = zb + 3;
+    const MG_GLOBAL ST* __restrict__ uin = gp((const ST*)((arg & 1) ? d.t : d.u));
+    MG_GLOBAL ST* __restrict__ uout = gp((ST*)((arg & 1) ? d.u : d.t));
+    const MG_GLOBAL ST* __restrict__ f = gp((const ST*)d.f);
+    MG_GLOBAL ST* __restrict__ fc = gp((ST*)d.fc);
+    const T c = (T)d.c, wd = (T)d.wd, om = (T)d.omega;
+    __shared__ T U[5][BY][BX];    // planes kk (entered), kk-1 (red done), kk-2 .. kk-4 (final)
+    __shared__ T F[4][BY][BX];    // right-hand side of planes kk .. kk-3
+    __shared__ T RS[3][BY][BX];   // residual of planes kk-3 .. kk-5
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gx = fx0 + lane;
+    const bool xin = gx >= 1 && gx <= nf - 2;
+    const unsigned xb = (unsigned)min(max(gx, 0), nf - 1) * (unsigned)sizeof(ST);
+    const size_t pl = (size_t)nf * nf;
+    T un[RPT], fn[RPT];
+    auto issue = [&](int z) {
+        const size_t zoff = (size_t)min(max(z, 0), nf - 1) * pl;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int gy = fy0 + w + 4 * m;
+            const size_t roff = zoff + (size_t)min(max(gy, 0), nf - 1) * nf;
+            un[m] = (T)ld_off(uin + roff, xb);
+            fn[m] = (T)ld_off(f + roff, xb);
+        }
+    };
+    auto inner = [&](int gy, int z) { return xin && gy >= 1 && gy <= nf - 2 && z >= 1 && z <= nf - 2; };
+    // residual at (ly, lane) of plane slot sc with the planes below / above
+    auto res_at = [&](int sb, int sc, int sa, int sf, int ly) {
+        return res_lap3(U[sc][ly][lane], U[sc][ly][lane - 1], U[sc][ly][lane + 1], U[sc][ly - 1][lane],
+                        U[sc][ly + 1][lane], U[sb][ly][lane], U[sa][ly][lane], F[sf][ly][lane], c);
+    };
+    issue(kstart);
+    for (int kk = kstart; kk <= kend; ++kk) {
+        const int q = kk - kstart;
+        const int u0 = q % 5, u1 = (q + 4) % 5, u2 = (q + 3) % 5, u3 = (q + 2) % 5, u4 = (q + 1) % 5;
+        const int f0 = q % 4, f1 = (q + 3) % 4, f2 = (q + 2) % 4, f3 = (q + 1) % 4;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            U[u0][w + 4 * m][lane] = un[m];
+            F[f0][w + 4 * m][lane] = fn[m];
+        }
+        if (kk < kend) issue(kk + 1);
+        __syncthreads();
+        // red on plane kk-1 (box minus one ring)
+        const int zr = kk - 1;
+        if (zr >= kstart + 1) {
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) {
+                const int ly = w + 4 * m, gy = fy0 + ly;
+                if (lane >= 1 && lane <= 2 * CX + 5 && ly >= 1 && ly <= 2 * CY + 5 && inner(gy, zr) &&
+                    ((gx + gy + zr) & 1) == 0) {
+                    const T r = res_at(u2, u1, u0, f1, ly);
+                    U[u1][ly][lane] = stored<ST>(relax<T, false>(U[u1][ly][lane], r, T(0), c, wd, om));
+                }
+            }
+        }
+        __syncthreads();
+        // black on plane kk-2 (box minus two rings); write the owned final values
+        const int zk = kk - 2;
+        if (zk >= kstart + 2) {
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) {
+                const int ly = w + 4 * m, gy = fy0 + ly;
+                const bool in = inner(gy, zk);
+                if (lane >= 2 && lane <= 2 * CX + 4 && ly >= 2 && ly <= 2 * CY + 4 && in &&
+                    ((gx + gy + zk) & 1) == 1) {
+                    const T r = res_at(u3, u2, u1, f2, ly);
+                    U[u2][ly][lane] = stored<ST>(relax<T, false>(U[u2][ly][lane], r, T(0), c, wd, om));
+                }
+                if (in && lane >= 3 && lane < 2 * CX + 3 && ly >= 3 && ly < 2 * CY + 3 && zk >= za && zk < zb)
+                    st_off(uout + (size_t)zk * pl + (size_t)gy * nf, xb, (ST)U[u2][ly][lane]);
+            }
+        }
+        __syncthreads();
+        // residual of the final values on plane kk-3 (box minus three rings)
+        const int zs = kk - 3;
+        const int r0 = q % 3, r1 = (q + 2) % 3, r2 = (q + 1) % 3;  // slots of planes kk-3, kk-4, kk-5
+        if (zs >= za && zs <= zb) {
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) {
+                const int ly = w + 4 * m, gy = fy0 + ly;
+                if (lane >= 3 && lane <= 2 * CX + 3 && ly >= 3 && ly <= 2 * CY + 3)
+                    RS[r0][ly][lane] = inner(gy, zs) ? res_at(u4, u3, u2, f3, ly) : T(0);
+            }
+        }
+        __syncthreads();
+        // full weighting of coarse plane K with 2K + 1 = kk - 3
+        if ((zs & 1) == 1 && zs >= za + 2 && zs <= zb) {
+            const int Kz = (zs - 1) / 2;
+            if (Kz <= nc - 2) {
+                for (int t = threadIdx.x; t < CX * CY; t += NT) {
+                    const int X = X0 + t % CX, Y = Y0 + t / CX;
+                    if (X <= nc - 2 && Y <= nc - 2)
+                        fc[((size_t)Kz * nc + Y) * nc + X] =
+                            (ST)fw3<T>(RS[r2], RS[r1], RS[r0], 2 * (Y - Y0) + 4, 2 * (X - X0) + 4);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Prolongation + correction u += P uc on inner fine nodes (used when no
 // post-smoothing sweep can absorb it), coarsest solve, copies.
 // ---------------------------------------------------------------------------
@@ -304,6 +435,25 @@ int smooth_tiles(int dim, int sm, int n, TileCfg cfg) {
     return cdiv(m, TX) * cdiv(m, TY) * nzchunks(m, cfg.zchunk);
 }
 
+// Tiles of the fused kernel: coarse nodes per workgroup 28 x (BY-7)/2 times zc planes
+int smooth_restrict_tiles(int nf, TileCfg cfg) {
+    const int nc = (nf - 1) / 2 + 1, CX = 28, CY = (cfg.by - 7) / 2;
+    return cdiv(nc - 1, CX) * cdiv(nc - 1, CY) * cdiv(nc - 1, cfg.zchunk);
+}
+
+template <typename T>
+hipError_t launch_smooth_restrict3d(const GridDesc* d, int ninst, int nf, int sel, TileCfg cfg, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        return hipErrorInvalidValue;  // the LDS rings hold FP32 values (FP64 would need 96 KB)
+    } else {
+        if (nf < 5 || ninst <= 0 || cfg.zchunk < 1 || cfg.by != 16) return hipErrorInvalidValue;
+        const dim3 grid(smooth_restrict_tiles(nf, cfg), ninst);
+        const int arg = (sel & 1) | (cfg.order == 1 ? 2 : 0);
+        k_smooth_restrict3d<T, 16><<<grid, NT, 0, s>>>(d, arg, cfg.zchunk);
+        return hipGetLastError();
+    }
+}
+
 int restrict_tiles(int dim, int nf, TileCfg cfg) {
     const int CX = (BX - 3) / 2, CY = (cfg.by - 3) / 2;
     const int mc = (nf - 1) / 2 + 1 - 2;
@@ -407,7 +557,8 @@ hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream
     template hipError_t launch_prolong<T>(int, const GridDesc*, int, int, int, hipStream_t);                    \
     template hipError_t launch_coarsest<T>(int, bool, const GridDesc*, int, hipStream_t);                       \
     template hipError_t launch_copy_t_to_u<T>(int, const GridDesc*, int, int, hipStream_t);                     \
-    template hipError_t launch_zero_u<T>(int, const GridDesc*, int, int, hipStream_t);
+    template hipError_t launch_zero_u<T>(int, const GridDesc*, int, int, hipStream_t);                       \
+    template hipError_t launch_smooth_restrict3d<T>(const GridDesc*, int, int, int, TileCfg, hipStream_t);
 MG_INST(double)
 MG_INST(float)
 MG_INST(half_t)
