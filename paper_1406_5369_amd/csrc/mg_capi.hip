@@ -760,8 +760,15 @@ size_t cd_cells(const CDState& S, int l) {
     return S.dim == 2 ? n * n : n * n * n;
 }
 
+// one sweep (both colours or Jacobi): tiled into the level's other buffer, or
+// per cell (small 3D levels) with g formed first
 hipError_t cd_sweep_level(CDState& S, int l, void*& cur, void*& other, const void* f, hipStream_t s) {
     const CDLevel L = cd_level(S.ln[(size_t)l]);
+    if (cd_tiled(S.dim, L.n)) {
+        const hipError_t e = cd_sweep(S.dim, S.jacobi, cur, other, f, S.K, L, s);
+        std::swap(cur, other);
+        return e;
+    }
     hipError_t e = cd_compute_g(cur, S.g[(size_t)l], cd_cells(S, l), S.K, s);
     if (e != hipSuccess) return e;
     if (S.jacobi) {

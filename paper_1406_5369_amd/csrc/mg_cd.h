@@ -19,8 +19,16 @@ struct CDLevel {
 CDLevel cd_level(int n);
 
 hipError_t cd_compute_g(const void* u, void* g, size_t N, CDConst K, hipStream_t s);
+// RBGS colour 'colour' in place (uin == uout) or a Jacobi sweep uin -> uout,
+// one cell per thread, g of the pre-sweep iterate in its array
 hipError_t cd_relax(int dim, bool jacobi, const void* uin, void* uout, const void* f, const void* g, CDConst K,
                     CDLevel L, int colour, hipStream_t s);
+// whether a level takes the tiled sweep (cd_sweep): 2D always, 3D from n = 128
+bool cd_tiled(int dim, int n);
+// One smoothing sweep uin -> uout (out of place; RBGS both colours, or Jacobi)
+// with the diffusivity of uin, in tiles.
+hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const void* f, CDConst K, CDLevel L,
+                    hipStream_t s);
 hipError_t cd_restrict(int dim, const void* u, const void* f, const void* g, void* uh, void* rc, CDConst K,
                        CDLevel L, hipStream_t s);
 hipError_t cd_coarse_rhs(int dim, const void* uh, const void* gc, void* fc, void* uc, CDConst K, CDLevel Lc,

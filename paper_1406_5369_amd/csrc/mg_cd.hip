@@ -112,7 +112,9 @@ __global__ __launch_bounds__(NT) void k_cd_g(const Cx* __restrict__ u, Cx* __res
     if (p < N) stc(gp(g), p, cd_g(K, ldc(gp(u), p)));
 }
 
-// RBGS colour in place (uin == uout) or Jacobi (out of place), g frozen.
+// One cell per thread (the small 3D levels, where a marching tile has too few
+// workgroups to hide its latency): an RBGS colour in place (uin == uout) or a
+// Jacobi sweep (out of place), g frozen in its array.
 template <int DIM, bool JAC>
 __global__ __launch_bounds__(NT) void k_cd_relax(const Cx* uin_, Cx* uout_, const Cx* __restrict__ f_,
                                                  const Cx* __restrict__ g_, CDConst K, CDLevel L, int colour) {
@@ -250,6 +252,301 @@ __global__ __launch_bounds__(NT) void k_cd_norm(const Cx* __restrict__ u_, const
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// ---------------------------------------------------------------------------
+// Tiled sweeps: both colours of a red-black sweep (or one Jacobi sweep) in one
+// launch, the diffusivity of the pre-sweep iterate formed on the fly.  g is
+// stored per cell as its real factor q = 1 / (1 + (Im u / (k theta))^2)
+// (g = (cos theta q, sin theta q), the same products as cd_g), u and q of a
+// box in LDS; red cells are relaxed on the box minus one ring in place (a
+// colour reads only the other colour), black cells on the box minus two
+// rings, and the tile is written to the output array (out of place, so a
+// neighbouring tile always reads the pre-sweep iterate).  Per cell the
+// arithmetic is that of the operator kernels (cd_apply), in the same order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double cd_q(const CDConst& K, Cx u) {
+    const double s = u.im / K.ktheta;
+    return 1.0 / (1.0 + s * s);
+}
+
+// one face: flux term (tr, ti) and face diffusivity (gr, gi), zeros outside the domain
+struct CDFace {
+    double tr, ti, gr, gi;
+};
+__device__ __forceinline__ CDFace cd_face_v(bool inside, Cx up, Cx gp, Cx uq, double qq, const CDConst& K) {
+    const double gqr = K.ct * qq, gqi = K.st * qq;
+    const double gr = 0.5 * (gp.re + gqr), gi = 0.5 * (gp.im + gqi);
+    const Cx t = cx_mul(Cx{gr, gi}, cx_sub(uq, up));
+    CDFace o;
+    o.tr = inside ? t.re : 0.0;
+    o.ti = inside ? t.im : 0.0;
+    o.gr = inside ? gr : 0.0;
+    o.gi = inside ? gi : 0.0;
+    return o;
+}
+
+// relaxation from the face sums: up + omega (f - N(u)) / D
+__device__ __forceinline__ Cx cd_relax_v(const CDConst& K, double c, Cx up, Cx F, Cx S, Cx fv) {
+    const Cx Nu{K.itau * up.re - c * F.re, K.itau * up.im - c * F.im};
+    const Cx r = cx_sub(fv, Nu);
+    const Cx D{K.itau + c * S.re, c * S.im};
+    return cx_add(up, cx_scale(K.omega, cx_div(r, D)));
+}
+
+__device__ __forceinline__ Cx lds_c(const d2v& v) { return Cx{v.x, v.y}; }
+__device__ __forceinline__ d2v to_v(Cx c) {
+    d2v v;
+    v.x = c.re;
+    v.y = c.im;
+    return v;
+}
+
+constexpr int CDB_Y = 16, CDB_Y3 = 12;  // box rows of the 2D / 3D tiles (64 lanes wide)
+
+// relaxation of the cell at (ly, lx) of an LDS plane P (u) / Q (q) with the
+// z-neighbours (ub, qb below; ua, qa above) given; 2D: no z faces
+template <int DIM, int W>
+__device__ __forceinline__ Cx cd_relax_lds(const CDConst& K, double c, const d2v (*P)[W], const double (*Q)[W],
+                                           int ly, int lx, int gx, int gy, int gz, int n, Cx ub, double qb, Cx ua,
+                                           double qa, Cx fv) {
+    const Cx up = lds_c(P[ly][lx]);
+    const double qp = Q[ly][lx];
+    const Cx gpv{K.ct * qp, K.st * qp};
+    const CDFace fW = cd_face_v(gx > 0, up, gpv, lds_c(P[ly][lx - 1]), Q[ly][lx - 1], K);
+    const CDFace fE = cd_face_v(gx < n - 1, up, gpv, lds_c(P[ly][lx + 1]), Q[ly][lx + 1], K);
+    const CDFace fS = cd_face_v(gy > 0, up, gpv, lds_c(P[ly - 1][lx]), Q[ly - 1][lx], K);
+    const CDFace fN = cd_face_v(gy < n - 1, up, gpv, lds_c(P[ly + 1][lx]), Q[ly + 1][lx], K);
+    // ((W + E) + (S + N)) [+ (B + T)], componentwise as cx_add
+    double Fr = (fW.tr + fE.tr) + (fS.tr + fN.tr), Fi = (fW.ti + fE.ti) + (fS.ti + fN.ti);
+    double Sr = (fW.gr + fE.gr) + (fS.gr + fN.gr), Si = (fW.gi + fE.gi) + (fS.gi + fN.gi);
+    if constexpr (DIM == 3) {
+        const CDFace fB = cd_face_v(gz > 0, up, gpv, ub, qb, K);
+        const CDFace fT = cd_face_v(gz < n - 1, up, gpv, ua, qa, K);
+        Fr = Fr + (fB.tr + fT.tr);
+        Fi = Fi + (fB.ti + fT.ti);
+        Sr = Sr + (fB.gr + fT.gr);
+        Si = Si + (fB.gi + fT.gi);
+    }
+    return cd_relax_v(K, c, up, Cx{Fr, Fi}, Cx{Sr, Si}, fv);
+}
+
+// 2D: a 64 x 16 box per workgroup; red on the box minus one ring, black (or
+// Jacobi) on the tile, written out
+template <bool JAC>
+__global__ __launch_bounds__(NT) void k_cd_sweep2d(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
+                                                   const Cx* __restrict__ f_, CDConst K, CDLevel L) {
+    constexpr int H = JAC ? 1 : 2, TX = 64 - 2 * H, TY = CDB_Y - 2 * H, RPT = CDB_Y / 4;
+    __shared__ d2v Ub[CDB_Y][64];
+    __shared__ double Qb[CDB_Y][64];
+    const int n = L.n;
+    const int ntx = (n + TX - 1) / TX;
+    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gx = tx * TX - H + lane;
+    const bool xd = gx >= 0 && gx < n;
+    const MG_GLOBAL Cx* uin = gp(uin_);
+    const MG_GLOBAL Cx* f = gp(f_);
+    MG_GLOBAL Cx* uout = gp(uout_);
+    const Cx z0{0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w + 4 * m, gy = ty * TY - H + ly;
+        const bool dom = xd && gy >= 0 && gy < n;
+        const Cx u = dom ? ldc(uin, (size_t)gy * n + gx) : z0;
+        Ub[ly][lane] = to_v(u);
+        Qb[ly][lane] = dom ? cd_q(K, u) : 1.0;
+    }
+    __syncthreads();
+    if constexpr (!JAC) {
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + 4 * m, gy = ty * TY - H + ly;
+            if (xd && gy >= 0 && gy < n && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y - 2 &&
+                ((gx + gy) & 1) == 0)
+                Ub[ly][lane] = to_v(cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, gx, gy, 0, n, z0, 1.0, z0, 1.0,
+                                                        ldc(f, (size_t)gy * n + gx)));
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w + 4 * m, gy = ty * TY - H + ly;
+        if (xd && gy >= 0 && gy < n && lane >= H && lane < 64 - H && ly >= H && ly < CDB_Y - H) {
+            Cx v = lds_c(Ub[ly][lane]);
+            if (JAC || ((gx + gy) & 1) == 1)
+                v = cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, gx, gy, 0, n, z0, 1.0, z0, 1.0,
+                                        ldc(f, (size_t)gy * n + gx));
+            stc(uout, (size_t)gy * n + gx, v);
+        }
+    }
+}
+
+// 3D: a 64 x 12 box in x-y marching along z through a chunk of zc planes.
+// Each thread keeps its own cells of the last four planes (u, q and f) in
+// registers for the z faces (ring position = plane mod 4, resolved at compile
+// time by unrolling four steps); the planes being relaxed are in an LDS ring
+// of three planes for the x-y faces.  RBGS step kk: plane kk enters (old u,
+// its q); red on plane kk-1 (box minus one ring, in place); black on plane
+// kk-2 (the tile), written out with its red cells.  Jacobi step kk: plane kk
+// enters; plane kk-1 is relaxed on the tile and written out.
+template <bool JAC>
+struct CDSweep3 {
+    static constexpr int H = JAC ? 1 : 2, TX = 64 - 2 * H, TY = CDB_Y3 - 2 * H, RPT = CDB_Y3 / 4;
+    d2v (*Ub)[CDB_Y3][64];
+    double (*Qb)[CDB_Y3][64];
+    const MG_GLOBAL Cx* uin;
+    const MG_GLOBAL Cx* f;
+    MG_GLOBAL Cx* uout;
+    CDConst K;
+    double c;
+    int n, lane, w, gx, z0, z1, kstart;
+    size_t pl;
+    bool xd;
+    int gyr[RPT];
+    bool yd[RPT];
+    double ure[4][RPT], uim[4][RPT], qr[4][RPT], fre[4][RPT], fim[4][RPT];
+    double pur[RPT], pui[RPT], pfr[RPT], pfi[RPT];  // u and f of the next plane, loaded one step ahead
+
+    __device__ __forceinline__ Cx U(int q, int m) const { return Cx{ure[q][m], uim[q][m]}; }
+    __device__ __forceinline__ Cx Fv(int q, int m) const { return Cx{fre[q][m], fim[q][m]}; }
+
+    __device__ __forceinline__ void prefetch(int z) {
+        const bool zd = z >= 0 && z < n;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            Cx u{0.0, 0.0}, fv{0.0, 0.0};
+            if (yd[m] && zd) {
+                const size_t p = (size_t)z * pl + (size_t)gyr[m] * n + gx;
+                u = ldc(uin, p);
+                fv = ldc(f, p);
+            }
+            pur[m] = u.re;
+            pui[m] = u.im;
+            pfr[m] = fv.re;
+            pfi[m] = fv.im;
+        }
+    }
+
+    template <int P>
+    __device__ __forceinline__ void step(int kk) {
+        constexpr int R0 = P, R1 = (P + 3) & 3, R2 = (P + 2) & 3, R3 = (P + 1) & 3;  // planes kk .. kk-3
+        const int q = kk - kstart;
+        const int s0 = q % 3, s1 = (q + 2) % 3, s2 = (q + 1) % 3;                     // LDS: kk, kk-1, kk-2
+        const bool zd = kk >= 0 && kk < n;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w + 4 * m;
+            const Cx u{pur[m], pui[m]};
+            const double qv = (yd[m] && zd) ? cd_q(K, u) : 1.0;
+            ure[R0][m] = u.re;
+            uim[R0][m] = u.im;
+            qr[R0][m] = qv;
+            fre[R0][m] = pfr[m];
+            fim[R0][m] = pfi[m];
+            Ub[s0][ly][lane] = to_v(u);
+            Qb[s0][ly][lane] = qv;
+        }
+        prefetch(kk + 1);  // after the last step this loads a plane nobody reads (inside the grid only)
+        __syncthreads();
+        if constexpr (JAC) {
+            const int zr = kk - 1;
+            if (zr >= z0 && zr < z1) {
+#pragma unroll
+                for (int m = 0; m < RPT; ++m) {
+                    const int ly = w + 4 * m;
+                    if (yd[m] && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y3 - 2) {
+                        const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, gx, gyr[m], zr, n, U(R2, m),
+                                                         qr[R2][m], U(R0, m), qr[R0][m], Fv(R1, m));
+                        stc(uout, (size_t)zr * pl + (size_t)gyr[m] * n + gx, v);
+                    }
+                }
+            }
+        } else {
+            const int zr = kk - 1;  // red plane
+            if (zr >= z0 - 1 && zr >= 0 && zr <= z1 && zr < n) {
+#pragma unroll
+                for (int m = 0; m < RPT; ++m) {
+                    const int ly = w + 4 * m;
+                    if (yd[m] && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y3 - 2 &&
+                        ((gx + gyr[m] + zr) & 1) == 0) {
+                        const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, gx, gyr[m], zr, n, U(R2, m),
+                                                         qr[R2][m], U(R0, m), qr[R0][m], Fv(R1, m));
+                        Ub[s1][ly][lane] = to_v(v);
+                        ure[R1][m] = v.re;
+                        uim[R1][m] = v.im;
+                    }
+                }
+            }
+            __syncthreads();
+            const int zb = kk - 2;  // black plane (output)
+            if (zb >= z0 && zb < z1) {
+#pragma unroll
+                for (int m = 0; m < RPT; ++m) {
+                    const int ly = w + 4 * m;
+                    if (yd[m] && lane >= 2 && lane <= 61 && ly >= 2 && ly <= CDB_Y3 - 3) {
+                        Cx v = lds_c(Ub[s2][ly][lane]);
+                        if (((gx + gyr[m] + zb) & 1) == 1)
+                            v = cd_relax_lds<3, 64>(K, c, Ub[s2], Qb[s2], ly, lane, gx, gyr[m], zb, n, U(R3, m),
+                                                    qr[R3][m], U(R1, m), qr[R1][m], Fv(R2, m));
+                        stc(uout, (size_t)zb * pl + (size_t)gyr[m] * n + gx, v);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void run() {
+        const int kend = z1 - 1 + H;
+        int kk = kstart;
+        for (; kk + 3 <= kend; kk += 4) {
+            step<0>(kk);
+            step<1>(kk + 1);
+            step<2>(kk + 2);
+            step<3>(kk + 3);
+        }
+        if (kk <= kend) step<0>(kk);
+        if (kk + 1 <= kend) step<1>(kk + 1);
+        if (kk + 2 <= kend) step<2>(kk + 2);
+    }
+};
+
+template <bool JAC>
+__global__ __launch_bounds__(NT) void k_cd_sweep3d(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
+                                                   const Cx* __restrict__ f_, CDConst K, CDLevel L, int zc) {
+    using S = CDSweep3<JAC>;
+    __shared__ d2v Ub[3][CDB_Y3][64];
+    __shared__ double Qb[3][CDB_Y3][64];
+    S s;
+    s.Ub = Ub;
+    s.Qb = Qb;
+    s.uin = gp(uin_);
+    s.f = gp(f_);
+    s.uout = gp(uout_);
+    s.K = K;
+    s.c = L.c;
+    const int n = L.n;
+    s.n = n;
+    const int ntx = (n + S::TX - 1) / S::TX, nty = (n + S::TY - 1) / S::TY;
+    const int tx = blockIdx.x % ntx, t2 = blockIdx.x / ntx, ty = t2 % nty, tz = t2 / nty;
+    s.z0 = tz * zc;
+    s.z1 = min(s.z0 + zc, n);
+    s.kstart = s.z0 - S::H;
+    s.lane = threadIdx.x & 63;
+    s.w = threadIdx.x >> 6;
+    s.gx = tx * S::TX - S::H + s.lane;
+    s.xd = s.gx >= 0 && s.gx < n;
+    s.pl = (size_t)n * n;
+#pragma unroll
+    for (int m = 0; m < S::RPT; ++m) {
+        s.gyr[m] = ty * S::TY - S::H + s.w + 4 * m;
+        s.yd[m] = s.xd && s.gyr[m] >= 0 && s.gyr[m] < n;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s.ure[q][m] = s.uim[q][m] = s.fre[q][m] = s.fim[q][m] = 0.0, s.qr[q][m] = 1.0;
+    }
+    s.prefetch(s.kstart);
+    s.run();
+}
+
 inline unsigned nblk(size_t N) { return (unsigned)((N + NT - 1) / NT); }
 inline size_t ncells(int dim, int n) { return dim == 2 ? (size_t)n * n : (size_t)n * n * n; }
 
@@ -281,6 +578,33 @@ hipError_t cd_relax(int dim, bool jacobi, const void* uin, void* uout, const voi
     } else {
         if (jacobi) k_cd_relax<3, true><<<b, NT, 0, s>>>(ui, uo, ff, gg, K, L, colour);
         else k_cd_relax<3, false><<<b, NT, 0, s>>>(ui, uo, ff, gg, K, L, colour);
+    }
+    return hipGetLastError();
+}
+
+// 3D levels from this edge on use the marching tiles (below it a march has
+// too few workgroups to hide its latency and the per-cell kernels are faster)
+constexpr int kCDTiled3D = 128;
+bool cd_tiled(int dim, int n) { return dim == 2 || n >= kCDTiled3D; }
+
+hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const void* f, CDConst K, CDLevel L,
+                    hipStream_t s) {
+    const int n = L.n;
+    auto ui = (const Cx*)uin;
+    auto uo = (Cx*)uout;
+    auto ff = (const Cx*)f;
+    if (dim == 2) {
+        const int H = jacobi ? 1 : 2;
+        const unsigned b = (unsigned)(((n + 64 - 2 * H - 1) / (64 - 2 * H)) * ((n + CDB_Y - 2 * H - 1) / (CDB_Y - 2 * H)));
+        if (jacobi) k_cd_sweep2d<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L);
+        else k_cd_sweep2d<false><<<b, NT, 0, s>>>(ui, uo, ff, K, L);
+    } else {
+        const int H = jacobi ? 1 : 2, zc = 16;
+        if (n < kCDTiled3D) return hipErrorInvalidValue;  // small levels take the per-cell kernels
+        const unsigned b = (unsigned)(((n + 64 - 2 * H - 1) / (64 - 2 * H)) *
+                                      ((n + CDB_Y3 - 2 * H - 1) / (CDB_Y3 - 2 * H)) * ((n + zc - 1) / zc));
+        if (jacobi) k_cd_sweep3d<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
+        else k_cd_sweep3d<false><<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
     }
     return hipGetLastError();
 }

@@ -42,7 +42,7 @@ def host(t):
     return t.cpu().numpy()
 
 
-SIZES = [(2, 2), (2, 4), (2, 64), (2, 256), (3, 2), (3, 8), (3, 32)]
+SIZES = [(2, 2), (2, 4), (2, 64), (2, 256), (3, 2), (3, 8), (3, 32), (3, 128)]  # 3D tiles from 128 cells
 
 
 @pytest.mark.parametrize("dim,n", SIZES)
@@ -79,7 +79,7 @@ def test_cd_fas_cycle_bitwise(dim, n, smoother, nu, dev_ok):
         mg().mg_destroy(ctx)
 
 
-@pytest.mark.parametrize("dim,n,steps", [(2, 128, 3), (2, 512, 2), (3, 32, 3), (3, 64, 2)])
+@pytest.mark.parametrize("dim,n,steps", [(2, 128, 3), (2, 512, 2), (3, 32, 3), (3, 64, 2), (3, 128, 1)])
 @pytest.mark.parametrize("smoother", [RB, JAC])
 def test_cd_run_matches_oracle(dim, n, steps, smoother, dev_ok):
     """Implicit-Euler steps with FAS per step: cycle counts equal, the final
