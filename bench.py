@@ -316,8 +316,11 @@ def bench_serving(args, mg, torch):
             pool[key] = inputs.uniform_rhs(req.dim, req.n, 5000 + req.seed % 3)
         return pool[key]
 
-    def run(reqs, closed_loop=False, host=None):
+    dpool = {}  # device copies of the pooled right-hand sides (device-fed requests)
+
+    def run(reqs, closed_loop=False, host=None, device=False):
         lat = []
+        douts = {}  # device-fed request -> its solution array
         i = 0
         start = time.perf_counter()
         arrival_of = {}
@@ -328,7 +331,17 @@ def bench_serving(args, mg, torch):
             # closed loop: a fixed number of requests in flight, a new one per completion
             while i < len(reqs) and (len(arrival_of) < inflight if closed_loop else reqs[i].t_arrival <= now):
                 t0 = clock()
-                rid = mg.mg_server_submit(ctx, rhs_for(reqs[i]))
+                if device:
+                    f = rhs_for(reqs[i])
+                    key = (reqs[i].dim, reqs[i].n, reqs[i].seed % 3)
+                    if key not in dpool:
+                        dpool[key] = torch.from_numpy(f).to("cuda")
+                        torch.cuda.synchronize()
+                    ud = torch.empty_like(dpool[key])
+                    rid = mg.mg_server_submit_device(ctx, dpool[key], ud)
+                    douts[rid] = ud
+                else:
+                    rid = mg.mg_server_submit(ctx, rhs_for(reqs[i]))
                 if host is not None:
                     host["submit"] += clock() - t0
                 arrival_of[rid] = clock() if closed_loop else start + reqs[i].t_arrival
@@ -343,7 +356,12 @@ def bench_serving(args, mg, torch):
             mg.mg_server_step(ctx)
             t1 = clock()
             for rid in mg.mg_server_poll(ctx):
-                st, _, cyc, rr, _ = mg.mg_server_fetch(ctx, rid, out=out_for(*shape_of.pop(rid)))
+                if device:
+                    shape_of.pop(rid)
+                    douts.pop(rid)
+                    st, _, cyc, rr, _ = mg.mg_server_fetch(ctx, rid)
+                else:
+                    st, _, cyc, rr, _ = mg.mg_server_fetch(ctx, rid, out=out_for(*shape_of.pop(rid)))
                 if st != 0:
                     raise RuntimeError(f"serving request {rid} ended with status {st}")
                 tdone = clock()
@@ -367,6 +385,15 @@ def bench_serving(args, mg, torch):
         f"{inflight} in flight, p50/p99 {sat_p[0]:.2f}/{sat_p[1]:.2f} ms); "
         f"host time in submit {host['submit']:.2f} s, step {host['step']:.2f} s ({host['steps']} calls), "
         f"poll+fetch {host['poll_fetch']:.2f} s")
+    # the same closed loop fed from device memory (right-hand sides resident in
+    # HBM, solutions copied device to device): no host staging of payloads
+    host_d = {"submit": 0.0, "step": 0.0, "poll_fetch": 0.0, "steps": 0}
+    lat_d, span_d = run(sat_reqs, closed_loop=True, host=host_d, device=True)
+    mu_dev = len(sat_reqs) / span_d
+    dev_p = [float(np.percentile(lat_d, q) * 1e3) for q in (50, 99)]
+    log(f"[bench] serving, device-fed: saturated {mu_dev:.1f} solves/s, p50/p99 {dev_p[0]:.2f}/{dev_p[1]:.2f} ms; "
+        f"host time in submit {host_d['submit']:.2f} s, step {host_d['step']:.2f} s, "
+        f"poll+fetch {host_d['poll_fetch']:.2f} s")
     sweep = []
     for frac in (0.2, 0.4, 0.6, 0.8, 0.95):
         reqs = inputs.serving_requests(args.serve_requests, rate=frac * mu_sat, seed=4)
@@ -426,7 +453,10 @@ def bench_serving(args, mg, torch):
                   "fp64_sequential_solves_per_s": fp64_rate, "fp64_sequential_requests": len(seq),
                   "served_over_fp64_sequential": mu_sat / fp64_rate,
                   "saturated_host_seconds": host, "saturated_p50_ms": sat_p[0], "saturated_p99_ms": sat_p[1],
-                  "saturated_dof_per_s": mu_sat * mean_dof, "lambda_sweep": sweep},
+                  "saturated_dof_per_s": mu_sat * mean_dof, "lambda_sweep": sweep,
+                  "device_fed": {"saturated_solves_per_s": mu_dev, "saturated_dof_per_s": mu_dev * mean_dof,
+                                 "saturated_p50_ms": dev_p[0], "saturated_p99_ms": dev_p[1],
+                                 "saturated_host_seconds": host_d}},
     }
 
 

@@ -402,6 +402,14 @@ int mg_server_create(const mg_server_params* sp, void* stream, mg_ctx** out);
 /* Queue a request: dim 2/3, n = 2^L+1 (5 <= n <= max edge), f_host: HOST array of n^dim
  * doubles (copied).  MG_ENOMEM if the request alone exceeds the budget. */
 int mg_server_submit(mg_ctx* ctx, int dim, int n, const double* f_host, long long* req_id);
+/* Queue a request whose data stay in device memory: f_dev (DEVICE, n^dim
+ * doubles, caller-owned, complete before the call) is copied device to device
+ * when the request is admitted and must stay unchanged until the request is
+ * reported done; the solution is copied into u_dev (DEVICE, n^dim doubles,
+ * caller-owned) on the server's copy stream and is there once mg_server_poll
+ * has reported the request.  mg_server_fetch then returns its statistics
+ * (u_host must be NULL for such a request).  Errors as mg_server_submit. */
+int mg_server_submit_device(mg_ctx* ctx, int dim, int n, const double* f_dev, double* u_dev, long long* req_id);
 /* Admit, queue one refinement step of every joined request, complete the ones
  * the previous step finished.  Waits for the previous step only (not for the
  * one it queues); the queued step runs on the server's stream.  n_active

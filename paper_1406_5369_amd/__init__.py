@@ -135,6 +135,7 @@ def lib():
             "mg_batch_solve": (i, [p, p, p, d, i, p, p]),
             "mg_server_create": (i, [C.POINTER(_ServerParams), p, C.POINTER(p)]),
             "mg_server_submit": (i, [p, i, i, p, C.POINTER(C.c_longlong)]),
+            "mg_server_submit_device": (i, [p, i, i, p, p, C.POINTER(C.c_longlong)]),
             "mg_server_step": (i, [p, C.POINTER(i), C.POINTER(i)]),
             "mg_server_poll": (i, [p, p, i, C.POINTER(i)]),
             "mg_server_fetch": (i, [p, C.c_longlong, p, C.POINTER(i), C.POINTER(d), C.POINTER(d)]),
@@ -673,6 +674,22 @@ def mg_server_submit(ctx: int, f_host) -> int:
     rid = C.c_longlong(0)
     _check(lib().mg_server_submit(ctx, f.ndim, f.shape[0], f.ctypes.data, C.byref(rid)), "mg_server_submit")
     _server_shapes[(ctx, rid.value)] = f.shape
+    return rid.value
+
+
+def mg_server_submit_device(ctx: int, f_dev, u_dev) -> int:
+    """Queue a request fed from device memory: f_dev (float64 tensor on the
+    device, left unchanged until the request is done) is copied device to
+    device at admission; the solution lands in u_dev (same shape) when
+    mg_server_poll reports the request."""
+    import torch
+
+    if tuple(u_dev.shape) != tuple(f_dev.shape):
+        raise ValueError("u_dev and f_dev must have the same shape")
+    rid = C.c_longlong(0)
+    _check(lib().mg_server_submit_device(ctx, f_dev.dim(), f_dev.shape[0], _dptr(f_dev, torch.float64, None, "f_dev"),
+                                         _dptr(u_dev, torch.float64, None, "u_dev"), C.byref(rid)),
+           "mg_server_submit_device")
     return rid.value
 
 

@@ -587,6 +587,8 @@ struct Request {
     double* f_pin = nullptr;   // pinned copy of the rhs (until uploaded)
     std::unique_ptr<double[]> f_heap;  // used instead when too many payloads are queued
     double* u_pin = nullptr;   // pinned result (filled by an asynchronous copy)
+    const double* f_dev = nullptr;  // device-fed request: the caller's right-hand side
+    double* u_dev = nullptr;        // and the caller's device array for the solution
     hipEvent_t ev = nullptr;   // completes when u_pin holds the result
     hipEvent_t up = nullptr;   // completes when the hierarchy holds u = 0 and f
     Inst* inst = nullptr;
@@ -976,6 +978,27 @@ int mg_server_submit(mg_ctx* ctx, int dim, int n, const double* f_host, long lon
     return MG_OK;
 }
 
+int mg_server_submit_device(mg_ctx* ctx, int dim, int n, const double* f_dev, double* u_dev, long long* req_id) {
+    if (!ctx || !registered(ctx) || !f_dev || !u_dev || !req_id) return MG_EINVAL;
+    mg_batch_handle* h = as_handle(ctx);
+    if (h->kind != 2) return MG_EINVAL;
+    Server& S = *h->server;
+    if (!valid_edge(dim, n) || n < 5) return MG_EINVAL;
+    if (n > (dim == 2 ? S.sp.max_n2d : S.sp.max_n3d)) return MG_EINVAL;
+    if (inst_bytes(dim, n, true) > S.sp.hbm_budget_bytes) return MG_ENOMEM;
+    auto R = std::make_unique<Request>();
+    R->id = S.next_id++;
+    R->dim = dim;
+    R->n = n;
+    R->f_dev = f_dev;
+    R->u_dev = u_dev;
+    R->t_submit = std::chrono::steady_clock::now();
+    *req_id = R->id;
+    S.sch.submit(R->id);
+    S.reqs[R->id] = std::move(R);
+    return MG_OK;
+}
+
 int mg_server_step(mg_ctx* ctx, int* n_active, int* n_queued) {
     if (!ctx || !registered(ctx)) return MG_EINVAL;
     mg_batch_handle* h = as_handle(ctx);
@@ -1030,8 +1053,9 @@ int mg_server_fetch(mg_ctx* ctx, long long req_id, double* u_host, int* cycles, 
     Request& R = *it->second;
     if (!R.complete) return MG_EBUSY;
     const size_t bytes = npts(R.dim, R.n) * sizeof(double);
+    if (R.u_dev && u_host) return MG_EINVAL;  // a device-fed request's solution is in its u_dev
     if (u_host) host_copy(u_host, R.u_pin, bytes);
-    S.pinned.put(R.u_pin, bytes);
+    if (R.u_pin) S.pinned.put(R.u_pin, bytes);
     R.u_pin = nullptr;
     if (R.ev) (void)hipEventDestroy(R.ev);
     R.ev = nullptr;
@@ -1080,7 +1104,9 @@ int server_admit(Server& S) {
         const size_t N = npts(R.dim, R.n);
         // ordered after the result copy of the hierarchy's previous request (same stream)
         BCK(hipMemsetAsync(I->u64, 0, N * sizeof(double), S.cs));
-        if (R.f_pin) {
+        if (R.f_dev) {
+            BCK(hipMemcpyAsync(I->f64, R.f_dev, N * sizeof(double), hipMemcpyDeviceToDevice, S.cs));
+        } else if (R.f_pin) {
             BCK(hipMemcpyAsync(I->f64, R.f_pin, N * sizeof(double), hipMemcpyHostToDevice, S.cs));
         } else {
             BCK(hipMemcpyAsync(I->f64, R.f_heap.get(), N * sizeof(double), hipMemcpyHostToDevice, S.cs));
@@ -1180,9 +1206,13 @@ int server_consume(Server& S, int d, long long upto, bool wait) {
             const int steps = c[E.cap + I->slot];
             const size_t bytes = npts(I->dim, I->n) * sizeof(double);
             const double* src = (steps & 1) ? I->u2 : I->u64;  // later steps skip the finished slot
-            R->u_pin = (double*)S.pinned.get(bytes);
-            if (!R->u_pin) return MG_ENOMEM;
-            BCK(hipMemcpyAsync(R->u_pin, src, bytes, hipMemcpyDeviceToHost, S.cs));
+            if (R->u_dev) {
+                BCK(hipMemcpyAsync(R->u_dev, src, bytes, hipMemcpyDeviceToDevice, S.cs));
+            } else {
+                R->u_pin = (double*)S.pinned.get(bytes);
+                if (!R->u_pin) return MG_ENOMEM;
+                BCK(hipMemcpyAsync(R->u_pin, src, bytes, hipMemcpyDeviceToHost, S.cs));
+            }
             const double n0 = nr[E.cap + I->slot];
             R->rel_res = n0 > 0.0 ? nr[I->slot] / n0 : 0.0;
             R->cycles = steps;

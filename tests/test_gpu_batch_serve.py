@@ -22,6 +22,13 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
+def host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
 def alone(dim, n, f):
     m = mg()
     s = m.Solver(m.Params(dim=dim, n=n, precision=m.PREC_FP32_IR))
@@ -220,3 +227,51 @@ def test_server_mix_at_full_request_sizes(dev_ok):
         u_ref, h_ref, rc = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-8, max_cycles=40)
         assert rc == 0 and cyc == len(h_ref) - 1, (rid, f.shape)
         assert np.array_equal(u, u_ref), (rid, f.shape)
+
+
+def test_server_device_fed_requests_in_a_mix(dev_ok):
+    """Requests fed from device memory (right-hand side copied device to
+    device at admission, solution copied into the caller's device array)
+    mixed with host-fed ones: every result equals the oracle's solve."""
+    import torch
+
+    m = mg()
+    sp = m.ServerParams(hbm_budget_bytes=512 << 20, max_slots=3, max_n2d=257, max_n3d=33, tol=1e-8, max_cycles=40)
+    ctx = m.mg_server_create(sp)
+    reqs = [(2, 129, 1, True), (3, 33, 2, False), (2, 257, 3, True), (3, 17, 4, True), (2, 65, 5, False),
+            (3, 33, 6, True), (2, 129, 7, True), (2, 33, 8, False)]
+    info, done = {}, {}
+    pending = list(reqs)
+    steps = 0
+    while pending or len(done) < len(reqs):
+        for _ in range(2):
+            if pending:
+                dim, n, seed, on_dev = pending.pop(0)
+                f = inputs.uniform_rhs(dim, n, 1300 + seed)
+                if on_dev:
+                    fd = dev(f)
+                    ud = torch.full_like(fd, float("nan"))
+                    torch.cuda.synchronize()
+                    rid = m.mg_server_submit_device(ctx, fd, ud)
+                    info[rid] = (f, fd, ud)
+                else:
+                    rid = m.mg_server_submit(ctx, f)
+                    info[rid] = (f, None, None)
+        m.mg_server_step(ctx)
+        for rid in m.mg_server_poll(ctx):
+            f, fd, ud = info[rid]
+            if ud is None:
+                st, u, cyc, rr, _ = m.mg_server_fetch(ctx, rid, shape=f.shape)
+            else:
+                st, _, cyc, rr, _ = m.mg_server_fetch(ctx, rid)
+                u = host(ud)
+            done[rid] = (st, u, cyc, rr)
+        steps += 1
+        assert steps < 500
+    for rid, (st, u, cyc, rr) in done.items():
+        f = info[rid][0]
+        assert st == 0 and rr <= 1e-8
+        u_ref, h_ref, _ = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-8, max_cycles=40)
+        assert cyc == len(h_ref) - 1
+        assert np.array_equal(u, u_ref)
+    m.mg_destroy(ctx)
