@@ -686,13 +686,24 @@ def main(argv=None) -> int:
                       "variants excluded)", launches, sweep_ms, (4 if var else 3) * word * dof,
                       traffic_record(args.workload, (by, zchunk, pd, wv)))
     pby, pzc, ppd, pwv, _, ppr = mg.mg_tile_config(solver.ctx, 0, 2, with_order=True)
-    pass_roof = roof(pass_kernel(dim, pby, ppd, var, ir, pwv, ppr, word=word), pass_blocks(dim, n, pby, pzc, ppr),
-                     ("finest-level FP64 refinement pass (u += e, r = f - A u, r to "
-                      + ("FP32" if word == 4 else "scaled binary16") + ", norm partials)") if ir
-                     else "finest-level FP64 residual-norm pass", pass_launches, pass_ms,
-                     (pass_bytes + (8 if var else 0)) * dof,
-                     traffic_record(args.workload, (pby, pzc, ppd, pwv) + (("p",) if ppr else ()),
-                                    key="pass_configs"))
+    nby, nzc, npd, nwv = mg.mg_tile_config(solver.ctx, 0, 6)
+    if not ir and nzc > 0:
+        # FP64 solves sum each cycle's residual norm in the next cycle's first
+        # pre-smoothing sweep (reads u and f, writes the other buffer): the
+        # event brackets time that sweep
+        pass_roof = roof(sweep_kernel(dim, word, nby, npd, var, nwv, flags=4), sweep_blocks(dim, n, nby, nzc),
+                         "finest-level FP64 first pre-smoothing sweep that also sums the residual norm of its "
+                         "incoming iterate", pass_launches, pass_ms, (4 if var else 3) * word * dof,
+                         traffic_record(args.workload, (nby, nzc, npd, nwv, "n")))
+    else:
+        pass_roof = roof(pass_kernel(dim, pby, ppd, var, ir, pwv, ppr, word=word),
+                         pass_blocks(dim, n, pby, pzc, ppr),
+                         ("finest-level FP64 refinement pass (u += e, r = f - A u, r to "
+                          + ("FP32" if word == 4 else "scaled binary16") + ", norm partials)") if ir
+                         else "finest-level FP64 residual-norm pass", pass_launches, pass_ms,
+                         (pass_bytes + (8 if var else 0)) * dof,
+                         traffic_record(args.workload, (pby, pzc, ppd, pwv) + (("p",) if ppr else ()),
+                                        key="pass_configs"))
     if pass_roof["total_ms"] > sweep_roof["total_ms"]:
         roofline, other = pass_roof, sweep_roof
     else:
@@ -707,7 +718,8 @@ def main(argv=None) -> int:
              "roofline_other_kernel": other,
              "fine_tiles": {fam: mg.mg_tile_config(solver.ctx, 0, i, with_order=True) for i, fam in
                             enumerate(["smooth", "restrict", "norm_or_refinement", "smooth_zero_guess",
-                                       "smooth_fused_correction", "smooth_fused_restriction"])}}
+                                       "smooth_fused_correction", "smooth_fused_restriction",
+                                       "smooth_with_norm"])}}
     if not args.no_fp64 and w["precision"] == 1:
         s64 = mg.Solver(mg.Params(dim=dim, n=n, precision=mg.PREC_FP64, op=op, k=kd))
         u = us[0]

@@ -162,7 +162,11 @@ int mg_num_levels(const mg_ctx* ctx);
  * pass, 3 smoothing from a zero iterate, 4 smoothing with the coarse-grid
  * correction fused in, 5 the last pre-smoothing sweep fused with the residual
  * and restriction: *zchunk coarse planes per workgroup, 0 when the level runs
- * the sweep and the restriction apart): tile rows *by, z-chunk *zchunk (3D planes per workgroup), for 3D
+ * the sweep and the restriction apart, 6 (level 0 of an FP64 context) the
+ * first pre-smoothing sweep that also sums the residual norm of its incoming
+ * iterate, which in mg_solve gives each cycle's norm (Section 2.4's L2
+ * residual; every field 0 when the norm is a pass of its own)): tile rows
+ * *by, z-chunk *zchunk (3D planes per workgroup), for 3D
  * marching kernels *prefetch = planes of u loaded ahead (1 or 2), *waves =
  * wavefronts per workgroup (4; 1 or 8 for 3D smoothing and the 3D pass), for
  * smoothing *order = block-to-tile order (0: each XCD takes a contiguous band

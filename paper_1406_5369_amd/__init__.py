@@ -297,8 +297,10 @@ def mg_num_levels(ctx: int) -> int:
 
 def mg_tile_config(ctx: int, level: int, family: int, with_order: bool = False):
     """(by, zchunk, prefetch, waves) used on a level by a kernel family (0 smooth, 1 restrict, 2 norm,
-    3 smooth from a zero iterate, 4 smooth with the fused coarse-grid correction); with_order adds the
-    block order (0 XCD bands, 1 linear) and the pairs flag (3D pass with two nodes per lane)."""
+    3 smooth from a zero iterate, 4 smooth with the fused coarse-grid correction, 5 last pre-smoothing
+    sweep fused with the restriction, 6 FP64 first pre-smoothing sweep that also sums the residual norm,
+    all 0 when the norm is a pass of its own); with_order adds the block order (0 XCD bands, 1 linear)
+    and the pairs flag (3D pass with two nodes per lane)."""
     by, zc, pd, wv, od, xp = (C.c_int(0) for _ in range(6))
     _check(lib().mg_tile_config(ctx, level, family, C.byref(by), C.byref(zc), C.byref(pd), C.byref(wv),
                                 C.byref(od), C.byref(xp)), "mg_tile_config")

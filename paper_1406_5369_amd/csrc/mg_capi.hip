@@ -307,6 +307,7 @@ void destroy(mg_ctx* c) {
     ffree(c->u64_scratch);
     ffree(c->k64);
     ffree(c->d_partial);
+    ffree(c->d_spart);
     ffree(c->d_norm);
     ffree(c->d_norm0);
     ffree(c->d_ctrl);
@@ -367,6 +368,21 @@ hipError_t enqueue_norm(mg_ctx* c, hipStream_t s, int step = 0) {
     return launch_norm_finalize(c->d_partial, c->pstride, nparts, 0, 1, c->d_norm, s);
 }
 
+// FP64 with the fused norm: the first pre-smoothing sweep of the next cycle
+// (reads the bound u, writes its ping-pong partner, leaving u as it is) and
+// the norm of u's residual that it sums, into d_norm.  With 'step' > 0 and
+// measurement on, the sweep is bracketed and tagged (step, kernel 1).
+hipError_t enqueue_nrm_sweep(mg_ctx* c, hipStream_t s, int step = 0) {
+    const TileCfg cfg = c->tl64[0].smooth_nrm;
+    const int nparts = smooth_tiles(c->p.dim, c->prob.smoother, c->p.n, cfg);
+    const bool timed = prof_begin(c, step, s);
+    hipError_t e = launch_smooth<double>(c->p.dim, c->prob.smoother, c->prob.var, c->G64[0].d, 1, c->p.n, 0,
+                                         SWEEP_NORM, cfg, s);
+    if (timed) prof_end(c, step, 1, s);
+    if (e != hipSuccess) return e;
+    return launch_norm_finalize(c->d_spart, nparts, nparts, 0, 1, c->d_norm, s);
+}
+
 hipError_t enqueue_ir(mg_ctx* c, int sel, int flags, hipStream_t s, int step = 0) {
     const int nparts = norm_tiles(c->p.dim, c->p.n, c->top.norm);
     const bool timed = prof_begin(c, step, s);
@@ -406,10 +422,12 @@ hipError_t enqueue_steps(mg_ctx* c, int K, double tol, int max_cycles, hipStream
         const int step = prof ? step0 + i + 1 : 0;
         const int n0 = c->prof_n;
         if (c->p.precision == MG_PREC_FP64) {
-            e = vcycle<double>(c->prob, c->G64, false, c->tl64, s, pev, pn, pcap, &c->tail64);
+            // with the fused norm the cycle's first sweep ran at the end of the
+            // previous step (or before the first); this step ends with the next one's
+            e = vcycle<double>(c->prob, c->G64, false, c->tl64, s, pev, pn, pcap, &c->tail64, c->nrm_fused);
             for (int j = n0; prof && j < c->prof_n; j += 2) c->prof_step.push_back(step), c->prof_kind.push_back(0);
             if (e != hipSuccess) return e;
-            e = enqueue_norm(c, s, step);
+            e = c->nrm_fused ? enqueue_nrm_sweep(c, s, step) : enqueue_norm(c, s, step);
         } else {
             e = is_h16(c->p) ? vcycle<half_t>(c->prob, c->G32, true, c->tl32, s, pev, pn, pcap, &c->tail32)
                              : vcycle<float>(c->prob, c->G32, true, c->tl32, s, pev, pn, pcap, &c->tail32);
@@ -1018,6 +1036,24 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
             }
             *vcfg[v] = cfg;
         }
+        // FP64 finest level: the first pre-smoothing sweep that also sums the
+        // incoming iterate's r^2 (LDS tile geometries only)
+        if (l == 0 && L.elem == 8 && c->nrm_fused) {
+            TuneKey kn{dim, 8, n, 0, sm, var ? 1 : 0, 13, 0};
+            if (!tune_lookup(kn, &cfg)) {
+                h.npart = c->d_spart;
+                e = hipMemcpyAsync(d, &h, sizeof(GridDesc), hipMemcpyHostToDevice, s);
+                if (e != hipSuccess) break;
+                std::vector<TileCfg> cands;
+                for (TileCfg t : tune_candidates(dim, n - 2, true, 0, 8, var))
+                    if (t.wv != 1 && smooth_tiles(dim, sm, n, t) <= c->spart_cap) cands.push_back(t);
+                auto run = [&](TileCfg t) { return launch_smooth<double>(dim, sm, var, d, 1, n, 0, SWEEP_NORM, t, s); };
+                cfg = pick_fastest(cands, tl[(size_t)l].smooth_nrm, run, s);
+                cfg = pick_order(cfg, run, s);
+                tune_store(kn, cfg);
+            }
+            tl[(size_t)l].smooth_nrm = cfg;
+        }
         TuneKey kr{dim, L.elem, n, 1, 0, var ? 1 : 0, 0, 0};
         if (!tune_lookup(kr, &cfg)) {
             std::vector<TileCfg> cands;
@@ -1342,7 +1378,23 @@ int mg_setup(const mg_params* p, void* stream, mg_ctx** out) {
     c->h_top.omega = c->p.omega;
     SETUP_CK(hipMalloc((void**)&c->d_top, sizeof(GridDesc)));
     SETUP_CK(hipMemcpyAsync(c->d_top, &c->h_top, sizeof(GridDesc), hipMemcpyHostToDevice, s));
+    // FP64: each cycle's residual norm from the next cycle's first pre-smoothing sweep
+    c->nrm_fused = p->precision == MG_PREC_FP64 && c->nlev >= 2 && p->nu1 >= 1 && c->tail64.first != 0 &&
+                   std::getenv("MG_NO_FUSED_NORM") == nullptr;
+    if (c->nrm_fused) {
+        const int sm = c->prob.smoother;
+        int cap = smooth_tiles(dim, sm, p->n, c->tl64[0].smooth_nrm);
+        for (TileCfg t : tune_candidates(dim, p->n - 2, true, 0, 8, c->prob.var))
+            if (t.wv != 1) cap = std::max(cap, smooth_tiles(dim, sm, p->n, t));
+        c->spart_cap = cap;
+        SETUP_CK(hipMalloc((void**)&c->d_spart, sizeof(double) * (size_t)cap));
+        GridDesc& d0 = c->G64[0].h[0];
+        d0.npart = c->d_spart;
+        SETUP_CK(hipMemcpyAsync(c->G64[0].d, &d0, sizeof(GridDesc), hipMemcpyHostToDevice, s));
+    }
     if (c->autotune) SETUP_CK(autotune(c));
+    if (c->nrm_fused && smooth_tiles(dim, c->prob.smoother, p->n, c->tl64[0].smooth_nrm) > c->spart_cap)
+        c->nrm_fused = false;
     c->pstride = std::max(1, norm_tiles(dim, p->n, c->top.norm));
     SETUP_CK(hipMalloc((void**)&c->d_partial, sizeof(double) * (size_t)c->pstride));
     if (is_h16(c->p)) {
@@ -1377,7 +1429,7 @@ int mg_num_levels(const mg_ctx* c) {
 
 int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch, int* waves,
                    int* order, int* pairs) {
-    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 5)
+    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 6)
         return MG_EINVAL;
     if (c->cc || c->st || c->cd) return MG_ENOTSUP;  // plain kernels, no tiles
     const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
@@ -1387,8 +1439,17 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
                       : family == 2 ? c->top.norm
                       : family == 3 ? tv.smooth_zg
                       : family == 4 ? tv.smooth_pro
-                                    : tv.fused;
-    if (family == 2 && level != 0) return MG_EINVAL;
+                      : family == 5 ? tv.fused
+                                    : tv.smooth_nrm;
+    if ((family == 2 || family == 6) && level != 0) return MG_EINVAL;
+    if (family == 6 && !c->nrm_fused) {  // the norm is a pass of its own
+        *by = *zchunk = 0;
+        if (prefetch) *prefetch = 0;
+        if (waves) *waves = 0;
+        if (order) *order = 0;
+        if (pairs) *pairs = 0;
+        return MG_OK;
+    }
     *by = t.by;
     *zchunk = t.zchunk;
     if (prefetch) *prefetch = t.pd;
@@ -1482,6 +1543,7 @@ int mg_solve(mg_ctx* c, double* u, const double* f, double tol, int max_cycles, 
     // rho_0 (clear the stop flag a previous solve left set first: every kernel honours it)
     CK(launch_fill_int(ctl_done(c), 0, 1, s));
     if (ir) CK(enqueue_ir_start(c, s));
+    else if (c->nrm_fused) CK(enqueue_nrm_sweep(c, s));
     else CK(enqueue_norm(c, s));
     CK(launch_solve_init(c->d_norm, c->d_norm0, ctl_done(c), ctl_steps(c), ctl_status(c), c->d_hist, c->hist_cap, 1,
                          s));

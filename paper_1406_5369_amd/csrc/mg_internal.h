@@ -45,6 +45,9 @@ enum Smoother { SM_RBGS = 0, SM_JACOBI = 1 };
 enum SweepFlags {
     SWEEP_ZERO_GUESS = 1,  // the incoming iterate is identically zero: read nothing
     SWEEP_PROLONG = 2,     // incoming iterate is u + P uc (coarse-grid correction fused into the load)
+    SWEEP_NORM = 4,        // FP64 Laplacian / coefficient-field sweeps of an LDS tile geometry: also sum
+                           // r^2 = (f - A u)^2 of the incoming iterate over the tile's output nodes
+                           // into npart[blockIdx.x] (one partial per workgroup)
 };
 
 // One grid at one level, as the kernels see it.  All pointers are device
@@ -67,6 +70,8 @@ struct GridDesc {
     double c;         // 1/h^2
     double wd;        // omega*h^2/(2d)
     double omega;     // smoother weight
+    double* npart;    // SWEEP_NORM: per-workgroup partial sums of r^2 (as many as the launch has
+                      // workgroups in x), or null
 };
 
 // FP64 refinement pass of one grid: u_out = u_in + e (inner nodes),

@@ -13,6 +13,9 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
     using T = arith_t<ST>;  // arithmetic type; ST is the storage type of u, f and the coarse correction
     static_assert(!VAR || sizeof(ST) == sizeof(T), "coefficient fields are stored in the arithmetic type");
     constexpr int flags = FL;
+    // SWEEP_NORM: also sum r^2 of the incoming iterate over the tile's output nodes
+    constexpr bool NRM = (FL & SWEEP_NORM) != 0;
+    static_assert(!NRM || sizeof(T) == 8, "the sweep's norm sums FP64 residuals");
     const GridDesc d = descs[blockIdx.y];
     if (d.done && *gp(d.done)) return;
     constexpr int H = SM == SM_RBGS ? 2 : 1;
@@ -80,6 +83,7 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
         fr[m] = (inn && lane1 && ly >= 1 && ly <= BY - 2) ? f[p] : T(0);
     }
     __syncthreads();
+    [[maybe_unused]] double nacc = 0.0;
     if constexpr (SM == SM_RBGS) {
         // first colour (red unless black first) on the tile plus a one-node ring
 #pragma unroll
@@ -88,10 +92,21 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
             if (lane1 && ly >= 1 && ly <= BY - 2) {
                 const bool inn = coli && gy >= 1 && gy <= n - 2;
                 T v = U[ly][lane];
-                if (inn && ((gx + gy) & 1) == cfirst) {
-                    T ds;
-                    const T r = lds_res2<T, VAR>(U, K, ly, lane, fr[m], c, ds);
-                    v = stored<ST>(relax<T, VAR>(v, r, ds, c, wd, om));
+                if constexpr (NRM) {
+                    // residual of both colours on the incoming values; summed over the output nodes
+                    if (inn) {
+                        T ds;
+                        const T r = lds_res2<T, VAR>(U, K, ly, lane, fr[m], c, ds);
+                        if (((gx + gy) & 1) == cfirst) v = stored<ST>(relax<T, VAR>(v, r, ds, c, wd, om));
+                        if (lane >= 2 && lane <= BX - 3 && ly >= 2 && ly <= BY - 3 && gx <= n - 2 && gy <= n - 2)
+                            nacc += r * r;
+                    }
+                } else {
+                    if (inn && ((gx + gy) & 1) == cfirst) {
+                        T ds;
+                        const T r = lds_res2<T, VAR>(U, K, ly, lane, fr[m], c, ds);
+                        v = stored<ST>(relax<T, VAR>(v, r, ds, c, wd, om));
+                    }
                 }
                 R[ly][lane] = v;
             }
@@ -118,9 +133,15 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
             if (lane1 && ly >= 1 && ly <= BY - 2 && gx <= n - 2 && gy <= n - 2) {
                 T ds;
                 const T r = lds_res2<T, VAR>(U, K, ly, lane, fr[m], c, ds);
+                if constexpr (NRM) nacc += r * r;
                 uout[(size_t)gy * n + gx] = (ST)relax<T, VAR>(U[ly][lane], r, ds, c, wd, om);
             }
         }
+    }
+    if constexpr (NRM) {
+        __shared__ double red4[4];
+        const double tot = block_sum(nacc, red4);
+        if (threadIdx.x == 0) gp(d.npart)[blockIdx.x] = tot;
     }
 }
 
@@ -140,6 +161,9 @@ hipError_t launch_smooth2d(int sm, bool var, const GridDesc* d, int sel, int fla
         case 0: return launch_smooth2d_fl<T, SMV, VARV, 0>(d, sel, cfg, grid, s);                           \
         case SWEEP_ZERO_GUESS: return launch_smooth2d_fl<T, SMV, VARV, SWEEP_ZERO_GUESS>(d, sel, cfg, grid, s); \
         case SWEEP_PROLONG: return launch_smooth2d_fl<T, SMV, VARV, SWEEP_PROLONG>(d, sel, cfg, grid, s);   \
+        case SWEEP_NORM:                                                                                   \
+            if constexpr (sizeof(T) == 8) return launch_smooth2d_fl<T, SMV, VARV, SWEEP_NORM>(d, sel, cfg, grid, s); \
+            return hipErrorInvalidValue;                                                                   \
         default: return hipErrorInvalidValue;                                                              \
     }
     if constexpr (sizeof(T) == 2) {  // binary16 storage: Laplacian only

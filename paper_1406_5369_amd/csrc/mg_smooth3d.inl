@@ -46,6 +46,8 @@ struct Smooth3D {
     static_assert(RPT >= 1 && RPT * WV == BY, "tile rows must be a multiple of the wavefronts");
 
     static constexpr bool PRO = (FL & SWEEP_PROLONG) != 0;
+    static constexpr bool NRM = (FL & SWEEP_NORM) != 0;
+    static_assert(!NRM || sizeof(T) == 8, "the sweep's norm sums FP64 residuals");
 
     T (*U)[BY][BX];   // old u of recent planes (y-neighbour exchange)
     T (*R)[BY][BX];   // red-updated u of recent planes
@@ -69,6 +71,7 @@ struct Smooth3D {
     // the node, and the +z face (to the plane above; set one step after the
     // plane enters, when the +z face of the plane three below is no longer read)
     T fxc[VAR ? 3 : 1][RPT], fys[VAR ? 3 : 1][RPT], fyn[VAR ? 3 : 1][RPT], fzc[VAR ? 3 : 1][RPT];
+    double nacc;  // SWEEP_NORM: this thread's sum of r^2 of the incoming iterate over its output nodes
 
     __device__ __forceinline__ int gy(int m) const { return y0 - H + w + WV * m; }
 
@@ -212,17 +215,22 @@ struct Smooth3D {
     // QC / QB: ring slots of the node's plane and of the plane below (faces);
     // kxw: the -x face, from the neighbouring lane (taken with every lane active)
     template <int QC, int QB>
-    __device__ __forceinline__ T relax_at(const T (*A)[BX], T uc, T ub, T ua, T uw, T ue, int ly, int m, T kxw,
-                                          T fv) const {
-        T ds, r;
+    __device__ __forceinline__ T res_at(const T (*A)[BX], T uc, T ub, T ua, T uw, T ue, int ly, int m, T kxw, T fv,
+                                        T& ds) const {
         const T uS = A[ly - 1][lane], uN = A[ly + 1][lane];
         if constexpr (VAR) {
-            r = res_var3f(uc, uw, ue, uS, uN, ub, ua, kxw, fxc[QC][m], fys[QC][m], fyn[QC][m], fzc[QB][m],
-                          fzc[QC][m], fv, c, ds);
+            return res_var3f(uc, uw, ue, uS, uN, ub, ua, kxw, fxc[QC][m], fys[QC][m], fyn[QC][m], fzc[QB][m],
+                             fzc[QC][m], fv, c, ds);
         } else {
             ds = T(0);
-            r = res_lap3(uc, uw, ue, uS, uN, ub, ua, fv, c);
+            return res_lap3(uc, uw, ue, uS, uN, ub, ua, fv, c);
         }
+    }
+    template <int QC, int QB>
+    __device__ __forceinline__ T relax_at(const T (*A)[BX], T uc, T ub, T ua, T uw, T ue, int ly, int m, T kxw,
+                                          T fv) const {
+        T ds;
+        const T r = res_at<QC, QB>(A, uc, ub, ua, uw, ue, ly, m, kxw, fv, ds);
         return relax<T, VAR>(uc, r, ds, c, wd, om);
     }
 
@@ -269,8 +277,21 @@ struct Smooth3D {
                     const T uw = lane_prev(uc), ue = lane_next(uc);
                     const T kxw = VAR ? lane_prev(fxc[VAR ? S1 : 0][m]) : T(0);
                     T v = uc;
-                    if (zin && ((mring >> m) & (minner >> m) & 1u) && ((gx + y + m1) & 1) == cfirst)
-                        v = stored<ST>(relax_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m]));
+                    if constexpr (NRM) {
+                        // the residual of every node of the relaxed region on the
+                        // incoming values; summed over the output nodes
+                        if (zin && ((mring >> m) & (minner >> m) & 1u)) {
+                            T ds;
+                            const T r = res_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw,
+                                                       fr[S1][m], ds);
+                            if (((gx + y + m1) & 1) == cfirst) v = stored<ST>(relax<T, VAR>(uc, r, ds, c, wd, om));
+                            if (m1 >= z0 && m1 < z1 && ((mtile >> m) & 1u)) nacc += r * r;
+                        }
+                    } else {
+                        if (zin && ((mring >> m) & (minner >> m) & 1u) && ((gx + y + m1) & 1) == cfirst)
+                            v = stored<ST>(
+                                relax_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m]));
+                    }
                     ro[S1][m] = v;
                     R[S1][ly][lane] = v;
                 }
@@ -302,9 +323,12 @@ struct Smooth3D {
                     const T uc = uo[S1][m];
                     const T uw = lane_prev(uc), ue = lane_next(uc);
                     const T kxw = VAR ? lane_prev(fxc[VAR ? S1 : 0][m]) : T(0);
-                    if (((mring >> m) & (minner >> m) & 1u))
-                        st_off(uout + (size_t)m1 * pl + rowoff(m), xb,
-                               (ST)relax_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m]));
+                    if (((mring >> m) & (minner >> m) & 1u)) {
+                        T ds;
+                        const T r = res_at<S1, S2>(U[S1], uc, uo[S2][m], uo[S0][m], uw, ue, ly, m, kxw, fr[S1][m], ds);
+                        if constexpr (NRM) nacc += r * r;
+                        st_off(uout + (size_t)m1 * pl + rowoff(m), xb, (ST)relax<T, VAR>(uc, r, ds, c, wd, om));
+                    }
                 }
             }
         }
@@ -388,7 +412,14 @@ __global__ __launch_bounds__(64 * WV) void k_smooth3d(const GridDesc* __restrict
     s.colg = s.gx >= 0 && s.gx < n;
     s.coli = s.gx >= 1 && s.gx <= n - 2;
     s.lane1 = s.lane >= 1 && s.lane <= BX - 2;
+    s.nacc = 0.0;
     s.run();
+    if constexpr (S::NRM) {
+        // per-workgroup partial in a fixed order (finalised in block order)
+        __shared__ double red[WV];
+        const double tot = block_sum_w<WV>(s.nacc, red);
+        if (threadIdx.x == 0) gp(d.npart)[blockIdx.x] = tot;
+    }
 }
 
 }  // namespace
@@ -417,13 +448,16 @@ hipError_t launch_smooth3d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid
     constexpr bool wide = sizeof(arith_t<T>) == 4 && !VARV;
     constexpr bool fp64var = sizeof(arith_t<T>) == 8 && VARV;  // two rows per thread at most
     if (cfg.wv == 1) {  // one wavefront per tile, rows in registers: 8 rows, or 12 in FP32 without coefficients
-        if constexpr (sizeof(arith_t<T>) == 8 && VARV) return hipErrorInvalidValue;
-        switch (cfg.by) {
-            case 8: return launch_smooth3d_rc<T, SMV, VARV, FL, 8>(d, sel, cfg, grid, s);
-            case 12:
-                if constexpr (wide) return launch_smooth3d_rc<T, SMV, VARV, FL, 12>(d, sel, cfg, grid, s);
-                return hipErrorInvalidValue;
-            default: return hipErrorInvalidValue;
+        if constexpr ((sizeof(arith_t<T>) == 8 && VARV) || (FL & SWEEP_NORM) != 0) {
+            return hipErrorInvalidValue;
+        } else {
+            switch (cfg.by) {
+                case 8: return launch_smooth3d_rc<T, SMV, VARV, FL, 8>(d, sel, cfg, grid, s);
+                case 12:
+                    if constexpr (wide) return launch_smooth3d_rc<T, SMV, VARV, FL, 12>(d, sel, cfg, grid, s);
+                    return hipErrorInvalidValue;
+                default: return hipErrorInvalidValue;
+            }
         }
     }
     if (cfg.wv == 4) {
@@ -458,6 +492,9 @@ hipError_t launch_smooth3d(int sm, bool var, const GridDesc* d, int sel, int fla
         case 0: return launch_smooth3d_fl<T, SMV, VARV, 0>(d, sel, cfg, grid, s);                           \
         case SWEEP_ZERO_GUESS: return launch_smooth3d_fl<T, SMV, VARV, SWEEP_ZERO_GUESS>(d, sel, cfg, grid, s); \
         case SWEEP_PROLONG: return launch_smooth3d_fl<T, SMV, VARV, SWEEP_PROLONG>(d, sel, cfg, grid, s);       \
+        case SWEEP_NORM:                                                                                   \
+            if constexpr (sizeof(T) == 8) return launch_smooth3d_fl<T, SMV, VARV, SWEEP_NORM>(d, sel, cfg, grid, s); \
+            return hipErrorInvalidValue;                                                                   \
         default: return hipErrorInvalidValue;                                                              \
     }
     if constexpr (sizeof(T) == 2) {  // binary16 storage: Laplacian only

@@ -24,7 +24,11 @@ struct Tiles {
     // Laplacian RBGS, FP32 / binary16): zchunk coarse planes per workgroup,
     // 0 = separate sweep and restriction (the autotuner's choice)
     TileCfg fused{16, 0};
+    // FP64 finest level: the first pre-smoothing sweep that also sums r^2 of
+    // its incoming iterate (an LDS tile geometry)
+    TileCfg smooth_nrm{16, 128, 1, 8};
     const TileCfg& sweep(int flags) const {
+        if (flags & SWEEP_NORM) return smooth_nrm;
         return (flags & SWEEP_ZERO_GUESS) ? smooth_zg : ((flags & SWEEP_PROLONG) ? smooth_pro : smooth);
     }
 };
@@ -81,9 +85,12 @@ int tail_first_level(int dim, int elem, const std::vector<int>& n, bool zero_top
 
 // V-cycle over groups[0..L-1] (groups[l] holds every instance's level l);
 // zero_top: the iterate at level 0 is known to be zero.  Works in precision T.
+// first_done: level 0's first pre-smoothing sweep has already run (its result
+// is in the ping-pong partner t; the cycle continues from the second sweep).
 template <typename T>
 hipError_t vcycle(const Problem& P, const std::vector<Group>& groups, bool zero_top, const std::vector<Tiles>& tiles,
-                  hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap, const TailPlan* tail = nullptr);
+                  hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap, const TailPlan* tail = nullptr,
+                  bool first_done = false);
 
 size_t npts(int dim, int n);
 int count_levels(int n);
@@ -127,6 +134,11 @@ struct mg_ctx {
     // solve control (one instance)
     double* d_partial = nullptr;
     int pstride = 0;
+    // FP64 solves: the residual norm of each cycle's result is summed by the
+    // next cycle's first pre-smoothing sweep (one partial per workgroup of it)
+    bool nrm_fused = false;
+    double* d_spart = nullptr;
+    int spart_cap = 0;
     double* d_norm = nullptr;   // [1]
     double* d_norm0 = nullptr;  // [1]
     double* d_hist = nullptr;

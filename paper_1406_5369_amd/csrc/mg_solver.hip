@@ -34,14 +34,15 @@ Tiles default_tiles(int dim, int elem_bytes, int n, int smoother) {
     const int target = 2048;
     if (dim == 2) {
         const int by = n >= 257 ? 32 : (n >= 65 ? 16 : 8);
-        t.smooth = t.smooth_zg = t.smooth_pro = {by, 1};
+        t.smooth = t.smooth_zg = t.smooth_pro = t.smooth_nrm = {by, 1};
         t.restr = {by < 16 ? 16 : by, 1};
         t.norm = {by, 1};
         return t;
     }
     // two rows per thread: within the register limit of every precision
     const int by = n >= 129 ? 16 : 8;
-    t.smooth = t.smooth_zg = t.smooth_pro = {by, heuristic_zchunk(3, n, by, H, target), 1, by >= 16 ? 8 : 4};
+    t.smooth = t.smooth_zg = t.smooth_pro = t.smooth_nrm = {by, heuristic_zchunk(3, n, by, H, target), 1,
+                                                           by >= 16 ? 8 : 4};
     const int nc = (n - 1) / 2 + 1;
     const int rb = 16;
     // restriction tiles: 30 x ((rb-3)/2) coarse nodes per z-chunk of coarse planes
@@ -60,6 +61,7 @@ template <typename T>
 hipError_t launch_smooth(int dim, int sm, bool var, const GridDesc* d, int ninst, int n, int sel, int flags,
                          TileCfg cfg, hipStream_t s) {
     if (n < 5 || ninst <= 0) return hipErrorInvalidValue;
+    if ((flags & SWEEP_NORM) && ninst != 1) return hipErrorInvalidValue;  // one partial row
     const dim3 grid(smooth_tiles(dim, sm, n, cfg), ninst);
     const hipError_t e = dim == 2 ? launch_smooth2d<T>(sm, var, d, sel, flags, cfg, grid, s)
                                   : launch_smooth3d<T>(sm, var, d, sel, flags, cfg, grid, s);
@@ -132,13 +134,13 @@ inline int post_sel(const Problem& P, int cur) { return cur | (P.sym ? SEL_BLACK
 // left.  Level by level (no coarse tail).
 template <typename T>
 hipError_t cycle_rec(const Problem& P, const std::vector<Group>& G, int l, int kind, bool zero,
-                     const std::vector<Tiles>& tiles, hipStream_t s, Prof& prof) {
+                     const std::vector<Tiles>& tiles, hipStream_t s, Prof& prof, bool first_done = false) {
     const int L = (int)G.size();
     const int dim = P.dim;
     const Group& g = G[(size_t)l];
     if (l == L - 1) return coarse_solve<T>(P, g, s);
-    int cur = 0;
-    for (int i = 0; i < P.nu1; ++i) {
+    int cur = first_done ? 1 : 0;
+    for (int i = first_done ? 1 : 0; i < P.nu1; ++i) {
         const int flags = (i == 0 && zero) ? SWEEP_ZERO_GUESS : 0;
         const bool timed = l == 0 && flags == 0;
         if (timed) prof.begin();
@@ -175,14 +177,18 @@ hipError_t cycle_rec(const Problem& P, const std::vector<Group>& G, int l, int k
 
 template <typename T>
 hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, const std::vector<Tiles>& tiles,
-                  hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap, const TailPlan* tail) {
+                  hipStream_t s, hipEvent_t* prof_ev, int* prof_n, int prof_cap, const TailPlan* tail,
+                  bool first_done) {
     const int L = (int)G.size();
     const int dim = P.dim;
     Prof prof{prof_ev, prof_n, prof_cap, s};
-    if (P.cycle != 0) return cycle_rec<T>(P, G, 0, P.cycle, zero_top, tiles, s, prof);
+    // a first sweep that already ran needs a level-0 pre-smoothing sweep to have been
+    if (first_done && (L < 2 || P.nu1 < 1 || zero_top)) return hipErrorInvalidValue;
+    if (P.cycle != 0) return cycle_rec<T>(P, G, 0, P.cycle, zero_top, tiles, s, prof, first_done);
     const bool use_tail = tail && tail->first >= 0 && tail->first < L && tail->d;
     // levels [0, stop) run level by level; the rest is the tail (or the coarsest solve)
     const int stop = use_tail ? tail->first : L - 1;
+    if (first_done && stop == 0) return hipErrorInvalidValue;
     if (stop == 0 && !use_tail) return coarse_solve<T>(P, G[0], s);
     std::vector<int> sel((size_t)L, 0);
     // descending leg: presmoothing, residual, restriction (Algorithm 1)
@@ -191,8 +197,9 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
         const bool zero = l == 0 ? zero_top : true;
         // the last sweep may carry the residual and restriction (a plain red-first sweep)
         const bool fuse = fused_restrict_ok<T>(P, dim, tiles[(size_t)l]) && P.nu1 >= (zero ? 2 : 1);
-        int cur = 0;
-        for (int i = 0; i < P.nu1; ++i) {
+        const bool skip1 = l == 0 && first_done;
+        int cur = skip1 ? 1 : 0;
+        for (int i = skip1 ? 1 : 0; i < P.nu1; ++i) {
             const int flags = (i == 0 && zero) ? SWEEP_ZERO_GUESS : 0;
             if (fuse && i == P.nu1 - 1) {
                 MG_TRY(launch_smooth_restrict3d<T>(g.d, g.ninst, g.n, cur, tiles[(size_t)l].fused, s));
@@ -238,10 +245,10 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
 }
 
 template hipError_t vcycle<double>(const Problem&, const std::vector<Group>&, bool, const std::vector<Tiles>&,
-                                   hipStream_t, hipEvent_t*, int*, int, const TailPlan*);
+                                   hipStream_t, hipEvent_t*, int*, int, const TailPlan*, bool);
 template hipError_t vcycle<float>(const Problem&, const std::vector<Group>&, bool, const std::vector<Tiles>&,
-                                  hipStream_t, hipEvent_t*, int*, int, const TailPlan*);
+                                  hipStream_t, hipEvent_t*, int*, int, const TailPlan*, bool);
 template hipError_t vcycle<half_t>(const Problem&, const std::vector<Group>&, bool, const std::vector<Tiles>&,
-                                   hipStream_t, hipEvent_t*, int*, int, const TailPlan*);
+                                   hipStream_t, hipEvent_t*, int*, int, const TailPlan*, bool);
 
 }  // namespace mg

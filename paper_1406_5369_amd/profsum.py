@@ -47,16 +47,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def sweep_kernel(dim: int, word: int, by: int, pd: int, var: bool = False, wv: int = 4) -> str:
-    """Demangled name of a plain (not zero-guess, no fused correction) RBGS
-    sweep with the given tile height, prefetch depth and wavefronts."""
+def sweep_kernel(dim: int, word: int, by: int, pd: int, var: bool = False, wv: int = 4, flags: int = 0) -> str:
+    """Demangled name of an RBGS sweep with the given tile height, prefetch
+    depth and wavefronts: plain (flags 0), or with flags 4 the FP64 sweep that
+    also sums the residual norm of its incoming iterate."""
     t = {2: "_Float16", 4: "float", 8: "double"}[word]
     v = "true" if var else "false"
     if dim == 2:
-        return f"mg::k_smooth2d<{t}, 0, {v}, {by}, 0>"
+        return f"mg::k_smooth2d<{t}, 0, {v}, {by}, {flags}>"
     if wv == 1:  # one wavefront per tile, rows in registers
-        return f"mg::k_smooth3d_rc<{t}, 0, {v}, {by}, {pd}, 0>"
-    return f"mg::k_smooth3d<{t}, 0, {v}, {by}, {pd}, 0, {wv}>"
+        return f"mg::k_smooth3d_rc<{t}, 0, {v}, {by}, {pd}, {flags}>"
+    return f"mg::k_smooth3d<{t}, 0, {v}, {by}, {pd}, {flags}, {wv}>"
 
 
 def pass_kernel(dim: int, by: int, pd: int, var: bool = False, ir: bool = True, wv: int = 4, pairs: int = 0,

@@ -38,3 +38,5 @@ def test_kernel_names():
     assert profsum.sweep_kernel(3, 4, 8, 2, wv=1) == "mg::k_smooth3d_rc<float, 0, false, 8, 2, 0>"
     assert profsum.sweep_kernel(3, 8, 32, 1, wv=8) == "mg::k_smooth3d<double, 0, false, 32, 1, 0, 8>"
     assert profsum.sweep_kernel(3, 2, 16, 2, wv=8) == "mg::k_smooth3d<_Float16, 0, false, 16, 2, 0, 8>"
+    assert profsum.sweep_kernel(3, 8, 16, 2, wv=8, flags=4) == "mg::k_smooth3d<double, 0, false, 16, 2, 4, 8>"
+    assert profsum.sweep_kernel(2, 8, 32, 1, flags=4) == "mg::k_smooth2d<double, 0, false, 32, 4>"
