@@ -165,7 +165,9 @@ int mg_num_levels(const mg_ctx* ctx);
  * the sweep and the restriction apart, 6 (level 0 of an FP64 context) the
  * first pre-smoothing sweep that also sums the residual norm of its incoming
  * iterate, which in mg_solve gives each cycle's norm (Section 2.4's L2
- * residual; every field 0 when the norm is a pass of its own)): tile rows
+ * residual; every field 0 when the norm is a pass of its own), 7 the first
+ * two pre-smoothing sweeps from a zero iterate in one launch (mg_level_
+ * smooth2_zero; *zchunk 0 when the level runs them apart)): tile rows
  * *by, z-chunk *zchunk (3D planes per workgroup), for 3D
  * marching kernels *prefetch = planes of u loaded ahead (1 or 2), *waves =
  * wavefronts per workgroup (4; 1 or 8 for 3D smoothing and the 3D pass), for
@@ -233,6 +235,17 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
  * kernels it replaces.  Synchronises the stream. */
 int mg_level_smooth_restrict(int dim, int n, int dtype, const void* u_in, const void* f, void* u_out, void* fc,
                              int zchunk, int order, void* stream);
+/* The first two pre-smoothing sweeps of a level whose iterate starts at zero
+ * (Algorithm 1: presmoothing from the zero coarse-grid guess), fused, 3D
+ * Laplacian, dtype 1 (FP32) or 2 (binary16), omega 1: two red-first
+ * red-black sweeps from u = 0, the result in u_out (inner nodes; f != u_out),
+ * bit for bit mg_level_smooth with zero_guess followed by mg_level_smooth.
+ * by: 12 or 16 rows per tile (the tile writes (64 - 6) x (by - 6) nodes per
+ * plane); zchunk: planes per workgroup (>= 1); order: 0 XCD bands, 1 linear
+ * block order.  The solver uses it in V-cycles where the autotuner times it
+ * faster than the two sweeps it replaces.  Synchronises the stream. */
+int mg_level_smooth2_zero(int dim, int n, int dtype, const void* f, void* u_out, int by, int zchunk, int order,
+                          void* stream);
 /* Conjugate gradients on a coarsest grid of n = 2^c + 1 nodes per axis
  * (mg_params.coarse_n): 'iters' steps (0: 4 (n - 1)) from u = 0 on A u = f;
  * u's boundary is written with zeros.  n at most 33 (2D) / 9 (3D) for dtype 0,

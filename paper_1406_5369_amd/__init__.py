@@ -112,6 +112,7 @@ def lib():
             "mg_level_prolong_correct": (i, [i, i, i, p, p, p]),
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
             "mg_level_smooth_restrict": (i, [i, i, i, p, p, p, p, i, i, p]),
+            "mg_level_smooth2_zero": (i, [i, i, i, p, p, i, i, i, p]),
             "mg_level_coarsest_cg": (i, [i, i, i, p, p, p, i, p]),
             "mg_cdiff_setup": (i, [C.POINTER(_CDiffParams), p, C.POINTER(p)]),
             "mg_cdiff_fas": (i, [p, p, p]),
@@ -299,7 +300,8 @@ def mg_tile_config(ctx: int, level: int, family: int, with_order: bool = False):
     """(by, zchunk, prefetch, waves) used on a level by a kernel family (0 smooth, 1 restrict, 2 norm,
     3 smooth from a zero iterate, 4 smooth with the fused coarse-grid correction, 5 last pre-smoothing
     sweep fused with the restriction, 6 FP64 first pre-smoothing sweep that also sums the residual norm,
-    all 0 when the norm is a pass of its own); with_order adds the block order (0 XCD bands, 1 linear)
+    all 0 when the norm is a pass of its own, 7 the first two pre-smoothing sweeps from a zero iterate in
+    one launch, zchunk 0 when they run apart); with_order adds the block order (0 XCD bands, 1 linear)
     and the pairs flag (3D pass with two nodes per lane)."""
     by, zc, pd, wv, od, xp = (C.c_int(0) for _ in range(6))
     _check(lib().mg_tile_config(ctx, level, family, C.byref(by), C.byref(zc), C.byref(pd), C.byref(wv),
@@ -379,6 +381,15 @@ def mg_level_smooth_restrict(u_in, f, u_out, fc, zchunk=4, order=0, stream=None)
                                           _dptr(f, dt, f.shape, "f"), _dptr(u_out, dt, f.shape, "u_out"),
                                           _dptr(fc, dt, (nc,) * dim, "fc"), int(zchunk), int(order),
                                           _stream(stream)), "mg_level_smooth_restrict")
+
+
+def mg_level_smooth2_zero(f, u_out, by=12, zchunk=16, order=0, stream=None) -> None:
+    """The first two red-first pre-smoothing sweeps from a zero iterate, fused (3D, float32 or float16)."""
+    dim, n = f.dim(), f.shape[0]
+    dt = f.dtype
+    _check(lib().mg_level_smooth2_zero(dim, n, _dtype_code(f), _dptr(f, dt, f.shape, "f"),
+                                       _dptr(u_out, dt, f.shape, "u_out"), int(by), int(zchunk), int(order),
+                                       _stream(stream)), "mg_level_smooth2_zero")
 
 
 def mg_level_prolong_correct(u, ec, stream=None) -> None:

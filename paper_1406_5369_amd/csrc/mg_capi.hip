@@ -1102,6 +1102,41 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
             tl[(size_t)l].fused = cfg;
             if (cfg.zchunk < 0) tl[(size_t)l].fused.zchunk = std::getenv("MG_FUSED_RESTRICT") ? -cfg.zchunk : 0;
         }
+        // the first two pre-smoothing sweeps from a zero iterate in one launch,
+        // kept if it beats the two sweeps it replaces
+        if (dim == 3 && !var && sm == SM_RBGS && L.elem <= 4 && c->p.nu1 >= 2) {
+            TuneKey k2{dim, L.elem, n, 6, sm, 0, 0, 0};
+            if (!tune_lookup(k2, &cfg)) {
+                std::vector<TileCfg> cands;
+                for (int by : {12, 16})
+                    for (int zc = 8; zc <= 128 && zc <= std::max(8, n - 2); zc *= 2)
+                        for (int order : {0, 1}) {
+                            TileCfg t{by, zc};
+                            t.order = order;
+                            cands.push_back(t);
+                        }
+                auto run2 = [&](TileCfg t) {
+                    return L.elem == 4 ? launch_smooth3d_zg2<float>(d, 1, n, 1, t, s)
+                                       : launch_smooth3d_zg2<half_t>(d, 1, n, 1, t, s);
+                };
+                TileCfg best = pick_fastest(cands, cands[0], run2, s);
+                const float t_two = time_launch(run2, best, s);
+                const TileCfg zg = tl[(size_t)l].smooth_zg, sw = tl[(size_t)l].smooth;
+                const float t_sep = time_launch([&](TileCfg) {
+                    if (L.elem == 4) {
+                        (void)launch_smooth<float>(dim, sm, false, d, 1, n, 0, SWEEP_ZERO_GUESS, zg, s);
+                        return launch_smooth<float>(dim, sm, false, d, 1, n, 1, 0, sw, s);
+                    }
+                    (void)launch_smooth<half_t>(dim, sm, false, d, 1, n, 0, SWEEP_ZERO_GUESS, zg, s);
+                    return launch_smooth<half_t>(dim, sm, false, d, 1, n, 1, 0, sw, s);
+                }, sw, s);
+                cfg = best;
+                if (!(t_two < t_sep)) cfg.zchunk = -best.zchunk;  // declined (depth kept for forcing)
+                tune_store(k2, cfg);
+            }
+            tl[(size_t)l].smooth_zg2 = cfg;
+            if (cfg.zchunk < 0) tl[(size_t)l].smooth_zg2.zchunk = std::getenv("MG_FUSED_SMOOTH2") ? -cfg.zchunk : 0;
+        }
     }
     hipError_t e2 = hipStreamSynchronize(s);
     (void)hipFree(d);
@@ -1429,7 +1464,7 @@ int mg_num_levels(const mg_ctx* c) {
 
 int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch, int* waves,
                    int* order, int* pairs) {
-    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 6)
+    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 7)
         return MG_EINVAL;
     if (c->cc || c->st || c->cd) return MG_ENOTSUP;  // plain kernels, no tiles
     const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
@@ -1440,7 +1475,8 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
                       : family == 3 ? tv.smooth_zg
                       : family == 4 ? tv.smooth_pro
                       : family == 5 ? tv.fused
-                                    : tv.smooth_nrm;
+                      : family == 6 ? tv.smooth_nrm
+                                    : tv.smooth_zg2;
     if ((family == 2 || family == 6) && level != 0) return MG_EINVAL;
     if (family == 6 && !c->nrm_fused) {  // the norm is a pass of its own
         *by = *zchunk = 0;
@@ -1754,6 +1790,30 @@ int mg_level_smooth_restrict(int dim, int n, int dtype, const void* u_in, const 
     cfg.order = order;
     const hipError_t e = elem == 4 ? launch_smooth_restrict3d<float>(d, 1, n, 0, cfg, s)
                                    : launch_smooth_restrict3d<half_t>(d, 1, n, 0, cfg, s);
+    return finish_desc(d, s, e);
+}
+
+int mg_level_smooth2_zero(int dim, int n, int dtype, const void* f, void* u_out, int by, int zchunk, int order,
+                          void* stream) {
+    const int elem = dtype_elem(dtype);
+    if (dim != 3 || !valid_edge(dim, n) || n < 5 || (elem != 4 && elem != 2)) return MG_EINVAL;
+    if (!f || !u_out || f == u_out || (by != 12 && by != 16) || zchunk < 1 || (order != 0 && order != 1))
+        return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    GridDesc h{};
+    h.u = u_out;  // the second sweep's output (select 1)
+    h.f = f;
+    h.n = n;
+    h.c = level_c(n);
+    h.wd = level_wd(dim, n, 1.0);
+    h.omega = 1.0;
+    GridDesc* d = nullptr;
+    int r = with_desc(h, s, &d);
+    if (r != MG_OK) return r;
+    TileCfg cfg{by, zchunk};
+    cfg.order = order;
+    const hipError_t e = elem == 4 ? launch_smooth3d_zg2<float>(d, 1, n, 1, cfg, s)
+                                   : launch_smooth3d_zg2<half_t>(d, 1, n, 1, cfg, s);
     return finish_desc(d, s, e);
 }
 

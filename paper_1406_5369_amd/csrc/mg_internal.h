@@ -125,6 +125,7 @@ inline int sweep_arg(int sel, const TileCfg& c) { return (sel & (1 | SEL_BLACK_F
 int smooth_tiles(int dim, int sm, int n, TileCfg cfg);
 int restrict_tiles(int dim, int nf, TileCfg cfg);
 int smooth_restrict_tiles(int nf, TileCfg cfg);
+int smooth2_tiles(int n, TileCfg cfg);
 int norm_tiles(int dim, int n, TileCfg cfg);
 
 // Kernel launchers.  'ninst' grids with equal n are processed by one launch
@@ -139,6 +140,12 @@ hipError_t launch_smooth2d(int sm, bool var, const GridDesc* d, int sel, int fla
 template <typename T>
 hipError_t launch_smooth3d(int sm, bool var, const GridDesc* d, int sel, int flags, TileCfg cfg, dim3 grid,
                            hipStream_t s);
+// 3D Laplacian, FP32 or binary16 storage: the first two red-first RBGS
+// pre-smoothing sweeps from a zero iterate in one launch, the second sweep's
+// result written to the output buffer of select 'sel' (1: u); cfg.by 12 or 16
+// rows, cfg.zchunk planes per workgroup, cfg.order the block order.
+template <typename T>
+hipError_t launch_smooth3d_zg2(const GridDesc* d, int ninst, int n, int sel, TileCfg cfg, hipStream_t s);
 // 3D Laplacian, FP32 or binary16 storage: the last red-first RBGS pre-smoothing
 // sweep of input 'sel' fused with the residual of its result and full
 // weighting into fc (cfg.by 16 rows, cfg.zchunk coarse planes per workgroup,

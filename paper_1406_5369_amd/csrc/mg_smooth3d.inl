@@ -2,6 +2,7 @@
 #pragma once
 #include "mg_kern.h"
 #include "mg_smooth3d_rc.inl"
+#include "mg_smooth3d_rc2.inl"
 
 namespace mg {
 namespace {
@@ -511,5 +512,23 @@ hipError_t launch_smooth3d(int sm, bool var, const GridDesc* d, int sel, int fla
 }
 
 template hipError_t launch_smooth3d<MG_T>(int, bool, const GridDesc*, int, int, TileCfg, dim3, hipStream_t);
+
+template <typename T>
+hipError_t launch_smooth3d_zg2(const GridDesc* d, int ninst, int n, int sel, TileCfg cfg, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        return hipErrorInvalidValue;  // built for FP32 and binary16 storage
+    } else {
+        if (n < 5 || ninst <= 0 || cfg.zchunk < 1) return hipErrorInvalidValue;
+        const dim3 grid(smooth2_tiles(n, cfg), ninst);
+        const int arg = sweep_arg(sel, cfg);
+        switch (cfg.by) {
+            case 12: k_smooth3d_zg2<T, 12><<<grid, 64, 0, s>>>(d, arg, cfg.zchunk); break;
+            case 16: k_smooth3d_zg2<T, 16><<<grid, 64, 0, s>>>(d, arg, cfg.zchunk); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+}
+template hipError_t launch_smooth3d_zg2<MG_T>(const GridDesc*, int, int, int, TileCfg, hipStream_t);
 
 }  // namespace mg

@@ -27,6 +27,10 @@ struct Tiles {
     // FP64 finest level: the first pre-smoothing sweep that also sums r^2 of
     // its incoming iterate (an LDS tile geometry)
     TileCfg smooth_nrm{16, 128, 1, 8};
+    // 3D Laplacian red-black, FP32 / binary16: the first two pre-smoothing
+    // sweeps from a zero iterate in one launch (rows 12 or 16, zchunk planes
+    // per workgroup; zchunk 0 = two separate sweeps, the autotuner's choice)
+    TileCfg smooth_zg2{12, 0};
     const TileCfg& sweep(int flags) const {
         if (flags & SWEEP_NORM) return smooth_nrm;
         return (flags & SWEEP_ZERO_GUESS) ? smooth_zg : ((flags & SWEEP_PROLONG) ? smooth_pro : smooth);

@@ -125,6 +125,14 @@ bool fused_restrict_ok(const Problem& P, int dim, const Tiles& t) {
            std::getenv("MG_NO_FUSED_RESTRICT") == nullptr;
 }
 
+// The first two pre-smoothing sweeps from a zero iterate in one launch: 3D
+// Laplacian red-black levels in FP32 or binary16 storage whose tiles chose it.
+template <typename T>
+bool smooth2_ok(const Problem& P, int dim, const Tiles& t, bool zero) {
+    return zero && sizeof(T) <= 4 && dim == 3 && !P.var && P.smoother == SM_RBGS && P.nu1 >= 2 &&
+           t.smooth_zg2.zchunk > 0 && std::getenv("MG_NO_FUSED_SMOOTH2") == nullptr;
+}
+
 // Post-smoothing select bits: the symmetric red-black smoother relaxes black first.
 inline int post_sel(const Problem& P, int cur) { return cur | (P.sym ? SEL_BLACK_FIRST : 0); }
 
@@ -140,7 +148,13 @@ hipError_t cycle_rec(const Problem& P, const std::vector<Group>& G, int l, int k
     const Group& g = G[(size_t)l];
     if (l == L - 1) return coarse_solve<T>(P, g, s);
     int cur = first_done ? 1 : 0;
-    for (int i = first_done ? 1 : 0; i < P.nu1; ++i) {
+    int i0 = first_done ? 1 : 0;
+    if (!first_done && smooth2_ok<T>(P, dim, tiles[(size_t)l], zero)) {
+        // sweeps 1 and 2 from the zero iterate: the result lands in u
+        MG_TRY(launch_smooth3d_zg2<T>(g.d, g.ninst, g.n, 1, tiles[(size_t)l].smooth_zg2, s));
+        i0 = 2;
+    }
+    for (int i = i0; i < P.nu1; ++i) {
         const int flags = (i == 0 && zero) ? SWEEP_ZERO_GUESS : 0;
         const bool timed = l == 0 && flags == 0;
         if (timed) prof.begin();
@@ -196,10 +210,17 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
         const Group& g = G[(size_t)l];
         const bool zero = l == 0 ? zero_top : true;
         // the last sweep may carry the residual and restriction (a plain red-first sweep)
-        const bool fuse = fused_restrict_ok<T>(P, dim, tiles[(size_t)l]) && P.nu1 >= (zero ? 2 : 1);
         const bool skip1 = l == 0 && first_done;
+        // sweeps 1 and 2 from the zero iterate in one launch (result in u)
+        const bool two = !skip1 && smooth2_ok<T>(P, dim, tiles[(size_t)l], zero);
+        const bool fuse = fused_restrict_ok<T>(P, dim, tiles[(size_t)l]) && P.nu1 >= (two ? 3 : (zero ? 2 : 1));
         int cur = skip1 ? 1 : 0;
-        for (int i = skip1 ? 1 : 0; i < P.nu1; ++i) {
+        int i0 = skip1 ? 1 : 0;
+        if (two) {
+            MG_TRY(launch_smooth3d_zg2<T>(g.d, g.ninst, g.n, 1, tiles[(size_t)l].smooth_zg2, s));
+            i0 = 2;
+        }
+        for (int i = i0; i < P.nu1; ++i) {
             const int flags = (i == 0 && zero) ? SWEEP_ZERO_GUESS : 0;
             if (fuse && i == P.nu1 - 1) {
                 MG_TRY(launch_smooth_restrict3d<T>(g.d, g.ninst, g.n, cur, tiles[(size_t)l].fused, s));

@@ -435,6 +435,13 @@ int smooth_tiles(int dim, int sm, int n, TileCfg cfg) {
     return cdiv(m, TX) * cdiv(m, TY) * nzchunks(m, cfg.zchunk);
 }
 
+// Tiles of the two fused pre-smoothing sweeps from a zero iterate: (64 - 6) x
+// (by - 6) nodes per workgroup times z-chunks
+int smooth2_tiles(int n, TileCfg cfg) {
+    const int m = n - 2;
+    return cdiv(m, BX - 6) * cdiv(m, cfg.by - 6) * nzchunks(m, cfg.zchunk);
+}
+
 // Tiles of the fused kernel: coarse nodes per workgroup 28 x (BY-7)/2 times zc planes
 int smooth_restrict_tiles(int nf, TileCfg cfg) {
     const int nc = (nf - 1) / 2 + 1, CX = 28, CY = (cfg.by - 7) / 2;
