@@ -31,12 +31,18 @@ def test_prof_counts_only_steps_the_solve_ran(precision, dev_ok):
     n_sweep, ms_sweep = m.mg_prof_read(s.ctx, 0)
     n_pass, ms_pass = m.mg_prof_read(s.ctx, 1)
     m.mg_prof_enable(s.ctx, False)
-    # V(2,2) plain finest-level sweeps per step: in refinement steps the first
-    # presmoothing sweep starts from a zero iterate, so the second presmoothing
-    # and the second postsmoothing sweep; in FP64 cycles both presmoothing
-    # sweeps and the second postsmoothing sweep (the first one carries the
-    # coarse-grid correction).  One refinement / norm pass per step.
-    per_step = 2 if precision == 1 else 3
+    # V(2,2) plain finest-level sweeps per step (the first postsmoothing sweep
+    # carries the coarse-grid correction, so the second postsmoothing sweep and):
+    # in refinement steps the first presmoothing sweep starts from a zero
+    # iterate, so the second presmoothing sweep, unless the two run as one
+    # launch (tile family 7); in FP64 cycles the second presmoothing sweep,
+    # the first one summing the norm of the previous cycle's result (tile
+    # family 6: then it is the measured pass) or both, the norm a pass of its
+    # own.  One refinement pass / norm pass or norm-carrying sweep per step.
+    if precision == 1:
+        per_step = 1 if m.mg_tile_config(s.ctx, 0, 7)[1] > 0 else 2
+    else:
+        per_step = 2 if m.mg_tile_config(s.ctx, 0, 6)[1] > 0 else 3
     assert n_sweep == per_step * total and n_pass == total
     assert ms_sweep > 0.0 and ms_pass > 0.0
     # reading resets the totals
