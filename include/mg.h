@@ -236,14 +236,16 @@ int mg_level_coarsest(int dim, int dtype, const void* k, void* u, const void* f,
 int mg_level_smooth_restrict(int dim, int n, int dtype, const void* u_in, const void* f, void* u_out, void* fc,
                              int zchunk, int order, void* stream);
 /* The first two pre-smoothing sweeps of a level whose iterate starts at zero
- * (Algorithm 1: presmoothing from the zero coarse-grid guess), fused, 3D
+ * (Algorithm 1: presmoothing from the zero coarse-grid guess), fused,
  * Laplacian, dtype 1 (FP32) or 2 (binary16), omega 1: two red-first
  * red-black sweeps from u = 0, the result in u_out (inner nodes; f != u_out),
  * bit for bit mg_level_smooth with zero_guess followed by mg_level_smooth.
- * by: 12 or 16 rows per tile (the tile writes (64 - 6) x (by - 6) nodes per
- * plane); zchunk: planes per workgroup (>= 1); order: 0 XCD bands, 1 linear
- * block order.  The solver uses it in V-cycles where the autotuner times it
- * faster than the two sweeps it replaces.  Synchronises the stream. */
+ * 3D: by 12 or 16 rows per tile (the tile writes (64 - 6) x (by - 6) nodes
+ * per plane), zchunk planes per workgroup; 2D: by ignored, zchunk rows per
+ * wavefront (64-wide strips writing 58 nodes per row); zchunk >= 1; order: 0
+ * XCD bands, 1 linear block order.  The solver uses it in V-cycles (and
+ * batches) where the autotuner times it faster than the two sweeps it
+ * replaces.  Synchronises the stream. */
 int mg_level_smooth2_zero(int dim, int n, int dtype, const void* f, void* u_out, int by, int zchunk, int order,
                           void* stream);
 /* Conjugate gradients on a coarsest grid of n = 2^c + 1 nodes per axis

@@ -384,7 +384,8 @@ def mg_level_smooth_restrict(u_in, f, u_out, fc, zchunk=4, order=0, stream=None)
 
 
 def mg_level_smooth2_zero(f, u_out, by=12, zchunk=16, order=0, stream=None) -> None:
-    """The first two red-first pre-smoothing sweeps from a zero iterate, fused (3D, float32 or float16)."""
+    """The first two red-first pre-smoothing sweeps from a zero iterate, fused (float32 or float16; 3D: by
+    12 or 16 rows, zchunk planes per workgroup; 2D: by ignored, zchunk rows per wavefront)."""
     dim, n = f.dim(), f.shape[0]
     dt = f.dtype
     _check(lib().mg_level_smooth2_zero(dim, n, _dtype_code(f), _dptr(f, dt, f.shape, "f"),

@@ -989,6 +989,22 @@ void tune_store(const TuneKey& k, TileCfg v) {
     g_tune[k] = v;
 }
 
+// Launch shapes of the two fused pre-smoothing sweeps from a zero iterate:
+// 3D rows 12 / 16 x z-chunks of 8 .. 128 planes, 2D chunks of 16 .. 256 rows
+// per wavefront; both block orders.
+std::vector<TileCfg> smooth2_candidates(int dim, int n) {
+    std::vector<TileCfg> cands;
+    const int m = n - 2;
+    for (int by : dim == 2 ? std::vector<int>{1} : std::vector<int>{12, 16})
+        for (int zc = dim == 2 ? 16 : 8; zc <= (dim == 2 ? 256 : 128) && zc <= std::max(dim == 2 ? 16 : 8, m); zc *= 2)
+            for (int order : {0, 1}) {
+                TileCfg t{dim == 2 ? 12 : by, zc};
+                t.order = order;
+                cands.push_back(t);
+            }
+    return cands;
+}
+
 // Tune one hierarchy (levels of 'elem' bytes).  scratch_u / scratch_f stand in
 // for caller-owned level-0 arrays.
 hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void* scratch_u, void* scratch_f) {
@@ -1104,18 +1120,14 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
         }
         // the first two pre-smoothing sweeps from a zero iterate in one launch,
         // kept if it beats the two sweeps it replaces
-        if (dim == 3 && !var && sm == SM_RBGS && L.elem <= 4 && c->p.nu1 >= 2) {
+        if (!var && sm == SM_RBGS && L.elem <= 4 && c->p.nu1 >= 2) {
             TuneKey k2{dim, L.elem, n, 6, sm, 0, 0, 0};
             if (!tune_lookup(k2, &cfg)) {
-                std::vector<TileCfg> cands;
-                for (int by : {12, 16})
-                    for (int zc = 8; zc <= 128 && zc <= std::max(8, n - 2); zc *= 2)
-                        for (int order : {0, 1}) {
-                            TileCfg t{by, zc};
-                            t.order = order;
-                            cands.push_back(t);
-                        }
+                const std::vector<TileCfg> cands = smooth2_candidates(dim, n);
                 auto run2 = [&](TileCfg t) {
+                    if (dim == 2)
+                        return L.elem == 4 ? launch_smooth2d_zg2<float>(d, 1, n, 1, t, s)
+                                           : launch_smooth2d_zg2<half_t>(d, 1, n, 1, t, s);
                     return L.elem == 4 ? launch_smooth3d_zg2<float>(d, 1, n, 1, t, s)
                                        : launch_smooth3d_zg2<half_t>(d, 1, n, 1, t, s);
                 };
@@ -1179,6 +1191,29 @@ hipError_t tune_group(int dim, int smoother, const GridDesc* d, int count, int n
         tune_store(kr, cfg);
     }
     t.restr = cfg;
+    // the two fused pre-smoothing sweeps from a zero iterate, kept if faster
+    if (smoother == SM_RBGS) {
+        TuneKey k2{dim, 4, n, 6, smoother, 0, 0, bucket};
+        if (!tune_lookup(k2, &cfg)) {
+            auto run2 = [&](TileCfg c) {
+                return dim == 2 ? launch_smooth2d_zg2<float>(d, count, n, 1, c, s)
+                                : launch_smooth3d_zg2<float>(d, count, n, 1, c, s);
+            };
+            const std::vector<TileCfg> cands = smooth2_candidates(dim, n);
+            TileCfg best = pick_fastest(cands, cands[0], run2, s);
+            const float t_two = time_launch(run2, best, s);
+            const TileCfg zg = t.smooth_zg, sw = t.smooth;
+            const float t_sep = time_launch([&](TileCfg) {
+                (void)launch_smooth<float>(dim, smoother, false, d, count, n, 0, SWEEP_ZERO_GUESS, zg, s);
+                return launch_smooth<float>(dim, smoother, false, d, count, n, 1, 0, sw, s);
+            }, sw, s);
+            cfg = best;
+            if (!(t_two < t_sep)) cfg.zchunk = -best.zchunk;
+            tune_store(k2, cfg);
+        }
+        t.smooth_zg2 = cfg;
+        if (cfg.zchunk < 0) t.smooth_zg2.zchunk = std::getenv("MG_FUSED_SMOOTH2") ? -cfg.zchunk : 0;
+    }
     return hipStreamSynchronize(s);
 }
 }  // namespace mg
@@ -1796,8 +1831,8 @@ int mg_level_smooth_restrict(int dim, int n, int dtype, const void* u_in, const 
 int mg_level_smooth2_zero(int dim, int n, int dtype, const void* f, void* u_out, int by, int zchunk, int order,
                           void* stream) {
     const int elem = dtype_elem(dtype);
-    if (dim != 3 || !valid_edge(dim, n) || n < 5 || (elem != 4 && elem != 2)) return MG_EINVAL;
-    if (!f || !u_out || f == u_out || (by != 12 && by != 16) || zchunk < 1 || (order != 0 && order != 1))
+    if (!valid_edge(dim, n) || n < 5 || (elem != 4 && elem != 2)) return MG_EINVAL;
+    if (!f || !u_out || f == u_out || (dim == 3 && by != 12 && by != 16) || zchunk < 1 || (order != 0 && order != 1))
         return MG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     GridDesc h{};
@@ -1812,8 +1847,9 @@ int mg_level_smooth2_zero(int dim, int n, int dtype, const void* f, void* u_out,
     if (r != MG_OK) return r;
     TileCfg cfg{by, zchunk};
     cfg.order = order;
-    const hipError_t e = elem == 4 ? launch_smooth3d_zg2<float>(d, 1, n, 1, cfg, s)
-                                   : launch_smooth3d_zg2<half_t>(d, 1, n, 1, cfg, s);
+    hipError_t e;
+    if (dim == 2) e = elem == 4 ? launch_smooth2d_zg2<float>(d, 1, n, 1, cfg, s) : launch_smooth2d_zg2<half_t>(d, 1, n, 1, cfg, s);
+    else e = elem == 4 ? launch_smooth3d_zg2<float>(d, 1, n, 1, cfg, s) : launch_smooth3d_zg2<half_t>(d, 1, n, 1, cfg, s);
     return finish_desc(d, s, e);
 }
 

@@ -146,6 +146,11 @@ hipError_t launch_smooth3d(int sm, bool var, const GridDesc* d, int sel, int fla
 // rows, cfg.zchunk planes per workgroup, cfg.order the block order.
 template <typename T>
 hipError_t launch_smooth3d_zg2(const GridDesc* d, int ninst, int n, int sel, TileCfg cfg, hipStream_t s);
+// The same in 2D: cfg.zchunk rows per wavefront (64-wide strips, four chunks
+// of a strip per workgroup), cfg.order the block order.
+template <typename T>
+hipError_t launch_smooth2d_zg2(const GridDesc* d, int ninst, int n, int sel, TileCfg cfg, hipStream_t s);
+int smooth2d_zg2_tiles(int n, int ychunk);
 // 3D Laplacian, FP32 or binary16 storage: the last red-first RBGS pre-smoothing
 // sweep of input 'sel' fused with the residual of its result and full
 // weighting into fc (cfg.by 16 rows, cfg.zchunk coarse planes per workgroup,

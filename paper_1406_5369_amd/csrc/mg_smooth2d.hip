@@ -145,7 +145,132 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2D Laplacian: the first two red-black pre-smoothing sweeps of a level whose
+// iterate starts at zero, in one launch.  A wavefront marches a 64-wide strip
+// (lane = x) along y through a chunk of rows, one value per lane per row; the
+// four half-sweeps trail each other by one row (step kk: red of row kk from
+// f, black of kk-1, red of kk-2, black of kk-3, which is written), each
+// valid on the strip minus one more lane per side, so a strip writes 58
+// nodes per row; y-neighbours come from a five-row ring in registers,
+// x-neighbours from the adjacent lanes: no LDS, no barrier.  The four
+// wavefronts of a workgroup take four consecutive chunks of one strip.  The
+// expressions are those of the two separate sweeps (the first with every old
+// value zero), stored values rounded to the storage type in between.
+// ---------------------------------------------------------------------------
+template <typename ST>
+struct Sweep2Row {
+    using T = arith_t<ST>;
+    static constexpr int H = 3, TX = BX - 2 * H, R = 5;
+    const MG_GLOBAL ST* __restrict__ f;
+    MG_GLOBAL ST* __restrict__ uout;
+    int n, x0, y0, y1, gx, lane;
+    bool coli;
+    unsigned xb;
+    T c, wd, om;
+    T v[R];   // latest value of rows kk-4 .. kk
+    T fr[R];  // f of rows kk-3 .. kk+1 (kk+1 in flight)
+
+    __device__ __forceinline__ T ldf(int y) const {
+        return ld_off(f + (size_t)min(max(y, 0), n - 1) * n, xb);
+    }
+    // half-sweep q of colour col on row y (value a), rows below / above bv / av
+    template <int q>
+    __device__ __forceinline__ void half(T& a, T bv, T av, T fv, int y, int col) {
+        const T uw = lane_prev(a), ue = lane_next(a);  // every lane active
+        const T r = res_lap2(a, uw, ue, bv, av, fv, c);
+        const T nv = stored<ST>(relax<T, false>(a, r, T(0), c, wd, om));
+        if (coli && lane >= q && lane <= BX - 1 - q && y >= 1 && y <= n - 2 && ((gx + y) & 1) == col) a = nv;
+    }
+    template <int P>
+    __device__ __forceinline__ void step(int kk) {
+        constexpr int S0 = P, S1 = (P + 4) % R, S2 = (P + 3) % R, S3 = (P + 2) % R, S4 = (P + 1) % R;
+        fr[S4] = ldf(kk + 1);  // slot of row kk-4, whose f is no longer read
+        {
+            const T zero = T(0);
+            const T r = res_lap2(zero, zero, zero, zero, zero, fr[S0], c);
+            const T nv = stored<ST>(relax<T, false>(zero, r, zero, c, wd, om));
+            v[S0] = (coli && kk >= 1 && kk <= n - 2 && ((gx + kk) & 1) == 0) ? nv : zero;
+        }
+        if (kk - 1 >= y0 - 2) half<1>(v[S1], v[S2], v[S0], fr[S1], kk - 1, 1);
+        if (kk - 2 >= y0 - 1) half<2>(v[S2], v[S3], v[S1], fr[S2], kk - 2, 0);
+        const int y3 = kk - 3;
+        if (y3 >= y0 && y3 < y1) {
+            half<3>(v[S3], v[S4], v[S2], fr[S3], y3, 1);
+            if (coli && lane >= H && lane <= BX - 1 - H && y3 >= 1 && y3 <= n - 2)
+                st_off(uout + (size_t)y3 * n, xb, (ST)v[S3]);
+        }
+    }
+    __device__ __forceinline__ void run() {
+        xb = (unsigned)min(max(gx, 0), n - 1) * (unsigned)sizeof(ST);
+        coli = gx >= 1 && gx <= n - 2;
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = fr[q] = T(0);
+        int kk = y0 - H;
+        const int kend = y1 - 1 + H;
+        fr[0] = ldf(kk);
+        for (; kk + 4 <= kend; kk += R) {
+            step<0>(kk);
+            step<1>(kk + 1);
+            step<2>(kk + 2);
+            step<3>(kk + 3);
+            step<4>(kk + 4);
+        }
+        if (kk <= kend) step<0>(kk);
+        if (kk + 1 <= kend) step<1>(kk + 1);
+        if (kk + 2 <= kend) step<2>(kk + 2);
+        if (kk + 3 <= kend) step<3>(kk + 3);
+    }
+};
+
+template <typename ST>
+__global__ __launch_bounds__(NT) void k_smooth2d_zg2(const GridDesc* __restrict__ descs, int sel, int ychunk) {
+    const GridDesc d = descs[blockIdx.y];
+    if (d.done && *gp(d.done)) return;
+    using S = Sweep2Row<ST>;
+    using T = arith_t<ST>;
+    S s;
+    const int n = d.n;
+    const int ntx = (n - 2 + S::TX - 1) / S::TX;
+    const int tile = sweep_tile(sel, blockIdx.x, gridDim.x);
+    const int tx = tile % ntx, tb = tile / ntx;
+    const int w = threadIdx.x >> 6;
+    s.n = n;
+    s.lane = threadIdx.x & 63;
+    s.x0 = 1 + tx * S::TX;
+    s.gx = s.x0 - S::H + s.lane;
+    s.y0 = min(1 + (tb * 4 + w) * ychunk, n - 1);
+    s.y1 = min(s.y0 + ychunk, n - 1);
+    if (s.y0 >= s.y1) return;  // a wavefront past the last chunk (no barrier follows)
+    s.uout = gp((ST*)((sel & 1) ? d.u : d.t));
+    s.f = gp((const ST*)d.f);
+    s.c = (T)d.c;
+    s.wd = (T)d.wd;
+    s.om = (T)d.omega;
+    s.run();
+}
+
 }  // namespace
+
+int smooth2d_zg2_tiles(int n, int ychunk) {
+    const int m = n - 2;
+    return cdiv(m, BX - 6) * cdiv(cdiv(m, ychunk), 4);
+}
+
+template <typename T>
+hipError_t launch_smooth2d_zg2(const GridDesc* d, int ninst, int n, int sel, TileCfg cfg, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        return hipErrorInvalidValue;  // built for FP32 and binary16 storage
+    } else {
+        if (n < 5 || ninst <= 0 || cfg.zchunk < 1) return hipErrorInvalidValue;
+        const dim3 grid(smooth2d_zg2_tiles(n, cfg.zchunk), ninst);
+        k_smooth2d_zg2<T><<<grid, NT, 0, s>>>(d, sweep_arg(sel, cfg), cfg.zchunk);
+        return hipGetLastError();
+    }
+}
+template hipError_t launch_smooth2d_zg2<double>(const GridDesc*, int, int, int, TileCfg, hipStream_t);
+template hipError_t launch_smooth2d_zg2<float>(const GridDesc*, int, int, int, TileCfg, hipStream_t);
+template hipError_t launch_smooth2d_zg2<half_t>(const GridDesc*, int, int, int, TileCfg, hipStream_t);
 
 template <typename T, int SMV, bool VARV, int FL>
 hipError_t launch_smooth2d_fl(const GridDesc* d, int sel, TileCfg cfg, dim3 grid, hipStream_t s) {

@@ -125,12 +125,17 @@ bool fused_restrict_ok(const Problem& P, int dim, const Tiles& t) {
            std::getenv("MG_NO_FUSED_RESTRICT") == nullptr;
 }
 
-// The first two pre-smoothing sweeps from a zero iterate in one launch: 3D
+// The first two pre-smoothing sweeps from a zero iterate in one launch:
 // Laplacian red-black levels in FP32 or binary16 storage whose tiles chose it.
 template <typename T>
 bool smooth2_ok(const Problem& P, int dim, const Tiles& t, bool zero) {
-    return zero && sizeof(T) <= 4 && dim == 3 && !P.var && P.smoother == SM_RBGS && P.nu1 >= 2 &&
+    return zero && sizeof(T) <= 4 && (dim == 2 || dim == 3) && !P.var && P.smoother == SM_RBGS && P.nu1 >= 2 &&
            t.smooth_zg2.zchunk > 0 && std::getenv("MG_NO_FUSED_SMOOTH2") == nullptr;
+}
+template <typename T>
+hipError_t launch_smooth2(int dim, const Group& g, const Tiles& t, hipStream_t s) {
+    return dim == 2 ? launch_smooth2d_zg2<T>(g.d, g.ninst, g.n, 1, t.smooth_zg2, s)
+                    : launch_smooth3d_zg2<T>(g.d, g.ninst, g.n, 1, t.smooth_zg2, s);
 }
 
 // Post-smoothing select bits: the symmetric red-black smoother relaxes black first.
@@ -151,7 +156,7 @@ hipError_t cycle_rec(const Problem& P, const std::vector<Group>& G, int l, int k
     int i0 = first_done ? 1 : 0;
     if (!first_done && smooth2_ok<T>(P, dim, tiles[(size_t)l], zero)) {
         // sweeps 1 and 2 from the zero iterate: the result lands in u
-        MG_TRY(launch_smooth3d_zg2<T>(g.d, g.ninst, g.n, 1, tiles[(size_t)l].smooth_zg2, s));
+        MG_TRY(launch_smooth2<T>(dim, g, tiles[(size_t)l], s));
         i0 = 2;
     }
     for (int i = i0; i < P.nu1; ++i) {
@@ -217,7 +222,7 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
         int cur = skip1 ? 1 : 0;
         int i0 = skip1 ? 1 : 0;
         if (two) {
-            MG_TRY(launch_smooth3d_zg2<T>(g.d, g.ninst, g.n, 1, tiles[(size_t)l].smooth_zg2, s));
+            MG_TRY(launch_smooth2<T>(dim, g, tiles[(size_t)l], s));
             i0 = 2;
         }
         for (int i = i0; i < P.nu1; ++i) {

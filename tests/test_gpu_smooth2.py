@@ -1,9 +1,9 @@
 """Parity of the first two pre-smoothing sweeps from a zero iterate fused in
 one launch (Algorithm 1: presmoothing from the zero coarse-grid guess) with
 the CPU oracle's two sweeps, bit for bit, in FP32 and in binary16 storage
-(FP32 arithmetic), over grid sizes that give one or many tiles, ragged last
-tiles in x, y and z, both tile heights and several chunk depths; and whole
-solves with the fused launch forced on and off.
+(FP32 arithmetic), 2D and 3D, over grid sizes that give one or many tiles,
+ragged last tiles in x, y and z, both 3D tile heights and several chunk
+depths; and whole solves and batches with the fused launch forced on and off.
 """
 
 import numpy as np
@@ -62,6 +62,24 @@ def test_two_sweeps_from_zero_bitwise(n, by, zc, dt, dev_ok):
         assert same(host(out), expect), (order,)
 
 
+@pytest.mark.parametrize("n", [5, 9, 33, 65, 129, 257, 513])
+@pytest.mark.parametrize("yc", [1, 3, 16, 64])
+@pytest.mark.parametrize("dt", [np.float32, np.float16])
+def test_two_sweeps_from_zero_bitwise_2d(n, yc, dt, dev_ok):
+    """2D: 64-wide strips (58 written nodes) marching chunks of yc rows, four
+    chunks per workgroup (ragged strips, chunks and workgroups)."""
+    if dt == np.float16:
+        f = (inputs.uniform_rhs(2, n, 970 + n + yc) * 12.0).astype(dt)
+    else:
+        f = (inputs.uniform_rhs(2, n, 970 + n + yc) * 50.0).astype(dt)
+    u1 = oracle.smooth(np.zeros_like(f), f, oracle.SMOOTH_RBGS, 1.0)
+    expect = oracle.smooth(u1, f, oracle.SMOOTH_RBGS, 1.0)
+    for order in (0, 1):
+        out = dev(np.zeros_like(f))
+        mg().mg_level_smooth2_zero(dev(f), out, zchunk=yc, order=order)
+        assert same(host(out), expect), (order,)
+
+
 def test_two_sweeps_equal_the_two_kernels_at_513(dev_ok):
     """513^3 FP32: the fused launch equals the zero-iterate sweep followed by
     the plain sweep of the tuned path's kernels (both pinned above against
@@ -82,20 +100,21 @@ def test_two_sweeps_equal_the_two_kernels_at_513(dev_ok):
         assert torch.equal(out, u), (by, zc)
 
 
-@pytest.mark.parametrize("n,precision", [(65, 1), (129, 1), (65, 2), (257, 1)])
-def test_solve_with_and_without_the_fused_sweeps(n, precision, dev_ok, monkeypatch):
+@pytest.mark.parametrize("dim,n,precision", [(3, 65, 1), (3, 129, 1), (3, 65, 2), (3, 257, 1), (2, 513, 1),
+                                             (2, 1025, 1), (2, 257, 2)])
+def test_solve_with_and_without_the_fused_sweeps(dim, n, precision, dev_ok, monkeypatch):
     """FP32-IR / binary16-IR solves as autotuned, with the fused launch forced
     on every level it applies to, and switched off: every history and field
     equals the oracle's."""
     m = mg()
-    f = inputs.uniform_rhs(3, n, 5)
+    f = inputs.uniform_rhs(dim, n, 5)
     solve = oracle.solve_ir_f32 if precision == 1 else oracle.solve_ir_f16
     res = solve(np.zeros_like(f), f, tol=1e-8, max_cycles=30)
     ue, he = res[0], res[1]
     for env in ({}, {"MG_FUSED_SMOOTH2": "1"}, {"MG_NO_FUSED_SMOOTH2": "1"}):
         for k, v in env.items():
             monkeypatch.setenv(k, v)
-        s = m.Solver(m.Params(dim=3, n=n, precision=precision))
+        s = m.Solver(m.Params(dim=dim, n=n, precision=precision))
         try:
             u = dev(np.zeros_like(f))
             st, cyc, hist = s.solve(u, dev(f), tol=1e-8, max_cycles=30)
@@ -106,6 +125,29 @@ def test_solve_with_and_without_the_fused_sweeps(n, precision, dev_ok, monkeypat
             s.close()
         for k in env:
             monkeypatch.delenv(k)
+
+
+@pytest.mark.parametrize("dim,edges", [(2, [65, 129, 33, 257, 65, 9, 129, 513]), (3, [17, 33, 9, 65, 33])])
+def test_batch_with_the_fused_sweeps_matches_oracle(dim, edges, dev_ok, monkeypatch):
+    """Batched solves with the fused launch forced on every level equal the
+    oracle's solves of each grid."""
+    import torch
+
+    m = mg()
+    monkeypatch.setenv("MG_FUSED_SMOOTH2", "1")
+    fs = [inputs.uniform_rhs(dim, n, 710 + i) for i, n in enumerate(edges)]
+    ctx = m.mg_batch_setup([m.Params(dim=dim, n=n, precision=m.PREC_FP32_IR) for n in edges])
+    try:
+        us = [dev(np.zeros_like(f)) for f in fs]
+        st, cyc, stt = m.mg_batch_solve(ctx, us, [dev(f) for f in fs], tol=1e-8, max_cycles=40)
+        assert st == 0 and all(x == 0 for x in stt)
+        torch.cuda.synchronize()
+        for i, f in enumerate(fs):
+            u_ref, h_ref, _ = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-8, max_cycles=40)
+            assert cyc[i] == len(h_ref) - 1
+            assert np.array_equal(us[i].cpu().numpy(), u_ref)
+    finally:
+        m.mg_destroy(ctx)
 
 
 def test_two_sweeps_reject_bad_arguments(dev_ok):
@@ -123,4 +165,6 @@ def test_two_sweeps_reject_bad_arguments(dev_ok):
         m.mg_level_smooth2_zero(f64, f64.clone())  # FP64 is not built
     f2 = torch.zeros((9, 9), dtype=torch.float32, device="cuda")
     with pytest.raises(m.MGError):
-        m.mg_level_smooth2_zero(f2, f2.clone())  # 3D only
+        m.mg_level_smooth2_zero(f2, f2.clone(), zchunk=0)
+    with pytest.raises(m.MGError):
+        m.mg_level_smooth2_zero(f2, f2)  # in place
