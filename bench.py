@@ -719,7 +719,7 @@ def main(argv=None) -> int:
              "fine_tiles": {fam: mg.mg_tile_config(solver.ctx, 0, i, with_order=True) for i, fam in
                             enumerate(["smooth", "restrict", "norm_or_refinement", "smooth_zero_guess",
                                        "smooth_fused_correction", "smooth_fused_restriction",
-                                       "smooth_with_norm", "two_smooths_from_zero"])}}
+                                       "smooth_with_norm", "two_smooths_from_zero", "two_post_smooths"])}}
     if not args.no_fp64 and w["precision"] == 1:
         s64 = mg.Solver(mg.Params(dim=dim, n=n, precision=mg.PREC_FP64, op=op, k=kd))
         u = us[0]

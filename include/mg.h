@@ -167,7 +167,9 @@ int mg_num_levels(const mg_ctx* ctx);
  * iterate, which in mg_solve gives each cycle's norm (Section 2.4's L2
  * residual; every field 0 when the norm is a pass of its own), 7 the first
  * two pre-smoothing sweeps from a zero iterate in one launch (mg_level_
- * smooth2_zero; *zchunk 0 when the level runs them apart)): tile rows
+ * smooth2_zero; *zchunk 0 when the level runs them apart), 8 the first two
+ * post-smoothing sweeps in one launch (mg_level_smooth2_correct, 2D; *zchunk
+ * 0 when the level runs them apart)): tile rows
  * *by, z-chunk *zchunk (3D planes per workgroup), for 3D
  * marching kernels *prefetch = planes of u loaded ahead (1 or 2), *waves =
  * wavefronts per workgroup (4; 1 or 8 for 3D smoothing and the 3D pass), for
@@ -248,6 +250,19 @@ int mg_level_smooth_restrict(int dim, int n, int dtype, const void* u_in, const 
  * replaces.  Synchronises the stream. */
 int mg_level_smooth2_zero(int dim, int n, int dtype, const void* f, void* u_out, int by, int zchunk, int order,
                           void* stream);
+/* The first two post-smoothing sweeps of a level (Algorithm 1: interpolation
+ * and correction, then postsmoothing), fused, 2D Laplacian, dtype 1 (FP32) or
+ * 2 (binary16), omega 1: the bilinear correction from the coarse grid ec
+ * (edge (n-1)/2+1) added to u_in at inner nodes, then two red-black sweeps
+ * (smoother 0: red first; 2: black first, the symmetric smoother's order),
+ * the result in u_out (inner nodes; u_out != u_in), bit for bit
+ * mg_level_smooth with ec followed by mg_level_smooth.  zchunk: rows per
+ * wavefront (64-wide strips writing 56 nodes per row); order: 0 XCD bands, 1
+ * linear block order.  The solver uses it in V-cycles (and batches) where the
+ * autotuner times it faster than the two sweeps it replaces.  Synchronises
+ * the stream. */
+int mg_level_smooth2_correct(int dim, int n, int dtype, int smoother, const void* u_in, const void* f,
+                             const void* ec, void* u_out, int zchunk, int order, void* stream);
 /* Conjugate gradients on a coarsest grid of n = 2^c + 1 nodes per axis
  * (mg_params.coarse_n): 'iters' steps (0: 4 (n - 1)) from u = 0 on A u = f;
  * u's boundary is written with zeros.  n at most 33 (2D) / 9 (3D) for dtype 0,

@@ -113,6 +113,7 @@ def lib():
             "mg_level_coarsest": (i, [i, i, p, p, p, p]),
             "mg_level_smooth_restrict": (i, [i, i, i, p, p, p, p, i, i, p]),
             "mg_level_smooth2_zero": (i, [i, i, i, p, p, i, i, i, p]),
+            "mg_level_smooth2_correct": (i, [i, i, i, i, p, p, p, p, i, i, p]),
             "mg_level_coarsest_cg": (i, [i, i, i, p, p, p, i, p]),
             "mg_cdiff_setup": (i, [C.POINTER(_CDiffParams), p, C.POINTER(p)]),
             "mg_cdiff_fas": (i, [p, p, p]),
@@ -301,7 +302,8 @@ def mg_tile_config(ctx: int, level: int, family: int, with_order: bool = False):
     3 smooth from a zero iterate, 4 smooth with the fused coarse-grid correction, 5 last pre-smoothing
     sweep fused with the restriction, 6 FP64 first pre-smoothing sweep that also sums the residual norm,
     all 0 when the norm is a pass of its own, 7 the first two pre-smoothing sweeps from a zero iterate in
-    one launch, zchunk 0 when they run apart); with_order adds the block order (0 XCD bands, 1 linear)
+    one launch, 8 the first two post-smoothing sweeps in one launch (2D), zchunk 0 when they run apart);
+    with_order adds the block order (0 XCD bands, 1 linear)
     and the pairs flag (3D pass with two nodes per lane)."""
     by, zc, pd, wv, od, xp = (C.c_int(0) for _ in range(6))
     _check(lib().mg_tile_config(ctx, level, family, C.byref(by), C.byref(zc), C.byref(pd), C.byref(wv),
@@ -391,6 +393,18 @@ def mg_level_smooth2_zero(f, u_out, by=12, zchunk=16, order=0, stream=None) -> N
     _check(lib().mg_level_smooth2_zero(dim, n, _dtype_code(f), _dptr(f, dt, f.shape, "f"),
                                        _dptr(u_out, dt, f.shape, "u_out"), int(by), int(zchunk), int(order),
                                        _stream(stream)), "mg_level_smooth2_zero")
+
+
+def mg_level_smooth2_correct(u_in, f, ec, u_out, smoother=SMOOTH_RBGS, zchunk=32, order=0, stream=None) -> None:
+    """The coarse-grid correction and the first two post-smoothing sweeps, fused (2D, float32 or float16;
+    smoother SMOOTH_RBGS red first or SMOOTH_RBGS_SYM black first)."""
+    dim, n = f.dim(), f.shape[0]
+    dt = f.dtype
+    nc = (n - 1) // 2 + 1
+    _check(lib().mg_level_smooth2_correct(dim, n, _dtype_code(f), int(smoother), _dptr(u_in, dt, f.shape, "u_in"),
+                                          _dptr(f, dt, f.shape, "f"), _dptr(ec, dt, (nc,) * dim, "ec"),
+                                          _dptr(u_out, dt, f.shape, "u_out"), int(zchunk), int(order),
+                                          _stream(stream)), "mg_level_smooth2_correct")
 
 
 def mg_level_prolong_correct(u, ec, stream=None) -> None:

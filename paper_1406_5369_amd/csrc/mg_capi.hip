@@ -1149,6 +1149,33 @@ hipError_t tune_levels(mg_ctx* c, const Levels& L, std::vector<Tiles>& tl, void*
             tl[(size_t)l].smooth_zg2 = cfg;
             if (cfg.zchunk < 0) tl[(size_t)l].smooth_zg2.zchunk = std::getenv("MG_FUSED_SMOOTH2") ? -cfg.zchunk : 0;
         }
+        // 2D: the first two post-smoothing sweeps in one launch, kept if faster
+        if (dim == 2 && !var && sm == SM_RBGS && L.elem <= 4 && c->p.nu2 >= 2) {
+            TuneKey kp{dim, L.elem, n, 7, sm, 0, 0, 0};
+            if (!tune_lookup(kp, &cfg)) {
+                const std::vector<TileCfg> cands = smooth2_candidates(dim, n);
+                auto runp = [&](TileCfg t) {
+                    return L.elem == 4 ? launch_smooth2d_pro2<float>(d, 1, n, 0, t, s)
+                                       : launch_smooth2d_pro2<half_t>(d, 1, n, 0, t, s);
+                };
+                TileCfg best = pick_fastest(cands, cands[0], runp, s);
+                const float t_two = time_launch(runp, best, s);
+                const TileCfg pr = tl[(size_t)l].smooth_pro, sw = tl[(size_t)l].smooth;
+                const float t_sep = time_launch([&](TileCfg) {
+                    if (L.elem == 4) {
+                        (void)launch_smooth<float>(dim, sm, false, d, 1, n, 0, SWEEP_PROLONG, pr, s);
+                        return launch_smooth<float>(dim, sm, false, d, 1, n, 1, 0, sw, s);
+                    }
+                    (void)launch_smooth<half_t>(dim, sm, false, d, 1, n, 0, SWEEP_PROLONG, pr, s);
+                    return launch_smooth<half_t>(dim, sm, false, d, 1, n, 1, 0, sw, s);
+                }, sw, s);
+                cfg = best;
+                if (!(t_two < t_sep)) cfg.zchunk = -best.zchunk;
+                tune_store(kp, cfg);
+            }
+            tl[(size_t)l].smooth_pro2 = cfg;
+            if (cfg.zchunk < 0) tl[(size_t)l].smooth_pro2.zchunk = std::getenv("MG_FUSED_POST2") ? -cfg.zchunk : 0;
+        }
     }
     hipError_t e2 = hipStreamSynchronize(s);
     (void)hipFree(d);
@@ -1213,6 +1240,25 @@ hipError_t tune_group(int dim, int smoother, const GridDesc* d, int count, int n
         }
         t.smooth_zg2 = cfg;
         if (cfg.zchunk < 0) t.smooth_zg2.zchunk = std::getenv("MG_FUSED_SMOOTH2") ? -cfg.zchunk : 0;
+    }
+    if (smoother == SM_RBGS && dim == 2) {
+        TuneKey kp{dim, 4, n, 7, smoother, 0, 0, bucket};
+        if (!tune_lookup(kp, &cfg)) {
+            auto runp = [&](TileCfg c) { return launch_smooth2d_pro2<float>(d, count, n, 0, c, s); };
+            const std::vector<TileCfg> cands = smooth2_candidates(dim, n);
+            TileCfg best = pick_fastest(cands, cands[0], runp, s);
+            const float t_two = time_launch(runp, best, s);
+            const TileCfg pr = t.smooth_pro, sw = t.smooth;
+            const float t_sep = time_launch([&](TileCfg) {
+                (void)launch_smooth<float>(dim, smoother, false, d, count, n, 0, SWEEP_PROLONG, pr, s);
+                return launch_smooth<float>(dim, smoother, false, d, count, n, 1, 0, sw, s);
+            }, sw, s);
+            cfg = best;
+            if (!(t_two < t_sep)) cfg.zchunk = -best.zchunk;
+            tune_store(kp, cfg);
+        }
+        t.smooth_pro2 = cfg;
+        if (cfg.zchunk < 0) t.smooth_pro2.zchunk = std::getenv("MG_FUSED_POST2") ? -cfg.zchunk : 0;
     }
     return hipStreamSynchronize(s);
 }
@@ -1499,7 +1545,7 @@ int mg_num_levels(const mg_ctx* c) {
 
 int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk, int* prefetch, int* waves,
                    int* order, int* pairs) {
-    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 7)
+    if (!c || is_batch_handle(c) || !by || !zchunk || level < 0 || level >= c->nlev || family < 0 || family > 8)
         return MG_EINVAL;
     if (c->cc || c->st || c->cd) return MG_ENOTSUP;  // plain kernels, no tiles
     const std::vector<Tiles>& tl = c->p.precision == MG_PREC_FP64 ? c->tl64 : c->tl32;
@@ -1511,7 +1557,8 @@ int mg_tile_config(const mg_ctx* c, int level, int family, int* by, int* zchunk,
                       : family == 4 ? tv.smooth_pro
                       : family == 5 ? tv.fused
                       : family == 6 ? tv.smooth_nrm
-                                    : tv.smooth_zg2;
+                      : family == 7 ? tv.smooth_zg2
+                                    : tv.smooth_pro2;
     if ((family == 2 || family == 6) && level != 0) return MG_EINVAL;
     if (family == 6 && !c->nrm_fused) {  // the norm is a pass of its own
         *by = *zchunk = 0;
@@ -1850,6 +1897,34 @@ int mg_level_smooth2_zero(int dim, int n, int dtype, const void* f, void* u_out,
     hipError_t e;
     if (dim == 2) e = elem == 4 ? launch_smooth2d_zg2<float>(d, 1, n, 1, cfg, s) : launch_smooth2d_zg2<half_t>(d, 1, n, 1, cfg, s);
     else e = elem == 4 ? launch_smooth3d_zg2<float>(d, 1, n, 1, cfg, s) : launch_smooth3d_zg2<half_t>(d, 1, n, 1, cfg, s);
+    return finish_desc(d, s, e);
+}
+
+int mg_level_smooth2_correct(int dim, int n, int dtype, int smoother, const void* u_in, const void* f,
+                             const void* ec, void* u_out, int zchunk, int order, void* stream) {
+    const int elem = dtype_elem(dtype);
+    if (dim != 2 || !valid_edge(dim, n) || n < 5 || (elem != 4 && elem != 2)) return MG_EINVAL;
+    if (!u_in || !f || !ec || !u_out || u_in == u_out || (smoother != 0 && smoother != 2) || zchunk < 1 ||
+        (order != 0 && order != 1))
+        return MG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    GridDesc h{};
+    h.u = const_cast<void*>(u_in);
+    h.t = u_out;
+    h.f = f;
+    h.uc = const_cast<void*>(ec);
+    h.n = n;
+    h.c = level_c(n);
+    h.wd = level_wd(dim, n, 1.0);
+    h.omega = 1.0;
+    GridDesc* d = nullptr;
+    int r = with_desc(h, s, &d);
+    if (r != MG_OK) return r;
+    TileCfg cfg{12, zchunk};
+    cfg.order = order;
+    const int sel = smoother == 2 ? SEL_BLACK_FIRST : 0;
+    const hipError_t e = elem == 4 ? launch_smooth2d_pro2<float>(d, 1, n, sel, cfg, s)
+                                   : launch_smooth2d_pro2<half_t>(d, 1, n, sel, cfg, s);
     return finish_desc(d, s, e);
 }
 

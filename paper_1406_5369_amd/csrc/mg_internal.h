@@ -151,6 +151,14 @@ hipError_t launch_smooth3d_zg2(const GridDesc* d, int ninst, int n, int sel, Til
 template <typename T>
 hipError_t launch_smooth2d_zg2(const GridDesc* d, int ninst, int n, int sel, TileCfg cfg, hipStream_t s);
 int smooth2d_zg2_tiles(int n, int ychunk);
+// 2D Laplacian, FP32 or binary16 storage: the first two red-black
+// post-smoothing sweeps of input 'sel' in one launch, the coarse-grid
+// correction from uc added as rows enter (sel bit 2: black first), the result
+// written to the ping-pong partner of the input; cfg.zchunk rows per
+// wavefront, cfg.order the block order.
+template <typename T>
+hipError_t launch_smooth2d_pro2(const GridDesc* d, int ninst, int n, int sel, TileCfg cfg, hipStream_t s);
+int smooth2d_pro2_tiles(int n, int ychunk);
 // 3D Laplacian, FP32 or binary16 storage: the last red-first RBGS pre-smoothing
 // sweep of input 'sel' fused with the residual of its result and full
 // weighting into fc (cfg.by 16 rows, cfg.zchunk coarse planes per workgroup,

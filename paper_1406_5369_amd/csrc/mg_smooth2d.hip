@@ -250,7 +250,156 @@ __global__ __launch_bounds__(NT) void k_smooth2d_zg2(const GridDesc* __restrict_
     s.run();
 }
 
+// ---------------------------------------------------------------------------
+// 2D Laplacian: the first two red-black post-smoothing sweeps in one launch,
+// the first with the coarse-grid correction (Algorithm 1: interpolation and
+// correction, postsmoothing) added as each row enters.  A wavefront marches
+// a 64-wide strip along y through a chunk of rows: step kk corrects row kk
+// (u + P uc at inner nodes, the bilinear weights of the separate sweep), the
+// first colour of row kk-1, the second of kk-2, the first of kk-3 and the
+// second of kk-4, which it writes to the ping-pong partner of its input.  The
+// half-sweeps are valid one lane narrower per side each, so a strip writes
+// 56 nodes per row; a six-row register ring holds every node's latest value
+// and a six-row ring f.  Colours follow the select's black-first bit (the
+// symmetric smoother relaxes black first after the correction).
+// ---------------------------------------------------------------------------
+template <typename ST>
+struct Sweep2Pro {
+    using T = arith_t<ST>;
+    static constexpr int H = 4, TX = BX - 2 * H, R = 6;
+    const MG_GLOBAL ST* __restrict__ uin;
+    MG_GLOBAL ST* __restrict__ uout;
+    const MG_GLOBAL ST* __restrict__ f;
+    const MG_GLOBAL ST* __restrict__ ec;
+    int n, nc, x0, y0, y1, gx, lane, cfirst;
+    bool coli, xo;
+    unsigned xb, cxb;
+    T c, wd, om;
+    T v[R];   // latest value of rows kk-5 .. kk
+    T fr[R];  // f of rows kk-4 .. kk+1 (kk+1 in flight)
+    T un;     // u of row kk+1 (in flight)
+
+    __device__ __forceinline__ T ldrow(const MG_GLOBAL ST* a, int y) const {
+        return ld_off(a + (size_t)min(max(y, 0), n - 1) * n, xb);
+    }
+    // u + P uc at row y (bilinear, as the separate sweep; inner nodes only)
+    __device__ __forceinline__ T corrected(T u, int y) const {
+        const int ycl = min(max(y, 0), n - 1);
+        const MG_GLOBAL ST* __restrict__ r0 = ec + (size_t)(ycl >> 1) * nc;
+        const T a = ld_off(r0, cxb), b = ld_off(r0 + ((ycl & 1) ? nc : 0), cxb);
+        const T an = lane_next(a), bn = lane_next(b);  // every lane active
+        const T sa = xo ? a + an : a;
+        const T sb = xo ? b + bn : b;
+        const T corr = (ycl & 1) ? (xo ? T(0.25) * (sa + sb) : T(0.5) * (sa + sb)) : (xo ? T(0.5) * sa : sa);
+        const bool inn = coli && y >= 1 && y <= n - 2;
+        return inn ? stored<ST>(u + corr) : u;
+    }
+    template <int q>
+    __device__ __forceinline__ void half(T& a, T bv, T av, T fv, int y, int col) {
+        const T uw = lane_prev(a), ue = lane_next(a);  // every lane active
+        const T r = res_lap2(a, uw, ue, bv, av, fv, c);
+        const T nv = stored<ST>(relax<T, false>(a, r, T(0), c, wd, om));
+        if (coli && lane >= q && lane <= BX - 1 - q && y >= 1 && y <= n - 2 && ((gx + y) & 1) == col) a = nv;
+    }
+    template <int P>
+    __device__ __forceinline__ void step(int kk) {
+        constexpr int S0 = P, S1 = (P + 5) % R, S2 = (P + 4) % R, S3 = (P + 3) % R, S4 = (P + 2) % R,
+                      S5 = (P + 1) % R;
+        const int c1 = cfirst, c2 = cfirst ^ 1;
+        v[S0] = corrected(un, kk);
+        un = ldrow(uin, kk + 1);
+        fr[S5] = ldrow(f, kk + 1);  // slot of row kk-5, whose f is no longer read
+        if (kk - 1 >= y0 - 3) half<1>(v[S1], v[S2], v[S0], fr[S1], kk - 1, c1);
+        if (kk - 2 >= y0 - 2) half<2>(v[S2], v[S3], v[S1], fr[S2], kk - 2, c2);
+        if (kk - 3 >= y0 - 1) half<3>(v[S3], v[S4], v[S2], fr[S3], kk - 3, c1);
+        const int y4 = kk - 4;
+        if (y4 >= y0 && y4 < y1) {
+            half<4>(v[S4], v[S5], v[S3], fr[S4], y4, c2);
+            if (coli && lane >= H && lane <= BX - 1 - H && y4 >= 1 && y4 <= n - 2)
+                st_off(uout + (size_t)y4 * n, xb, (ST)v[S4]);
+        }
+    }
+    __device__ __forceinline__ void run() {
+        const int xc = min(max(gx, 0), n - 1);
+        xb = (unsigned)xc * (unsigned)sizeof(ST);
+        // x0 is odd and the halo even: even lanes hold odd x and pair with the next lane
+        cxb = (unsigned)(xc >> 1) * (unsigned)sizeof(ST);
+        xo = (gx & 1) != 0;
+        coli = gx >= 1 && gx <= n - 2;
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = fr[q] = T(0);
+        int kk = y0 - H;
+        const int kend = y1 - 1 + H;
+        un = ldrow(uin, kk);
+        fr[0] = ldrow(f, kk);
+        for (; kk + 5 <= kend; kk += R) {
+            step<0>(kk);
+            step<1>(kk + 1);
+            step<2>(kk + 2);
+            step<3>(kk + 3);
+            step<4>(kk + 4);
+            step<5>(kk + 5);
+        }
+        if (kk <= kend) step<0>(kk);
+        if (kk + 1 <= kend) step<1>(kk + 1);
+        if (kk + 2 <= kend) step<2>(kk + 2);
+        if (kk + 3 <= kend) step<3>(kk + 3);
+        if (kk + 4 <= kend) step<4>(kk + 4);
+    }
+};
+
+template <typename ST>
+__global__ __launch_bounds__(NT) void k_smooth2d_pro2(const GridDesc* __restrict__ descs, int sel, int ychunk) {
+    const GridDesc d = descs[blockIdx.y];
+    if (d.done && *gp(d.done)) return;
+    using S = Sweep2Pro<ST>;
+    using T = arith_t<ST>;
+    S s;
+    const int n = d.n;
+    const int ntx = (n - 2 + S::TX - 1) / S::TX;
+    const int tile = sweep_tile(sel, blockIdx.x, gridDim.x);
+    const int tx = tile % ntx, tb = tile / ntx;
+    const int w = threadIdx.x >> 6;
+    s.n = n;
+    s.nc = (n - 1) / 2 + 1;
+    s.lane = threadIdx.x & 63;
+    s.x0 = 1 + tx * S::TX;
+    s.gx = s.x0 - S::H + s.lane;
+    s.y0 = min(1 + (tb * 4 + w) * ychunk, n - 1);
+    s.y1 = min(s.y0 + ychunk, n - 1);
+    if (s.y0 >= s.y1) return;  // a wavefront past the last chunk (no barrier follows)
+    s.cfirst = (sel & SEL_BLACK_FIRST) ? 1 : 0;
+    s.uin = gp((const ST*)((sel & 1) ? d.t : d.u));
+    s.uout = gp((ST*)((sel & 1) ? d.u : d.t));
+    s.f = gp((const ST*)d.f);
+    s.ec = gp((const ST*)d.uc);
+    s.c = (T)d.c;
+    s.wd = (T)d.wd;
+    s.om = (T)d.omega;
+    s.run();
+}
+
 }  // namespace
+
+int smooth2d_pro2_tiles(int n, int ychunk) {
+    const int m = n - 2;
+    return cdiv(m, BX - 8) * cdiv(cdiv(m, ychunk), 4);
+}
+
+template <typename T>
+hipError_t launch_smooth2d_pro2(const GridDesc* d, int ninst, int n, int sel, TileCfg cfg, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        return hipErrorInvalidValue;  // built for FP32 and binary16 storage
+    } else {
+        if (n < 5 || ninst <= 0 || cfg.zchunk < 1) return hipErrorInvalidValue;
+        const dim3 grid(smooth2d_pro2_tiles(n, cfg.zchunk), ninst);
+        k_smooth2d_pro2<T><<<grid, NT, 0, s>>>(d, sweep_arg(sel, cfg), cfg.zchunk);
+        return hipGetLastError();
+    }
+}
+template hipError_t launch_smooth2d_pro2<double>(const GridDesc*, int, int, int, TileCfg, hipStream_t);
+template hipError_t launch_smooth2d_pro2<float>(const GridDesc*, int, int, int, TileCfg, hipStream_t);
+template hipError_t launch_smooth2d_pro2<half_t>(const GridDesc*, int, int, int, TileCfg, hipStream_t);
 
 int smooth2d_zg2_tiles(int n, int ychunk) {
     const int m = n - 2;

@@ -31,6 +31,10 @@ struct Tiles {
     // sweeps from a zero iterate in one launch (rows 12 or 16, zchunk planes
     // per workgroup; zchunk 0 = two separate sweeps, the autotuner's choice)
     TileCfg smooth_zg2{12, 0};
+    // 2D Laplacian red-black, FP32 / binary16: the first two post-smoothing
+    // sweeps (the coarse-grid correction fused into the first) in one launch
+    // (zchunk rows per wavefront; 0 = separate sweeps, the autotuner's choice)
+    TileCfg smooth_pro2{12, 0};
     const TileCfg& sweep(int flags) const {
         if (flags & SWEEP_NORM) return smooth_nrm;
         return (flags & SWEEP_ZERO_GUESS) ? smooth_zg : ((flags & SWEEP_PROLONG) ? smooth_pro : smooth);

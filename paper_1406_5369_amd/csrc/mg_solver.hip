@@ -132,10 +132,19 @@ bool smooth2_ok(const Problem& P, int dim, const Tiles& t, bool zero) {
     return zero && sizeof(T) <= 4 && (dim == 2 || dim == 3) && !P.var && P.smoother == SM_RBGS && P.nu1 >= 2 &&
            t.smooth_zg2.zchunk > 0 && std::getenv("MG_NO_FUSED_SMOOTH2") == nullptr;
 }
+// 'sel' names the output buffer (1: u, 0: t; the input is the zero iterate).
 template <typename T>
-hipError_t launch_smooth2(int dim, const Group& g, const Tiles& t, hipStream_t s) {
-    return dim == 2 ? launch_smooth2d_zg2<T>(g.d, g.ninst, g.n, 1, t.smooth_zg2, s)
-                    : launch_smooth3d_zg2<T>(g.d, g.ninst, g.n, 1, t.smooth_zg2, s);
+hipError_t launch_smooth2(int dim, const Group& g, const Tiles& t, int sel, hipStream_t s) {
+    return dim == 2 ? launch_smooth2d_zg2<T>(g.d, g.ninst, g.n, sel, t.smooth_zg2, s)
+                    : launch_smooth3d_zg2<T>(g.d, g.ninst, g.n, sel, t.smooth_zg2, s);
+}
+// The first two post-smoothing sweeps (correction fused into the first) in one
+// launch: 2D Laplacian red-black levels in FP32 or binary16 storage whose
+// tiles chose it.
+template <typename T>
+bool post2_ok(const Problem& P, int dim, const Tiles& t) {
+    return sizeof(T) <= 4 && dim == 2 && !P.var && P.smoother == SM_RBGS && P.nu2 >= 2 &&
+           t.smooth_pro2.zchunk > 0 && std::getenv("MG_NO_FUSED_POST2") == nullptr;
 }
 
 // Post-smoothing select bits: the symmetric red-black smoother relaxes black first.
@@ -156,7 +165,7 @@ hipError_t cycle_rec(const Problem& P, const std::vector<Group>& G, int l, int k
     int i0 = first_done ? 1 : 0;
     if (!first_done && smooth2_ok<T>(P, dim, tiles[(size_t)l], zero)) {
         // sweeps 1 and 2 from the zero iterate: the result lands in u
-        MG_TRY(launch_smooth2<T>(dim, g, tiles[(size_t)l], s));
+        MG_TRY(launch_smooth2<T>(dim, g, tiles[(size_t)l], 1, s));
         i0 = 2;
     }
     for (int i = i0; i < P.nu1; ++i) {
@@ -221,9 +230,13 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
         const bool fuse = fused_restrict_ok<T>(P, dim, tiles[(size_t)l]) && P.nu1 >= (two ? 3 : (zero ? 2 : 1));
         int cur = skip1 ? 1 : 0;
         int i0 = skip1 ? 1 : 0;
+        // with the fused post-smoothing pair on this level the two sweeps land
+        // in t, so that the pair (t -> u) leaves the iterate in u
+        const bool post2 = two && P.nu1 == 2 && post2_ok<T>(P, dim, tiles[(size_t)l]);
         if (two) {
-            MG_TRY(launch_smooth2<T>(dim, g, tiles[(size_t)l], s));
+            MG_TRY(launch_smooth2<T>(dim, g, tiles[(size_t)l], post2 ? 0 : 1, s));
             i0 = 2;
+            cur = post2 ? 1 : 0;
         }
         for (int i = i0; i < P.nu1; ++i) {
             const int flags = (i == 0 && zero) ? SWEEP_ZERO_GUESS : 0;
@@ -256,7 +269,14 @@ hipError_t vcycle(const Problem& P, const std::vector<Group>& G, bool zero_top, 
         int cur = sel[(size_t)l];
         const bool fuse = P.nu2 > 0;  // the first post-sweep adds P uc while loading
         if (!fuse) MG_TRY(launch_prolong<T>(dim, g.d, g.ninst, g.n, cur, s));
-        for (int i = 0; i < P.nu2; ++i) {
+        int i0 = 0;
+        if (cur == 1 && post2_ok<T>(P, dim, tiles[(size_t)l])) {
+            // post-sweeps 1 and 2 (correction in the first), t -> u
+            MG_TRY(launch_smooth2d_pro2<T>(g.d, g.ninst, g.n, post_sel(P, cur), tiles[(size_t)l].smooth_pro2, s));
+            cur = 0;
+            i0 = 2;
+        }
+        for (int i = i0; i < P.nu2; ++i) {
             const int flags = (i == 0 && fuse) ? SWEEP_PROLONG : 0;
             const bool timed = l == 0 && flags == 0;
             if (timed) prof.begin();

@@ -80,6 +80,36 @@ def test_two_sweeps_from_zero_bitwise_2d(n, yc, dt, dev_ok):
         assert same(host(out), expect), (order,)
 
 
+@pytest.mark.parametrize("n", [5, 9, 33, 65, 129, 257, 513])
+@pytest.mark.parametrize("yc", [1, 3, 16, 64])
+@pytest.mark.parametrize("dt", [np.float32, np.float16])
+@pytest.mark.parametrize("smoother", [0, 2])
+def test_two_post_sweeps_with_correction_bitwise_2d(n, yc, dt, smoother, dev_ok):
+    """2D: the bilinear correction and two red-black sweeps (red first, or
+    black first as the symmetric smoother's post-smoothing) in one launch,
+    against the oracle's correction and two sweeps."""
+    nc = (n - 1) // 2 + 1
+    if dt == np.float16:
+        scale = 8.0 / (n - 1) ** 2
+        u = (inputs.random_guess(2, n, 980 + n) * scale).astype(dt)
+        f = (inputs.uniform_rhs(2, n, 981 + yc) * 12.0).astype(dt)
+        ec = (inputs.random_guess(2, nc, 982 + n) * scale).astype(dt)
+    else:
+        u = inputs.random_guess(2, n, 980 + n).astype(dt)
+        f = (inputs.uniform_rhs(2, n, 981 + yc) * 50.0).astype(dt)
+        ec = inputs.random_guess(2, nc, 982 + n).astype(dt)
+    sm = oracle.SMOOTH_RBGS_SYM if smoother == 2 else oracle.SMOOTH_RBGS
+    u1 = oracle.smooth(oracle.prolong_correct(u, ec), f, smoother=sm)
+    expect = oracle.smooth(u1, f, smoother=sm)
+    for order in (0, 1):
+        out = dev(np.zeros_like(u))
+        mg().mg_level_smooth2_correct(dev(u), dev(f), dev(ec), out, smoother=smoother, zchunk=yc, order=order)
+        got = host(out)
+        # the boundary is not written (zero in out, as loaded in the oracle's copy)
+        inner = (slice(1, -1),) * 2
+        assert same(np.ascontiguousarray(got[inner]), np.ascontiguousarray(expect[inner])), (order,)
+
+
 def test_two_sweeps_equal_the_two_kernels_at_513(dev_ok):
     """513^3 FP32: the fused launch equals the zero-iterate sweep followed by
     the plain sweep of the tuned path's kernels (both pinned above against
@@ -111,7 +141,8 @@ def test_solve_with_and_without_the_fused_sweeps(dim, n, precision, dev_ok, monk
     solve = oracle.solve_ir_f32 if precision == 1 else oracle.solve_ir_f16
     res = solve(np.zeros_like(f), f, tol=1e-8, max_cycles=30)
     ue, he = res[0], res[1]
-    for env in ({}, {"MG_FUSED_SMOOTH2": "1"}, {"MG_NO_FUSED_SMOOTH2": "1"}):
+    for env in ({}, {"MG_FUSED_SMOOTH2": "1", "MG_FUSED_POST2": "1"}, {"MG_NO_FUSED_SMOOTH2": "1"},
+                {"MG_NO_FUSED_POST2": "1"}, {"MG_FUSED_POST2": "1", "MG_NO_FUSED_SMOOTH2": "1"}):
         for k, v in env.items():
             monkeypatch.setenv(k, v)
         s = m.Solver(m.Params(dim=dim, n=n, precision=precision))
@@ -127,6 +158,27 @@ def test_solve_with_and_without_the_fused_sweeps(dim, n, precision, dev_ok, monk
             monkeypatch.delenv(k)
 
 
+def test_symmetric_smoother_solves_with_the_fused_sweeps(dev_ok, monkeypatch):
+    """The symmetric red-black smoother (black first after the correction)
+    with both fused pairs forced on, V and W cycles, equals the oracle."""
+    m = mg()
+    f = inputs.uniform_rhs(2, 257, 8)
+    monkeypatch.setenv("MG_FUSED_SMOOTH2", "1")
+    monkeypatch.setenv("MG_FUSED_POST2", "1")
+    for cycle in (m.CYCLE_V, m.CYCLE_W):
+        ue, he, _ = oracle.solve_ir_f32(np.zeros_like(f), f, tol=1e-8, max_cycles=30, smoother=oracle.SMOOTH_RBGS_SYM,
+                                        cycle=cycle)
+        s = m.Solver(m.Params(dim=2, n=257, precision=m.PREC_FP32_IR, smoother=m.SMOOTH_RBGS_SYM, cycle=cycle))
+        try:
+            u = dev(np.zeros_like(f))
+            st, cyc, hist = s.solve(u, dev(f), tol=1e-8, max_cycles=30)
+            assert cyc == len(he) - 1
+            np.testing.assert_allclose(hist, he, rtol=1e-12, atol=0)
+            assert np.array_equal(host(u), ue)
+        finally:
+            s.close()
+
+
 @pytest.mark.parametrize("dim,edges", [(2, [65, 129, 33, 257, 65, 9, 129, 513]), (3, [17, 33, 9, 65, 33])])
 def test_batch_with_the_fused_sweeps_matches_oracle(dim, edges, dev_ok, monkeypatch):
     """Batched solves with the fused launch forced on every level equal the
@@ -135,6 +187,7 @@ def test_batch_with_the_fused_sweeps_matches_oracle(dim, edges, dev_ok, monkeypa
 
     m = mg()
     monkeypatch.setenv("MG_FUSED_SMOOTH2", "1")
+    monkeypatch.setenv("MG_FUSED_POST2", "1")
     fs = [inputs.uniform_rhs(dim, n, 710 + i) for i, n in enumerate(edges)]
     ctx = m.mg_batch_setup([m.Params(dim=dim, n=n, precision=m.PREC_FP32_IR) for n in edges])
     try:
@@ -168,3 +221,10 @@ def test_two_sweeps_reject_bad_arguments(dev_ok):
         m.mg_level_smooth2_zero(f2, f2.clone(), zchunk=0)
     with pytest.raises(m.MGError):
         m.mg_level_smooth2_zero(f2, f2)  # in place
+    e2 = torch.zeros((5, 5), dtype=torch.float32, device="cuda")
+    with pytest.raises(m.MGError):
+        m.mg_level_smooth2_correct(f2, f2.clone(), e2, f2)  # in place
+    with pytest.raises(m.MGError):
+        m.mg_level_smooth2_correct(f2, f2.clone(), e2, f2.clone(), smoother=1)  # Jacobi is not built
+    with pytest.raises(m.MGError):
+        m.mg_level_smooth2_correct(f, f.clone(), torch.zeros((5, 5, 5), device="cuda"), f.clone())  # 2D only
