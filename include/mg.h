@@ -244,7 +244,7 @@ int mg_level_smooth_restrict(int dim, int n, int dtype, const void* u_in, const 
  * bit for bit mg_level_smooth with zero_guess followed by mg_level_smooth.
  * 3D: by 12 or 16 rows per tile (the tile writes (64 - 6) x (by - 6) nodes
  * per plane), zchunk planes per workgroup; 2D: by ignored, zchunk rows per
- * wavefront (64-wide strips writing 58 nodes per row); zchunk >= 1; order: 0
+ * wavefront (strips of 128 nodes, two per lane, writing 122 per row); zchunk >= 1; order: 0
  * XCD bands, 1 linear block order.  The solver uses it in V-cycles (and
  * batches) where the autotuner times it faster than the two sweeps it
  * replaces.  Synchronises the stream. */
@@ -257,7 +257,7 @@ int mg_level_smooth2_zero(int dim, int n, int dtype, const void* f, void* u_out,
  * (smoother 0: red first; 2: black first, the symmetric smoother's order),
  * the result in u_out (inner nodes; u_out != u_in), bit for bit
  * mg_level_smooth with ec followed by mg_level_smooth.  zchunk: rows per
- * wavefront (64-wide strips writing 56 nodes per row); order: 0 XCD bands, 1
+ * wavefront (strips of 128 nodes, two per lane, writing 120 per row); order: 0 XCD bands, 1
  * linear block order.  The solver uses it in V-cycles (and batches) where the
  * autotuner times it faster than the two sweeps it replaces.  Synchronises
  * the stream. */

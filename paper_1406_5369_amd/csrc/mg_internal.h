@@ -146,7 +146,7 @@ hipError_t launch_smooth3d(int sm, bool var, const GridDesc* d, int sel, int fla
 // rows, cfg.zchunk planes per workgroup, cfg.order the block order.
 template <typename T>
 hipError_t launch_smooth3d_zg2(const GridDesc* d, int ninst, int n, int sel, TileCfg cfg, hipStream_t s);
-// The same in 2D: cfg.zchunk rows per wavefront (64-wide strips, four chunks
+// The same in 2D: cfg.zchunk rows per wavefront (128-node strips, four chunks
 // of a strip per workgroup), cfg.order the block order.
 template <typename T>
 hipError_t launch_smooth2d_zg2(const GridDesc* d, int ninst, int n, int sel, TileCfg cfg, hipStream_t s);

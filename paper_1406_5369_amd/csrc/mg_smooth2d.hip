@@ -147,68 +147,119 @@ __global__ __launch_bounds__(NT) void k_smooth2d(const GridDesc* __restrict__ de
 
 // ---------------------------------------------------------------------------
 // 2D Laplacian: the first two red-black pre-smoothing sweeps of a level whose
-// iterate starts at zero, in one launch.  A wavefront marches a 64-wide strip
-// (lane = x) along y through a chunk of rows, one value per lane per row; the
-// four half-sweeps trail each other by one row (step kk: red of row kk from
-// f, black of kk-1, red of kk-2, black of kk-3, which is written), each
-// valid on the strip minus one more lane per side, so a strip writes 58
-// nodes per row; y-neighbours come from a five-row ring in registers,
-// x-neighbours from the adjacent lanes: no LDS, no barrier.  The four
+// iterate starts at zero, in one launch.  A wavefront marches a strip of 128
+// nodes (two per lane) along y through a chunk of rows; the four
+// half-sweeps trail each other by one row (step kk: red of row kk from f,
+// black of kk-1, red of kk-2, black of kk-3, which is written), each valid
+// on the strip minus one more node per side, so a strip writes 122 nodes per
+// row; y-neighbours come from five-row rings in registers, x-neighbours from
+// the lane's other node and the adjacent lanes: no LDS, no barrier.  The four
 // wavefronts of a workgroup take four consecutive chunks of one strip.  The
 // expressions are those of the two separate sweeps (the first with every old
 // value zero), stored values rounded to the storage type in between.
 // ---------------------------------------------------------------------------
+// Two adjacent nodes per lane (xa = xs + 2 lane, xb = xa + 1): the colour of
+// the a-node of a row is the same on every lane, so each half-sweep updates
+// exactly one node of every lane (a uniform choice); x-neighbours are the
+// lane's other node and the adjacent lane's.
+template <typename ST, int H>
+struct PairRow {
+    using T = arith_t<ST>;
+    static constexpr int TX = 2 * BX - 2 * H;
+    int n, xs, lane;
+    unsigned ba, bb;   // byte offsets of the two nodes (clamped)
+    bool ia, ib;       // the node is an inner node in x
+    __device__ __forceinline__ void init() {
+        const int xa = xs + 2 * lane;
+        ba = (unsigned)min(max(xa, 0), n - 1) * (unsigned)sizeof(ST);
+        bb = (unsigned)min(max(xa + 1, 0), n - 1) * (unsigned)sizeof(ST);
+        ia = xa >= 1 && xa <= n - 2;
+        ib = xa + 1 >= 1 && xa + 1 <= n - 2;
+    }
+    __device__ __forceinline__ const MG_GLOBAL ST* row(const MG_GLOBAL ST* p, int y) const {
+        return p + (size_t)min(max(y, 0), n - 1) * n;
+    }
+    // node offsets 2 lane (a) and 2 lane + 1 (b) inside [q, 2 BX - 1 - q]
+    template <int q>
+    __device__ __forceinline__ bool va_ok() const { return 2 * lane >= q && 2 * lane <= 2 * BX - 1 - q; }
+    template <int q>
+    __device__ __forceinline__ bool vb_ok() const { return 2 * lane + 1 >= q && 2 * lane + 1 <= 2 * BX - 1 - q; }
+    // half-sweep q of colour col on row y: (a, b) the row, (sa, sb) / (na, nb) the rows below / above
+    template <int q>
+    __device__ __forceinline__ void half(T& a, T& b, T sa, T sb, T na, T nb, T fa, T fb, int y, int col, T c, T wd,
+                                         T om) const {
+        const bool yin = y >= 1 && y <= n - 2;
+        const T bw = lane_prev(b), an = lane_next(a);  // every lane active
+        if (((xs + y) & 1) == col) {
+            const T r = res_lap2(a, bw, b, sa, na, fa, c);
+            const T nv = stored<ST>(relax<T, false>(a, r, T(0), c, wd, om));
+            if (yin && ia && va_ok<q>()) a = nv;
+        } else {
+            const T r = res_lap2(b, a, an, sb, nb, fb, c);
+            const T nv = stored<ST>(relax<T, false>(b, r, T(0), c, wd, om));
+            if (yin && ib && vb_ok<q>()) b = nv;
+        }
+    }
+};
+
 template <typename ST>
 struct Sweep2Row {
     using T = arith_t<ST>;
-    static constexpr int H = 3, TX = BX - 2 * H, R = 5;
+    static constexpr int H = 3, R = 5;
+    using PR = PairRow<ST, H>;
+    static constexpr int TX = PR::TX;
+    PR pr;
     const MG_GLOBAL ST* __restrict__ f;
     MG_GLOBAL ST* __restrict__ uout;
-    int n, x0, y0, y1, gx, lane;
-    bool coli;
-    unsigned xb;
+    int n, y0, y1;
     T c, wd, om;
-    T v[R];   // latest value of rows kk-4 .. kk
-    T fr[R];  // f of rows kk-3 .. kk+1 (kk+1 in flight)
+    T va[R], vb[R];   // latest values of rows kk-4 .. kk
+    T fa[R], fb[R];   // f of rows kk-3 .. kk+1 (kk+1 in flight)
 
-    __device__ __forceinline__ T ldf(int y) const {
-        return ld_off(f + (size_t)min(max(y, 0), n - 1) * n, xb);
-    }
-    // half-sweep q of colour col on row y (value a), rows below / above bv / av
-    template <int q>
-    __device__ __forceinline__ void half(T& a, T bv, T av, T fv, int y, int col) {
-        const T uw = lane_prev(a), ue = lane_next(a);  // every lane active
-        const T r = res_lap2(a, uw, ue, bv, av, fv, c);
-        const T nv = stored<ST>(relax<T, false>(a, r, T(0), c, wd, om));
-        if (coli && lane >= q && lane <= BX - 1 - q && y >= 1 && y <= n - 2 && ((gx + y) & 1) == col) a = nv;
-    }
     template <int P>
     __device__ __forceinline__ void step(int kk) {
         constexpr int S0 = P, S1 = (P + 4) % R, S2 = (P + 3) % R, S3 = (P + 2) % R, S4 = (P + 1) % R;
-        fr[S4] = ldf(kk + 1);  // slot of row kk-4, whose f is no longer read
+        {
+            const MG_GLOBAL ST* fr = pr.row(f, kk + 1);
+            fa[S4] = ld_off(fr, pr.ba);
+            fb[S4] = ld_off(fr, pr.bb);
+        }
         {
             const T zero = T(0);
-            const T r = res_lap2(zero, zero, zero, zero, zero, fr[S0], c);
-            const T nv = stored<ST>(relax<T, false>(zero, r, zero, c, wd, om));
-            v[S0] = (coli && kk >= 1 && kk <= n - 2 && ((gx + kk) & 1) == 0) ? nv : zero;
+            const bool zin = kk >= 1 && kk <= n - 2;
+            const T ra = res_lap2(zero, zero, zero, zero, zero, fa[S0], c);
+            const T rb = res_lap2(zero, zero, zero, zero, zero, fb[S0], c);
+            const T na = stored<ST>(relax<T, false>(zero, ra, zero, c, wd, om));
+            const T nb = stored<ST>(relax<T, false>(zero, rb, zero, c, wd, om));
+            const bool a_red = ((pr.xs + kk) & 1) == 0;
+            va[S0] = (zin && pr.ia && a_red) ? na : zero;
+            vb[S0] = (zin && pr.ib && !a_red) ? nb : zero;
         }
-        if (kk - 1 >= y0 - 2) half<1>(v[S1], v[S2], v[S0], fr[S1], kk - 1, 1);
-        if (kk - 2 >= y0 - 1) half<2>(v[S2], v[S3], v[S1], fr[S2], kk - 2, 0);
+        if (kk - 1 >= y0 - 2)
+            pr.template half<1>(va[S1], vb[S1], va[S2], vb[S2], va[S0], vb[S0], fa[S1], fb[S1], kk - 1, 1, c, wd, om);
+        if (kk - 2 >= y0 - 1)
+            pr.template half<2>(va[S2], vb[S2], va[S3], vb[S3], va[S1], vb[S1], fa[S2], fb[S2], kk - 2, 0, c, wd, om);
         const int y3 = kk - 3;
         if (y3 >= y0 && y3 < y1) {
-            half<3>(v[S3], v[S4], v[S2], fr[S3], y3, 1);
-            if (coli && lane >= H && lane <= BX - 1 - H && y3 >= 1 && y3 <= n - 2)
-                st_off(uout + (size_t)y3 * n, xb, (ST)v[S3]);
+            pr.template half<3>(va[S3], vb[S3], va[S4], vb[S4], va[S2], vb[S2], fa[S3], fb[S3], y3, 1, c, wd, om);
+            if (y3 >= 1 && y3 <= n - 2) {
+                MG_GLOBAL ST* o = uout + (size_t)y3 * n;
+                if (pr.ia && pr.template va_ok<H>()) st_off(o, pr.ba, (ST)va[S3]);
+                if (pr.ib && pr.template vb_ok<H>()) st_off(o, pr.bb, (ST)vb[S3]);
+            }
         }
     }
     __device__ __forceinline__ void run() {
-        xb = (unsigned)min(max(gx, 0), n - 1) * (unsigned)sizeof(ST);
-        coli = gx >= 1 && gx <= n - 2;
+        pr.init();
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = fr[q] = T(0);
+        for (int q = 0; q < R; ++q) va[q] = vb[q] = fa[q] = fb[q] = T(0);
         int kk = y0 - H;
         const int kend = y1 - 1 + H;
-        fr[0] = ldf(kk);
+        {
+            const MG_GLOBAL ST* fr = pr.row(f, kk);
+            fa[0] = ld_off(fr, pr.ba);
+            fb[0] = ld_off(fr, pr.bb);
+        }
         for (; kk + 4 <= kend; kk += R) {
             step<0>(kk);
             step<1>(kk + 1);
@@ -236,9 +287,9 @@ __global__ __launch_bounds__(NT) void k_smooth2d_zg2(const GridDesc* __restrict_
     const int tx = tile % ntx, tb = tile / ntx;
     const int w = threadIdx.x >> 6;
     s.n = n;
-    s.lane = threadIdx.x & 63;
-    s.x0 = 1 + tx * S::TX;
-    s.gx = s.x0 - S::H + s.lane;
+    s.pr.n = n;
+    s.pr.lane = threadIdx.x & 63;
+    s.pr.xs = 1 + tx * S::TX - S::H;
     s.y0 = min(1 + (tb * 4 + w) * ychunk, n - 1);
     s.y1 = min(s.y0 + ychunk, n - 1);
     if (s.y0 >= s.y1) return;  // a wavefront past the last chunk (no barrier follows)
@@ -254,84 +305,99 @@ __global__ __launch_bounds__(NT) void k_smooth2d_zg2(const GridDesc* __restrict_
 // 2D Laplacian: the first two red-black post-smoothing sweeps in one launch,
 // the first with the coarse-grid correction (Algorithm 1: interpolation and
 // correction, postsmoothing) added as each row enters.  A wavefront marches
-// a 64-wide strip along y through a chunk of rows: step kk corrects row kk
-// (u + P uc at inner nodes, the bilinear weights of the separate sweep), the
-// first colour of row kk-1, the second of kk-2, the first of kk-3 and the
-// second of kk-4, which it writes to the ping-pong partner of its input.  The
-// half-sweeps are valid one lane narrower per side each, so a strip writes
-// 56 nodes per row; a six-row register ring holds every node's latest value
-// and a six-row ring f.  Colours follow the select's black-first bit (the
-// symmetric smoother relaxes black first after the correction).
+// a strip of 128 nodes (two per lane) along y through a chunk of rows: step
+// kk corrects row kk (u + P uc at inner nodes, the bilinear weights of the
+// separate sweep), the first colour of row kk-1, the second of kk-2, the
+// first of kk-3 and the second of kk-4, which it writes to the ping-pong
+// partner of its input.  The half-sweeps are valid one node narrower per
+// side each, so a strip writes 120 nodes per row; six-row register rings
+// hold every node's latest value and f.  Colours follow the select's
+// black-first bit (the symmetric smoother relaxes black first after the
+// correction).
 // ---------------------------------------------------------------------------
 template <typename ST>
 struct Sweep2Pro {
     using T = arith_t<ST>;
-    static constexpr int H = 4, TX = BX - 2 * H, R = 6;
+    static constexpr int H = 4, R = 6;
+    using PR = PairRow<ST, H>;
+    static constexpr int TX = PR::TX;
+    PR pr;
     const MG_GLOBAL ST* __restrict__ uin;
     MG_GLOBAL ST* __restrict__ uout;
     const MG_GLOBAL ST* __restrict__ f;
     const MG_GLOBAL ST* __restrict__ ec;
-    int n, nc, x0, y0, y1, gx, lane, cfirst;
-    bool coli, xo;
-    unsigned xb, cxb;
+    int n, nc, y0, y1, cfirst;
+    unsigned cbb;  // byte offset of the coarse column of the b-node (xs odd: b is even, a = b - 1 is odd)
+    unsigned cab;  // byte offset of the coarse column left of the a-node
     T c, wd, om;
-    T v[R];   // latest value of rows kk-5 .. kk
-    T fr[R];  // f of rows kk-4 .. kk+1 (kk+1 in flight)
-    T un;     // u of row kk+1 (in flight)
+    T va[R], vb[R];   // latest values of rows kk-5 .. kk
+    T fa[R], fb[R];   // f of rows kk-4 .. kk+1 (kk+1 in flight)
+    T ua, ub;         // u of row kk+1 (in flight)
 
-    __device__ __forceinline__ T ldrow(const MG_GLOBAL ST* a, int y) const {
-        return ld_off(a + (size_t)min(max(y, 0), n - 1) * n, xb);
-    }
-    // u + P uc at row y (bilinear, as the separate sweep; inner nodes only)
-    __device__ __forceinline__ T corrected(T u, int y) const {
+    // (a, b) += P uc at row y (bilinear, as the separate sweep; inner nodes only)
+    __device__ __forceinline__ void correct(T& a, T& b, int y) const {
         const int ycl = min(max(y, 0), n - 1);
         const MG_GLOBAL ST* __restrict__ r0 = ec + (size_t)(ycl >> 1) * nc;
-        const T a = ld_off(r0, cxb), b = ld_off(r0 + ((ycl & 1) ? nc : 0), cxb);
-        const T an = lane_next(a), bn = lane_next(b);  // every lane active
-        const T sa = xo ? a + an : a;
-        const T sb = xo ? b + bn : b;
-        const T corr = (ycl & 1) ? (xo ? T(0.25) * (sa + sb) : T(0.5) * (sa + sb)) : (xo ? T(0.5) * sa : sa);
-        const bool inn = coli && y >= 1 && y <= n - 2;
-        return inn ? stored<ST>(u + corr) : u;
-    }
-    template <int q>
-    __device__ __forceinline__ void half(T& a, T bv, T av, T fv, int y, int col) {
-        const T uw = lane_prev(a), ue = lane_next(a);  // every lane active
-        const T r = res_lap2(a, uw, ue, bv, av, fv, c);
-        const T nv = stored<ST>(relax<T, false>(a, r, T(0), c, wd, om));
-        if (coli && lane >= q && lane <= BX - 1 - q && y >= 1 && y <= n - 2 && ((gx + y) & 1) == col) a = nv;
+        const MG_GLOBAL ST* __restrict__ r1 = r0 + ((ycl & 1) ? nc : 0);
+        const T c0 = ld_off(r0, cbb), c1 = ld_off(r1, cbb);  // column of b (and right of a)
+        const T p0 = ld_off(r0, cab), p1 = ld_off(r1, cab);  // column left of a
+        // a (odd x): the coarse columns left and right; b (even x): its own column
+        const T sa0 = p0 + c0, sa1 = p1 + c1;
+        const T ca = (ycl & 1) ? T(0.25) * (sa0 + sa1) : T(0.5) * sa0;
+        const T cb = (ycl & 1) ? T(0.5) * (c0 + c1) : c0;
+        const bool yin = y >= 1 && y <= n - 2;
+        if (yin && pr.ia) a = stored<ST>(a + ca);
+        if (yin && pr.ib) b = stored<ST>(b + cb);
     }
     template <int P>
     __device__ __forceinline__ void step(int kk) {
         constexpr int S0 = P, S1 = (P + 5) % R, S2 = (P + 4) % R, S3 = (P + 3) % R, S4 = (P + 2) % R,
                       S5 = (P + 1) % R;
         const int c1 = cfirst, c2 = cfirst ^ 1;
-        v[S0] = corrected(un, kk);
-        un = ldrow(uin, kk + 1);
-        fr[S5] = ldrow(f, kk + 1);  // slot of row kk-5, whose f is no longer read
-        if (kk - 1 >= y0 - 3) half<1>(v[S1], v[S2], v[S0], fr[S1], kk - 1, c1);
-        if (kk - 2 >= y0 - 2) half<2>(v[S2], v[S3], v[S1], fr[S2], kk - 2, c2);
-        if (kk - 3 >= y0 - 1) half<3>(v[S3], v[S4], v[S2], fr[S3], kk - 3, c1);
+        va[S0] = ua;
+        vb[S0] = ub;
+        correct(va[S0], vb[S0], kk);
+        {
+            const MG_GLOBAL ST* ur = pr.row(uin, kk + 1);
+            ua = ld_off(ur, pr.ba);
+            ub = ld_off(ur, pr.bb);
+            const MG_GLOBAL ST* fr = pr.row(f, kk + 1);
+            fa[S5] = ld_off(fr, pr.ba);  // slot of row kk-5, whose f is no longer read
+            fb[S5] = ld_off(fr, pr.bb);
+        }
+        if (kk - 1 >= y0 - 3)
+            pr.template half<1>(va[S1], vb[S1], va[S2], vb[S2], va[S0], vb[S0], fa[S1], fb[S1], kk - 1, c1, c, wd, om);
+        if (kk - 2 >= y0 - 2)
+            pr.template half<2>(va[S2], vb[S2], va[S3], vb[S3], va[S1], vb[S1], fa[S2], fb[S2], kk - 2, c2, c, wd, om);
+        if (kk - 3 >= y0 - 1)
+            pr.template half<3>(va[S3], vb[S3], va[S4], vb[S4], va[S2], vb[S2], fa[S3], fb[S3], kk - 3, c1, c, wd, om);
         const int y4 = kk - 4;
         if (y4 >= y0 && y4 < y1) {
-            half<4>(v[S4], v[S5], v[S3], fr[S4], y4, c2);
-            if (coli && lane >= H && lane <= BX - 1 - H && y4 >= 1 && y4 <= n - 2)
-                st_off(uout + (size_t)y4 * n, xb, (ST)v[S4]);
+            pr.template half<4>(va[S4], vb[S4], va[S5], vb[S5], va[S3], vb[S3], fa[S4], fb[S4], y4, c2, c, wd, om);
+            if (y4 >= 1 && y4 <= n - 2) {
+                MG_GLOBAL ST* o = uout + (size_t)y4 * n;
+                if (pr.ia && pr.template va_ok<H>()) st_off(o, pr.ba, (ST)va[S4]);
+                if (pr.ib && pr.template vb_ok<H>()) st_off(o, pr.bb, (ST)vb[S4]);
+            }
         }
     }
     __device__ __forceinline__ void run() {
-        const int xc = min(max(gx, 0), n - 1);
-        xb = (unsigned)xc * (unsigned)sizeof(ST);
-        // x0 is odd and the halo even: even lanes hold odd x and pair with the next lane
-        cxb = (unsigned)(xc >> 1) * (unsigned)sizeof(ST);
-        xo = (gx & 1) != 0;
-        coli = gx >= 1 && gx <= n - 2;
+        pr.init();
+        const int xb = pr.xs + 2 * pr.lane + 1;
+        cbb = (unsigned)(min(max(xb, 0), n - 1) >> 1) * (unsigned)sizeof(ST);
+        cab = (unsigned)(min(max(xb - 2, 0), n - 1) >> 1) * (unsigned)sizeof(ST);
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = fr[q] = T(0);
+        for (int q = 0; q < R; ++q) va[q] = vb[q] = fa[q] = fb[q] = T(0);
         int kk = y0 - H;
         const int kend = y1 - 1 + H;
-        un = ldrow(uin, kk);
-        fr[0] = ldrow(f, kk);
+        {
+            const MG_GLOBAL ST* ur = pr.row(uin, kk);
+            ua = ld_off(ur, pr.ba);
+            ub = ld_off(ur, pr.bb);
+            const MG_GLOBAL ST* fr = pr.row(f, kk);
+            fa[0] = ld_off(fr, pr.ba);
+            fb[0] = ld_off(fr, pr.bb);
+        }
         for (; kk + 5 <= kend; kk += R) {
             step<0>(kk);
             step<1>(kk + 1);
@@ -362,9 +428,9 @@ __global__ __launch_bounds__(NT) void k_smooth2d_pro2(const GridDesc* __restrict
     const int w = threadIdx.x >> 6;
     s.n = n;
     s.nc = (n - 1) / 2 + 1;
-    s.lane = threadIdx.x & 63;
-    s.x0 = 1 + tx * S::TX;
-    s.gx = s.x0 - S::H + s.lane;
+    s.pr.n = n;
+    s.pr.lane = threadIdx.x & 63;
+    s.pr.xs = 1 + tx * S::TX - S::H;  // odd
     s.y0 = min(1 + (tb * 4 + w) * ychunk, n - 1);
     s.y1 = min(s.y0 + ychunk, n - 1);
     if (s.y0 >= s.y1) return;  // a wavefront past the last chunk (no barrier follows)
@@ -383,7 +449,7 @@ __global__ __launch_bounds__(NT) void k_smooth2d_pro2(const GridDesc* __restrict
 
 int smooth2d_pro2_tiles(int n, int ychunk) {
     const int m = n - 2;
-    return cdiv(m, BX - 8) * cdiv(cdiv(m, ychunk), 4);
+    return cdiv(m, 2 * BX - 8) * cdiv(cdiv(m, ychunk), 4);
 }
 
 template <typename T>
@@ -403,7 +469,7 @@ template hipError_t launch_smooth2d_pro2<half_t>(const GridDesc*, int, int, int,
 
 int smooth2d_zg2_tiles(int n, int ychunk) {
     const int m = n - 2;
-    return cdiv(m, BX - 6) * cdiv(cdiv(m, ychunk), 4);
+    return cdiv(m, 2 * BX - 6) * cdiv(cdiv(m, ychunk), 4);
 }
 
 template <typename T>
