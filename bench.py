@@ -708,6 +708,10 @@ def main(argv=None) -> int:
         roofline, other = pass_roof, sweep_roof
     else:
         roofline, other = sweep_roof, pass_roof
+    if not other["launches"]:
+        # no launch of that kernel in the timed solves (2D levels run their
+        # sweeps as the fused pairs): nothing to report
+        other = None
     log(f"[bench] finest sweep {sweep_roof['avg_launch_ms'] * 1e3:.1f} us x {launches}: "
         f"{sweep_roof['achieved']:.0f} GB/s; refinement/norm pass {pass_roof['avg_launch_ms'] * 1e3:.1f} us x "
         f"{pass_launches}: {pass_roof['achieved']:.0f} GB/s")
