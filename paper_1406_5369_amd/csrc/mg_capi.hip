@@ -809,8 +809,7 @@ hipError_t cd_fas_level(CDState& S, int l, void*& cur, void*& other, const void*
     const size_t c1 = (size_t)l + 1;
     void* ucur = S.u[c1];
     void* uoth = S.t[c1];
-    if ((e = cd_compute_g(cur, S.g[(size_t)l], N, S.K, s)) != hipSuccess) return e;
-    if ((e = cd_restrict(S.dim, cur, f, S.g[(size_t)l], S.uh[c1], S.f[c1], S.K, L, s)) != hipSuccess) return e;
+    if ((e = cd_restrict(S.dim, cur, f, S.uh[c1], S.f[c1], S.K, L, s)) != hipSuccess) return e;
     if ((e = cd_compute_g(S.uh[c1], S.g[c1], cd_cells(S, l + 1), S.K, s)) != hipSuccess) return e;
     if ((e = cd_coarse_rhs(S.dim, S.uh[c1], S.g[c1], S.f[c1], ucur, S.K, Lc, s)) != hipSuccess) return e;
     if ((e = cd_fas_level(S, l + 1, ucur, uoth, S.f[c1], s)) != hipSuccess) return e;
@@ -831,8 +830,7 @@ hipError_t cd_fas_top(CDState& S, void* u, const void* f, hipStream_t s) {
 
 // ||f - N(u)|| (g of u) to the host
 int cd_norm_host(CDState& S, const void* u, const void* f, hipStream_t s, double* out) {
-    CK(cd_compute_g(u, S.g[0], cd_cells(S, 0), S.K, s));
-    CK(cd_norm(S.dim, u, f, S.g[0], S.K, cd_level(S.n), S.part, S.norm, s));
+    CK(cd_norm(S.dim, u, f, S.K, cd_level(S.n), S.part, S.norm, s));
     CK(hipMemcpyAsync(S.h_norm, S.norm, sizeof(double), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     *out = S.h_norm[0];

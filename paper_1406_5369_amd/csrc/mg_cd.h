@@ -29,15 +29,17 @@ bool cd_tiled(int dim, int n);
 // with the diffusivity of uin, in tiles.
 hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const void* f, CDConst K, CDLevel L,
                     hipStream_t s);
-hipError_t cd_restrict(int dim, const void* u, const void* f, const void* g, void* uh, void* rc, CDConst K,
-                       CDLevel L, hipStream_t s);
+// uh = R u, rc = R (f - N(u)) with g of u formed on the fly (n >= 2)
+hipError_t cd_restrict(int dim, const void* u, const void* f, void* uh, void* rc, CDConst K, CDLevel L,
+                       hipStream_t s);
 hipError_t cd_coarse_rhs(int dim, const void* uh, const void* gc, void* fc, void* uc, CDConst K, CDLevel Lc,
                          hipStream_t s);
 hipError_t cd_prolong(int dim, void* u, const void* uc, const void* uh, int n, hipStream_t s);
 hipError_t cd_scale(const void* a, void* out, size_t N, double sc, hipStream_t s);
 hipError_t cd_apply_op(int dim, const void* u, const void* g, void* out, CDConst K, CDLevel L, hipStream_t s);
 int cd_norm_parts(int dim, int n);
-hipError_t cd_norm(int dim, const void* u, const void* f, const void* g, CDConst K, CDLevel L, double* part,
-                   double* norm, hipStream_t s);
+// ||f - N(u)|| (g of u formed on the fly) into *norm (device), part: cd_norm_parts doubles
+hipError_t cd_norm(int dim, const void* u, const void* f, CDConst K, CDLevel L, double* part, double* norm,
+                   hipStream_t s);
 
 }  // namespace mg

@@ -135,51 +135,6 @@ __global__ __launch_bounds__(NT) void k_cd_relax(const Cx* uin_, Cx* uout_, cons
     stc(gp(uout_), p, cx_add(up, cx_scale(K.omega, cx_div(r, D))));
 }
 
-// Per coarse cell: uh = average of the children's u, rc = average of the
-// children's residuals f - N(u) (g of u), componentwise in the order of the
-// cell-centred restriction.
-template <int DIM>
-__global__ __launch_bounds__(NT) void k_cd_restrict(const Cx* __restrict__ u_, const Cx* __restrict__ f_,
-                                                    const Cx* __restrict__ g_, Cx* __restrict__ uh_,
-                                                    Cx* __restrict__ rc_, CDConst K, CDLevel L) {
-    const int n = L.n, nc = n / 2;
-    const size_t Nc = DIM == 2 ? (size_t)nc * nc : (size_t)nc * nc * nc;
-    const size_t q = (size_t)blockIdx.x * NT + threadIdx.x;
-    if (q >= Nc) return;
-    int I, J, KK;
-    cd_ijk<DIM>(q, nc, I, J, KK);
-    const MG_GLOBAL Cx* u = gp(u_);
-    const MG_GLOBAL Cx* f = gp(f_);
-    const MG_GLOBAL Cx* g = gp(g_);
-    auto at = [&](int i, int j, int k) { return ((size_t)k * n + j) * n + i; };
-    auto res = [&](int i, int j, int k) {
-        const size_t p = at(i, j, k);
-        return cx_sub(ldc(f, p), cd_apply<DIM>(u, g, n, L.c, K.itau, i, j, k, p));
-    };
-    const int i = 2 * I, j = 2 * J, k = 2 * KK;
-    const Cx r00 = res(i, j, k), r10 = res(i + 1, j, k), r01 = res(i, j + 1, k), r11 = res(i + 1, j + 1, k);
-    const Cx u00 = ldc(u, at(i, j, k)), u10 = ldc(u, at(i + 1, j, k)), u01 = ldc(u, at(i, j + 1, k)),
-             u11 = ldc(u, at(i + 1, j + 1, k));
-    const Cx rq0 = cx_add(cx_add(r00, r10), cx_add(r01, r11));
-    const Cx uq0 = cx_add(cx_add(u00, u10), cx_add(u01, u11));
-    Cx rv, uv;
-    if constexpr (DIM == 2) {
-        rv = cx_scale(0.25, rq0);
-        uv = cx_scale(0.25, uq0);
-    } else {
-        const Cx s00 = res(i, j, k + 1), s10 = res(i + 1, j, k + 1), s01 = res(i, j + 1, k + 1),
-                 s11 = res(i + 1, j + 1, k + 1);
-        const Cx v00 = ldc(u, at(i, j, k + 1)), v10 = ldc(u, at(i + 1, j, k + 1)), v01 = ldc(u, at(i, j + 1, k + 1)),
-                 v11 = ldc(u, at(i + 1, j + 1, k + 1));
-        const Cx rq1 = cx_add(cx_add(s00, s10), cx_add(s01, s11));
-        const Cx uq1 = cx_add(cx_add(v00, v10), cx_add(v01, v11));
-        rv = cx_scale(0.125, cx_add(rq0, rq1));
-        uv = cx_scale(0.125, cx_add(uq0, uq1));
-    }
-    stc(gp(rc_), q, rv);
-    stc(gp(uh_), q, uv);
-}
-
 // fc = N_c(uh) + rc (in place over rc), uc = uh; gc = g(uh)
 template <int DIM>
 __global__ __launch_bounds__(NT) void k_cd_coarse_rhs(const Cx* __restrict__ uh_, const Cx* __restrict__ gc_,
@@ -230,26 +185,6 @@ __global__ __launch_bounds__(NT) void k_cd_apply(const Cx* __restrict__ u_, cons
     int i, j, k;
     cd_ijk<DIM>(p, n, i, j, k);
     stc(gp(out), p, cd_apply<DIM>(gp(u_), gp(g_), n, L.c, K.itau, i, j, k, p));
-}
-
-// per-block partial sums of |f - N(u)|^2 (re^2 + im^2)
-template <int DIM>
-__global__ __launch_bounds__(NT) void k_cd_norm(const Cx* __restrict__ u_, const Cx* __restrict__ f_,
-                                                const Cx* __restrict__ g_, CDConst K, CDLevel L,
-                                                double* __restrict__ part) {
-    __shared__ double red4[4];
-    const int n = L.n;
-    const size_t N = DIM == 2 ? (size_t)n * n : (size_t)n * n * n;
-    const size_t p = (size_t)blockIdx.x * NT + threadIdx.x;
-    double acc = 0.0;
-    if (p < N) {
-        int i, j, k;
-        cd_ijk<DIM>(p, n, i, j, k);
-        const Cx r = cx_sub(ldc(gp(f_), p), cd_apply<DIM>(gp(u_), gp(g_), n, L.c, K.itau, i, j, k, p));
-        acc = r.re * r.re + r.im * r.im;
-    }
-    const double s = block_sum(acc, red4);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -547,6 +482,171 @@ __global__ __launch_bounds__(NT) void k_cd_sweep3d(const Cx* __restrict__ uin_, 
     s.run();
 }
 
+// ---------------------------------------------------------------------------
+// Residual blocks: one wavefront per coarse row (2D) or per coarse row of a
+// coarse plane (3D), four consecutive coarse rows per workgroup, lane =
+// coarse x.  A lane loads u of its children's fine x (2X, 2X+1) on the fine
+// rows 2J-1 .. 2J+2 of its children's planes and, in 3D, on rows 2J, 2J+1 of
+// planes 2K-1 and 2K+2, forms q of each value once (the diffusivity of u,
+// the products of the operator kernels), and takes the x neighbours of its
+// children from the adjacent lanes (the lanes at the wavefront's two ends
+// load theirs).  Every fine value is loaded once per wavefront, 16 B per lane
+// and load, instead of once per face that reads it, and g needs no array.
+// From these the lane forms its children's residuals f - N(u), per cell in
+// the order of cd_apply, and either restricts them and u (the cell-centred
+// averages, in k_cd_restrict's former order: (c00 + c10) + (c01 + c11) per
+// fine plane, then the planes) or sums their squares (the norm).
+// ---------------------------------------------------------------------------
+template <int DIM, bool NORM>
+__global__ __launch_bounds__(NT) void k_cd_resblk(const Cx* __restrict__ u_, const Cx* __restrict__ f_,
+                                                  Cx* __restrict__ uh_, Cx* __restrict__ rc_, CDConst K, CDLevel L,
+                                                  double* __restrict__ part) {
+    constexpr int NP = DIM == 3 ? 4 : 1;   // planes 2K-1 .. 2K+2 (3D), the one plane (2D)
+    constexpr int P0 = DIM == 3 ? 1 : 0;   // first of the children's planes
+    constexpr int NPC = DIM == 3 ? 2 : 1;  // children's planes
+    __shared__ double red4[4];
+    const int n = L.n, nc = n / 2;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ntx = (nc + 63) >> 6, nty = (nc + 3) >> 2;
+    const int tx = (int)(blockIdx.x % (unsigned)ntx), b2 = (int)(blockIdx.x / (unsigned)ntx);
+    const int J = (b2 % nty) * 4 + w, KK = DIM == 3 ? b2 / nty : 0;
+    const int X = tx * 64 + lane;
+    const bool live = X < nc && J < nc;  // KK < nc by the grid
+    const MG_GLOBAL Cx* u = gp(u_);
+    const MG_GLOBAL Cx* f = gp(f_);
+    const size_t pl = (size_t)n * n;
+    // in-bounds addresses for every lane (lanes past the row load the last
+    // pair; only live lanes use their values)
+    const int xa = min(2 * X, n - 2);
+    const int xe = lane == 0 ? max(2 * X - 1, 0) : min(2 * X + 2, n - 1);
+    auto row_at = [&](int p, int r) -> size_t {
+        const int y = min(max(2 * J - 1 + r, 0), n - 1);
+        const int z = DIM == 3 ? min(max(2 * KK - 1 + p, 0), n - 1) : 0;
+        return (size_t)z * pl + (size_t)y * n;
+    };
+    auto needed = [](int p, int r) { return DIM == 2 || p == 1 || p == 2 || r == 1 || r == 2; };
+
+    Cx U[NP][4][2];
+    double Q[NP][4][2];
+    Cx Ue[NPC][2], Fv[NPC][2][2];
+    double Qe[NPC][2];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (needed(p, r)) {
+                const size_t a = row_at(p, r) + (size_t)xa;
+                U[p][r][0] = ldc(u, a);
+                U[p][r][1] = ldc(u, a + 1);
+            }
+#pragma unroll
+    for (int pc = 0; pc < NPC; ++pc)
+#pragma unroll
+        for (int rc = 0; rc < 2; ++rc) {
+            const size_t a = row_at(P0 + pc, 1 + rc);
+            Ue[pc][rc] = ldc(u, a + (size_t)xe);
+            Fv[pc][rc][0] = ldc(f, a + (size_t)xa);
+            Fv[pc][rc][1] = ldc(f, a + (size_t)xa + 1);
+        }
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (needed(p, r)) {
+                Q[p][r][0] = cd_q(K, U[p][r][0]);
+                Q[p][r][1] = cd_q(K, U[p][r][1]);
+            }
+#pragma unroll
+    for (int pc = 0; pc < NPC; ++pc)
+#pragma unroll
+        for (int rc = 0; rc < 2; ++rc) Qe[pc][rc] = cd_q(K, Ue[pc][rc]);
+
+    // residual of the child at fine (2X + e, 2J + rc, 2K + pc)
+    Cx R[NPC][2][2];
+#pragma unroll
+    for (int pc = 0; pc < NPC; ++pc)
+#pragma unroll
+        for (int rc = 0; rc < 2; ++rc)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int p = P0 + pc, r = 1 + rc;
+                const int x = 2 * X + e, y = 2 * J + rc, z = 2 * KK + pc;
+                const Cx up = U[p][r][e];
+                const double qp = Q[p][r][e];
+                const Cx gpv{K.ct * qp, K.st * qp};
+                Cx uw, ue;
+                double qw, qe;
+                if (e == 0) {
+                    uw = Cx{lane_prev(U[p][r][1].re), lane_prev(U[p][r][1].im)};
+                    qw = lane_prev(Q[p][r][1]);
+                    if (lane == 0) {
+                        uw = Ue[pc][rc];
+                        qw = Qe[pc][rc];
+                    }
+                    ue = U[p][r][1];
+                    qe = Q[p][r][1];
+                } else {
+                    uw = U[p][r][0];
+                    qw = Q[p][r][0];
+                    ue = Cx{lane_next(U[p][r][0].re), lane_next(U[p][r][0].im)};
+                    qe = lane_next(Q[p][r][0]);
+                    if (lane == 63) {
+                        ue = Ue[pc][rc];
+                        qe = Qe[pc][rc];
+                    }
+                }
+                const CDFace fW = cd_face_v(x > 0, up, gpv, uw, qw, K);
+                const CDFace fE = cd_face_v(x < n - 1, up, gpv, ue, qe, K);
+                const CDFace fS = cd_face_v(y > 0, up, gpv, U[p][r - 1][e], Q[p][r - 1][e], K);
+                const CDFace fN = cd_face_v(y < n - 1, up, gpv, U[p][r + 1][e], Q[p][r + 1][e], K);
+                double Fr = (fW.tr + fE.tr) + (fS.tr + fN.tr), Fi = (fW.ti + fE.ti) + (fS.ti + fN.ti);
+                if constexpr (DIM == 3) {
+                    const CDFace fB = cd_face_v(z > 0, up, gpv, U[p - 1][r][e], Q[p - 1][r][e], K);
+                    const CDFace fT = cd_face_v(z < n - 1, up, gpv, U[p + 1][r][e], Q[p + 1][r][e], K);
+                    Fr = Fr + (fB.tr + fT.tr);
+                    Fi = Fi + (fB.ti + fT.ti);
+                }
+                const Cx Nu{K.itau * up.re - L.c * Fr, K.itau * up.im - L.c * Fi};
+                R[pc][rc][e] = cx_sub(Fv[pc][rc][e], Nu);
+            }
+
+    if constexpr (NORM) {
+        double acc = 0.0;
+#pragma unroll
+        for (int pc = 0; pc < NPC; ++pc)
+#pragma unroll
+            for (int rc = 0; rc < 2; ++rc)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const Cx& v = R[pc][rc][e];
+                    acc += v.re * v.re + v.im * v.im;
+                }
+        const double s = block_sum(live ? acc : 0.0, red4);
+        if (threadIdx.x == 0) part[blockIdx.x] = s;
+    } else {
+        if (!live) return;
+        auto quad = [](const Cx (&A)[2][2]) { return cx_add(cx_add(A[0][0], A[0][1]), cx_add(A[1][0], A[1][1])); };
+        Cx uq[NPC][2][2];
+#pragma unroll
+        for (int pc = 0; pc < NPC; ++pc)
+#pragma unroll
+            for (int rc = 0; rc < 2; ++rc)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) uq[pc][rc][e] = U[P0 + pc][1 + rc][e];
+        Cx rv, uv;
+        if constexpr (DIM == 2) {
+            rv = cx_scale(0.25, quad(R[0]));
+            uv = cx_scale(0.25, quad(uq[0]));
+        } else {
+            rv = cx_scale(0.125, cx_add(quad(R[0]), quad(R[1])));
+            uv = cx_scale(0.125, cx_add(quad(uq[0]), quad(uq[1])));
+        }
+        const size_t q = ((size_t)KK * nc + J) * nc + X;
+        stc(gp(rc_), q, rv);
+        stc(gp(uh_), q, uv);
+    }
+}
+
 inline unsigned nblk(size_t N) { return (unsigned)((N + NT - 1) / NT); }
 inline size_t ncells(int dim, int n) { return dim == 2 ? (size_t)n * n : (size_t)n * n * n; }
 
@@ -609,13 +709,20 @@ hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const voi
     return hipGetLastError();
 }
 
-hipError_t cd_restrict(int dim, const void* u, const void* f, const void* g, void* uh, void* rc, CDConst K,
-                       CDLevel L, hipStream_t s) {
-    const unsigned b = nblk(ncells(dim, L.n / 2));
+static unsigned cd_resblk_blocks(int dim, int n) {
+    const unsigned nc = (unsigned)(n / 2);
+    const unsigned b = ((nc + 63) / 64) * ((nc + 3) / 4);
+    return dim == 3 ? b * nc : b;
+}
+
+hipError_t cd_restrict(int dim, const void* u, const void* f, void* uh, void* rc, CDConst K, CDLevel L,
+                       hipStream_t s) {
+    if (L.n < 2) return hipErrorInvalidValue;
+    const unsigned b = cd_resblk_blocks(dim, L.n);
     if (dim == 2)
-        k_cd_restrict<2><<<b, NT, 0, s>>>((const Cx*)u, (const Cx*)f, (const Cx*)g, (Cx*)uh, (Cx*)rc, K, L);
+        k_cd_resblk<2, false><<<b, NT, 0, s>>>((const Cx*)u, (const Cx*)f, (Cx*)uh, (Cx*)rc, K, L, nullptr);
     else
-        k_cd_restrict<3><<<b, NT, 0, s>>>((const Cx*)u, (const Cx*)f, (const Cx*)g, (Cx*)uh, (Cx*)rc, K, L);
+        k_cd_resblk<3, false><<<b, NT, 0, s>>>((const Cx*)u, (const Cx*)f, (Cx*)uh, (Cx*)rc, K, L, nullptr);
     return hipGetLastError();
 }
 
@@ -648,13 +755,14 @@ hipError_t cd_apply_op(int dim, const void* u, const void* g, void* out, CDConst
     return hipGetLastError();
 }
 
-int cd_norm_parts(int dim, int n) { return (int)nblk(ncells(dim, n)); }
+int cd_norm_parts(int dim, int n) { return (int)cd_resblk_blocks(dim, n); }
 
-hipError_t cd_norm(int dim, const void* u, const void* f, const void* g, CDConst K, CDLevel L, double* part,
-                   double* norm, hipStream_t s) {
+hipError_t cd_norm(int dim, const void* u, const void* f, CDConst K, CDLevel L, double* part, double* norm,
+                   hipStream_t s) {
+    if (L.n < 2) return hipErrorInvalidValue;
     const int np = cd_norm_parts(dim, L.n);
-    if (dim == 2) k_cd_norm<2><<<np, NT, 0, s>>>((const Cx*)u, (const Cx*)f, (const Cx*)g, K, L, part);
-    else k_cd_norm<3><<<np, NT, 0, s>>>((const Cx*)u, (const Cx*)f, (const Cx*)g, K, L, part);
+    if (dim == 2) k_cd_resblk<2, true><<<np, NT, 0, s>>>((const Cx*)u, (const Cx*)f, nullptr, nullptr, K, L, part);
+    else k_cd_resblk<3, true><<<np, NT, 0, s>>>((const Cx*)u, (const Cx*)f, nullptr, nullptr, K, L, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_norm_finalize(part, np, np, 0, 1, norm, s);
