@@ -483,6 +483,233 @@ __global__ __launch_bounds__(NT) void k_cd_sweep3d(const Cx* __restrict__ uin_, 
 }
 
 // ---------------------------------------------------------------------------
+// Red-black sweeps with row pairs.  The colours alternate along x, so with
+// one cell per lane half the lanes of every row idle in each half-sweep.
+// Here a thread owns two vertically adjacent cells of its column (box rows
+// 2p and 2p+1): exactly one of them is red (row 2p when x + y (+ z) of row 2p
+// is even), so each half-sweep relaxes one cell per thread and no lane
+// idles.  LDS reads and the global f load take the per-lane row; register
+// values (3D z-neighbours) are selected per lane.  The arithmetic per cell is
+// that of cd_relax_lds, as in the one-cell-per-lane sweeps.
+// ---------------------------------------------------------------------------
+
+// 2D: a 64 x 16 box per workgroup, row pairs p = w, w + 4 of the box; red on
+// the box minus one ring in place, black on the tile, written out with the
+// red cells.
+__global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
+                                                      const Cx* __restrict__ f_, CDConst K, CDLevel L) {
+    constexpr int H = 2, TX = 64 - 2 * H, TY = CDB_Y - 2 * H, RPT = CDB_Y / 4, NPR = CDB_Y / 8;
+    __shared__ d2v Ub[CDB_Y][64];
+    __shared__ double Qb[CDB_Y][64];
+    const int n = L.n;
+    const int ntx = (n + TX - 1) / TX;
+    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gx = tx * TX - H + lane;
+    const bool xd = gx >= 0 && gx < n;
+    const MG_GLOBAL Cx* uin = gp(uin_);
+    const MG_GLOBAL Cx* f = gp(f_);
+    MG_GLOBAL Cx* uout = gp(uout_);
+    const Cx z0{0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w + 4 * m, gy = ty * TY - H + ly;
+        const bool dom = xd && gy >= 0 && gy < n;
+        const Cx u = dom ? ldc(uin, (size_t)gy * n + gx) : z0;
+        Ub[ly][lane] = to_v(u);
+        Qb[ly][lane] = dom ? cd_q(K, u) : 1.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NPR; ++m) {
+        const int ly0 = 2 * (w + 4 * m), gy0 = ty * TY - H + ly0;
+        const int s = (gx + gy0) & 1;  // red row of the pair
+        const int ly = ly0 + s, gy = gy0 + s;
+        if (xd && gy >= 0 && gy < n && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y - 2)
+            Ub[ly][lane] = to_v(cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, gx, gy, 0, n, z0, 1.0, z0, 1.0,
+                                                    ldc(f, (size_t)gy * n + gx)));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NPR; ++m) {
+        const int ly0 = 2 * (w + 4 * m), gy0 = ty * TY - H + ly0;
+        const int b = 1 - ((gx + gy0) & 1);  // black row of the pair
+        const int lyb = ly0 + b, gyb = gy0 + b;
+        Cx vb = z0;
+        if (xd && gyb >= 0 && gyb < n && lane >= H && lane < 64 - H && lyb >= H && lyb < CDB_Y - H)
+            vb = cd_relax_lds<2, 64>(K, L.c, Ub, Qb, lyb, lane, gx, gyb, 0, n, z0, 1.0, z0, 1.0,
+                                     ldc(f, (size_t)gyb * n + gx));
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int ly = ly0 + e, gy = gy0 + e;
+            if (xd && gy >= 0 && gy < n && lane >= H && lane < 64 - H && ly >= H && ly < CDB_Y - H)
+                stc(uout, (size_t)gy * n + gx, e == b ? vb : lds_c(Ub[ly][lane]));
+        }
+    }
+}
+
+// 3D: a 64 x 2NW box in x-y (NW wavefronts, wavefront w owning the row pair
+// 2w, 2w+1) marching along z through a chunk of planes as CDSweep3 does:
+// step kk: plane kk enters (registers and an LDS ring of three planes); red on
+// plane kk-1 (box minus one ring, in place); black on plane kk-2 (the tile),
+// written out with its red cells.  Each thread keeps its two cells of the
+// last four planes (u, q, f) in registers for the z faces.
+template <int NW>
+struct CDSweep3RB {
+    static constexpr int BY = 2 * NW, H = 2, TX = 64 - 2 * H, TY = BY - 2 * H;
+    d2v (*Ub)[BY][64];
+    double (*Qb)[BY][64];
+    const MG_GLOBAL Cx* uin;
+    const MG_GLOBAL Cx* f;
+    MG_GLOBAL Cx* uout;
+    CDConst K;
+    double c;
+    int n, lane, w, gx, gy0, z0, z1, kstart;
+    size_t pl;
+    bool xd, yd[2];
+    double ure[4][2], uim[4][2], qr[4][2], fre[4][2], fim[4][2];
+    double pur[2], pui[2], pfr[2], pfi[2];  // u and f of the next plane, loaded one step ahead
+
+    __device__ __forceinline__ void prefetch(int z) {
+        const bool zd = z >= 0 && z < n;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            Cx u{0.0, 0.0}, fv{0.0, 0.0};
+            if (yd[e] && zd) {
+                const size_t p = (size_t)z * pl + (size_t)(gy0 + e) * n + gx;
+                u = ldc(uin, p);
+                fv = ldc(f, p);
+            }
+            pur[e] = u.re;
+            pui[e] = u.im;
+            pfr[e] = fv.re;
+            pfi[e] = fv.im;
+        }
+    }
+
+    // register value of ring slot R for the row chosen per lane (e = 0 / 1)
+    template <int R>
+    __device__ __forceinline__ Cx Usel(int e) const {
+        return Cx{e ? ure[R][1] : ure[R][0], e ? uim[R][1] : uim[R][0]};
+    }
+    template <int R>
+    __device__ __forceinline__ double Qsel(int e) const { return e ? qr[R][1] : qr[R][0]; }
+    template <int R>
+    __device__ __forceinline__ Cx Fsel(int e) const {
+        return Cx{e ? fre[R][1] : fre[R][0], e ? fim[R][1] : fim[R][0]};
+    }
+
+    template <int P>
+    __device__ __forceinline__ void step(int kk) {
+        constexpr int R0 = P, R1 = (P + 3) & 3, R2 = (P + 2) & 3, R3 = (P + 1) & 3;  // planes kk .. kk-3
+        const int q = kk - kstart;
+        const int s0 = q % 3, s1 = (q + 2) % 3, s2 = (q + 1) % 3;                     // LDS: kk, kk-1, kk-2
+        const bool zd = kk >= 0 && kk < n;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int ly = 2 * w + e;
+            const Cx u{pur[e], pui[e]};
+            const double qv = (yd[e] && zd) ? cd_q(K, u) : 1.0;
+            ure[R0][e] = u.re;
+            uim[R0][e] = u.im;
+            qr[R0][e] = qv;
+            fre[R0][e] = pfr[e];
+            fim[R0][e] = pfi[e];
+            Ub[s0][ly][lane] = to_v(u);
+            Qb[s0][ly][lane] = qv;
+        }
+        prefetch(kk + 1);  // after the last step this loads a plane nobody reads (inside the grid only)
+        __syncthreads();
+        const int zr = kk - 1;  // red plane
+        if (zr >= z0 - 1 && zr >= 0 && zr <= z1 && zr < n) {
+            const int s = (gx + gy0 + zr) & 1;  // red row of the pair
+            const int ly = 2 * w + s;
+            if ((s ? yd[1] : yd[0]) && lane >= 1 && lane <= 62 && ly >= 1 && ly <= BY - 2) {
+                const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, gx, gy0 + s, zr, n, Usel<R2>(s),
+                                                 Qsel<R2>(s), Usel<R0>(s), Qsel<R0>(s), Fsel<R1>(s));
+                Ub[s1][ly][lane] = to_v(v);
+                if (s) {
+                    ure[R1][1] = v.re;
+                    uim[R1][1] = v.im;
+                } else {
+                    ure[R1][0] = v.re;
+                    uim[R1][0] = v.im;
+                }
+            }
+        }
+        __syncthreads();
+        const int zb = kk - 2;  // black plane (output)
+        if (zb >= z0 && zb < z1) {
+            const int b = 1 - ((gx + gy0 + zb) & 1);  // black row of the pair
+            const int lyb = 2 * w + b;
+            Cx vb{0.0, 0.0};
+            if ((b ? yd[1] : yd[0]) && lane >= 2 && lane <= 61 && lyb >= 2 && lyb <= BY - 3)
+                vb = cd_relax_lds<3, 64>(K, c, Ub[s2], Qb[s2], lyb, lane, gx, gy0 + b, zb, n, Usel<R3>(b),
+                                         Qsel<R3>(b), Usel<R1>(b), Qsel<R1>(b), Fsel<R2>(b));
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int ly = 2 * w + e;
+                if (yd[e] && lane >= 2 && lane <= 61 && ly >= 2 && ly <= BY - 3)
+                    stc(uout, (size_t)zb * pl + (size_t)(gy0 + e) * n + gx,
+                        e == b ? vb : Cx{ure[R2][e], uim[R2][e]});
+            }
+        }
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void run() {
+        const int kend = z1 - 1 + H;
+        int kk = kstart;
+        for (; kk + 3 <= kend; kk += 4) {
+            step<0>(kk);
+            step<1>(kk + 1);
+            step<2>(kk + 2);
+            step<3>(kk + 3);
+        }
+        if (kk <= kend) step<0>(kk);
+        if (kk + 1 <= kend) step<1>(kk + 1);
+        if (kk + 2 <= kend) step<2>(kk + 2);
+    }
+};
+
+template <int NW, int MINW>
+__global__ __launch_bounds__(64 * NW, MINW) void k_cd_sweep3d_rb(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
+                                                           const Cx* __restrict__ f_, CDConst K, CDLevel L, int zc) {
+    using S = CDSweep3RB<NW>;
+    __shared__ d2v Ub[3][S::BY][64];
+    __shared__ double Qb[3][S::BY][64];
+    S s;
+    s.Ub = Ub;
+    s.Qb = Qb;
+    s.uin = gp(uin_);
+    s.f = gp(f_);
+    s.uout = gp(uout_);
+    s.K = K;
+    s.c = L.c;
+    const int n = L.n;
+    s.n = n;
+    const int ntx = (n + S::TX - 1) / S::TX, nty = (n + S::TY - 1) / S::TY;
+    const int tx = blockIdx.x % ntx, t2 = blockIdx.x / ntx, ty = t2 % nty, tz = t2 / nty;
+    s.z0 = tz * zc;
+    s.z1 = min(s.z0 + zc, n);
+    s.kstart = s.z0 - S::H;
+    s.lane = threadIdx.x & 63;
+    s.w = threadIdx.x >> 6;
+    s.gx = tx * S::TX - S::H + s.lane;
+    s.xd = s.gx >= 0 && s.gx < n;
+    s.gy0 = ty * S::TY - S::H + 2 * s.w;
+    s.pl = (size_t)n * n;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        s.yd[e] = s.xd && s.gy0 + e >= 0 && s.gy0 + e < n;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s.ure[q][e] = s.uim[q][e] = s.fre[q][e] = s.fim[q][e] = 0.0, s.qr[q][e] = 1.0;
+    }
+    s.prefetch(s.kstart);
+    s.run();
+}
+
+// ---------------------------------------------------------------------------
 // Residual blocks: one wavefront per coarse row (2D) or per coarse row of a
 // coarse plane (3D), four consecutive coarse rows per workgroup, lane =
 // coarse x.  A lane loads u of its children's fine x (2X, 2X+1) on the fine
@@ -494,8 +721,8 @@ __global__ __launch_bounds__(NT) void k_cd_sweep3d(const Cx* __restrict__ uin_, 
 // and load, instead of once per face that reads it, and g needs no array.
 // From these the lane forms its children's residuals f - N(u), per cell in
 // the order of cd_apply, and either restricts them and u (the cell-centred
-// averages, in k_cd_restrict's former order: (c00 + c10) + (c01 + c11) per
-// fine plane, then the planes) or sums their squares (the norm).
+// averages, (c00 + c10) + (c01 + c11) per fine plane, then the planes) or
+// sums their squares (the norm).
 // ---------------------------------------------------------------------------
 template <int DIM, bool NORM>
 __global__ __launch_bounds__(NT) void k_cd_resblk(const Cx* __restrict__ u_, const Cx* __restrict__ f_,
@@ -685,6 +912,8 @@ hipError_t cd_relax(int dim, bool jacobi, const void* uin, void* uout, const voi
 // 3D levels from this edge on use the marching tiles (below it a march has
 // too few workgroups to hide its latency and the per-cell kernels are faster)
 constexpr int kCDTiled3D = 128;
+// wavefronts (row pairs) per workgroup of the 3D red-black sweep
+constexpr int kCDSweep3Waves = 8, kCDSweep3MinWaves = 2;
 bool cd_tiled(int dim, int n) { return dim == 2 || n >= kCDTiled3D; }
 
 hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const void* f, CDConst K, CDLevel L,
@@ -697,14 +926,20 @@ hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const voi
         const int H = jacobi ? 1 : 2;
         const unsigned b = (unsigned)(((n + 64 - 2 * H - 1) / (64 - 2 * H)) * ((n + CDB_Y - 2 * H - 1) / (CDB_Y - 2 * H)));
         if (jacobi) k_cd_sweep2d<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L);
-        else k_cd_sweep2d<false><<<b, NT, 0, s>>>(ui, uo, ff, K, L);
+        else k_cd_sweep2d_rb<<<b, NT, 0, s>>>(ui, uo, ff, K, L);
     } else {
-        const int H = jacobi ? 1 : 2, zc = 16;
         if (n < kCDTiled3D) return hipErrorInvalidValue;  // small levels take the per-cell kernels
-        const unsigned b = (unsigned)(((n + 64 - 2 * H - 1) / (64 - 2 * H)) *
-                                      ((n + CDB_Y3 - 2 * H - 1) / (CDB_Y3 - 2 * H)) * ((n + zc - 1) / zc));
-        if (jacobi) k_cd_sweep3d<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
-        else k_cd_sweep3d<false><<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
+        auto cdiv = [](int a, int d) { return (unsigned)((a + d - 1) / d); };
+        if (jacobi) {
+            constexpr int zc = 8;
+            const unsigned b = cdiv(n, 64 - 2) * cdiv(n, CDB_Y3 - 2) * cdiv(n, zc);
+            k_cd_sweep3d<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
+        } else {
+            constexpr int NW = kCDSweep3Waves, zc = 16;
+            using S = CDSweep3RB<NW>;
+            const unsigned b = cdiv(n, S::TX) * cdiv(n, S::TY) * cdiv(n, zc);
+            k_cd_sweep3d_rb<NW, kCDSweep3MinWaves><<<b, 64 * NW, 0, s>>>(ui, uo, ff, K, L, zc);
+        }
     }
     return hipGetLastError();
 }
