@@ -264,12 +264,11 @@ __device__ __forceinline__ Cx cd_relax_lds(const CDConst& K, double c, const d2v
     return cd_relax_v(K, c, up, Cx{Fr, Fi}, Cx{Sr, Si}, fv);
 }
 
-// 2D: a 64 x 16 box per workgroup; red on the box minus one ring, black (or
-// Jacobi) on the tile, written out
-template <bool JAC>
-__global__ __launch_bounds__(NT) void k_cd_sweep2d(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
-                                                   const Cx* __restrict__ f_, CDConst K, CDLevel L) {
-    constexpr int H = JAC ? 1 : 2, TX = 64 - 2 * H, TY = CDB_Y - 2 * H, RPT = CDB_Y / 4;
+// 2D Jacobi: a 64 x 16 box per workgroup, the tile (box minus one ring)
+// relaxed and written out
+__global__ __launch_bounds__(NT) void k_cd_sweep2d_jac(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
+                                                       const Cx* __restrict__ f_, CDConst K, CDLevel L) {
+    constexpr int H = 1, TX = 64 - 2 * H, TY = CDB_Y - 2 * H, RPT = CDB_Y / 4;
     __shared__ d2v Ub[CDB_Y][64];
     __shared__ double Qb[CDB_Y][64];
     const int n = L.n;
@@ -291,41 +290,25 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d(const Cx* __restrict__ uin_, 
         Qb[ly][lane] = dom ? cd_q(K, u) : 1.0;
     }
     __syncthreads();
-    if constexpr (!JAC) {
-#pragma unroll
-        for (int m = 0; m < RPT; ++m) {
-            const int ly = w + 4 * m, gy = ty * TY - H + ly;
-            if (xd && gy >= 0 && gy < n && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y - 2 &&
-                ((gx + gy) & 1) == 0)
-                Ub[ly][lane] = to_v(cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, gx, gy, 0, n, z0, 1.0, z0, 1.0,
-                                                        ldc(f, (size_t)gy * n + gx)));
-        }
-        __syncthreads();
-    }
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
         const int ly = w + 4 * m, gy = ty * TY - H + ly;
-        if (xd && gy >= 0 && gy < n && lane >= H && lane < 64 - H && ly >= H && ly < CDB_Y - H) {
-            Cx v = lds_c(Ub[ly][lane]);
-            if (JAC || ((gx + gy) & 1) == 1)
-                v = cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, gx, gy, 0, n, z0, 1.0, z0, 1.0,
-                                        ldc(f, (size_t)gy * n + gx));
-            stc(uout, (size_t)gy * n + gx, v);
-        }
+        if (xd && gy >= 0 && gy < n && lane >= H && lane < 64 - H && ly >= H && ly < CDB_Y - H)
+            stc(uout, (size_t)gy * n + gx,
+                cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, gx, gy, 0, n, z0, 1.0, z0, 1.0,
+                                    ldc(f, (size_t)gy * n + gx)));
     }
 }
 
-// 3D: a 64 x 12 box in x-y marching along z through a chunk of zc planes.
-// Each thread keeps its own cells of the last four planes (u, q and f) in
-// registers for the z faces (ring position = plane mod 4, resolved at compile
-// time by unrolling four steps); the planes being relaxed are in an LDS ring
-// of three planes for the x-y faces.  RBGS step kk: plane kk enters (old u,
-// its q); red on plane kk-1 (box minus one ring, in place); black on plane
-// kk-2 (the tile), written out with its red cells.  Jacobi step kk: plane kk
-// enters; plane kk-1 is relaxed on the tile and written out.
-template <bool JAC>
-struct CDSweep3 {
-    static constexpr int H = JAC ? 1 : 2, TX = 64 - 2 * H, TY = CDB_Y3 - 2 * H, RPT = CDB_Y3 / 4;
+// 3D Jacobi: a 64 x 12 box in x-y marching along z through a chunk of zc
+// planes.  Each thread keeps its own cells of the last four planes (u, q and
+// f) in registers for the z faces (ring position = plane mod 4, resolved at
+// compile time by unrolling four steps); the plane being relaxed is in an LDS
+// ring of three planes for the x-y faces.  Step kk: plane kk enters (old u,
+// its q); plane kk-1 is relaxed on the tile (box minus one ring) and written
+// out.
+struct CDSweep3J {
+    static constexpr int H = 1, TX = 64 - 2 * H, TY = CDB_Y3 - 2 * H, RPT = CDB_Y3 / 4;
     d2v (*Ub)[CDB_Y3][64];
     double (*Qb)[CDB_Y3][64];
     const MG_GLOBAL Cx* uin;
@@ -382,48 +365,15 @@ struct CDSweep3 {
         }
         prefetch(kk + 1);  // after the last step this loads a plane nobody reads (inside the grid only)
         __syncthreads();
-        if constexpr (JAC) {
-            const int zr = kk - 1;
-            if (zr >= z0 && zr < z1) {
+        const int zr = kk - 1;
+        if (zr >= z0 && zr < z1) {
 #pragma unroll
-                for (int m = 0; m < RPT; ++m) {
-                    const int ly = w + 4 * m;
-                    if (yd[m] && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y3 - 2) {
-                        const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, gx, gyr[m], zr, n, U(R2, m),
-                                                         qr[R2][m], U(R0, m), qr[R0][m], Fv(R1, m));
-                        stc(uout, (size_t)zr * pl + (size_t)gyr[m] * n + gx, v);
-                    }
-                }
-            }
-        } else {
-            const int zr = kk - 1;  // red plane
-            if (zr >= z0 - 1 && zr >= 0 && zr <= z1 && zr < n) {
-#pragma unroll
-                for (int m = 0; m < RPT; ++m) {
-                    const int ly = w + 4 * m;
-                    if (yd[m] && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y3 - 2 &&
-                        ((gx + gyr[m] + zr) & 1) == 0) {
-                        const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, gx, gyr[m], zr, n, U(R2, m),
-                                                         qr[R2][m], U(R0, m), qr[R0][m], Fv(R1, m));
-                        Ub[s1][ly][lane] = to_v(v);
-                        ure[R1][m] = v.re;
-                        uim[R1][m] = v.im;
-                    }
-                }
-            }
-            __syncthreads();
-            const int zb = kk - 2;  // black plane (output)
-            if (zb >= z0 && zb < z1) {
-#pragma unroll
-                for (int m = 0; m < RPT; ++m) {
-                    const int ly = w + 4 * m;
-                    if (yd[m] && lane >= 2 && lane <= 61 && ly >= 2 && ly <= CDB_Y3 - 3) {
-                        Cx v = lds_c(Ub[s2][ly][lane]);
-                        if (((gx + gyr[m] + zb) & 1) == 1)
-                            v = cd_relax_lds<3, 64>(K, c, Ub[s2], Qb[s2], ly, lane, gx, gyr[m], zb, n, U(R3, m),
-                                                    qr[R3][m], U(R1, m), qr[R1][m], Fv(R2, m));
-                        stc(uout, (size_t)zb * pl + (size_t)gyr[m] * n + gx, v);
-                    }
+            for (int m = 0; m < RPT; ++m) {
+                const int ly = w + 4 * m;
+                if (yd[m] && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y3 - 2) {
+                    const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, gx, gyr[m], zr, n, U(R2, m),
+                                                     qr[R2][m], U(R0, m), qr[R0][m], Fv(R1, m));
+                    stc(uout, (size_t)zr * pl + (size_t)gyr[m] * n + gx, v);
                 }
             }
         }
@@ -445,10 +395,9 @@ struct CDSweep3 {
     }
 };
 
-template <bool JAC>
-__global__ __launch_bounds__(NT) void k_cd_sweep3d(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
-                                                   const Cx* __restrict__ f_, CDConst K, CDLevel L, int zc) {
-    using S = CDSweep3<JAC>;
+__global__ __launch_bounds__(NT) void k_cd_sweep3d_jac(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
+                                                       const Cx* __restrict__ f_, CDConst K, CDLevel L, int zc) {
+    using S = CDSweep3J;
     __shared__ d2v Ub[3][CDB_Y3][64];
     __shared__ double Qb[3][CDB_Y3][64];
     S s;
@@ -549,7 +498,7 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin
 }
 
 // 3D: a 64 x 2NW box in x-y (NW wavefronts, wavefront w owning the row pair
-// 2w, 2w+1) marching along z through a chunk of planes as CDSweep3 does:
+// 2w, 2w+1) marching along z through a chunk of planes as CDSweep3J does:
 // step kk: plane kk enters (registers and an LDS ring of three planes); red on
 // plane kk-1 (box minus one ring, in place); black on plane kk-2 (the tile),
 // written out with its red cells.  Each thread keeps its two cells of the
@@ -925,7 +874,7 @@ hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const voi
     if (dim == 2) {
         const int H = jacobi ? 1 : 2;
         const unsigned b = (unsigned)(((n + 64 - 2 * H - 1) / (64 - 2 * H)) * ((n + CDB_Y - 2 * H - 1) / (CDB_Y - 2 * H)));
-        if (jacobi) k_cd_sweep2d<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L);
+        if (jacobi) k_cd_sweep2d_jac<<<b, NT, 0, s>>>(ui, uo, ff, K, L);
         else k_cd_sweep2d_rb<<<b, NT, 0, s>>>(ui, uo, ff, K, L);
     } else {
         if (n < kCDTiled3D) return hipErrorInvalidValue;  // small levels take the per-cell kernels
@@ -933,9 +882,11 @@ hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const voi
         if (jacobi) {
             constexpr int zc = 8;
             const unsigned b = cdiv(n, 64 - 2) * cdiv(n, CDB_Y3 - 2) * cdiv(n, zc);
-            k_cd_sweep3d<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
+            k_cd_sweep3d_jac<<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
         } else {
-            constexpr int NW = kCDSweep3Waves, zc = 16;
+            // 16-plane chunks at 256^3; smaller levels take 8 for twice the workgroups
+            constexpr int NW = kCDSweep3Waves;
+            const int zc = n >= 256 ? 16 : 8;
             using S = CDSweep3RB<NW>;
             const unsigned b = cdiv(n, S::TX) * cdiv(n, S::TY) * cdiv(n, zc);
             k_cd_sweep3d_rb<NW, kCDSweep3MinWaves><<<b, 64 * NW, 0, s>>>(ui, uo, ff, K, L, zc);
