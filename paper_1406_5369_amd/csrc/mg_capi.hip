@@ -780,10 +780,11 @@ size_t cd_cells(const CDState& S, int l) {
 
 // one sweep (both colours or Jacobi): tiled into the level's other buffer, or
 // per cell (small 3D levels) with g formed first
-hipError_t cd_sweep_level(CDState& S, int l, void*& cur, void*& other, const void* f, hipStream_t s) {
+hipError_t cd_sweep_level(CDState& S, int l, void*& cur, void*& other, const void* f, hipStream_t s,
+                          const void* uc = nullptr, const void* uh = nullptr) {
     const CDLevel L = cd_level(S.ln[(size_t)l]);
     if (cd_tiled(S.dim, L.n)) {
-        const hipError_t e = cd_sweep(S.dim, S.jacobi, cur, other, f, S.K, L, s);
+        const hipError_t e = cd_sweep(S.dim, S.jacobi, cur, other, f, S.K, L, s, uc, uh);
         std::swap(cur, other);
         return e;
     }
@@ -815,8 +816,13 @@ hipError_t cd_fas_level(CDState& S, int l, void*& cur, void*& other, const void*
     if ((e = cd_fas_level(S, l + 1, ucur, uoth, S.f[c1], s)) != hipSuccess) return e;
     S.u[c1] = ucur;
     S.t[c1] = uoth;
-    if ((e = cd_prolong(S.dim, cur, ucur, S.uh[c1], S.ln[(size_t)l], s)) != hipSuccess) return e;
-    for (int i = 0; i < S.nu2 && e == hipSuccess; ++i) e = cd_sweep_level(S, l, cur, other, f, s);
+    // tiled levels (3D Jacobi aside) apply the correction in the first
+    // post-smoothing sweep's loads
+    const bool fused = S.nu2 >= 1 && cd_sweep_corrects(S.dim, S.jacobi, S.ln[(size_t)l]);
+    if (!fused && (e = cd_prolong(S.dim, cur, ucur, S.uh[c1], S.ln[(size_t)l], s)) != hipSuccess) return e;
+    for (int i = 0; i < S.nu2 && e == hipSuccess; ++i)
+        e = fused && i == 0 ? cd_sweep_level(S, l, cur, other, f, s, ucur, S.uh[c1])
+                            : cd_sweep_level(S, l, cur, other, f, s);
     return e;
 }
 

@@ -25,10 +25,14 @@ hipError_t cd_relax(int dim, bool jacobi, const void* uin, void* uout, const voi
                     CDLevel L, int colour, hipStream_t s);
 // whether a level takes the tiled sweep (cd_sweep): 2D always, 3D from n = 128
 bool cd_tiled(int dim, int n);
+// whether cd_sweep takes the FAS correction (uc, uh) on such a level
+bool cd_sweep_corrects(int dim, bool jacobi, int n);
 // One smoothing sweep uin -> uout (out of place; RBGS both colours, or Jacobi)
-// with the diffusivity of uin, in tiles.
+// with the diffusivity of uin, in tiles.  With uc and uh (the coarse iterate
+// after and before its cycle, level n/2) the sweep starts from uin + P (uc - uh)
+// instead (the FAS correction applied to every loaded value; uin unchanged).
 hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const void* f, CDConst K, CDLevel L,
-                    hipStream_t s);
+                    hipStream_t s, const void* uc = nullptr, const void* uh = nullptr);
 // uh = R u, rc = R (f - N(u)) with g of u formed on the fly (n >= 2)
 hipError_t cd_restrict(int dim, const void* u, const void* f, void* uh, void* rc, CDConst K, CDLevel L,
                        hipStream_t s);

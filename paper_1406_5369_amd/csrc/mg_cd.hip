@@ -235,6 +235,23 @@ __device__ __forceinline__ d2v to_v(Cx c) {
     return v;
 }
 
+// The FAS correction u + (uc - uh) of the cell's parent (the expression of
+// k_cd_prolong), applied to each value a tiled sweep loads when it is the
+// first sweep after the coarse cycle; uc null: no correction.
+struct CDCorr {
+    const Cx* uc;
+    const Cx* uh;
+};
+__device__ __forceinline__ size_t cd_parent(int n, int x, int y, int z) {
+    const int nc = n >> 1;
+    return ((size_t)(z >> 1) * nc + (y >> 1)) * nc + (x >> 1);
+}
+__device__ __forceinline__ Cx cd_corr(const CDCorr& C, Cx u, int n, int x, int y, int z) {
+    if (!C.uc) return u;
+    const size_t q = cd_parent(n, x, y, z);
+    return cx_add(u, cx_sub(ldc(gp(C.uc), q), ldc(gp(C.uh), q)));
+}
+
 constexpr int CDB_Y = 16, CDB_Y3 = 12;  // box rows of the 2D / 3D tiles (64 lanes wide)
 
 // relaxation of the cell at (ly, lx) of an LDS plane P (u) / Q (q) with the
@@ -266,8 +283,9 @@ __device__ __forceinline__ Cx cd_relax_lds(const CDConst& K, double c, const d2v
 
 // 2D Jacobi: a 64 x 16 box per workgroup, the tile (box minus one ring)
 // relaxed and written out
+template <bool CORR>
 __global__ __launch_bounds__(NT) void k_cd_sweep2d_jac(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
-                                                       const Cx* __restrict__ f_, CDConst K, CDLevel L) {
+                                                       const Cx* __restrict__ f_, CDConst K, CDLevel L, CDCorr C) {
     constexpr int H = 1, TX = 64 - 2 * H, TY = CDB_Y - 2 * H, RPT = CDB_Y / 4;
     __shared__ d2v Ub[CDB_Y][64];
     __shared__ double Qb[CDB_Y][64];
@@ -285,7 +303,9 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_jac(const Cx* __restrict__ ui
     for (int m = 0; m < RPT; ++m) {
         const int ly = w + 4 * m, gy = ty * TY - H + ly;
         const bool dom = xd && gy >= 0 && gy < n;
-        const Cx u = dom ? ldc(uin, (size_t)gy * n + gx) : z0;
+        Cx u = dom ? ldc(uin, (size_t)gy * n + gx) : z0;
+        if constexpr (CORR)
+            if (dom) u = cd_corr(C, u, n, gx, gy, 0);
         Ub[ly][lane] = to_v(u);
         Qb[ly][lane] = dom ? cd_q(K, u) : 1.0;
     }
@@ -445,8 +465,9 @@ __global__ __launch_bounds__(NT) void k_cd_sweep3d_jac(const Cx* __restrict__ ui
 // 2D: a 64 x 16 box per workgroup, row pairs p = w, w + 4 of the box; red on
 // the box minus one ring in place, black on the tile, written out with the
 // red cells.
+template <bool CORR>
 __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
-                                                      const Cx* __restrict__ f_, CDConst K, CDLevel L) {
+                                                      const Cx* __restrict__ f_, CDConst K, CDLevel L, CDCorr C) {
     constexpr int H = 2, TX = 64 - 2 * H, TY = CDB_Y - 2 * H, RPT = CDB_Y / 4, NPR = CDB_Y / 8;
     __shared__ d2v Ub[CDB_Y][64];
     __shared__ double Qb[CDB_Y][64];
@@ -464,7 +485,9 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin
     for (int m = 0; m < RPT; ++m) {
         const int ly = w + 4 * m, gy = ty * TY - H + ly;
         const bool dom = xd && gy >= 0 && gy < n;
-        const Cx u = dom ? ldc(uin, (size_t)gy * n + gx) : z0;
+        Cx u = dom ? ldc(uin, (size_t)gy * n + gx) : z0;
+        if constexpr (CORR)
+            if (dom) u = cd_corr(C, u, n, gx, gy, 0);
         Ub[ly][lane] = to_v(u);
         Qb[ly][lane] = dom ? cd_q(K, u) : 1.0;
     }
@@ -503,7 +526,7 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin
 // plane kk-1 (box minus one ring, in place); black on plane kk-2 (the tile),
 // written out with its red cells.  Each thread keeps its two cells of the
 // last four planes (u, q, f) in registers for the z faces.
-template <int NW>
+template <int NW, bool CORR>
 struct CDSweep3RB {
     static constexpr int BY = 2 * NW, H = 2, TX = 64 - 2 * H, TY = BY - 2 * H;
     d2v (*Ub)[BY][64];
@@ -512,27 +535,38 @@ struct CDSweep3RB {
     const MG_GLOBAL Cx* f;
     MG_GLOBAL Cx* uout;
     CDConst K;
+    CDCorr C;
     double c;
     int n, lane, w, gx, gy0, z0, z1, kstart;
     size_t pl;
     bool xd, yd[2];
     double ure[4][2], uim[4][2], qr[4][2], fre[4][2], fim[4][2];
     double pur[2], pui[2], pfr[2], pfi[2];  // u and f of the next plane, loaded one step ahead
+    double pcr[2], pci[2], phr[2], phi[2];  // uc and uh of the parent (CORR: the correcting sweep)
 
     __device__ __forceinline__ void prefetch(int z) {
         const bool zd = z >= 0 && z < n;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            Cx u{0.0, 0.0}, fv{0.0, 0.0};
+            Cx u{0.0, 0.0}, fv{0.0, 0.0}, cu{0.0, 0.0}, hu{0.0, 0.0};
             if (yd[e] && zd) {
                 const size_t p = (size_t)z * pl + (size_t)(gy0 + e) * n + gx;
                 u = ldc(uin, p);
+                if constexpr (CORR) {
+                    const size_t pq = cd_parent(n, gx, gy0 + e, z);
+                    cu = ldc(gp(C.uc), pq);
+                    hu = ldc(gp(C.uh), pq);
+                }
                 fv = ldc(f, p);
             }
             pur[e] = u.re;
             pui[e] = u.im;
             pfr[e] = fv.re;
             pfi[e] = fv.im;
+            pcr[e] = cu.re;
+            pci[e] = cu.im;
+            phr[e] = hu.re;
+            phi[e] = hu.im;
         }
     }
 
@@ -557,7 +591,8 @@ struct CDSweep3RB {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int ly = 2 * w + e;
-            const Cx u{pur[e], pui[e]};
+            Cx u{pur[e], pui[e]};
+            if constexpr (CORR) u = cx_add(u, cx_sub(Cx{pcr[e], pci[e]}, Cx{phr[e], phi[e]}));
             const double qv = (yd[e] && zd) ? cd_q(K, u) : 1.0;
             ure[R0][e] = u.re;
             uim[R0][e] = u.im;
@@ -621,10 +656,10 @@ struct CDSweep3RB {
     }
 };
 
-template <int NW, int MINW>
+template <int NW, int MINW, bool CORR>
 __global__ __launch_bounds__(64 * NW, MINW) void k_cd_sweep3d_rb(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
-                                                           const Cx* __restrict__ f_, CDConst K, CDLevel L, int zc) {
-    using S = CDSweep3RB<NW>;
+                                                           const Cx* __restrict__ f_, CDConst K, CDLevel L, int zc, CDCorr C) {
+    using S = CDSweep3RB<NW, CORR>;
     __shared__ d2v Ub[3][S::BY][64];
     __shared__ double Qb[3][S::BY][64];
     S s;
@@ -634,6 +669,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void k_cd_sweep3d_rb(const Cx* __res
     s.f = gp(f_);
     s.uout = gp(uout_);
     s.K = K;
+    s.C = C;
     s.c = L.c;
     const int n = L.n;
     s.n = n;
@@ -864,9 +900,14 @@ constexpr int kCDTiled3D = 128;
 // wavefronts (row pairs) per workgroup of the 3D red-black sweep
 constexpr int kCDSweep3Waves = 8, kCDSweep3MinWaves = 2;
 bool cd_tiled(int dim, int n) { return dim == 2 || n >= kCDTiled3D; }
+// the 3D Jacobi march holds three cells per thread: the correction's registers
+// would leave it one wavefront per SIMD, so it keeps the separate pass
+bool cd_sweep_corrects(int dim, bool jacobi, int n) { return cd_tiled(dim, n) && !(dim == 3 && jacobi); }
 
 hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const void* f, CDConst K, CDLevel L,
-                    hipStream_t s) {
+                    hipStream_t s, const void* uc, const void* uh) {
+    if ((uc == nullptr) != (uh == nullptr)) return hipErrorInvalidValue;
+    const CDCorr C{(const Cx*)uc, (const Cx*)uh};
     const int n = L.n;
     auto ui = (const Cx*)uin;
     auto uo = (Cx*)uout;
@@ -874,22 +915,29 @@ hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const voi
     if (dim == 2) {
         const int H = jacobi ? 1 : 2;
         const unsigned b = (unsigned)(((n + 64 - 2 * H - 1) / (64 - 2 * H)) * ((n + CDB_Y - 2 * H - 1) / (CDB_Y - 2 * H)));
-        if (jacobi) k_cd_sweep2d_jac<<<b, NT, 0, s>>>(ui, uo, ff, K, L);
-        else k_cd_sweep2d_rb<<<b, NT, 0, s>>>(ui, uo, ff, K, L);
+        if (jacobi) {
+            if (C.uc) k_cd_sweep2d_jac<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
+            else k_cd_sweep2d_jac<false><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
+        } else {
+            if (C.uc) k_cd_sweep2d_rb<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
+            else k_cd_sweep2d_rb<false><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
+        }
     } else {
         if (n < kCDTiled3D) return hipErrorInvalidValue;  // small levels take the per-cell kernels
         auto cdiv = [](int a, int d) { return (unsigned)((a + d - 1) / d); };
         if (jacobi) {
             constexpr int zc = 8;
             const unsigned b = cdiv(n, 64 - 2) * cdiv(n, CDB_Y3 - 2) * cdiv(n, zc);
+            if (C.uc) return hipErrorInvalidValue;  // the 3D Jacobi march takes no correction
             k_cd_sweep3d_jac<<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
         } else {
             // 16-plane chunks at 256^3; smaller levels take 8 for twice the workgroups
             constexpr int NW = kCDSweep3Waves;
             const int zc = n >= 256 ? 16 : 8;
-            using S = CDSweep3RB<NW>;
+            using S = CDSweep3RB<NW, false>;
             const unsigned b = cdiv(n, S::TX) * cdiv(n, S::TY) * cdiv(n, zc);
-            k_cd_sweep3d_rb<NW, kCDSweep3MinWaves><<<b, 64 * NW, 0, s>>>(ui, uo, ff, K, L, zc);
+            if (C.uc) k_cd_sweep3d_rb<NW, kCDSweep3MinWaves, true><<<b, 64 * NW, 0, s>>>(ui, uo, ff, K, L, zc, C);
+            else k_cd_sweep3d_rb<NW, kCDSweep3MinWaves, false><<<b, 64 * NW, 0, s>>>(ui, uo, ff, K, L, zc, C);
         }
     }
     return hipGetLastError();
