@@ -327,10 +327,11 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_jac(const Cx* __restrict__ ui
 // ring of three planes for the x-y faces.  Step kk: plane kk enters (old u,
 // its q); plane kk-1 is relaxed on the tile (box minus one ring) and written
 // out.
+template <int RPT>
 struct CDSweep3J {
-    static constexpr int H = 1, TX = 64 - 2 * H, TY = CDB_Y3 - 2 * H, RPT = CDB_Y3 / 4;
-    d2v (*Ub)[CDB_Y3][64];
-    double (*Qb)[CDB_Y3][64];
+    static constexpr int BY = 4 * RPT, H = 1, TX = 64 - 2 * H, TY = BY - 2 * H;
+    d2v (*Ub)[BY][64];
+    double (*Qb)[BY][64];
     const MG_GLOBAL Cx* uin;
     const MG_GLOBAL Cx* f;
     MG_GLOBAL Cx* uout;
@@ -390,7 +391,7 @@ struct CDSweep3J {
 #pragma unroll
             for (int m = 0; m < RPT; ++m) {
                 const int ly = w + 4 * m;
-                if (yd[m] && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y3 - 2) {
+                if (yd[m] && lane >= 1 && lane <= 62 && ly >= 1 && ly <= BY - 2) {
                     const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, gx, gyr[m], zr, n, U(R2, m),
                                                      qr[R2][m], U(R0, m), qr[R0][m], Fv(R1, m));
                     stc(uout, (size_t)zr * pl + (size_t)gyr[m] * n + gx, v);
@@ -415,11 +416,12 @@ struct CDSweep3J {
     }
 };
 
-__global__ __launch_bounds__(NT) void k_cd_sweep3d_jac(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
+template <int RPT, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_cd_sweep3d_jac(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
                                                        const Cx* __restrict__ f_, CDConst K, CDLevel L, int zc) {
-    using S = CDSweep3J;
-    __shared__ d2v Ub[3][CDB_Y3][64];
-    __shared__ double Qb[3][CDB_Y3][64];
+    using S = CDSweep3J<RPT>;
+    __shared__ d2v Ub[3][S::BY][64];
+    __shared__ double Qb[3][S::BY][64];
     S s;
     s.Ub = Ub;
     s.Qb = Qb;
@@ -441,7 +443,7 @@ __global__ __launch_bounds__(NT) void k_cd_sweep3d_jac(const Cx* __restrict__ ui
     s.xd = s.gx >= 0 && s.gx < n;
     s.pl = (size_t)n * n;
 #pragma unroll
-    for (int m = 0; m < S::RPT; ++m) {
+    for (int m = 0; m < RPT; ++m) {
         s.gyr[m] = ty * S::TY - S::H + s.w + 4 * m;
         s.yd[m] = s.xd && s.gyr[m] >= 0 && s.gyr[m] < n;
 #pragma unroll
@@ -899,6 +901,8 @@ hipError_t cd_relax(int dim, bool jacobi, const void* uin, void* uout, const voi
 constexpr int kCDTiled3D = 128;
 // wavefronts (row pairs) per workgroup of the 3D red-black sweep
 constexpr int kCDSweep3Waves = 8, kCDSweep3MinWaves = 2;
+// rows per thread (box height / 4) and minimum wavefronts per SIMD of the 3D Jacobi march
+constexpr int kCDJacRows = 3, kCDJacMinWaves = 2;
 bool cd_tiled(int dim, int n) { return dim == 2 || n >= kCDTiled3D; }
 // the 3D Jacobi march holds three cells per thread: the correction's registers
 // would leave it one wavefront per SIMD, so it keeps the separate pass
@@ -927,9 +931,10 @@ hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const voi
         auto cdiv = [](int a, int d) { return (unsigned)((a + d - 1) / d); };
         if (jacobi) {
             constexpr int zc = 8;
-            const unsigned b = cdiv(n, 64 - 2) * cdiv(n, CDB_Y3 - 2) * cdiv(n, zc);
+            using S = CDSweep3J<kCDJacRows>;
+            const unsigned b = cdiv(n, S::TX) * cdiv(n, S::TY) * cdiv(n, zc);
             if (C.uc) return hipErrorInvalidValue;  // the 3D Jacobi march takes no correction
-            k_cd_sweep3d_jac<<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
+            k_cd_sweep3d_jac<kCDJacRows, kCDJacMinWaves><<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
         } else {
             // 16-plane chunks at 256^3; smaller levels take 8 for twice the workgroups
             constexpr int NW = kCDSweep3Waves;
