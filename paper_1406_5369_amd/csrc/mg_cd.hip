@@ -236,8 +236,9 @@ __device__ __forceinline__ d2v to_v(Cx c) {
 }
 
 // The FAS correction u + (uc - uh) of the cell's parent (the expression of
-// k_cd_prolong), applied to each value a tiled sweep loads when it is the
-// first sweep after the coarse cycle; uc null: no correction.
+// k_cd_prolong), applied by the CORR variants of the tiled sweeps (the first
+// post-smoothing sweep after the coarse cycle) to every in-domain value they
+// load; the other variants never read uc / uh.
 struct CDCorr {
     const Cx* uc;
     const Cx* uh;
