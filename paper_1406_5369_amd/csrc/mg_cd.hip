@@ -292,7 +292,8 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_jac(const Cx* __restrict__ ui
     __shared__ double Qb[CDB_Y][64];
     const int n = L.n;
     const int ntx = (n + TX - 1) / TX;
-    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);  // XCD bands: halo rows shared in one L2
+    const int tx = tile % ntx, ty = tile / ntx;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int gx = tx * TX - H + lane;
     const bool xd = gx >= 0 && gx < n;
@@ -434,7 +435,8 @@ __global__ __launch_bounds__(NT, MINW) void k_cd_sweep3d_jac(const Cx* __restric
     const int n = L.n;
     s.n = n;
     const int ntx = (n + S::TX - 1) / S::TX, nty = (n + S::TY - 1) / S::TY;
-    const int tx = blockIdx.x % ntx, t2 = blockIdx.x / ntx, ty = t2 % nty, tz = t2 / nty;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);  // XCD bands: halo rows shared in one L2
+    const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
     s.z0 = tz * zc;
     s.z1 = min(s.z0 + zc, n);
     s.kstart = s.z0 - S::H;
@@ -476,7 +478,8 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin
     __shared__ double Qb[CDB_Y][64];
     const int n = L.n;
     const int ntx = (n + TX - 1) / TX;
-    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);  // XCD bands: halo rows shared in one L2
+    const int tx = tile % ntx, ty = tile / ntx;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int gx = tx * TX - H + lane;
     const bool xd = gx >= 0 && gx < n;
@@ -677,7 +680,8 @@ __global__ __launch_bounds__(64 * NW, MINW) void k_cd_sweep3d_rb(const Cx* __res
     const int n = L.n;
     s.n = n;
     const int ntx = (n + S::TX - 1) / S::TX, nty = (n + S::TY - 1) / S::TY;
-    const int tx = blockIdx.x % ntx, t2 = blockIdx.x / ntx, ty = t2 % nty, tz = t2 / nty;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);  // XCD bands: halo rows shared in one L2
+    const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
     s.z0 = tz * zc;
     s.z1 = min(s.z0 + zc, n);
     s.kstart = s.z0 - S::H;
