@@ -203,21 +203,10 @@ __device__ __forceinline__ double cd_q(const CDConst& K, Cx u) {
     return 1.0 / (1.0 + s * s);
 }
 
-// one face: flux term (tr, ti) and face diffusivity (gr, gi), zeros outside the domain
+// one face: flux term (tr, ti) and face diffusivity (gr, gi)
 struct CDFace {
     double tr, ti, gr, gi;
 };
-__device__ __forceinline__ CDFace cd_face_v(bool inside, Cx up, Cx gp, Cx uq, double qq, const CDConst& K) {
-    const double gqr = K.ct * qq, gqi = K.st * qq;
-    const double gr = 0.5 * (gp.re + gqr), gi = 0.5 * (gp.im + gqi);
-    const Cx t = cx_mul(Cx{gr, gi}, cx_sub(uq, up));
-    CDFace o;
-    o.tr = inside ? t.re : 0.0;
-    o.ti = inside ? t.im : 0.0;
-    o.gr = inside ? gr : 0.0;
-    o.gi = inside ? gi : 0.0;
-    return o;
-}
 
 // relaxation from the face sums: up + omega (f - N(u)) / D
 __device__ __forceinline__ Cx cd_relax_v(const CDConst& K, double c, Cx up, Cx F, Cx S, Cx fv) {
@@ -255,25 +244,40 @@ __device__ __forceinline__ Cx cd_corr(const CDCorr& C, Cx u, int n, int x, int y
 
 constexpr int CDB_Y = 16, CDB_Y3 = 12;  // box rows of the 2D / 3D tiles (64 lanes wide)
 
-// relaxation of the cell at (ly, lx) of an LDS plane P (u) / Q (q) with the
-// z-neighbours (ub, qb below; ua, qa above) given; 2D: no z faces
+// One face with no domain test.  The tiled sweeps store each box cell outside
+// the domain as a mirror ghost: u of the inner cell it faces (a clamped load)
+// and that cell's q negated.  A boundary face then computes uq - up = +0 and
+// a diffusivity 0.5 (ct q + ct (-q)) = +0 (likewise sin), so its flux and
+// diffusivity terms are exactly the +0 the domain test would give (for
+// finite iterates), with no selects.  Only the inner cell next to a ghost
+// reads it, while its own value is still the one the ghost copied (a cell
+// changes only in its own colour phase, after which no cell reads the ghost).
+__device__ __forceinline__ CDFace cd_face_m(Cx up, Cx gp, Cx uq, double qq, const CDConst& K) {
+    const double gqr = K.ct * qq, gqi = K.st * qq;
+    const double gr = 0.5 * (gp.re + gqr), gi = 0.5 * (gp.im + gqi);
+    const Cx t = cx_mul(Cx{gr, gi}, cx_sub(uq, up));
+    return CDFace{t.re, t.im, gr, gi};
+}
+
+// relaxation of the cell at (ly, lx) of an LDS plane P (u) / Q (q, mirror
+// ghosts outside the domain) with the z-neighbours (ub, qb below; ua, qa
+// above) given; 2D: no z faces
 template <int DIM, int W>
 __device__ __forceinline__ Cx cd_relax_lds(const CDConst& K, double c, const d2v (*P)[W], const double (*Q)[W],
-                                           int ly, int lx, int gx, int gy, int gz, int n, Cx ub, double qb, Cx ua,
-                                           double qa, Cx fv) {
+                                           int ly, int lx, Cx ub, double qb, Cx ua, double qa, Cx fv) {
     const Cx up = lds_c(P[ly][lx]);
     const double qp = Q[ly][lx];
     const Cx gpv{K.ct * qp, K.st * qp};
-    const CDFace fW = cd_face_v(gx > 0, up, gpv, lds_c(P[ly][lx - 1]), Q[ly][lx - 1], K);
-    const CDFace fE = cd_face_v(gx < n - 1, up, gpv, lds_c(P[ly][lx + 1]), Q[ly][lx + 1], K);
-    const CDFace fS = cd_face_v(gy > 0, up, gpv, lds_c(P[ly - 1][lx]), Q[ly - 1][lx], K);
-    const CDFace fN = cd_face_v(gy < n - 1, up, gpv, lds_c(P[ly + 1][lx]), Q[ly + 1][lx], K);
+    const CDFace fW = cd_face_m(up, gpv, lds_c(P[ly][lx - 1]), Q[ly][lx - 1], K);
+    const CDFace fE = cd_face_m(up, gpv, lds_c(P[ly][lx + 1]), Q[ly][lx + 1], K);
+    const CDFace fS = cd_face_m(up, gpv, lds_c(P[ly - 1][lx]), Q[ly - 1][lx], K);
+    const CDFace fN = cd_face_m(up, gpv, lds_c(P[ly + 1][lx]), Q[ly + 1][lx], K);
     // ((W + E) + (S + N)) [+ (B + T)], componentwise as cx_add
     double Fr = (fW.tr + fE.tr) + (fS.tr + fN.tr), Fi = (fW.ti + fE.ti) + (fS.ti + fN.ti);
     double Sr = (fW.gr + fE.gr) + (fS.gr + fN.gr), Si = (fW.gi + fE.gi) + (fS.gi + fN.gi);
     if constexpr (DIM == 3) {
-        const CDFace fB = cd_face_v(gz > 0, up, gpv, ub, qb, K);
-        const CDFace fT = cd_face_v(gz < n - 1, up, gpv, ua, qa, K);
+        const CDFace fB = cd_face_m(up, gpv, ub, qb, K);
+        const CDFace fT = cd_face_m(up, gpv, ua, qa, K);
         Fr = Fr + (fB.tr + fT.tr);
         Fi = Fi + (fB.ti + fT.ti);
         Sr = Sr + (fB.gr + fT.gr);
@@ -304,12 +308,13 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_jac(const Cx* __restrict__ ui
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
         const int ly = w + 4 * m, gy = ty * TY - H + ly;
-        const bool dom = xd && gy >= 0 && gy < n;
-        Cx u = dom ? ldc(uin, (size_t)gy * n + gx) : z0;
-        if constexpr (CORR)
-            if (dom) u = cd_corr(C, u, n, gx, gy, 0);
+        const bool dom = xd && gy >= 0 && gy < n;  // else a mirror ghost (clamped load, q negated)
+        const int gxc = min(max(gx, 0), n - 1), gyc = min(max(gy, 0), n - 1);
+        Cx u = ldc(uin, (size_t)gyc * n + gxc);
+        if constexpr (CORR) u = cd_corr(C, u, n, gxc, gyc, 0);
+        const double q = cd_q(K, u);
         Ub[ly][lane] = to_v(u);
-        Qb[ly][lane] = dom ? cd_q(K, u) : 1.0;
+        Qb[ly][lane] = dom ? q : -q;
     }
     __syncthreads();
 #pragma unroll
@@ -317,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_jac(const Cx* __restrict__ ui
         const int ly = w + 4 * m, gy = ty * TY - H + ly;
         if (xd && gy >= 0 && gy < n && lane >= H && lane < 64 - H && ly >= H && ly < CDB_Y - H)
             stc(uout, (size_t)gy * n + gx,
-                cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, gx, gy, 0, n, z0, 1.0, z0, 1.0,
+                cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, z0, 1.0, z0, 1.0,
                                     ldc(f, (size_t)gy * n + gx)));
     }
 }
@@ -350,16 +355,15 @@ struct CDSweep3J {
     __device__ __forceinline__ Cx U(int q, int m) const { return Cx{ure[q][m], uim[q][m]}; }
     __device__ __forceinline__ Cx Fv(int q, int m) const { return Cx{fre[q][m], fim[q][m]}; }
 
+    // clamped addresses: cells outside the domain load the inner cell they
+    // face (mirror ghosts, q negated when the plane enters)
     __device__ __forceinline__ void prefetch(int z) {
-        const bool zd = z >= 0 && z < n;
+        const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
+        const int gxc = min(max(gx, 0), n - 1);
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            Cx u{0.0, 0.0}, fv{0.0, 0.0};
-            if (yd[m] && zd) {
-                const size_t p = (size_t)z * pl + (size_t)gyr[m] * n + gx;
-                u = ldc(uin, p);
-                fv = ldc(f, p);
-            }
+            const size_t p = zoff + (size_t)min(max(gyr[m], 0), n - 1) * n + gxc;
+            const Cx u = ldc(uin, p), fv = ldc(f, p);
             pur[m] = u.re;
             pui[m] = u.im;
             pfr[m] = fv.re;
@@ -377,7 +381,8 @@ struct CDSweep3J {
         for (int m = 0; m < RPT; ++m) {
             const int ly = w + 4 * m;
             const Cx u{pur[m], pui[m]};
-            const double qv = (yd[m] && zd) ? cd_q(K, u) : 1.0;
+            const double qq = cd_q(K, u);
+            const double qv = (yd[m] && zd) ? qq : -qq;
             ure[R0][m] = u.re;
             uim[R0][m] = u.im;
             qr[R0][m] = qv;
@@ -394,7 +399,7 @@ struct CDSweep3J {
             for (int m = 0; m < RPT; ++m) {
                 const int ly = w + 4 * m;
                 if (yd[m] && lane >= 1 && lane <= 62 && ly >= 1 && ly <= BY - 2) {
-                    const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, gx, gyr[m], zr, n, U(R2, m),
+                    const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, U(R2, m),
                                                      qr[R2][m], U(R0, m), qr[R0][m], Fv(R1, m));
                     stc(uout, (size_t)zr * pl + (size_t)gyr[m] * n + gx, v);
                 }
@@ -490,12 +495,13 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
         const int ly = w + 4 * m, gy = ty * TY - H + ly;
-        const bool dom = xd && gy >= 0 && gy < n;
-        Cx u = dom ? ldc(uin, (size_t)gy * n + gx) : z0;
-        if constexpr (CORR)
-            if (dom) u = cd_corr(C, u, n, gx, gy, 0);
+        const bool dom = xd && gy >= 0 && gy < n;  // else a mirror ghost (clamped load, q negated)
+        const int gxc = min(max(gx, 0), n - 1), gyc = min(max(gy, 0), n - 1);
+        Cx u = ldc(uin, (size_t)gyc * n + gxc);
+        if constexpr (CORR) u = cd_corr(C, u, n, gxc, gyc, 0);
+        const double q = cd_q(K, u);
         Ub[ly][lane] = to_v(u);
-        Qb[ly][lane] = dom ? cd_q(K, u) : 1.0;
+        Qb[ly][lane] = dom ? q : -q;
     }
     __syncthreads();
 #pragma unroll
@@ -504,7 +510,7 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin
         const int s = (gx + gy0) & 1;  // red row of the pair
         const int ly = ly0 + s, gy = gy0 + s;
         if (xd && gy >= 0 && gy < n && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y - 2)
-            Ub[ly][lane] = to_v(cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, gx, gy, 0, n, z0, 1.0, z0, 1.0,
+            Ub[ly][lane] = to_v(cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, z0, 1.0, z0, 1.0,
                                                     ldc(f, (size_t)gy * n + gx)));
     }
     __syncthreads();
@@ -515,7 +521,7 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin
         const int lyb = ly0 + b, gyb = gy0 + b;
         Cx vb = z0;
         if (xd && gyb >= 0 && gyb < n && lane >= H && lane < 64 - H && lyb >= H && lyb < CDB_Y - H)
-            vb = cd_relax_lds<2, 64>(K, L.c, Ub, Qb, lyb, lane, gx, gyb, 0, n, z0, 1.0, z0, 1.0,
+            vb = cd_relax_lds<2, 64>(K, L.c, Ub, Qb, lyb, lane, z0, 1.0, z0, 1.0,
                                      ldc(f, (size_t)gyb * n + gx));
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
@@ -550,21 +556,22 @@ struct CDSweep3RB {
     double pur[2], pui[2], pfr[2], pfi[2];  // u and f of the next plane, loaded one step ahead
     double pcr[2], pci[2], phr[2], phi[2];  // uc and uh of the parent (CORR: the correcting sweep)
 
+    // clamped addresses: cells outside the domain load the inner cell they
+    // face (mirror ghosts, q negated when the plane enters)
     __device__ __forceinline__ void prefetch(int z) {
-        const bool zd = z >= 0 && z < n;
+        const int zc = min(max(z, 0), n - 1), gxc = min(max(gx, 0), n - 1);
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            Cx u{0.0, 0.0}, fv{0.0, 0.0}, cu{0.0, 0.0}, hu{0.0, 0.0};
-            if (yd[e] && zd) {
-                const size_t p = (size_t)z * pl + (size_t)(gy0 + e) * n + gx;
-                u = ldc(uin, p);
-                if constexpr (CORR) {
-                    const size_t pq = cd_parent(n, gx, gy0 + e, z);
-                    cu = ldc(gp(C.uc), pq);
-                    hu = ldc(gp(C.uh), pq);
-                }
-                fv = ldc(f, p);
+            const int gyc = min(max(gy0 + e, 0), n - 1);
+            const size_t p = (size_t)zc * pl + (size_t)gyc * n + gxc;
+            const Cx u = ldc(uin, p);
+            Cx cu{0.0, 0.0}, hu{0.0, 0.0};
+            if constexpr (CORR) {
+                const size_t pq = cd_parent(n, gxc, gyc, zc);
+                cu = ldc(gp(C.uc), pq);
+                hu = ldc(gp(C.uh), pq);
             }
+            const Cx fv = ldc(f, p);
             pur[e] = u.re;
             pui[e] = u.im;
             pfr[e] = fv.re;
@@ -599,7 +606,8 @@ struct CDSweep3RB {
             const int ly = 2 * w + e;
             Cx u{pur[e], pui[e]};
             if constexpr (CORR) u = cx_add(u, cx_sub(Cx{pcr[e], pci[e]}, Cx{phr[e], phi[e]}));
-            const double qv = (yd[e] && zd) ? cd_q(K, u) : 1.0;
+            const double qq = cd_q(K, u);
+            const double qv = (yd[e] && zd) ? qq : -qq;
             ure[R0][e] = u.re;
             uim[R0][e] = u.im;
             qr[R0][e] = qv;
@@ -615,7 +623,7 @@ struct CDSweep3RB {
             const int s = (gx + gy0 + zr) & 1;  // red row of the pair
             const int ly = 2 * w + s;
             if ((s ? yd[1] : yd[0]) && lane >= 1 && lane <= 62 && ly >= 1 && ly <= BY - 2) {
-                const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, gx, gy0 + s, zr, n, Usel<R2>(s),
+                const Cx v = cd_relax_lds<3, 64>(K, c, Ub[s1], Qb[s1], ly, lane, Usel<R2>(s),
                                                  Qsel<R2>(s), Usel<R0>(s), Qsel<R0>(s), Fsel<R1>(s));
                 Ub[s1][ly][lane] = to_v(v);
                 if (s) {
@@ -634,7 +642,7 @@ struct CDSweep3RB {
             const int lyb = 2 * w + b;
             Cx vb{0.0, 0.0};
             if ((b ? yd[1] : yd[0]) && lane >= 2 && lane <= 61 && lyb >= 2 && lyb <= BY - 3)
-                vb = cd_relax_lds<3, 64>(K, c, Ub[s2], Qb[s2], lyb, lane, gx, gy0 + b, zb, n, Usel<R3>(b),
+                vb = cd_relax_lds<3, 64>(K, c, Ub[s2], Qb[s2], lyb, lane, Usel<R3>(b),
                                          Qsel<R3>(b), Usel<R1>(b), Qsel<R1>(b), Fsel<R2>(b));
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
@@ -734,9 +742,11 @@ __global__ __launch_bounds__(NT) void k_cd_resblk(const Cx* __restrict__ u_, con
     const MG_GLOBAL Cx* u = gp(u_);
     const MG_GLOBAL Cx* f = gp(f_);
     const size_t pl = (size_t)n * n;
-    // in-bounds addresses for every lane (lanes past the row load the last
-    // pair; only live lanes use their values)
-    const int xa = min(2 * X, n - 2);
+    // clamped addresses for every lane: a neighbour outside the domain loads
+    // the cell it faces (uq - up = +0, so the face's flux is the +0 the
+    // domain test would give; see cd_face_m), lanes past the row the last
+    // cell (their values serve only as such neighbours)
+    const int xa0 = min(2 * X, n - 1), xa1 = min(2 * X + 1, n - 1);
     const int xe = lane == 0 ? max(2 * X - 1, 0) : min(2 * X + 2, n - 1);
     auto row_at = [&](int p, int r) -> size_t {
         const int y = min(max(2 * J - 1 + r, 0), n - 1);
@@ -754,9 +764,9 @@ __global__ __launch_bounds__(NT) void k_cd_resblk(const Cx* __restrict__ u_, con
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             if (needed(p, r)) {
-                const size_t a = row_at(p, r) + (size_t)xa;
-                U[p][r][0] = ldc(u, a);
-                U[p][r][1] = ldc(u, a + 1);
+                const size_t a = row_at(p, r);
+                U[p][r][0] = ldc(u, a + (size_t)xa0);
+                U[p][r][1] = ldc(u, a + (size_t)xa1);
             }
 #pragma unroll
     for (int pc = 0; pc < NPC; ++pc)
@@ -764,8 +774,8 @@ __global__ __launch_bounds__(NT) void k_cd_resblk(const Cx* __restrict__ u_, con
         for (int rc = 0; rc < 2; ++rc) {
             const size_t a = row_at(P0 + pc, 1 + rc);
             Ue[pc][rc] = ldc(u, a + (size_t)xe);
-            Fv[pc][rc][0] = ldc(f, a + (size_t)xa);
-            Fv[pc][rc][1] = ldc(f, a + (size_t)xa + 1);
+            Fv[pc][rc][0] = ldc(f, a + (size_t)xa0);
+            Fv[pc][rc][1] = ldc(f, a + (size_t)xa1);
         }
 #pragma unroll
     for (int p = 0; p < NP; ++p)
@@ -789,7 +799,6 @@ __global__ __launch_bounds__(NT) void k_cd_resblk(const Cx* __restrict__ u_, con
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int p = P0 + pc, r = 1 + rc;
-                const int x = 2 * X + e, y = 2 * J + rc, z = 2 * KK + pc;
                 const Cx up = U[p][r][e];
                 const double qp = Q[p][r][e];
                 const Cx gpv{K.ct * qp, K.st * qp};
@@ -814,14 +823,14 @@ __global__ __launch_bounds__(NT) void k_cd_resblk(const Cx* __restrict__ u_, con
                         qe = Qe[pc][rc];
                     }
                 }
-                const CDFace fW = cd_face_v(x > 0, up, gpv, uw, qw, K);
-                const CDFace fE = cd_face_v(x < n - 1, up, gpv, ue, qe, K);
-                const CDFace fS = cd_face_v(y > 0, up, gpv, U[p][r - 1][e], Q[p][r - 1][e], K);
-                const CDFace fN = cd_face_v(y < n - 1, up, gpv, U[p][r + 1][e], Q[p][r + 1][e], K);
+                const CDFace fW = cd_face_m(up, gpv, uw, qw, K);
+                const CDFace fE = cd_face_m(up, gpv, ue, qe, K);
+                const CDFace fS = cd_face_m(up, gpv, U[p][r - 1][e], Q[p][r - 1][e], K);
+                const CDFace fN = cd_face_m(up, gpv, U[p][r + 1][e], Q[p][r + 1][e], K);
                 double Fr = (fW.tr + fE.tr) + (fS.tr + fN.tr), Fi = (fW.ti + fE.ti) + (fS.ti + fN.ti);
                 if constexpr (DIM == 3) {
-                    const CDFace fB = cd_face_v(z > 0, up, gpv, U[p - 1][r][e], Q[p - 1][r][e], K);
-                    const CDFace fT = cd_face_v(z < n - 1, up, gpv, U[p + 1][r][e], Q[p + 1][r][e], K);
+                    const CDFace fB = cd_face_m(up, gpv, U[p - 1][r][e], Q[p - 1][r][e], K);
+                    const CDFace fT = cd_face_m(up, gpv, U[p + 1][r][e], Q[p + 1][r][e], K);
                     Fr = Fr + (fB.tr + fT.tr);
                     Fi = Fi + (fB.ti + fT.ti);
                 }
