@@ -816,8 +816,7 @@ hipError_t cd_fas_level(CDState& S, int l, void*& cur, void*& other, const void*
     if ((e = cd_fas_level(S, l + 1, ucur, uoth, S.f[c1], s)) != hipSuccess) return e;
     S.u[c1] = ucur;
     S.t[c1] = uoth;
-    // tiled levels (3D Jacobi aside) apply the correction in the first
-    // post-smoothing sweep's loads
+    // tiled levels apply the correction in the first post-smoothing sweep's loads
     const bool fused = S.nu2 >= 1 && cd_sweep_corrects(S.dim, S.jacobi, S.ln[(size_t)l]);
     if (!fused && (e = cd_prolong(S.dim, cur, ucur, S.uh[c1], S.ln[(size_t)l], s)) != hipSuccess) return e;
     for (int i = 0; i < S.nu2 && e == hipSuccess; ++i)

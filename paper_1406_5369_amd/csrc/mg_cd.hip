@@ -334,7 +334,7 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_jac(const Cx* __restrict__ ui
 // ring of three planes for the x-y faces.  Step kk: plane kk enters (old u,
 // its q); plane kk-1 is relaxed on the tile (box minus one ring) and written
 // out.
-template <int RPT>
+template <int RPT, bool CORR>
 struct CDSweep3J {
     static constexpr int BY = 4 * RPT, H = 1, TX = 64 - 2 * H, TY = BY - 2 * H;
     d2v (*Ub)[BY][64];
@@ -343,6 +343,7 @@ struct CDSweep3J {
     const MG_GLOBAL Cx* f;
     MG_GLOBAL Cx* uout;
     CDConst K;
+    CDCorr C;
     double c;
     int n, lane, w, gx, z0, z1, kstart;
     size_t pl;
@@ -351,6 +352,7 @@ struct CDSweep3J {
     bool yd[RPT];
     double ure[4][RPT], uim[4][RPT], qr[4][RPT], fre[4][RPT], fim[4][RPT];
     double pur[RPT], pui[RPT], pfr[RPT], pfi[RPT];  // u and f of the next plane, loaded one step ahead
+    double pcr[RPT], pci[RPT], phr[RPT], phi[RPT];  // uc and uh of the parent (CORR: the correcting sweep)
 
     __device__ __forceinline__ Cx U(int q, int m) const { return Cx{ure[q][m], uim[q][m]}; }
     __device__ __forceinline__ Cx Fv(int q, int m) const { return Cx{fre[q][m], fim[q][m]}; }
@@ -358,12 +360,22 @@ struct CDSweep3J {
     // clamped addresses: cells outside the domain load the inner cell they
     // face (mirror ghosts, q negated when the plane enters)
     __device__ __forceinline__ void prefetch(int z) {
-        const size_t zoff = (size_t)min(max(z, 0), n - 1) * pl;
+        const int zc = min(max(z, 0), n - 1);
+        const size_t zoff = (size_t)zc * pl;
         const int gxc = min(max(gx, 0), n - 1);
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const size_t p = zoff + (size_t)min(max(gyr[m], 0), n - 1) * n + gxc;
+            const int gyc = min(max(gyr[m], 0), n - 1);
+            const size_t p = zoff + (size_t)gyc * n + gxc;
             const Cx u = ldc(uin, p), fv = ldc(f, p);
+            if constexpr (CORR) {
+                const size_t pq = cd_parent(n, gxc, gyc, zc);
+                const Cx cu = ldc(gp(C.uc), pq), hu = ldc(gp(C.uh), pq);
+                pcr[m] = cu.re;
+                pci[m] = cu.im;
+                phr[m] = hu.re;
+                phi[m] = hu.im;
+            }
             pur[m] = u.re;
             pui[m] = u.im;
             pfr[m] = fv.re;
@@ -380,7 +392,8 @@ struct CDSweep3J {
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const int ly = w + 4 * m;
-            const Cx u{pur[m], pui[m]};
+            Cx u{pur[m], pui[m]};
+            if constexpr (CORR) u = cx_add(u, cx_sub(Cx{pcr[m], pci[m]}, Cx{phr[m], phi[m]}));
             const double qq = cd_q(K, u);
             const double qv = (yd[m] && zd) ? qq : -qq;
             ure[R0][m] = u.re;
@@ -423,10 +436,10 @@ struct CDSweep3J {
     }
 };
 
-template <int RPT, int MINW>
+template <int RPT, int MINW, bool CORR>
 __global__ __launch_bounds__(NT, MINW) void k_cd_sweep3d_jac(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
-                                                       const Cx* __restrict__ f_, CDConst K, CDLevel L, int zc) {
-    using S = CDSweep3J<RPT>;
+                                                       const Cx* __restrict__ f_, CDConst K, CDLevel L, int zc, CDCorr C) {
+    using S = CDSweep3J<RPT, CORR>;
     __shared__ d2v Ub[3][S::BY][64];
     __shared__ double Qb[3][S::BY][64];
     S s;
@@ -436,6 +449,7 @@ __global__ __launch_bounds__(NT, MINW) void k_cd_sweep3d_jac(const Cx* __restric
     s.f = gp(f_);
     s.uout = gp(uout_);
     s.K = K;
+    s.C = C;
     s.c = L.c;
     const int n = L.n;
     s.n = n;
@@ -918,9 +932,7 @@ constexpr int kCDSweep3Waves = 8, kCDSweep3MinWaves = 2;
 // rows per thread (box height / 4) and minimum wavefronts per SIMD of the 3D Jacobi march
 constexpr int kCDJacRows = 3, kCDJacMinWaves = 2;
 bool cd_tiled(int dim, int n) { return dim == 2 || n >= kCDTiled3D; }
-// the 3D Jacobi march holds three cells per thread: the correction's registers
-// would leave it one wavefront per SIMD, so it keeps the separate pass
-bool cd_sweep_corrects(int dim, bool jacobi, int n) { return cd_tiled(dim, n) && !(dim == 3 && jacobi); }
+bool cd_sweep_corrects(int dim, bool jacobi, int n) { return cd_tiled(dim, n); }
 
 hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const void* f, CDConst K, CDLevel L,
                     hipStream_t s, const void* uc, const void* uh) {
@@ -945,10 +957,15 @@ hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const voi
         auto cdiv = [](int a, int d) { return (unsigned)((a + d - 1) / d); };
         if (jacobi) {
             constexpr int zc = 8;
-            using S = CDSweep3J<kCDJacRows>;
-            const unsigned b = cdiv(n, S::TX) * cdiv(n, S::TY) * cdiv(n, zc);
-            if (C.uc) return hipErrorInvalidValue;  // the 3D Jacobi march takes no correction
-            k_cd_sweep3d_jac<kCDJacRows, kCDJacMinWaves><<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc);
+            if (C.uc) {  // two rows per thread: room for the correction's registers
+                using S = CDSweep3J<2, true>;
+                const unsigned b = cdiv(n, S::TX) * cdiv(n, S::TY) * cdiv(n, zc);
+                k_cd_sweep3d_jac<2, kCDJacMinWaves, true><<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc, C);
+            } else {
+                using S = CDSweep3J<kCDJacRows, false>;
+                const unsigned b = cdiv(n, S::TX) * cdiv(n, S::TY) * cdiv(n, zc);
+                k_cd_sweep3d_jac<kCDJacRows, kCDJacMinWaves, false><<<b, NT, 0, s>>>(ui, uo, ff, K, L, zc, C);
+            }
         } else {
             // 16-plane chunks at 256^3; smaller levels take 8 for twice the workgroups
             constexpr int NW = kCDSweep3Waves;
