@@ -288,12 +288,12 @@ __device__ __forceinline__ Cx cd_relax_lds(const CDConst& K, double c, const d2v
 
 // 2D Jacobi: a 64 x 16 box per workgroup, the tile (box minus one ring)
 // relaxed and written out
-template <bool CORR>
+template <bool CORR, int BY>
 __global__ __launch_bounds__(NT) void k_cd_sweep2d_jac(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
                                                        const Cx* __restrict__ f_, CDConst K, CDLevel L, CDCorr C) {
-    constexpr int H = 1, TX = 64 - 2 * H, TY = CDB_Y - 2 * H, RPT = CDB_Y / 4;
-    __shared__ d2v Ub[CDB_Y][64];
-    __shared__ double Qb[CDB_Y][64];
+    constexpr int H = 1, TX = 64 - 2 * H, TY = BY - 2 * H, RPT = BY / 4;
+    __shared__ d2v Ub[BY][64];
+    __shared__ double Qb[BY][64];
     const int n = L.n;
     const int ntx = (n + TX - 1) / TX;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);  // XCD bands: halo rows shared in one L2
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_jac(const Cx* __restrict__ ui
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
         const int ly = w + 4 * m, gy = ty * TY - H + ly;
-        if (xd && gy >= 0 && gy < n && lane >= H && lane < 64 - H && ly >= H && ly < CDB_Y - H)
+        if (xd && gy >= 0 && gy < n && lane >= H && lane < 64 - H && ly >= H && ly < BY - H)
             stc(uout, (size_t)gy * n + gx,
                 cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, z0, 1.0, z0, 1.0,
                                     ldc(f, (size_t)gy * n + gx)));
@@ -489,12 +489,12 @@ __global__ __launch_bounds__(NT, MINW) void k_cd_sweep3d_jac(const Cx* __restric
 // 2D: a 64 x 16 box per workgroup, row pairs p = w, w + 4 of the box; red on
 // the box minus one ring in place, black on the tile, written out with the
 // red cells.
-template <bool CORR>
+template <bool CORR, int BY>
 __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
                                                       const Cx* __restrict__ f_, CDConst K, CDLevel L, CDCorr C) {
-    constexpr int H = 2, TX = 64 - 2 * H, TY = CDB_Y - 2 * H, RPT = CDB_Y / 4, NPR = CDB_Y / 8;
-    __shared__ d2v Ub[CDB_Y][64];
-    __shared__ double Qb[CDB_Y][64];
+    constexpr int H = 2, TX = 64 - 2 * H, TY = BY - 2 * H, RPT = BY / 4, NPR = BY / 8;
+    __shared__ d2v Ub[BY][64];
+    __shared__ double Qb[BY][64];
     const int n = L.n;
     const int ntx = (n + TX - 1) / TX;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);  // XCD bands: halo rows shared in one L2
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin
         const int ly0 = 2 * (w + 4 * m), gy0 = ty * TY - H + ly0;
         const int s = (gx + gy0) & 1;  // red row of the pair
         const int ly = ly0 + s, gy = gy0 + s;
-        if (xd && gy >= 0 && gy < n && lane >= 1 && lane <= 62 && ly >= 1 && ly <= CDB_Y - 2)
+        if (xd && gy >= 0 && gy < n && lane >= 1 && lane <= 62 && ly >= 1 && ly <= BY - 2)
             Ub[ly][lane] = to_v(cd_relax_lds<2, 64>(K, L.c, Ub, Qb, ly, lane, z0, 1.0, z0, 1.0,
                                                     ldc(f, (size_t)gy * n + gx)));
     }
@@ -534,13 +534,13 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin
         const int b = 1 - ((gx + gy0) & 1);  // black row of the pair
         const int lyb = ly0 + b, gyb = gy0 + b;
         Cx vb = z0;
-        if (xd && gyb >= 0 && gyb < n && lane >= H && lane < 64 - H && lyb >= H && lyb < CDB_Y - H)
+        if (xd && gyb >= 0 && gyb < n && lane >= H && lane < 64 - H && lyb >= H && lyb < BY - H)
             vb = cd_relax_lds<2, 64>(K, L.c, Ub, Qb, lyb, lane, z0, 1.0, z0, 1.0,
                                      ldc(f, (size_t)gyb * n + gx));
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int ly = ly0 + e, gy = gy0 + e;
-            if (xd && gy >= 0 && gy < n && lane >= H && lane < 64 - H && ly >= H && ly < CDB_Y - H)
+            if (xd && gy >= 0 && gy < n && lane >= H && lane < 64 - H && ly >= H && ly < BY - H)
                 stc(uout, (size_t)gy * n + gx, e == b ? vb : lds_c(Ub[ly][lane]));
         }
     }
@@ -944,13 +944,14 @@ hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const voi
     auto ff = (const Cx*)f;
     if (dim == 2) {
         const int H = jacobi ? 1 : 2;
-        const unsigned b = (unsigned)(((n + 64 - 2 * H - 1) / (64 - 2 * H)) * ((n + CDB_Y - 2 * H - 1) / (CDB_Y - 2 * H)));
+        constexpr int BY = CDB_Y;
+        const unsigned b = (unsigned)(((n + 64 - 2 * H - 1) / (64 - 2 * H)) * ((n + BY - 2 * H - 1) / (BY - 2 * H)));
         if (jacobi) {
-            if (C.uc) k_cd_sweep2d_jac<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
-            else k_cd_sweep2d_jac<false><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
+            if (C.uc) k_cd_sweep2d_jac<true, BY><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
+            else k_cd_sweep2d_jac<false, BY><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
         } else {
-            if (C.uc) k_cd_sweep2d_rb<true><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
-            else k_cd_sweep2d_rb<false><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
+            if (C.uc) k_cd_sweep2d_rb<true, BY><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
+            else k_cd_sweep2d_rb<false, BY><<<b, NT, 0, s>>>(ui, uo, ff, K, L, C);
         }
     } else {
         if (n < kCDTiled3D) return hipErrorInvalidValue;  // small levels take the per-cell kernels
