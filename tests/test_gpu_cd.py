@@ -79,18 +79,20 @@ def test_cd_fas_cycle_bitwise(dim, n, smoother, nu, dev_ok):
         mg().mg_destroy(ctx)
 
 
-@pytest.mark.parametrize("dim,n", [(3, 256), (2, 4096)])
-@pytest.mark.parametrize("smoother", [RB, JAC])
-def test_cd_fas_cycle_bitwise_full_size(dim, n, smoother, dev_ok):
+@pytest.mark.parametrize("dim,n,smoother,nu", [(3, 256, RB, (2, 2)), (3, 256, JAC, (2, 2)), (2, 4096, RB, (2, 2)),
+                                               (2, 4096, JAC, (2, 2)), (3, 256, RB, (1, 0)), (3, 256, JAC, (3, 1)),
+                                               (2, 4096, JAC, (0, 3)), (2, 4096, RB, (1, 0))])
+def test_cd_fas_cycle_bitwise_full_size(dim, n, smoother, nu, dev_ok):
     """Table 2's sizes in the launch shapes the benchmark times (3D red-black
     boxes with 16-plane chunks at 256^3 and 8 at 128^3, Jacobi chunks of 8;
-    2D boxes over 4096^2): one FAS V(2,2) cycle bit for bit."""
+    2D boxes over 4096^2): one FAS cycle bit for bit, with the correction in
+    the first post-smoothing sweep (nu2 >= 1) or as its own pass (nu2 = 0)."""
     P = oracle.CD(tau=10.0 / n**2, k=0.1)
     u0 = inputs.noisy_image(dim, n, 8)
     f = u0 / P.tau + 0.05 * inputs.random_complex(dim, n, 9)
     omega = 1.0 if smoother == RB else 0.8
-    expect = oracle.cd_fas(u0, f, P, smoother, omega, 2, 2)
-    ctx = mg().mg_cdiff_setup(dim, n, P.tau, P.theta, P.k, smoother=smoother, nu1=2, nu2=2)
+    expect = oracle.cd_fas(u0, f, P, smoother, omega, *nu)
+    ctx = mg().mg_cdiff_setup(dim, n, P.tau, P.theta, P.k, smoother=smoother, nu1=nu[0], nu2=nu[1])
     try:
         u = dev(u0)
         mg().mg_cdiff_fas(ctx, u, dev(f))
