@@ -101,6 +101,29 @@ def test_cd_fas_cycle_bitwise_full_size(dim, n, smoother, nu, dev_ok):
         mg().mg_destroy(ctx)
 
 
+@pytest.mark.parametrize("dim,n,steps,smoother", [(3, 256, 1, RB), (2, 4096, 1, JAC)])
+def test_cd_run_matches_oracle_full_size(dim, n, steps, smoother, dev_ok):
+    """One implicit-Euler step at Table 2's sizes (the residual norm in the
+    benchmark's launch shape): cycle count equal, the field bit for bit, the
+    residual history to 1e-12 relative."""
+    P = oracle.CD(tau=10.0 / n**2, k=0.1)
+    u0 = inputs.noisy_image(dim, n, 5)
+    omega = 1.0 if smoother == RB else 0.8
+    u_exp, cyc_exp, hist_exp, rc_exp = oracle.cd_run(u0, P, steps=steps, tol=1e-5, max_cycles=12, smoother=smoother,
+                                                     omega=omega)
+    ctx = mg().mg_cdiff_setup(dim, n, P.tau, P.theta, P.k, smoother=smoother)
+    try:
+        u = dev(u0)
+        st, cyc, hist = mg().mg_cdiff_run(ctx, u, steps, 1e-5, 12)
+        assert (st == 0) == (rc_exp == 0)
+        assert list(cyc) == list(cyc_exp)
+        for h, he in zip(hist, hist_exp):
+            np.testing.assert_allclose(h, he, rtol=1e-12, atol=0)
+        assert np.array_equal(host(u), u_exp)
+    finally:
+        mg().mg_destroy(ctx)
+
+
 @pytest.mark.parametrize("dim,n,steps", [(2, 128, 3), (2, 512, 2), (3, 32, 3), (3, 64, 2), (3, 128, 1)])
 @pytest.mark.parametrize("smoother", [RB, JAC])
 def test_cd_run_matches_oracle(dim, n, steps, smoother, dev_ok):
