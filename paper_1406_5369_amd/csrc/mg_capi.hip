@@ -811,8 +811,7 @@ hipError_t cd_fas_level(CDState& S, int l, void*& cur, void*& other, const void*
     void* ucur = S.u[c1];
     void* uoth = S.t[c1];
     if ((e = cd_restrict(S.dim, cur, f, S.uh[c1], S.f[c1], S.K, L, s)) != hipSuccess) return e;
-    if ((e = cd_compute_g(S.uh[c1], S.g[c1], cd_cells(S, l + 1), S.K, s)) != hipSuccess) return e;
-    if ((e = cd_coarse_rhs(S.dim, S.uh[c1], S.g[c1], S.f[c1], ucur, S.K, Lc, s)) != hipSuccess) return e;
+    if ((e = cd_coarse_rhs(S.dim, S.uh[c1], S.f[c1], ucur, S.K, Lc, s)) != hipSuccess) return e;
     if ((e = cd_fas_level(S, l + 1, ucur, uoth, S.f[c1], s)) != hipSuccess) return e;
     S.u[c1] = ucur;
     S.t[c1] = uoth;

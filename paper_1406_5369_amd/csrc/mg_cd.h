@@ -36,8 +36,8 @@ hipError_t cd_sweep(int dim, bool jacobi, const void* uin, void* uout, const voi
 // uh = R u, rc = R (f - N(u)) with g of u formed on the fly (n >= 2)
 hipError_t cd_restrict(int dim, const void* u, const void* f, void* uh, void* rc, CDConst K, CDLevel L,
                        hipStream_t s);
-hipError_t cd_coarse_rhs(int dim, const void* uh, const void* gc, void* fc, void* uc, CDConst K, CDLevel Lc,
-                         hipStream_t s);
+// fc = N_c(uh) + fc (in place), uc = uh, g of uh formed on the fly
+hipError_t cd_coarse_rhs(int dim, const void* uh, void* fc, void* uc, CDConst K, CDLevel Lc, hipStream_t s);
 hipError_t cd_prolong(int dim, void* u, const void* uc, const void* uh, int n, hipStream_t s);
 hipError_t cd_scale(const void* a, void* out, size_t N, double sc, hipStream_t s);
 hipError_t cd_apply_op(int dim, const void* u, const void* g, void* out, CDConst K, CDLevel L, hipStream_t s);

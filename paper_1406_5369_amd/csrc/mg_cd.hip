@@ -135,11 +135,32 @@ __global__ __launch_bounds__(NT) void k_cd_relax(const Cx* uin_, Cx* uout_, cons
     stc(gp(uout_), p, cx_add(up, cx_scale(K.omega, cx_div(r, D))));
 }
 
-// fc = N_c(uh) + rc (in place over rc), uc = uh; gc = g(uh)
+// Flux sum F of cell p as cd_faces forms it, with g of each cell formed from
+// u (cd_g) instead of read from an array.
 template <int DIM>
-__global__ __launch_bounds__(NT) void k_cd_coarse_rhs(const Cx* __restrict__ uh_, const Cx* __restrict__ gc_,
-                                                      Cx* __restrict__ fc_, Cx* __restrict__ uc_, CDConst K,
-                                                      CDLevel L) {
+__device__ __forceinline__ Cx cd_flux_u(const MG_GLOBAL Cx* u, const CDConst& K, int n, int i, int j, int k,
+                                        size_t p) {
+    const Cx up = ldc(u, p), gq0 = cd_g(K, up);
+    const Cx zero{0.0, 0.0};
+    auto face = [&](bool inside, size_t q) {
+        if (!inside) return zero;
+        const Cx uq = ldc(u, q), gq = cd_g(K, uq);
+        const Cx gf{0.5 * (gq0.re + gq.re), 0.5 * (gq0.im + gq.im)};
+        return cx_mul(gf, cx_sub(uq, up));
+    };
+    Cx F = cx_add(cx_add(face(i > 0, p - 1), face(i < n - 1, p + 1)),
+                  cx_add(face(j > 0, p - (size_t)n), face(j < n - 1, p + (size_t)n)));
+    if constexpr (DIM == 3) {
+        const size_t sz = (size_t)n * n;
+        F = cx_add(F, cx_add(face(k > 0, p - sz), face(k < n - 1, p + sz)));
+    }
+    return F;
+}
+
+// fc = N_c(uh) + rc (in place over rc), uc = uh; g of uh formed on the fly
+template <int DIM>
+__global__ __launch_bounds__(NT) void k_cd_coarse_rhs(const Cx* __restrict__ uh_, Cx* __restrict__ fc_,
+                                                      Cx* __restrict__ uc_, CDConst K, CDLevel L) {
     const int n = L.n;
     const size_t N = DIM == 2 ? (size_t)n * n : (size_t)n * n * n;
     const size_t p = (size_t)blockIdx.x * NT + threadIdx.x;
@@ -147,10 +168,12 @@ __global__ __launch_bounds__(NT) void k_cd_coarse_rhs(const Cx* __restrict__ uh_
     int i, j, k;
     cd_ijk<DIM>(p, n, i, j, k);
     const MG_GLOBAL Cx* uh = gp(uh_);
-    const Cx Nv = cd_apply<DIM>(uh, gp(gc_), n, L.c, K.itau, i, j, k, p);
+    const Cx F = cd_flux_u<DIM>(uh, K, n, i, j, k, p);
+    const Cx up = ldc(uh, p);
+    const Cx Nv{K.itau * up.re - L.c * F.re, K.itau * up.im - L.c * F.im};  // cd_apply's expression
     MG_GLOBAL Cx* fc = gp(fc_);
     stc(fc, p, cx_add(Nv, ldc(fc, p)));
-    stc(gp(uc_), p, ldc(uh, p));
+    stc(gp(uc_), p, up);
 }
 
 // u += uc(parent) - uh(parent)
@@ -997,13 +1020,12 @@ hipError_t cd_restrict(int dim, const void* u, const void* f, void* uh, void* rc
     return hipGetLastError();
 }
 
-hipError_t cd_coarse_rhs(int dim, const void* uh, const void* gc, void* fc, void* uc, CDConst K, CDLevel Lc,
-                         hipStream_t s) {
+hipError_t cd_coarse_rhs(int dim, const void* uh, void* fc, void* uc, CDConst K, CDLevel Lc, hipStream_t s) {
     const unsigned b = nblk(ncells(dim, Lc.n));
     if (dim == 2)
-        k_cd_coarse_rhs<2><<<b, NT, 0, s>>>((const Cx*)uh, (const Cx*)gc, (Cx*)fc, (Cx*)uc, K, Lc);
+        k_cd_coarse_rhs<2><<<b, NT, 0, s>>>((const Cx*)uh, (Cx*)fc, (Cx*)uc, K, Lc);
     else
-        k_cd_coarse_rhs<3><<<b, NT, 0, s>>>((const Cx*)uh, (const Cx*)gc, (Cx*)fc, (Cx*)uc, K, Lc);
+        k_cd_coarse_rhs<3><<<b, NT, 0, s>>>((const Cx*)uh, (Cx*)fc, (Cx*)uc, K, Lc);
     return hipGetLastError();
 }
 
