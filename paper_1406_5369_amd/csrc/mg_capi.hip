@@ -779,7 +779,7 @@ size_t cd_cells(const CDState& S, int l) {
 }
 
 // one sweep (both colours or Jacobi): tiled into the level's other buffer, or
-// per cell (small 3D levels) with g formed first
+// per cell (small 3D levels), g of the pre-sweep iterate formed in the relaxation
 hipError_t cd_sweep_level(CDState& S, int l, void*& cur, void*& other, const void* f, hipStream_t s,
                           const void* uc = nullptr, const void* uh = nullptr) {
     const CDLevel L = cd_level(S.ln[(size_t)l]);
@@ -788,8 +788,7 @@ hipError_t cd_sweep_level(CDState& S, int l, void*& cur, void*& other, const voi
         std::swap(cur, other);
         return e;
     }
-    hipError_t e = cd_compute_g(cur, S.g[(size_t)l], cd_cells(S, l), S.K, s);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
     if (S.jacobi) {
         e = cd_relax(S.dim, true, cur, other, f, S.g[(size_t)l], S.K, L, 0, s);
         std::swap(cur, other);

@@ -19,10 +19,11 @@ struct CDLevel {
 CDLevel cd_level(int n);
 
 hipError_t cd_compute_g(const void* u, void* g, size_t N, CDConst K, hipStream_t s);
-// RBGS colour 'colour' in place (uin == uout) or a Jacobi sweep uin -> uout,
-// one cell per thread, g of the pre-sweep iterate in its array
-hipError_t cd_relax(int dim, bool jacobi, const void* uin, void* uout, const void* f, const void* g, CDConst K,
-                    CDLevel L, int colour, hipStream_t s);
+// RBGS colour 'colour' in place (uin == uout; red, colour 0, first: it
+// stores the pre-sweep g of its cells in g for the black colour) or a Jacobi
+// sweep uin -> uout (g unused), one cell per thread, g of the pre-sweep iterate
+hipError_t cd_relax(int dim, bool jacobi, const void* uin, void* uout, const void* f, void* g, CDConst K, CDLevel L,
+                    int colour, hipStream_t s);
 // whether a level takes the tiled sweep (cd_sweep): 2D always, 3D from n = 128
 bool cd_tiled(int dim, int n);
 // whether cd_sweep takes the FAS correction (uc, uh) on such a level

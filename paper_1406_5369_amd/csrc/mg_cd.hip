@@ -65,11 +65,11 @@ __device__ __forceinline__ void cd_ijk(size_t p, int n, int& i, int& j, int& k) 
 }
 
 // Flux sum F and diagonal sum S of cell p (faces W, E, S, N[, B, T] paired as
-// ((W+E)+(S+N))+(B+T); a boundary face contributes zeros).
-template <int DIM>
-__device__ __forceinline__ void cd_faces(const MG_GLOBAL Cx* u, const MG_GLOBAL Cx* g, int n, int i, int j, int k,
-                                         size_t p, Cx& F, Cx& S) {
-    const Cx up = ldc(u, p), gq0 = ldc(g, p);
+// ((W+E)+(S+N))+(B+T); a boundary face contributes zeros).  up, gq0: u and g
+// of cell p; gof(q, uq): g of neighbour q (from an array or formed from uq).
+template <int DIM, typename GOF>
+__device__ __forceinline__ void cd_faces_with(const MG_GLOBAL Cx* u, int n, int i, int j, int k, size_t p, Cx up,
+                                              Cx gq0, GOF gof, Cx& F, Cx& S) {
     const Cx zero{0.0, 0.0};
     auto face = [&](bool inside, size_t q, Cx& t, Cx& gf) {
         if (!inside) {
@@ -77,9 +77,10 @@ __device__ __forceinline__ void cd_faces(const MG_GLOBAL Cx* u, const MG_GLOBAL 
             gf = zero;
             return;
         }
-        const Cx gq = ldc(g, q);
+        const Cx uq = ldc(u, q);
+        const Cx gq = gof(q, uq);
         gf = Cx{0.5 * (gq0.re + gq.re), 0.5 * (gq0.im + gq.im)};
-        t = cx_mul(gf, cx_sub(ldc(u, q), up));
+        t = cx_mul(gf, cx_sub(uq, up));
     };
     Cx tW, tE, tS, tN, gW, gE, gS, gN;
     face(i > 0, p - 1, tW, gW);
@@ -98,6 +99,13 @@ __device__ __forceinline__ void cd_faces(const MG_GLOBAL Cx* u, const MG_GLOBAL 
     }
 }
 
+// the same with g of every cell read from its array
+template <int DIM>
+__device__ __forceinline__ void cd_faces(const MG_GLOBAL Cx* u, const MG_GLOBAL Cx* g, int n, int i, int j, int k,
+                                         size_t p, Cx& F, Cx& S) {
+    cd_faces_with<DIM>(u, n, i, j, k, p, ldc(u, p), ldc(g, p), [&](size_t q, Cx) { return ldc(g, q); }, F, S);
+}
+
 template <int DIM>
 __device__ __forceinline__ Cx cd_apply(const MG_GLOBAL Cx* u, const MG_GLOBAL Cx* g, int n, double c, double itau,
                                        int i, int j, int k, size_t p) {
@@ -113,25 +121,32 @@ __global__ __launch_bounds__(NT) void k_cd_g(const Cx* __restrict__ u, Cx* __res
 }
 
 // One cell per thread (the small 3D levels, where a marching tile has too few
-// workgroups to hide its latency): an RBGS colour in place (uin == uout) or a
-// Jacobi sweep (out of place), g frozen in its array.
-template <int DIM, bool JAC>
-__global__ __launch_bounds__(NT) void k_cd_relax(const Cx* uin_, Cx* uout_, const Cx* __restrict__ f_,
-                                                 const Cx* __restrict__ g_, CDConst K, CDLevel L, int colour) {
+// workgroups to hide its latency), g of the pre-sweep iterate: MODE 0 a
+// Jacobi sweep (out of place, every g formed from uin); MODE 1 the red colour
+// in place (g formed from the cells, which are all pre-sweep during it; each
+// red cell also stores its pre-sweep g for the black colour); MODE 2 the
+// black colour in place (its own g formed, its red neighbours' read back).
+template <int DIM, int MODE>
+__global__ __launch_bounds__(NT) void k_cd_relax(const Cx* uin_, Cx* uout_, const Cx* __restrict__ f_, Cx* g_,
+                                                 CDConst K, CDLevel L) {
     const int n = L.n;
     const size_t N = DIM == 2 ? (size_t)n * n : (size_t)n * n * n;
     const size_t p = (size_t)blockIdx.x * NT + threadIdx.x;
     if (p >= N) return;
     int i, j, k;
     cd_ijk<DIM>(p, n, i, j, k);
-    if (!JAC && ((i + j + k) & 1) != colour) return;
+    if (MODE != 0 && ((i + j + k) & 1) != (MODE == 1 ? 0 : 1)) return;
     const MG_GLOBAL Cx* uin = gp(uin_);
+    MG_GLOBAL Cx* g = gp(g_);
+    const Cx up = ldc(uin, p), gq0 = cd_g(K, up);
     Cx F, S;
-    cd_faces<DIM>(uin, gp(g_), n, i, j, k, p, F, S);
-    const Cx up = ldc(uin, p);
+    cd_faces_with<DIM>(uin, n, i, j, k, p, up, gq0,
+                       [&](size_t q, Cx uq) { return MODE == 2 ? ldc((const MG_GLOBAL Cx*)g, q) : cd_g(K, uq); }, F,
+                       S);
     const Cx Nu{K.itau * up.re - L.c * F.re, K.itau * up.im - L.c * F.im};
     const Cx r = cx_sub(ldc(gp(f_), p), Nu);
     const Cx D{K.itau + L.c * S.re, L.c * S.im};
+    if constexpr (MODE == 1) stc(g, p, gq0);
     stc(gp(uout_), p, cx_add(up, cx_scale(K.omega, cx_div(r, D))));
 }
 
@@ -930,20 +945,25 @@ hipError_t cd_compute_g(const void* u, void* g, size_t N, CDConst K, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t cd_relax(int dim, bool jacobi, const void* uin, void* uout, const void* f, const void* g, CDConst K,
-                    CDLevel L, int colour, hipStream_t s) {
+hipError_t cd_relax(int dim, bool jacobi, const void* uin, void* uout, const void* f, void* g, CDConst K, CDLevel L,
+                    int colour, hipStream_t s) {
+    if (!jacobi && colour != 0 && colour != 1) return hipErrorInvalidValue;
     const unsigned b = nblk(ncells(dim, L.n));
     auto ui = (const Cx*)uin;
     auto uo = (Cx*)uout;
     auto ff = (const Cx*)f;
-    auto gg = (const Cx*)g;
+    auto gg = (Cx*)g;
+    const int mode = jacobi ? 0 : 1 + colour;
+#define MG_CD_RELAX(D)                                                                      \
+    if (mode == 0) k_cd_relax<D, 0><<<b, NT, 0, s>>>(ui, uo, ff, gg, K, L);                 \
+    else if (mode == 1) k_cd_relax<D, 1><<<b, NT, 0, s>>>(ui, uo, ff, gg, K, L);            \
+    else k_cd_relax<D, 2><<<b, NT, 0, s>>>(ui, uo, ff, gg, K, L);
     if (dim == 2) {
-        if (jacobi) k_cd_relax<2, true><<<b, NT, 0, s>>>(ui, uo, ff, gg, K, L, colour);
-        else k_cd_relax<2, false><<<b, NT, 0, s>>>(ui, uo, ff, gg, K, L, colour);
+        MG_CD_RELAX(2)
     } else {
-        if (jacobi) k_cd_relax<3, true><<<b, NT, 0, s>>>(ui, uo, ff, gg, K, L, colour);
-        else k_cd_relax<3, false><<<b, NT, 0, s>>>(ui, uo, ff, gg, K, L, colour);
+        MG_CD_RELAX(3)
     }
+#undef MG_CD_RELAX
     return hipGetLastError();
 }
 
