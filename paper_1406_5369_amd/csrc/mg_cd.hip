@@ -456,7 +456,8 @@ struct CDSweep3J {
                 }
             }
         }
-        __syncthreads();
+        // no barrier here: the next step writes the slot of plane kk-2, whose
+        // last reads (step kk-1) this step's barrier already ordered
     }
 
     __device__ __forceinline__ void run() {
@@ -586,7 +587,7 @@ __global__ __launch_bounds__(NT) void k_cd_sweep2d_rb(const Cx* __restrict__ uin
 
 // 3D: a 64 x 2NW box in x-y (NW wavefronts, wavefront w owning the row pair
 // 2w, 2w+1) marching along z through a chunk of planes as CDSweep3J does:
-// step kk: plane kk enters (registers and an LDS ring of three planes); red on
+// step kk: plane kk enters (registers and an LDS ring of four planes); red on
 // plane kk-1 (box minus one ring, in place); black on plane kk-2 (the tile),
 // written out with its red cells.  Each thread keeps its two cells of the
 // last four planes (u, q, f) in registers for the z faces.
@@ -651,7 +652,7 @@ struct CDSweep3RB {
     __device__ __forceinline__ void step(int kk) {
         constexpr int R0 = P, R1 = (P + 3) & 3, R2 = (P + 2) & 3, R3 = (P + 1) & 3;  // planes kk .. kk-3
         const int q = kk - kstart;
-        const int s0 = q % 3, s1 = (q + 2) % 3, s2 = (q + 1) % 3;                     // LDS: kk, kk-1, kk-2
+        const int s0 = q & 3, s1 = (q + 3) & 3, s2 = (q + 2) & 3;  // LDS ring of four: kk, kk-1, kk-2
         const bool zd = kk >= 0 && kk < n;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
@@ -704,7 +705,10 @@ struct CDSweep3RB {
                         e == b ? vb : Cx{ure[R2][e], uim[R2][e]});
             }
         }
-        __syncthreads();
+        // no barrier here: with four slots the next step writes the slot of
+        // plane kk-3 (last read by step kk-1's black half, ordered by this
+        // step's barriers) and its red half changes plane kk's slot, which
+        // this black half does not read
     }
 
     __device__ __forceinline__ void run() {
@@ -726,8 +730,8 @@ template <int NW, int MINW, bool CORR>
 __global__ __launch_bounds__(64 * NW, MINW) void k_cd_sweep3d_rb(const Cx* __restrict__ uin_, Cx* __restrict__ uout_,
                                                            const Cx* __restrict__ f_, CDConst K, CDLevel L, int zc, CDCorr C) {
     using S = CDSweep3RB<NW, CORR>;
-    __shared__ d2v Ub[3][S::BY][64];
-    __shared__ double Qb[3][S::BY][64];
+    __shared__ d2v Ub[4][S::BY][64];
+    __shared__ double Qb[4][S::BY][64];
     S s;
     s.Ub = Ub;
     s.Qb = Qb;
